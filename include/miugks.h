@@ -1,0 +1,191 @@
+/*
+ * miugks.h - C ABI of the MI355X (gfx950) implementation of the multigrid
+ * implicit unified gas-kinetic scheme (MIUGKS) of Zhu, Zhong & Xu,
+ * "Unified gas-kinetic scheme with multigrid convergence for rarefied flow
+ * study" (arXiv:1704.03151).
+ *
+ * One context holds one steady problem on a structured 2-D mesh with a
+ * tensor-product discrete velocity grid, the coarsened mesh hierarchy of
+ * Sec. III A, and all device memory of the solver (owned by the library,
+ * allocated in miugks_create, released in miugks_destroy).  Every hot step
+ * runs in the library's HIP kernels on the stream given at creation.
+ *
+ * Conventions
+ *  - All functions return MIUGKS_OK (0) or an error code; the text of the
+ *    last error of a context is returned by miugks_last_error().
+ *  - Host arrays passed in are copied and never retained; host arrays passed
+ *    out are owned by the caller.  A pointer argument documented as
+ *    "may be NULL" is skipped when NULL.
+ *  - Cell arrays are [ny][nx] (x fastest).  Macroscopic fields are
+ *    nondimensional: lengths by the reference length, density by rho0,
+ *    temperature by T0, speeds by sqrt(2 R T0) (so R T0 = 1/2).
+ *  - Distribution arrays hold the reduced pair (G, H): G integrates f over the
+ *    K_int extra velocity components, H integrates their squared magnitude.
+ *    Layout [2][Nk][ny][nx]: G plane then H plane, each velocity-major with
+ *    cells fastest; velocity index k = ku * nv + kv.
+ *  - A context is not thread-safe; use one context per host thread.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef MIUGKS_H
+#define MIUGKS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MIUGKS_OK 0
+#define MIUGKS_EINVAL 1          /* bad argument or unsupported configuration */
+#define MIUGKS_ENOMEM 2          /* device or host allocation failed */
+#define MIUGKS_EDEVICE 3         /* HIP runtime error (text in miugks_last_error) */
+#define MIUGKS_EDIVERGED 4       /* residual non-finite or blew up; state is the last finite cycle */
+#define MIUGKS_ENOTCONVERGED 5   /* max_cycles reached above the tolerance; state valid */
+#define MIUGKS_ESTATE 6          /* call not valid in the current state */
+
+/* face tags (Sec. III B boundary conditions) */
+#define MIUGKS_FACE_INTERIOR 0   /* two fluid cells */
+#define MIUGKS_FACE_WALL 1       /* diffuse isothermal wall, full accommodation */
+#define MIUGKS_FACE_FARFIELD 2   /* freestream Maxwellian enters, the cell's distribution leaves */
+#define MIUGKS_FACE_OUTFLOW 3    /* zero gradient */
+
+/* precision of the distribution and of the per-velocity arithmetic */
+#define MIUGKS_FP64 0            /* everything in double */
+#define MIUGKS_FP32F 1           /* f, flux, residual and smoother arithmetic in float;
+                                    moments, macroscopic prediction and norms in double */
+
+/* one-dimensional quadrature rules (velocity grids, Sec. IV) */
+#define MIUGKS_QUAD_TRAPEZOID 0
+#define MIUGKS_QUAD_SIMPSON38 1  /* composite Simpson 3/8, needs (n-1) % 3 == 0 */
+#define MIUGKS_QUAD_GAUSS_HERMITE 2
+
+typedef struct miugks_ctx miugks_ctx;
+
+/* Structured mesh (Sec. III A).  Cell (ix, iy) spans [x[ix], x[ix+1]] x
+ * [y[iy], y[iy+1]].  x-face (ix, iy), index iy*(nx+1)+ix, lies on x = x[ix];
+ * y-face (ix, iy), index iy*nx+ix, lies on y = y[iy].  Domain-boundary faces
+ * must not be INTERIOR; a face between a fluid and a solid cell must be a
+ * WALL.  wall_x / wall_y hold (T_w, U_w, V_w) per face (3 doubles), read only
+ * for WALL faces (may be NULL when there is no wall).  solid may be NULL.
+ * n_levels >= 1; nx, ny must be divisible by 2^(n_levels-1), coarse faces must
+ * not mix tags and coarse cells must not mix fluid and solid. */
+typedef struct {
+    int nx, ny, n_levels;
+    const double* x;
+    const double* y;
+    const uint8_t* face_type_x;
+    const uint8_t* face_type_y;
+    const double* wall_x;
+    const double* wall_y;
+    const uint8_t* solid;
+} miugks_mesh_desc;
+
+/* Tensor-product velocity grid: nodes u[nu], v[nv], 1-D weights wu[nu], wv[nv]. */
+typedef struct {
+    int nu, nv;
+    const double* u;
+    const double* v;
+    const double* wu;
+    const double* wv;
+} miugks_vgrid_desc;
+
+/* Gas: K_int extra degrees of freedom (1 for a monatomic gas in 2-D), Prandtl
+ * number (Shakhov model), viscosity mu = mu_ref T^omega with mu_ref fixed by
+ * the VHS mean free path Kn (alpha = 1), freestream state for FARFIELD faces. */
+typedef struct {
+    int K_int;
+    double Pr, omega, Kn;
+    double rho_inf, U_inf, V_inf, T_inf;
+} miugks_gas_desc;
+
+/* Solver: precision (MIUGKS_FP64 / MIUGKS_FP32F), smoothing counts nu1
+ * (pre), nu2 (post), nu_coarse (coarsest level), Courant number of the
+ * physical step, growth a of the pseudo step dt_n = a^n dt_p (0 = off,
+ * Sec. III D), mass_renorm: 1 = keep total mass, 0 = off, -1 = on iff the
+ * domain has walls only. */
+typedef struct {
+    int precision;
+    int nu1, nu2, nu_coarse;
+    double cfl;
+    double dtn_growth;
+    int mass_renorm;
+} miugks_solver_desc;
+
+/* Nodes and weights of a 1-D rule on [lo, hi] (ignored for Gauss-Hermite,
+ * whose weights integrate plain functions: w = w_GH * exp(u^2)).  nodes and
+ * weights are host arrays of n doubles.  Sec. IV (trapezoid, Newton-Cotes). */
+int miugks_quadrature(int kind, int n, double lo, double hi, double* nodes, double* weights);
+
+/* Build the level hierarchy and allocate device memory.  hip_stream is a
+ * hipStream_t (e.g. torch.cuda.current_stream().cuda_stream) or NULL for the
+ * default stream.  The distribution starts as the rest state rho = T = 1. */
+int miugks_create(miugks_ctx** out, const miugks_mesh_desc* mesh, const miugks_vgrid_desc* vgrid,
+                  const miugks_gas_desc* gas, const miugks_solver_desc* solver, void* hip_stream);
+
+/* Free all memory of ctx; NULL is a no-op. */
+void miugks_destroy(miugks_ctx* ctx);
+
+/* Text of the last error on ctx (NULL ctx: last creation error). */
+const char* miugks_last_error(const miugks_ctx* ctx);
+
+/* f := cell Maxwellian of host fields rho, U, V, T [ny][nx] (solid cells: 0);
+ * resets the cycle counter and the reference mass. */
+int miugks_init_macro(miugks_ctx* ctx, const double* rho, const double* U, const double* V,
+                      const double* T);
+
+/* Outer MIUGKS cycles, Steps 1-8 of Sec. II D: for each cycle compute the UGKS
+ * residuals; stop if every RMS residual component (Sec. IV A) is below tol;
+ * otherwise run the FAS prediction, micro residual, CS correction and update.
+ * cycles_done (may be NULL) receives the number of updates made, res (may be
+ * NULL) the four RMS residuals of the last check.  Synchronises the stream. */
+int miugks_iterate(miugks_ctx* ctx, int max_cycles, double tol, int* cycles_done, double res[4]);
+
+/* Host outputs [ny][nx] (each may be NULL): primitive fields and heat flux of
+ * the current distribution. */
+int miugks_get_macro(miugks_ctx* ctx, double* rho, double* U, double* V, double* T, double* qx,
+                     double* qy);
+
+/* Copy the distribution [2][Nk][ny][nx] out of / into the context.  dtype is
+ * MIUGKS_FP64 (double) or MIUGKS_FP32F (float); it is converted as needed.
+ * on_device = 1: dst/src is a device pointer on the context's device.
+ * set_f recomputes the moments; it is the checkpoint/restore path. */
+int miugks_get_f(miugks_ctx* ctx, void* dst, int dtype, int on_device);
+int miugks_set_f(miugks_ctx* ctx, const void* src, int dtype, int on_device);
+
+/* --- one call per step of the hot path (parity and profiling) ------------- */
+
+/* Step 1 alone (Sec. II A, residual definitions; UGKS flux): recompute the
+ * transport term div and the macroscopic residual R of the current f.  R
+ * (host [4][ny][nx], may be NULL) and the RMS norms res (may be NULL) out. */
+int miugks_residual(miugks_ctx* ctx, double* R, double res[4]);
+
+/* Transport term div of the last miugks_residual, layout as f. */
+int miugks_get_div(miugks_ctx* ctx, void* dst, int dtype, int on_device);
+
+/* Step 2 alone (FAS V-cycle, Sec. II D): predicted conservative variables
+ * W_out [4][ny][nx] from W [4][ny][nx] and target residual R [4][ny][nx]
+ * (host arrays), with the pseudo step of the current cycle counter. */
+int miugks_predict(miugks_ctx* ctx, const double* W, const double* R, double* W_out);
+
+/* Steps 3-4 alone: micro residual r = (g~ - f)/tau~ - div from the predicted
+ * state Wt [4][ny][nx] (host), the current f, heat flux and the div of the
+ * last miugks_residual.  r_out layout as f (dtype, on_device as get_f);
+ * tau_inv_out (host [ny][nx], may be NULL) receives 1/tau~. */
+int miugks_micro_residual(miugks_ctx* ctx, const double* Wt, void* r_out, double* tau_inv_out,
+                          int dtype, int on_device);
+
+/* Step 5 alone (CS V-cycle, Sec. II D): correction df_out of the linear
+ * correction equation with right-hand side r and collision frequency
+ * tau_inv (host [ny][nx]).  r and df_out layout as f. */
+int miugks_correct(miugks_ctx* ctx, const void* r, const double* tau_inv, void* df_out, int dtype,
+                   int on_device);
+
+/* Sizes: cells, fluid cells, velocities, levels. */
+int miugks_sizes(const miugks_ctx* ctx, int* nc, int* n_fluid, int* nk, int* n_levels);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIUGKS_H */

@@ -1,0 +1,1128 @@
+// HIP kernels of the MIUGKS hot path for gfx950 (templated on the storage /
+// arithmetic type T of the distribution: double, or float for the FP32-f
+// form in which moments, macroscopic prediction and norms stay double).
+//
+// Data layout (HBM): distributions are [2][Nk][nc] (G plane, H plane,
+// velocity-major, cells fastest), so a wavefront of 64 lanes covers 64
+// consecutive cells of one velocity and every access coalesces.  Per-cell
+// macroscopic arrays are [m][nc] doubles.
+//
+// Most per-(cell, velocity) kernels use one launch shape: a block of 256
+// threads = 64 lanes (consecutive cells) x 4 waves, the waves taking
+// interleaved velocities of a chunk of KCH = 4 * MK velocities; each thread
+// keeps MK velocities in registers, and reductions over the velocities are
+// written as per-chunk partial sums that a finalize kernel adds in a fixed
+// order (deterministic, no floating-point atomics).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "setup.hpp"
+
+namespace miugks {
+
+constexpr int TILE = 64;
+constexpr int WAVES = 4;
+constexpr int MK = 8;                 // velocities per thread per chunk
+constexpr int KCH = WAVES * MK;       // velocities per chunk
+constexpr int NFP = 24;               // doubles per interface record
+constexpr int NCP = 7;                // doubles per cell record of the predicted equilibrium
+
+struct Geo {
+    int nx, ny, nc, n_wall;
+    const double *xc, *yc, *dx, *dy, *dcent, *dt;
+    const int* nb;
+    const unsigned char* solid;
+    const int *w_cell, *w_side;
+    const double *w_T, *w_U, *w_V, *w_den;
+    const int* p_idx;
+    const double* p_w;
+};
+
+struct Vel {
+    int nk;
+    const double *u, *v, *w;
+    const float *uf, *vf, *wf;
+};
+
+struct Gas {
+    int K_int;
+    double K, gamma, Pr, omega, mu_ref;
+    double W_inf[4];
+    double rho_inf, U_inf, V_inf, lam_inf;
+};
+
+__device__ __forceinline__ bool is_wall(int code) { return code <= NB_WALL0; }
+__device__ __forceinline__ int wall_of(int code) { return NB_WALL0 - code; }
+
+template <typename T> __device__ __forceinline__ T vel_u(const Vel& v, int k);
+template <typename T> __device__ __forceinline__ T vel_v(const Vel& v, int k);
+template <typename T> __device__ __forceinline__ T vel_w(const Vel& v, int k);
+template <> __device__ __forceinline__ double vel_u<double>(const Vel& v, int k) { return v.u[k]; }
+template <> __device__ __forceinline__ double vel_v<double>(const Vel& v, int k) { return v.v[k]; }
+template <> __device__ __forceinline__ double vel_w<double>(const Vel& v, int k) { return v.w[k]; }
+template <> __device__ __forceinline__ float vel_u<float>(const Vel& v, int k) { return v.uf[k]; }
+template <> __device__ __forceinline__ float vel_v<float>(const Vel& v, int k) { return v.vf[k]; }
+template <> __device__ __forceinline__ float vel_w<float>(const Vel& v, int k) { return v.wf[k]; }
+
+__device__ __forceinline__ double dexp(double x) { return exp(x); }
+__device__ __forceinline__ float dexp(float x) { return expf(x); }
+
+// van Leer limiter: harmonic mean of one-sided slopes of equal sign, else 0
+template <typename T> __device__ __forceinline__ T van_leer(T a, T b) {
+    T s = a * b;
+    return s > T(0) ? T(2) * s / (a + b) : T(0);
+}
+
+// ---------------------------------------------------------------------------
+// gas-model helpers (double)
+
+__device__ __forceinline__ double mu_of(const Gas& g, double T) { return g.mu_ref * pow(T, g.omega); }
+
+__device__ __forceinline__ void prim_of(const double* W, double K, double& rho, double& U, double& V,
+                                        double& lam) {
+    rho = W[0];
+    U = W[1] / rho;
+    V = W[2] / rho;
+    double e = W[3] - 0.5 * rho * (U * U + V * V);
+    lam = K * rho / (4.0 * e);
+}
+
+__device__ __forceinline__ void cons_of(double rho, double U, double V, double lam, double K, double* W) {
+    W[0] = rho;
+    W[1] = rho * U;
+    W[2] = rho * V;
+    W[3] = 0.5 * rho * (U * U + V * V) + K * rho / (4.0 * lam);
+}
+
+// abar = a1 + a2 u + a3 v + a4 (u^2+v^2+xi^2)/2 with <abar psi g0> = rho0 b for
+// a Maxwellian g0 with K total degrees of freedom (closed-form inverse of the
+// moment matrix; the standard GKS micro-slope relation).
+__device__ __forceinline__ void micro_slope(const double* b, double U, double V, double lam, double K,
+                                            double* a) {
+    double e = U * U + V * V + K / (2.0 * lam);
+    double R2 = b[1] - U * b[0];
+    double R3 = b[2] - V * b[0];
+    double R4 = 2.0 * b[3] - e * b[0];
+    a[3] = 4.0 * lam * lam / K * (R4 - 2.0 * U * R2 - 2.0 * V * R3);
+    a[2] = 2.0 * lam * R3 - V * a[3];
+    a[1] = 2.0 * lam * R2 - U * a[3];
+    a[0] = b[0] - U * a[1] - V * a[2] - 0.5 * a[3] * e;
+}
+
+// Exact integrals over [0, dt] of the time factors of the UGKS interface
+// distribution (x = dt/tau): (1 - e^{-t/tau}), ((t+tau) e^{-t/tau} - tau),
+// (t - tau + tau e^{-t/tau}), e^{-t/tau}, -t e^{-t/tau}.  For x < 1/2 the
+// closed forms cancel, so Taylor series (25 terms) are summed instead.
+__device__ __forceinline__ void time_coeffs(double dt, double tau, double* q) {
+    double x = dt / tau;
+    double em1 = -expm1(-x);
+    q[3] = tau * em1;
+    if (x < 0.5) {
+        double s1 = 0, s2 = 0, s3 = 0, s5 = 0, fact = 1.0, xp = 1.0;   // xp = x^(m-2)
+        for (int m = 1; m <= 25; ++m) {
+            fact *= m;
+            double sg = (m & 1) ? -1.0 : 1.0;
+            if (m >= 2) {
+                s1 += sg * xp * x / fact;
+                s5 += sg * (1 - m) * xp / fact;
+                if (m >= 3) {
+                    s2 += sg * (m - 2) * xp / fact;
+                    s3 -= sg * xp / fact;
+                }
+                xp *= x;
+            }
+        }
+        q[0] = dt * s1;
+        q[1] = dt * dt * s2;
+        q[2] = dt * dt * s3;
+        q[4] = dt * dt * s5;
+    } else {
+        double e = exp(-x);
+        q[0] = dt - tau * em1;
+        q[1] = 2.0 * tau * tau * em1 - tau * dt - tau * dt * e;
+        q[2] = 0.5 * dt * dt - tau * dt + tau * tau * em1;
+        q[4] = tau * dt * e - tau * tau * em1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// helpers shared by the chunked kernels
+
+struct Chunk {
+    int c, lane, wave, k0, k1;
+    bool valid;
+};
+
+__device__ __forceinline__ Chunk chunk_of(int nc, int nk) {
+    Chunk ch;
+    ch.lane = threadIdx.x & (TILE - 1);
+    ch.wave = threadIdx.x / TILE;
+    ch.c = blockIdx.x * TILE + ch.lane;
+    ch.valid = ch.c < nc;
+    ch.k0 = blockIdx.y * KCH;
+    ch.k1 = min(nk, ch.k0 + KCH);
+    return ch;
+}
+
+// sum M partial values across the 4 waves of the block and store them as
+// part[(chunk * M + m) * n + i]
+template <int M>
+__device__ __forceinline__ void reduce_store(double* acc, double* sh, double* part, int n, int i,
+                                             bool valid) {
+    int lane = threadIdx.x & (TILE - 1), wave = threadIdx.x / TILE;
+    for (int m = 0; m < M; ++m) sh[(m * WAVES + wave) * TILE + lane] = acc[m];
+    __syncthreads();
+    if (wave == 0 && valid) {
+        for (int m = 0; m < M; ++m) {
+            double s = sh[(m * WAVES + 0) * TILE + lane];
+            for (int w = 1; w < WAVES; ++w) s += sh[(m * WAVES + w) * TILE + lane];
+            part[((size_t)blockIdx.y * M + m) * n + i] = s;
+        }
+    }
+}
+
+// raw moments of (G, H): sum w {G, uG, vG, u^2 G, uvG, v^2 G, u|u|^2 G, v|u|^2 G, H, uH, vH}
+constexpr int NRAW = 11;
+
+__device__ __forceinline__ void raw_accumulate(double* a, double w, double u, double v, double G,
+                                               double H) {
+    double wG = w * G, wH = w * H, e2 = u * u + v * v;
+    a[0] += wG;
+    a[1] += u * wG;
+    a[2] += v * wG;
+    a[3] += u * u * wG;
+    a[4] += u * v * wG;
+    a[5] += v * v * wG;
+    a[6] += u * e2 * wG;
+    a[7] += v * e2 * wG;
+    a[8] += wH;
+    a[9] += u * wH;
+    a[10] += v * wH;
+}
+
+// conservative variables and heat flux (about the mean velocity) from raw moments
+__device__ __forceinline__ void raw_to_macro(const double* M, double* W, double* q) {
+    double rho = M[0], U = M[1] / rho, V = M[2] / rho;
+    W[0] = M[0];
+    W[1] = M[1];
+    W[2] = M[2];
+    W[3] = 0.5 * (M[3] + M[5] + M[8]);
+    double U2 = U * U + V * V, E2 = M[3] + M[5];
+    double cx = M[6] - 2.0 * U * M[3] - 2.0 * V * M[4] + U2 * M[1] - U * E2 + 2.0 * U * U * M[1] +
+                2.0 * U * V * M[2] - U * U2 * M[0];
+    double cy = M[7] - 2.0 * U * M[4] - 2.0 * V * M[5] + U2 * M[2] - V * E2 + 2.0 * U * V * M[1] +
+                2.0 * V * V * M[2] - V * U2 * M[0];
+    q[0] = 0.5 * (cx + M[9] - U * M[8]);
+    q[1] = 0.5 * (cy + M[10] - V * M[8]);
+}
+
+// ---------------------------------------------------------------------------
+// initial distribution: reduced Maxwellian of (rho, U, V, T) per cell
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_init(Geo g, Vel vel, Gas gas, const double* __restrict__ prim,
+                                              T* __restrict__ f) {
+    Chunk ch = chunk_of(g.nc, vel.nk);
+    if (!ch.valid) return;
+    int c = ch.c;
+    bool fluid = !g.solid[c];
+    double rho = prim[c], U = prim[g.nc + c], V = prim[2 * g.nc + c], lam = 1.0 / prim[3 * g.nc + c];
+    for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
+        double du = vel.u[k] - U, dv = vel.v[k] - V;
+        double G = fluid ? rho * (lam / M_PI) * exp(-lam * (du * du + dv * dv)) : 0.0;
+        f[(size_t)k * g.nc + c] = T(G);
+        f[(size_t)(vel.nk + k) * g.nc + c] = T(gas.K_int / (2.0 * lam) * G);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// cell moments (Step 7 and the compatibility condition): W and q of f.
+// With df != nullptr the kernel first applies Step 6, f += df, and stores f.
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_moments_partial(Geo g, Vel vel, T* __restrict__ f,
+                                                         const T* __restrict__ df,
+                                                         double* __restrict__ part) {
+    __shared__ double sh[NRAW * WAVES * TILE];
+    Chunk ch = chunk_of(g.nc, vel.nk);
+    double a[NRAW];
+    for (int m = 0; m < NRAW; ++m) a[m] = 0.0;
+    if (ch.valid) {
+        size_t nc = g.nc;
+        for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
+            size_t ig = (size_t)k * nc + ch.c, ih = (size_t)(vel.nk + k) * nc + ch.c;
+            T G = f[ig], H = f[ih];
+            if (df) {
+                G += df[ig];
+                H += df[ih];
+                f[ig] = G;
+                f[ih] = H;
+            }
+            raw_accumulate(a, vel.w[k], vel.u[k], vel.v[k], double(G), double(H));
+        }
+    }
+    reduce_store<NRAW>(a, sh, part, g.nc, ch.c, ch.valid);
+}
+
+__global__ void k_moments_finalize(Geo g, const double* __restrict__ part, int nkc,
+                                   double* __restrict__ W, double* __restrict__ q) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nc) return;
+    if (g.solid[c]) {
+        for (int m = 0; m < 4; ++m) W[m * g.nc + c] = 0.0;
+        q[c] = q[g.nc + c] = 0.0;
+        return;
+    }
+    double M[NRAW];
+    for (int m = 0; m < NRAW; ++m) {
+        double s = 0.0;
+        for (int j = 0; j < nkc; ++j) s += part[((size_t)j * NRAW + m) * g.nc + c];
+        M[m] = s;
+    }
+    double w4[4], q2[2];
+    raw_to_macro(M, w4, q2);
+    for (int m = 0; m < 4; ++m) W[m * g.nc + c] = w4[m];
+    q[c] = q2[0];
+    q[g.nc + c] = q2[1];
+}
+
+// total mass sum_c V_c rho_c over fluid cells (one block)
+__global__ void k_mass(Geo g, const double* __restrict__ W, double* __restrict__ out) {
+    __shared__ double sh[1024];
+    double s = 0.0;
+    for (int c = threadIdx.x; c < g.nc; c += blockDim.x)
+        if (!g.solid[c]) s += g.dx[c % g.nx] * g.dy[c / g.nx] * W[c];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// closed-domain renormalisation f *= M0 / M (and W, q alike)
+template <typename T>
+__global__ void k_scale_f(T* __restrict__ f, size_t n, const double* __restrict__ mass, double M0) {
+    double s = M0 / mass[0];
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        f[i] = T(double(f[i]) * s);
+}
+
+__global__ void k_scale_d(double* __restrict__ a, size_t n, const double* __restrict__ mass, double M0) {
+    double s = M0 / mass[0];
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        a[i] *= s;
+}
+
+// ---------------------------------------------------------------------------
+// Step 1, interface reconstruction (Sec. II A 1; UGKS flux).  Every interior
+// face is the -x or -y face of exactly one cell R with neighbour L across it.
+
+// limited slopes of the two cells of the face on side (2d) of cell c, and the
+// upwind interface values for one velocity.  Returns false if not interior.
+template <typename T>
+__device__ __forceinline__ bool face_upwind(const Geo& g, int c, int d, const T* __restrict__ F, int nk,
+                                            int k, T un, T& Gup, T& Hup, T& sGup, T& sHup) {
+    int nc = g.nc;
+    int L = g.nb[(2 * d) * nc + c];
+    if (L < 0) return false;
+    int LL = g.nb[(2 * d) * nc + L];
+    int RR = g.nb[(2 * d + 1) * nc + c];
+    size_t ho = (size_t)nk * nc;
+    size_t kc = (size_t)k * nc;
+    T dcLR = T(g.dcent[(2 * d) * nc + c]);
+    T dL = T(0.5) * T(d == 0 ? g.dx[L % g.nx] : g.dy[L / g.nx]);
+    T dR = T(0.5) * T(d == 0 ? g.dx[c % g.nx] : g.dy[c / g.nx]);
+    T GL = F[kc + L], GR = F[kc + c], HL = F[ho + kc + L], HR = F[ho + kc + c];
+    T gLR = (GR - GL) / dcLR, hLR = (HR - HL) / dcLR;
+    T sGL = 0, sHL = 0, sGR = 0, sHR = 0;
+    if (un >= T(0)) {   // left slope needed (and both for un == 0)
+        T gm = 0, hm = 0;
+        if (LL >= 0) {
+            T dc = T(g.dcent[(2 * d) * nc + L]);
+            gm = (GL - F[kc + LL]) / dc;
+            hm = (HL - F[ho + kc + LL]) / dc;
+        }
+        sGL = van_leer(gm, gLR);
+        sHL = van_leer(hm, hLR);
+    }
+    if (un <= T(0)) {
+        T gp = 0, hp = 0;
+        if (RR >= 0) {
+            T dc = T(g.dcent[(2 * d + 1) * nc + c]);
+            gp = (F[kc + RR] - GR) / dc;
+            hp = (F[ho + kc + RR] - HR) / dc;
+        }
+        sGR = van_leer(gLR, gp);
+        sHR = van_leer(hLR, hp);
+    }
+    if (un > T(0)) {
+        Gup = GL + sGL * dL;
+        Hup = HL + sHL * dL;
+        sGup = sGL;
+        sHup = sHL;
+    } else if (un < T(0)) {
+        Gup = GR - sGR * dR;
+        Hup = HR - sHR * dR;
+        sGup = sGR;
+        sHup = sHR;
+    } else {
+        Gup = T(0.5) * (GL + sGL * dL + GR - sGR * dR);
+        Hup = T(0.5) * (HL + sHL * dL + HR - sHR * dR);
+        sGup = T(0.5) * (sGL + sGR);
+        sHup = T(0.5) * (sHL + sHR);
+    }
+    return true;
+}
+
+// raw moments of the upwind interface distribution of the -x and -y faces
+template <typename T>
+__global__ void __launch_bounds__(256) k_face_moments_partial(Geo g, Vel vel, const T* __restrict__ f,
+                                                              double* __restrict__ part) {
+    __shared__ double sh[2 * NRAW * WAVES * TILE];
+    Chunk ch = chunk_of(g.nc, vel.nk);
+    double a[2 * NRAW];
+    for (int m = 0; m < 2 * NRAW; ++m) a[m] = 0.0;
+    if (ch.valid && !g.solid[ch.c]) {
+        for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
+            T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
+            double w = vel.w[k];
+            for (int d = 0; d < 2; ++d) {
+                T Gup, Hup, sG, sH;
+                if (face_upwind<T>(g, ch.c, d, f, vel.nk, k, d == 0 ? u : v, Gup, Hup, sG, sH))
+                    raw_accumulate(a + d * NRAW, w, vel.u[k], vel.v[k], double(Gup), double(Hup));
+            }
+        }
+    }
+    reduce_store<2 * NRAW>(a, sh, part, g.nc, ch.c, ch.valid);
+}
+
+// Interface record, per (direction d, cell c) = the face on side 2d of c:
+//  0 rho0  1 U0  2 V0  3 lam0  4,5 Shakhov coefficients 0.8(1-Pr) lam0^2 q0 / rho0
+//  6-9 abar left  10-13 abar right  14-17 Abar  18-22 q1..q5 / dt  23 interior flag
+__global__ void k_face_finalize(Geo g, Gas gas, const double* __restrict__ part, int nkc,
+                                const double* __restrict__ W, double* __restrict__ fp) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nc) return;
+    size_t stride = 2 * (size_t)g.nc;
+    for (int d = 0; d < 2; ++d) {
+        double* rec = fp + (size_t)d * g.nc + c;
+        int L = g.nb[(2 * d) * g.nc + c];
+        if (g.solid[c] || L < 0) {
+            for (int m = 0; m < NFP; ++m) rec[m * stride] = 0.0;
+            continue;
+        }
+        double M[NRAW];
+        for (int m = 0; m < NRAW; ++m) {
+            double s = 0.0;
+            for (int j = 0; j < nkc; ++j) s += part[((size_t)j * 2 * NRAW + d * NRAW + m) * g.nc + c];
+            M[m] = s;
+        }
+        double W0[4], q0[2];
+        raw_to_macro(M, W0, q0);
+        double rho, U, V, lam;
+        prim_of(W0, gas.K, rho, U, V, lam);
+        double tau = mu_of(gas, 1.0 / lam) / (rho / (2.0 * lam));
+        double dt = fmin(g.dt[L], g.dt[c]);
+        double q[5];
+        time_coeffs(dt, tau, q);
+        double dL = 0.5 * (d == 0 ? g.dx[L % g.nx] : g.dy[L / g.nx]);
+        double dR = 0.5 * (d == 0 ? g.dx[c % g.nx] : g.dy[c / g.nx]);
+        double bL[4], bR[4], aL[4], aR[4];
+        for (int m = 0; m < 4; ++m) {
+            bL[m] = (W0[m] - W[m * g.nc + L]) / dL / rho;
+            bR[m] = (W[m * g.nc + c] - W0[m]) / dR / rho;
+        }
+        micro_slope(bL, U, V, lam, gas.K, aL);
+        micro_slope(bR, U, V, lam, gas.K, aR);
+        double sh = 0.8 * (1.0 - gas.Pr) * lam * lam / rho;
+        double vals[NFP] = {rho, U, V, lam, sh * q0[0], sh * q0[1],
+                            aL[0], aL[1], aL[2], aL[3], aR[0], aR[1], aR[2], aR[3],
+                            0, 0, 0, 0,
+                            q[0] / dt, q[1] / dt, q[2] / dt, q[3] / dt, q[4] / dt, 1.0};
+        for (int m = 0; m < NFP; ++m) rec[m * stride] = vals[m];
+    }
+}
+
+// G- and H-parts of (a1 + a2 u + a3 v + a4 (u^2+v^2+xi^2)/2) times the
+// Maxwellian after integration over the K_int extra components
+template <typename T>
+__device__ __forceinline__ void slope_poly(const T* a, T u, T v, T lam, int K_int, T& pG, T& pH) {
+    pG = a[0] + a[1] * u + a[2] * v + T(0.5) * a[3] * (u * u + v * v) + T(0.5) * a[3] * T(K_int) / (T(2) * lam);
+    pH = pG + a[3] / (T(2) * lam);
+}
+
+// time slope Abar from the compatibility condition (discrete form):
+// <Abar psi g0> = -sum_k w u_n (abar_side g0) psi
+template <typename T>
+__global__ void __launch_bounds__(256) k_face_timeslope_partial(Geo g, Vel vel, Gas gas,
+                                                                const double* __restrict__ fp,
+                                                                double* __restrict__ part) {
+    __shared__ double sh[8 * WAVES * TILE];
+    Chunk ch = chunk_of(g.nc, vel.nk);
+    double a[8];
+    for (int m = 0; m < 8; ++m) a[m] = 0.0;
+    if (ch.valid && !g.solid[ch.c]) {
+        size_t stride = 2 * (size_t)g.nc;
+        for (int d = 0; d < 2; ++d) {
+            const double* rec = fp + (size_t)d * g.nc + ch.c;
+            if (rec[23 * stride] == 0.0) continue;
+            T rho = T(rec[0]), U = T(rec[stride]), V = T(rec[2 * stride]), lam = T(rec[3 * stride]);
+            T aL[4], aR[4];
+            for (int m = 0; m < 4; ++m) {
+                aL[m] = T(rec[(6 + m) * stride]);
+                aR[m] = T(rec[(10 + m) * stride]);
+            }
+            T pref = rho * lam / T(M_PI);
+            for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
+                T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
+                T un = d == 0 ? u : v;
+                T du = u - U, dv = v - V;
+                T G0 = pref * dexp(-lam * (du * du + dv * dv));
+                T H0 = T(gas.K_int) / (T(2) * lam) * G0;
+                T pG, pH, qG, qH;
+                slope_poly<T>(un > T(0) ? aL : aR, u, v, lam, gas.K_int, pG, pH);
+                if (un == T(0)) {
+                    slope_poly<T>(aL, u, v, lam, gas.K_int, pG, pH);
+                    slope_poly<T>(aR, u, v, lam, gas.K_int, qG, qH);
+                    pG = T(0.5) * (pG + qG);
+                    pH = T(0.5) * (pH + qH);
+                }
+                double sG = double(un) * double(pG * G0), sH = double(un) * double(pH * H0);
+                double w = vel.w[k], ud = vel.u[k], vd = vel.v[k];
+                a[4 * d + 0] += w * sG;
+                a[4 * d + 1] += w * ud * sG;
+                a[4 * d + 2] += w * vd * sG;
+                a[4 * d + 3] += 0.5 * w * ((ud * ud + vd * vd) * sG + sH);
+            }
+        }
+    }
+    reduce_store<8>(a, sh, part, g.nc, ch.c, ch.valid);
+}
+
+__global__ void k_face_timeslope_finalize(Geo g, Gas gas, const double* __restrict__ part, int nkc,
+                                          double* __restrict__ fp) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nc) return;
+    size_t stride = 2 * (size_t)g.nc;
+    for (int d = 0; d < 2; ++d) {
+        double* rec = fp + (size_t)d * g.nc + c;
+        if (rec[23 * stride] == 0.0) continue;
+        double rho = rec[0], U = rec[stride], V = rec[2 * stride], lam = rec[3 * stride];
+        double b[4], A[4];
+        for (int m = 0; m < 4; ++m) {
+            double s = 0.0;
+            for (int j = 0; j < nkc; ++j) s += part[((size_t)j * 8 + 4 * d + m) * g.nc + c];
+            b[m] = -s / rho;
+        }
+        micro_slope(b, U, V, lam, gas.K, A);
+        for (int m = 0; m < 4; ++m) rec[(14 + m) * stride] = A[m];
+    }
+}
+
+// diffuse-wall density from zero mass flux: out[j] = -sum_{u_n>0} w u_n G / den_j
+// (Sec. III B); G is the first (G) plane of f or of a correction
+template <typename T>
+__global__ void __launch_bounds__(256) k_wall_partial(Geo g, Vel vel, const T* __restrict__ G,
+                                                      double* __restrict__ part) {
+    __shared__ double sh[WAVES * TILE];
+    Chunk ch = chunk_of(g.n_wall, vel.nk);
+    double a[1] = {0.0};
+    if (ch.valid) {
+        int j = ch.c, c = g.w_cell[j], s = g.w_side[j];
+        double sign = (s & 1) ? 1.0 : -1.0;
+        for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
+            double un = sign * (s < 2 ? vel.u[k] : vel.v[k]);
+            if (un > 0) a[0] += vel.w[k] * un * double(G[(size_t)k * g.nc + c]);
+        }
+    }
+    reduce_store<1>(a, sh, part, g.n_wall, ch.c, ch.valid);
+}
+
+__global__ void k_wall_finalize(Geo g, const double* __restrict__ part, int nkc, double* __restrict__ out) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= g.n_wall) return;
+    double s = 0.0;
+    for (int i = 0; i < nkc; ++i) s += part[(size_t)i * g.n_wall + j];
+    out[j] = -s / g.w_den[j];
+}
+
+// UGKS time-averaged flux of G and H through an interior face for one
+// velocity, normal pointing from L to R (Sec. II A 1; see the interface record)
+template <typename T>
+__device__ __forceinline__ void face_flux(const T* P, T u, T v, T un, T Gup, T Hup, T sGup, T sHup,
+                                          int K_int, T& PG, T& PH) {
+    T rho = P[0], U = P[1], V = P[2], lam = P[3];
+    T cx = u - U, cy = v - V, c2 = cx * cx + cy * cy;
+    T G0 = rho * lam / T(M_PI) * dexp(-lam * c2);
+    T H0 = T(K_int) / (T(2) * lam) * G0;
+    T sk = P[4] * cx + P[5] * cy;
+    T Geq = G0 * (T(1) + sk * (T(2) * lam * c2 + T(K_int) - T(5)));
+    T Heq = H0 * (T(1) + sk * (T(2) * lam * c2 + T(K_int) - T(3)));
+    T aG, aH, bG, bH;
+    if (un > T(0)) {
+        slope_poly<T>(P + 6, u, v, lam, K_int, aG, aH);
+    } else {
+        slope_poly<T>(P + 10, u, v, lam, K_int, aG, aH);
+    }
+    slope_poly<T>(P + 14, u, v, lam, K_int, bG, bH);
+    PG = un * (P[18] * Geq + P[19] * un * aG * G0 + P[20] * bG * G0 + P[21] * Gup + P[22] * un * sGup);
+    PH = un * (P[18] * Heq + P[19] * un * aH * H0 + P[20] * bH * H0 + P[21] * Hup + P[22] * un * sHup);
+}
+
+// Step 1: div_ik = (1/V_i) sum_faces S u_n ftilde (outward) for G and H, and
+// partial sums of the macroscopic residual R_i = -sum_k w psi div_ik
+template <typename T>
+__global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const T* __restrict__ f,
+                                                  const double* __restrict__ fp,
+                                                  const double* __restrict__ rho_w,
+                                                  const T* __restrict__ finf, T* __restrict__ div,
+                                                  double* __restrict__ part) {
+    __shared__ double sh[4 * WAVES * TILE];
+    Chunk ch = chunk_of(g.nc, vel.nk);
+    double acc[4] = {0, 0, 0, 0};
+    int c = ch.c;
+    if (ch.valid) {
+        size_t nc = g.nc, ho = (size_t)vel.nk * nc;
+        int nk = vel.nk;
+        int kk[MK];
+        int nmine = 0;
+        for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) kk[nmine++] = k;
+        T dG[MK], dH[MK];
+        for (int j = 0; j < MK; ++j) dG[j] = dH[j] = T(0);
+        bool fluid = !g.solid[c];
+        int ix = c % g.nx, iy = c / g.nx;
+        if (fluid) {
+            for (int s = 0; s < 4; ++s) {
+                int code = g.nb[s * g.nc + c];
+                int d = s >> 1;
+                T sign = (s & 1) ? T(1) : T(-1);
+                T sv = T(1.0 / (d == 0 ? g.dx[ix] : g.dy[iy]));   // S / V
+                if (code >= 0) {
+                    // face record: the -d face of the cell on the positive side
+                    int R = (s & 1) ? code : c;
+                    const double* rec = fp + (size_t)d * g.nc + R;
+                    size_t stride = 2 * nc;
+                    T P[23];
+                    for (int m = 0; m < 23; ++m) P[m] = T(rec[m * stride]);
+                    for (int j = 0; j < nmine; ++j) {
+                        int k = kk[j];
+                        T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
+                        T un = d == 0 ? u : v;
+                        T Gup, Hup, sGu, sHu, PG, PH;
+                        face_upwind<T>(g, R, d, f, nk, k, un, Gup, Hup, sGu, sHu);
+                        face_flux<T>(P, u, v, un, Gup, Hup, sGu, sHu, gas.K_int, PG, PH);
+                        dG[j] += sign * sv * PG;
+                        dH[j] += sign * sv * PH;
+                    }
+                } else if (is_wall(code)) {
+                    int jw = wall_of(code);
+                    T lam = T(1.0 / g.w_T[jw]), Uw = T(g.w_U[jw]), Vw = T(g.w_V[jw]);
+                    T rw = T(rho_w[jw]);
+                    for (int j = 0; j < nmine; ++j) {
+                        int k = kk[j];
+                        T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
+                        T un = sign * (d == 0 ? u : v);
+                        T Gf, Hf;
+                        if (un > T(0)) {
+                            Gf = f[(size_t)k * nc + c];
+                            Hf = f[ho + (size_t)k * nc + c];
+                        } else {
+                            T du = u - Uw, dv = v - Vw;
+                            T C = lam / T(M_PI) * dexp(-lam * (du * du + dv * dv));
+                            Gf = rw * C;
+                            Hf = rw * T(gas.K_int) / (T(2) * lam) * C;
+                        }
+                        dG[j] += sv * un * Gf;
+                        dH[j] += sv * un * Hf;
+                    }
+                } else {
+                    bool far = code == NB_FARFIELD;
+                    for (int j = 0; j < nmine; ++j) {
+                        int k = kk[j];
+                        T un = sign * (d == 0 ? vel_u<T>(vel, k) : vel_v<T>(vel, k));
+                        T Gf, Hf;
+                        if (far && un <= T(0)) {
+                            Gf = finf[k];
+                            Hf = finf[nk + k];
+                        } else {
+                            Gf = f[(size_t)k * nc + c];
+                            Hf = f[ho + (size_t)k * nc + c];
+                        }
+                        dG[j] += sv * un * Gf;
+                        dH[j] += sv * un * Hf;
+                    }
+                }
+            }
+        }
+        for (int j = 0; j < nmine; ++j) {
+            int k = kk[j];
+            div[(size_t)k * nc + c] = dG[j];
+            div[ho + (size_t)k * nc + c] = dH[j];
+            double w = vel.w[k], u = vel.u[k], v = vel.v[k];
+            double gd = double(dG[j]), hd = double(dH[j]);
+            acc[0] += w * gd;
+            acc[1] += w * u * gd;
+            acc[2] += w * v * gd;
+            acc[3] += 0.5 * w * ((u * u + v * v) * gd + hd);
+        }
+    }
+    reduce_store<4>(acc, sh, part, g.nc, c, ch.valid);
+}
+
+__global__ void k_residual_finalize(Geo g, const double* __restrict__ part, int nkc, double* __restrict__ R) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nc) return;
+    for (int m = 0; m < 4; ++m) {
+        double s = 0.0;
+        for (int j = 0; j < nkc; ++j) s += part[((size_t)j * 4 + m) * g.nc + c];
+        R[m * g.nc + c] = g.solid[c] ? 0.0 : -s;
+    }
+}
+
+// RMS residual of each conservative variable over fluid cells (Sec. IV A), one block
+__global__ void k_residual_norm(Geo g, int n_fluid, const double* __restrict__ R, double* __restrict__ out) {
+    __shared__ double sh[4][256];
+    double s[4] = {0, 0, 0, 0};
+    for (int c = threadIdx.x; c < g.nc; c += blockDim.x)
+        if (!g.solid[c])
+            for (int m = 0; m < 4; ++m) {
+                double r = R[m * g.nc + c];
+                s[m] += r * r;
+            }
+    for (int m = 0; m < 4; ++m) sh[m][threadIdx.x] = s[m];
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int m = 0; m < 4; ++m) sh[m][threadIdx.x] += sh[m][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[threadIdx.x] = sqrt(sh[threadIdx.x][0] / n_fluid);
+}
+
+// ---------------------------------------------------------------------------
+// Steps 3-4: predicted Shakhov equilibrium and micro residual
+
+// positivity guard, then per-cell record {rho lam/pi, U, V, lam, shx, shy, 1/tau}
+__global__ void k_cell_prep(Geo g, Gas gas, double* __restrict__ Wt, const double* __restrict__ Wn,
+                            const double* __restrict__ q, double* __restrict__ cp, double* __restrict__ tau_inv) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nc) return;
+    if (g.solid[c]) {
+        for (int m = 0; m < NCP; ++m) cp[m * g.nc + c] = 0.0;
+        tau_inv[c] = 0.0;
+        return;
+    }
+    double w[4];
+    for (int m = 0; m < 4; ++m) w[m] = Wt[m * g.nc + c];
+    double rho, U, V, lam;
+    prim_of(w, gas.K, rho, U, V, lam);
+    if (!(rho > 0.0) || !(lam > 0.0) || !isfinite(lam)) {
+        for (int m = 0; m < 4; ++m) Wt[m * g.nc + c] = w[m] = Wn[m * g.nc + c];
+        prim_of(w, gas.K, rho, U, V, lam);
+    }
+    double ti = (rho / (2.0 * lam)) / mu_of(gas, 1.0 / lam);
+    double sh = 0.8 * (1.0 - gas.Pr) * lam * lam / rho;
+    double vals[NCP] = {rho * lam / M_PI, U, V, lam, sh * q[c], sh * q[g.nc + c], ti};
+    for (int m = 0; m < NCP; ++m) cp[m * g.nc + c] = vals[m];
+    tau_inv[c] = ti;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_micro_residual(Geo g, Vel vel, Gas gas, const T* __restrict__ f,
+                                                        const T* __restrict__ div,
+                                                        const double* __restrict__ cp, T* __restrict__ r) {
+    Chunk ch = chunk_of(g.nc, vel.nk);
+    if (!ch.valid) return;
+    int c = ch.c;
+    size_t nc = g.nc, ho = (size_t)vel.nk * nc;
+    bool fluid = !g.solid[c];
+    T pref = T(cp[c]), U = T(cp[nc + c]), V = T(cp[2 * nc + c]), lam = T(cp[3 * nc + c]);
+    T shx = T(cp[4 * nc + c]), shy = T(cp[5 * nc + c]), ti = T(cp[6 * nc + c]);
+    for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
+        size_t ig = (size_t)k * nc + c;
+        if (!fluid) {
+            r[ig] = T(0);
+            r[ho + ig] = T(0);
+            continue;
+        }
+        T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
+        T cx = u - U, cy = v - V, c2 = cx * cx + cy * cy;
+        T G0 = pref * dexp(-lam * c2);
+        T H0 = T(gas.K_int) / (T(2) * lam) * G0;
+        T sk = shx * cx + shy * cy;
+        T Gt = G0 * (T(1) + sk * (T(2) * lam * c2 + T(gas.K_int) - T(5)));
+        T Ht = H0 * (T(1) + sk * (T(2) * lam * c2 + T(gas.K_int) - T(3)));
+        r[ig] = (Gt - f[ig]) * ti - div[ig];
+        r[ho + ig] = (Ht - f[ho + ig]) * ti - div[ho + ig];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Step 5: correction equation (Sec. II A 2) on one level.
+
+// transport part of the diagonal D_ik (outgoing normal speeds over the
+// sides; an outflow side adds its inflow speed as well)
+template <typename T>
+__device__ __forceinline__ T transport_diag(const Geo& g, int c, T u, T v) {
+    T invx = T(1.0 / g.dx[c % g.nx]), invy = T(1.0 / g.dy[c / g.nx]);
+    T D = T(0);
+    for (int s = 0; s < 4; ++s) {
+        T un = ((s & 1) ? T(1) : T(-1)) * (s < 2 ? u : v);
+        T a = g.nb[s * g.nc + c] == NB_OUTFLOW ? un : (un > T(0) ? un : T(0));
+        D += a * (s < 2 ? invx : invy);
+    }
+    return D;
+}
+
+// D_jk times the correction across the upwind side s of cell c (the side
+// with negative normal speed): neighbour value (passed in), wall ghost
+// C_k drho_w, or zero (farfield; outflow lives on the diagonal)
+template <typename T>
+__device__ __forceinline__ void upwind_term(const Geo& g, int c, int s, T u, T v, int K_int, T nbG, T nbH,
+                                            const double* __restrict__ drho, T& tG, T& tH) {
+    int code = g.nb[s * g.nc + c];
+    T un = ((s & 1) ? T(1) : T(-1)) * (s < 2 ? u : v);
+    T coef = (un < T(0) ? un : T(0)) * T(1.0 / (s < 2 ? g.dx[c % g.nx] : g.dy[c / g.nx]));
+    if (code >= 0) {
+        tG = coef * nbG;
+        tH = coef * nbH;
+    } else if (is_wall(code)) {
+        int j = wall_of(code);
+        T lam = T(1.0 / g.w_T[j]);
+        T du = u - T(g.w_U[j]), dv = v - T(g.w_V[j]);
+        T C = lam / T(M_PI) * dexp(-lam * (du * du + dv * dv));
+        T dr = T(drho[j]);
+        tG = coef * C * dr;
+        tH = coef * T(K_int) / (T(2) * lam) * C * dr;
+    } else {
+        tG = T(0);
+        tH = T(0);
+    }
+}
+
+// One Gauss-Seidel sweep of every velocity in its own upwind order (the
+// LU-SGS sweep of Sec. II A 2 taken along the direction of each velocity):
+// block k sweeps velocity k; thread t owns row t (counted from the upwind
+// y-side) and processes column s - t at step s, so each cell sees its
+// x-upwind neighbour from its own previous step and its y-upwind neighbour
+// from thread t-1's previous step (through LDS).  Wall densities drho are
+// those of the correction before the sweep.
+template <typename T>
+__global__ void k_sweep(Geo g, Vel vel, int K_int, const T* __restrict__ r, T* __restrict__ df,
+                        const double* __restrict__ tau_inv, const double* __restrict__ dtn_inv,
+                        const double* __restrict__ drho) {
+    __shared__ T bufG[2][1024];
+    __shared__ T bufH[2][1024];
+    int k = blockIdx.x, t = threadIdx.x;
+    int nx = g.nx, ny = g.ny;
+    size_t nc = g.nc, ho = (size_t)vel.nk * nc, kc = (size_t)k * nc;
+    T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
+    bool px = u >= T(0), py = v >= T(0);
+    int upx = px ? 0 : 1, upy = py ? 2 : 3;
+    int iy = py ? t : ny - 1 - t;
+    bool row = t < ny;
+    T carryG = 0, carryH = 0;
+    int nsteps = nx + ny - 1;
+    for (int s = 0; s < nsteps; ++s) {
+        int jx = s - t;
+        T nG = 0, nH = 0;
+        if (row && jx >= 0 && jx < nx) {
+            int ix = px ? jx : nx - 1 - jx;
+            int c = iy * nx + ix;
+            if (!g.solid[c]) {
+                T D = T(tau_inv[c]) + T(dtn_inv[c]) + transport_diag<T>(g, c, u, v);
+                T upG = t > 0 ? bufG[(s - 1) & 1][t - 1] : T(0);
+                T upH = t > 0 ? bufH[(s - 1) & 1][t - 1] : T(0);
+                T xG, xH, yG, yH;
+                upwind_term<T>(g, c, upx, u, v, K_int, carryG, carryH, drho, xG, xH);
+                upwind_term<T>(g, c, upy, u, v, K_int, upG, upH, drho, yG, yH);
+                nG = (r[kc + c] - xG - yG) / D;
+                nH = (r[ho + kc + c] - xH - yH) / D;
+                df[kc + c] = nG;
+                df[ho + kc + c] = nH;
+            }
+            carryG = nG;
+            carryH = nH;
+        }
+        bufG[s & 1][t] = nG;
+        bufH[s & 1][t] = nH;
+        __syncthreads();
+    }
+}
+
+// renewed residual r - A df on the fine level, restricted to the coarse
+// level by the volume-weighted mean (Sec. II C 1); thread per coarse cell
+template <typename T>
+__global__ void __launch_bounds__(256) k_defect_restrict(Geo g, Geo gc, Vel vel, int K_int,
+                                                         const T* __restrict__ r, const T* __restrict__ df,
+                                                         const double* __restrict__ tau_inv,
+                                                         const double* __restrict__ dtn_inv,
+                                                         const double* __restrict__ drho,
+                                                         T* __restrict__ rc) {
+    Chunk ch = chunk_of(gc.nc, vel.nk);
+    if (!ch.valid) return;
+    int C = ch.c, I = C % gc.nx, J = C / gc.nx;
+    size_t nc = g.nc, ho = (size_t)vel.nk * nc, ncc = gc.nc, hoc = (size_t)vel.nk * ncc;
+    for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
+        T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
+        size_t kc = (size_t)k * nc;
+        double sG = 0.0, sH = 0.0, vol = 0.0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                int c = (2 * J + a) * g.nx + 2 * I + b;
+                if (g.solid[c]) continue;
+                T D = T(tau_inv[c]) + T(dtn_inv[c]) + transport_diag<T>(g, c, u, v);
+                int sx = u >= T(0) ? 0 : 1, sy = v >= T(0) ? 2 : 3;
+                int ox = g.nb[sx * g.nc + c], oy = g.nb[sy * g.nc + c];
+                T xnG = ox >= 0 ? df[kc + ox] : T(0), xnH = ox >= 0 ? df[ho + kc + ox] : T(0);
+                T ynG = oy >= 0 ? df[kc + oy] : T(0), ynH = oy >= 0 ? df[ho + kc + oy] : T(0);
+                T xG, xH, yG, yH;
+                upwind_term<T>(g, c, sx, u, v, K_int, xnG, xnH, drho, xG, xH);
+                upwind_term<T>(g, c, sy, u, v, K_int, ynG, ynH, drho, yG, yH);
+                T eG = r[kc + c] - D * df[kc + c] - xG - yG;
+                T eH = r[ho + kc + c] - D * df[ho + kc + c] - xH - yH;
+                double V = g.dx[c % g.nx] * g.dy[c / g.nx];
+                sG += V * double(eG);
+                sH += V * double(eH);
+                vol += V;
+            }
+        size_t o = (size_t)k * ncc + C;
+        rc[o] = vol > 0 ? T(sG / vol) : T(0);
+        rc[hoc + o] = vol > 0 ? T(sH / vol) : T(0);
+    }
+}
+
+// df_fine += I_H^h df_coarse (bilinear with extrapolation, Sec. II C 3)
+template <typename T>
+__global__ void __launch_bounds__(256) k_prolong_add(Geo g, Vel vel, int ncc, const T* __restrict__ dfc,
+                                                     T* __restrict__ df) {
+    Chunk ch = chunk_of(g.nc, vel.nk);
+    if (!ch.valid) return;
+    int c = ch.c;
+    if (g.solid[c]) return;
+    size_t nc = g.nc, ho = (size_t)vel.nk * nc, hoc = (size_t)vel.nk * ncc;
+    int id[4];
+    T w[4];
+    for (int a = 0; a < 4; ++a) {
+        id[a] = g.p_idx[a * g.nc + c];
+        w[a] = T(g.p_w[a * g.nc + c]);
+    }
+    for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
+        size_t kc = (size_t)k * ncc;
+        T aG = w[0] * dfc[kc + id[0]] + w[1] * dfc[kc + id[1]] + w[2] * dfc[kc + id[2]] + w[3] * dfc[kc + id[3]];
+        T aH = w[0] * dfc[hoc + kc + id[0]] + w[1] * dfc[hoc + kc + id[1]] + w[2] * dfc[hoc + kc + id[2]] +
+               w[3] * dfc[hoc + kc + id[3]];
+        df[(size_t)k * nc + c] += aG;
+        df[ho + (size_t)k * nc + c] += aH;
+    }
+}
+
+// restrict a per-cell double field (volume-weighted mean over fluid children)
+__global__ void k_restrict_cells(Geo g, Geo gc, int m, const double* __restrict__ a, double* __restrict__ ac) {
+    int C = blockIdx.x * blockDim.x + threadIdx.x;
+    if (C >= gc.nc) return;
+    int I = C % gc.nx, J = C / gc.nx;
+    for (int q = 0; q < m; ++q) {
+        double s = 0.0, vol = 0.0;
+        for (int aa = 0; aa < 2; ++aa)
+            for (int b = 0; b < 2; ++b) {
+                int c = (2 * J + aa) * g.nx + 2 * I + b;
+                if (g.solid[c]) continue;
+                double V = g.dx[c % g.nx] * g.dy[c / g.nx];
+                s += V * a[(size_t)q * g.nc + c];
+                vol += V;
+            }
+        ac[(size_t)q * gc.nc + C] = vol > 0 ? s / vol : 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Step 2: FAS cycle of the macroscopic prediction (Sec. II A 1, Sec. II C 2)
+
+__device__ __forceinline__ void euler_flux(const double* W, int d, double sign, double K, double* F) {
+    double rho = W[0], U = W[1] / rho, V = W[2] / rho;
+    double p = (2.0 / K) * (W[3] - 0.5 * rho * (U * U + V * V));
+    double un = sign * (d == 0 ? U : V);
+    F[0] = rho * un;
+    F[1] = W[1] * un + (d == 0 ? sign * p : 0.0);
+    F[2] = W[2] * un + (d == 1 ? sign * p : 0.0);
+    F[3] = (W[3] + p) * un;
+}
+
+// state across side s of cell c: neighbour, wall ghost (Sec. III B wall
+// relation), freestream or copy; kind 0 interior, 1 farfield, 2 outflow, 3 wall
+__device__ __forceinline__ int side_state(const Geo& g, const Gas& gas, const double* W, int c, int s,
+                                          const double* Wi, double* Wj, int& wall) {
+    int code = g.nb[s * g.nc + c];
+    if (code >= 0) {
+        for (int m = 0; m < 4; ++m) Wj[m] = W[m * g.nc + code];
+        return 0;
+    }
+    if (code == NB_FARFIELD) {
+        for (int m = 0; m < 4; ++m) Wj[m] = gas.W_inf[m];
+        return 1;
+    }
+    if (code == NB_OUTFLOW) {
+        for (int m = 0; m < 4; ++m) Wj[m] = Wi[m];
+        return 2;
+    }
+    wall = wall_of(code);
+    double rho, U, V, lam;
+    prim_of(Wi, gas.K, rho, U, V, lam);
+    cons_of(rho, 2.0 * g.w_U[wall] - U, 2.0 * g.w_V[wall] - V, 2.0 / g.w_T[wall] - lam, gas.K, Wj);
+    return 3;
+}
+
+__global__ void k_fas_gamma(Geo g, Gas gas, const double* __restrict__ W, double* __restrict__ Gam) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nc) return;
+    if (g.solid[c]) {
+        for (int s = 0; s < 4; ++s) Gam[s * g.nc + c] = 0.0;
+        return;
+    }
+    double Wi[4], Wj[4];
+    for (int m = 0; m < 4; ++m) Wi[m] = W[m * g.nc + c];
+    double ri, Ui, Vi, li;
+    prim_of(Wi, gas.K, ri, Ui, Vi, li);
+    for (int s = 0; s < 4; ++s) {
+        int wall = -1;
+        side_state(g, gas, W, c, s, Wi, Wj, wall);
+        double rj, Uj, Vj, lj;
+        prim_of(Wj, gas.K, rj, Uj, Vj, lj);
+        double rm = 0.5 * (ri + rj), Um = 0.5 * (Ui + Uj), Vm = 0.5 * (Vi + Vj);
+        double Tm = 0.5 * (1.0 / li + 1.0 / lj);
+        double un = fabs(s < 2 ? Um : Vm);
+        double as = sqrt(gas.gamma * Tm / 2.0);
+        double nu = mu_of(gas, Tm) / rm;
+        Gam[s * g.nc + c] = un + as + 2.0 * nu / g.dcent[s * g.nc + c];
+    }
+}
+
+// out = base + sgn * R_split(W), R_split_i = -(1/V_i) sum_j S_ij F_ij(W)
+__global__ void k_fas_rsplit(Geo g, Gas gas, const double* __restrict__ W, const double* __restrict__ Gam,
+                             const double* __restrict__ base, double sgn, double* __restrict__ out) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nc) return;
+    if (g.solid[c]) {
+        for (int m = 0; m < 4; ++m) out[m * g.nc + c] = 0.0;
+        return;
+    }
+    double Wi[4], Wj[4], Fi[4], Fj[4], acc[4] = {0, 0, 0, 0};
+    for (int m = 0; m < 4; ++m) Wi[m] = W[m * g.nc + c];
+    double dx = g.dx[c % g.nx], dy = g.dy[c / g.nx];
+    for (int s = 0; s < 4; ++s) {
+        int wall = -1;
+        side_state(g, gas, W, c, s, Wi, Wj, wall);
+        int d = s >> 1;
+        double sign = (s & 1) ? 1.0 : -1.0;
+        euler_flux(Wi, d, sign, gas.K, Fi);
+        euler_flux(Wj, d, sign, gas.K, Fj);
+        double S = d == 0 ? dy : dx, G = Gam[s * g.nc + c];
+        for (int m = 0; m < 4; ++m) acc[m] += S * 0.5 * (Fi[m] + Fj[m] + G * (Wi[m] - Wj[m]));
+    }
+    double V = dx * dy;
+    for (int m = 0; m < 4; ++m) out[m * g.nc + c] = base[m * g.nc + c] + sgn * (-acc[m] / V);
+}
+
+// one red-black half-sweep of the linearised defect equation of Sec. II A 1
+__global__ void k_fas_halfsweep(Geo g, Gas gas, const double* __restrict__ W, double* __restrict__ E,
+                                const double* __restrict__ Rm, const double* __restrict__ Gam,
+                                const double* __restrict__ dtn_inv, int colour) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nc) return;
+    int ix = c % g.nx, iy = c / g.nx;
+    if (((ix + iy) & 1) != colour || g.solid[c]) return;
+    double Wi[4], Ei[4], Wj[4], Ej[4], A[4], B[4], acc[4] = {0, 0, 0, 0};
+    for (int m = 0; m < 4; ++m) {
+        Wi[m] = W[m * g.nc + c];
+        Ei[m] = E[m * g.nc + c];
+    }
+    double dx = g.dx[ix], dy = g.dy[iy], V = dx * dy, Dsum = 0.0;
+    for (int s = 0; s < 4; ++s) {
+        int wall = -1;
+        int kind = side_state(g, gas, W, c, s, Wi, Wj, wall);
+        int d = s >> 1;
+        double sign = (s & 1) ? 1.0 : -1.0;
+        double S = d == 0 ? dy : dx, G = Gam[s * g.nc + c];
+        if (kind == 0) {
+            int o = g.nb[s * g.nc + c];
+            for (int m = 0; m < 4; ++m) Ej[m] = E[m * g.nc + o];
+        } else if (kind == 1) {
+            for (int m = 0; m < 4; ++m) Ej[m] = 0.0;
+        } else if (kind == 2) {
+            for (int m = 0; m < 4; ++m) Ej[m] = Ei[m];
+        } else {
+            // linearised wall ghost dW_j = J dW_i (Sec. III B), K total degrees of freedom
+            double rho, U, V2, lam;
+            prim_of(Wi, gas.K, rho, U, V2, lam);
+            double Uw = g.w_U[wall], Vw = g.w_V[wall], lw = 1.0 / g.w_T[wall];
+            double Y = lam / (lam - 2.0 * lw);
+            Ej[0] = Ei[0];
+            Ej[1] = 2.0 * Uw * Ei[0] - Ei[1];
+            Ej[2] = 2.0 * Vw * Ei[0] - Ei[2];
+            Ej[3] = (2.0 * (Uw * Uw + Vw * Vw) - 0.5 * (U * U + V2 * V2) * (1.0 + Y * Y) +
+                     gas.K / (4.0 * lam) * (Y * Y - Y)) * Ei[0] +
+                    (U - 2.0 * Uw + U * Y * Y) * Ei[1] + (V2 - 2.0 * Vw + V2 * Y * Y) * Ei[2] - Y * Y * Ei[3];
+        }
+        double WE[4];
+        for (int m = 0; m < 4; ++m) WE[m] = Wj[m] + Ej[m];
+        euler_flux(WE, d, sign, gas.K, A);
+        euler_flux(Wj, d, sign, gas.K, B);
+        for (int m = 0; m < 4; ++m) acc[m] += S * (A[m] - B[m] - G * Ej[m]);
+        Dsum += S * G;
+    }
+    double D = Dsum / (2.0 * V) + dtn_inv[c];
+    for (int m = 0; m < 4; ++m) E[m * g.nc + c] = (Rm[m * g.nc + c] - acc[m] / (2.0 * V)) / D;
+}
+
+// W += E (fluid cells) and clear E
+__global__ void k_fas_apply(Geo g, double* __restrict__ W, double* __restrict__ E) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nc) return;
+    for (int m = 0; m < 4; ++m) {
+        if (!g.solid[c]) W[m * g.nc + c] += E[m * g.nc + c];
+        E[m * g.nc + c] = 0.0;
+    }
+}
+
+// W_fine += I_H^h (W_coarse - W0_coarse)
+__global__ void k_fas_prolong(Geo g, int ncc, const double* __restrict__ Wc, const double* __restrict__ Wc0,
+                              double* __restrict__ W) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nc || g.solid[c]) return;
+    for (int m = 0; m < 4; ++m) {
+        double s = 0.0;
+        for (int a = 0; a < 4; ++a) {
+            int id = g.p_idx[a * g.nc + c];
+            s += g.p_w[a * g.nc + c] * (Wc[(size_t)m * ncc + id] - Wc0[(size_t)m * ncc + id]);
+        }
+        W[m * g.nc + c] += s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// small utilities
+
+template <typename T>
+__global__ void k_zero(T* __restrict__ a, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        a[i] = T(0);
+}
+
+template <typename A, typename B>
+__global__ void k_convert(const A* __restrict__ a, B* __restrict__ b, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b[i] = B(a[i]);
+}
+
+__global__ void k_dtn(Geo g, double factor, double* __restrict__ out) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < g.nc) out[c] = factor > 0.0 ? factor / g.dt[c] : 0.0;
+}
+
+}  // namespace miugks

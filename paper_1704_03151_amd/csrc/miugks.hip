@@ -1,0 +1,849 @@
+// Host driver and C ABI of the MIUGKS library (see include/miugks.h).
+//
+// The outer iteration follows Steps 1-8 of Sec. II D: UGKS residuals, FAS
+// V-cycle of the macroscopic prediction, Shakhov equilibrium and micro
+// residual, CS V-cycle of the correction, update and moments.  All work is
+// enqueued on one HIP stream; the only host round trips are the four
+// residual norms of each cycle (Step 8) and the closed-domain mass check
+// (kept on the device).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "miugks.h"
+#include "setup.hpp"
+
+using namespace miugks;
+
+namespace {
+
+std::string g_create_error;
+
+struct DevLevel {
+    Geo geo;
+    std::vector<void*> owned;
+};
+
+}  // namespace
+
+struct miugks_ctx {
+    std::string err;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int prec = MIUGKS_FP64;
+    size_t esize = 8;
+    int nk = 0, nu = 0, nv = 0, L = 1;
+    int nu1 = 2, nu2 = 1, nuc = 10;
+    double dtn_growth = 0.0;
+    bool renorm = false;
+    HostVel hv;
+    std::vector<HostLevel> hl;
+    std::vector<Geo> geo;
+    Vel vel{};
+    Gas gas{};
+    std::vector<void*> allocs;
+    // level 0
+    void *f = nullptr, *div = nullptr, *finf = nullptr;
+    double *W = nullptr, *q = nullptr, *R = nullptr, *Wt = nullptr, *fp = nullptr, *cp = nullptr;
+    double *part = nullptr, *norms = nullptr, *rho_w = nullptr, *mass = nullptr;
+    size_t part_bytes = 0;
+    // per level
+    std::vector<void*> r, df;
+    std::vector<double*> tau_inv, dtn_inv, drho;
+    std::vector<double*> fW, fW0, fR, fP, fE, fGam, fRm;
+    double* h_norms = nullptr;   // pinned
+    double M0 = 1.0;
+    int cycle = 0;
+    bool have_div = false;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            ctx->err = std::string(#expr) + ": " + hipGetErrorString(e_);                      \
+            return MIUGKS_EDEVICE;                                                             \
+        }                                                                                      \
+    } while (0)
+
+int dev_alloc(miugks_ctx* ctx, void** p, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        ctx->err = std::string("hipMalloc: ") + hipGetErrorString(e);
+        return MIUGKS_ENOMEM;
+    }
+    ctx->allocs.push_back(*p);
+    return MIUGKS_OK;
+}
+
+template <typename P>
+int upload(miugks_ctx* ctx, P** dst, const std::vector<P>& src) {
+    int rc = dev_alloc(ctx, (void**)dst, src.size() * sizeof(P));
+    if (rc) return rc;
+    if (!src.empty()) HIP_TRY(hipMemcpy(*dst, src.data(), src.size() * sizeof(P), hipMemcpyHostToDevice));
+    return MIUGKS_OK;
+}
+
+inline int nchunks(int nk) { return (nk + KCH - 1) / KCH; }
+inline int ntiles(int n) { return (n + TILE - 1) / TILE; }
+inline int nblk(int n, int b = 256) { return (n + b - 1) / b; }
+
+int check_launch(miugks_ctx* ctx) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        ctx->err = std::string("kernel launch: ") + hipGetErrorString(e);
+        return MIUGKS_EDEVICE;
+    }
+    return MIUGKS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the hot path, per precision
+
+template <typename T>
+struct Path {
+    static T* F(miugks_ctx* c) { return (T*)c->f; }
+
+    // Step 7: W, q of f (optionally after f += df, Step 6)
+    static void moments(miugks_ctx* c, const T* df) {
+        const Geo& g = c->geo[0];
+        int nkc = nchunks(c->nk);
+        hipLaunchKernelGGL(k_moments_partial<T>, dim3(ntiles(g.nc), nkc), dim3(256), 0, c->stream, g, c->vel,
+                           F(c), df, c->part);
+        hipLaunchKernelGGL(k_moments_finalize, dim3(nblk(g.nc)), dim3(256), 0, c->stream, g, c->part, nkc,
+                           c->W, c->q);
+    }
+
+    static void wall_sums(miugks_ctx* c, int l, const T* G, double* out) {
+        const Geo& g = c->geo[l];
+        if (g.n_wall == 0) return;
+        int nkc = nchunks(c->nk);
+        hipLaunchKernelGGL(k_wall_partial<T>, dim3(ntiles(g.n_wall), nkc), dim3(256), 0, c->stream, g, c->vel,
+                           G, c->part);
+        hipLaunchKernelGGL(k_wall_finalize, dim3(nblk(g.n_wall)), dim3(256), 0, c->stream, g, c->part, nkc, out);
+    }
+
+    // Step 1: interface records, div, R and the RMS norms (into c->norms)
+    static void residual(miugks_ctx* c) {
+        const Geo& g = c->geo[0];
+        int nkc = nchunks(c->nk), nt = ntiles(g.nc);
+        hipLaunchKernelGGL(k_face_moments_partial<T>, dim3(nt, nkc), dim3(256), 0, c->stream, g, c->vel, F(c),
+                           c->part);
+        hipLaunchKernelGGL(k_face_finalize, dim3(nblk(g.nc)), dim3(256), 0, c->stream, g, c->gas, c->part, nkc,
+                           c->W, c->fp);
+        hipLaunchKernelGGL(k_face_timeslope_partial<T>, dim3(nt, nkc), dim3(256), 0, c->stream, g, c->vel,
+                           c->gas, c->fp, c->part);
+        hipLaunchKernelGGL(k_face_timeslope_finalize, dim3(nblk(g.nc)), dim3(256), 0, c->stream, g, c->gas,
+                           c->part, nkc, c->fp);
+        wall_sums(c, 0, F(c), c->rho_w);
+        hipLaunchKernelGGL(k_flux_div<T>, dim3(nt, nkc), dim3(256), 0, c->stream, g, c->vel, c->gas, F(c), c->fp,
+                           c->rho_w, (const T*)c->finf, (T*)c->div, c->part);
+        hipLaunchKernelGGL(k_residual_finalize, dim3(nblk(g.nc)), dim3(256), 0, c->stream, g, c->part, nkc, c->R);
+        hipLaunchKernelGGL(k_residual_norm, dim3(1), dim3(256), 0, c->stream, g, c->hl[0].n_fluid, c->R, c->norms);
+        c->have_div = true;
+    }
+
+    // Steps 3-4 (with the positivity guard on c->Wt)
+    static void micro_residual(miugks_ctx* c) {
+        const Geo& g = c->geo[0];
+        hipLaunchKernelGGL(k_cell_prep, dim3(nblk(g.nc)), dim3(256), 0, c->stream, g, c->gas, c->Wt, c->W, c->q,
+                           c->cp, c->tau_inv[0]);
+        hipLaunchKernelGGL(k_micro_residual<T>, dim3(ntiles(g.nc), nchunks(c->nk)), dim3(256), 0, c->stream, g,
+                           c->vel, c->gas, F(c), (const T*)c->div, c->cp, (T*)c->r[0]);
+    }
+
+    static void smooth(miugks_ctx* c, int l) {
+        const Geo& g = c->geo[l];
+        wall_sums(c, l, (const T*)c->df[l], c->drho[l]);
+        int threads = ((g.ny + 63) / 64) * 64;
+        hipLaunchKernelGGL(k_sweep<T>, dim3(c->nk), dim3(threads), 0, c->stream, g, c->vel, c->gas.K_int,
+                           (const T*)c->r[l], (T*)c->df[l], c->tau_inv[l], c->dtn_inv[l], c->drho[l]);
+    }
+
+    // dF_l = CS(l, r_l) (Sec. II D); r_l, tau_inv_l, dtn_inv_l in place
+    static void cs(miugks_ctx* c, int l) {
+        const Geo& g = c->geo[l];
+        size_t n = 2 * (size_t)c->nk * g.nc;
+        hipLaunchKernelGGL(k_zero<T>, dim3(nblk((int)std::min<size_t>(n, 1 << 24))), dim3(256), 0, c->stream,
+                           (T*)c->df[l], n);
+        if (l == c->L - 1) {
+            for (int i = 0; i < c->nuc; ++i) smooth(c, l);
+            return;
+        }
+        for (int i = 0; i < c->nu1; ++i) smooth(c, l);
+        const Geo& gc = c->geo[l + 1];
+        wall_sums(c, l, (const T*)c->df[l], c->drho[l]);
+        hipLaunchKernelGGL(k_defect_restrict<T>, dim3(ntiles(gc.nc), nchunks(c->nk)), dim3(256), 0, c->stream, g,
+                           gc, c->vel, c->gas.K_int, (const T*)c->r[l], (const T*)c->df[l], c->tau_inv[l],
+                           c->dtn_inv[l], c->drho[l], (T*)c->r[l + 1]);
+        cs(c, l + 1);
+        hipLaunchKernelGGL(k_prolong_add<T>, dim3(ntiles(g.nc), nchunks(c->nk)), dim3(256), 0, c->stream, g,
+                           c->vel, gc.nc, (const T*)c->df[l + 1], (T*)c->df[l]);
+        for (int i = 0; i < c->nu2; ++i) smooth(c, l);
+    }
+
+    static void correct(miugks_ctx* c) {
+        for (int l = 0; l + 1 < c->L; ++l)
+            hipLaunchKernelGGL(k_restrict_cells, dim3(nblk(c->geo[l + 1].nc)), dim3(256), 0, c->stream,
+                               c->geo[l], c->geo[l + 1], 1, c->tau_inv[l], c->tau_inv[l + 1]);
+        cs(c, 0);
+    }
+
+    // Steps 6-7 and the closed-domain renormalisation
+    static void update(miugks_ctx* c) {
+        moments(c, (const T*)c->df[0]);
+        if (c->renorm) {
+            const Geo& g = c->geo[0];
+            hipLaunchKernelGGL(k_mass, dim3(1), dim3(1024), 0, c->stream, g, c->W, c->mass);
+            size_t n = 2 * (size_t)c->nk * g.nc;
+            hipLaunchKernelGGL(k_scale_f<T>, dim3(nblk((int)std::min<size_t>(n, 1 << 24))), dim3(256), 0,
+                               c->stream, F(c), n, c->mass, c->M0);
+            hipLaunchKernelGGL(k_scale_d, dim3(nblk(6 * g.nc)), dim3(256), 0, c->stream, c->W, 4 * (size_t)g.nc,
+                               c->mass, c->M0);
+            hipLaunchKernelGGL(k_scale_d, dim3(nblk(2 * g.nc)), dim3(256), 0, c->stream, c->q, 2 * (size_t)g.nc,
+                               c->mass, c->M0);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// FAS cycle (precision independent, FP64)
+
+void fas_smooth(miugks_ctx* c, int l) {
+    const Geo& g = c->geo[l];
+    int nb = nblk(g.nc);
+    hipLaunchKernelGGL(k_fas_rsplit, dim3(nb), dim3(256), 0, c->stream, g, c->gas, c->fW[l], c->fGam[l], c->fP[l],
+                       1.0, c->fRm[l]);
+    for (int col : {0, 1, 0})
+        hipLaunchKernelGGL(k_fas_halfsweep, dim3(nb), dim3(256), 0, c->stream, g, c->gas, c->fW[l], c->fE[l],
+                           c->fRm[l], c->fGam[l], c->dtn_inv[l], col);
+    hipLaunchKernelGGL(k_fas_apply, dim3(nb), dim3(256), 0, c->stream, g, c->fW[l], c->fE[l]);
+}
+
+// W_l^{n+1} = FAS(l, W_l^n, R_l^n): fW[l] holds W_l^n on entry and the result
+// on exit; fR[l] holds the target residual
+void fas(miugks_ctx* c, int l) {
+    const Geo& g = c->geo[l];
+    int nb = nblk(g.nc);
+    size_t bytes = 4 * (size_t)g.nc * sizeof(double);
+    hipMemcpyAsync(c->fW0[l], c->fW[l], bytes, hipMemcpyDeviceToDevice, c->stream);
+    hipLaunchKernelGGL(k_fas_gamma, dim3(nb), dim3(256), 0, c->stream, g, c->gas, c->fW[l], c->fGam[l]);
+    hipLaunchKernelGGL(k_fas_rsplit, dim3(nb), dim3(256), 0, c->stream, g, c->gas, c->fW[l], c->fGam[l], c->fR[l],
+                       -1.0, c->fP[l]);
+    if (l == c->L - 1) {
+        for (int i = 0; i < c->nuc; ++i) fas_smooth(c, l);
+        return;
+    }
+    for (int i = 0; i < c->nu1; ++i) fas_smooth(c, l);
+    const Geo& gc = c->geo[l + 1];
+    hipLaunchKernelGGL(k_fas_rsplit, dim3(nb), dim3(256), 0, c->stream, g, c->gas, c->fW[l], c->fGam[l], c->fP[l],
+                       1.0, c->fRm[l]);
+    hipLaunchKernelGGL(k_restrict_cells, dim3(nblk(gc.nc)), dim3(256), 0, c->stream, g, gc, 4, c->fW[l],
+                       c->fW[l + 1]);
+    hipLaunchKernelGGL(k_restrict_cells, dim3(nblk(gc.nc)), dim3(256), 0, c->stream, g, gc, 4, c->fRm[l],
+                       c->fR[l + 1]);
+    fas(c, l + 1);
+    hipLaunchKernelGGL(k_fas_prolong, dim3(nb), dim3(256), 0, c->stream, g, gc.nc, c->fW[l + 1], c->fW0[l + 1],
+                       c->fW[l]);
+    for (int i = 0; i < c->nu2; ++i) fas_smooth(c, l);
+}
+
+void set_dtn(miugks_ctx* c) {
+    double factor = c->dtn_growth > 0.0 ? std::pow(c->dtn_growth, -(double)c->cycle) : 0.0;
+    for (int l = 0; l < c->L; ++l)
+        hipLaunchKernelGGL(k_dtn, dim3(nblk(c->geo[l].nc)), dim3(256), 0, c->stream, c->geo[l], factor,
+                           c->dtn_inv[l]);
+}
+
+// Step 2 on the device arrays: fW[0] := W^n, fR[0] := R, result into Wt
+void predict(miugks_ctx* c) {
+    size_t bytes = 4 * (size_t)c->geo[0].nc * sizeof(double);
+    hipMemcpyAsync(c->fW[0], c->W, bytes, hipMemcpyDeviceToDevice, c->stream);
+    hipMemcpyAsync(c->fR[0], c->R, bytes, hipMemcpyDeviceToDevice, c->stream);
+    fas(c, 0);
+    hipMemcpyAsync(c->Wt, c->fW[0], bytes, hipMemcpyDeviceToDevice, c->stream);
+}
+
+template <typename T>
+int run_cycles(miugks_ctx* c, int max_cycles, double tol, int* done, double* res) {
+    int n = 0;
+    double last[4] = {0, 0, 0, 0};
+    double first_max = -1.0;
+    int rc = MIUGKS_ENOTCONVERGED;
+    for (int it = 0; it < max_cycles; ++it) {
+        Path<T>::residual(c);
+        hipMemcpyAsync(c->h_norms, c->norms, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            c->err = std::string("hipStreamSynchronize: ") + hipGetErrorString(e);
+            return MIUGKS_EDEVICE;
+        }
+        if ((rc = check_launch(c))) return rc;
+        double mx = 0.0;
+        bool finite = true;
+        for (int m = 0; m < 4; ++m) {
+            last[m] = c->h_norms[m];
+            finite = finite && std::isfinite(last[m]);
+            mx = std::fmax(mx, last[m]);
+        }
+        if (first_max < 0) first_max = mx;
+        if (!finite || mx > 1e6 * std::fmax(first_max, 1e-300)) {
+            c->err = "residual diverged";
+            rc = MIUGKS_EDIVERGED;
+            break;
+        }
+        if (mx < tol) {
+            rc = MIUGKS_OK;
+            break;
+        }
+        set_dtn(c);
+        predict(c);
+        Path<T>::micro_residual(c);
+        Path<T>::correct(c);
+        Path<T>::update(c);
+        ++c->cycle;
+        ++n;
+        rc = MIUGKS_ENOTCONVERGED;
+    }
+    hipError_t se = hipStreamSynchronize(c->stream);
+    if (se != hipSuccess) {
+        c->err = std::string("hipStreamSynchronize: ") + hipGetErrorString(se);
+        return MIUGKS_EDEVICE;
+    }
+    if (int e = check_launch(c)) return e;
+    if (done) *done = n;
+    if (res)
+        for (int m = 0; m < 4; ++m) res[m] = last[m];
+    return rc;
+}
+
+int build_device(miugks_ctx* ctx) {
+    int rc;
+    ctx->geo.resize(ctx->L);
+    for (int l = 0; l < ctx->L; ++l) {
+        HostLevel& h = ctx->hl[l];
+        Geo& g = ctx->geo[l];
+        g.nx = h.nx;
+        g.ny = h.ny;
+        g.nc = h.nc;
+        g.n_wall = (int)h.w_cell.size();
+        double *xc, *yc, *dx, *dy, *dcent, *dt, *wT, *wU, *wV, *wden, *pw;
+        int *nb, *wc, *ws, *pidx;
+        unsigned char* solid;
+        if ((rc = upload(ctx, &xc, h.xc)) || (rc = upload(ctx, &yc, h.yc)) || (rc = upload(ctx, &dx, h.dx)) ||
+            (rc = upload(ctx, &dy, h.dy)) || (rc = upload(ctx, &dcent, h.dcent)) || (rc = upload(ctx, &dt, h.dt)) ||
+            (rc = upload(ctx, &nb, h.nb)) || (rc = upload(ctx, &solid, h.solid)) ||
+            (rc = upload(ctx, &wc, h.w_cell)) || (rc = upload(ctx, &ws, h.w_side)) ||
+            (rc = upload(ctx, &wT, h.w_T)) || (rc = upload(ctx, &wU, h.w_U)) || (rc = upload(ctx, &wV, h.w_V)) ||
+            (rc = upload(ctx, &wden, h.w_den)) || (rc = upload(ctx, &pidx, h.p_idx)) || (rc = upload(ctx, &pw, h.p_w)))
+            return rc;
+        g.xc = xc;
+        g.yc = yc;
+        g.dx = dx;
+        g.dy = dy;
+        g.dcent = dcent;
+        g.dt = dt;
+        g.nb = nb;
+        g.solid = solid;
+        g.w_cell = wc;
+        g.w_side = ws;
+        g.w_T = wT;
+        g.w_U = wU;
+        g.w_V = wV;
+        g.w_den = wden;
+        g.p_idx = pidx;
+        g.p_w = pw;
+    }
+    // velocities
+    std::vector<float> uf(ctx->hv.u.begin(), ctx->hv.u.end()), vf(ctx->hv.v.begin(), ctx->hv.v.end()),
+        wf(ctx->hv.w.begin(), ctx->hv.w.end());
+    double *u, *v, *w;
+    float *uu, *vv, *ww;
+    if ((rc = upload(ctx, &u, ctx->hv.u)) || (rc = upload(ctx, &v, ctx->hv.v)) || (rc = upload(ctx, &w, ctx->hv.w)) ||
+        (rc = upload(ctx, &uu, uf)) || (rc = upload(ctx, &vv, vf)) || (rc = upload(ctx, &ww, wf)))
+        return rc;
+    ctx->vel.nk = ctx->nk;
+    ctx->vel.u = u;
+    ctx->vel.v = v;
+    ctx->vel.w = w;
+    ctx->vel.uf = uu;
+    ctx->vel.vf = vv;
+    ctx->vel.wf = ww;
+    // freestream distribution (farfield faces)
+    {
+        int nk = ctx->nk;
+        std::vector<double> fi(2 * nk);
+        double lam = ctx->gas.lam_inf;
+        for (int k = 0; k < nk; ++k) {
+            double du = ctx->hv.u[k] - ctx->gas.U_inf, dv = ctx->hv.v[k] - ctx->gas.V_inf;
+            fi[k] = ctx->gas.rho_inf * lam / M_PI * std::exp(-lam * (du * du + dv * dv));
+            fi[nk + k] = ctx->gas.K_int / (2.0 * lam) * fi[k];
+        }
+        if (ctx->prec == MIUGKS_FP64) {
+            double* p;
+            if ((rc = upload(ctx, &p, fi))) return rc;
+            ctx->finf = p;
+        } else {
+            std::vector<float> ff(fi.begin(), fi.end());
+            float* p;
+            if ((rc = upload(ctx, &p, ff))) return rc;
+            ctx->finf = p;
+        }
+    }
+    size_t nc0 = ctx->hl[0].nc, nk = ctx->nk, es = ctx->esize;
+    size_t fbytes = 2 * nk * nc0 * es;
+    if ((rc = dev_alloc(ctx, &ctx->f, fbytes)) || (rc = dev_alloc(ctx, &ctx->div, fbytes))) return rc;
+    void* p;
+    auto dalloc = [&](double** d, size_t n) -> int {
+        int r2 = dev_alloc(ctx, &p, n * sizeof(double));
+        *d = (double*)p;
+        return r2;
+    };
+    if ((rc = dalloc(&ctx->W, 4 * nc0)) || (rc = dalloc(&ctx->q, 2 * nc0)) || (rc = dalloc(&ctx->R, 4 * nc0)) ||
+        (rc = dalloc(&ctx->Wt, 4 * nc0)) || (rc = dalloc(&ctx->fp, NFP * 2 * nc0)) ||
+        (rc = dalloc(&ctx->cp, NCP * nc0)) || (rc = dalloc(&ctx->norms, 4)) ||
+        (rc = dalloc(&ctx->rho_w, ctx->hl[0].w_cell.size() + 1)) || (rc = dalloc(&ctx->mass, 1)))
+        return rc;
+    // partial sums: the largest is 2 * NRAW per cell per chunk
+    size_t maxw = 1;
+    for (auto& h : ctx->hl) maxw = std::max(maxw, h.w_cell.size());
+    ctx->part_bytes = (size_t)nchunks(ctx->nk) * std::max<size_t>(2 * NRAW * nc0, maxw) * sizeof(double);
+    if ((rc = dev_alloc(ctx, &p, ctx->part_bytes))) return rc;
+    ctx->part = (double*)p;
+    ctx->r.resize(ctx->L);
+    ctx->df.resize(ctx->L);
+    for (auto* v2 : {&ctx->tau_inv, &ctx->dtn_inv, &ctx->drho, &ctx->fW, &ctx->fW0, &ctx->fR, &ctx->fP, &ctx->fE,
+                     &ctx->fGam, &ctx->fRm})
+        v2->resize(ctx->L);
+    for (int l = 0; l < ctx->L; ++l) {
+        size_t nc = ctx->hl[l].nc;
+        if ((rc = dev_alloc(ctx, &ctx->r[l], 2 * nk * nc * es)) || (rc = dev_alloc(ctx, &ctx->df[l], 2 * nk * nc * es)))
+            return rc;
+        if ((rc = dalloc(&ctx->tau_inv[l], nc)) || (rc = dalloc(&ctx->dtn_inv[l], nc)) ||
+            (rc = dalloc(&ctx->drho[l], ctx->hl[l].w_cell.size() + 1)) || (rc = dalloc(&ctx->fW[l], 4 * nc)) ||
+            (rc = dalloc(&ctx->fW0[l], 4 * nc)) || (rc = dalloc(&ctx->fR[l], 4 * nc)) ||
+            (rc = dalloc(&ctx->fP[l], 4 * nc)) || (rc = dalloc(&ctx->fE[l], 4 * nc)) ||
+            (rc = dalloc(&ctx->fGam[l], 4 * nc)) || (rc = dalloc(&ctx->fRm[l], 4 * nc)))
+            return rc;
+        HIP_TRY(hipMemset(ctx->fE[l], 0, 4 * nc * sizeof(double)));
+        HIP_TRY(hipMemset(ctx->dtn_inv[l], 0, nc * sizeof(double)));
+    }
+    HIP_TRY(hipHostMalloc((void**)&ctx->h_norms, 4 * sizeof(double), hipHostMallocDefault));
+    return MIUGKS_OK;
+}
+
+template <typename T>
+void init_f(miugks_ctx* c, const double* dprim) {
+    const Geo& g = c->geo[0];
+    hipLaunchKernelGGL(k_init<T>, dim3(ntiles(g.nc), nchunks(c->nk)), dim3(256), 0, c->stream, g, c->vel, c->gas,
+                       dprim, (T*)c->f);
+    Path<T>::moments(c, nullptr);
+}
+
+int reset_mass(miugks_ctx* c) {
+    hipLaunchKernelGGL(k_mass, dim3(1), dim3(1024), 0, c->stream, c->geo[0], c->W, c->mass);
+    double m = 0;
+    hipError_t e = hipMemcpyAsync(&m, c->mass, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        c->err = std::string("mass: ") + hipGetErrorString(e);
+        return MIUGKS_EDEVICE;
+    }
+    c->M0 = m;
+    return MIUGKS_OK;
+}
+
+// copy a distribution-shaped device array out / in with conversion
+int copy_out(miugks_ctx* ctx, const void* src, void* dst, int dtype, int on_device) {
+    size_t n = 2 * (size_t)ctx->nk * ctx->hl[0].nc;
+    size_t des = dtype == MIUGKS_FP64 ? 8 : 4;
+    if (dtype != MIUGKS_FP64 && dtype != MIUGKS_FP32F) {
+        ctx->err = "dtype must be MIUGKS_FP64 or MIUGKS_FP32F";
+        return MIUGKS_EINVAL;
+    }
+    if (!dst) {
+        ctx->err = "null destination";
+        return MIUGKS_EINVAL;
+    }
+    void* tmp = nullptr;
+    void* target = dst;
+    if (!on_device) {
+        HIP_TRY(hipMalloc(&tmp, n * des));
+        target = tmp;
+    }
+    if (dtype == ctx->prec) {
+        hipMemcpyAsync(target, src, n * des, hipMemcpyDeviceToDevice, ctx->stream);
+    } else if (ctx->prec == MIUGKS_FP64) {
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(1024), dim3(256), 0, ctx->stream, (const double*)src,
+                           (float*)target, n);
+    } else {
+        hipLaunchKernelGGL((k_convert<float, double>), dim3(1024), dim3(256), 0, ctx->stream, (const float*)src,
+                           (double*)target, n);
+    }
+    if (!on_device) hipMemcpyAsync(dst, tmp, n * des, hipMemcpyDeviceToHost, ctx->stream);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (tmp) hipFree(tmp);
+    if (e != hipSuccess) {
+        ctx->err = std::string("copy: ") + hipGetErrorString(e);
+        return MIUGKS_EDEVICE;
+    }
+    return check_launch(ctx);
+}
+
+int copy_in(miugks_ctx* ctx, const void* src, void* dst, int dtype, int on_device) {
+    size_t n = 2 * (size_t)ctx->nk * ctx->hl[0].nc;
+    size_t des = dtype == MIUGKS_FP64 ? 8 : 4;
+    if (dtype != MIUGKS_FP64 && dtype != MIUGKS_FP32F) {
+        ctx->err = "dtype must be MIUGKS_FP64 or MIUGKS_FP32F";
+        return MIUGKS_EINVAL;
+    }
+    if (!src) {
+        ctx->err = "null source";
+        return MIUGKS_EINVAL;
+    }
+    void* tmp = nullptr;
+    const void* from = src;
+    if (!on_device) {
+        HIP_TRY(hipMalloc(&tmp, n * des));
+        hipMemcpyAsync(tmp, src, n * des, hipMemcpyHostToDevice, ctx->stream);
+        from = tmp;
+    }
+    if (dtype == ctx->prec) {
+        hipMemcpyAsync(dst, from, n * des, hipMemcpyDeviceToDevice, ctx->stream);
+    } else if (ctx->prec == MIUGKS_FP64) {
+        hipLaunchKernelGGL((k_convert<float, double>), dim3(1024), dim3(256), 0, ctx->stream, (const float*)from,
+                           (double*)dst, n);
+    } else {
+        hipLaunchKernelGGL((k_convert<double, float>), dim3(1024), dim3(256), 0, ctx->stream, (const double*)from,
+                           (float*)dst, n);
+    }
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (tmp) hipFree(tmp);
+    if (e != hipSuccess) {
+        ctx->err = std::string("copy: ") + hipGetErrorString(e);
+        return MIUGKS_EDEVICE;
+    }
+    return check_launch(ctx);
+}
+
+int upload_cells(miugks_ctx* ctx, double* dst, const double* src, int m) {
+    if (!src) {
+        ctx->err = "null input";
+        return MIUGKS_EINVAL;
+    }
+    HIP_TRY(hipMemcpyAsync(dst, src, (size_t)m * ctx->hl[0].nc * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    return MIUGKS_OK;
+}
+
+int download_cells(miugks_ctx* ctx, double* dst, const double* src, int m) {
+    HIP_TRY(hipMemcpyAsync(dst, src, (size_t)m * ctx->hl[0].nc * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return check_launch(ctx);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+int miugks_quadrature(int kind, int n, double lo, double hi, double* nodes, double* weights) {
+    return quadrature_rule(kind, n, lo, hi, nodes, weights) ? MIUGKS_OK : MIUGKS_EINVAL;
+}
+
+const char* miugks_last_error(const miugks_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+void miugks_destroy(miugks_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->stream) hipStreamSynchronize(ctx->stream);
+    for (void* p : ctx->allocs) hipFree(p);
+    if (ctx->h_norms) hipHostFree(ctx->h_norms);
+    delete ctx;
+}
+
+int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgrid_desc* v, const miugks_gas_desc* g,
+                  const miugks_solver_desc* s, void* hip_stream) {
+    g_create_error.clear();
+    if (!out || !m || !v || !g || !s) {
+        g_create_error = "null argument";
+        return MIUGKS_EINVAL;
+    }
+    *out = nullptr;
+    miugks_ctx* ctx = new (std::nothrow) miugks_ctx();
+    if (!ctx) {
+        g_create_error = "out of host memory";
+        return MIUGKS_ENOMEM;
+    }
+    ctx->stream = (hipStream_t)hip_stream;
+    if (s->precision != MIUGKS_FP64 && s->precision != MIUGKS_FP32F) {
+        g_create_error = "precision must be MIUGKS_FP64 or MIUGKS_FP32F";
+        delete ctx;
+        return MIUGKS_EINVAL;
+    }
+    if (v->nu < 1 || v->nv < 1 || !v->u || !v->v || !v->wu || !v->wv || s->nu1 < 0 || s->nu2 < 0 ||
+        s->nu_coarse < 1 || !(s->cfl > 0) || g->K_int < 0 || !(g->Kn > 0) || !(g->T_inf > 0)) {
+        g_create_error = "bad velocity grid, gas or solver description";
+        delete ctx;
+        return MIUGKS_EINVAL;
+    }
+    if (m->ny > 1024) {
+        g_create_error = "ny > 1024 is not supported by the ordered sweep";
+        delete ctx;
+        return MIUGKS_EINVAL;
+    }
+    ctx->prec = s->precision;
+    ctx->esize = s->precision == MIUGKS_FP64 ? 8 : 4;
+    ctx->nu = v->nu;
+    ctx->nv = v->nv;
+    ctx->nk = v->nu * v->nv;
+    ctx->L = m->n_levels;
+    ctx->nu1 = s->nu1;
+    ctx->nu2 = s->nu2;
+    ctx->nuc = s->nu_coarse;
+    ctx->dtn_growth = s->dtn_growth;
+    HostVel& hv = ctx->hv;
+    hv.nu = v->nu;
+    hv.nv = v->nv;
+    hv.nk = ctx->nk;
+    hv.u.resize(hv.nk);
+    hv.v.resize(hv.nk);
+    hv.w.resize(hv.nk);
+    for (int a = 0; a < v->nu; ++a)
+        for (int b = 0; b < v->nv; ++b) {
+            int k = a * v->nv + b;
+            hv.u[k] = v->u[a];
+            hv.v[k] = v->v[b];
+            hv.w[k] = v->wu[a] * v->wv[b];
+        }
+    for (int a = 0; a < v->nu; ++a) hv.umax = std::fmax(hv.umax, std::fabs(v->u[a]));
+    for (int b = 0; b < v->nv; ++b) hv.vmax = std::fmax(hv.vmax, std::fabs(v->v[b]));
+    // gas constants; mu_ref from the VHS mean free path (alpha = 1)
+    Gas& gas = ctx->gas;
+    gas.K_int = g->K_int;
+    gas.K = g->K_int + 2.0;
+    gas.gamma = (gas.K + 2.0) / gas.K;
+    gas.Pr = g->Pr;
+    gas.omega = g->omega;
+    gas.mu_ref = 15.0 * std::sqrt(M_PI) * g->Kn / (2.0 * (5.0 - 2.0 * g->omega) * (7.0 - 2.0 * g->omega));
+    gas.rho_inf = g->rho_inf;
+    gas.U_inf = g->U_inf;
+    gas.V_inf = g->V_inf;
+    gas.lam_inf = 1.0 / g->T_inf;
+    gas.W_inf[0] = g->rho_inf;
+    gas.W_inf[1] = g->rho_inf * g->U_inf;
+    gas.W_inf[2] = g->rho_inf * g->V_inf;
+    gas.W_inf[3] = 0.5 * g->rho_inf * (g->U_inf * g->U_inf + g->V_inf * g->V_inf) +
+                   gas.K * g->rho_inf * g->T_inf / 4.0;
+    std::string err;
+    if (!build_levels(m->nx, m->ny, m->n_levels, m->x, m->y, m->face_type_x, m->face_type_y, m->wall_x, m->wall_y,
+                      m->solid, hv, s->cfl, ctx->hl, err)) {
+        g_create_error = err;
+        delete ctx;
+        return MIUGKS_EINVAL;
+    }
+    bool closed = true;
+    for (auto t : ctx->hl[0].ftx) closed = closed && t != MIUGKS_FACE_FARFIELD && t != MIUGKS_FACE_OUTFLOW;
+    for (auto t : ctx->hl[0].fty) closed = closed && t != MIUGKS_FACE_FARFIELD && t != MIUGKS_FACE_OUTFLOW;
+    ctx->renorm = s->mass_renorm < 0 ? closed : s->mass_renorm != 0;
+    hipGetDevice(&ctx->device);
+    int rc = build_device(ctx);
+    if (rc) {
+        g_create_error = ctx->err;
+        miugks_destroy(ctx);
+        return rc;
+    }
+    // start from the rest state
+    size_t nc = ctx->hl[0].nc;
+    std::vector<double> prim(4 * nc, 0.0);
+    for (size_t c = 0; c < nc; ++c) {
+        prim[c] = 1.0;
+        prim[3 * nc + c] = 1.0;
+    }
+    rc = miugks_init_macro(ctx, prim.data(), prim.data() + nc, prim.data() + 2 * nc, prim.data() + 3 * nc);
+    if (rc) {
+        g_create_error = ctx->err;
+        miugks_destroy(ctx);
+        return rc;
+    }
+    *out = ctx;
+    return MIUGKS_OK;
+}
+
+int miugks_init_macro(miugks_ctx* ctx, const double* rho, const double* U, const double* V, const double* T) {
+    if (!ctx) return MIUGKS_EINVAL;
+    if (!rho || !U || !V || !T) {
+        ctx->err = "null field";
+        return MIUGKS_EINVAL;
+    }
+    size_t nc = ctx->hl[0].nc;
+    for (size_t c = 0; c < nc; ++c)
+        if (!ctx->hl[0].solid[c] && !(rho[c] > 0 && T[c] > 0)) {
+            ctx->err = "density and temperature must be positive";
+            return MIUGKS_EINVAL;
+        }
+    std::vector<double> prim(4 * nc);
+    std::memcpy(prim.data(), rho, nc * 8);
+    std::memcpy(prim.data() + nc, U, nc * 8);
+    std::memcpy(prim.data() + 2 * nc, V, nc * 8);
+    std::memcpy(prim.data() + 3 * nc, T, nc * 8);
+    for (size_t c = 0; c < nc; ++c)
+        if (ctx->hl[0].solid[c]) prim[3 * nc + c] = 1.0;
+    HIP_TRY(hipMemcpy(ctx->Wt, prim.data(), 4 * nc * sizeof(double), hipMemcpyHostToDevice));
+    if (ctx->prec == MIUGKS_FP64)
+        init_f<double>(ctx, ctx->Wt);
+    else
+        init_f<float>(ctx, ctx->Wt);
+    ctx->cycle = 0;
+    ctx->have_div = false;
+    return reset_mass(ctx);
+}
+
+int miugks_iterate(miugks_ctx* ctx, int max_cycles, double tol, int* cycles_done, double res[4]) {
+    if (!ctx) return MIUGKS_EINVAL;
+    if (max_cycles < 0) {
+        ctx->err = "max_cycles must be >= 0";
+        return MIUGKS_EINVAL;
+    }
+    if (ctx->prec == MIUGKS_FP64) return run_cycles<double>(ctx, max_cycles, tol, cycles_done, res);
+    return run_cycles<float>(ctx, max_cycles, tol, cycles_done, res);
+}
+
+int miugks_get_macro(miugks_ctx* ctx, double* rho, double* U, double* V, double* T, double* qx, double* qy) {
+    if (!ctx) return MIUGKS_EINVAL;
+    size_t nc = ctx->hl[0].nc;
+    std::vector<double> W(4 * nc), q(2 * nc);
+    int rc = download_cells(ctx, W.data(), ctx->W, 4);
+    if (rc) return rc;
+    if ((rc = download_cells(ctx, q.data(), ctx->q, 2))) return rc;
+    double K = ctx->gas.K;
+    for (size_t c = 0; c < nc; ++c) {
+        double r = W[c], u = 0, v = 0, t = 0;
+        if (r != 0.0) {
+            u = W[nc + c] / r;
+            v = W[2 * nc + c] / r;
+            double e = W[3 * nc + c] - 0.5 * r * (u * u + v * v);
+            t = 4.0 * e / (K * r);
+        }
+        if (rho) rho[c] = r;
+        if (U) U[c] = u;
+        if (V) V[c] = v;
+        if (T) T[c] = t;
+        if (qx) qx[c] = q[c];
+        if (qy) qy[c] = q[nc + c];
+    }
+    return MIUGKS_OK;
+}
+
+int miugks_get_f(miugks_ctx* ctx, void* dst, int dtype, int on_device) {
+    if (!ctx) return MIUGKS_EINVAL;
+    return copy_out(ctx, ctx->f, dst, dtype, on_device);
+}
+
+int miugks_set_f(miugks_ctx* ctx, const void* src, int dtype, int on_device) {
+    if (!ctx) return MIUGKS_EINVAL;
+    int rc = copy_in(ctx, src, ctx->f, dtype, on_device);
+    if (rc) return rc;
+    if (ctx->prec == MIUGKS_FP64)
+        Path<double>::moments(ctx, nullptr);
+    else
+        Path<float>::moments(ctx, nullptr);
+    ctx->have_div = false;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return check_launch(ctx);
+}
+
+int miugks_residual(miugks_ctx* ctx, double* R, double res[4]) {
+    if (!ctx) return MIUGKS_EINVAL;
+    if (ctx->prec == MIUGKS_FP64)
+        Path<double>::residual(ctx);
+    else
+        Path<float>::residual(ctx);
+    int rc;
+    if (R && (rc = download_cells(ctx, R, ctx->R, 4))) return rc;
+    double nrm[4];
+    HIP_TRY(hipMemcpyAsync(nrm, ctx->norms, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if ((rc = check_launch(ctx))) return rc;
+    if (res)
+        for (int m = 0; m < 4; ++m) res[m] = nrm[m];
+    return MIUGKS_OK;
+}
+
+int miugks_get_div(miugks_ctx* ctx, void* dst, int dtype, int on_device) {
+    if (!ctx) return MIUGKS_EINVAL;
+    if (!ctx->have_div) {
+        ctx->err = "no div: call miugks_residual first";
+        return MIUGKS_ESTATE;
+    }
+    return copy_out(ctx, ctx->div, dst, dtype, on_device);
+}
+
+int miugks_predict(miugks_ctx* ctx, const double* W, const double* R, double* W_out) {
+    if (!ctx) return MIUGKS_EINVAL;
+    if (!W_out) {
+        ctx->err = "null output";
+        return MIUGKS_EINVAL;
+    }
+    int rc;
+    if ((rc = upload_cells(ctx, ctx->fW[0], W, 4)) || (rc = upload_cells(ctx, ctx->fR[0], R, 4))) return rc;
+    set_dtn(ctx);
+    fas(ctx, 0);
+    return download_cells(ctx, W_out, ctx->fW[0], 4);
+}
+
+int miugks_micro_residual(miugks_ctx* ctx, const double* Wt, void* r_out, double* tau_inv_out, int dtype,
+                          int on_device) {
+    if (!ctx) return MIUGKS_EINVAL;
+    if (!ctx->have_div) {
+        ctx->err = "no div: call miugks_residual first";
+        return MIUGKS_ESTATE;
+    }
+    int rc;
+    if ((rc = upload_cells(ctx, ctx->Wt, Wt, 4))) return rc;
+    if (ctx->prec == MIUGKS_FP64)
+        Path<double>::micro_residual(ctx);
+    else
+        Path<float>::micro_residual(ctx);
+    if (tau_inv_out && (rc = download_cells(ctx, tau_inv_out, ctx->tau_inv[0], 1))) return rc;
+    if (r_out) return copy_out(ctx, ctx->r[0], r_out, dtype, on_device);
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return check_launch(ctx);
+}
+
+int miugks_correct(miugks_ctx* ctx, const void* r, const double* tau_inv, void* df_out, int dtype, int on_device) {
+    if (!ctx) return MIUGKS_EINVAL;
+    int rc;
+    if ((rc = copy_in(ctx, r, ctx->r[0], dtype, on_device))) return rc;
+    if ((rc = upload_cells(ctx, ctx->tau_inv[0], tau_inv, 1))) return rc;
+    set_dtn(ctx);
+    if (ctx->prec == MIUGKS_FP64)
+        Path<double>::correct(ctx);
+    else
+        Path<float>::correct(ctx);
+    if (df_out) return copy_out(ctx, ctx->df[0], df_out, dtype, on_device);
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return check_launch(ctx);
+}
+
+int miugks_sizes(const miugks_ctx* ctx, int* nc, int* n_fluid, int* nk, int* n_levels) {
+    if (!ctx) return MIUGKS_EINVAL;
+    if (nc) *nc = ctx->hl[0].nc;
+    if (n_fluid) *n_fluid = ctx->hl[0].n_fluid;
+    if (nk) *nk = ctx->nk;
+    if (n_levels) *n_levels = ctx->L;
+    return MIUGKS_OK;
+}
+
+}  // extern "C"

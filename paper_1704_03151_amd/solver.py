@@ -1,0 +1,167 @@
+"""Python handle of one MIUGKS problem on the GPU (thin wrapper of the C ABI).
+
+All computation happens in libmiugks.so; this class only converts a
+`workloads.Case` into the C descriptors and numpy arrays into pointers.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _C
+
+_QUAD = {"trapezoid": _C.QUAD_TRAPEZOID, "simpson38": _C.QUAD_SIMPSON38,
+         "gauss_hermite": _C.QUAD_GAUSS_HERMITE}
+_PREC = {"fp64": _C.FP64, "fp32f": _C.FP32F}
+
+
+def _stream_handle(stream):
+    if stream is not None:
+        return int(stream)
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream)
+    except Exception:   # torch absent or without a device: default stream
+        pass
+    return 0
+
+
+class Solver:
+    """One context: create from a case, iterate, read fields."""
+
+    def __init__(self, case, precision=None, stream=None, mass_renorm=-1):
+        self.case = case
+        prec = _PREC[precision or case.precision]
+        self.precision = prec
+        self.dtype = np.float64 if prec == _C.FP64 else np.float32
+        kind = _QUAD[case.quad]
+        self.u1, self.wu = _C.quadrature(kind, case.nu, case.vlo, case.vhi)
+        self.v1, self.wv = _C.quadrature(kind, case.nv, case.vlo, case.vhi)
+        # keep every array alive while the descriptors point at them
+        self._keep = [np.ascontiguousarray(a) for a in (
+            np.asarray(case.x, float), np.asarray(case.y, float),
+            np.asarray(case.face_type_x, np.uint8), np.asarray(case.face_type_y, np.uint8),
+            np.asarray(case.wall_x, float), np.asarray(case.wall_y, float),
+            np.asarray(case.solid, np.uint8))]
+        x, y, ftx, fty, wx, wy, sol = self._keep
+        mesh = _C.MeshDesc(case.nx, case.ny, case.n_levels, _C.dptr(x), _C.dptr(y), _C.u8ptr(ftx),
+                           _C.u8ptr(fty), _C.dptr(wx), _C.dptr(wy), _C.u8ptr(sol))
+        vg = _C.VGridDesc(case.nu, case.nv, _C.dptr(self.u1), _C.dptr(self.v1), _C.dptr(self.wu),
+                          _C.dptr(self.wv))
+        rho, U, V, T = case.farfield
+        gas = _C.GasDesc(case.K_int, case.Pr, case.omega, case.Kn, rho, U, V, T)
+        sd = _C.SolverDesc(prec, case.nu1, case.nu2, case.nu_coarse, case.cfl, case.dtn_growth,
+                           mass_renorm)
+        h = ctypes.c_void_p()
+        rc = _C.lib.miugks_create(ctypes.byref(h), ctypes.byref(mesh), ctypes.byref(vg),
+                                  ctypes.byref(gas), ctypes.byref(sd), ctypes.c_void_p(_stream_handle(stream)))
+        if rc:
+            raise _C.MiugksError(rc, _C.lib.miugks_last_error(None).decode())
+        self.h = h
+        nc, nf, nk, nl = (ctypes.c_int() for _ in range(4))
+        _C.lib.miugks_sizes(h, ctypes.byref(nc), ctypes.byref(nf), ctypes.byref(nk), ctypes.byref(nl))
+        self.nc, self.n_fluid, self.nk, self.n_levels = nc.value, nf.value, nk.value, nl.value
+        self.fshape = (2, self.nk, case.ny, case.nx)
+        self.init_macro(case.init)
+
+    # ------------------------------------------------------------------ plumbing
+    def _check(self, rc, allow=()):
+        if rc and rc not in allow:
+            raise _C.MiugksError(rc, _C.lib.miugks_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            _C.lib.miugks_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _cells(self, a, m=None):
+        shape = (self.case.ny, self.case.nx) if m is None else (m, self.case.ny, self.case.nx)
+        out = np.ascontiguousarray(np.asarray(a, float).reshape(shape))
+        return out
+
+    # ------------------------------------------------------------------ API
+    def init_macro(self, prim):
+        p = [self._cells(a) for a in prim]
+        self._check(_C.lib.miugks_init_macro(self.h, *(_C.dptr(a) for a in p)))
+
+    def iterate(self, max_cycles, tol=1e-6):
+        """Returns (status, cycles_done, residual norms); status OK, ENOTCONVERGED or EDIVERGED."""
+        n = ctypes.c_int()
+        res = np.zeros(4)
+        rc = _C.lib.miugks_iterate(self.h, int(max_cycles), float(tol), ctypes.byref(n), _C.dptr(res))
+        self._check(rc, allow=(_C.ENOTCONVERGED, _C.EDIVERGED))
+        return rc, n.value, res
+
+    def macro(self):
+        shape = (self.case.ny, self.case.nx)
+        out = {k: np.zeros(shape) for k in ("rho", "U", "V", "T", "qx", "qy")}
+        self._check(_C.lib.miugks_get_macro(self.h, *(_C.dptr(out[k]) for k in ("rho", "U", "V", "T", "qx", "qy"))))
+        return out
+
+    def get_f(self, dtype=None):
+        dt = np.dtype(dtype or self.dtype)
+        out = np.zeros(self.fshape, dt)
+        code = _C.FP64 if dt == np.float64 else _C.FP32F
+        self._check(_C.lib.miugks_get_f(self.h, out.ctypes.data_as(ctypes.c_void_p), code, 0))
+        return out
+
+    def set_f(self, f):
+        a = np.ascontiguousarray(f)
+        code = _C.FP64 if a.dtype == np.float64 else _C.FP32F
+        if a.dtype not in (np.float64, np.float32) or a.shape != self.fshape:
+            raise ValueError(f"f must be float32/float64 shaped {self.fshape}")
+        self._check(_C.lib.miugks_set_f(self.h, a.ctypes.data_as(ctypes.c_void_p), code, 0))
+
+    def residual(self):
+        R = np.zeros((4, self.case.ny, self.case.nx))
+        res = np.zeros(4)
+        self._check(_C.lib.miugks_residual(self.h, _C.dptr(R), _C.dptr(res)))
+        return R, res
+
+    def div(self, dtype=None):
+        dt = np.dtype(dtype or self.dtype)
+        out = np.zeros(self.fshape, dt)
+        code = _C.FP64 if dt == np.float64 else _C.FP32F
+        self._check(_C.lib.miugks_get_div(self.h, out.ctypes.data_as(ctypes.c_void_p), code, 0))
+        return out
+
+    def predict(self, W, R):
+        W = self._cells(W, 4)
+        R = self._cells(R, 4)
+        out = np.zeros_like(W)
+        self._check(_C.lib.miugks_predict(self.h, _C.dptr(W), _C.dptr(R), _C.dptr(out)))
+        return out
+
+    def micro_residual(self, Wt, dtype=None):
+        Wt = self._cells(Wt, 4)
+        dt = np.dtype(dtype or self.dtype)
+        r = np.zeros(self.fshape, dt)
+        ti = np.zeros((self.case.ny, self.case.nx))
+        code = _C.FP64 if dt == np.float64 else _C.FP32F
+        self._check(_C.lib.miugks_micro_residual(self.h, _C.dptr(Wt), r.ctypes.data_as(ctypes.c_void_p),
+                                                 _C.dptr(ti), code, 0))
+        return r, ti
+
+    def correct(self, r, tau_inv):
+        a = np.ascontiguousarray(r)
+        code = _C.FP64 if a.dtype == np.float64 else _C.FP32F
+        ti = self._cells(tau_inv)
+        out = np.zeros_like(a)
+        self._check(_C.lib.miugks_correct(self.h, a.ctypes.data_as(ctypes.c_void_p), _C.dptr(ti),
+                                          out.ctypes.data_as(ctypes.c_void_p), code, 0))
+        return out

@@ -1,0 +1,59 @@
+"""Shared helpers of the GPU parity tests: small cases covering every boundary
+tag, ragged sizes, and the comparison metrics."""
+import numpy as np
+
+import workloads as wl
+
+
+def small_cases():
+    """Cases the oracle finishes in seconds, spanning several 64-cell tiles and
+    32-velocity chunks, with ragged tails, and every boundary tag."""
+    c = {}
+    c["cavity16_kn10"] = wl.config1()
+    c["box12x10_ragged"] = wl.cavity(n=12, ny=10, Kn=0.3, n_levels=2, quad="gauss_hermite", nvel=9, nvel_y=10,
+                                     vlo=0.0, vhi=0.0, mach=0.3, name="box12x10_ragged")
+    c["plate32x24"] = wl.flat_plate(scale=4, quad="trapezoid", nu=14, nv=12, vlo=-5.0, vhi=5.0, n_levels=2,
+                                    precision="fp64", Kn=0.2)
+    c["square20x20"] = wl.square_cylinder(scale=8, quad="trapezoid", nu=16, nv=16, vlo=-12.0, vhi=12.0,
+                                          n_levels=2, precision="fp64", nu_coarse=4)
+    return c
+
+
+def rel_max(a, ref):
+    """max |a - ref| / max |ref| (a max-norm scale: fields cross zero)."""
+    return float(np.max(np.abs(np.asarray(a) - ref)) / max(np.max(np.abs(ref)), 1e-300))
+
+
+def field_errors(macro, prim_ref, fluid=None):
+    """Per-field max-norm relative error of rho, U, V, T over fluid cells
+    (solid cells carry no gas); NaN anywhere counts as an infinite error."""
+    out = {}
+    for name, ref in zip(("rho", "U", "V", "T"), prim_ref):
+        ref = np.asarray(ref).reshape(macro[name].shape)
+        got = macro[name]
+        if fluid is not None:
+            m = np.asarray(fluid).reshape(ref.shape)
+            ref, got = ref[m], got[m]
+        if not (np.all(np.isfinite(ref)) and np.all(np.isfinite(got))):
+            out[name] = float("inf")
+            continue
+        scale = max(np.max(np.abs(ref)), 1e-300)
+        out[name] = float(np.max(np.abs(got - ref)) / scale)
+    return out
+
+
+def perturbed_state(case, seed):
+    """Seeded macro fields and multiplicative perturbation of f (inputs only)."""
+    prim = wl.random_macro(case, seed=seed, amp=0.08)
+    pert = wl.random_perturbation(case, seed=seed + 1, amp=0.05)
+    return prim, pert
+
+
+def to_oracle(f):
+    """(2, Nk, ny, nx) -> (G, H) each (Nk, Nc)."""
+    nk = f.shape[1]
+    return f[0].reshape(nk, -1).astype(float), f[1].reshape(nk, -1).astype(float)
+
+
+def from_oracle(G, H, case):
+    return np.stack([G.reshape(-1, case.ny, case.nx), H.reshape(-1, case.ny, case.nx)])

@@ -1,0 +1,153 @@
+"""GPU (HIP, through the C ABI) against the FP64 CPU oracle, element by
+element, on seeded inputs: one test per step of the hot path and whole
+outer cycles.  FP64 tolerances: 1e-11 (max-norm relative) for single steps,
+1e-10 for fields after several cycles."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from _parity import field_errors, from_oracle, perturbed_state, rel_max, small_cases, to_oracle
+from oracle.cs import cs_cycle
+from oracle.fas import fas_cycle
+from oracle.solver import Oracle
+
+pytestmark = pytest.mark.gpu
+
+CASES = small_cases()
+_CACHE = {}
+
+
+def pair(name):
+    """(case, gpu solver, oracle) for a small case, FP64 on the GPU."""
+    if name not in _CACHE:
+        from paper_1704_03151_amd import Solver
+        case = CASES[name]
+        print(f"[parity] case {name}: {case.nx}x{case.ny} cells, {case.n_vel} velocities, "
+              f"{case.n_levels} levels", flush=True)
+        _CACHE[name] = (case, Solver(case, precision="fp64"), Oracle(case))
+    return _CACHE[name]
+
+
+def perturbed_pair(name, seed):
+    case, gpu, orc = pair(name)
+    prim, pert = perturbed_state(case, seed)
+    gpu.init_macro(prim)
+    orc.init_macro(prim)
+    f = gpu.get_f() * pert
+    gpu.set_f(f)
+    orc.set_f(orc.G * pert[0].reshape(orc.G.shape), orc.H * pert[1].reshape(orc.H.shape))
+    return case, gpu, orc
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_init_and_moments(name):
+    case, gpu, orc = pair(name)
+    prim, _ = perturbed_state(case, 3)
+    gpu.init_macro(prim)
+    orc.init_macro(prim)
+    f = gpu.get_f()
+    G, H = to_oracle(f)
+    assert rel_max(G, orc.G) < 1e-13 and rel_max(H, orc.H) < 1e-13
+    m = gpu.macro()
+    err = field_errors(m, orc.primitive(), orc.lev0.fluid)
+    assert max(err.values()) < 1e-12, err
+    # q comes from one pass of raw third moments (~1), so its error is absolute
+    qref = orc.q.reshape(2, case.ny, case.nx)
+    assert np.max(np.abs(m["qx"] - qref[0])) < 1e-12 and np.max(np.abs(m["qy"] - qref[1])) < 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_step1_flux_residual(name):
+    """Row a1: UGKS interface flux -> div and R; row a2 through the moments."""
+    case, gpu, orc = perturbed_pair(name, 5)
+    R, norms = gpu.residual()
+    div = gpu.div()
+    norms_ref = orc.step1()
+    dG, dH = to_oracle(div)
+    assert rel_max(dG, orc.divG) < 1e-11, rel_max(dG, orc.divG)
+    assert rel_max(dH, orc.divH) < 1e-11, rel_max(dH, orc.divH)
+    Rref = orc.R.reshape(4, case.ny, case.nx)
+    for m in range(4):
+        assert rel_max(R[m], Rref[m]) < 1e-11, (m, rel_max(R[m], Rref[m]))
+    assert np.allclose(norms, norms_ref, rtol=1e-11, atol=0)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_step2_fas_prediction(name):
+    """Row a3: FAS V-cycle of the macroscopic prediction."""
+    case, gpu, orc = perturbed_pair(name, 7)
+    W = orc.W.copy()
+    Rt = 0.02 * wl.random_field(W.shape, seed=17) * orc.lev0.fluid
+    out = gpu.predict(W.reshape(4, case.ny, case.nx), Rt.reshape(4, case.ny, case.nx))
+    ref = fas_cycle(orc.fas_levels, orc.levels, orc.prolongs, 0, W, Rt, orc.params, orc.dtn_inv())
+    for m in range(4):
+        e = rel_max(out[m].ravel(), ref[m])
+        assert e < 1e-11, (m, e)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_steps34_micro_residual(name):
+    """Row a4: predicted Shakhov equilibrium and micro residual."""
+    case, gpu, orc = perturbed_pair(name, 9)
+    gpu.residual()
+    orc.step1()
+    Wt = orc.W * (1.0 + 0.01 * wl.random_field(orc.W.shape, seed=19))
+    r, ti = gpu.micro_residual(Wt.reshape(4, case.ny, case.nx))
+    rG, rH, ti_ref = orc.micro_residual(Wt)
+    gG, gH = to_oracle(r)
+    assert rel_max(gG, rG) < 1e-11 and rel_max(gH, rH) < 1e-11, (rel_max(gG, rG), rel_max(gH, rH))
+    assert rel_max(ti.ravel(), ti_ref) < 1e-13
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_step5_cs_correction(name):
+    """Row a5: CS V-cycle with ordered sweeps, wall coupling, transfers."""
+    case, gpu, orc = pair(name)
+    fl = orc.lev0.fluid
+    r = wl.random_field((2, case.n_vel, case.ny, case.nx), seed=23) * fl.reshape(case.ny, case.nx)
+    ti = wl.random_field((case.ny, case.nx), seed=29, lo=0.5, hi=3.0)
+    orc.cycle = 0
+    gpu.init_macro(case.init)         # resets the cycle counter of the pseudo step
+    out = gpu.correct(r, ti)
+    rG, rH = to_oracle(r)
+    dG, dH = cs_cycle(orc.cs_levels, orc.levels, orc.prolongs, 0, rG, rH,
+                      orc.level_tau_inv(ti.ravel() * fl), orc.dtn_inv(), orc.params)
+    gG, gH = to_oracle(out)
+    assert rel_max(gG, dG) < 1e-11 and rel_max(gH, dH) < 1e-11, (rel_max(gG, dG), rel_max(gH, dH))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_full_cycles_trajectory(name):
+    """Rows a1-a6 together: three outer cycles from the initial state."""
+    case, gpu, orc = pair(name)
+    gpu.init_macro(case.init)
+    orc.init_macro(case.init)
+    orc.cycle = 0
+    orc.history = []
+    rc, n, res = gpu.iterate(3, tol=0.0)
+    ok, res_ref = orc.iterate(3, tol=0.0)
+    assert n == 3
+    err = field_errors(gpu.macro(), orc.primitive(), orc.lev0.fluid)
+    print(f"[parity] {name} after 3 cycles: {err}", flush=True)
+    assert max(err.values()) < 1e-10, err
+    G, H = to_oracle(gpu.get_f())
+    assert rel_max(G, orc.G) < 1e-10
+
+
+def test_config1_converges_with_the_oracle():
+    """Cavity 16x16, Kn 10, FP64: same cycle count to residual 1e-6 and the
+    same fields to 1e-10."""
+    case, gpu, orc = pair("cavity16_kn10")
+    gpu.init_macro(case.init)
+    orc.init_macro(case.init)
+    orc.cycle = 0
+    orc.history = []
+    rc, n, res = gpu.iterate(200, tol=1e-6)
+    ok, res_ref = orc.iterate(200, tol=1e-6)
+    assert rc == 0 and ok
+    assert n == len(orc.history) - 1, (n, len(orc.history))
+    err = field_errors(gpu.macro(), orc.primitive(), orc.lev0.fluid)
+    print(f"[parity] cavity16 converged in {n} cycles: {err}", flush=True)
+    assert max(err.values()) < 1e-10, err

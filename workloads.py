@@ -166,28 +166,32 @@ AIR = dict(K_int=3, Pr=0.72, omega=0.77)
 
 def cavity(n=16, first=None, Kn=10.0, mach=0.16, n_levels=2, quad=QUAD_TRAPEZOID,
            nvel=16, vlo=-4.0, vhi=4.0, precision="fp64", name=None, wall_T_bottom=None,
-           **kw) -> Case:
+           ny=None, nvel_y=None, **kw) -> Case:
     """Lid-driven cavity on [0,1]^2: diffuse walls at T = 1, top lid moving in +x.
 
-    `wall_T_bottom` optionally gives one wall temperature per bottom face.
+    n (and optionally ny) cells, nvel (and optionally nvel_y) velocities per
+    axis; `wall_T_bottom` optionally gives one wall temperature per bottom face.
     """
-    nodes = np.linspace(0.0, 1.0, n + 1) if first is None else tanh_two_sided(n, first)
-    ftx, fty, wx, wy = _blank(n, n)
-    ftx[:, 0] = ftx[:, n] = FACE_WALL
-    fty[0, :] = fty[n, :] = FACE_WALL
+    nx = n
+    ny = n if ny is None else ny
+    xn = np.linspace(0.0, 1.0, nx + 1) if first is None else tanh_two_sided(nx, first)
+    yn = np.linspace(0.0, 1.0, ny + 1) if first is None else tanh_two_sided(ny, first)
+    ftx, fty, wx, wy = _blank(nx, ny)
+    ftx[:, 0] = ftx[:, nx] = FACE_WALL
+    fty[0, :] = fty[ny, :] = FACE_WALL
     gamma = (ARGON["K_int"] + 4.0) / (ARGON["K_int"] + 2.0)
-    wx[:, 0, 0] = wx[:, n, 0] = 1.0
+    wx[:, 0, 0] = wx[:, nx, 0] = 1.0
     wy[0, :, 0] = 1.0 if wall_T_bottom is None else np.asarray(wall_T_bottom, float)
-    wy[n, :, 0] = 1.0
-    wy[n, :, 1] = lid_speed(mach, gamma)
-    init = np.zeros((4, n, n))
+    wy[ny, :, 0] = 1.0
+    wy[ny, :, 1] = lid_speed(mach, gamma)
+    init = np.zeros((4, ny, nx))
     init[0] = 1.0
     init[3] = 1.0
-    return Case(name=name or f"cavity{n}", x=nodes.copy(), y=nodes.copy(), face_type_x=ftx,
-                face_type_y=fty, wall_x=wx, wall_y=wy, solid=np.zeros((n, n), np.uint8),
-                n_levels=n_levels, quad=quad, nu=nvel, nv=nvel, vlo=vlo, vhi=vhi,
-                Kn=Kn, farfield=(1.0, 0.0, 0.0, 1.0), init=init, precision=precision,
-                **ARGON, **kw)
+    return Case(name=name or f"cavity{nx}x{ny}", x=xn.copy(), y=yn.copy(), face_type_x=ftx,
+                face_type_y=fty, wall_x=wx, wall_y=wy, solid=np.zeros((ny, nx), np.uint8),
+                n_levels=n_levels, quad=quad, nu=nvel, nv=nvel if nvel_y is None else nvel_y,
+                vlo=vlo, vhi=vhi, Kn=Kn, farfield=(1.0, 0.0, 0.0, 1.0), init=init,
+                precision=precision, **ARGON, **kw)
 
 
 def config1(**kw) -> Case:
