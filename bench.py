@@ -1,0 +1,162 @@
+"""Benchmark of the MIUGKS hot path on one MI355X.
+
+Workload: lid-driven cavity, 64x64 tanh-clustered cells (first cell 0.005),
+28x28 Gauss-Hermite velocities, Kn 0.075, lid Mach 0.16, 4-level V-cycles,
+FP32 distribution with FP64 moments / macroscopic prediction / norms.  A step
+is one outer MIUGKS cycle (Steps 1-8: UGKS flux and residuals, FAS
+prediction, micro residual, CS correction, update and moments).  The input
+is synthetic (no dataset); every array lives in HBM before timing starts.
+
+Prints one JSON line:
+  value      cell-velocity updates per second per MG cycle
+             (fluid cells x velocities / seconds per cycle)
+  roofline   dominant kernel: algorithmic bytes per launch / mean launch time
+             (HIP events on the library's stream) against 8 TB/s
+  cpu_baseline  the FP64 CPU oracle timed on this host on a bounded sample
+plus the wall time and cycle count to an RMS residual of 1e-6 for the
+FP32-f form and the FP64 form.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell·velocity updates/s per MG cycle; wall time to residual 1e-6; HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+# traffic of the dominant kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE per
+# launch (bytes), scaled by a plain-copy calibration; None until measured
+# for the current kernel
+MEASURED_TRAFFIC = {}
+
+
+def cpu_baseline(case, cycles):
+    """The oracle (numpy FP64) on the same case: setup untimed, then `cycles`
+    full outer cycles timed, single thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.solver import Oracle
+    with threadpool_limits(limits=1):
+        o = Oracle(case.with_(precision="fp64"))
+        t0 = time.perf_counter()
+        for _ in range(cycles):
+            o.step1()
+            o.advance()
+        dt = (time.perf_counter() - t0) / cycles
+    return {"value": case.n_fluid * case.n_vel / dt, "unit": "cell*velocity updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{cycles} full outer cycle(s) of the same {case.nx}x{case.ny}x{case.n_vel} cavity, "
+                      f"numpy FP64 oracle, one thread, {dt:.2f} s per cycle"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp32f", choices=["fp32f", "fp64"])
+    ap.add_argument("--config", type=int, default=2, help="workload recipe (2 = the headline cavity)")
+    ap.add_argument("--cpu-cycles", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-converge", action="store_true", help="skip the time-to-1e-6 runs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the design notes describe how it would shard over velocities).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as wl
+    from paper_1704_03151_amd import Solver
+
+    torch.cuda.set_device(0)
+    case = wl.CONFIGS[args.config]()
+    solver = Solver(case, precision=args.precision)
+    pts = case.n_fluid * case.n_vel
+    print(f"[bench] {case.name}: {case.nx}x{case.ny} cells ({case.n_fluid} fluid) x {case.n_vel} velocities, "
+          f"{case.n_levels} levels, {args.precision}", file=sys.stderr, flush=True)
+
+    # warm-up, then exactly K timed cycles
+    solver.iterate(args.warmup, tol=0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, n, res = solver.iterate(args.steps, tol=0.0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert n == args.steps, (rc, n)
+    sec = (t1 - t0) / args.steps
+    value = pts / sec
+    print(f"[bench] {args.steps} cycles: {sec * 1e3:.3f} ms/cycle", file=sys.stderr, flush=True)
+
+    # per-kernel timing over K more cycles (HIP events on the library stream)
+    solver.set_timing(True)
+    solver.iterate(args.steps, tol=0.0)
+    stats = solver.timing()
+    solver.set_timing(False)
+    total_ms = sum(v[1] for v in stats.values())
+    dom = max(stats, key=lambda k: stats[k][1])
+    launches, ms, by = stats[dom]
+    achieved = by / launches / (ms / launches * 1e-3) / 1e9
+    cycle_bytes = sum(v[2] for v in stats.values()) / args.steps
+    kernels = {k: {"launches": v[0], "ms_per_cycle": v[1] / args.steps,
+                   "gbs": (v[2] / (v[1] * 1e-3) / 1e9 if v[1] > 0 else None)}
+               for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
+    traffic = MEASURED_TRAFFIC.get((case.name, args.precision, dom))
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "bytes_per_launch": by / launches, "mean_launch_ms": ms / launches}
+    print(f"[bench] dominant kernel {dom}: {ms / launches * 1e3:.1f} us/launch, {achieved:.0f} GB/s",
+          file=sys.stderr, flush=True)
+
+    extra = {}
+    if not args.no_converge:
+        for prec in (args.precision, "fp64" if args.precision != "fp64" else None):
+            if prec is None:
+                continue
+            s = solver if prec == args.precision else Solver(case, precision=prec)
+            s.init_macro(case.init)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, cyc, res = s.iterate(1000, tol=1e-6)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            extra[prec] = {"converged": rc == 0, "cycles": cyc, "wall_s": wall,
+                           "final_residual": [float(x) for x in res]}
+            print(f"[bench] {prec}: residual 1e-6 after {cyc} cycles, {wall:.3f} s", file=sys.stderr, flush=True)
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell*velocity updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32f" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{case.name}: lid-driven cavity {case.nx}x{case.ny} cells "
+                               f"(tanh, first cell 0.005) x {case.nu}x{case.nv} Gauss-Hermite velocities, "
+                               f"Kn {case.Kn}, lid Mach 0.16, {case.n_levels}-level V-cycles",
+                   "cells": case.n_cells, "fluid_cells": case.n_fluid, "velocities": case.n_vel,
+                   "levels": case.n_levels, "precision": args.precision},
+        "roofline": roofline,
+        "cycle_algorithmic_gbs": cycle_bytes / (total_ms / args.steps * 1e-3) / 1e9,
+        "kernel_ms_per_cycle": {k: v["ms_per_cycle"] for k, v in kernels.items()},
+        "to_residual_1e-6": extra,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(case, args.cpu_cycles)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -181,6 +181,19 @@ int miugks_micro_residual(miugks_ctx* ctx, const double* Wt, void* r_out, double
 int miugks_correct(miugks_ctx* ctx, const void* r, const double* tau_inv, void* df_out, int dtype,
                    int on_device);
 
+/* Per-kernel timing for profiling: on = 1 clears previous records and starts
+ * bracketing every kernel the library launches with HIP events on its
+ * stream; on = 0 stops.  Timing adds a few microseconds per launch. */
+int miugks_set_timing(miugks_ctx* ctx, int on);
+
+/* Aggregate of the timed launches since miugks_set_timing(ctx, 1), one entry
+ * per kernel label: launch count, summed duration (ms) and summed
+ * algorithmic bytes (what the step must read and write once, per the byte
+ * model of each kernel).  Fills at most cap entries of the caller's arrays
+ * (each may be NULL); label strings stay valid until the next call on ctx.
+ * Returns the number of distinct labels, or a negative error code. */
+int miugks_timing(miugks_ctx* ctx, int cap, const char** names, int* launches, double* ms, double* bytes);
+
 /* Sizes: cells, fluid cells, velocities, levels. */
 int miugks_sizes(const miugks_ctx* ctx, int* nc, int* n_fluid, int* nk, int* n_levels);
 

@@ -66,6 +66,9 @@ _SIGS = {
                                              ctypes.c_int]),
     "miugks_correct": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, _dp, ctypes.c_void_p, ctypes.c_int,
                                       ctypes.c_int]),
+    "miugks_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "miugks_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), _ip, _dp,
+                                     _dp]),
     "miugks_sizes": (ctypes.c_int, [ctypes.c_void_p, _ip, _ip, _ip, _ip]),
 }
 

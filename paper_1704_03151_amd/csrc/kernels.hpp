@@ -324,9 +324,9 @@ __global__ void k_scale_d(double* __restrict__ a, size_t n, const double* __rest
 
 // limited slopes of the two cells of the face on side (2d) of cell c, and the
 // upwind interface values for one velocity.  Returns false if not interior.
-template <typename T>
+template <typename T, typename A>
 __device__ __forceinline__ bool face_upwind(const Geo& g, int c, int d, const T* __restrict__ F, int nk,
-                                            int k, T un, T& Gup, T& Hup, T& sGup, T& sHup) {
+                                            int k, A un, A& Gup, A& Hup, A& sGup, A& sHup) {
     int nc = g.nc;
     int L = g.nb[(2 * d) * nc + c];
     if (L < 0) return false;
@@ -334,52 +334,53 @@ __device__ __forceinline__ bool face_upwind(const Geo& g, int c, int d, const T*
     int RR = g.nb[(2 * d + 1) * nc + c];
     size_t ho = (size_t)nk * nc;
     size_t kc = (size_t)k * nc;
-    T dcLR = T(g.dcent[(2 * d) * nc + c]);
-    T dL = T(0.5) * T(d == 0 ? g.dx[L % g.nx] : g.dy[L / g.nx]);
-    T dR = T(0.5) * T(d == 0 ? g.dx[c % g.nx] : g.dy[c / g.nx]);
-    T GL = F[kc + L], GR = F[kc + c], HL = F[ho + kc + L], HR = F[ho + kc + c];
-    T gLR = (GR - GL) / dcLR, hLR = (HR - HL) / dcLR;
-    T sGL = 0, sHL = 0, sGR = 0, sHR = 0;
-    if (un >= T(0)) {   // left slope needed (and both for un == 0)
-        T gm = 0, hm = 0;
+    A dcLR = A(g.dcent[(2 * d) * nc + c]);
+    A dL = A(0.5) * A(d == 0 ? g.dx[L % g.nx] : g.dy[L / g.nx]);
+    A dR = A(0.5) * A(d == 0 ? g.dx[c % g.nx] : g.dy[c / g.nx]);
+    A GL = A(F[kc + L]), GR = A(F[kc + c]), HL = A(F[ho + kc + L]), HR = A(F[ho + kc + c]);
+    A gLR = (GR - GL) / dcLR, hLR = (HR - HL) / dcLR;
+    A sGL = 0, sHL = 0, sGR = 0, sHR = 0;
+    if (un >= A(0)) {   // left slope needed (and both for un == 0)
+        A gm = 0, hm = 0;
         if (LL >= 0) {
-            T dc = T(g.dcent[(2 * d) * nc + L]);
-            gm = (GL - F[kc + LL]) / dc;
-            hm = (HL - F[ho + kc + LL]) / dc;
+            A dc = A(g.dcent[(2 * d) * nc + L]);
+            gm = (GL - A(F[kc + LL])) / dc;
+            hm = (HL - A(F[ho + kc + LL])) / dc;
         }
         sGL = van_leer(gm, gLR);
         sHL = van_leer(hm, hLR);
     }
-    if (un <= T(0)) {
-        T gp = 0, hp = 0;
+    if (un <= A(0)) {
+        A gp = 0, hp = 0;
         if (RR >= 0) {
-            T dc = T(g.dcent[(2 * d + 1) * nc + c]);
-            gp = (F[kc + RR] - GR) / dc;
-            hp = (F[ho + kc + RR] - HR) / dc;
+            A dc = A(g.dcent[(2 * d + 1) * nc + c]);
+            gp = (A(F[kc + RR]) - GR) / dc;
+            hp = (A(F[ho + kc + RR]) - HR) / dc;
         }
         sGR = van_leer(gLR, gp);
         sHR = van_leer(hLR, hp);
     }
-    if (un > T(0)) {
+    if (un > A(0)) {
         Gup = GL + sGL * dL;
         Hup = HL + sHL * dL;
         sGup = sGL;
         sHup = sHL;
-    } else if (un < T(0)) {
+    } else if (un < A(0)) {
         Gup = GR - sGR * dR;
         Hup = HR - sHR * dR;
         sGup = sGR;
         sHup = sHR;
     } else {
-        Gup = T(0.5) * (GL + sGL * dL + GR - sGR * dR);
-        Hup = T(0.5) * (HL + sHL * dL + HR - sHR * dR);
-        sGup = T(0.5) * (sGL + sGR);
-        sHup = T(0.5) * (sHL + sHR);
+        Gup = A(0.5) * (GL + sGL * dL + GR - sGR * dR);
+        Hup = A(0.5) * (HL + sHL * dL + HR - sHR * dR);
+        sGup = A(0.5) * (sGL + sGR);
+        sHup = A(0.5) * (sHL + sHR);
     }
     return true;
 }
 
 // raw moments of the upwind interface distribution of the -x and -y faces
+// (interface values formed in double from the stored distribution)
 template <typename T>
 __global__ void __launch_bounds__(256) k_face_moments_partial(Geo g, Vel vel, const T* __restrict__ f,
                                                               double* __restrict__ part) {
@@ -389,16 +390,44 @@ __global__ void __launch_bounds__(256) k_face_moments_partial(Geo g, Vel vel, co
     for (int m = 0; m < 2 * NRAW; ++m) a[m] = 0.0;
     if (ch.valid && !g.solid[ch.c]) {
         for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
-            T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
+            double u = vel.u[k], v = vel.v[k];
             double w = vel.w[k];
             for (int d = 0; d < 2; ++d) {
-                T Gup, Hup, sG, sH;
-                if (face_upwind<T>(g, ch.c, d, f, vel.nk, k, d == 0 ? u : v, Gup, Hup, sG, sH))
-                    raw_accumulate(a + d * NRAW, w, vel.u[k], vel.v[k], double(Gup), double(Hup));
+                double Gup, Hup, sG, sH;
+                if (face_upwind<T, double>(g, ch.c, d, f, vel.nk, k, d == 0 ? u : v, Gup, Hup, sG, sH))
+                    raw_accumulate(a + d * NRAW, w, u, v, Gup, Hup);
             }
         }
     }
     reduce_store<2 * NRAW>(a, sh, part, g.nc, ch.c, ch.valid);
+}
+
+// Reductions over all velocities inside one block: 64 lanes (consecutive
+// cells) x FW waves, wave w taking velocities w, w + FW, ...; the waves'
+// partial sums are added in LDS in a fixed order (deterministic) by wave 0,
+// which then owns the totals.
+constexpr int FW = 8;
+
+template <int M>
+__device__ __forceinline__ void block_sum_waves(double* acc, double* sh) {
+    // sh holds at least ceil(M/2) * FW * 64 doubles; two rounds of M/2 moments
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int H = (M + 1) / 2;
+    double tot[M];
+    for (int half = 0; half < 2; ++half) {
+        int m0 = half * H, m1 = M < m0 + H ? M : m0 + H;
+        for (int m = m0; m < m1; ++m) sh[((m - m0) * FW + wave) * 64 + lane] = acc[m];
+        __syncthreads();
+        if (wave == 0)
+            for (int m = m0; m < m1; ++m) {
+                double t = sh[((m - m0) * FW + 0) * 64 + lane];
+                for (int w = 1; w < FW; ++w) t += sh[((m - m0) * FW + w) * 64 + lane];
+                tot[m] = t;
+            }
+        __syncthreads();
+    }
+    if (wave == 0)
+        for (int m = 0; m < M; ++m) acc[m] = tot[m];
 }
 
 // Interface record, per (direction d, cell c) = the face on side 2d of c:
@@ -446,6 +475,69 @@ __global__ void k_face_finalize(Geo g, Gas gas, const double* __restrict__ part,
                             q[0] / dt, q[1] / dt, q[2] / dt, q[3] / dt, q[4] / dt, 1.0};
         for (int m = 0; m < NFP; ++m) rec[m * stride] = vals[m];
     }
+}
+
+// Interface record of one face from the raw moments of its upwind
+// distribution (shared by the face kernels)
+__device__ __forceinline__ void face_record(const Geo& g, const Gas& gas, const double* M, int d, int c,
+                                            const double* __restrict__ W, double* __restrict__ fp) {
+    size_t stride = 2 * (size_t)g.nc;
+    double* rec = fp + (size_t)d * g.nc + c;
+    int L = g.nb[(2 * d) * g.nc + c];
+    if (g.solid[c] || L < 0) {
+        for (int m = 0; m < NFP; ++m) rec[m * stride] = 0.0;
+        return;
+    }
+    double W0[4], q0[2];
+    raw_to_macro(M, W0, q0);
+    double rho, U, V, lam;
+    prim_of(W0, gas.K, rho, U, V, lam);
+    double tau = mu_of(gas, 1.0 / lam) / (rho / (2.0 * lam));
+    double dt = fmin(g.dt[L], g.dt[c]);
+    double q[5];
+    time_coeffs(dt, tau, q);
+    double dL = 0.5 * (d == 0 ? g.dx[L % g.nx] : g.dy[L / g.nx]);
+    double dR = 0.5 * (d == 0 ? g.dx[c % g.nx] : g.dy[c / g.nx]);
+    double bL[4], bR[4], aL[4], aR[4];
+    for (int m = 0; m < 4; ++m) {
+        bL[m] = (W0[m] - W[m * g.nc + L]) / dL / rho;
+        bR[m] = (W[m * g.nc + c] - W0[m]) / dR / rho;
+    }
+    micro_slope(bL, U, V, lam, gas.K, aL);
+    micro_slope(bR, U, V, lam, gas.K, aR);
+    double sh = 0.8 * (1.0 - gas.Pr) * lam * lam / rho;
+    double vals[NFP] = {rho, U, V, lam, sh * q0[0], sh * q0[1],
+                        aL[0], aL[1], aL[2], aL[3], aR[0], aR[1], aR[2], aR[3],
+                        0, 0, 0, 0,
+                        q[0] / dt, q[1] / dt, q[2] / dt, q[3] / dt, q[4] / dt, 1.0};
+    for (int m = 0; m < NFP; ++m) rec[m * stride] = vals[m];
+}
+
+// Step 1, first part: raw moments of the upwind interface distribution of
+// the -x and -y faces of 64 cells over all velocities, then the interface
+// records (equilibrium, Shakhov heat flux, micro-slopes, time coefficients)
+template <typename T>
+__global__ void __launch_bounds__(64 * FW) k_face_prep(Geo g, Vel vel, Gas gas, const T* __restrict__ f,
+                                                       const double* __restrict__ W, double* __restrict__ fp) {
+    __shared__ double sh[NRAW * FW * 64];
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int c = blockIdx.x * 64 + lane;
+    bool valid = c < g.nc;
+    double a[2 * NRAW];
+    for (int m = 0; m < 2 * NRAW; ++m) a[m] = 0.0;
+    if (valid && !g.solid[c]) {
+        for (int k = wave; k < vel.nk; k += FW) {
+            double u = vel.u[k], v = vel.v[k], w = vel.w[k];
+            for (int d = 0; d < 2; ++d) {
+                double Gup, Hup, sG, sH;
+                if (face_upwind<T, double>(g, c, d, f, vel.nk, k, d == 0 ? u : v, Gup, Hup, sG, sH))
+                    raw_accumulate(a + d * NRAW, w, u, v, Gup, Hup);
+            }
+        }
+    }
+    block_sum_waves<2 * NRAW>(a, sh);
+    if (wave == 0 && valid)
+        for (int d = 0; d < 2; ++d) face_record(g, gas, a + d * NRAW, d, c, W, fp);
 }
 
 // G- and H-parts of (a1 + a2 u + a3 v + a4 (u^2+v^2+xi^2)/2) times the
@@ -502,6 +594,105 @@ __global__ void __launch_bounds__(256) k_face_timeslope_partial(Geo g, Vel vel, 
         }
     }
     reduce_store<8>(a, sh, part, g.nc, ch.c, ch.valid);
+}
+
+// Step 1, second part: time slope Abar of each face from the compatibility
+// condition in discrete form, over all velocities in one block
+template <typename T>
+__global__ void __launch_bounds__(64 * FW) k_face_timeslope(Geo g, Vel vel, Gas gas, double* __restrict__ fp) {
+    __shared__ double sh[4 * FW * 64];
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int c = blockIdx.x * 64 + lane;
+    bool valid = c < g.nc;
+    double a[8];
+    for (int m = 0; m < 8; ++m) a[m] = 0.0;
+    size_t stride = 2 * (size_t)g.nc;
+    if (valid && !g.solid[c]) {
+        for (int d = 0; d < 2; ++d) {
+            const double* rec = fp + (size_t)d * g.nc + c;
+            if (rec[23 * stride] == 0.0) continue;
+            T rho = T(rec[0]), U = T(rec[stride]), V = T(rec[2 * stride]), lam = T(rec[3 * stride]);
+            T aL[4], aR[4];
+            for (int m = 0; m < 4; ++m) {
+                aL[m] = T(rec[(6 + m) * stride]);
+                aR[m] = T(rec[(10 + m) * stride]);
+            }
+            T pref = rho * lam / T(M_PI);
+            for (int k = wave; k < vel.nk; k += FW) {
+                T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
+                T un = d == 0 ? u : v;
+                T du = u - U, dv = v - V;
+                T G0 = pref * dexp(-lam * (du * du + dv * dv));
+                T H0 = T(gas.K_int) / (T(2) * lam) * G0;
+                T pG, pH, qG, qH;
+                slope_poly<T>(un > T(0) ? aL : aR, u, v, lam, gas.K_int, pG, pH);
+                if (un == T(0)) {
+                    slope_poly<T>(aL, u, v, lam, gas.K_int, pG, pH);
+                    slope_poly<T>(aR, u, v, lam, gas.K_int, qG, qH);
+                    pG = T(0.5) * (pG + qG);
+                    pH = T(0.5) * (pH + qH);
+                }
+                double sG = double(un) * double(pG * G0), sH = double(un) * double(pH * H0);
+                double w = vel.w[k], ud = vel.u[k], vd = vel.v[k];
+                a[4 * d + 0] += w * sG;
+                a[4 * d + 1] += w * ud * sG;
+                a[4 * d + 2] += w * vd * sG;
+                a[4 * d + 3] += 0.5 * w * ((ud * ud + vd * vd) * sG + sH);
+            }
+        }
+    }
+    block_sum_waves<8>(a, sh);
+    if (wave == 0 && valid && !g.solid[c])
+        for (int d = 0; d < 2; ++d) {
+            double* rec = fp + (size_t)d * g.nc + c;
+            if (rec[23 * stride] == 0.0) continue;
+            double rho = rec[0], U = rec[stride], V = rec[2 * stride], lam = rec[3 * stride];
+            double b[4], A[4];
+            for (int m = 0; m < 4; ++m) b[m] = -a[4 * d + m] / rho;
+            micro_slope(b, U, V, lam, gas.K, A);
+            for (int m = 0; m < 4; ++m) rec[(14 + m) * stride] = A[m];
+        }
+}
+
+// Step 7 (and Step 6 when df != nullptr): f += df, then W and q of f, over
+// all velocities in one block
+template <typename T>
+__global__ void __launch_bounds__(64 * FW) k_moments_full(Geo g, Vel vel, T* __restrict__ f,
+                                                          const T* __restrict__ df, double* __restrict__ W,
+                                                          double* __restrict__ q) {
+    __shared__ double sh[6 * FW * 64];
+    int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int c = blockIdx.x * 64 + lane;
+    bool valid = c < g.nc;
+    double a[NRAW];
+    for (int m = 0; m < NRAW; ++m) a[m] = 0.0;
+    if (valid) {
+        size_t nc = g.nc;
+        for (int k = wave; k < vel.nk; k += FW) {
+            size_t ig = (size_t)k * nc + c, ih = (size_t)(vel.nk + k) * nc + c;
+            T G = f[ig], H = f[ih];
+            if (df) {
+                G += df[ig];
+                H += df[ih];
+                f[ig] = G;
+                f[ih] = H;
+            }
+            raw_accumulate(a, vel.w[k], vel.u[k], vel.v[k], double(G), double(H));
+        }
+    }
+    block_sum_waves<NRAW>(a, sh);
+    if (wave == 0 && valid) {
+        if (g.solid[c]) {
+            for (int m = 0; m < 4; ++m) W[m * g.nc + c] = 0.0;
+            q[c] = q[g.nc + c] = 0.0;
+        } else {
+            double w4[4], q2[2];
+            raw_to_macro(a, w4, q2);
+            for (int m = 0; m < 4; ++m) W[m * g.nc + c] = w4[m];
+            q[c] = q2[0];
+            q[g.nc + c] = q2[1];
+        }
+    }
 }
 
 __global__ void k_face_timeslope_finalize(Geo g, Gas gas, const double* __restrict__ part, int nkc,
@@ -575,13 +766,17 @@ __device__ __forceinline__ void face_flux(const T* P, T u, T v, T un, T Gup, T H
 }
 
 // Step 1: div_ik = (1/V_i) sum_faces S u_n ftilde (outward) for G and H, and
-// partial sums of the macroscopic residual R_i = -sum_k w psi div_ik
+// partial sums of the macroscopic residual R_i = -sum_k w psi div_ik.  The
+// flux arithmetic runs in double on the stored (T) distribution: R is a
+// difference of fluxes scaled by S/V, and single-precision products would
+// leave ~1e-6 of rounding noise in it; div is stored in T.
 template <typename T>
 __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const T* __restrict__ f,
                                                   const double* __restrict__ fp,
                                                   const double* __restrict__ rho_w,
                                                   const T* __restrict__ finf, T* __restrict__ div,
                                                   double* __restrict__ part) {
+    typedef double A;
     __shared__ double sh[4 * WAVES * TILE];
     Chunk ch = chunk_of(g.nc, vel.nk);
     double acc[4] = {0, 0, 0, 0};
@@ -592,50 +787,50 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
         int kk[MK];
         int nmine = 0;
         for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) kk[nmine++] = k;
-        T dG[MK], dH[MK];
-        for (int j = 0; j < MK; ++j) dG[j] = dH[j] = T(0);
+        A dG[MK], dH[MK];
+        for (int j = 0; j < MK; ++j) dG[j] = dH[j] = A(0);
         bool fluid = !g.solid[c];
         int ix = c % g.nx, iy = c / g.nx;
         if (fluid) {
             for (int s = 0; s < 4; ++s) {
                 int code = g.nb[s * g.nc + c];
                 int d = s >> 1;
-                T sign = (s & 1) ? T(1) : T(-1);
-                T sv = T(1.0 / (d == 0 ? g.dx[ix] : g.dy[iy]));   // S / V
+                A sign = (s & 1) ? A(1) : A(-1);
+                A sv = A(1.0 / (d == 0 ? g.dx[ix] : g.dy[iy]));   // S / V
                 if (code >= 0) {
                     // face record: the -d face of the cell on the positive side
                     int R = (s & 1) ? code : c;
                     const double* rec = fp + (size_t)d * g.nc + R;
                     size_t stride = 2 * nc;
-                    T P[23];
-                    for (int m = 0; m < 23; ++m) P[m] = T(rec[m * stride]);
+                    A P[23];
+                    for (int m = 0; m < 23; ++m) P[m] = A(rec[m * stride]);
                     for (int j = 0; j < nmine; ++j) {
                         int k = kk[j];
-                        T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
-                        T un = d == 0 ? u : v;
-                        T Gup, Hup, sGu, sHu, PG, PH;
-                        face_upwind<T>(g, R, d, f, nk, k, un, Gup, Hup, sGu, sHu);
-                        face_flux<T>(P, u, v, un, Gup, Hup, sGu, sHu, gas.K_int, PG, PH);
+                        A u = vel.u[k], v = vel.v[k];
+                        A un = d == 0 ? u : v;
+                        A Gup, Hup, sGu, sHu, PG, PH;
+                        face_upwind<T, A>(g, R, d, f, nk, k, un, Gup, Hup, sGu, sHu);
+                        face_flux<A>(P, u, v, un, Gup, Hup, sGu, sHu, gas.K_int, PG, PH);
                         dG[j] += sign * sv * PG;
                         dH[j] += sign * sv * PH;
                     }
                 } else if (is_wall(code)) {
                     int jw = wall_of(code);
-                    T lam = T(1.0 / g.w_T[jw]), Uw = T(g.w_U[jw]), Vw = T(g.w_V[jw]);
-                    T rw = T(rho_w[jw]);
+                    A lam = A(1.0 / g.w_T[jw]), Uw = A(g.w_U[jw]), Vw = A(g.w_V[jw]);
+                    A rw = A(rho_w[jw]);
                     for (int j = 0; j < nmine; ++j) {
                         int k = kk[j];
-                        T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
-                        T un = sign * (d == 0 ? u : v);
-                        T Gf, Hf;
-                        if (un > T(0)) {
-                            Gf = f[(size_t)k * nc + c];
-                            Hf = f[ho + (size_t)k * nc + c];
+                        A u = vel.u[k], v = vel.v[k];
+                        A un = sign * (d == 0 ? u : v);
+                        A Gf, Hf;
+                        if (un > A(0)) {
+                            Gf = A(f[(size_t)k * nc + c]);
+                            Hf = A(f[ho + (size_t)k * nc + c]);
                         } else {
-                            T du = u - Uw, dv = v - Vw;
-                            T C = lam / T(M_PI) * dexp(-lam * (du * du + dv * dv));
+                            A du = u - Uw, dv = v - Vw;
+                            A C = lam / A(M_PI) * dexp(-lam * (du * du + dv * dv));
                             Gf = rw * C;
-                            Hf = rw * T(gas.K_int) / (T(2) * lam) * C;
+                            Hf = rw * A(gas.K_int) / (A(2) * lam) * C;
                         }
                         dG[j] += sv * un * Gf;
                         dH[j] += sv * un * Hf;
@@ -644,14 +839,14 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
                     bool far = code == NB_FARFIELD;
                     for (int j = 0; j < nmine; ++j) {
                         int k = kk[j];
-                        T un = sign * (d == 0 ? vel_u<T>(vel, k) : vel_v<T>(vel, k));
-                        T Gf, Hf;
-                        if (far && un <= T(0)) {
-                            Gf = finf[k];
-                            Hf = finf[nk + k];
+                        A un = sign * (d == 0 ? A(vel.u[k]) : A(vel.v[k]));
+                        A Gf, Hf;
+                        if (far && un <= A(0)) {
+                            Gf = A(finf[k]);
+                            Hf = A(finf[nk + k]);
                         } else {
-                            Gf = f[(size_t)k * nc + c];
-                            Hf = f[ho + (size_t)k * nc + c];
+                            Gf = A(f[(size_t)k * nc + c]);
+                            Hf = A(f[ho + (size_t)k * nc + c]);
                         }
                         dG[j] += sv * un * Gf;
                         dH[j] += sv * un * Hf;
@@ -661,8 +856,8 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
         }
         for (int j = 0; j < nmine; ++j) {
             int k = kk[j];
-            div[(size_t)k * nc + c] = dG[j];
-            div[ho + (size_t)k * nc + c] = dH[j];
+            div[(size_t)k * nc + c] = T(dG[j]);
+            div[ho + (size_t)k * nc + c] = T(dH[j]);
             double w = vel.w[k], u = vel.u[k], v = vel.v[k];
             double gd = double(dG[j]), hd = double(dH[j]);
             acc[0] += w * gd;
@@ -805,54 +1000,260 @@ __device__ __forceinline__ void upwind_term(const Geo& g, int c, int s, T u, T v
     }
 }
 
+// Side types packed per cell for the sweeps: 2 bits per side (0 interior,
+// 1 wall, 2 farfield, 3 outflow), bit 8 = solid cell, bits 9-31 = index of
+// the cell's first wall side in the level's wall list (the wall sides of a
+// cell are listed consecutively in side order).
+constexpr unsigned FLAG_SOLID = 0x100;
+constexpr int FLAG_WALL_SHIFT = 9;
+
+__device__ __forceinline__ int side_type(unsigned fl, int s) { return (fl >> (2 * s)) & 3; }
+
+// wall-list index of side s of a cell whose flags are fl (side s is a wall)
+__device__ __forceinline__ int wall_index_fl(unsigned fl, int s) {
+    int j = (int)(fl >> FLAG_WALL_SHIFT);
+    for (int q = 0; q < s; ++q) j += side_type(fl, q) == 1;
+    return j;
+}
+
+// transport part of D_ik from the packed side types
+template <typename T>
+__device__ __forceinline__ T transport_diag_fl(unsigned fl, T u, T v, T invdx, T invdy) {
+    T D = T(0);
+    for (int s = 0; s < 4; ++s) {
+        T un = ((s & 1) ? T(1) : T(-1)) * (s < 2 ? u : v);
+        T a = side_type(fl, s) == 3 ? un : (un > T(0) ? un : T(0));
+        D += a * (s < 2 ? invdx : invdy);
+    }
+    return D;
+}
+
+// wall ghost C_k drho_w of the G (part 0) or H (part 1) correction at wall j
+template <typename T>
+__device__ __forceinline__ T wall_ghost_j(const Geo& g, int j, T u, T v, int K_int, int part,
+                                          const double* __restrict__ drho) {
+    T lam = T(1.0 / g.w_T[j]);
+    T du = u - T(g.w_U[j]), dv = v - T(g.w_V[j]);
+    T C = lam / T(M_PI) * dexp(-lam * (du * du + dv * dv));
+    if (part) C *= T(K_int) / (T(2) * lam);
+    return C * T(drho[j]);
+}
+
+// After a sweep: w_k u_n dG_k at every wall side for this velocity (zero for
+// u_n <= 0), the per-velocity terms of the next wall densities
+template <typename T>
+__device__ __forceinline__ void wall_products(const Geo& g, const Vel& vel, int k, const T* Gk,
+                                              double* __restrict__ wbuf) {
+    double u = vel.u[k], v = vel.v[k], w = vel.w[k];
+    for (int j = threadIdx.x; j < g.n_wall; j += blockDim.x) {
+        int s = g.w_side[j];
+        double un = ((s & 1) ? 1.0 : -1.0) * (s < 2 ? u : v);
+        wbuf[(size_t)j * vel.nk + k] = un > 0.0 ? w * un * double(Gk[g.w_cell[j]]) : 0.0;
+    }
+}
+
+// Copy n elements between global memory and LDS with every thread keeping
+// four 16-byte accesses in flight (the tiles are latency-bound otherwise);
+// element counts that are not a multiple of the vector width finish
+// element by element.
+template <typename T>
+__device__ __forceinline__ void bulk_copy(T* __restrict__ dst, const T* __restrict__ src, int n) {
+    constexpr int V = 16 / sizeof(T);
+    typedef __attribute__((ext_vector_type(V))) T vec;
+    int tid = threadIdx.x, nthr = blockDim.x;
+    bool aligned = ((((size_t)dst) | ((size_t)src)) & 15) == 0;
+    int nv = aligned ? n / V : 0;
+    const vec* s = (const vec*)src;
+    vec* d = (vec*)dst;
+    int i = tid;
+    for (; i + 3 * nthr < nv; i += 4 * nthr) {
+        vec a = s[i], b = s[i + nthr], c = s[i + 2 * nthr], e = s[i + 3 * nthr];
+        d[i] = a;
+        d[i + nthr] = b;
+        d[i + 2 * nthr] = c;
+        d[i + 3 * nthr] = e;
+    }
+    for (; i < nv; i += nthr) d[i] = s[i];
+    for (int j = nv * V + tid; j < n; j += nthr) dst[j] = src[j];
+}
+
 // One Gauss-Seidel sweep of every velocity in its own upwind order (the
-// LU-SGS sweep of Sec. II A 2 taken along the direction of each velocity):
-// block k sweeps velocity k; thread t owns row t (counted from the upwind
-// y-side) and processes column s - t at step s, so each cell sees its
-// x-upwind neighbour from its own previous step and its y-upwind neighbour
-// from thread t-1's previous step (through LDS).  Wall densities drho are
-// those of the correction before the sweep.
+// LU-SGS sweep of Sec. II A 2 taken along the direction of each velocity),
+// staged in LDS.  A block runs P pipelines side by side; pipeline p sweeps
+// item blockIdx.x * P + p, item = 2 k + part (G or H of velocity k), and the
+// per-cell data (1/tau + 1/dt_n, side flags, 1/dx) is shared by the P tiles.
+// Thread t of a pipeline owns row t (counted from the upwind y-side) and
+// updates column s - t at step s, so both upwind neighbours were written one
+// step earlier (one barrier per step); the thread keeps its own previous
+// cell in a register and reads the one below it from LDS, and it loads the
+// data of its next cell before the barrier.  The tile holds r and is
+// overwritten by the correction, which needs no initial value.  Wall ghosts
+// use the wall densities of the correction before the sweep, evaluated per
+// item before the first step.
+template <typename T>
+__global__ void k_sweep_lds(Geo g, Vel vel, int K_int, const T* __restrict__ r, T* __restrict__ df,
+                            const double* __restrict__ tau_inv, const double* __restrict__ dtn_inv,
+                            const unsigned* __restrict__ flags_g, const double* __restrict__ drho,
+                            double* __restrict__ wbuf, int npad, int P) {
+    extern __shared__ double smem_d[];
+    int nc = g.nc, nx = g.nx, ny = g.ny, nw = g.n_wall;
+    T* tiles = (T*)smem_d;                 // [P][nc]
+    T* coef = tiles + (size_t)P * nc;      // [nc]  1/tau + 1/dt_n
+    T* invdx = coef + nc;                  // [nx]
+    T* ghosts = invdx + nx;                // [P][n_wall]
+    unsigned* flags = (unsigned*)(ghosts + (size_t)P * nw);   // [nc]
+    int tid = threadIdx.x, nthr = blockDim.x;
+    int nitems = 2 * vel.nk;
+    int item0 = blockIdx.x * P;
+    for (int i = tid; i < nc; i += nthr) {
+        coef[i] = T(tau_inv[i] + dtn_inv[i]);
+        flags[i] = flags_g[i];
+    }
+    for (int i = tid; i < nx; i += nthr) invdx[i] = T(1.0 / g.dx[i]);
+    for (int q = 0; q < P; ++q) {
+        int item = item0 + q;
+        if (item >= nitems) break;
+        int k = item >> 1, part = item & 1;
+        bulk_copy<T>(tiles + (size_t)q * nc, r + ((size_t)part * vel.nk + k) * nc, nc);
+        T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
+        for (int j = tid; j < nw; j += nthr)
+            ghosts[(size_t)q * nw + j] = wall_ghost_j<T>(g, j, u, v, K_int, part, drho);
+    }
+    __syncthreads();
+    int p = tid / npad, t = tid - p * npad;
+    int item = item0 + p;
+    bool live = p < P && item < nitems && t < ny;
+    int k = live ? (item >> 1) : 0;
+    T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
+    T* F = tiles + (size_t)(p < P ? p : 0) * nc;
+    const T* ghost = ghosts + (size_t)(p < P ? p : 0) * nw;
+    bool px = u >= T(0), py = v >= T(0);
+    int upx = px ? 0 : 1, upy = py ? 2 : 3;
+    int sx = px ? 1 : -1, sy = py ? 1 : -1;
+    int iy = py ? t : ny - 1 - t;
+    T invdy = live ? T(1.0 / g.dy[iy]) : T(0);
+    T au = px ? u : -u, av = py ? v : -v;   // |u|, |v|
+    T carry = T(0);
+    // data of the next cell of this row (prefetched one step ahead)
+    int c = 0, ix = 0;
+    unsigned fl = 0;
+    T rc = T(0), cf = T(0), idx = T(0);
+    auto fetch = [&](int jx) {
+        ix = px ? jx : nx - 1 - jx;
+        c = iy * nx + ix;
+        fl = flags[c];
+        rc = F[c];
+        cf = coef[c];
+        idx = invdx[ix];
+    };
+    if (live && t == 0) fetch(0);
+    int nsteps = nx + ny - 1;
+    for (int s = 0; s < nsteps; ++s) {
+        int jx = s - t;
+        bool act = live && jx >= 0 && jx < nx;
+        if (act) {
+            T val = T(0);
+            if (!(fl & FLAG_SOLID)) {
+                T D = cf + transport_diag_fl<T>(fl, u, v, idx, invdy);
+                T tx = T(0), ty = T(0);
+                int tpx = side_type(fl, upx), tpy = side_type(fl, upy);
+                if (tpx == 0)
+                    tx = -au * idx * carry;
+                else if (tpx == 1)
+                    tx = -au * idx * ghost[wall_index_fl(fl, upx)];
+                if (tpy == 0)
+                    ty = -av * invdy * F[c - sy * nx];
+                else if (tpy == 1)
+                    ty = -av * invdy * ghost[wall_index_fl(fl, upy)];
+                val = (rc - tx - ty) / D;
+                F[c] = val;
+            }
+            carry = val;
+        }
+        // prefetch the next cell of this row (never written by other threads)
+        if (live && jx + 1 >= 0 && jx + 1 < nx) fetch(jx + 1);
+        __syncthreads();
+    }
+    for (int q = 0; q < P; ++q) {
+        int it = item0 + q;
+        if (it >= nitems) break;
+        int kq = it >> 1, part = it & 1;
+        const T* src = tiles + (size_t)q * nc;
+        bulk_copy<T>(df + ((size_t)part * vel.nk + kq) * nc, src, nc);
+        if (part == 0) wall_products<T>(g, vel, kq, src, wbuf);
+    }
+}
+
+// The same sweep with the tile in global memory, for levels whose tile does
+// not fit in LDS (one thread per row handles G and H; the neighbour in the
+// previous row is read back from global memory after the step barrier).
 template <typename T>
 __global__ void k_sweep(Geo g, Vel vel, int K_int, const T* __restrict__ r, T* __restrict__ df,
                         const double* __restrict__ tau_inv, const double* __restrict__ dtn_inv,
-                        const double* __restrict__ drho) {
-    __shared__ T bufG[2][1024];
-    __shared__ T bufH[2][1024];
+                        const unsigned* __restrict__ flags, const double* __restrict__ drho,
+                        double* __restrict__ wbuf) {
     int k = blockIdx.x, t = threadIdx.x;
     int nx = g.nx, ny = g.ny;
     size_t nc = g.nc, ho = (size_t)vel.nk * nc, kc = (size_t)k * nc;
     T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
     bool px = u >= T(0), py = v >= T(0);
     int upx = px ? 0 : 1, upy = py ? 2 : 3;
+    int sx = px ? 1 : -1, sy = py ? 1 : -1;
     int iy = py ? t : ny - 1 - t;
     bool row = t < ny;
-    T carryG = 0, carryH = 0;
+    T invdy = row ? T(1.0 / g.dy[iy]) : T(0);
+    T* G = df + kc;
+    T* H = df + ho + kc;
     int nsteps = nx + ny - 1;
     for (int s = 0; s < nsteps; ++s) {
         int jx = s - t;
-        T nG = 0, nH = 0;
         if (row && jx >= 0 && jx < nx) {
             int ix = px ? jx : nx - 1 - jx;
             int c = iy * nx + ix;
-            if (!g.solid[c]) {
-                T D = T(tau_inv[c]) + T(dtn_inv[c]) + transport_diag<T>(g, c, u, v);
-                T upG = t > 0 ? bufG[(s - 1) & 1][t - 1] : T(0);
-                T upH = t > 0 ? bufH[(s - 1) & 1][t - 1] : T(0);
-                T xG, xH, yG, yH;
-                upwind_term<T>(g, c, upx, u, v, K_int, carryG, carryH, drho, xG, xH);
-                upwind_term<T>(g, c, upy, u, v, K_int, upG, upH, drho, yG, yH);
-                nG = (r[kc + c] - xG - yG) / D;
-                nH = (r[ho + kc + c] - xH - yH) / D;
-                df[kc + c] = nG;
-                df[ho + kc + c] = nH;
+            unsigned fl = flags[c];
+            T nG = T(0), nH = T(0);
+            if (!(fl & FLAG_SOLID)) {
+                T idx = T(1.0 / g.dx[ix]);
+                T D = T(tau_inv[c] + dtn_inv[c]) + transport_diag_fl<T>(fl, u, v, idx, invdy);
+                T txG = 0, txH = 0, tyG = 0, tyH = 0;
+                int tpx = side_type(fl, upx), tpy = side_type(fl, upy);
+                T cx = (px ? -u : u) * idx, cy = (py ? -v : v) * invdy;
+                if (tpx == 0) {
+                    txG = cx * G[c - sx];
+                    txH = cx * H[c - sx];
+                } else if (tpx == 1) {
+                    int j = wall_index_fl(fl, upx);
+                    txG = cx * wall_ghost_j<T>(g, j, u, v, K_int, 0, drho);
+                    txH = cx * wall_ghost_j<T>(g, j, u, v, K_int, 1, drho);
+                }
+                if (tpy == 0) {
+                    tyG = cy * G[c - sy * nx];
+                    tyH = cy * H[c - sy * nx];
+                } else if (tpy == 1) {
+                    int j = wall_index_fl(fl, upy);
+                    tyG = cy * wall_ghost_j<T>(g, j, u, v, K_int, 0, drho);
+                    tyH = cy * wall_ghost_j<T>(g, j, u, v, K_int, 1, drho);
+                }
+                nG = (r[kc + c] - txG - tyG) / D;
+                nH = (r[ho + kc + c] - txH - tyH) / D;
             }
-            carryG = nG;
-            carryH = nH;
+            G[c] = nG;
+            H[c] = nH;
         }
-        bufG[s & 1][t] = nG;
-        bufH[s & 1][t] = nH;
         __syncthreads();
     }
+    wall_products<T>(g, vel, k, G, wbuf);
+}
+
+// drho_w = -sum_k wbuf[j][k] / den_j: one wavefront per wall side
+__global__ void k_drho(Geo g, int nk, const double* __restrict__ wbuf, double* __restrict__ drho) {
+    int j = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    int lane = threadIdx.x & 63;
+    double s = 0.0;
+    if (j < g.n_wall)
+        for (int k = lane; k < nk; k += 64) s += wbuf[(size_t)j * nk + k];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0 && j < g.n_wall) drho[j] = -s / g.w_den[j];
 }
 
 // renewed residual r - A df on the fine level, restricted to the coarse
@@ -923,9 +1324,8 @@ __global__ void __launch_bounds__(256) k_prolong_add(Geo g, Vel vel, int ncc, co
 }
 
 // restrict a per-cell double field (volume-weighted mean over fluid children)
-__global__ void k_restrict_cells(Geo g, Geo gc, int m, const double* __restrict__ a, double* __restrict__ ac) {
-    int C = blockIdx.x * blockDim.x + threadIdx.x;
-    if (C >= gc.nc) return;
+__device__ __forceinline__ void restrict_cell(const Geo& g, const Geo& gc, int m, const double* __restrict__ a,
+                                              double* __restrict__ ac, int C) {
     int I = C % gc.nx, J = C / gc.nx;
     for (int q = 0; q < m; ++q) {
         double s = 0.0, vol = 0.0;
@@ -939,6 +1339,11 @@ __global__ void k_restrict_cells(Geo g, Geo gc, int m, const double* __restrict_
             }
         ac[(size_t)q * gc.nc + C] = vol > 0 ? s / vol : 0.0;
     }
+}
+
+__global__ void k_restrict_cells(Geo g, Geo gc, int m, const double* __restrict__ a, double* __restrict__ ac) {
+    int C = blockIdx.x * blockDim.x + threadIdx.x;
+    if (C < gc.nc) restrict_cell(g, gc, m, a, ac, C);
 }
 
 // ---------------------------------------------------------------------------
@@ -978,9 +1383,10 @@ __device__ __forceinline__ int side_state(const Geo& g, const Gas& gas, const do
     return 3;
 }
 
-__global__ void k_fas_gamma(Geo g, Gas gas, const double* __restrict__ W, double* __restrict__ Gam) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= g.nc) return;
+// Gamma per side (frozen for a level visit): mean primitive state of the cell
+// and its neighbour or ghost
+__device__ __forceinline__ void fas_gamma_cell(const Geo& g, const Gas& gas, const double* __restrict__ W,
+                                               double* __restrict__ Gam, int c) {
     if (g.solid[c]) {
         for (int s = 0; s < 4; ++s) Gam[s * g.nc + c] = 0.0;
         return;
@@ -1004,10 +1410,9 @@ __global__ void k_fas_gamma(Geo g, Gas gas, const double* __restrict__ W, double
 }
 
 // out = base + sgn * R_split(W), R_split_i = -(1/V_i) sum_j S_ij F_ij(W)
-__global__ void k_fas_rsplit(Geo g, Gas gas, const double* __restrict__ W, const double* __restrict__ Gam,
-                             const double* __restrict__ base, double sgn, double* __restrict__ out) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= g.nc) return;
+__device__ __forceinline__ void fas_rsplit_cell(const Geo& g, const Gas& gas, const double* __restrict__ W,
+                                                const double* __restrict__ Gam, const double* __restrict__ base,
+                                                double sgn, double* __restrict__ out, int c) {
     if (g.solid[c]) {
         for (int m = 0; m < 4; ++m) out[m * g.nc + c] = 0.0;
         return;
@@ -1030,11 +1435,11 @@ __global__ void k_fas_rsplit(Geo g, Gas gas, const double* __restrict__ W, const
 }
 
 // one red-black half-sweep of the linearised defect equation of Sec. II A 1
-__global__ void k_fas_halfsweep(Geo g, Gas gas, const double* __restrict__ W, double* __restrict__ E,
-                                const double* __restrict__ Rm, const double* __restrict__ Gam,
-                                const double* __restrict__ dtn_inv, int colour) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= g.nc) return;
+// on cell c (if it has the colour)
+__device__ __forceinline__ void fas_halfsweep_cell(const Geo& g, const Gas& gas, const double* __restrict__ W,
+                                                   double* __restrict__ E, const double* __restrict__ Rm,
+                                                   const double* __restrict__ Gam,
+                                                   const double* __restrict__ dtn_inv, int colour, int c) {
     int ix = c % g.nx, iy = c / g.nx;
     if (((ix + iy) & 1) != colour || g.solid[c]) return;
     double Wi[4], Ei[4], Wj[4], Ej[4], A[4], B[4], acc[4] = {0, 0, 0, 0};
@@ -1081,9 +1486,7 @@ __global__ void k_fas_halfsweep(Geo g, Gas gas, const double* __restrict__ W, do
 }
 
 // W += E (fluid cells) and clear E
-__global__ void k_fas_apply(Geo g, double* __restrict__ W, double* __restrict__ E) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= g.nc) return;
+__device__ __forceinline__ void fas_apply_cell(const Geo& g, double* __restrict__ W, double* __restrict__ E, int c) {
     for (int m = 0; m < 4; ++m) {
         if (!g.solid[c]) W[m * g.nc + c] += E[m * g.nc + c];
         E[m * g.nc + c] = 0.0;
@@ -1091,10 +1494,9 @@ __global__ void k_fas_apply(Geo g, double* __restrict__ W, double* __restrict__ 
 }
 
 // W_fine += I_H^h (W_coarse - W0_coarse)
-__global__ void k_fas_prolong(Geo g, int ncc, const double* __restrict__ Wc, const double* __restrict__ Wc0,
-                              double* __restrict__ W) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= g.nc || g.solid[c]) return;
+__device__ __forceinline__ void fas_prolong_cell(const Geo& g, int ncc, const double* __restrict__ Wc,
+                                                 const double* __restrict__ Wc0, double* __restrict__ W, int c) {
+    if (g.solid[c]) return;
     for (int m = 0; m < 4; ++m) {
         double s = 0.0;
         for (int a = 0; a < 4; ++a) {
@@ -1102,6 +1504,108 @@ __global__ void k_fas_prolong(Geo g, int ncc, const double* __restrict__ Wc, con
             s += g.p_w[a * g.nc + c] * (Wc[(size_t)m * ncc + id] - Wc0[(size_t)m * ncc + id]);
         }
         W[m * g.nc + c] += s;
+    }
+}
+
+#define CELL_KERNEL_INDEX                               \
+    int c = blockIdx.x * blockDim.x + threadIdx.x;      \
+    if (c >= g.nc) return;
+
+__global__ void k_fas_gamma(Geo g, Gas gas, const double* __restrict__ W, double* __restrict__ Gam) {
+    CELL_KERNEL_INDEX
+    fas_gamma_cell(g, gas, W, Gam, c);
+}
+
+__global__ void k_fas_rsplit(Geo g, Gas gas, const double* __restrict__ W, const double* __restrict__ Gam,
+                             const double* __restrict__ base, double sgn, double* __restrict__ out) {
+    CELL_KERNEL_INDEX
+    fas_rsplit_cell(g, gas, W, Gam, base, sgn, out, c);
+}
+
+__global__ void k_fas_halfsweep(Geo g, Gas gas, const double* __restrict__ W, double* __restrict__ E,
+                                const double* __restrict__ Rm, const double* __restrict__ Gam,
+                                const double* __restrict__ dtn_inv, int colour) {
+    CELL_KERNEL_INDEX
+    fas_halfsweep_cell(g, gas, W, E, Rm, Gam, dtn_inv, colour, c);
+}
+
+__global__ void k_fas_apply(Geo g, double* __restrict__ W, double* __restrict__ E) {
+    CELL_KERNEL_INDEX
+    fas_apply_cell(g, W, E, c);
+}
+
+__global__ void k_fas_prolong(Geo g, int ncc, const double* __restrict__ Wc, const double* __restrict__ Wc0,
+                              double* __restrict__ W) {
+    CELL_KERNEL_INDEX
+    fas_prolong_cell(g, ncc, Wc, Wc0, W, c);
+}
+
+// The FAS V-cycle on levels l0 .. L-1, all in one workgroup: every phase of
+// the recursion (copy, Gamma, forcing, smoothing sweeps, renewal,
+// restriction, prolongation) is a loop over the cells of one level followed
+// by a workgroup barrier.  Used for the small levels, where a phase is far
+// shorter than a kernel launch.
+constexpr int FAS_MAXL = 8;
+
+struct FasSet {
+    int l0, L, nu1, nu2, nuc;
+    Geo geo[FAS_MAXL];
+    double *W[FAS_MAXL], *W0[FAS_MAXL], *R[FAS_MAXL], *P[FAS_MAXL], *E[FAS_MAXL], *Gam[FAS_MAXL],
+        *Rm[FAS_MAXL], *dtn[FAS_MAXL];
+};
+
+__device__ __forceinline__ void fas_block_smooth(const FasSet& F, const Gas& gas, int l, int count) {
+    const Geo& g = F.geo[l];
+    for (int it = 0; it < count; ++it) {
+        for (int c = threadIdx.x; c < g.nc; c += blockDim.x)
+            fas_rsplit_cell(g, gas, F.W[l], F.Gam[l], F.P[l], 1.0, F.Rm[l], c);
+        __syncthreads();
+        for (int col : {0, 1, 0}) {
+            for (int c = threadIdx.x; c < g.nc; c += blockDim.x)
+                fas_halfsweep_cell(g, gas, F.W[l], F.E[l], F.Rm[l], F.Gam[l], F.dtn[l], col, c);
+            __syncthreads();
+        }
+        for (int c = threadIdx.x; c < g.nc; c += blockDim.x) fas_apply_cell(g, F.W[l], F.E[l], c);
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void fas_block_enter(const FasSet& F, const Gas& gas, int l) {
+    const Geo& g = F.geo[l];
+    for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
+        for (int m = 0; m < 4; ++m) F.W0[l][m * g.nc + c] = F.W[l][m * g.nc + c];
+        fas_gamma_cell(g, gas, F.W[l], F.Gam[l], c);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < g.nc; c += blockDim.x)
+        fas_rsplit_cell(g, gas, F.W[l], F.Gam[l], F.R[l], -1.0, F.P[l], c);
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(512) k_fas_cycle_block(FasSet F, Gas gas) {
+    int L = F.L;
+    for (int l = F.l0; l < L - 1; ++l) {
+        const Geo& g = F.geo[l];
+        const Geo& gc = F.geo[l + 1];
+        fas_block_enter(F, gas, l);
+        fas_block_smooth(F, gas, l, F.nu1);
+        for (int c = threadIdx.x; c < g.nc; c += blockDim.x)
+            fas_rsplit_cell(g, gas, F.W[l], F.Gam[l], F.P[l], 1.0, F.Rm[l], c);
+        __syncthreads();
+        for (int C = threadIdx.x; C < gc.nc; C += blockDim.x) {
+            restrict_cell(g, gc, 4, F.W[l], F.W[l + 1], C);
+            restrict_cell(g, gc, 4, F.Rm[l], F.R[l + 1], C);
+        }
+        __syncthreads();
+    }
+    fas_block_enter(F, gas, L - 1);
+    fas_block_smooth(F, gas, L - 1, F.nuc);
+    for (int l = L - 2; l >= F.l0; --l) {
+        const Geo& g = F.geo[l];
+        for (int c = threadIdx.x; c < g.nc; c += blockDim.x)
+            fas_prolong_cell(g, F.geo[l + 1].nc, F.W[l + 1], F.W0[l + 1], F.W[l], c);
+        __syncthreads();
+        fas_block_smooth(F, gas, l, F.nu2);
     }
 }
 
@@ -1120,9 +1624,24 @@ __global__ void k_convert(const A* __restrict__ a, B* __restrict__ b, size_t n) 
         b[i] = B(a[i]);
 }
 
-__global__ void k_dtn(Geo g, double factor, double* __restrict__ out) {
+// 1/dt_n = a^{-n} / dt_p per cell; the factor a^{-n} is read from device
+// memory so that a captured graph serves every cycle
+__global__ void k_dtn(Geo g, const double* __restrict__ factor, double* __restrict__ out) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < g.nc) out[c] = factor > 0.0 ? factor / g.dt[c] : 0.0;
+    double f = factor[0];
+    if (c < g.nc) out[c] = f > 0.0 ? f / g.dt[c] : 0.0;
+}
+
+// copy n doubles from up to two sources to two destinations each (b may be
+// null); keeps graph captures free of memcpy nodes
+__global__ void k_copy2(const double* __restrict__ a, double* __restrict__ a1, double* __restrict__ a2,
+                        const double* __restrict__ b, double* __restrict__ b1, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        double x = a[i];
+        a1[i] = x;
+        if (a2) a2[i] = x;
+        if (b) b1[i] = b[i];
+    }
 }
 
 }  // namespace miugks

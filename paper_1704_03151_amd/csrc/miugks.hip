@@ -10,6 +10,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -31,6 +32,8 @@ struct DevLevel {
 };
 
 }  // namespace
+
+struct miugks_timing_state;
 
 struct miugks_ctx {
     std::string err;
@@ -61,6 +64,20 @@ struct miugks_ctx {
     double M0 = 1.0;
     int cycle = 0;
     bool have_div = false;
+    struct miugks_timing_state* timing = nullptr;
+    // ordered-sweep support per level
+    std::vector<unsigned*> flags;
+    std::vector<double*> wbuf;
+    std::vector<char> sweep_lds;
+    // graphs of Step 1 and Steps 2-7; pseudo-step factor a^{-n}
+    bool use_graphs = true;
+    bool own_stream = false;
+    hipGraphExec_t g_step1 = nullptr, g_rest = nullptr;
+    double* d_factor = nullptr;
+    double* h_factor = nullptr;
+    // FAS levels run inside one workgroup from this level on
+    int fas_block_l0 = 1 << 30;
+    FasSet fasset{};
 };
 
 namespace {
@@ -107,94 +124,214 @@ int check_launch(miugks_ctx* ctx) {
 }
 
 // ---------------------------------------------------------------------------
+// per-kernel timing: HIP events around each launch on the library's stream,
+// aggregated by kernel label together with the launch's algorithmic bytes
+
+struct TimingRec {
+    const char* name;
+    double bytes;
+    hipEvent_t a, b;
+};
+
+struct TimingAgg {
+    std::string name;
+    long launches = 0;
+    double ms = 0.0, bytes = 0.0;
+};
+
+}  // namespace
+
+struct miugks_timing_state {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<TimingRec> pending;
+    std::vector<TimingAgg> agg;
+};
+
+namespace {
+
+miugks_timing_state& timing(miugks_ctx* c) {
+    if (!c->timing) c->timing = new miugks_timing_state();
+    return *c->timing;
+}
+
+TimingRec* timing_begin(miugks_ctx* c, const char* name, double bytes) {
+    miugks_timing_state& t = timing(c);
+    if (!t.on) return nullptr;
+    hipEvent_t e[2];
+    for (int i = 0; i < 2; ++i) {
+        if (t.pool.empty()) {
+            if (hipEventCreate(&e[i]) != hipSuccess) return nullptr;
+        } else {
+            e[i] = t.pool.back();
+            t.pool.pop_back();
+        }
+    }
+    t.pending.push_back({name, bytes, e[0], e[1]});
+    (void)hipEventRecord(e[0], c->stream);
+    return &t.pending.back();
+}
+
+void timing_end(miugks_ctx* c, TimingRec* r) {
+    if (r) (void)hipEventRecord(r->b, c->stream);
+}
+
+// fold completed records into the aggregate (call after a stream sync)
+void timing_harvest(miugks_ctx* c) {
+    miugks_timing_state& t = timing(c);
+    for (auto& r : t.pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            TimingAgg* a = nullptr;
+            for (auto& x : t.agg)
+                if (x.name == r.name) a = &x;
+            if (!a) {
+                t.agg.push_back(TimingAgg());
+                a = &t.agg.back();
+                a->name = r.name;
+            }
+            a->launches += 1;
+            a->ms += ms;
+            a->bytes += r.bytes;
+        }
+        t.pool.push_back(r.a);
+        t.pool.push_back(r.b);
+    }
+    t.pending.clear();
+}
+
+#define LAUNCH_SH(c, name, bytes, shmem, kernel, grid, block, ...)                \
+    do {                                                                          \
+        TimingRec* rec_ = timing_begin((c), (name), (double)(bytes));             \
+        hipLaunchKernelGGL(kernel, grid, block, shmem, (c)->stream, __VA_ARGS__); \
+        timing_end((c), rec_);                                                    \
+    } while (0)
+#define LAUNCH(c, name, bytes, kernel, grid, block, ...) \
+    LAUNCH_SH(c, name, bytes, 0, kernel, grid, block, __VA_ARGS__)
+
+// LDS bytes of the staged sweep on a level: r/df tile (G, H), 1/tau + 1/dt_n,
+// 1/dx, side flags
+template <typename T>
+size_t sweep_lds_bytes(const Geo& g, int P) {
+    size_t b = ((size_t)P * g.nc + g.nc + g.nx + (size_t)P * g.n_wall) * sizeof(T) + 4 * (size_t)g.nc;
+    return (b + 15) & ~(size_t)15;
+}
+
+// ---------------------------------------------------------------------------
 // the hot path, per precision
 
 template <typename T>
 struct Path {
     static T* F(miugks_ctx* c) { return (T*)c->f; }
+    // bytes of one distribution-shaped array on level l
+    static double arr(miugks_ctx* c, int l) { return 2.0 * c->nk * c->geo[l].nc * sizeof(T); }
 
     // Step 7: W, q of f (optionally after f += df, Step 6)
     static void moments(miugks_ctx* c, const T* df) {
         const Geo& g = c->geo[0];
-        int nkc = nchunks(c->nk);
-        hipLaunchKernelGGL(k_moments_partial<T>, dim3(ntiles(g.nc), nkc), dim3(256), 0, c->stream, g, c->vel,
-                           F(c), df, c->part);
-        hipLaunchKernelGGL(k_moments_finalize, dim3(nblk(g.nc)), dim3(256), 0, c->stream, g, c->part, nkc,
-                           c->W, c->q);
+        LAUNCH(c, df ? "update_moments" : "moments", (df ? 3 : 1) * arr(c, 0) + 6.0 * g.nc * 8, k_moments_full<T>,
+               dim3(ntiles(g.nc)), dim3(64 * FW), g, c->vel, F(c), df, c->W, c->q);
     }
 
     static void wall_sums(miugks_ctx* c, int l, const T* G, double* out) {
         const Geo& g = c->geo[l];
         if (g.n_wall == 0) return;
         int nkc = nchunks(c->nk);
-        hipLaunchKernelGGL(k_wall_partial<T>, dim3(ntiles(g.n_wall), nkc), dim3(256), 0, c->stream, g, c->vel,
-                           G, c->part);
-        hipLaunchKernelGGL(k_wall_finalize, dim3(nblk(g.n_wall)), dim3(256), 0, c->stream, g, c->part, nkc, out);
+        LAUNCH(c, "wall_sums", (double)g.n_wall * c->nk * sizeof(T), k_wall_partial<T>,
+               dim3(ntiles(g.n_wall), nkc), dim3(256), g, c->vel, G, c->part);
+        LAUNCH(c, "wall_finalize", (double)g.n_wall * (nkc + 2) * 8, k_wall_finalize, dim3(nblk(g.n_wall)),
+               dim3(256), g, c->part, nkc, out);
     }
 
     // Step 1: interface records, div, R and the RMS norms (into c->norms)
     static void residual(miugks_ctx* c) {
         const Geo& g = c->geo[0];
         int nkc = nchunks(c->nk), nt = ntiles(g.nc);
-        hipLaunchKernelGGL(k_face_moments_partial<T>, dim3(nt, nkc), dim3(256), 0, c->stream, g, c->vel, F(c),
-                           c->part);
-        hipLaunchKernelGGL(k_face_finalize, dim3(nblk(g.nc)), dim3(256), 0, c->stream, g, c->gas, c->part, nkc,
-                           c->W, c->fp);
-        hipLaunchKernelGGL(k_face_timeslope_partial<T>, dim3(nt, nkc), dim3(256), 0, c->stream, g, c->vel,
-                           c->gas, c->fp, c->part);
-        hipLaunchKernelGGL(k_face_timeslope_finalize, dim3(nblk(g.nc)), dim3(256), 0, c->stream, g, c->gas,
-                           c->part, nkc, c->fp);
+        double nc8 = g.nc * 8.0;
+        LAUNCH(c, "face_prep", arr(c, 0) + (4 + 2 * NFP) * nc8, k_face_prep<T>, dim3(nt), dim3(64 * FW), g,
+               c->vel, c->gas, F(c), c->W, c->fp);
+        LAUNCH(c, "face_timeslope", (2.0 * NFP + 8) * nc8, k_face_timeslope<T>, dim3(nt), dim3(64 * FW), g,
+               c->vel, c->gas, c->fp);
         wall_sums(c, 0, F(c), c->rho_w);
-        hipLaunchKernelGGL(k_flux_div<T>, dim3(nt, nkc), dim3(256), 0, c->stream, g, c->vel, c->gas, F(c), c->fp,
-                           c->rho_w, (const T*)c->finf, (T*)c->div, c->part);
-        hipLaunchKernelGGL(k_residual_finalize, dim3(nblk(g.nc)), dim3(256), 0, c->stream, g, c->part, nkc, c->R);
-        hipLaunchKernelGGL(k_residual_norm, dim3(1), dim3(256), 0, c->stream, g, c->hl[0].n_fluid, c->R, c->norms);
+        LAUNCH(c, "flux_div", 2 * arr(c, 0) + (2.0 * NFP + 4.0 * nkc) * nc8, k_flux_div<T>, dim3(nt, nkc),
+               dim3(256), g, c->vel, c->gas, F(c), c->fp, c->rho_w, (const T*)c->finf, (T*)c->div, c->part);
+        LAUNCH(c, "residual_finalize", (4.0 * nkc + 4) * nc8, k_residual_finalize, dim3(nblk(g.nc)), dim3(256),
+               g, c->part, nkc, c->R);
+        LAUNCH(c, "residual_norm", 4 * nc8, k_residual_norm, dim3(1), dim3(256), g, c->hl[0].n_fluid, c->R,
+               c->norms);
         c->have_div = true;
     }
 
     // Steps 3-4 (with the positivity guard on c->Wt)
     static void micro_residual(miugks_ctx* c) {
         const Geo& g = c->geo[0];
-        hipLaunchKernelGGL(k_cell_prep, dim3(nblk(g.nc)), dim3(256), 0, c->stream, g, c->gas, c->Wt, c->W, c->q,
-                           c->cp, c->tau_inv[0]);
-        hipLaunchKernelGGL(k_micro_residual<T>, dim3(ntiles(g.nc), nchunks(c->nk)), dim3(256), 0, c->stream, g,
-                           c->vel, c->gas, F(c), (const T*)c->div, c->cp, (T*)c->r[0]);
+        LAUNCH(c, "cell_prep", (14.0 + NCP) * g.nc * 8, k_cell_prep, dim3(nblk(g.nc)), dim3(256), g, c->gas, c->Wt,
+               c->W, c->q, c->cp, c->tau_inv[0]);
+        LAUNCH(c, "micro_residual", 3 * arr(c, 0) + NCP * g.nc * 8.0, k_micro_residual<T>,
+               dim3(ntiles(g.nc), nchunks(c->nk)), dim3(256), g, c->vel, c->gas, F(c), (const T*)c->div, c->cp,
+               (T*)c->r[0]);
     }
 
-    static void smooth(miugks_ctx* c, int l) {
+    // one smoothing on level l: wall densities from the current correction
+    // (skipped when drho is already current), then the ordered sweep, which
+    // also leaves the wall products of its result in wbuf
+    static void smooth(miugks_ctx* c, int l, bool drho_current) {
         const Geo& g = c->geo[l];
-        wall_sums(c, l, (const T*)c->df[l], c->drho[l]);
-        int threads = ((g.ny + 63) / 64) * 64;
-        hipLaunchKernelGGL(k_sweep<T>, dim3(c->nk), dim3(threads), 0, c->stream, g, c->vel, c->gas.K_int,
-                           (const T*)c->r[l], (T*)c->df[l], c->tau_inv[l], c->dtn_inv[l], c->drho[l]);
+        if (!drho_current && g.n_wall)
+            LAUNCH(c, "drho", (double)g.n_wall * c->nk * 8, k_drho, dim3((g.n_wall + 3) / 4), dim3(256), g, c->nk,
+                   c->wbuf[l], c->drho[l]);
+        const char* name = l == 0 ? "sweep_fine" : "sweep_coarse";
+        if (c->sweep_lds[l]) {
+            int npad = ((g.ny + 63) / 64) * 64, P = c->sweep_lds[l];
+            int blocks = (2 * c->nk + P - 1) / P;
+            LAUNCH_SH(c, name, 2 * arr(c, l), sweep_lds_bytes<T>(g, P), k_sweep_lds<T>, dim3(blocks), dim3(P * npad),
+                      g, c->vel, c->gas.K_int, (const T*)c->r[l], (T*)c->df[l], c->tau_inv[l], c->dtn_inv[l],
+                      c->flags[l], c->drho[l], c->wbuf[l], npad, P);
+        } else {
+            int threads = ((g.ny + 63) / 64) * 64;
+            LAUNCH(c, name, 2 * arr(c, l), k_sweep<T>, dim3(c->nk), dim3(threads), g, c->vel, c->gas.K_int,
+                   (const T*)c->r[l], (T*)c->df[l], c->tau_inv[l], c->dtn_inv[l], c->flags[l], c->drho[l],
+                   c->wbuf[l]);
+        }
     }
 
-    // dF_l = CS(l, r_l) (Sec. II D); r_l, tau_inv_l, dtn_inv_l in place
+    // dF_l = CS(l, r_l) (Sec. II D); r_l, tau_inv_l, dtn_inv_l in place.  The
+    // correction starts at zero: zero wall densities for the first sweep (the
+    // sweep itself needs no initial correction).
     static void cs(miugks_ctx* c, int l) {
         const Geo& g = c->geo[l];
-        size_t n = 2 * (size_t)c->nk * g.nc;
-        hipLaunchKernelGGL(k_zero<T>, dim3(nblk((int)std::min<size_t>(n, 1 << 24))), dim3(256), 0, c->stream,
-                           (T*)c->df[l], n);
-        if (l == c->L - 1) {
-            for (int i = 0; i < c->nuc; ++i) smooth(c, l);
-            return;
+        if (g.n_wall)
+            LAUNCH(c, "zero", (double)g.n_wall * 8, k_zero<double>, dim3(1), dim3(256), c->drho[l],
+                   (size_t)g.n_wall);
+        int pre = l == c->L - 1 ? c->nuc : c->nu1;
+        for (int i = 0; i < pre; ++i) smooth(c, l, i == 0);
+        if (l == c->L - 1) return;
+        if (pre == 0) {
+            size_t n = 2 * (size_t)c->nk * g.nc;
+            LAUNCH(c, "zero", arr(c, l), k_zero<T>, dim3(nblk((int)std::min<size_t>(n, 1 << 24))), dim3(256),
+                   (T*)c->df[l], n);
+        } else if (g.n_wall) {
+            LAUNCH(c, "drho", (double)g.n_wall * c->nk * 8, k_drho, dim3((g.n_wall + 3) / 4), dim3(256), g, c->nk,
+                   c->wbuf[l], c->drho[l]);
         }
-        for (int i = 0; i < c->nu1; ++i) smooth(c, l);
         const Geo& gc = c->geo[l + 1];
-        wall_sums(c, l, (const T*)c->df[l], c->drho[l]);
-        hipLaunchKernelGGL(k_defect_restrict<T>, dim3(ntiles(gc.nc), nchunks(c->nk)), dim3(256), 0, c->stream, g,
-                           gc, c->vel, c->gas.K_int, (const T*)c->r[l], (const T*)c->df[l], c->tau_inv[l],
-                           c->dtn_inv[l], c->drho[l], (T*)c->r[l + 1]);
+        LAUNCH(c, "defect_restrict", 2 * arr(c, l) + arr(c, l + 1), k_defect_restrict<T>,
+               dim3(ntiles(gc.nc), nchunks(c->nk)), dim3(256), g, gc, c->vel, c->gas.K_int, (const T*)c->r[l],
+               (const T*)c->df[l], c->tau_inv[l], c->dtn_inv[l], c->drho[l], (T*)c->r[l + 1]);
         cs(c, l + 1);
-        hipLaunchKernelGGL(k_prolong_add<T>, dim3(ntiles(g.nc), nchunks(c->nk)), dim3(256), 0, c->stream, g,
-                           c->vel, gc.nc, (const T*)c->df[l + 1], (T*)c->df[l]);
-        for (int i = 0; i < c->nu2; ++i) smooth(c, l);
+        LAUNCH(c, "prolong_add", 2 * arr(c, l) + arr(c, l + 1), k_prolong_add<T>,
+               dim3(ntiles(g.nc), nchunks(c->nk)), dim3(256), g, c->vel, gc.nc, (const T*)c->df[l + 1],
+               (T*)c->df[l]);
+        // the prolongation changed the correction: wall densities from it
+        if (c->nu2 > 0) wall_sums(c, l, (const T*)c->df[l], c->drho[l]);
+        for (int i = 0; i < c->nu2; ++i) smooth(c, l, i == 0);
     }
 
     static void correct(miugks_ctx* c) {
         for (int l = 0; l + 1 < c->L; ++l)
-            hipLaunchKernelGGL(k_restrict_cells, dim3(nblk(c->geo[l + 1].nc)), dim3(256), 0, c->stream,
-                               c->geo[l], c->geo[l + 1], 1, c->tau_inv[l], c->tau_inv[l + 1]);
+            LAUNCH(c, "restrict_cells", (c->geo[l].nc + c->geo[l + 1].nc) * 8.0, k_restrict_cells,
+                   dim3(nblk(c->geo[l + 1].nc)), dim3(256), c->geo[l], c->geo[l + 1], 1, c->tau_inv[l],
+                   c->tau_inv[l + 1]);
         cs(c, 0);
     }
 
@@ -203,14 +340,14 @@ struct Path {
         moments(c, (const T*)c->df[0]);
         if (c->renorm) {
             const Geo& g = c->geo[0];
-            hipLaunchKernelGGL(k_mass, dim3(1), dim3(1024), 0, c->stream, g, c->W, c->mass);
+            LAUNCH(c, "mass", 4.0 * g.nc * 8, k_mass, dim3(1), dim3(1024), g, c->W, c->mass);
             size_t n = 2 * (size_t)c->nk * g.nc;
-            hipLaunchKernelGGL(k_scale_f<T>, dim3(nblk((int)std::min<size_t>(n, 1 << 24))), dim3(256), 0,
-                               c->stream, F(c), n, c->mass, c->M0);
-            hipLaunchKernelGGL(k_scale_d, dim3(nblk(6 * g.nc)), dim3(256), 0, c->stream, c->W, 4 * (size_t)g.nc,
-                               c->mass, c->M0);
-            hipLaunchKernelGGL(k_scale_d, dim3(nblk(2 * g.nc)), dim3(256), 0, c->stream, c->q, 2 * (size_t)g.nc,
-                               c->mass, c->M0);
+            LAUNCH(c, "scale_f", 2 * arr(c, 0), k_scale_f<T>, dim3(nblk((int)std::min<size_t>(n, 1 << 24))),
+                   dim3(256), F(c), n, c->mass, c->M0);
+            LAUNCH(c, "scale_moments", 12.0 * g.nc * 8, k_scale_d, dim3(nblk(6 * g.nc)), dim3(256), c->W,
+                   4 * (size_t)g.nc, c->mass, c->M0);
+            LAUNCH(c, "scale_moments", 4.0 * g.nc * 8, k_scale_d, dim3(nblk(2 * g.nc)), dim3(256), c->q,
+                   2 * (size_t)g.nc, c->mass, c->M0);
         }
     }
 };
@@ -221,56 +358,112 @@ struct Path {
 void fas_smooth(miugks_ctx* c, int l) {
     const Geo& g = c->geo[l];
     int nb = nblk(g.nc);
-    hipLaunchKernelGGL(k_fas_rsplit, dim3(nb), dim3(256), 0, c->stream, g, c->gas, c->fW[l], c->fGam[l], c->fP[l],
-                       1.0, c->fRm[l]);
+    double nc8 = g.nc * 8.0;
+    LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas_rsplit, dim3(nb), dim3(256), g, c->gas, c->fW[l], c->fGam[l], c->fP[l],
+           1.0, c->fRm[l]);
     for (int col : {0, 1, 0})
-        hipLaunchKernelGGL(k_fas_halfsweep, dim3(nb), dim3(256), 0, c->stream, g, c->gas, c->fW[l], c->fE[l],
-                           c->fRm[l], c->fGam[l], c->dtn_inv[l], col);
-    hipLaunchKernelGGL(k_fas_apply, dim3(nb), dim3(256), 0, c->stream, g, c->fW[l], c->fE[l]);
+        LAUNCH(c, "fas_halfsweep", 18 * nc8, k_fas_halfsweep, dim3(nb), dim3(256), g, c->gas, c->fW[l], c->fE[l],
+               c->fRm[l], c->fGam[l], c->dtn_inv[l], col);
+    LAUNCH(c, "fas_apply", 16 * nc8, k_fas_apply, dim3(nb), dim3(256), g, c->fW[l], c->fE[l]);
 }
 
 // W_l^{n+1} = FAS(l, W_l^n, R_l^n): fW[l] holds W_l^n on entry and the result
 // on exit; fR[l] holds the target residual
 void fas(miugks_ctx* c, int l) {
+    if (l >= c->fas_block_l0) {
+        FasSet F = c->fasset;
+        F.l0 = l;
+        double cells = 0;
+        for (int q = l; q < c->L; ++q) cells += c->geo[q].nc;
+        LAUNCH(c, "fas_cycle_block", 60 * cells * 8.0, k_fas_cycle_block, dim3(1), dim3(512), F, c->gas);
+        return;
+    }
     const Geo& g = c->geo[l];
     int nb = nblk(g.nc);
-    size_t bytes = 4 * (size_t)g.nc * sizeof(double);
-    hipMemcpyAsync(c->fW0[l], c->fW[l], bytes, hipMemcpyDeviceToDevice, c->stream);
-    hipLaunchKernelGGL(k_fas_gamma, dim3(nb), dim3(256), 0, c->stream, g, c->gas, c->fW[l], c->fGam[l]);
-    hipLaunchKernelGGL(k_fas_rsplit, dim3(nb), dim3(256), 0, c->stream, g, c->gas, c->fW[l], c->fGam[l], c->fR[l],
-                       -1.0, c->fP[l]);
+    double nc8 = g.nc * 8.0;
+    LAUNCH(c, "copy", 8 * nc8, k_copy2, dim3(nblk(4 * g.nc)), dim3(256), c->fW[l], c->fW0[l], (double*)nullptr,
+           (const double*)nullptr, (double*)nullptr, 4 * (size_t)g.nc);
+    LAUNCH(c, "fas_gamma", 8 * nc8, k_fas_gamma, dim3(nb), dim3(256), g, c->gas, c->fW[l], c->fGam[l]);
+    LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas_rsplit, dim3(nb), dim3(256), g, c->gas, c->fW[l], c->fGam[l], c->fR[l],
+           -1.0, c->fP[l]);
     if (l == c->L - 1) {
         for (int i = 0; i < c->nuc; ++i) fas_smooth(c, l);
         return;
     }
     for (int i = 0; i < c->nu1; ++i) fas_smooth(c, l);
     const Geo& gc = c->geo[l + 1];
-    hipLaunchKernelGGL(k_fas_rsplit, dim3(nb), dim3(256), 0, c->stream, g, c->gas, c->fW[l], c->fGam[l], c->fP[l],
-                       1.0, c->fRm[l]);
-    hipLaunchKernelGGL(k_restrict_cells, dim3(nblk(gc.nc)), dim3(256), 0, c->stream, g, gc, 4, c->fW[l],
-                       c->fW[l + 1]);
-    hipLaunchKernelGGL(k_restrict_cells, dim3(nblk(gc.nc)), dim3(256), 0, c->stream, g, gc, 4, c->fRm[l],
-                       c->fR[l + 1]);
+    LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas_rsplit, dim3(nb), dim3(256), g, c->gas, c->fW[l], c->fGam[l], c->fP[l],
+           1.0, c->fRm[l]);
+    LAUNCH(c, "fas_restrict", 5 * nc8, k_restrict_cells, dim3(nblk(gc.nc)), dim3(256), g, gc, 4, c->fW[l],
+           c->fW[l + 1]);
+    LAUNCH(c, "fas_restrict", 5 * nc8, k_restrict_cells, dim3(nblk(gc.nc)), dim3(256), g, gc, 4, c->fRm[l],
+           c->fR[l + 1]);
     fas(c, l + 1);
-    hipLaunchKernelGGL(k_fas_prolong, dim3(nb), dim3(256), 0, c->stream, g, gc.nc, c->fW[l + 1], c->fW0[l + 1],
-                       c->fW[l]);
+    LAUNCH(c, "fas_prolong", 10 * nc8, k_fas_prolong, dim3(nb), dim3(256), g, gc.nc, c->fW[l + 1], c->fW0[l + 1],
+           c->fW[l]);
     for (int i = 0; i < c->nu2; ++i) fas_smooth(c, l);
 }
 
+// pseudo step of the current cycle: the host writes a^{-n} to device memory
+// (outside any graph), the dtn kernels scale it by each level's 1/dt_p
+void set_dtn_factor(miugks_ctx* c) {
+    if (!(c->dtn_growth > 0.0)) return;
+    c->h_factor[0] = std::pow(c->dtn_growth, -(double)c->cycle);
+    (void)hipMemcpyAsync(c->d_factor, c->h_factor, sizeof(double), hipMemcpyHostToDevice, c->stream);
+}
+
 void set_dtn(miugks_ctx* c) {
-    double factor = c->dtn_growth > 0.0 ? std::pow(c->dtn_growth, -(double)c->cycle) : 0.0;
+    if (!(c->dtn_growth > 0.0)) return;
     for (int l = 0; l < c->L; ++l)
-        hipLaunchKernelGGL(k_dtn, dim3(nblk(c->geo[l].nc)), dim3(256), 0, c->stream, c->geo[l], factor,
-                           c->dtn_inv[l]);
+        LAUNCH(c, "dtn", 2.0 * c->geo[l].nc * 8, k_dtn, dim3(nblk(c->geo[l].nc)), dim3(256), c->geo[l],
+               (const double*)c->d_factor, c->dtn_inv[l]);
 }
 
 // Step 2 on the device arrays: fW[0] := W^n, fR[0] := R, result into Wt
 void predict(miugks_ctx* c) {
-    size_t bytes = 4 * (size_t)c->geo[0].nc * sizeof(double);
-    hipMemcpyAsync(c->fW[0], c->W, bytes, hipMemcpyDeviceToDevice, c->stream);
-    hipMemcpyAsync(c->fR[0], c->R, bytes, hipMemcpyDeviceToDevice, c->stream);
+    size_t n = 4 * (size_t)c->geo[0].nc;
+    LAUNCH(c, "copy", 24.0 * n, k_copy2, dim3(nblk((int)n)), dim3(256), (const double*)c->W, c->fW[0],
+           (double*)nullptr, (const double*)c->R, c->fR[0], n);
     fas(c, 0);
-    hipMemcpyAsync(c->Wt, c->fW[0], bytes, hipMemcpyDeviceToDevice, c->stream);
+    LAUNCH(c, "copy", 16.0 * n, k_copy2, dim3(nblk((int)n)), dim3(256), (const double*)c->fW[0], c->Wt,
+           (double*)nullptr, (const double*)nullptr, (double*)nullptr, n);
+}
+
+// Steps 2-7 of one cycle
+template <typename T>
+void cycle_rest(miugks_ctx* c) {
+    set_dtn(c);
+    predict(c);
+    Path<T>::micro_residual(c);
+    Path<T>::correct(c);
+    Path<T>::update(c);
+}
+
+// capture Step 1 and Steps 2-7 as two graphs (once per context); timing
+// runs stay eager because each launch is bracketed by events
+template <typename T>
+int ensure_graphs(miugks_ctx* c) {
+    if (c->g_step1 && c->g_rest) return MIUGKS_OK;
+    hipGraph_t gr;
+    for (int which = 0; which < 2; ++which) {
+        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            c->err = std::string("hipStreamBeginCapture: ") + hipGetErrorString(e);
+            return MIUGKS_EDEVICE;
+        }
+        if (which == 0)
+            Path<T>::residual(c);
+        else
+            cycle_rest<T>(c);
+        e = hipStreamEndCapture(c->stream, &gr);
+        if (e == hipSuccess) e = hipGraphInstantiate(which == 0 ? &c->g_step1 : &c->g_rest, gr, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipGraphDestroy(gr);
+        if (e != hipSuccess) {
+            c->err = std::string("graph capture: ") + hipGetErrorString(e);
+            return MIUGKS_EDEVICE;
+        }
+    }
+    return MIUGKS_OK;
 }
 
 template <typename T>
@@ -279,15 +472,26 @@ int run_cycles(miugks_ctx* c, int max_cycles, double tol, int* done, double* res
     double last[4] = {0, 0, 0, 0};
     double first_max = -1.0;
     int rc = MIUGKS_ENOTCONVERGED;
+    bool graphs = c->use_graphs && !timing(c).on;
+    if (graphs && (rc = ensure_graphs<T>(c))) return rc;
     for (int it = 0; it < max_cycles; ++it) {
-        Path<T>::residual(c);
-        hipMemcpyAsync(c->h_norms, c->norms, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (graphs) {
+            hipError_t ge = hipGraphLaunch(c->g_step1, c->stream);
+            if (ge != hipSuccess) {
+                c->err = std::string("hipGraphLaunch: ") + hipGetErrorString(ge);
+                return MIUGKS_EDEVICE;
+            }
+        } else {
+            Path<T>::residual(c);
+        }
+        (void)hipMemcpyAsync(c->h_norms, c->norms, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) {
             c->err = std::string("hipStreamSynchronize: ") + hipGetErrorString(e);
             return MIUGKS_EDEVICE;
         }
         if ((rc = check_launch(c))) return rc;
+        timing_harvest(c);
         double mx = 0.0;
         bool finite = true;
         for (int m = 0; m < 4; ++m) {
@@ -305,11 +509,16 @@ int run_cycles(miugks_ctx* c, int max_cycles, double tol, int* done, double* res
             rc = MIUGKS_OK;
             break;
         }
-        set_dtn(c);
-        predict(c);
-        Path<T>::micro_residual(c);
-        Path<T>::correct(c);
-        Path<T>::update(c);
+        set_dtn_factor(c);
+        if (graphs) {
+            hipError_t ge = hipGraphLaunch(c->g_rest, c->stream);
+            if (ge != hipSuccess) {
+                c->err = std::string("hipGraphLaunch: ") + hipGetErrorString(ge);
+                return MIUGKS_EDEVICE;
+            }
+        } else {
+            cycle_rest<T>(c);
+        }
         ++c->cycle;
         ++n;
         rc = MIUGKS_ENOTCONVERGED;
@@ -320,6 +529,7 @@ int run_cycles(miugks_ctx* c, int max_cycles, double tol, int* done, double* res
         return MIUGKS_EDEVICE;
     }
     if (int e = check_launch(c)) return e;
+    timing_harvest(c);
     if (done) *done = n;
     if (res)
         for (int m = 0; m < 4; ++m) res[m] = last[m];
@@ -362,6 +572,89 @@ int build_device(miugks_ctx* ctx) {
         g.w_den = wden;
         g.p_idx = pidx;
         g.p_w = pw;
+    }
+    // side flags per level, wall-product buffers, sweep variant
+    int dev = 0, max_lds = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    ctx->flags.resize(ctx->L);
+    ctx->wbuf.resize(ctx->L);
+    ctx->sweep_lds.assign(ctx->L, 0);
+    size_t need_max = 0;
+    for (int l = 0; l < ctx->L; ++l) {
+        HostLevel& h = ctx->hl[l];
+        std::vector<unsigned> fl(h.nc, 0);
+        for (int c = 0; c < h.nc; ++c) {
+            if (h.solid[c]) {
+                fl[c] = FLAG_SOLID;
+                continue;
+            }
+            unsigned f = 0;
+            int first_wall = -1;
+            for (int s = 0; s < 4; ++s) {
+                int code = h.nb[s * h.nc + c];
+                int t = code >= 0 ? 0 : (code <= NB_WALL0 ? 1 : (code == NB_FARFIELD ? 2 : 3));
+                if (t == 1 && first_wall < 0) first_wall = NB_WALL0 - code;
+                f |= (unsigned)(t << (2 * s));
+            }
+            if (first_wall >= (1 << (32 - FLAG_WALL_SHIFT))) {
+                ctx->err = "too many wall sides";
+                return MIUGKS_EINVAL;
+            }
+            if (first_wall > 0) f |= (unsigned)first_wall << FLAG_WALL_SHIFT;
+            fl[c] = f;
+        }
+        unsigned* p;
+        if ((rc = upload(ctx, &p, fl))) return rc;
+        ctx->flags[l] = p;
+        void* wb;
+        if ((rc = dev_alloc(ctx, &wb, std::max<size_t>(1, h.w_cell.size()) * ctx->nk * sizeof(double)))) return rc;
+        ctx->wbuf[l] = (double*)wb;
+        // pipelines per block: as many as fit in LDS and 1024 threads, but
+        // no more than needed to cover every item in one round of blocks
+        int npad = ((h.ny + 63) / 64) * 64;
+        int cus = 256;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        int best = 0;
+        for (int P = 1; P * npad <= 1024; ++P) {
+            size_t need = ctx->prec == MIUGKS_FP64 ? sweep_lds_bytes<double>(ctx->geo[l], P)
+                                                    : sweep_lds_bytes<float>(ctx->geo[l], P);
+            if (need > (size_t)max_lds) break;
+            best = P;
+            if ((2 * ctx->nk + P - 1) / P <= cus) break;
+        }
+        if (const char* e = getenv("MIUGKS_SWEEP_P")) best = std::min(best, atoi(e));
+        if (best > 0 && !getenv("MIUGKS_NO_LDS_SWEEP")) {
+            ctx->sweep_lds[l] = (char)best;
+            size_t need = ctx->prec == MIUGKS_FP64 ? sweep_lds_bytes<double>(ctx->geo[l], best)
+                                                    : sweep_lds_bytes<float>(ctx->geo[l], best);
+            need_max = std::max(need_max, need);
+        }
+    }
+    if (need_max > 65536) {
+        hipError_t e = ctx->prec == MIUGKS_FP64
+                           ? hipFuncSetAttribute((const void*)k_sweep_lds<double>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)need_max)
+                           : hipFuncSetAttribute((const void*)k_sweep_lds<float>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)need_max);
+        if (e != hipSuccess)
+            for (int l = 0; l < ctx->L; ++l)
+                if (ctx->sweep_lds[l] &&
+                    (ctx->prec == MIUGKS_FP64 ? sweep_lds_bytes<double>(ctx->geo[l], ctx->sweep_lds[l])
+                                              : sweep_lds_bytes<float>(ctx->geo[l], ctx->sweep_lds[l])) > 65536)
+                    ctx->sweep_lds[l] = 0;
+    }
+    if (getenv("MIUGKS_DEBUG"))
+        for (int l = 0; l < ctx->L; ++l)
+            fprintf(stderr, "[miugks] level %d: %dx%d cells, %d wall sides, sweep in %s, %d pipelines/block\n", l,
+                    ctx->hl[l].nx, ctx->hl[l].ny, (int)ctx->hl[l].w_cell.size(),
+                    ctx->sweep_lds[l] ? "LDS" : "global memory", (int)ctx->sweep_lds[l]);
+    {
+        void* df;
+        if ((rc = dev_alloc(ctx, &df, sizeof(double)))) return rc;
+        ctx->d_factor = (double*)df;
+        HIP_TRY(hipMemset(ctx->d_factor, 0, sizeof(double)));
+        HIP_TRY(hipHostMalloc((void**)&ctx->h_factor, sizeof(double), hipHostMallocDefault));
     }
     // velocities
     std::vector<float> uf(ctx->hv.u.begin(), ctx->hv.u.end()), vf(ctx->hv.v.begin(), ctx->hv.v.end()),
@@ -436,6 +729,29 @@ int build_device(miugks_ctx* ctx) {
             return rc;
         HIP_TRY(hipMemset(ctx->fE[l], 0, 4 * nc * sizeof(double)));
         HIP_TRY(hipMemset(ctx->dtn_inv[l], 0, nc * sizeof(double)));
+    }
+    // FAS in one workgroup for the trailing levels of at most this many cells
+    {
+        int lim = 256;
+        if (const char* e = getenv("MIUGKS_FAS_BLOCK_CELLS")) lim = atoi(e);
+        if (ctx->L <= FAS_MAXL)
+            for (int l = ctx->L - 1; l >= 0 && ctx->hl[l].nc <= lim; --l) ctx->fas_block_l0 = l;
+        FasSet& F = ctx->fasset;
+        F.L = ctx->L;
+        F.nu1 = ctx->nu1;
+        F.nu2 = ctx->nu2;
+        F.nuc = ctx->nuc;
+        for (int l = 0; l < ctx->L && l < FAS_MAXL; ++l) {
+            F.geo[l] = ctx->geo[l];
+            F.W[l] = ctx->fW[l];
+            F.W0[l] = ctx->fW0[l];
+            F.R[l] = ctx->fR[l];
+            F.P[l] = ctx->fP[l];
+            F.E[l] = ctx->fE[l];
+            F.Gam[l] = ctx->fGam[l];
+            F.Rm[l] = ctx->fRm[l];
+            F.dtn[l] = ctx->dtn_inv[l];
+        }
     }
     HIP_TRY(hipHostMalloc((void**)&ctx->h_norms, 4 * sizeof(double), hipHostMallocDefault));
     return MIUGKS_OK;
@@ -567,9 +883,18 @@ const char* miugks_last_error(const miugks_ctx* ctx) {
 
 void miugks_destroy(miugks_ctx* ctx) {
     if (!ctx) return;
-    if (ctx->stream) hipStreamSynchronize(ctx->stream);
-    for (void* p : ctx->allocs) hipFree(p);
-    if (ctx->h_norms) hipHostFree(ctx->h_norms);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->timing) {
+        timing_harvest(ctx);
+        for (hipEvent_t e : ctx->timing->pool) (void)hipEventDestroy(e);
+        delete ctx->timing;
+    }
+    if (ctx->g_step1) (void)hipGraphExecDestroy(ctx->g_step1);
+    if (ctx->g_rest) (void)hipGraphExecDestroy(ctx->g_rest);
+    for (void* p : ctx->allocs) (void)hipFree(p);
+    if (ctx->h_norms) (void)hipHostFree(ctx->h_norms);
+    if (ctx->h_factor) (void)hipHostFree(ctx->h_factor);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
 
@@ -587,6 +912,7 @@ int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgri
         return MIUGKS_ENOMEM;
     }
     ctx->stream = (hipStream_t)hip_stream;
+    ctx->use_graphs = getenv("MIUGKS_NO_GRAPH") == nullptr;
     if (s->precision != MIUGKS_FP64 && s->precision != MIUGKS_FP32F) {
         g_create_error = "precision must be MIUGKS_FP64 or MIUGKS_FP32F";
         delete ctx;
@@ -657,7 +983,16 @@ int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgri
     for (auto t : ctx->hl[0].ftx) closed = closed && t != MIUGKS_FACE_FARFIELD && t != MIUGKS_FACE_OUTFLOW;
     for (auto t : ctx->hl[0].fty) closed = closed && t != MIUGKS_FACE_FARFIELD && t != MIUGKS_FACE_OUTFLOW;
     ctx->renorm = s->mass_renorm < 0 ? closed : s->mass_renorm != 0;
-    hipGetDevice(&ctx->device);
+    (void)hipGetDevice(&ctx->device);
+    if (!ctx->stream) {
+        // the legacy default stream cannot be captured into graphs
+        if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+            g_create_error = "hipStreamCreateWithFlags failed";
+            delete ctx;
+            return MIUGKS_EDEVICE;
+        }
+        ctx->own_stream = true;
+    }
     int rc = build_device(ctx);
     if (rc) {
         g_create_error = ctx->err;
@@ -798,6 +1133,7 @@ int miugks_predict(miugks_ctx* ctx, const double* W, const double* R, double* W_
     }
     int rc;
     if ((rc = upload_cells(ctx, ctx->fW[0], W, 4)) || (rc = upload_cells(ctx, ctx->fR[0], R, 4))) return rc;
+    set_dtn_factor(ctx);
     set_dtn(ctx);
     fas(ctx, 0);
     return download_cells(ctx, W_out, ctx->fW[0], 4);
@@ -827,6 +1163,7 @@ int miugks_correct(miugks_ctx* ctx, const void* r, const double* tau_inv, void* 
     int rc;
     if ((rc = copy_in(ctx, r, ctx->r[0], dtype, on_device))) return rc;
     if ((rc = upload_cells(ctx, ctx->tau_inv[0], tau_inv, 1))) return rc;
+    set_dtn_factor(ctx);
     set_dtn(ctx);
     if (ctx->prec == MIUGKS_FP64)
         Path<double>::correct(ctx);
@@ -835,6 +1172,34 @@ int miugks_correct(miugks_ctx* ctx, const void* r, const double* tau_inv, void* 
     if (df_out) return copy_out(ctx, ctx->df[0], df_out, dtype, on_device);
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return check_launch(ctx);
+}
+
+int miugks_set_timing(miugks_ctx* ctx, int on) {
+    if (!ctx) return MIUGKS_EINVAL;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    miugks_timing_state& t = timing(ctx);
+    timing_harvest(ctx);
+    t.agg.clear();
+    t.on = on != 0;
+    return MIUGKS_OK;
+}
+
+int miugks_timing(miugks_ctx* ctx, int cap, const char** names, int* launches, double* ms, double* bytes) {
+    if (!ctx) return -MIUGKS_EINVAL;
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        ctx->err = "hipStreamSynchronize failed";
+        return -MIUGKS_EDEVICE;
+    }
+    miugks_timing_state& t = timing(ctx);
+    timing_harvest(ctx);
+    int n = (int)t.agg.size();
+    for (int i = 0; i < n && i < cap; ++i) {
+        if (names) names[i] = t.agg[i].name.c_str();
+        if (launches) launches[i] = (int)t.agg[i].launches;
+        if (ms) ms[i] = t.agg[i].ms;
+        if (bytes) bytes[i] = t.agg[i].bytes;
+    }
+    return n;
 }
 
 int miugks_sizes(const miugks_ctx* ctx, int* nc, int* n_fluid, int* nk, int* n_levels) {

@@ -157,6 +157,21 @@ class Solver:
                                                  _C.dptr(ti), code, 0))
         return r, ti
 
+    def set_timing(self, on=True):
+        self._check(_C.lib.miugks_set_timing(self.h, 1 if on else 0))
+
+    def timing(self):
+        """{label: (launches, total ms, algorithmic bytes)} since set_timing(True)."""
+        cap = 64
+        names = (ctypes.c_char_p * cap)()
+        launches = (ctypes.c_int * cap)()
+        ms = np.zeros(cap)
+        by = np.zeros(cap)
+        n = _C.lib.miugks_timing(self.h, cap, names, launches, _C.dptr(ms), _C.dptr(by))
+        if n < 0:
+            self._check(-n)
+        return {names[i].decode(): (launches[i], float(ms[i]), float(by[i])) for i in range(min(n, cap))}
+
     def correct(self, r, tau_inv):
         a = np.ascontiguousarray(r)
         code = _C.FP64 if a.dtype == np.float64 else _C.FP32F

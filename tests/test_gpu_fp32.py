@@ -1,0 +1,92 @@
+"""FP32-f form (float distribution and per-velocity arithmetic, double
+moments / prediction / norms) against the FP64 oracle.  Tolerances follow
+from float rounding: single steps 2e-5 of the max-norm, fields after a few
+cycles 1e-5, steady states 1e-5 (max-norm relative per field)."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from _parity import field_errors, perturbed_state, rel_max, small_cases, to_oracle
+from oracle.cs import cs_cycle
+from oracle.solver import Oracle
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _solver(case):
+    from paper_1704_03151_amd import Solver
+    return Solver(case, precision="fp32f")
+
+
+@pytest.mark.parametrize("name", ["cavity16_kn10", "plate32x24", "square20x20"])
+def test_fp32_steps(name):
+    case = small_cases()[name]
+    print(f"[fp32] case {name}", flush=True)
+    gpu = _solver(case)
+    orc = Oracle(case)
+    prim, pert = perturbed_state(case, 5)
+    gpu.init_macro(prim)
+    orc.init_macro(prim)
+    gpu.set_f((gpu.get_f(np.float64) * pert).astype(np.float32))
+    # the oracle sees the same float-rounded distribution
+    f32 = gpu.get_f(np.float64)
+    G, H = to_oracle(f32)
+    orc.set_f(G, H)
+    R, norms = gpu.residual()
+    orc.step1()
+    dG, dH = to_oracle(gpu.div(np.float64))
+    assert rel_max(dG, orc.divG) < 2e-5 and rel_max(dH, orc.divH) < 2e-5, (rel_max(dG, orc.divG),)
+    Rref = orc.R.reshape(4, case.ny, case.nx)
+    for m in range(4):
+        assert rel_max(R[m], Rref[m]) < 2e-5, (m, rel_max(R[m], Rref[m]))
+    fl = orc.lev0.fluid
+    r = wl.random_field((2, case.n_vel, case.ny, case.nx), seed=23) * fl.reshape(case.ny, case.nx)
+    ti = wl.random_field((case.ny, case.nx), seed=29, lo=0.5, hi=3.0)
+    gpu.init_macro(case.init)
+    orc.cycle = 0
+    out = gpu.correct(r.astype(np.float32), ti)
+    rG, rH = to_oracle(r.astype(np.float32))
+    cG, cH = cs_cycle(orc.cs_levels, orc.levels, orc.prolongs, 0, rG, rH, orc.level_tau_inv(ti.ravel() * fl),
+                      orc.dtn_inv(), orc.params)
+    gG, gH = to_oracle(out)
+    assert rel_max(gG, cG) < 2e-5 and rel_max(gH, cH) < 2e-5, (rel_max(gG, cG), rel_max(gH, cH))
+    gpu.close()
+
+
+def test_fp32_bench_case_three_cycles():
+    """The bench workload at full size (64x64 x 784, 4 levels): three outer
+    cycles of the FP32-f form against three FP64 oracle cycles."""
+    case = wl.config2()
+    print("[fp32] cavity64 3 cycles", flush=True)
+    gpu = _solver(case)
+    rc, n, res = gpu.iterate(3, tol=0.0)
+    orc = Oracle(case.with_(precision="fp64"))
+    orc.iterate(3, tol=0.0)
+    err = field_errors(gpu.macro(), orc.primitive(), orc.lev0.fluid)
+    print(f"[fp32] cavity64 after 3 cycles: {err}, residuals {res}", flush=True)
+    assert max(err.values()) < 1e-5, err
+    gpu.close()
+
+
+def test_fp32_bench_case_steady_state():
+    """FP32-f steady state of the bench workload against the oracle's FP64
+    steady state (converged to 5e-9, tests/golden)."""
+    path = os.path.join(GOLDEN, "cavity64_kn0.075_steady.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden steady state not generated")
+    ref = np.load(path)
+    case = wl.config2()
+    gpu = _solver(case)
+    rc, n, res = gpu.iterate(400, tol=1e-6)
+    assert rc == 0, (rc, n, res)
+    rc2, n2, res2 = gpu.iterate(400, tol=2e-7)
+    m = gpu.macro()
+    err = field_errors(m, (ref["rho"], ref["U"], ref["V"], ref["T"]))
+    print(f"[fp32] cavity64 steady: 1e-6 after {n} cycles (oracle {int(ref['cycles_to_1e6'])}), "
+          f"then {n2} more to {res2.max():.2e}; field errors {err}", flush=True)
+    assert max(err.values()) < 1e-5, err
+    gpu.close()
