@@ -29,9 +29,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell·velocity updates/s per MG cycle; wall time to residual 1e-6; HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-# traffic of the dominant kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE per
-# launch (bytes), scaled by a plain-copy calibration; None until measured
-# for the current kernel
+# HBM-side traffic of the dominant kernel, bytes per launch (mean over its
+# launches in one profiled run): rocprofv3 FETCH_SIZE and WRITE_SIZE, each
+# scaled by the ratio of known bytes to counted bytes of a plain copy in the
+# same run (--copy-calibration).  Keyed by (workload, precision, kernel); an
+# entry is dropped whenever that kernel changes.
 MEASURED_TRAFFIC = {}
 
 
@@ -64,6 +66,9 @@ def main():
     ap.add_argument("--cpu-cycles", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true", help="skip the time-to-1e-6 runs")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="end with one plain device-to-device copy of MIB MiB, the reference launch "
+                         "that scales the FETCH_SIZE / WRITE_SIZE counters of a profiled run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -100,14 +105,24 @@ def main():
     stats = solver.timing()
     solver.set_timing(False)
     total_ms = sum(v[1] for v in stats.values())
-    dom = max(stats, key=lambda k: stats[k][1])
-    launches, ms, by = stats[dom]
+    # labels "kernel/level" are one kernel launched on several levels: the
+    # roofline takes the kernel with the largest total time over all levels
+    per_kernel = {}
+    for k, (n_l, ms_l, by_l) in stats.items():
+        a = per_kernel.setdefault(k.split("/")[0], [0, 0.0, 0.0])
+        a[0] += n_l
+        a[1] += ms_l
+        a[2] += by_l
+    dom = max(per_kernel, key=lambda k: per_kernel[k][1])
+    launches, ms, by = per_kernel[dom]
     achieved = by / launches / (ms / launches * 1e-3) / 1e9
     cycle_bytes = sum(v[2] for v in stats.values()) / args.steps
     kernels = {k: {"launches": v[0], "ms_per_cycle": v[1] / args.steps,
                    "gbs": (v[2] / (v[1] * 1e-3) / 1e9 if v[1] > 0 else None)}
                for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
     traffic = MEASURED_TRAFFIC.get((case.name, args.precision, dom))
+    if traffic is not None:
+        traffic = dict(traffic, frac_of_algorithmic=traffic["bytes_per_launch"] / (by / launches))
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "bytes_per_launch": by / launches, "mean_launch_ms": ms / launches}
@@ -151,8 +166,19 @@ def main():
         "roofline": roofline,
         "cycle_algorithmic_gbs": cycle_bytes / (total_ms / args.steps * 1e-3) / 1e9,
         "kernel_ms_per_cycle": {k: v["ms_per_cycle"] for k, v in kernels.items()},
+        "kernel_us_per_launch": {k: 1e3 * v[1] / v[0] for k, v in
+                                 sorted(stats.items(), key=lambda kv: -kv[1][1])},
         "to_residual_1e-6": extra,
     }
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = n * 4
+        del src, dst
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_cycles)
     print(json.dumps(line), flush=True)

@@ -1043,9 +1043,9 @@ __device__ __forceinline__ T wall_ghost_j(const Geo& g, int j, T u, T v, int K_i
 // u_n <= 0), the per-velocity terms of the next wall densities
 template <typename T>
 __device__ __forceinline__ void wall_products(const Geo& g, const Vel& vel, int k, const T* Gk,
-                                              double* __restrict__ wbuf) {
+                                              double* __restrict__ wbuf, int tid, int nthr) {
     double u = vel.u[k], v = vel.v[k], w = vel.w[k];
-    for (int j = threadIdx.x; j < g.n_wall; j += blockDim.x) {
+    for (int j = tid; j < g.n_wall; j += nthr) {
         int s = g.w_side[j];
         double un = ((s & 1) ? 1.0 : -1.0) * (s < 2 ? u : v);
         wbuf[(size_t)j * vel.nk + k] = un > 0.0 ? w * un * double(Gk[g.w_cell[j]]) : 0.0;
@@ -1180,7 +1180,7 @@ __global__ void k_sweep_lds(Geo g, Vel vel, int K_int, const T* __restrict__ r, 
         int kq = it >> 1, part = it & 1;
         const T* src = tiles + (size_t)q * nc;
         bulk_copy<T>(df + ((size_t)part * vel.nk + kq) * nc, src, nc);
-        if (part == 0) wall_products<T>(g, vel, kq, src, wbuf);
+        if (part == 0) wall_products<T>(g, vel, kq, src, wbuf, threadIdx.x, blockDim.x);
     }
 }
 
@@ -1242,7 +1242,221 @@ __global__ void k_sweep(Geo g, Vel vel, int K_int, const T* __restrict__ r, T* _
         }
         __syncthreads();
     }
-    wall_products<T>(g, vel, k, G, wbuf);
+    wall_products<T>(g, vel, k, G, wbuf, threadIdx.x, blockDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Ordered sweep with one wavefront per group of velocities.
+//
+// In the upwind order of one velocity, row t (counted from the upwind
+// y-side) at anti-diagonal step s needs two results of step s - 1: its own
+// previous cell (x-upwind) and the cell of row t - 1 in the same column
+// (y-upwind).  With lane = row the second one is the previous result of the
+// neighbouring lane, so a one-lane rotation of the wavefront (DPP wave_ror:1)
+// carries it: no LDS exchange and no barrier per step.  Rows beyond 64 are
+// held as R row slots per lane (slot p = rows 64 p .. 64 p + 63; the row
+// below slot p of lane 0 is slot p - 1 of lane 63).  When ny <= 32,
+// I = 64 / ny velocities share a wavefront, lanes q ny .. q ny + ny - 1
+// holding velocity q; the rotation into the first row of a velocity is never
+// used, because that row's y-upwind side is a domain boundary.
+//
+// The r tiles (G and H) are staged in LDS by direct global-to-LDS loads and
+// overwritten in place by the correction.  The wall ghosts C_k drho_w are
+// constant during a sweep, so their upwind terms are added to the staged
+// r before the first step (x-sides, then y-sides: a cell has at most one
+// upwind side per direction).  Per-cell data shared by the wavefronts of a
+// block (1/tau + 1/dt_n, side types, 1/dx) is staged once per block, and
+// each lane loads the data of its next cell one step ahead.
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void gbl_void_t;
+
+// lane i takes the value of lane i - 1 (lane 0 that of lane 63)
+__device__ __forceinline__ float lane_rotate1(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x13C, 0xf, 0xf,
+                                                                 false));
+}
+__device__ __forceinline__ double lane_rotate1(double x) {
+    unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0x13C, 0xf, 0xf, false);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0x13C, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// 1 / x: the hardware reciprocal (1 ulp) in float, a correctly rounded
+// division in double
+__device__ __forceinline__ float sweep_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double sweep_rcp(double x) { return 1.0 / x; }
+
+// n elements from global memory into LDS by the 64 lanes of one wavefront:
+// 16-byte direct global-to-LDS loads when both ends are 16-byte aligned and
+// the size is a multiple of 16 bytes, element by element otherwise
+template <typename T>
+__device__ __forceinline__ void wave_load_lds(T* dst, const T* __restrict__ src, int n, int lane) {
+    size_t bytes = (size_t)n * sizeof(T);
+    if (((((size_t)dst) | ((size_t)src) | bytes) & 15) == 0) {
+        int nv = (int)(bytes >> 4);
+        for (int i = 0; i < nv; i += 64)
+            if (i + lane < nv)
+                __builtin_amdgcn_global_load_lds((gbl_void_t*)((const char*)src + ((size_t)(i + lane) << 4)),
+                                                 (lds_void_t*)((char*)dst + ((size_t)i << 4)), 16, 0, 0);
+    } else {
+        for (int i = lane; i < n; i += 64) dst[i] = src[i];
+    }
+}
+
+// n elements from LDS to global memory by one wavefront (16-byte stores when
+// aligned)
+template <typename T>
+__device__ __forceinline__ void wave_store(T* __restrict__ dst, const T* src, int n, int lane) {
+    size_t bytes = (size_t)n * sizeof(T);
+    if (((((size_t)dst) | ((size_t)src) | bytes) & 15) == 0) {
+        typedef __attribute__((ext_vector_type(4))) unsigned u4;
+        int nv = (int)(bytes >> 4);
+        const u4* s = (const u4*)src;
+        u4* d = (u4*)dst;
+        for (int i = lane; i < nv; i += 64) d[i] = s[i];
+    } else {
+        for (int i = lane; i < n; i += 64) dst[i] = src[i];
+    }
+}
+
+// LDS bytes of k_sweep_wave for W wavefronts of I velocities each
+template <typename T>
+size_t sweep_wave_lds_bytes(int nc, int nx, int W, int I) {
+    size_t b = ((size_t)W * 2 * I * nc + nc + nx) * sizeof(T) + (size_t)nc;
+    return (b + 15) & ~(size_t)15;
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, const T* __restrict__ r,
+                                                    T* __restrict__ df, const double* __restrict__ tau_inv,
+                                                    const double* __restrict__ dtn_inv,
+                                                    const unsigned char* __restrict__ stype,
+                                                    const double* __restrict__ drho, double* __restrict__ wbuf,
+                                                    int I) {
+    extern __shared__ double smem_d[];
+    const int nc = g.nc, nx = g.nx, ny = g.ny, nw = g.n_wall, nk = vel.nk;
+    const int W = blockDim.x >> 6, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    T* tiles = (T*)smem_d;                                  // [W][2][I][nc]
+    T* coef = tiles + (size_t)W * 2 * I * nc;               // [nc]  1/tau + 1/dt_n, -1 on solid cells
+    T* invdx = coef + nc;                                   // [nx]
+    unsigned char* st = (unsigned char*)(invdx + nx);       // [nc]  side types, 2 bits per side
+    const int k0 = (blockIdx.x * W + w) * I;                // first velocity of this wavefront
+    const int nq = max(0, min(I, nk - k0));                 // velocities it holds
+    T* tw = tiles + (size_t)w * 2 * I * nc;
+    if (nq > 0) {
+        wave_load_lds<T>(tw, r + (size_t)k0 * nc, nq * nc, lane);
+        wave_load_lds<T>(tw + (size_t)I * nc, r + ((size_t)nk + k0) * nc, nq * nc, lane);
+    }
+    for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+        coef[i] = g.solid[i] ? T(-1) : T(tau_inv[i] + dtn_inv[i]);
+        st[i] = stype[i];
+    }
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) invdx[i] = T(1.0 / g.dx[i]);
+    __syncthreads();
+    // upwind wall-ghost terms into r: x-sides first, then y-sides
+    for (int dir = 0; dir < 2; ++dir) {
+        for (int q = 0; q < nq; ++q) {
+            T u = vel_u<T>(vel, k0 + q), v = vel_v<T>(vel, k0 + q);
+            for (int j = lane; j < nw; j += 64) {
+                int sd = g.w_side[j];
+                if ((sd >> 1) != dir) continue;
+                T un = ((sd & 1) ? T(1) : T(-1)) * (dir == 0 ? u : v);
+                if (!(un < T(0))) continue;
+                int cell = g.w_cell[j];
+                T a = -un * T(1.0 / (dir == 0 ? g.dx[cell % nx] : g.dy[cell / nx]));
+                tw[(size_t)q * nc + cell] += a * wall_ghost_j<T>(g, j, u, v, K_int, 0, drho);
+                tw[((size_t)I + q) * nc + cell] += a * wall_ghost_j<T>(g, j, u, v, K_int, 1, drho);
+            }
+        }
+        __syncthreads();
+    }
+
+    const int q = I > 1 ? lane / ny : 0;
+    const bool live = q < nq;
+    const int qq = live ? q : 0;
+    const int t0 = I > 1 ? lane - q * ny : lane;
+    const int k = live ? k0 + q : 0;
+    const T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
+    const bool px = u >= T(0), py = v >= T(0);
+    const int shx = px ? 0 : 2, shy = py ? 4 : 6;           // bit offset of the upwind x / y side type
+    const T au = px ? u : -u, av = py ? v : -v;
+    T* tG = tw + (size_t)qq * nc;
+    T* tH = tw + ((size_t)I + qq) * nc;
+    int rowc[R];                                            // first cell of the slot's row
+    bool rowok[R];
+    T by[R], cG[R], cH[R];
+    T nf_cf[R], nf_idx[R], nf_rG[R], nf_rH[R];              // data of the slot's next cell
+    unsigned nf_sc[R];
+    auto fetch = [&](int p, int jx) {
+        int jc = jx < 0 ? 0 : (jx >= nx ? nx - 1 : jx);
+        int ix = px ? jc : nx - 1 - jc;
+        int c = rowc[p] + ix;
+        nf_cf[p] = coef[c];
+        nf_sc[p] = st[c];
+        nf_idx[p] = invdx[ix];
+        nf_rG[p] = tG[c];
+        nf_rH[p] = tH[c];
+    };
+#pragma unroll
+    for (int p = 0; p < R; ++p) {
+        int row = t0 + 64 * p;
+        rowok[p] = live && row < ny;
+        int iy = rowok[p] ? (py ? row : ny - 1 - row) : 0;
+        rowc[p] = iy * nx;
+        by[p] = rowok[p] ? av * T(1.0 / g.dy[iy]) : T(0);
+        cG[p] = T(0);
+        cH[p] = T(0);
+        fetch(p, -row);
+    }
+    const int nsteps = nx + ny - 1;
+    for (int s = 0; s < nsteps; ++s) {
+        T rotG[R], rotH[R];
+#pragma unroll
+        for (int p = 0; p < R; ++p) {
+            rotG[p] = lane_rotate1(cG[p]);
+            rotH[p] = lane_rotate1(cH[p]);
+        }
+#pragma unroll
+        for (int p = 0; p < R; ++p) {
+            int jx = s - (t0 + 64 * p);
+            bool valid = rowok[p] && (unsigned)jx < (unsigned)nx;
+            T cf = nf_cf[p], idx = nf_idx[p], rG = nf_rG[p], rH = nf_rH[p];
+            unsigned sc = nf_sc[p];
+            int c = rowc[p] + (px ? jx : nx - 1 - jx);
+            fetch(p, jx + 1);
+            T nbG = rotG[p], nbH = rotH[p];
+            if (R > 1 && lane == 0) {
+                nbG = p > 0 ? rotG[p > 0 ? p - 1 : 0] : T(0);
+                nbH = p > 0 ? rotH[p > 0 ? p - 1 : 0] : T(0);
+            }
+            unsigned tpx = (sc >> shx) & 3u, tpy = (sc >> shy) & 3u;
+            T bx = au * idx, byp = by[p];
+            // transport diagonal: every downwind side, and an upwind side
+            // only if it is an outflow (where the two cancel)
+            T D = cf + (tpx == 3u ? T(0) : bx) + (tpy == 3u ? T(0) : byp);
+            T inv = sweep_rcp(D);
+            T exG = tpx == 0u ? cG[p] : T(0), exH = tpx == 0u ? cH[p] : T(0);
+            T eyG = tpy == 0u ? nbG : T(0), eyH = tpy == 0u ? nbH : T(0);
+            T vG = (rG + bx * exG + byp * eyG) * inv;
+            T vH = (rH + bx * exH + byp * eyH) * inv;
+            vG = cf < T(0) ? T(0) : vG;
+            vH = cf < T(0) ? T(0) : vH;
+            if (valid) {
+                tG[c] = vG;
+                tH[c] = vH;
+            }
+            cG[p] = vG;
+            cH[p] = vH;
+        }
+    }
+    __syncthreads();
+    if (nq > 0) {
+        wave_store<T>(df + (size_t)k0 * nc, tw, nq * nc, lane);
+        wave_store<T>(df + ((size_t)nk + k0) * nc, tw + (size_t)I * nc, nq * nc, lane);
+        for (int qv = 0; qv < nq; ++qv) wall_products<T>(g, vel, k0 + qv, tw + (size_t)qv * nc, wbuf, lane, 64);
+    }
 }
 
 // drho_w = -sum_k wbuf[j][k] / den_j: one wavefront per wall side

@@ -69,6 +69,14 @@ struct miugks_ctx {
     std::vector<unsigned*> flags;
     std::vector<double*> wbuf;
     std::vector<char> sweep_lds;
+    // wavefront sweep (k_sweep_wave): side types and launch shape per level
+    // (W = 0: not used on that level)
+    struct WaveCfg {
+        int W = 0, I = 1, R = 1, blocks = 0;
+        size_t lds = 0;
+    };
+    std::vector<unsigned char*> stype;
+    std::vector<WaveCfg> wave;
     // graphs of Step 1 and Steps 2-7; pseudo-step factor a^{-n}
     bool use_graphs = true;
     bool own_stream = false;
@@ -217,6 +225,26 @@ size_t sweep_lds_bytes(const Geo& g, int P) {
     return (b + 15) & ~(size_t)15;
 }
 
+hipError_t set_wave_lds(int prec, int R, int bytes) {
+    auto set = [bytes](const void* f) {
+        return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    };
+    if (prec == MIUGKS_FP64) {
+        switch (R) {
+            case 1: return set((const void*)k_sweep_wave<double, 1>);
+            case 2: return set((const void*)k_sweep_wave<double, 2>);
+            case 3: return set((const void*)k_sweep_wave<double, 3>);
+            default: return set((const void*)k_sweep_wave<double, 4>);
+        }
+    }
+    switch (R) {
+        case 1: return set((const void*)k_sweep_wave<float, 1>);
+        case 2: return set((const void*)k_sweep_wave<float, 2>);
+        case 3: return set((const void*)k_sweep_wave<float, 3>);
+        default: return set((const void*)k_sweep_wave<float, 4>);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // the hot path, per precision
 
@@ -280,8 +308,23 @@ struct Path {
         if (!drho_current && g.n_wall)
             LAUNCH(c, "drho", (double)g.n_wall * c->nk * 8, k_drho, dim3((g.n_wall + 3) / 4), dim3(256), g, c->nk,
                    c->wbuf[l], c->drho[l]);
-        const char* name = l == 0 ? "sweep_fine" : "sweep_coarse";
-        if (c->sweep_lds[l]) {
+        static const char* const names[] = {"sweep/l0", "sweep/l1", "sweep/l2", "sweep/l3",
+                                            "sweep/l4", "sweep/l5", "sweep/l6", "sweep/l7"};
+        const char* name = names[l < 8 ? l : 7];
+        const miugks_ctx::WaveCfg& wc = c->wave[l];
+        if (wc.W) {
+#define MIUGKS_WAVE_LAUNCH(RR)                                                                                 \
+    LAUNCH_SH(c, name, 2 * arr(c, l), wc.lds, (k_sweep_wave<T, RR>), dim3(wc.blocks), dim3(64 * wc.W), g, c->vel, \
+              c->gas.K_int, (const T*)c->r[l], (T*)c->df[l], c->tau_inv[l], c->dtn_inv[l], c->stype[l],          \
+              c->drho[l], c->wbuf[l], wc.I)
+            switch (wc.R) {
+                case 1: MIUGKS_WAVE_LAUNCH(1); break;
+                case 2: MIUGKS_WAVE_LAUNCH(2); break;
+                case 3: MIUGKS_WAVE_LAUNCH(3); break;
+                default: MIUGKS_WAVE_LAUNCH(4); break;
+            }
+#undef MIUGKS_WAVE_LAUNCH
+        } else if (c->sweep_lds[l]) {
             int npad = ((g.ny + 63) / 64) * 64, P = c->sweep_lds[l];
             int blocks = (2 * c->nk + P - 1) / P;
             LAUNCH_SH(c, name, 2 * arr(c, l), sweep_lds_bytes<T>(g, P), k_sweep_lds<T>, dim3(blocks), dim3(P * npad),
@@ -580,7 +623,9 @@ int build_device(miugks_ctx* ctx) {
     ctx->flags.resize(ctx->L);
     ctx->wbuf.resize(ctx->L);
     ctx->sweep_lds.assign(ctx->L, 0);
-    size_t need_max = 0;
+    ctx->stype.assign(ctx->L, nullptr);
+    ctx->wave.assign(ctx->L, miugks_ctx::WaveCfg());
+    size_t need_max = 0, wave_need_max = 0;
     for (int l = 0; l < ctx->L; ++l) {
         HostLevel& h = ctx->hl[l];
         std::vector<unsigned> fl(h.nc, 0);
@@ -607,6 +652,13 @@ int build_device(miugks_ctx* ctx) {
         unsigned* p;
         if ((rc = upload(ctx, &p, fl))) return rc;
         ctx->flags[l] = p;
+        {
+            std::vector<unsigned char> st(h.nc);
+            for (int c = 0; c < h.nc; ++c) st[c] = (unsigned char)(fl[c] & 0xffu);
+            unsigned char* sp;
+            if ((rc = upload(ctx, &sp, st))) return rc;
+            ctx->stype[l] = sp;
+        }
         void* wb;
         if ((rc = dev_alloc(ctx, &wb, std::max<size_t>(1, h.w_cell.size()) * ctx->nk * sizeof(double)))) return rc;
         ctx->wbuf[l] = (double*)wb;
@@ -630,6 +682,43 @@ int build_device(miugks_ctx* ctx) {
                                                     : sweep_lds_bytes<float>(ctx->geo[l], best);
             need_max = std::max(need_max, need);
         }
+        // wavefront sweep: W wavefronts of I velocities per block, W taken
+        // for the fewest rounds of blocks over the chip (ties: smaller W)
+        if (!getenv("MIUGKS_NO_WAVE_SWEEP") && h.ny <= 256) {
+            miugks_ctx::WaveCfg wc;
+            wc.I = h.ny <= 32 ? 64 / h.ny : 1;
+            wc.R = (h.ny + 63) / 64;
+            int nwaves = (ctx->nk + wc.I - 1) / wc.I;
+            long best_rounds = 0;
+            int force_w = getenv("MIUGKS_WAVE_W") ? atoi(getenv("MIUGKS_WAVE_W")) : 0;
+            for (int W : {1, 2, 4}) {
+                if (force_w && W != force_w) continue;
+                size_t need = ctx->prec == MIUGKS_FP64
+                                  ? sweep_wave_lds_bytes<double>(h.nc, h.nx, W, wc.I)
+                                  : sweep_wave_lds_bytes<float>(h.nc, h.nx, W, wc.I);
+                if (need > (size_t)max_lds) continue;
+                long per_cu = std::min<long>((long)max_lds / (long)need, 8);
+                long cap = (long)cus * per_cu * W;
+                long rounds = (nwaves + cap - 1) / cap;
+                if (!wc.W || rounds < best_rounds) {
+                    wc.W = W;
+                    wc.lds = need;
+                    best_rounds = rounds;
+                }
+            }
+            if (wc.W) {
+                wc.blocks = (nwaves + wc.W - 1) / wc.W;
+                ctx->wave[l] = wc;
+                wave_need_max = std::max(wave_need_max, wc.lds);
+            }
+        }
+    }
+    if (wave_need_max > 65536) {
+        hipError_t e = hipSuccess;
+        for (int R = 1; R <= 4 && e == hipSuccess; ++R) e = set_wave_lds(ctx->prec, R, (int)wave_need_max);
+        if (e != hipSuccess)
+            for (int l = 0; l < ctx->L; ++l)
+                if (ctx->wave[l].lds > 65536) ctx->wave[l].W = 0;
     }
     if (need_max > 65536) {
         hipError_t e = ctx->prec == MIUGKS_FP64
@@ -646,9 +735,13 @@ int build_device(miugks_ctx* ctx) {
     }
     if (getenv("MIUGKS_DEBUG"))
         for (int l = 0; l < ctx->L; ++l)
-            fprintf(stderr, "[miugks] level %d: %dx%d cells, %d wall sides, sweep in %s, %d pipelines/block\n", l,
-                    ctx->hl[l].nx, ctx->hl[l].ny, (int)ctx->hl[l].w_cell.size(),
-                    ctx->sweep_lds[l] ? "LDS" : "global memory", (int)ctx->sweep_lds[l]);
+            fprintf(stderr,
+                    "[miugks] level %d: %dx%d cells, %d wall sides, sweep: %s (wavefronts/block %d, velocities/"
+                    "wavefront %d, rows/lane %d, blocks %d, LDS %zu; pipelines/block %d)\n",
+                    l, ctx->hl[l].nx, ctx->hl[l].ny, (int)ctx->hl[l].w_cell.size(),
+                    ctx->wave[l].W ? "wavefront" : (ctx->sweep_lds[l] ? "LDS pipelines" : "global memory"),
+                    ctx->wave[l].W, ctx->wave[l].I, ctx->wave[l].R, ctx->wave[l].blocks, ctx->wave[l].lds,
+                    (int)ctx->sweep_lds[l]);
     {
         void* df;
         if ((rc = dev_alloc(ctx, &df, sizeof(double)))) return rc;
