@@ -289,6 +289,46 @@ __global__ void k_moments_finalize(Geo g, const double* __restrict__ part, int n
     q[g.nc + c] = q2[1];
 }
 
+// W, q of every cell from the summed raw moments Msum[m nc + c] (zero on
+// solid cells); one thread per cell
+__global__ void k_moments_records(Geo g, const double* __restrict__ Msum, double* __restrict__ W,
+                                  double* __restrict__ q) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.nc) return;
+    if (g.solid[c]) {
+        for (int m = 0; m < 4; ++m) W[m * g.nc + c] = 0.0;
+        q[c] = q[g.nc + c] = 0.0;
+        return;
+    }
+    double M[NRAW];
+    for (int m = 0; m < NRAW; ++m) M[m] = Msum[(size_t)m * g.nc + c];
+    double w4[4], q2[2];
+    raw_to_macro(M, w4, q2);
+    for (int m = 0; m < 4; ++m) W[m * g.nc + c] = w4[m];
+    q[c] = q2[0];
+    q[g.nc + c] = q2[1];
+}
+
+// diffuse-wall density from zero mass flux, out[j] = -sum_{u_n>0} w u_n G / den_j
+// (Sec. III B), one wavefront per wall side summing over all velocities in
+// lane order; G is the first (G) plane of f or of a correction
+template <typename T>
+__global__ void k_wall_density(Geo g, Vel vel, const T* __restrict__ G, double* __restrict__ out) {
+    int j = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    int lane = threadIdx.x & 63;
+    double s = 0.0;
+    if (j < g.n_wall) {
+        int c = g.w_cell[j], sd = g.w_side[j];
+        double sign = (sd & 1) ? 1.0 : -1.0;
+        for (int k = lane; k < vel.nk; k += 64) {
+            double un = sign * (sd < 2 ? vel.u[k] : vel.v[k]);
+            if (un > 0) s += vel.w[k] * un * double(G[(size_t)k * g.nc + c]);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0 && j < g.n_wall) out[j] = -s / g.w_den[j];
+}
+
 // total mass sum_c V_c rho_c over fluid cells (one block)
 __global__ void k_mass(Geo g, const double* __restrict__ W, double* __restrict__ out) {
     __shared__ double sh[1024];
@@ -321,6 +361,92 @@ __global__ void k_scale_d(double* __restrict__ a, size_t n, const double* __rest
 // ---------------------------------------------------------------------------
 // Step 1, interface reconstruction (Sec. II A 1; UGKS flux).  Every interior
 // face is the -x or -y face of exactly one cell R with neighbour L across it.
+
+// 1/x from the hardware reciprocal refined by Newton steps (two in double,
+// one in float): the van Leer limiter below divides once per call
+__device__ __forceinline__ double rcp_refined(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_refined(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+template <typename T> __device__ __forceinline__ T van_leer_fast(T a, T b) {
+    T s = a * b;
+    return s > T(0) ? T(2) * s * rcp_refined(a + b) : T(0);
+}
+
+// Geometry of the face on side 2d of cell c (the cell R = c, neighbour L
+// across it), independent of the velocity
+template <typename A>
+struct FaceGeom {
+    int L, LL, RR;        // neighbour across the face, L's neighbour beyond it, c's neighbour beyond (<0: none)
+    A idc, idcL, idcR;    // inverse centre distances L-c, LL-L, c-RR
+    A dL, dR;             // half widths of L and c normal to the face
+};
+
+template <typename A>
+__device__ __forceinline__ bool face_geom(const Geo& g, int c, int d, FaceGeom<A>& fg) {
+    int nc = g.nc;
+    fg.L = g.nb[(2 * d) * nc + c];
+    if (fg.L < 0) return false;
+    fg.LL = g.nb[(2 * d) * nc + fg.L];
+    fg.RR = g.nb[(2 * d + 1) * nc + c];
+    fg.idc = A(1.0 / g.dcent[(2 * d) * nc + c]);
+    fg.idcL = fg.LL >= 0 ? A(1.0 / g.dcent[(2 * d) * nc + fg.L]) : A(0);
+    fg.idcR = fg.RR >= 0 ? A(1.0 / g.dcent[(2 * d + 1) * nc + c]) : A(0);
+    fg.dL = A(0.5) * A(d == 0 ? g.dx[fg.L % g.nx] : g.dy[fg.L / g.nx]);
+    fg.dR = A(0.5) * A(d == 0 ? g.dx[c % g.nx] : g.dy[c / g.nx]);
+    return true;
+}
+
+// limited slopes and upwind interface values of one velocity (row offset kc
+// into the G plane, ho = offset of the H plane) at an interior face
+template <typename T, typename A>
+__device__ __forceinline__ void face_upwind_k(const FaceGeom<A>& fg, int c, const T* __restrict__ F, size_t ho,
+                                              size_t kc, A un, A& Gup, A& Hup, A& sGup, A& sHup) {
+    A GL = A(F[kc + fg.L]), GR = A(F[kc + c]), HL = A(F[ho + kc + fg.L]), HR = A(F[ho + kc + c]);
+    A gLR = (GR - GL) * fg.idc, hLR = (HR - HL) * fg.idc;
+    A sGL = 0, sHL = 0, sGR = 0, sHR = 0;
+    if (un >= A(0)) {   // left slope needed (and both for un == 0)
+        A gm = 0, hm = 0;
+        if (fg.LL >= 0) {
+            gm = (GL - A(F[kc + fg.LL])) * fg.idcL;
+            hm = (HL - A(F[ho + kc + fg.LL])) * fg.idcL;
+        }
+        sGL = van_leer_fast(gm, gLR);
+        sHL = van_leer_fast(hm, hLR);
+    }
+    if (un <= A(0)) {
+        A gp = 0, hp = 0;
+        if (fg.RR >= 0) {
+            gp = (A(F[kc + fg.RR]) - GR) * fg.idcR;
+            hp = (A(F[ho + kc + fg.RR]) - HR) * fg.idcR;
+        }
+        sGR = van_leer_fast(gLR, gp);
+        sHR = van_leer_fast(hLR, hp);
+    }
+    if (un > A(0)) {
+        Gup = GL + sGL * fg.dL;
+        Hup = HL + sHL * fg.dL;
+        sGup = sGL;
+        sHup = sHL;
+    } else if (un < A(0)) {
+        Gup = GR - sGR * fg.dR;
+        Hup = HR - sHR * fg.dR;
+        sGup = sGR;
+        sHup = sHR;
+    } else {
+        Gup = A(0.5) * (GL + sGL * fg.dL + GR - sGR * fg.dR);
+        Hup = A(0.5) * (HL + sHL * fg.dL + HR - sHR * fg.dR);
+        sGup = A(0.5) * (sGL + sGR);
+        sHup = A(0.5) * (sHL + sHR);
+    }
+}
 
 // limited slopes of the two cells of the face on side (2d) of cell c, and the
 // upwind interface values for one velocity.  Returns false if not interior.
@@ -389,13 +515,15 @@ __global__ void __launch_bounds__(256) k_face_moments_partial(Geo g, Vel vel, co
     double a[2 * NRAW];
     for (int m = 0; m < 2 * NRAW; ++m) a[m] = 0.0;
     if (ch.valid && !g.solid[ch.c]) {
-        for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
-            double u = vel.u[k], v = vel.v[k];
-            double w = vel.w[k];
-            for (int d = 0; d < 2; ++d) {
+        const size_t ho = (size_t)vel.nk * g.nc;
+        for (int d = 0; d < 2; ++d) {
+            FaceGeom<double> fg;
+            if (!face_geom<double>(g, ch.c, d, fg)) continue;
+            for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
+                double u = vel.u[k], v = vel.v[k], w = vel.w[k];
                 double Gup, Hup, sG, sH;
-                if (face_upwind<T, double>(g, ch.c, d, f, vel.nk, k, d == 0 ? u : v, Gup, Hup, sG, sH))
-                    raw_accumulate(a + d * NRAW, w, u, v, Gup, Hup);
+                face_upwind_k<T, double>(fg, ch.c, f, ho, (size_t)k * g.nc, d == 0 ? u : v, Gup, Hup, sG, sH);
+                raw_accumulate(a + d * NRAW, w, u, v, Gup, Hup);
             }
         }
     }
@@ -511,6 +639,48 @@ __device__ __forceinline__ void face_record(const Geo& g, const Gas& gas, const 
                         0, 0, 0, 0,
                         q[0] / dt, q[1] / dt, q[2] / dt, q[3] / dt, q[4] / dt, 1.0};
     for (int m = 0; m < NFP; ++m) rec[m * stride] = vals[m];
+}
+
+// out[m n + i] = scale * sum_j part[(j M + m) n + i] over the nkc chunks in
+// chunk order (zero where mask[i] is set); one thread per (m, i)
+__global__ void k_chunk_sum(const double* __restrict__ part, int nkc, int M, int n, double scale,
+                            const unsigned char* __restrict__ mask, double* __restrict__ out) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= M * n) return;
+    int m = t / n, i = t - m * n;
+    double s = 0.0;
+#pragma unroll 5
+    for (int j = 0; j < nkc; ++j) s += part[((size_t)j * M + m) * n + i];
+    out[t] = (mask && mask[i]) ? 0.0 : scale * s;
+}
+
+// Step 1: interface records of every face from the summed raw moments
+// Msum[(d NRAW + m) nc + c]; one thread per (face direction, cell)
+__global__ void k_face_records(Geo g, Gas gas, const double* __restrict__ Msum, const double* __restrict__ W,
+                               double* __restrict__ fp) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * g.nc) return;
+    int d = t / g.nc, c = t - d * g.nc;
+    double M[NRAW];
+    for (int m = 0; m < NRAW; ++m) M[m] = Msum[((size_t)d * NRAW + m) * g.nc + c];
+    face_record(g, gas, M, d, c, W, fp);
+}
+
+// Step 1: time slope Abar of every face from the summed compatibility sums
+// Ssum[(4 d + m) nc + c]; one thread per (face direction, cell)
+__global__ void k_face_timeslope_records(Geo g, Gas gas, const double* __restrict__ Ssum,
+                                         double* __restrict__ fp) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * g.nc) return;
+    int d = t / g.nc, c = t - d * g.nc;
+    size_t stride = 2 * (size_t)g.nc;
+    double* rec = fp + (size_t)d * g.nc + c;
+    if (rec[23 * stride] == 0.0) return;
+    double rho = rec[0], U = rec[stride], V = rec[2 * stride], lam = rec[3 * stride];
+    double b[4], A[4];
+    for (int m = 0; m < 4; ++m) b[m] = -Ssum[((size_t)4 * d + m) * g.nc + c] / rho;
+    micro_slope(b, U, V, lam, gas.K, A);
+    for (int m = 0; m < 4; ++m) rec[(14 + m) * stride] = A[m];
 }
 
 // Step 1, first part: raw moments of the upwind interface distribution of
@@ -804,12 +974,14 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
                     size_t stride = 2 * nc;
                     A P[23];
                     for (int m = 0; m < 23; ++m) P[m] = A(rec[m * stride]);
+                    FaceGeom<A> fg;
+                    face_geom<A>(g, R, d, fg);
                     for (int j = 0; j < nmine; ++j) {
                         int k = kk[j];
                         A u = vel.u[k], v = vel.v[k];
                         A un = d == 0 ? u : v;
                         A Gup, Hup, sGu, sHu, PG, PH;
-                        face_upwind<T, A>(g, R, d, f, nk, k, un, Gup, Hup, sGu, sHu);
+                        face_upwind_k<T, A>(fg, R, f, ho, (size_t)k * nc, un, Gup, Hup, sGu, sHu);
                         face_flux<A>(P, u, v, un, Gup, Hup, sGu, sHu, gas.K_int, PG, PH);
                         dG[j] += sign * sv * PG;
                         dH[j] += sign * sv * PH;
@@ -1328,10 +1500,12 @@ size_t sweep_wave_lds_bytes(int nc, int nx, int W, int I) {
     return (b + 15) & ~(size_t)15;
 }
 
+// coef = 1/tau + 1/dt_n per cell (-1 on solid cells) in the sweep's type;
+// drho != nullptr: wall densities of the correction before the sweep
+// (nullptr: the correction starts from zero, no ghost terms)
 template <typename T, int R>
 __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, const T* __restrict__ r,
-                                                    T* __restrict__ df, const double* __restrict__ tau_inv,
-                                                    const double* __restrict__ dtn_inv,
+                                                    T* __restrict__ df, const T* __restrict__ coef_g,
                                                     const unsigned char* __restrict__ stype,
                                                     const double* __restrict__ drho, double* __restrict__ wbuf,
                                                     int I) {
@@ -1339,46 +1513,63 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
     const int nc = g.nc, nx = g.nx, ny = g.ny, nw = g.n_wall, nk = vel.nk;
     const int W = blockDim.x >> 6, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     T* tiles = (T*)smem_d;                                  // [W][2][I][nc]
-    T* coef = tiles + (size_t)W * 2 * I * nc;               // [nc]  1/tau + 1/dt_n, -1 on solid cells
+    T* coef = tiles + (size_t)W * 2 * I * nc;               // [nc]
     T* invdx = coef + nc;                                   // [nx]
     unsigned char* st = (unsigned char*)(invdx + nx);       // [nc]  side types, 2 bits per side
     const int k0 = (blockIdx.x * W + w) * I;                // first velocity of this wavefront
     const int nq = max(0, min(I, nk - k0));                 // velocities it holds
     T* tw = tiles + (size_t)w * 2 * I * nc;
+    // every load of the prologue is issued before the first wait
     if (nq > 0) {
         wave_load_lds<T>(tw, r + (size_t)k0 * nc, nq * nc, lane);
         wave_load_lds<T>(tw + (size_t)I * nc, r + ((size_t)nk + k0) * nc, nq * nc, lane);
     }
-    for (int i = threadIdx.x; i < nc; i += blockDim.x) {
-        coef[i] = g.solid[i] ? T(-1) : T(tau_inv[i] + dtn_inv[i]);
-        st[i] = stype[i];
-    }
+    if (w == 0) wave_load_lds<T>(coef, coef_g, nc, lane);
+    if (w == W - 1) wave_load_lds<unsigned char>(st, stype, nc, lane);
     for (int i = threadIdx.x; i < nx; i += blockDim.x) invdx[i] = T(1.0 / g.dx[i]);
+    // velocities of this wavefront: lane q < nq holds velocity k0 + q
+    const T uq_l = lane < nq ? vel_u<T>(vel, k0 + lane) : T(0);
+    const T vq_l = lane < nq ? vel_v<T>(vel, k0 + lane) : T(0);
     __syncthreads();
-    // upwind wall-ghost terms into r: x-sides first, then y-sides
-    for (int dir = 0; dir < 2; ++dir) {
-        for (int q = 0; q < nq; ++q) {
-            T u = vel_u<T>(vel, k0 + q), v = vel_v<T>(vel, k0 + q);
-            for (int j = lane; j < nw; j += 64) {
-                int sd = g.w_side[j];
-                if ((sd >> 1) != dir) continue;
-                T un = ((sd & 1) ? T(1) : T(-1)) * (dir == 0 ? u : v);
-                if (!(un < T(0))) continue;
-                int cell = g.w_cell[j];
-                T a = -un * T(1.0 / (dir == 0 ? g.dx[cell % nx] : g.dy[cell / nx]));
-                tw[(size_t)q * nc + cell] += a * wall_ghost_j<T>(g, j, u, v, K_int, 0, drho);
-                tw[((size_t)I + q) * nc + cell] += a * wall_ghost_j<T>(g, j, u, v, K_int, 1, drho);
+    // upwind wall-ghost terms into r (x-sides, then y-sides); wall data is
+    // loaded once per 64 wall sides
+    if (drho) {
+        for (int jb = 0; jb < nw; jb += 64) {
+            const int j = jb + lane;
+            const bool ok = j < nw;
+            int sd = 0, cell = 0;
+            T invd = T(0), lam = T(1), wu = T(0), wv = T(0), dr = T(0);
+            if (ok) {
+                sd = g.w_side[j];
+                cell = g.w_cell[j];
+                invd = T(1.0 / (sd < 2 ? g.dx[cell % nx] : g.dy[cell / nx]));
+                lam = T(1.0 / g.w_T[j]);
+                wu = T(g.w_U[j]);
+                wv = T(g.w_V[j]);
+                dr = T(drho[j]);
+            }
+            for (int dir = 0; dir < 2; ++dir) {
+                for (int q = 0; q < nq; ++q) {
+                    const T u = __shfl(uq_l, q, 64), v = __shfl(vq_l, q, 64);
+                    const T un = ((sd & 1) ? T(1) : T(-1)) * (sd < 2 ? u : v);
+                    if (ok && (sd >> 1) == dir && un < T(0)) {
+                        T du = u - wu, dv = v - wv;
+                        T C = lam / T(M_PI) * dexp(-lam * (du * du + dv * dv));
+                        T a = -un * invd;
+                        tw[(size_t)q * nc + cell] += a * (C * dr);
+                        tw[((size_t)I + q) * nc + cell] += a * (C * T(K_int) / (T(2) * lam) * dr);
+                    }
+                }
+                __syncthreads();
             }
         }
-        __syncthreads();
     }
 
     const int q = I > 1 ? lane / ny : 0;
     const bool live = q < nq;
     const int qq = live ? q : 0;
     const int t0 = I > 1 ? lane - q * ny : lane;
-    const int k = live ? k0 + q : 0;
-    const T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
+    const T u = __shfl(uq_l, qq, 64), v = __shfl(vq_l, qq, 64);
     const bool px = u >= T(0), py = v >= T(0);
     const int shx = px ? 0 : 2, shy = py ? 4 : 6;           // bit offset of the upwind x / y side type
     const T au = px ? u : -u, av = py ? v : -v;
@@ -1455,7 +1646,21 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
     if (nq > 0) {
         wave_store<T>(df + (size_t)k0 * nc, tw, nq * nc, lane);
         wave_store<T>(df + ((size_t)nk + k0) * nc, tw + (size_t)I * nc, nq * nc, lane);
-        for (int qv = 0; qv < nq; ++qv) wall_products<T>(g, vel, k0 + qv, tw + (size_t)qv * nc, wbuf, lane, 64);
+        // w_k u_n dG_k at every wall side (zero for u_n <= 0): the
+        // per-velocity terms of the next wall densities
+        const double ud = lane < nq ? vel.u[k0 + lane] : 0.0, vd = lane < nq ? vel.v[k0 + lane] : 0.0,
+                     wd = lane < nq ? vel.w[k0 + lane] : 0.0;
+        for (int jb = 0; jb < nw; jb += 64) {
+            const int j = jb + lane;
+            const bool ok = j < nw;
+            const int sd = ok ? g.w_side[j] : 0, cell = ok ? g.w_cell[j] : 0;
+            for (int qv = 0; qv < nq; ++qv) {
+                double uu = __shfl(ud, qv, 64), vv = __shfl(vd, qv, 64), ww = __shfl(wd, qv, 64);
+                double un = ((sd & 1) ? 1.0 : -1.0) * (sd < 2 ? uu : vv);
+                if (ok)
+                    wbuf[(size_t)j * nk + k0 + qv] = un > 0.0 ? ww * un * double(tw[(size_t)qv * nc + cell]) : 0.0;
+            }
+        }
     }
 }
 
@@ -1509,6 +1714,72 @@ __global__ void __launch_bounds__(256) k_defect_restrict(Geo g, Geo gc, Vel vel,
         size_t o = (size_t)k * ncc + C;
         rc[o] = vol > 0 ? T(sG / vol) : T(0);
         rc[hoc + o] = vol > 0 ? T(sH / vol) : T(0);
+    }
+}
+
+// drho_w = -sum_k wbuf[j][k] / den_j as k_drho, also keeping the change from
+// the densities the last sweep used (old_zero: that sweep used zero)
+__global__ void k_drho_delta(Geo g, int nk, const double* __restrict__ wbuf, double* __restrict__ drho,
+                             double* __restrict__ ddrho, int old_zero) {
+    int j = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    int lane = threadIdx.x & 63;
+    double s = 0.0;
+    if (j < g.n_wall)
+        for (int k = lane; k < nk; k += 64) s += wbuf[(size_t)j * nk + k];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0 && j < g.n_wall) {
+        double d = -s / g.w_den[j];
+        ddrho[j] = d - (old_zero ? 0.0 : drho[j]);
+        drho[j] = d;
+    }
+}
+
+// Restricted defect after a complete ordered sweep.  The sweep solves every
+// cell's equation exactly with the wall densities it used, so r - A df
+// vanishes except at cells with an upwind wall side, where it is that side's
+// ghost term times the change of the wall density (ddrho).  cw[C] holds the
+// two ranges of the fine wall list that belong to the children of coarse
+// cell C (rows 2J and 2J+1), civol[C] the inverse fluid volume of C.
+template <typename T>
+__global__ void __launch_bounds__(256) k_defect_walls(Geo g, Geo gc, Vel vel, int K_int,
+                                                      const int4* __restrict__ cw,
+                                                      const double* __restrict__ civol,
+                                                      const double* __restrict__ ddrho, T* __restrict__ rc) {
+    Chunk ch = chunk_of(gc.nc, vel.nk);
+    if (!ch.valid) return;
+    const int C = ch.c;
+    const size_t ncc = gc.nc, hoc = (size_t)vel.nk * ncc;
+    const int4 rg = cw[C];
+    if (rg.x == rg.y && rg.z == rg.w) {
+        for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
+            rc[(size_t)k * ncc + C] = T(0);
+            rc[hoc + (size_t)k * ncc + C] = T(0);
+        }
+        return;
+    }
+    const double iv = civol[C];
+    for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
+        double u = vel.u[k], v = vel.v[k];
+        double sG = 0.0, sH = 0.0;
+        for (int part = 0; part < 2; ++part) {
+            int j0 = part ? rg.z : rg.x, j1 = part ? rg.w : rg.y;
+            for (int j = j0; j < j1; ++j) {
+                int sd = g.w_side[j], cell = g.w_cell[j];
+                double un = ((sd & 1) ? 1.0 : -1.0) * (sd < 2 ? u : v);
+                if (!(un < 0.0)) continue;
+                double dx = g.dx[cell % g.nx], dy = g.dy[cell / g.nx];
+                double a = -un / (sd < 2 ? dx : dy);
+                // ghost terms in the sweep's type, as the sweep added them
+                T lam = T(1.0 / g.w_T[j]);
+                T du = T(u) - T(g.w_U[j]), dv = T(v) - T(g.w_V[j]);
+                T Ck = lam / T(M_PI) * dexp(-lam * (du * du + dv * dv));
+                double e = a * double(Ck) * ddrho[j] * dx * dy;
+                sG += e;
+                sH += e * double(T(K_int) / (T(2) * lam));
+            }
+        }
+        rc[(size_t)k * ncc + C] = T(sG * iv);
+        rc[hoc + (size_t)k * ncc + C] = T(sH * iv);
     }
 }
 
@@ -1856,6 +2127,23 @@ __global__ void k_copy2(const double* __restrict__ a, double* __restrict__ a1, d
         if (a2) a2[i] = x;
         if (b) b1[i] = b[i];
     }
+}
+
+// 1/tau + 1/dt_n of every level in the sweep's type (-1 on solid cells),
+// one launch for all levels (threads over the cells of the finest level)
+struct CoefSet {
+    int L;
+    int nc[FAS_MAXL];
+    const unsigned char* solid[FAS_MAXL];
+    const double *tau[FAS_MAXL], *dtn[FAS_MAXL];
+    void* out[FAS_MAXL];
+};
+
+template <typename T>
+__global__ void k_sweep_coef(CoefSet S) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int l = 0; l < S.L; ++l)
+        if (i < S.nc[l]) ((T*)S.out[l])[i] = S.solid[l][i] ? T(-1) : T(S.tau[l][i] + S.dtn[l][i]);
 }
 
 }  // namespace miugks

@@ -54,7 +54,7 @@ struct miugks_ctx {
     // level 0
     void *f = nullptr, *div = nullptr, *finf = nullptr;
     double *W = nullptr, *q = nullptr, *R = nullptr, *Wt = nullptr, *fp = nullptr, *cp = nullptr;
-    double *part = nullptr, *norms = nullptr, *rho_w = nullptr, *mass = nullptr;
+    double *part = nullptr, *norms = nullptr, *rho_w = nullptr, *mass = nullptr, *msum = nullptr;
     size_t part_bytes = 0;
     // per level
     std::vector<void*> r, df;
@@ -76,6 +76,14 @@ struct miugks_ctx {
         size_t lds = 0;
     };
     std::vector<unsigned char*> stype;
+    std::vector<void*> coefT;   // 1/tau + 1/dt_n per level in the distribution's type
+    // restricted defect after an ordered sweep: per coarse cell the ranges of
+    // the fine wall list under it and its inverse fluid volume; the change of
+    // the wall densities since the last sweep
+    std::vector<int4*> cwall;
+    std::vector<double*> civol, ddrho;
+    std::vector<char> last_from_zero;
+    CoefSet coefset{};
     std::vector<WaveCfg> wave;
     // graphs of Step 1 and Steps 2-7; pseudo-step factor a^{-n}
     bool use_graphs = true;
@@ -257,18 +265,21 @@ struct Path {
     // Step 7: W, q of f (optionally after f += df, Step 6)
     static void moments(miugks_ctx* c, const T* df) {
         const Geo& g = c->geo[0];
-        LAUNCH(c, df ? "update_moments" : "moments", (df ? 3 : 1) * arr(c, 0) + 6.0 * g.nc * 8, k_moments_full<T>,
-               dim3(ntiles(g.nc)), dim3(64 * FW), g, c->vel, F(c), df, c->W, c->q);
+        int nkc = nchunks(c->nk);
+        double nc8 = g.nc * 8.0;
+        LAUNCH(c, df ? "update_moments" : "moments", (df ? 3 : 1) * arr(c, 0) + NRAW * nkc * nc8,
+               k_moments_partial<T>, dim3(ntiles(g.nc), nkc), dim3(256), g, c->vel, F(c), df, c->part);
+        LAUNCH(c, "chunk_sum", NRAW * (nkc + 1.0) * nc8, k_chunk_sum, dim3(nblk(NRAW * g.nc)), dim3(256),
+               (const double*)c->part, nkc, NRAW, g.nc, 1.0, (const unsigned char*)nullptr, c->msum);
+        LAUNCH(c, "moments_records", (NRAW + 6.0) * nc8, k_moments_records, dim3(nblk(g.nc)), dim3(256), g,
+               (const double*)c->msum, c->W, c->q);
     }
 
     static void wall_sums(miugks_ctx* c, int l, const T* G, double* out) {
         const Geo& g = c->geo[l];
         if (g.n_wall == 0) return;
-        int nkc = nchunks(c->nk);
-        LAUNCH(c, "wall_sums", (double)g.n_wall * c->nk * sizeof(T), k_wall_partial<T>,
-               dim3(ntiles(g.n_wall), nkc), dim3(256), g, c->vel, G, c->part);
-        LAUNCH(c, "wall_finalize", (double)g.n_wall * (nkc + 2) * 8, k_wall_finalize, dim3(nblk(g.n_wall)),
-               dim3(256), g, c->part, nkc, out);
+        LAUNCH(c, "wall_density", (double)g.n_wall * c->nk * sizeof(T), k_wall_density<T>,
+               dim3((g.n_wall + 3) / 4), dim3(256), g, c->vel, G, out);
     }
 
     // Step 1: interface records, div, R and the RMS norms (into c->norms)
@@ -276,15 +287,26 @@ struct Path {
         const Geo& g = c->geo[0];
         int nkc = nchunks(c->nk), nt = ntiles(g.nc);
         double nc8 = g.nc * 8.0;
-        LAUNCH(c, "face_prep", arr(c, 0) + (4 + 2 * NFP) * nc8, k_face_prep<T>, dim3(nt), dim3(64 * FW), g,
-               c->vel, c->gas, F(c), c->W, c->fp);
-        LAUNCH(c, "face_timeslope", (2.0 * NFP + 8) * nc8, k_face_timeslope<T>, dim3(nt), dim3(64 * FW), g,
-               c->vel, c->gas, c->fp);
+        // raw moments of the upwind interface distributions, per velocity
+        // chunk, summed in chunk order; interface records
+        LAUNCH(c, "face_moments", arr(c, 0) + 2.0 * NRAW * nkc * nc8, k_face_moments_partial<T>, dim3(nt, nkc),
+               dim3(256), g, c->vel, F(c), c->part);
+        LAUNCH(c, "chunk_sum", 2.0 * NRAW * (nkc + 1) * nc8, k_chunk_sum, dim3(nblk(2 * NRAW * g.nc)), dim3(256),
+               (const double*)c->part, nkc, 2 * NRAW, g.nc, 1.0, (const unsigned char*)nullptr, c->msum);
+        LAUNCH(c, "face_records", (2.0 * NRAW + 8 + 2 * NFP) * nc8, k_face_records, dim3(nblk(2 * g.nc)),
+               dim3(256), g, c->gas, (const double*)c->msum, (const double*)c->W, c->fp);
+        // time slopes from the discrete compatibility condition
+        LAUNCH(c, "face_timeslope", (2.0 * NFP + 8.0 * nkc) * nc8, k_face_timeslope_partial<T>, dim3(nt, nkc),
+               dim3(256), g, c->vel, c->gas, (const double*)c->fp, c->part);
+        LAUNCH(c, "chunk_sum", 8.0 * (nkc + 1) * nc8, k_chunk_sum, dim3(nblk(8 * g.nc)), dim3(256),
+               (const double*)c->part, nkc, 8, g.nc, 1.0, (const unsigned char*)nullptr, c->msum);
+        LAUNCH(c, "timeslope_records", (8.0 + 2 * 8) * nc8, k_face_timeslope_records, dim3(nblk(2 * g.nc)),
+               dim3(256), g, c->gas, (const double*)c->msum, c->fp);
         wall_sums(c, 0, F(c), c->rho_w);
         LAUNCH(c, "flux_div", 2 * arr(c, 0) + (2.0 * NFP + 4.0 * nkc) * nc8, k_flux_div<T>, dim3(nt, nkc),
                dim3(256), g, c->vel, c->gas, F(c), c->fp, c->rho_w, (const T*)c->finf, (T*)c->div, c->part);
-        LAUNCH(c, "residual_finalize", (4.0 * nkc + 4) * nc8, k_residual_finalize, dim3(nblk(g.nc)), dim3(256),
-               g, c->part, nkc, c->R);
+        LAUNCH(c, "chunk_sum", 4.0 * (nkc + 1) * nc8, k_chunk_sum, dim3(nblk(4 * g.nc)), dim3(256),
+               (const double*)c->part, nkc, 4, g.nc, -1.0, g.solid, c->R);
         LAUNCH(c, "residual_norm", 4 * nc8, k_residual_norm, dim3(1), dim3(256), g, c->hl[0].n_fluid, c->R,
                c->norms);
         c->have_div = true;
@@ -303,8 +325,9 @@ struct Path {
     // one smoothing on level l: wall densities from the current correction
     // (skipped when drho is already current), then the ordered sweep, which
     // also leaves the wall products of its result in wbuf
-    static void smooth(miugks_ctx* c, int l, bool drho_current) {
+    static void smooth(miugks_ctx* c, int l, bool drho_current, bool from_zero = false) {
         const Geo& g = c->geo[l];
+        c->last_from_zero[l] = from_zero && c->wave[l].W;
         if (!drho_current && g.n_wall)
             LAUNCH(c, "drho", (double)g.n_wall * c->nk * 8, k_drho, dim3((g.n_wall + 3) / 4), dim3(256), g, c->nk,
                    c->wbuf[l], c->drho[l]);
@@ -315,8 +338,8 @@ struct Path {
         if (wc.W) {
 #define MIUGKS_WAVE_LAUNCH(RR)                                                                                 \
     LAUNCH_SH(c, name, 2 * arr(c, l), wc.lds, (k_sweep_wave<T, RR>), dim3(wc.blocks), dim3(64 * wc.W), g, c->vel, \
-              c->gas.K_int, (const T*)c->r[l], (T*)c->df[l], c->tau_inv[l], c->dtn_inv[l], c->stype[l],          \
-              c->drho[l], c->wbuf[l], wc.I)
+              c->gas.K_int, (const T*)c->r[l], (T*)c->df[l], (const T*)c->coefT[l], c->stype[l],                \
+              from_zero ? (const double*)nullptr : (const double*)c->drho[l], c->wbuf[l], wc.I)
             switch (wc.R) {
                 case 1: MIUGKS_WAVE_LAUNCH(1); break;
                 case 2: MIUGKS_WAVE_LAUNCH(2); break;
@@ -343,24 +366,37 @@ struct Path {
     // sweep itself needs no initial correction).
     static void cs(miugks_ctx* c, int l) {
         const Geo& g = c->geo[l];
-        if (g.n_wall)
+        int pre = l == c->L - 1 ? c->nuc : c->nu1;
+        // the wavefront sweep starts from zero wall densities by itself
+        if (g.n_wall && (!c->wave[l].W || pre == 0))
             LAUNCH(c, "zero", (double)g.n_wall * 8, k_zero<double>, dim3(1), dim3(256), c->drho[l],
                    (size_t)g.n_wall);
-        int pre = l == c->L - 1 ? c->nuc : c->nu1;
-        for (int i = 0; i < pre; ++i) smooth(c, l, i == 0);
+        for (int i = 0; i < pre; ++i) smooth(c, l, i == 0, i == 0);
         if (l == c->L - 1) return;
         if (pre == 0) {
             size_t n = 2 * (size_t)c->nk * g.nc;
             LAUNCH(c, "zero", arr(c, l), k_zero<T>, dim3(nblk((int)std::min<size_t>(n, 1 << 24))), dim3(256),
                    (T*)c->df[l], n);
         } else if (g.n_wall) {
-            LAUNCH(c, "drho", (double)g.n_wall * c->nk * 8, k_drho, dim3((g.n_wall + 3) / 4), dim3(256), g, c->nk,
-                   c->wbuf[l], c->drho[l]);
+            LAUNCH(c, "drho", (double)g.n_wall * c->nk * 8, k_drho_delta, dim3((g.n_wall + 3) / 4), dim3(256), g,
+                   c->nk, c->wbuf[l], c->drho[l], c->ddrho[l], (int)c->last_from_zero[l]);
         }
         const Geo& gc = c->geo[l + 1];
-        LAUNCH(c, "defect_restrict", 2 * arr(c, l) + arr(c, l + 1), k_defect_restrict<T>,
-               dim3(ntiles(gc.nc), nchunks(c->nk)), dim3(256), g, gc, c->vel, c->gas.K_int, (const T*)c->r[l],
-               (const T*)c->df[l], c->tau_inv[l], c->dtn_inv[l], c->drho[l], (T*)c->r[l + 1]);
+        if (pre > 0) {
+            // after an ordered sweep the defect lives on the wall cells only
+            if (!g.n_wall)
+                LAUNCH(c, "zero", arr(c, l + 1), k_zero<T>, dim3(nblk((int)std::min<size_t>(2 * (size_t)c->nk * gc.nc,
+                                                                                           1 << 24))),
+                       dim3(256), (T*)c->r[l + 1], 2 * (size_t)c->nk * gc.nc);
+            else
+                LAUNCH(c, "defect_walls", arr(c, l + 1), k_defect_walls<T>, dim3(ntiles(gc.nc), nchunks(c->nk)),
+                       dim3(256), g, gc, c->vel, c->gas.K_int, (const int4*)c->cwall[l + 1],
+                       (const double*)c->civol[l + 1], (const double*)c->ddrho[l], (T*)c->r[l + 1]);
+        } else {
+            LAUNCH(c, "defect_restrict", 2 * arr(c, l) + arr(c, l + 1), k_defect_restrict<T>,
+                   dim3(ntiles(gc.nc), nchunks(c->nk)), dim3(256), g, gc, c->vel, c->gas.K_int, (const T*)c->r[l],
+                   (const T*)c->df[l], c->tau_inv[l], c->dtn_inv[l], c->drho[l], (T*)c->r[l + 1]);
+        }
         cs(c, l + 1);
         LAUNCH(c, "prolong_add", 2 * arr(c, l) + arr(c, l + 1), k_prolong_add<T>,
                dim3(ntiles(g.nc), nchunks(c->nk)), dim3(256), g, c->vel, gc.nc, (const T*)c->df[l + 1],
@@ -375,6 +411,7 @@ struct Path {
             LAUNCH(c, "restrict_cells", (c->geo[l].nc + c->geo[l + 1].nc) * 8.0, k_restrict_cells,
                    dim3(nblk(c->geo[l + 1].nc)), dim3(256), c->geo[l], c->geo[l + 1], 1, c->tau_inv[l],
                    c->tau_inv[l + 1]);
+        LAUNCH(c, "sweep_coef", 0.0, k_sweep_coef<T>, dim3(nblk(c->geo[0].nc)), dim3(256), c->coefset);
         cs(c, 0);
     }
 
@@ -797,7 +834,8 @@ int build_device(miugks_ctx* ctx) {
     if ((rc = dalloc(&ctx->W, 4 * nc0)) || (rc = dalloc(&ctx->q, 2 * nc0)) || (rc = dalloc(&ctx->R, 4 * nc0)) ||
         (rc = dalloc(&ctx->Wt, 4 * nc0)) || (rc = dalloc(&ctx->fp, NFP * 2 * nc0)) ||
         (rc = dalloc(&ctx->cp, NCP * nc0)) || (rc = dalloc(&ctx->norms, 4)) ||
-        (rc = dalloc(&ctx->rho_w, ctx->hl[0].w_cell.size() + 1)) || (rc = dalloc(&ctx->mass, 1)))
+        (rc = dalloc(&ctx->rho_w, ctx->hl[0].w_cell.size() + 1)) || (rc = dalloc(&ctx->mass, 1)) ||
+        (rc = dalloc(&ctx->msum, 2 * NRAW * nc0)))
         return rc;
     // partial sums: the largest is 2 * NRAW per cell per chunk
     size_t maxw = 1;
@@ -822,6 +860,53 @@ int build_device(miugks_ctx* ctx) {
             return rc;
         HIP_TRY(hipMemset(ctx->fE[l], 0, 4 * nc * sizeof(double)));
         HIP_TRY(hipMemset(ctx->dtn_inv[l], 0, nc * sizeof(double)));
+    }
+    ctx->cwall.assign(ctx->L, nullptr);
+    ctx->civol.assign(ctx->L, nullptr);
+    ctx->ddrho.assign(ctx->L, nullptr);
+    ctx->last_from_zero.assign(ctx->L, 0);
+    for (int l = 0; l < ctx->L; ++l) {
+        const HostLevel& h = ctx->hl[l];
+        if ((rc = dalloc(&ctx->ddrho[l], h.w_cell.size() + 1))) return rc;
+        if (l == 0) continue;
+        // coarse level l, fine level l - 1
+        const HostLevel& f = ctx->hl[l - 1];
+        std::vector<int> first(f.nc + 1, 0);
+        for (size_t j = 0; j < f.w_cell.size(); ++j) first[f.w_cell[j] + 1] += 1;
+        for (int c = 0; c < f.nc; ++c) first[c + 1] += first[c];
+        std::vector<int4> cw(h.nc);
+        std::vector<double> iv(h.nc);
+        for (int J = 0; J < h.ny; ++J)
+            for (int I = 0; I < h.nx; ++I) {
+                int C = J * h.nx + I, c0 = (2 * J) * f.nx + 2 * I, c1 = (2 * J + 1) * f.nx + 2 * I;
+                cw[C] = make_int4(first[c0], first[c0 + 2], first[c1], first[c1 + 2]);
+                double vol = 0.0;
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b) {
+                        int c = (2 * J + a) * f.nx + 2 * I + b;
+                        if (!f.solid[c]) vol += f.dx[c % f.nx] * f.dy[c / f.nx];
+                    }
+                iv[C] = vol > 0.0 ? 1.0 / vol : 0.0;
+            }
+        int4* cwp;
+        double* ivp;
+        if ((rc = upload(ctx, &cwp, cw)) || (rc = upload(ctx, &ivp, iv))) return rc;
+        ctx->cwall[l] = cwp;
+        ctx->civol[l] = ivp;
+    }
+    ctx->coefT.assign(ctx->L, nullptr);
+    ctx->coefset.L = std::min(ctx->L, FAS_MAXL);
+    for (int l = 0; l < ctx->L; ++l) {
+        if ((rc = dev_alloc(ctx, &ctx->coefT[l], ctx->hl[l].nc * es))) return rc;
+        if (l < FAS_MAXL) {
+            ctx->coefset.nc[l] = ctx->hl[l].nc;
+            ctx->coefset.solid[l] = ctx->geo[l].solid;
+            ctx->coefset.tau[l] = ctx->tau_inv[l];
+            ctx->coefset.dtn[l] = ctx->dtn_inv[l];
+            ctx->coefset.out[l] = ctx->coefT[l];
+        } else {
+            ctx->wave[l].W = 0;
+        }
     }
     // FAS in one workgroup for the trailing levels of at most this many cells
     {
