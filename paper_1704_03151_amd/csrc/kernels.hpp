@@ -37,6 +37,7 @@ struct Geo {
     const unsigned char* solid;
     const int *w_cell, *w_side;
     const double *w_T, *w_U, *w_V, *w_den;
+    const double *w_invd, *w_vol;   // 1 / width of the wall's cell normal to the wall, its volume
     const int* p_idx;
     const double* p_w;
 };
@@ -1495,8 +1496,8 @@ __device__ __forceinline__ void wave_store(T* __restrict__ dst, const T* src, in
 
 // LDS bytes of k_sweep_wave for W wavefronts of I velocities each
 template <typename T>
-size_t sweep_wave_lds_bytes(int nc, int nx, int W, int I) {
-    size_t b = ((size_t)W * 2 * I * nc + nc + nx) * sizeof(T) + (size_t)nc;
+size_t sweep_wave_lds_bytes(int nc, int nx, int nw, int W, int I) {
+    size_t b = ((size_t)W * 2 * I * nc + nc + nx + 5 * (size_t)nw) * sizeof(T) + 4 * (size_t)nw + (size_t)nc;
     return (b + 15) & ~(size_t)15;
 }
 
@@ -1515,7 +1516,9 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
     T* tiles = (T*)smem_d;                                  // [W][2][I][nc]
     T* coef = tiles + (size_t)W * 2 * I * nc;               // [nc]
     T* invdx = coef + nc;                                   // [nx]
-    unsigned char* st = (unsigned char*)(invdx + nx);       // [nc]  side types, 2 bits per side
+    T* wl = invdx + nx;                                     // [5][n_wall]  1/d, lam_w, U_w, V_w, drho
+    int* wsc = (int*)(wl + 5 * (size_t)nw);                 // [n_wall]  side + 4 cell
+    unsigned char* st = (unsigned char*)(wsc + nw);         // [nc]  side types, 2 bits per side
     const int k0 = (blockIdx.x * W + w) * I;                // first velocity of this wavefront
     const int nq = max(0, min(I, nk - k0));                 // velocities it holds
     T* tw = tiles + (size_t)w * 2 * I * nc;
@@ -1527,12 +1530,19 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
     if (w == 0) wave_load_lds<T>(coef, coef_g, nc, lane);
     if (w == W - 1) wave_load_lds<unsigned char>(st, stype, nc, lane);
     for (int i = threadIdx.x; i < nx; i += blockDim.x) invdx[i] = T(1.0 / g.dx[i]);
+    for (int j = threadIdx.x; j < nw; j += blockDim.x) {
+        wl[j] = T(g.w_invd[j]);
+        wl[nw + j] = T(1.0 / g.w_T[j]);
+        wl[2 * nw + j] = T(g.w_U[j]);
+        wl[3 * nw + j] = T(g.w_V[j]);
+        wl[4 * nw + j] = drho ? T(drho[j]) : T(0);
+        wsc[j] = g.w_side[j] + 4 * g.w_cell[j];
+    }
     // velocities of this wavefront: lane q < nq holds velocity k0 + q
     const T uq_l = lane < nq ? vel_u<T>(vel, k0 + lane) : T(0);
     const T vq_l = lane < nq ? vel_v<T>(vel, k0 + lane) : T(0);
     __syncthreads();
-    // upwind wall-ghost terms into r (x-sides, then y-sides); wall data is
-    // loaded once per 64 wall sides
+    // upwind wall-ghost terms into r (x-sides, then y-sides)
     if (drho) {
         for (int jb = 0; jb < nw; jb += 64) {
             const int j = jb + lane;
@@ -1540,13 +1550,13 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
             int sd = 0, cell = 0;
             T invd = T(0), lam = T(1), wu = T(0), wv = T(0), dr = T(0);
             if (ok) {
-                sd = g.w_side[j];
-                cell = g.w_cell[j];
-                invd = T(1.0 / (sd < 2 ? g.dx[cell % nx] : g.dy[cell / nx]));
-                lam = T(1.0 / g.w_T[j]);
-                wu = T(g.w_U[j]);
-                wv = T(g.w_V[j]);
-                dr = T(drho[j]);
+                sd = wsc[j] & 3;
+                cell = wsc[j] >> 2;
+                invd = wl[j];
+                lam = wl[nw + j];
+                wu = wl[2 * nw + j];
+                wv = wl[3 * nw + j];
+                dr = wl[4 * nw + j];
             }
             for (int dir = 0; dir < 2; ++dir) {
                 for (int q = 0; q < nq; ++q) {
@@ -1653,7 +1663,7 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
         for (int jb = 0; jb < nw; jb += 64) {
             const int j = jb + lane;
             const bool ok = j < nw;
-            const int sd = ok ? g.w_side[j] : 0, cell = ok ? g.w_cell[j] : 0;
+            const int sd = ok ? wsc[j] & 3 : 0, cell = ok ? wsc[j] >> 2 : 0;
             for (int qv = 0; qv < nq; ++qv) {
                 double uu = __shfl(ud, qv, 64), vv = __shfl(vd, qv, 64), ww = __shfl(wd, qv, 64);
                 double un = ((sd & 1) ? 1.0 : -1.0) * (sd < 2 ? uu : vv);
@@ -1750,36 +1760,44 @@ __global__ void __launch_bounds__(256) k_defect_walls(Geo g, Geo gc, Vel vel, in
     const int C = ch.c;
     const size_t ncc = gc.nc, hoc = (size_t)vel.nk * ncc;
     const int4 rg = cw[C];
-    if (rg.x == rg.y && rg.z == rg.w) {
-        for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
-            rc[(size_t)k * ncc + C] = T(0);
-            rc[hoc + (size_t)k * ncc + C] = T(0);
-        }
-        return;
+    // the thread's velocities k = k0 + wave + WAVES i (statically indexed)
+    double sG[MK], sH[MK], uk[MK], vk[MK];
+#pragma unroll
+    for (int i = 0; i < MK; ++i) {
+        int k = min(ch.k0 + ch.wave + WAVES * i, vel.nk - 1);
+        uk[i] = vel.u[k];
+        vk[i] = vel.v[k];
+        sG[i] = sH[i] = 0.0;
     }
-    const double iv = civol[C];
-    for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
-        double u = vel.u[k], v = vel.v[k];
-        double sG = 0.0, sH = 0.0;
-        for (int part = 0; part < 2; ++part) {
-            int j0 = part ? rg.z : rg.x, j1 = part ? rg.w : rg.y;
-            for (int j = j0; j < j1; ++j) {
-                int sd = g.w_side[j], cell = g.w_cell[j];
-                double un = ((sd & 1) ? 1.0 : -1.0) * (sd < 2 ? u : v);
-                if (!(un < 0.0)) continue;
-                double dx = g.dx[cell % g.nx], dy = g.dy[cell / g.nx];
-                double a = -un / (sd < 2 ? dx : dy);
-                // ghost terms in the sweep's type, as the sweep added them
-                T lam = T(1.0 / g.w_T[j]);
-                T du = T(u) - T(g.w_U[j]), dv = T(v) - T(g.w_V[j]);
+    for (int part = 0; part < 2; ++part) {
+        int j0 = part ? rg.z : rg.x, j1 = part ? rg.w : rg.y;
+        for (int j = j0; j < j1; ++j) {
+            // wall data once, then every velocity of the thread
+            const int sd = g.w_side[j];
+            const double aw = g.w_invd[j] * g.w_vol[j] * ddrho[j];
+            const T lam = T(1.0 / g.w_T[j]), wu = T(g.w_U[j]), wv = T(g.w_V[j]);
+            const double hfac = double(T(K_int) / (T(2) * lam));
+            const double sgn = (sd & 1) ? 1.0 : -1.0;
+#pragma unroll
+            for (int i = 0; i < MK; ++i) {
+                double un = sgn * (sd < 2 ? uk[i] : vk[i]);
+                // ghost term in the sweep's type, as the sweep added it
+                T du = T(uk[i]) - wu, dv = T(vk[i]) - wv;
                 T Ck = lam / T(M_PI) * dexp(-lam * (du * du + dv * dv));
-                double e = a * double(Ck) * ddrho[j] * dx * dy;
-                sG += e;
-                sH += e * double(T(K_int) / (T(2) * lam));
+                double e = un < 0.0 ? -un * double(Ck) * aw : 0.0;
+                sG[i] += e;
+                sH[i] += e * hfac;
             }
         }
-        rc[(size_t)k * ncc + C] = T(sG * iv);
-        rc[hoc + (size_t)k * ncc + C] = T(sH * iv);
+    }
+    const double iv = civol[C];
+#pragma unroll
+    for (int i = 0; i < MK; ++i) {
+        int k = ch.k0 + ch.wave + WAVES * i;
+        if (k < ch.k1) {
+            rc[(size_t)k * ncc + C] = T(sG[i] * iv);
+            rc[hoc + (size_t)k * ncc + C] = T(sH[i] * iv);
+        }
     }
 }
 
@@ -1992,6 +2010,225 @@ __device__ __forceinline__ void fas_prolong_cell(const Geo& g, int ncc, const do
     }
 }
 
+// --- the same operations with four lanes per cell, lane s taking side s
+// (and conservative component s where a cell writes its four results); the
+// four consecutive lanes of a cell add their side terms by two butterfly
+// shuffles.  Used by the kernels below: a cell's dependent chain of FP64
+// work is a quarter as long, which is what bounds these small levels.
+
+__device__ __forceinline__ double quad_sum(double x) {
+    x += __shfl_xor(x, 1, 64);
+    x += __shfl_xor(x, 2, 64);
+    return x;
+}
+
+// Euler flux of W through a side of normal sign * e_d (division-free: the
+// reciprocal density is refined to full precision)
+__device__ __forceinline__ void euler_flux_r(const double* W, int d, double sign, double K, double* F) {
+    double ir = rcp_refined(W[0]);
+    double U = W[1] * ir, V = W[2] * ir;
+    double p = (2.0 / K) * (W[3] - 0.5 * W[0] * (U * U + V * V));
+    double un = sign * (d == 0 ? U : V);
+    F[0] = W[0] * un;
+    F[1] = W[1] * un + (d == 0 ? sign * p : 0.0);
+    F[2] = W[2] * un + (d == 1 ? sign * p : 0.0);
+    F[3] = (W[3] + p) * un;
+}
+
+__device__ __forceinline__ double fas_gamma_side(const Geo& g, const Gas& gas, const double* __restrict__ W,
+                                                 int c, int s) {
+    double Wi[4], Wj[4];
+    for (int m = 0; m < 4; ++m) Wi[m] = W[m * g.nc + c];
+    int wall = -1;
+    side_state(g, gas, W, c, s, Wi, Wj, wall);
+    double ri, Ui, Vi, li, rj, Uj, Vj, lj;
+    prim_of(Wi, gas.K, ri, Ui, Vi, li);
+    prim_of(Wj, gas.K, rj, Uj, Vj, lj);
+    double rm = 0.5 * (ri + rj), Um = 0.5 * (Ui + Uj), Vm = 0.5 * (Vi + Vj);
+    double Tm = 0.5 * (1.0 / li + 1.0 / lj);
+    double un = fabs(s < 2 ? Um : Vm);
+    double as = sqrt(gas.gamma * Tm / 2.0);
+    double nu = mu_of(gas, Tm) / rm;
+    return un + as + 2.0 * nu / g.dcent[s * g.nc + c];
+}
+
+// side-s term of sum_j S_ij F_ij(W) (the split flux of Sec. II A 1)
+__device__ __forceinline__ void fas_rsplit_side(const Geo& g, const Gas& gas, const double* __restrict__ W,
+                                                const double* __restrict__ Gam, int c, int s, double* acc) {
+    double Wi[4], Wj[4], Fi[4], Fj[4];
+    for (int m = 0; m < 4; ++m) Wi[m] = W[m * g.nc + c];
+    int wall = -1;
+    side_state(g, gas, W, c, s, Wi, Wj, wall);
+    int d = s >> 1;
+    double sign = (s & 1) ? 1.0 : -1.0;
+    euler_flux_r(Wi, d, sign, gas.K, Fi);
+    euler_flux_r(Wj, d, sign, gas.K, Fj);
+    double S = d == 0 ? g.dy[c / g.nx] : g.dx[c % g.nx], G = Gam[s * g.nc + c];
+    for (int m = 0; m < 4; ++m) acc[m] = S * 0.5 * (Fi[m] + Fj[m] + G * (Wi[m] - Wj[m]));
+}
+
+// side-s terms of the linearised defect equation of one half-sweep:
+// S (F(W_j + E_j) - F(W_j) - Gam E_j) and S Gam
+__device__ __forceinline__ void fas_half_side(const Geo& g, const Gas& gas, const double* __restrict__ W,
+                                              const double* __restrict__ E, const double* __restrict__ Gam,
+                                              int c, int s, double* acc, double& sg) {
+    double Wi[4], Ei[4], Wj[4], Ej[4], A[4], B[4];
+    for (int m = 0; m < 4; ++m) {
+        Wi[m] = W[m * g.nc + c];
+        Ei[m] = E[m * g.nc + c];
+    }
+    int wall = -1;
+    int kind = side_state(g, gas, W, c, s, Wi, Wj, wall);
+    int d = s >> 1;
+    double sign = (s & 1) ? 1.0 : -1.0;
+    double S = d == 0 ? g.dy[c / g.nx] : g.dx[c % g.nx], G = Gam[s * g.nc + c];
+    if (kind == 0) {
+        int o = g.nb[s * g.nc + c];
+        for (int m = 0; m < 4; ++m) Ej[m] = E[m * g.nc + o];
+    } else if (kind == 1) {
+        for (int m = 0; m < 4; ++m) Ej[m] = 0.0;
+    } else if (kind == 2) {
+        for (int m = 0; m < 4; ++m) Ej[m] = Ei[m];
+    } else {
+        // linearised wall ghost dW_j = J dW_i (Sec. III B), K total degrees of freedom
+        double rho, U, V2, lam;
+        prim_of(Wi, gas.K, rho, U, V2, lam);
+        double Uw = g.w_U[wall], Vw = g.w_V[wall], lw = 1.0 / g.w_T[wall];
+        double Y = lam / (lam - 2.0 * lw);
+        Ej[0] = Ei[0];
+        Ej[1] = 2.0 * Uw * Ei[0] - Ei[1];
+        Ej[2] = 2.0 * Vw * Ei[0] - Ei[2];
+        Ej[3] = (2.0 * (Uw * Uw + Vw * Vw) - 0.5 * (U * U + V2 * V2) * (1.0 + Y * Y) +
+                 gas.K / (4.0 * lam) * (Y * Y - Y)) * Ei[0] +
+                (U - 2.0 * Uw + U * Y * Y) * Ei[1] + (V2 - 2.0 * Vw + V2 * Y * Y) * Ei[2] - Y * Y * Ei[3];
+    }
+    double WE[4];
+    for (int m = 0; m < 4; ++m) WE[m] = Wj[m] + Ej[m];
+    euler_flux_r(WE, d, sign, gas.K, A);
+    euler_flux_r(Wj, d, sign, gas.K, B);
+    for (int m = 0; m < 4; ++m) acc[m] = S * (A[m] - B[m] - G * Ej[m]);
+    sg = S * G;
+}
+
+// phases with four lanes per cell: item t = 4 c + s over [0, 4 nc)
+__device__ __forceinline__ void fas4_gamma(const Geo& g, const Gas& gas, const double* __restrict__ W,
+                                           double* __restrict__ W0, double* __restrict__ Gam, int t) {
+    int c = t >> 2, s = t & 3;
+    if (W0) W0[s * g.nc + c] = W[s * g.nc + c];
+    Gam[s * g.nc + c] = g.solid[c] ? 0.0 : fas_gamma_side(g, gas, W, c, s);
+}
+
+// out = base + sgn * R_split(W), R_split_i = -(1/V_i) sum_j S_ij F_ij(W)
+__device__ __forceinline__ void fas4_rsplit(const Geo& g, const Gas& gas, const double* __restrict__ W,
+                                            const double* __restrict__ Gam, const double* __restrict__ base,
+                                            double sgn, double* __restrict__ out, int t) {
+    int c = t >> 2, s = t & 3;
+    bool solid = g.solid[c];
+    double acc[4] = {0, 0, 0, 0};
+    if (!solid) fas_rsplit_side(g, gas, W, Gam, c, s, acc);
+    double tot[4];
+    for (int m = 0; m < 4; ++m) tot[m] = quad_sum(acc[m]);
+    double iv = 1.0 / (g.dx[c % g.nx] * g.dy[c / g.nx]);
+    double mine = s == 0 ? tot[0] : s == 1 ? tot[1] : s == 2 ? tot[2] : tot[3];
+    out[s * g.nc + c] = solid ? 0.0 : base[s * g.nc + c] + sgn * (-mine * iv);
+}
+
+// one red-black half-sweep on the cells of the given colour
+__device__ __forceinline__ void fas4_halfsweep(const Geo& g, const Gas& gas, const double* __restrict__ W,
+                                               double* __restrict__ E, const double* __restrict__ Rm,
+                                               const double* __restrict__ Gam,
+                                               const double* __restrict__ dtn_inv, int colour, int t) {
+    int c = t >> 2, s = t & 3;
+    int ix = c % g.nx, iy = c / g.nx;
+    if (((ix + iy) & 1) != colour || g.solid[c]) return;   // all four lanes of the cell alike
+    double acc[4], sg;
+    fas_half_side(g, gas, W, E, Gam, c, s, acc, sg);
+    double tot[4];
+    for (int m = 0; m < 4; ++m) tot[m] = quad_sum(acc[m]);
+    double Dsum = quad_sum(sg);
+    double V = g.dx[ix] * g.dy[iy];
+    double D = Dsum / (2.0 * V) + dtn_inv[c];
+    double mine = s == 0 ? tot[0] : s == 1 ? tot[1] : s == 2 ? tot[2] : tot[3];
+    E[s * g.nc + c] = (Rm[s * g.nc + c] - mine / (2.0 * V)) / D;
+}
+
+__device__ __forceinline__ void fas4_apply(const Geo& g, double* __restrict__ W, double* __restrict__ E, int t) {
+    int c = t >> 2, m = t & 3;
+    if (!g.solid[c]) W[m * g.nc + c] += E[m * g.nc + c];
+    E[m * g.nc + c] = 0.0;
+}
+
+__device__ __forceinline__ void fas4_prolong(const Geo& g, int ncc, const double* __restrict__ Wc,
+                                             const double* __restrict__ Wc0, double* __restrict__ W, int t) {
+    int c = t >> 2, m = t & 3;
+    if (g.solid[c]) return;
+    double s = 0.0;
+    for (int a = 0; a < 4; ++a) {
+        int id = g.p_idx[a * g.nc + c];
+        s += g.p_w[a * g.nc + c] * (Wc[(size_t)m * ncc + id] - Wc0[(size_t)m * ncc + id]);
+    }
+    W[m * g.nc + c] += s;
+}
+
+// component m of coarse cell C: volume-weighted mean over fluid children
+__device__ __forceinline__ void restrict_comp(const Geo& g, const Geo& gc, const double* __restrict__ a,
+                                              double* __restrict__ ac, int C, int m) {
+    int I = C % gc.nx, J = C / gc.nx;
+    double s = 0.0, vol = 0.0;
+    for (int aa = 0; aa < 2; ++aa)
+        for (int b = 0; b < 2; ++b) {
+            int c = (2 * J + aa) * g.nx + 2 * I + b;
+            if (g.solid[c]) continue;
+            double V = g.dx[c % g.nx] * g.dy[c / g.nx];
+            s += V * a[(size_t)m * g.nc + c];
+            vol += V;
+        }
+    ac[(size_t)m * gc.nc + C] = vol > 0 ? s / vol : 0.0;
+}
+
+#define ITEM4_KERNEL_INDEX                              \
+    int t = blockIdx.x * blockDim.x + threadIdx.x;      \
+    if (t >= 4 * g.nc) return;
+
+__global__ void k_fas4_gamma(Geo g, Gas gas, const double* __restrict__ W, double* __restrict__ W0,
+                             double* __restrict__ Gam) {
+    ITEM4_KERNEL_INDEX
+    fas4_gamma(g, gas, W, W0, Gam, t);
+}
+
+__global__ void k_fas4_rsplit(Geo g, Gas gas, const double* __restrict__ W, const double* __restrict__ Gam,
+                              const double* __restrict__ base, double sgn, double* __restrict__ out) {
+    ITEM4_KERNEL_INDEX
+    fas4_rsplit(g, gas, W, Gam, base, sgn, out, t);
+}
+
+__global__ void k_fas4_halfsweep(Geo g, Gas gas, const double* __restrict__ W, double* __restrict__ E,
+                                 const double* __restrict__ Rm, const double* __restrict__ Gam,
+                                 const double* __restrict__ dtn_inv, int colour) {
+    ITEM4_KERNEL_INDEX
+    fas4_halfsweep(g, gas, W, E, Rm, Gam, dtn_inv, colour, t);
+}
+
+__global__ void k_fas4_apply(Geo g, double* __restrict__ W, double* __restrict__ E) {
+    ITEM4_KERNEL_INDEX
+    fas4_apply(g, W, E, t);
+}
+
+__global__ void k_fas4_prolong(Geo g, int ncc, const double* __restrict__ Wc, const double* __restrict__ Wc0,
+                               double* __restrict__ W) {
+    ITEM4_KERNEL_INDEX
+    fas4_prolong(g, ncc, Wc, Wc0, W, t);
+}
+
+// W and R of level l + 1 from level l (fine W and the renewed residual)
+__global__ void k_fas4_restrict(Geo g, Geo gc, const double* __restrict__ W, const double* __restrict__ Rm,
+                                double* __restrict__ Wc, double* __restrict__ Rc) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * gc.nc) return;
+    restrict_comp(g, gc, W, Wc, t >> 2, t & 3);
+    restrict_comp(g, gc, Rm, Rc, t >> 2, t & 3);
+}
+
 #define CELL_KERNEL_INDEX                               \
     int c = blockIdx.x * blockDim.x + threadIdx.x;      \
     if (c >= g.nc) return;
@@ -2041,45 +2278,110 @@ struct FasSet {
 
 __device__ __forceinline__ void fas_block_smooth(const FasSet& F, const Gas& gas, int l, int count) {
     const Geo& g = F.geo[l];
+    const int n4 = 4 * g.nc;
     for (int it = 0; it < count; ++it) {
-        for (int c = threadIdx.x; c < g.nc; c += blockDim.x)
-            fas_rsplit_cell(g, gas, F.W[l], F.Gam[l], F.P[l], 1.0, F.Rm[l], c);
+        for (int t = threadIdx.x; t < n4; t += blockDim.x)
+            fas4_rsplit(g, gas, F.W[l], F.Gam[l], F.P[l], 1.0, F.Rm[l], t);
         __syncthreads();
         for (int col : {0, 1, 0}) {
-            for (int c = threadIdx.x; c < g.nc; c += blockDim.x)
-                fas_halfsweep_cell(g, gas, F.W[l], F.E[l], F.Rm[l], F.Gam[l], F.dtn[l], col, c);
+            for (int t = threadIdx.x; t < n4; t += blockDim.x)
+                fas4_halfsweep(g, gas, F.W[l], F.E[l], F.Rm[l], F.Gam[l], F.dtn[l], col, t);
             __syncthreads();
         }
-        for (int c = threadIdx.x; c < g.nc; c += blockDim.x) fas_apply_cell(g, F.W[l], F.E[l], c);
+        for (int t = threadIdx.x; t < n4; t += blockDim.x) fas4_apply(g, F.W[l], F.E[l], t);
         __syncthreads();
     }
 }
 
 __device__ __forceinline__ void fas_block_enter(const FasSet& F, const Gas& gas, int l) {
     const Geo& g = F.geo[l];
-    for (int c = threadIdx.x; c < g.nc; c += blockDim.x) {
-        for (int m = 0; m < 4; ++m) F.W0[l][m * g.nc + c] = F.W[l][m * g.nc + c];
-        fas_gamma_cell(g, gas, F.W[l], F.Gam[l], c);
-    }
+    const int n4 = 4 * g.nc;
+    for (int t = threadIdx.x; t < n4; t += blockDim.x) fas4_gamma(g, gas, F.W[l], F.W0[l], F.Gam[l], t);
     __syncthreads();
-    for (int c = threadIdx.x; c < g.nc; c += blockDim.x)
-        fas_rsplit_cell(g, gas, F.W[l], F.Gam[l], F.R[l], -1.0, F.P[l], c);
+    for (int t = threadIdx.x; t < n4; t += blockDim.x)
+        fas4_rsplit(g, gas, F.W[l], F.Gam[l], F.R[l], -1.0, F.P[l], t);
     __syncthreads();
 }
 
-__global__ void __launch_bounds__(512) k_fas_cycle_block(FasSet F, Gas gas) {
-    int L = F.L;
+// LDS layout of k_fas_cycle_block: for every level from l0 on, the FAS
+// arrays (W, W0, R, P, E, Gam, Rm: 4 per cell), 1/dt_n, and the geometry the
+// smoother reads (side codes, centre distances, widths, solid flags,
+// prolongation stencil); wall states stay in global memory.
+__host__ __device__ inline size_t fas_lds_align(size_t b) { return (b + 15) & ~(size_t)15; }
+
+__host__ __device__ inline size_t fas_level_lds_bytes(int nx, int ny) {
+    size_t nc = (size_t)nx * ny;
+    return 7 * fas_lds_align(4 * nc * 8) + fas_lds_align(nc * 8) + fas_lds_align(4 * nc * 4) +
+           fas_lds_align(4 * nc * 8) + fas_lds_align(nx * 8) + fas_lds_align(ny * 8) + fas_lds_align(nc) +
+           fas_lds_align(4 * nc * 4) + fas_lds_align(4 * nc * 8);
+}
+
+template <typename P>
+__device__ __forceinline__ void block_copy(P* dst, const P* __restrict__ src, size_t n) {
+    for (size_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+__global__ void __launch_bounds__(1024) k_fas_cycle_block(FasSet G, Gas gas) {
+    extern __shared__ double fsm[];
+    __shared__ FasSet F;
+    if (threadIdx.x == 0) {
+        F = G;
+        char* p = (char*)fsm;
+        auto take = [&](size_t bytes) {
+            char* q = p;
+            p += fas_lds_align(bytes);
+            return q;
+        };
+        for (int l = G.l0; l < G.L; ++l) {
+            const Geo& g = G.geo[l];
+            size_t nc = g.nc;
+            F.W[l] = (double*)take(4 * nc * 8);
+            F.W0[l] = (double*)take(4 * nc * 8);
+            F.R[l] = (double*)take(4 * nc * 8);
+            F.P[l] = (double*)take(4 * nc * 8);
+            F.E[l] = (double*)take(4 * nc * 8);
+            F.Gam[l] = (double*)take(4 * nc * 8);
+            F.Rm[l] = (double*)take(4 * nc * 8);
+            F.dtn[l] = (double*)take(nc * 8);
+            F.geo[l].nb = (const int*)take(4 * nc * 4);
+            F.geo[l].dcent = (const double*)take(4 * nc * 8);
+            F.geo[l].dx = (const double*)take(g.nx * 8);
+            F.geo[l].dy = (const double*)take(g.ny * 8);
+            F.geo[l].solid = (const unsigned char*)take(nc);
+            F.geo[l].p_idx = (const int*)take(4 * nc * 4);
+            F.geo[l].p_w = (const double*)take(4 * nc * 8);
+        }
+    }
+    __syncthreads();
+    for (int l = G.l0; l < G.L; ++l) {
+        const Geo& g = G.geo[l];
+        size_t nc = g.nc;
+        block_copy((int*)F.geo[l].nb, g.nb, 4 * nc);
+        block_copy((double*)F.geo[l].dcent, g.dcent, 4 * nc);
+        block_copy((double*)F.geo[l].dx, g.dx, (size_t)g.nx);
+        block_copy((double*)F.geo[l].dy, g.dy, (size_t)g.ny);
+        block_copy((unsigned char*)F.geo[l].solid, g.solid, nc);
+        block_copy((int*)F.geo[l].p_idx, g.p_idx, 4 * nc);
+        block_copy((double*)F.geo[l].p_w, g.p_w, 4 * nc);
+        block_copy(F.dtn[l], G.dtn[l], nc);
+        for (size_t i = threadIdx.x; i < 4 * nc; i += blockDim.x) F.E[l][i] = 0.0;
+    }
+    block_copy(F.W[G.l0], G.W[G.l0], 4 * (size_t)G.geo[G.l0].nc);
+    block_copy(F.R[G.l0], G.R[G.l0], 4 * (size_t)G.geo[G.l0].nc);
+    __syncthreads();
+
+    const int L = F.L;
     for (int l = F.l0; l < L - 1; ++l) {
         const Geo& g = F.geo[l];
         const Geo& gc = F.geo[l + 1];
         fas_block_enter(F, gas, l);
         fas_block_smooth(F, gas, l, F.nu1);
-        for (int c = threadIdx.x; c < g.nc; c += blockDim.x)
-            fas_rsplit_cell(g, gas, F.W[l], F.Gam[l], F.P[l], 1.0, F.Rm[l], c);
+        for (int t = threadIdx.x; t < 4 * g.nc; t += blockDim.x)
+            fas4_rsplit(g, gas, F.W[l], F.Gam[l], F.P[l], 1.0, F.Rm[l], t);
         __syncthreads();
-        for (int C = threadIdx.x; C < gc.nc; C += blockDim.x) {
-            restrict_cell(g, gc, 4, F.W[l], F.W[l + 1], C);
-            restrict_cell(g, gc, 4, F.Rm[l], F.R[l + 1], C);
+        for (int t = threadIdx.x; t < 4 * gc.nc; t += blockDim.x) {
+            restrict_comp(g, gc, F.W[l], F.W[l + 1], t >> 2, t & 3);
+            restrict_comp(g, gc, F.Rm[l], F.R[l + 1], t >> 2, t & 3);
         }
         __syncthreads();
     }
@@ -2087,11 +2389,14 @@ __global__ void __launch_bounds__(512) k_fas_cycle_block(FasSet F, Gas gas) {
     fas_block_smooth(F, gas, L - 1, F.nuc);
     for (int l = L - 2; l >= F.l0; --l) {
         const Geo& g = F.geo[l];
-        for (int c = threadIdx.x; c < g.nc; c += blockDim.x)
-            fas_prolong_cell(g, F.geo[l + 1].nc, F.W[l + 1], F.W0[l + 1], F.W[l], c);
+        for (int t = threadIdx.x; t < 4 * g.nc; t += blockDim.x)
+            fas4_prolong(g, F.geo[l + 1].nc, F.W[l + 1], F.W0[l + 1], F.W[l], t);
         __syncthreads();
         fas_block_smooth(F, gas, l, F.nu2);
     }
+    // result and the state the parent level prolongs from
+    block_copy(G.W[G.l0], F.W[G.l0], 4 * (size_t)G.geo[G.l0].nc);
+    block_copy(G.W0[G.l0], F.W0[G.l0], 4 * (size_t)G.geo[G.l0].nc);
 }
 
 // ---------------------------------------------------------------------------

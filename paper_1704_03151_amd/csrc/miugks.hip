@@ -93,6 +93,7 @@ struct miugks_ctx {
     double* h_factor = nullptr;
     // FAS levels run inside one workgroup from this level on
     int fas_block_l0 = 1 << 30;
+    std::vector<size_t> fas_block_lds;   // LDS of the one-workgroup FAS kernel starting at level l
     FasSet fasset{};
 };
 
@@ -435,16 +436,19 @@ struct Path {
 // ---------------------------------------------------------------------------
 // FAS cycle (precision independent, FP64)
 
+// one smoothing of Sec. II C 2: renewed residual, red-black half-sweeps of
+// colours 0, 1, 0, then W += E (four lanes per cell in every phase)
 void fas_smooth(miugks_ctx* c, int l) {
     const Geo& g = c->geo[l];
-    int nb = nblk(g.nc);
+    int nb = nblk(4 * g.nc);
     double nc8 = g.nc * 8.0;
-    LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas_rsplit, dim3(nb), dim3(256), g, c->gas, c->fW[l], c->fGam[l], c->fP[l],
-           1.0, c->fRm[l]);
+    LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas4_rsplit, dim3(nb), dim3(256), g, c->gas, (const double*)c->fW[l],
+           (const double*)c->fGam[l], (const double*)c->fP[l], 1.0, c->fRm[l]);
     for (int col : {0, 1, 0})
-        LAUNCH(c, "fas_halfsweep", 18 * nc8, k_fas_halfsweep, dim3(nb), dim3(256), g, c->gas, c->fW[l], c->fE[l],
-               c->fRm[l], c->fGam[l], c->dtn_inv[l], col);
-    LAUNCH(c, "fas_apply", 16 * nc8, k_fas_apply, dim3(nb), dim3(256), g, c->fW[l], c->fE[l]);
+        LAUNCH(c, "fas_halfsweep", 18 * nc8, k_fas4_halfsweep, dim3(nb), dim3(256), g, c->gas,
+               (const double*)c->fW[l], c->fE[l], (const double*)c->fRm[l], (const double*)c->fGam[l],
+               (const double*)c->dtn_inv[l], col);
+    LAUNCH(c, "fas_apply", 16 * nc8, k_fas4_apply, dim3(nb), dim3(256), g, c->fW[l], c->fE[l]);
 }
 
 // W_l^{n+1} = FAS(l, W_l^n, R_l^n): fW[l] holds W_l^n on entry and the result
@@ -455,32 +459,31 @@ void fas(miugks_ctx* c, int l) {
         F.l0 = l;
         double cells = 0;
         for (int q = l; q < c->L; ++q) cells += c->geo[q].nc;
-        LAUNCH(c, "fas_cycle_block", 60 * cells * 8.0, k_fas_cycle_block, dim3(1), dim3(512), F, c->gas);
+        LAUNCH_SH(c, "fas_cycle_block", 60 * cells * 8.0, c->fas_block_lds[l], k_fas_cycle_block, dim3(1),
+                  dim3(1024), F, c->gas);
         return;
     }
     const Geo& g = c->geo[l];
-    int nb = nblk(g.nc);
+    int nb = nblk(4 * g.nc);
     double nc8 = g.nc * 8.0;
-    LAUNCH(c, "copy", 8 * nc8, k_copy2, dim3(nblk(4 * g.nc)), dim3(256), c->fW[l], c->fW0[l], (double*)nullptr,
-           (const double*)nullptr, (double*)nullptr, 4 * (size_t)g.nc);
-    LAUNCH(c, "fas_gamma", 8 * nc8, k_fas_gamma, dim3(nb), dim3(256), g, c->gas, c->fW[l], c->fGam[l]);
-    LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas_rsplit, dim3(nb), dim3(256), g, c->gas, c->fW[l], c->fGam[l], c->fR[l],
-           -1.0, c->fP[l]);
+    // W0 := W and the frozen Gamma, then the forcing P = R - R_split(W0)
+    LAUNCH(c, "fas_gamma", 16 * nc8, k_fas4_gamma, dim3(nb), dim3(256), g, c->gas, (const double*)c->fW[l],
+           c->fW0[l], c->fGam[l]);
+    LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas4_rsplit, dim3(nb), dim3(256), g, c->gas, (const double*)c->fW[l],
+           (const double*)c->fGam[l], (const double*)c->fR[l], -1.0, c->fP[l]);
     if (l == c->L - 1) {
         for (int i = 0; i < c->nuc; ++i) fas_smooth(c, l);
         return;
     }
     for (int i = 0; i < c->nu1; ++i) fas_smooth(c, l);
     const Geo& gc = c->geo[l + 1];
-    LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas_rsplit, dim3(nb), dim3(256), g, c->gas, c->fW[l], c->fGam[l], c->fP[l],
-           1.0, c->fRm[l]);
-    LAUNCH(c, "fas_restrict", 5 * nc8, k_restrict_cells, dim3(nblk(gc.nc)), dim3(256), g, gc, 4, c->fW[l],
-           c->fW[l + 1]);
-    LAUNCH(c, "fas_restrict", 5 * nc8, k_restrict_cells, dim3(nblk(gc.nc)), dim3(256), g, gc, 4, c->fRm[l],
-           c->fR[l + 1]);
+    LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas4_rsplit, dim3(nb), dim3(256), g, c->gas, (const double*)c->fW[l],
+           (const double*)c->fGam[l], (const double*)c->fP[l], 1.0, c->fRm[l]);
+    LAUNCH(c, "fas_restrict", 10 * nc8, k_fas4_restrict, dim3(nblk(4 * gc.nc)), dim3(256), g, gc,
+           (const double*)c->fW[l], (const double*)c->fRm[l], c->fW[l + 1], c->fR[l + 1]);
     fas(c, l + 1);
-    LAUNCH(c, "fas_prolong", 10 * nc8, k_fas_prolong, dim3(nb), dim3(256), g, gc.nc, c->fW[l + 1], c->fW0[l + 1],
-           c->fW[l]);
+    LAUNCH(c, "fas_prolong", 10 * nc8, k_fas4_prolong, dim3(nb), dim3(256), g, gc.nc, (const double*)c->fW[l + 1],
+           (const double*)c->fW0[l + 1], c->fW[l]);
     for (int i = 0; i < c->nu2; ++i) fas_smooth(c, l);
 }
 
@@ -626,7 +629,14 @@ int build_device(miugks_ctx* ctx) {
         g.ny = h.ny;
         g.nc = h.nc;
         g.n_wall = (int)h.w_cell.size();
-        double *xc, *yc, *dx, *dy, *dcent, *dt, *wT, *wU, *wV, *wden, *pw;
+        double *xc, *yc, *dx, *dy, *dcent, *dt, *wT, *wU, *wV, *wden, *pw, *winvd, *wvol;
+        std::vector<double> hinvd(h.w_cell.size()), hvol(h.w_cell.size());
+        for (size_t j = 0; j < h.w_cell.size(); ++j) {
+            int cc = h.w_cell[j];
+            double ddx = h.dx[cc % h.nx], ddy = h.dy[cc / h.nx];
+            hinvd[j] = 1.0 / (h.w_side[j] < 2 ? ddx : ddy);
+            hvol[j] = ddx * ddy;
+        }
         int *nb, *wc, *ws, *pidx;
         unsigned char* solid;
         if ((rc = upload(ctx, &xc, h.xc)) || (rc = upload(ctx, &yc, h.yc)) || (rc = upload(ctx, &dx, h.dx)) ||
@@ -634,8 +644,11 @@ int build_device(miugks_ctx* ctx) {
             (rc = upload(ctx, &nb, h.nb)) || (rc = upload(ctx, &solid, h.solid)) ||
             (rc = upload(ctx, &wc, h.w_cell)) || (rc = upload(ctx, &ws, h.w_side)) ||
             (rc = upload(ctx, &wT, h.w_T)) || (rc = upload(ctx, &wU, h.w_U)) || (rc = upload(ctx, &wV, h.w_V)) ||
-            (rc = upload(ctx, &wden, h.w_den)) || (rc = upload(ctx, &pidx, h.p_idx)) || (rc = upload(ctx, &pw, h.p_w)))
+            (rc = upload(ctx, &wden, h.w_den)) || (rc = upload(ctx, &pidx, h.p_idx)) || (rc = upload(ctx, &pw, h.p_w)) ||
+            (rc = upload(ctx, &winvd, hinvd)) || (rc = upload(ctx, &wvol, hvol)))
             return rc;
+        g.w_invd = winvd;
+        g.w_vol = wvol;
         g.xc = xc;
         g.yc = yc;
         g.dx = dx;
@@ -731,8 +744,8 @@ int build_device(miugks_ctx* ctx) {
             for (int W : {1, 2, 4}) {
                 if (force_w && W != force_w) continue;
                 size_t need = ctx->prec == MIUGKS_FP64
-                                  ? sweep_wave_lds_bytes<double>(h.nc, h.nx, W, wc.I)
-                                  : sweep_wave_lds_bytes<float>(h.nc, h.nx, W, wc.I);
+                                  ? sweep_wave_lds_bytes<double>(h.nc, h.nx, (int)h.w_cell.size(), W, wc.I)
+                                  : sweep_wave_lds_bytes<float>(h.nc, h.nx, (int)h.w_cell.size(), W, wc.I);
                 if (need > (size_t)max_lds) continue;
                 long per_cu = std::min<long>((long)max_lds / (long)need, 8);
                 long cap = (long)cus * per_cu * W;
@@ -912,8 +925,24 @@ int build_device(miugks_ctx* ctx) {
     {
         int lim = 256;
         if (const char* e = getenv("MIUGKS_FAS_BLOCK_CELLS")) lim = atoi(e);
+        // the levels it takes must also fit in LDS
+        int max_lds = 65536;
+        (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device);
+        ctx->fas_block_lds.assign(ctx->L, 0);
+        size_t acc = 0;
         if (ctx->L <= FAS_MAXL)
-            for (int l = ctx->L - 1; l >= 0 && ctx->hl[l].nc <= lim; --l) ctx->fas_block_l0 = l;
+            for (int l = ctx->L - 1; l >= 0 && ctx->hl[l].nc <= lim; --l) {
+                size_t need = acc + fas_level_lds_bytes(ctx->hl[l].nx, ctx->hl[l].ny);
+                if (need + sizeof(FasSet) + 1024 > (size_t)max_lds) break;   // static LDS beside it
+                acc = need;
+                ctx->fas_block_lds[l] = acc;
+                ctx->fas_block_l0 = l;
+            }
+        if (acc > 65536 &&
+            hipFuncSetAttribute((const void*)k_fas_cycle_block, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)acc) != hipSuccess)
+            for (int l = 0; l < ctx->L; ++l)
+                if (ctx->fas_block_lds[l] > 65536) ctx->fas_block_l0 = std::max(ctx->fas_block_l0, l + 1);
         FasSet& F = ctx->fasset;
         F.L = ctx->L;
         F.nu1 = ctx->nu1;
