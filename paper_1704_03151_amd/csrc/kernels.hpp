@@ -330,6 +330,39 @@ __global__ void k_wall_density(Geo g, Vel vel, const T* __restrict__ G, double* 
     if (lane == 0 && j < g.n_wall) out[j] = -s / g.w_den[j];
 }
 
+// Wall densities of df_fine + I_H^h df_coarse from the G planes, evaluated
+// at the wall cells only (the prolonged correction is needed nowhere else
+// when a sweep follows); one wavefront per wall side
+template <typename T>
+__global__ void k_wall_density_prolonged(Geo g, Vel vel, const T* __restrict__ Gf, int ncc,
+                                         const T* __restrict__ Gc, double* __restrict__ out) {
+    int j = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    int lane = threadIdx.x & 63;
+    double s = 0.0;
+    if (j < g.n_wall) {
+        int c = g.w_cell[j], sd = g.w_side[j];
+        double sign = (sd & 1) ? 1.0 : -1.0;
+        int id[4];
+        T pw[4];
+        for (int a = 0; a < 4; ++a) {
+            id[a] = g.p_idx[a * g.nc + c];
+            pw[a] = T(g.p_w[a * g.nc + c]);
+        }
+        for (int k = lane; k < vel.nk; k += 64) {
+            double un = sign * (sd < 2 ? vel.u[k] : vel.v[k]);
+            if (un > 0) {
+                size_t kc = (size_t)k * ncc;
+                T add = pw[0] * Gc[kc + id[0]] + pw[1] * Gc[kc + id[1]] + pw[2] * Gc[kc + id[2]] +
+                        pw[3] * Gc[kc + id[3]];
+                T G = Gf[(size_t)k * g.nc + c] + add;
+                s += vel.w[k] * un * double(G);
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0 && j < g.n_wall) out[j] = -s / g.w_den[j];
+}
+
 // total mass sum_c V_c rho_c over fluid cells (one block)
 __global__ void k_mass(Geo g, const double* __restrict__ W, double* __restrict__ out) {
     __shared__ double sh[1024];
@@ -1494,17 +1527,21 @@ __device__ __forceinline__ void wave_store(T* __restrict__ dst, const T* src, in
     }
 }
 
-// LDS bytes of k_sweep_wave for W wavefronts of I velocities each
+// LDS bytes of k_sweep_wave for W wavefronts of I velocities each and NP
+// planes (1: G only, 2: G and H)
 template <typename T>
-size_t sweep_wave_lds_bytes(int nc, int nx, int nw, int W, int I) {
-    size_t b = ((size_t)W * 2 * I * nc + nc + nx + 5 * (size_t)nw) * sizeof(T) + 4 * (size_t)nw + (size_t)nc;
+size_t sweep_wave_lds_bytes(int nc, int nx, int nw, int W, int I, int NP) {
+    size_t b = ((size_t)W * NP * I * nc + nc + nx + 5 * (size_t)nw) * sizeof(T) + 4 * (size_t)nw + (size_t)nc;
     return (b + 15) & ~(size_t)15;
 }
 
 // coef = 1/tau + 1/dt_n per cell (-1 on solid cells) in the sweep's type;
 // drho != nullptr: wall densities of the correction before the sweep
-// (nullptr: the correction starts from zero, no ghost terms)
-template <typename T, int R>
+// (nullptr: the correction starts from zero, no ghost terms).  NP = 1 sweeps
+// the G plane only: the sweep reads no earlier correction except through the
+// wall densities, which depend on G alone, so a sweep whose H result is
+// overwritten before use needs only G.
+template <typename T, int R, int NP>
 __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, const T* __restrict__ r,
                                                     T* __restrict__ df, const T* __restrict__ coef_g,
                                                     const unsigned char* __restrict__ stype,
@@ -1513,19 +1550,19 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
     extern __shared__ double smem_d[];
     const int nc = g.nc, nx = g.nx, ny = g.ny, nw = g.n_wall, nk = vel.nk;
     const int W = blockDim.x >> 6, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    T* tiles = (T*)smem_d;                                  // [W][2][I][nc]
-    T* coef = tiles + (size_t)W * 2 * I * nc;               // [nc]
+    T* tiles = (T*)smem_d;                                  // [W][NP][I][nc]
+    T* coef = tiles + (size_t)W * NP * I * nc;              // [nc]
     T* invdx = coef + nc;                                   // [nx]
     T* wl = invdx + nx;                                     // [5][n_wall]  1/d, lam_w, U_w, V_w, drho
     int* wsc = (int*)(wl + 5 * (size_t)nw);                 // [n_wall]  side + 4 cell
     unsigned char* st = (unsigned char*)(wsc + nw);         // [nc]  side types, 2 bits per side
     const int k0 = (blockIdx.x * W + w) * I;                // first velocity of this wavefront
     const int nq = max(0, min(I, nk - k0));                 // velocities it holds
-    T* tw = tiles + (size_t)w * 2 * I * nc;
+    T* tw = tiles + (size_t)w * NP * I * nc;
     // every load of the prologue is issued before the first wait
     if (nq > 0) {
         wave_load_lds<T>(tw, r + (size_t)k0 * nc, nq * nc, lane);
-        wave_load_lds<T>(tw + (size_t)I * nc, r + ((size_t)nk + k0) * nc, nq * nc, lane);
+        if constexpr (NP == 2) wave_load_lds<T>(tw + (size_t)I * nc, r + ((size_t)nk + k0) * nc, nq * nc, lane);
     }
     if (w == 0) wave_load_lds<T>(coef, coef_g, nc, lane);
     if (w == W - 1) wave_load_lds<unsigned char>(st, stype, nc, lane);
@@ -1567,7 +1604,8 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
                         T C = lam / T(M_PI) * dexp(-lam * (du * du + dv * dv));
                         T a = -un * invd;
                         tw[(size_t)q * nc + cell] += a * (C * dr);
-                        tw[((size_t)I + q) * nc + cell] += a * (C * T(K_int) / (T(2) * lam) * dr);
+                        if constexpr (NP == 2)
+                            tw[((size_t)I + q) * nc + cell] += a * (C * T(K_int) / (T(2) * lam) * dr);
                     }
                 }
                 __syncthreads();
@@ -1584,7 +1622,7 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
     const int shx = px ? 0 : 2, shy = py ? 4 : 6;           // bit offset of the upwind x / y side type
     const T au = px ? u : -u, av = py ? v : -v;
     T* tG = tw + (size_t)qq * nc;
-    T* tH = tw + ((size_t)I + qq) * nc;
+    T* tH = tw + ((size_t)(NP == 2 ? I : 0) + qq) * nc;
     int rowc[R];                                            // first cell of the slot's row
     bool rowok[R];
     T by[R], cG[R], cH[R];
@@ -1598,7 +1636,7 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
         nf_sc[p] = st[c];
         nf_idx[p] = invdx[ix];
         nf_rG[p] = tG[c];
-        nf_rH[p] = tH[c];
+        if constexpr (NP == 2) nf_rH[p] = tH[c];
     };
 #pragma unroll
     for (int p = 0; p < R; ++p) {
@@ -1609,6 +1647,7 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
         by[p] = rowok[p] ? av * T(1.0 / g.dy[iy]) : T(0);
         cG[p] = T(0);
         cH[p] = T(0);
+        nf_rH[p] = T(0);
         fetch(p, -row);
     }
     const int nsteps = nx + ny - 1;
@@ -1617,7 +1656,7 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
 #pragma unroll
         for (int p = 0; p < R; ++p) {
             rotG[p] = lane_rotate1(cG[p]);
-            rotH[p] = lane_rotate1(cH[p]);
+            if constexpr (NP == 2) rotH[p] = lane_rotate1(cH[p]);
         }
 #pragma unroll
         for (int p = 0; p < R; ++p) {
@@ -1627,10 +1666,10 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
             unsigned sc = nf_sc[p];
             int c = rowc[p] + (px ? jx : nx - 1 - jx);
             fetch(p, jx + 1);
-            T nbG = rotG[p], nbH = rotH[p];
+            T nbG = rotG[p], nbH = NP == 2 ? rotH[p] : T(0);
             if (R > 1 && lane == 0) {
                 nbG = p > 0 ? rotG[p > 0 ? p - 1 : 0] : T(0);
-                nbH = p > 0 ? rotH[p > 0 ? p - 1 : 0] : T(0);
+                if constexpr (NP == 2) nbH = p > 0 ? rotH[p > 0 ? p - 1 : 0] : T(0);
             }
             unsigned tpx = (sc >> shx) & 3u, tpy = (sc >> shy) & 3u;
             T bx = au * idx, byp = by[p];
@@ -1638,24 +1677,24 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
             // only if it is an outflow (where the two cancel)
             T D = cf + (tpx == 3u ? T(0) : bx) + (tpy == 3u ? T(0) : byp);
             T inv = sweep_rcp(D);
-            T exG = tpx == 0u ? cG[p] : T(0), exH = tpx == 0u ? cH[p] : T(0);
-            T eyG = tpy == 0u ? nbG : T(0), eyH = tpy == 0u ? nbH : T(0);
+            T exG = tpx == 0u ? cG[p] : T(0), eyG = tpy == 0u ? nbG : T(0);
             T vG = (rG + bx * exG + byp * eyG) * inv;
-            T vH = (rH + bx * exH + byp * eyH) * inv;
             vG = cf < T(0) ? T(0) : vG;
-            vH = cf < T(0) ? T(0) : vH;
-            if (valid) {
-                tG[c] = vG;
-                tH[c] = vH;
-            }
+            if (valid) tG[c] = vG;
             cG[p] = vG;
-            cH[p] = vH;
+            if constexpr (NP == 2) {
+                T exH = tpx == 0u ? cH[p] : T(0), eyH = tpy == 0u ? nbH : T(0);
+                T vH = (rH + bx * exH + byp * eyH) * inv;
+                vH = cf < T(0) ? T(0) : vH;
+                if (valid) tH[c] = vH;
+                cH[p] = vH;
+            }
         }
     }
     __syncthreads();
     if (nq > 0) {
         wave_store<T>(df + (size_t)k0 * nc, tw, nq * nc, lane);
-        wave_store<T>(df + ((size_t)nk + k0) * nc, tw + (size_t)I * nc, nq * nc, lane);
+        if constexpr (NP == 2) wave_store<T>(df + ((size_t)nk + k0) * nc, tw + (size_t)I * nc, nq * nc, lane);
         // w_k u_n dG_k at every wall side (zero for u_n <= 0): the
         // per-velocity terms of the next wall densities
         const double ud = lane < nq ? vel.u[k0 + lane] : 0.0, vd = lane < nq ? vel.v[k0 + lane] : 0.0,
@@ -1754,7 +1793,8 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_defect_walls(Geo g, Geo gc, Vel vel, int K_int,
                                                       const int4* __restrict__ cw,
                                                       const double* __restrict__ civol,
-                                                      const double* __restrict__ ddrho, T* __restrict__ rc) {
+                                                      const double* __restrict__ ddrho, T* __restrict__ rc,
+                                                      int planes) {
     Chunk ch = chunk_of(gc.nc, vel.nk);
     if (!ch.valid) return;
     const int C = ch.c;
@@ -1796,7 +1836,7 @@ __global__ void __launch_bounds__(256) k_defect_walls(Geo g, Geo gc, Vel vel, in
         int k = ch.k0 + ch.wave + WAVES * i;
         if (k < ch.k1) {
             rc[(size_t)k * ncc + C] = T(sG[i] * iv);
-            rc[hoc + (size_t)k * ncc + C] = T(sH[i] * iv);
+            if (planes == 2) rc[hoc + (size_t)k * ncc + C] = T(sH[i] * iv);
         }
     }
 }

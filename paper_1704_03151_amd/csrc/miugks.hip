@@ -84,7 +84,7 @@ struct miugks_ctx {
     std::vector<double*> civol, ddrho;
     std::vector<char> last_from_zero;
     CoefSet coefset{};
-    std::vector<WaveCfg> wave;
+    std::vector<WaveCfg> wave, wave1;   // sweeping G and H, G only
     // graphs of Step 1 and Steps 2-7; pseudo-step factor a^{-n}
     bool use_graphs = true;
     bool own_stream = false;
@@ -234,24 +234,22 @@ size_t sweep_lds_bytes(const Geo& g, int P) {
     return (b + 15) & ~(size_t)15;
 }
 
-hipError_t set_wave_lds(int prec, int R, int bytes) {
+template <typename T, int NP>
+hipError_t set_wave_lds_t(int R, int bytes) {
     auto set = [bytes](const void* f) {
         return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     };
-    if (prec == MIUGKS_FP64) {
-        switch (R) {
-            case 1: return set((const void*)k_sweep_wave<double, 1>);
-            case 2: return set((const void*)k_sweep_wave<double, 2>);
-            case 3: return set((const void*)k_sweep_wave<double, 3>);
-            default: return set((const void*)k_sweep_wave<double, 4>);
-        }
-    }
     switch (R) {
-        case 1: return set((const void*)k_sweep_wave<float, 1>);
-        case 2: return set((const void*)k_sweep_wave<float, 2>);
-        case 3: return set((const void*)k_sweep_wave<float, 3>);
-        default: return set((const void*)k_sweep_wave<float, 4>);
+        case 1: return set((const void*)k_sweep_wave<T, 1, NP>);
+        case 2: return set((const void*)k_sweep_wave<T, 2, NP>);
+        case 3: return set((const void*)k_sweep_wave<T, 3, NP>);
+        default: return set((const void*)k_sweep_wave<T, 4, NP>);
     }
+}
+
+hipError_t set_wave_lds(int prec, int R, int np, int bytes) {
+    if (prec == MIUGKS_FP64) return np == 1 ? set_wave_lds_t<double, 1>(R, bytes) : set_wave_lds_t<double, 2>(R, bytes);
+    return np == 1 ? set_wave_lds_t<float, 1>(R, bytes) : set_wave_lds_t<float, 2>(R, bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -326,7 +324,7 @@ struct Path {
     // one smoothing on level l: wall densities from the current correction
     // (skipped when drho is already current), then the ordered sweep, which
     // also leaves the wall products of its result in wbuf
-    static void smooth(miugks_ctx* c, int l, bool drho_current, bool from_zero = false) {
+    static void smooth(miugks_ctx* c, int l, bool drho_current, bool from_zero = false, int np = 2) {
         const Geo& g = c->geo[l];
         c->last_from_zero[l] = from_zero && c->wave[l].W;
         if (!drho_current && g.n_wall)
@@ -335,17 +333,26 @@ struct Path {
         static const char* const names[] = {"sweep/l0", "sweep/l1", "sweep/l2", "sweep/l3",
                                             "sweep/l4", "sweep/l5", "sweep/l6", "sweep/l7"};
         const char* name = names[l < 8 ? l : 7];
-        const miugks_ctx::WaveCfg& wc = c->wave[l];
+        const miugks_ctx::WaveCfg& wc = np == 1 ? c->wave1[l] : c->wave[l];
         if (wc.W) {
-#define MIUGKS_WAVE_LAUNCH(RR)                                                                                 \
-    LAUNCH_SH(c, name, 2 * arr(c, l), wc.lds, (k_sweep_wave<T, RR>), dim3(wc.blocks), dim3(64 * wc.W), g, c->vel, \
-              c->gas.K_int, (const T*)c->r[l], (T*)c->df[l], (const T*)c->coefT[l], c->stype[l],                \
+#define MIUGKS_WAVE_LAUNCH(RR, NP)                                                                              \
+    LAUNCH_SH(c, name, (NP) * arr(c, l), wc.lds, (k_sweep_wave<T, RR, NP>), dim3(wc.blocks), dim3(64 * wc.W), g, \
+              c->vel, c->gas.K_int, (const T*)c->r[l], (T*)c->df[l], (const T*)c->coefT[l], c->stype[l],        \
               from_zero ? (const double*)nullptr : (const double*)c->drho[l], c->wbuf[l], wc.I)
-            switch (wc.R) {
-                case 1: MIUGKS_WAVE_LAUNCH(1); break;
-                case 2: MIUGKS_WAVE_LAUNCH(2); break;
-                case 3: MIUGKS_WAVE_LAUNCH(3); break;
-                default: MIUGKS_WAVE_LAUNCH(4); break;
+            if (np == 1) {
+                switch (wc.R) {
+                    case 1: MIUGKS_WAVE_LAUNCH(1, 1); break;
+                    case 2: MIUGKS_WAVE_LAUNCH(2, 1); break;
+                    case 3: MIUGKS_WAVE_LAUNCH(3, 1); break;
+                    default: MIUGKS_WAVE_LAUNCH(4, 1); break;
+                }
+            } else {
+                switch (wc.R) {
+                    case 1: MIUGKS_WAVE_LAUNCH(1, 2); break;
+                    case 2: MIUGKS_WAVE_LAUNCH(2, 2); break;
+                    case 3: MIUGKS_WAVE_LAUNCH(3, 2); break;
+                    default: MIUGKS_WAVE_LAUNCH(4, 2); break;
+                }
             }
 #undef MIUGKS_WAVE_LAUNCH
         } else if (c->sweep_lds[l]) {
@@ -392,7 +399,7 @@ struct Path {
             else
                 LAUNCH(c, "defect_walls", arr(c, l + 1), k_defect_walls<T>, dim3(ntiles(gc.nc), nchunks(c->nk)),
                        dim3(256), g, gc, c->vel, c->gas.K_int, (const int4*)c->cwall[l + 1],
-                       (const double*)c->civol[l + 1], (const double*)c->ddrho[l], (T*)c->r[l + 1]);
+                       (const double*)c->civol[l + 1], (const double*)c->ddrho[l], (T*)c->r[l + 1], 2);
         } else {
             LAUNCH(c, "defect_restrict", 2 * arr(c, l) + arr(c, l + 1), k_defect_restrict<T>,
                    dim3(ntiles(gc.nc), nchunks(c->nk)), dim3(256), g, gc, c->vel, c->gas.K_int, (const T*)c->r[l],
@@ -407,13 +414,61 @@ struct Path {
         for (int i = 0; i < c->nu2; ++i) smooth(c, l, i == 0);
     }
 
+    // The same V-cycle when every level smooths before and after its coarse
+    // correction.  An ordered sweep recomputes the correction from r and the
+    // wall densities alone, so (i) a sweep whose result is overwritten by a
+    // later sweep needs only its G plane (the wall densities depend on G),
+    // which leaves the final sweep of the finest level as the only one that
+    // sweeps H; (ii) the coarse levels need the G plane of r only; (iii) the
+    // prolonged coarse correction enters only the wall densities of the next
+    // sweep, so it is evaluated at the wall cells only.
+    static bool cs_reduced_ok(miugks_ctx* c) {
+        if (c->nu1 < 1 || c->nu2 < 1 || c->nuc < 1 || getenv("MIUGKS_FULL_CS")) return false;
+        for (int l = 0; l < c->L; ++l)
+            if (!c->wave[l].W) return false;
+        return true;
+    }
+
+    static void cs_reduced(miugks_ctx* c, int l) {
+        const Geo& g = c->geo[l];
+        const bool coarsest = l == c->L - 1;
+        int pre = coarsest ? c->nuc : c->nu1;
+        for (int i = 0; i < pre; ++i) {
+            // the finest level's last sweep is final only if it is also the coarsest
+            int np = (l == 0 && coarsest && i == pre - 1) ? 2 : 1;
+            smooth(c, l, i == 0, i == 0, np);
+        }
+        if (coarsest) return;
+        const Geo& gc = c->geo[l + 1];
+        if (g.n_wall) {
+            LAUNCH(c, "drho", (double)g.n_wall * c->nk * 8, k_drho_delta, dim3((g.n_wall + 3) / 4), dim3(256), g,
+                   c->nk, c->wbuf[l], c->drho[l], c->ddrho[l], (int)c->last_from_zero[l]);
+            LAUNCH(c, "defect_walls", arr(c, l + 1) / 2, k_defect_walls<T>, dim3(ntiles(gc.nc), nchunks(c->nk)),
+                   dim3(256), g, gc, c->vel, c->gas.K_int, (const int4*)c->cwall[l + 1],
+                   (const double*)c->civol[l + 1], (const double*)c->ddrho[l], (T*)c->r[l + 1], 1);
+        } else {
+            size_t n = (size_t)c->nk * gc.nc;
+            LAUNCH(c, "zero", arr(c, l + 1) / 2, k_zero<T>, dim3(nblk((int)std::min<size_t>(n, 1 << 24))), dim3(256),
+                   (T*)c->r[l + 1], n);
+        }
+        cs_reduced(c, l + 1);
+        if (g.n_wall)
+            LAUNCH(c, "wall_density", (double)g.n_wall * c->nk * 5 * sizeof(T), k_wall_density_prolonged<T>,
+                   dim3((g.n_wall + 3) / 4), dim3(256), g, c->vel, (const T*)c->df[l], gc.nc,
+                   (const T*)c->df[l + 1], c->drho[l]);
+        for (int i = 0; i < c->nu2; ++i) smooth(c, l, i == 0, false, (l == 0 && i == c->nu2 - 1) ? 2 : 1);
+    }
+
     static void correct(miugks_ctx* c) {
         for (int l = 0; l + 1 < c->L; ++l)
             LAUNCH(c, "restrict_cells", (c->geo[l].nc + c->geo[l + 1].nc) * 8.0, k_restrict_cells,
                    dim3(nblk(c->geo[l + 1].nc)), dim3(256), c->geo[l], c->geo[l + 1], 1, c->tau_inv[l],
                    c->tau_inv[l + 1]);
         LAUNCH(c, "sweep_coef", 0.0, k_sweep_coef<T>, dim3(nblk(c->geo[0].nc)), dim3(256), c->coefset);
-        cs(c, 0);
+        if (cs_reduced_ok(c))
+            cs_reduced(c, 0);
+        else
+            cs(c, 0);
     }
 
     // Steps 6-7 and the closed-domain renormalisation
@@ -675,6 +730,7 @@ int build_device(miugks_ctx* ctx) {
     ctx->sweep_lds.assign(ctx->L, 0);
     ctx->stype.assign(ctx->L, nullptr);
     ctx->wave.assign(ctx->L, miugks_ctx::WaveCfg());
+    ctx->wave1.assign(ctx->L, miugks_ctx::WaveCfg());
     size_t need_max = 0, wave_need_max = 0;
     for (int l = 0; l < ctx->L; ++l) {
         HostLevel& h = ctx->hl[l];
@@ -735,40 +791,46 @@ int build_device(miugks_ctx* ctx) {
         // wavefront sweep: W wavefronts of I velocities per block, W taken
         // for the fewest rounds of blocks over the chip (ties: smaller W)
         if (!getenv("MIUGKS_NO_WAVE_SWEEP") && h.ny <= 256) {
-            miugks_ctx::WaveCfg wc;
-            wc.I = h.ny <= 32 ? 64 / h.ny : 1;
-            wc.R = (h.ny + 63) / 64;
-            int nwaves = (ctx->nk + wc.I - 1) / wc.I;
-            long best_rounds = 0;
-            int force_w = getenv("MIUGKS_WAVE_W") ? atoi(getenv("MIUGKS_WAVE_W")) : 0;
-            for (int W : {1, 2, 4}) {
-                if (force_w && W != force_w) continue;
-                size_t need = ctx->prec == MIUGKS_FP64
-                                  ? sweep_wave_lds_bytes<double>(h.nc, h.nx, (int)h.w_cell.size(), W, wc.I)
-                                  : sweep_wave_lds_bytes<float>(h.nc, h.nx, (int)h.w_cell.size(), W, wc.I);
-                if (need > (size_t)max_lds) continue;
-                long per_cu = std::min<long>((long)max_lds / (long)need, 8);
-                long cap = (long)cus * per_cu * W;
-                long rounds = (nwaves + cap - 1) / cap;
-                if (!wc.W || rounds < best_rounds) {
-                    wc.W = W;
-                    wc.lds = need;
-                    best_rounds = rounds;
+            for (int np = 1; np <= 2; ++np) {
+                miugks_ctx::WaveCfg wc;
+                wc.I = h.ny <= 32 ? 64 / h.ny : 1;
+                wc.R = (h.ny + 63) / 64;
+                int nwaves = (ctx->nk + wc.I - 1) / wc.I;
+                long best_rounds = 0;
+                int force_w = getenv("MIUGKS_WAVE_W") ? atoi(getenv("MIUGKS_WAVE_W")) : 0;
+                for (int W : {1, 2, 4}) {
+                    if (force_w && W != force_w) continue;
+                    size_t need =
+                        ctx->prec == MIUGKS_FP64
+                            ? sweep_wave_lds_bytes<double>(h.nc, h.nx, (int)h.w_cell.size(), W, wc.I, np)
+                            : sweep_wave_lds_bytes<float>(h.nc, h.nx, (int)h.w_cell.size(), W, wc.I, np);
+                    if (need > (size_t)max_lds) continue;
+                    long per_cu = std::min<long>((long)max_lds / (long)need, 8);
+                    long cap = (long)cus * per_cu * W;
+                    long rounds = (nwaves + cap - 1) / cap;
+                    if (!wc.W || rounds < best_rounds) {
+                        wc.W = W;
+                        wc.lds = need;
+                        best_rounds = rounds;
+                    }
+                }
+                if (wc.W) {
+                    wc.blocks = (nwaves + wc.W - 1) / wc.W;
+                    (np == 2 ? ctx->wave : ctx->wave1)[l] = wc;
+                    wave_need_max = std::max(wave_need_max, wc.lds);
                 }
             }
-            if (wc.W) {
-                wc.blocks = (nwaves + wc.W - 1) / wc.W;
-                ctx->wave[l] = wc;
-                wave_need_max = std::max(wave_need_max, wc.lds);
-            }
+            // both forms or neither
+            if (!ctx->wave[l].W || !ctx->wave1[l].W) ctx->wave[l].W = ctx->wave1[l].W = 0;
         }
     }
     if (wave_need_max > 65536) {
         hipError_t e = hipSuccess;
-        for (int R = 1; R <= 4 && e == hipSuccess; ++R) e = set_wave_lds(ctx->prec, R, (int)wave_need_max);
+        for (int R = 1; R <= 4 && e == hipSuccess; ++R)
+            for (int np = 1; np <= 2 && e == hipSuccess; ++np) e = set_wave_lds(ctx->prec, R, np, (int)wave_need_max);
         if (e != hipSuccess)
             for (int l = 0; l < ctx->L; ++l)
-                if (ctx->wave[l].lds > 65536) ctx->wave[l].W = 0;
+                if (ctx->wave[l].lds > 65536 || ctx->wave1[l].lds > 65536) ctx->wave[l].W = ctx->wave1[l].W = 0;
     }
     if (need_max > 65536) {
         hipError_t e = ctx->prec == MIUGKS_FP64
