@@ -34,7 +34,11 @@ HBM_PEAK_GBS = 8000.0
 # scaled by the ratio of known bytes to counted bytes of a plain copy in the
 # same run (--copy-calibration).  Keyed by (workload, precision, kernel); an
 # entry is dropped whenever that kernel changes.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # profiles/sweep_wave_cavity64_fp32f_hbm_traffic.md: 133 dispatches of the
+    # sweep (18 G-only and 1 G+H per cycle), scaled FETCH_SIZE + WRITE_SIZE
+    ("cavity64_kn0.075", "fp32f", "sweep"): 8.04e6,
+}
 
 
 def cpu_baseline(case, cycles):
@@ -121,11 +125,10 @@ def main():
                    "gbs": (v[2] / (v[1] * 1e-3) / 1e9 if v[1] > 0 else None)}
                for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
     traffic = MEASURED_TRAFFIC.get((case.name, args.precision, dom))
-    if traffic is not None:
-        traffic = dict(traffic, frac_of_algorithmic=traffic["bytes_per_launch"] / (by / launches))
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "bytes_per_launch": by / launches, "mean_launch_ms": ms / launches}
+                "bytes_per_launch": by / launches, "mean_launch_ms": ms / launches,
+                "traffic_over_algorithmic": (traffic / (by / launches)) if traffic else None}
     print(f"[bench] dominant kernel {dom}: {ms / launches * 1e3:.1f} us/launch, {achieved:.0f} GB/s",
           file=sys.stderr, flush=True)
 

@@ -118,6 +118,46 @@ def test_step5_cs_correction(name):
     assert rel_max(gG, dG) < 1e-11 and rel_max(gH, dH) < 1e-11, (rel_max(gG, dG), rel_max(gH, dH))
 
 
+@pytest.mark.parametrize("name", ["cavity16_kn10", "square20x20", "plate32x24"])
+def test_step5_reduced_and_full_v_cycles_agree(name, monkeypatch):
+    """The V-cycle that sweeps H only in its final sweep and prolongs at
+    wall cells only gives the full V-cycle's correction."""
+    case, gpu, orc = pair(name)
+    fl = orc.lev0.fluid
+    r = wl.random_field((2, case.n_vel, case.ny, case.nx), seed=31) * fl.reshape(case.ny, case.nx)
+    ti = wl.random_field((case.ny, case.nx), seed=37, lo=0.5, hi=3.0)
+    gpu.init_macro(case.init)
+    reduced = gpu.correct(r, ti)
+    monkeypatch.setenv("MIUGKS_FULL_CS", "1")
+    gpu.init_macro(case.init)
+    full = gpu.correct(r, ti)
+    monkeypatch.delenv("MIUGKS_FULL_CS")
+    assert rel_max(reduced[0], full[0]) < 1e-12 and rel_max(reduced[1], full[1]) < 1e-12
+
+
+@pytest.mark.parametrize("nu1,nu2", [(0, 1), (2, 0), (1, 2)])
+def test_step5_other_smoothing_counts(nu1, nu2):
+    """The CS V-cycle with other pre/post smoothing counts (including none,
+    which takes the general path) against the oracle."""
+    from paper_1704_03151_amd import Solver
+    case = CASES["square20x20"].with_(nu1=nu1, nu2=nu2)
+    print(f"[parity] square20x20 nu1={nu1} nu2={nu2}", flush=True)
+    gpu = Solver(case, precision="fp64")
+    orc = Oracle(case)
+    fl = orc.lev0.fluid
+    r = wl.random_field((2, case.n_vel, case.ny, case.nx), seed=41) * fl.reshape(case.ny, case.nx)
+    ti = wl.random_field((case.ny, case.nx), seed=43, lo=0.5, hi=3.0)
+    orc.cycle = 0
+    gpu.init_macro(case.init)
+    out = gpu.correct(r, ti)
+    rG, rH = to_oracle(r)
+    dG, dH = cs_cycle(orc.cs_levels, orc.levels, orc.prolongs, 0, rG, rH,
+                      orc.level_tau_inv(ti.ravel() * fl), orc.dtn_inv(), orc.params)
+    gG, gH = to_oracle(out)
+    assert rel_max(gG, dG) < 1e-11 and rel_max(gH, dH) < 1e-11, (rel_max(gG, dG), rel_max(gH, dH))
+    gpu.close()
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_full_cycles_trajectory(name):
     """Rows a1-a6 together: three outer cycles from the initial state."""
