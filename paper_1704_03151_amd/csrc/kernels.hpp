@@ -153,7 +153,7 @@ __device__ __forceinline__ void time_coeffs(double dt, double tau, double* q) {
 // helpers shared by the chunked kernels
 
 struct Chunk {
-    int c, lane, wave, k0, k1;
+    int c, lane, wave, k0, k1, chunk;
     bool valid;
 };
 
@@ -165,6 +165,35 @@ __device__ __forceinline__ Chunk chunk_of(int nc, int nk) {
     ch.valid = ch.c < nc;
     ch.k0 = blockIdx.y * KCH;
     ch.k1 = min(nk, ch.k0 + KCH);
+    ch.chunk = blockIdx.y;
+    return ch;
+}
+
+// The chip dispatches workgroup b of a launch to XCD b mod 8, each XCD with
+// its own L2.  Logical block of workgroup b such that every XCD takes a
+// contiguous range of logical blocks (a bijection of [0, nb)).
+__device__ __forceinline__ int xcd_swizzle(int b, int nb) {
+    constexpr int X = 8;
+    int q = nb / X, r = nb % X;
+    int x = b % X, i = b / X;
+    return x * q + min(x, r) + i;
+}
+
+// chunk_of for kernels whose stencil reaches the rows above and below: the
+// tiles of one velocity chunk are spread over as few XCDs as possible, so
+// the neighbouring rows of a tile are found in the same L2
+__device__ __forceinline__ Chunk chunk_of_xcd(int nc, int nk) {
+    int nt = gridDim.x, nb = gridDim.x * gridDim.y;
+    int Lb = xcd_swizzle(blockIdx.x + nt * blockIdx.y, nb);
+    int tile = Lb % nt, chunk = Lb / nt;
+    Chunk ch;
+    ch.lane = threadIdx.x & (TILE - 1);
+    ch.wave = threadIdx.x / TILE;
+    ch.c = tile * TILE + ch.lane;
+    ch.valid = ch.c < nc;
+    ch.k0 = chunk * KCH;
+    ch.k1 = min(nk, ch.k0 + KCH);
+    ch.chunk = chunk;
     return ch;
 }
 
@@ -172,7 +201,8 @@ __device__ __forceinline__ Chunk chunk_of(int nc, int nk) {
 // part[(chunk * M + m) * n + i]
 template <int M>
 __device__ __forceinline__ void reduce_store(double* acc, double* sh, double* part, int n, int i,
-                                             bool valid) {
+                                             bool valid, int chunk = -1) {
+    if (chunk < 0) chunk = blockIdx.y;
     int lane = threadIdx.x & (TILE - 1), wave = threadIdx.x / TILE;
     for (int m = 0; m < M; ++m) sh[(m * WAVES + wave) * TILE + lane] = acc[m];
     __syncthreads();
@@ -180,7 +210,7 @@ __device__ __forceinline__ void reduce_store(double* acc, double* sh, double* pa
         for (int m = 0; m < M; ++m) {
             double s = sh[(m * WAVES + 0) * TILE + lane];
             for (int w = 1; w < WAVES; ++w) s += sh[(m * WAVES + w) * TILE + lane];
-            part[((size_t)blockIdx.y * M + m) * n + i] = s;
+            part[((size_t)chunk * M + m) * n + i] = s;
         }
     }
 }
@@ -438,6 +468,54 @@ __device__ __forceinline__ bool face_geom(const Geo& g, int c, int d, FaceGeom<A
     return true;
 }
 
+// the stored values a face reconstruction reads for one velocity: L and the
+// cell c, L's far neighbour LL and c's far neighbour RR (zero when absent)
+template <typename T>
+struct FaceVals {
+    T GL, GR, HL, HR, GLL, HLL, GRR, HRR;
+};
+
+template <typename T, typename A>
+__device__ __forceinline__ void face_load(const FaceGeom<A>& fg, int c, const T* __restrict__ F, size_t ho,
+                                          size_t kc, FaceVals<T>& q) {
+    q.GL = F[kc + fg.L];
+    q.GR = F[kc + c];
+    q.HL = F[ho + kc + fg.L];
+    q.HR = F[ho + kc + c];
+    q.GLL = fg.LL >= 0 ? F[kc + fg.LL] : T(0);
+    q.HLL = fg.LL >= 0 ? F[ho + kc + fg.LL] : T(0);
+    q.GRR = fg.RR >= 0 ? F[kc + fg.RR] : T(0);
+    q.HRR = fg.RR >= 0 ? F[ho + kc + fg.RR] : T(0);
+}
+
+// face_upwind_k on values already loaded
+template <typename T, typename A>
+__device__ __forceinline__ void face_upwind_vals(const FaceGeom<A>& fg, const FaceVals<T>& q, A un, A& Gup,
+                                                 A& Hup, A& sGup, A& sHup) {
+    A GL = A(q.GL), GR = A(q.GR), HL = A(q.HL), HR = A(q.HR);
+    A gLR = (GR - GL) * fg.idc, hLR = (HR - HL) * fg.idc;
+    A gm = fg.LL >= 0 ? (GL - A(q.GLL)) * fg.idcL : A(0), hm = fg.LL >= 0 ? (HL - A(q.HLL)) * fg.idcL : A(0);
+    A gp = fg.RR >= 0 ? (A(q.GRR) - GR) * fg.idcR : A(0), hp = fg.RR >= 0 ? (A(q.HRR) - HR) * fg.idcR : A(0);
+    A sGL = un >= A(0) ? van_leer_fast(gm, gLR) : A(0), sHL = un >= A(0) ? van_leer_fast(hm, hLR) : A(0);
+    A sGR = un <= A(0) ? van_leer_fast(gLR, gp) : A(0), sHR = un <= A(0) ? van_leer_fast(hLR, hp) : A(0);
+    if (un > A(0)) {
+        Gup = GL + sGL * fg.dL;
+        Hup = HL + sHL * fg.dL;
+        sGup = sGL;
+        sHup = sHL;
+    } else if (un < A(0)) {
+        Gup = GR - sGR * fg.dR;
+        Hup = HR - sHR * fg.dR;
+        sGup = sGR;
+        sHup = sHR;
+    } else {
+        Gup = A(0.5) * (GL + sGL * fg.dL + GR - sGR * fg.dR);
+        Hup = A(0.5) * (HL + sHL * fg.dL + HR - sHR * fg.dR);
+        sGup = A(0.5) * (sGL + sGR);
+        sHup = A(0.5) * (sHL + sHR);
+    }
+}
+
 // limited slopes and upwind interface values of one velocity (row offset kc
 // into the G plane, ho = offset of the H plane) at an interior face
 template <typename T, typename A>
@@ -545,7 +623,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_face_moments_partial(Geo g, Vel vel, const T* __restrict__ f,
                                                               double* __restrict__ part) {
     __shared__ double sh[2 * NRAW * WAVES * TILE];
-    Chunk ch = chunk_of(g.nc, vel.nk);
+    Chunk ch = chunk_of_xcd(g.nc, vel.nk);
     double a[2 * NRAW];
     for (int m = 0; m < 2 * NRAW; ++m) a[m] = 0.0;
     if (ch.valid && !g.solid[ch.c]) {
@@ -561,7 +639,7 @@ __global__ void __launch_bounds__(256) k_face_moments_partial(Geo g, Vel vel, co
             }
         }
     }
-    reduce_store<2 * NRAW>(a, sh, part, g.nc, ch.c, ch.valid);
+    reduce_store<2 * NRAW>(a, sh, part, g.nc, ch.c, ch.valid, ch.chunk);
 }
 
 // Reductions over all velocities inside one block: 64 lanes (consecutive
@@ -1008,14 +1086,20 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
                     size_t stride = 2 * nc;
                     A P[23];
                     for (int m = 0; m < 23; ++m) P[m] = A(rec[m * stride]);
-                    FaceGeom<A> fg;
-                    face_geom<A>(g, R, d, fg);
+                    FaceGeom<T> fg;
+                    face_geom<T>(g, R, d, fg);
+                    // the stencil values of the next velocity load while this one computes
+                    FaceVals<T> cur{}, nxt{};
+                    face_load<T, T>(fg, R, f, ho, (size_t)kk[0] * nc, nxt);
                     for (int j = 0; j < nmine; ++j) {
                         int k = kk[j];
+                        cur = nxt;
+                        if (j + 1 < nmine) face_load<T, T>(fg, R, f, ho, (size_t)kk[j + 1] * nc, nxt);
                         A u = vel.u[k], v = vel.v[k];
                         A un = d == 0 ? u : v;
-                        A Gup, Hup, sGu, sHu, PG, PH;
-                        face_upwind_k<T, A>(fg, R, f, ho, (size_t)k * nc, un, Gup, Hup, sGu, sHu);
+                        T Gu, Hu, sGt, sHt;
+                        face_upwind_vals<T, T>(fg, cur, T(un), Gu, Hu, sGt, sHt);
+                        A Gup = Gu, Hup = Hu, sGu = sGt, sHu = sHt, PG, PH;
                         face_flux<A>(P, u, v, un, Gup, Hup, sGu, sHu, gas.K_int, PG, PH);
                         dG[j] += sign * sv * PG;
                         dH[j] += sign * sv * PH;
@@ -1073,6 +1157,37 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
         }
     }
     reduce_store<4>(acc, sh, part, g.nc, c, ch.valid);
+}
+
+// outward flux u_n ftilde through the non-interior side s (code < 0) of a
+// fluid cell c for velocity k: at a wall the outgoing f and the incoming
+// rho_w C_k, at a farfield side the incoming freestream, else f
+template <typename T, typename A>
+__device__ __forceinline__ void boundary_flux(const Geo& g, const Vel& vel, const Gas& gas, const T* __restrict__ f,
+                                              const double* __restrict__ rho_w, const T* __restrict__ finf, int c,
+                                              int s, int code, int k, A& oG, A& oH) {
+    const size_t nc = g.nc, ho = (size_t)vel.nk * nc;
+    int d = s >> 1;
+    A sign = (s & 1) ? A(1) : A(-1);
+    A u = vel.u[k], v = vel.v[k];
+    A un = sign * (d == 0 ? u : v);
+    A Gf, Hf;
+    if (is_wall(code) && !(un > A(0))) {
+        int jw = wall_of(code);
+        A lam = A(1.0 / g.w_T[jw]), du = u - A(g.w_U[jw]), dv = v - A(g.w_V[jw]);
+        A C = lam / A(M_PI) * dexp(-lam * (du * du + dv * dv));
+        A rw = A(rho_w[jw]);
+        Gf = rw * C;
+        Hf = rw * A(gas.K_int) / (A(2) * lam) * C;
+    } else if (code == NB_FARFIELD && un <= A(0)) {
+        Gf = A(finf[k]);
+        Hf = A(finf[vel.nk + k]);
+    } else {
+        Gf = A(f[(size_t)k * nc + c]);
+        Hf = A(f[ho + (size_t)k * nc + c]);
+    }
+    oG = un * Gf;
+    oH = un * Hf;
 }
 
 __global__ void k_residual_finalize(Geo g, const double* __restrict__ part, int nkc, double* __restrict__ R) {
