@@ -1361,7 +1361,8 @@ __device__ __forceinline__ T wall_ghost_j(const Geo& g, int j, T u, T v, int K_i
 }
 
 // After a sweep: w_k u_n dG_k at every wall side for this velocity (zero for
-// u_n <= 0), the per-velocity terms of the next wall densities
+// u_n <= 0), the per-velocity terms of the next wall densities, stored
+// velocity-major: wbuf[k][j] (the per-velocity partial sums of k_drho)
 template <typename T>
 __device__ __forceinline__ void wall_products(const Geo& g, const Vel& vel, int k, const T* Gk,
                                               double* __restrict__ wbuf, int tid, int nthr) {
@@ -1369,7 +1370,7 @@ __device__ __forceinline__ void wall_products(const Geo& g, const Vel& vel, int 
     for (int j = tid; j < g.n_wall; j += nthr) {
         int s = g.w_side[j];
         double un = ((s & 1) ? 1.0 : -1.0) * (s < 2 ? u : v);
-        wbuf[(size_t)j * vel.nk + k] = un > 0.0 ? w * un * double(Gk[g.w_cell[j]]) : 0.0;
+        wbuf[(size_t)k * g.n_wall + j] = un > 0.0 ? w * un * double(Gk[g.w_cell[j]]) : 0.0;
     }
 }
 
@@ -1642,11 +1643,22 @@ __device__ __forceinline__ void wave_store(T* __restrict__ dst, const T* src, in
     }
 }
 
+// wall sides of a level that k_sweep_wave handles
+constexpr int SWEEP_WAVE_MAX_WALLS = 512;
+
 // LDS bytes of k_sweep_wave for W wavefronts of I velocities each and NP
 // planes (1: G only, 2: G and H)
+// (the tile region also holds the per-wavefront wall sums of the epilogue)
+template <typename T>
+__host__ __device__ inline size_t sweep_wave_tiles_elems(int nc, int nw, int W, int I, int NP) {
+    size_t t = (size_t)W * NP * I * nc, red = ((size_t)W * nw * sizeof(double) + sizeof(T) - 1) / sizeof(T);
+    return t > red ? t : red;
+}
+
 template <typename T>
 size_t sweep_wave_lds_bytes(int nc, int nx, int nw, int W, int I, int NP) {
-    size_t b = ((size_t)W * NP * I * nc + nc + nx + 5 * (size_t)nw) * sizeof(T) + 4 * (size_t)nw + (size_t)nc;
+    size_t b = (sweep_wave_tiles_elems<T>(nc, nw, W, I, NP) + nc + nx + 5 * (size_t)nw) * sizeof(T) +
+               4 * (size_t)nw + (size_t)nc;
     return (b + 15) & ~(size_t)15;
 }
 
@@ -1656,17 +1668,22 @@ size_t sweep_wave_lds_bytes(int nc, int nx, int nw, int W, int I, int NP) {
 // the G plane only: the sweep reads no earlier correction except through the
 // wall densities, which depend on G alone, so a sweep whose H result is
 // overwritten before use needs only G.
+// Epilogue: the block's sums over its velocities of w_k u_n dG_k at every
+// wall side (u_n > 0) go to wpart[block][j], the partial sums of the next
+// wall densities.
 template <typename T, int R, int NP>
 __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, const T* __restrict__ r,
                                                     T* __restrict__ df, const T* __restrict__ coef_g,
                                                     const unsigned char* __restrict__ stype,
-                                                    const double* __restrict__ drho, double* __restrict__ wbuf,
+                                                    const double* __restrict__ drho, double* __restrict__ wpart,
                                                     int I) {
-    extern __shared__ double smem_d[];
+    // (no static LDS in this kernel: the tiles must start 16-byte aligned
+    // for the direct global-to-LDS loads)
+    extern __shared__ __attribute__((aligned(16))) double smem_d[];
     const int nc = g.nc, nx = g.nx, ny = g.ny, nw = g.n_wall, nk = vel.nk;
     const int W = blockDim.x >> 6, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     T* tiles = (T*)smem_d;                                  // [W][NP][I][nc]
-    T* coef = tiles + (size_t)W * NP * I * nc;              // [nc]
+    T* coef = tiles + sweep_wave_tiles_elems<T>(nc, nw, W, I, NP);   // [nc]
     T* invdx = coef + nc;                                   // [nx]
     T* wl = invdx + nx;                                     // [5][n_wall]  1/d, lam_w, U_w, V_w, drho
     int* wsc = (int*)(wl + 5 * (size_t)nw);                 // [n_wall]  side + 4 cell
@@ -1810,31 +1827,49 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
     if (nq > 0) {
         wave_store<T>(df + (size_t)k0 * nc, tw, nq * nc, lane);
         if constexpr (NP == 2) wave_store<T>(df + ((size_t)nk + k0) * nc, tw + (size_t)I * nc, nq * nc, lane);
-        // w_k u_n dG_k at every wall side (zero for u_n <= 0): the
-        // per-velocity terms of the next wall densities
-        const double ud = lane < nq ? vel.u[k0 + lane] : 0.0, vd = lane < nq ? vel.v[k0 + lane] : 0.0,
-                     wd = lane < nq ? vel.w[k0 + lane] : 0.0;
-        for (int jb = 0; jb < nw; jb += 64) {
-            const int j = jb + lane;
-            const bool ok = j < nw;
-            const int sd = ok ? wsc[j] & 3 : 0, cell = ok ? wsc[j] >> 2 : 0;
+    }
+    // per-wavefront sums over its velocities of w_k u_n dG_k at the wall sides
+    const double ud = lane < nq ? vel.u[k0 + lane] : 0.0, vd = lane < nq ? vel.v[k0 + lane] : 0.0,
+                 wd = lane < nq ? vel.w[k0 + lane] : 0.0;
+    // (at most SWEEP_WAVE_MAX_WALLS wall sides: one register per 64 of them)
+    double wsum[SWEEP_WAVE_MAX_WALLS / 64];
+#pragma unroll
+    for (int jc = 0; jc < SWEEP_WAVE_MAX_WALLS / 64; ++jc) {
+        const int j = jc * 64 + lane;
+        const bool ok = j < nw;
+        const int sd = ok ? wsc[j] & 3 : 0, cell = ok ? wsc[j] >> 2 : 0;
+        double sum = 0.0;
+        if (jc * 64 < nw)
             for (int qv = 0; qv < nq; ++qv) {
                 double uu = __shfl(ud, qv, 64), vv = __shfl(vd, qv, 64), ww = __shfl(wd, qv, 64);
                 double un = ((sd & 1) ? 1.0 : -1.0) * (sd < 2 ? uu : vv);
-                if (ok)
-                    wbuf[(size_t)j * nk + k0 + qv] = un > 0.0 ? ww * un * double(tw[(size_t)qv * nc + cell]) : 0.0;
+                if (ok && un > 0.0) sum += ww * un * double(tw[(size_t)qv * nc + cell]);
             }
-        }
+        wsum[jc] = sum;
+    }
+    __syncthreads();   // every tile is read: the sums go where the tiles were
+    double* red = (double*)tiles;   // [W][n_wall]
+#pragma unroll
+    for (int jc = 0; jc < SWEEP_WAVE_MAX_WALLS / 64; ++jc) {
+        const int j = jc * 64 + lane;
+        if (j < nw) red[(size_t)w * nw + j] = wsum[jc];
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < nw; j += blockDim.x) {
+        double s = 0.0;
+        for (int ww = 0; ww < W; ++ww) s += red[(size_t)ww * nw + j];
+        wpart[(size_t)blockIdx.x * nw + j] = s;
     }
 }
 
-// drho_w = -sum_k wbuf[j][k] / den_j: one wavefront per wall side
-__global__ void k_drho(Geo g, int nk, const double* __restrict__ wbuf, double* __restrict__ drho) {
+// drho_w = -sum_b wpart[b][j] / den_j over the partial sums of the last sweep
+// (per block or per velocity), in part order: one wavefront per wall side
+__global__ void k_drho(Geo g, int nparts, const double* __restrict__ wpart, double* __restrict__ drho) {
     int j = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
     int lane = threadIdx.x & 63;
     double s = 0.0;
     if (j < g.n_wall)
-        for (int k = lane; k < nk; k += 64) s += wbuf[(size_t)j * nk + k];
+        for (int b = lane; b < nparts; b += 64) s += wpart[(size_t)b * g.n_wall + j];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if (lane == 0 && j < g.n_wall) drho[j] = -s / g.w_den[j];
 }
@@ -1881,15 +1916,15 @@ __global__ void __launch_bounds__(256) k_defect_restrict(Geo g, Geo gc, Vel vel,
     }
 }
 
-// drho_w = -sum_k wbuf[j][k] / den_j as k_drho, also keeping the change from
+// drho_w as k_drho, also keeping the change from
 // the densities the last sweep used (old_zero: that sweep used zero)
-__global__ void k_drho_delta(Geo g, int nk, const double* __restrict__ wbuf, double* __restrict__ drho,
+__global__ void k_drho_delta(Geo g, int nparts, const double* __restrict__ wpart, double* __restrict__ drho,
                              double* __restrict__ ddrho, int old_zero) {
     int j = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
     int lane = threadIdx.x & 63;
     double s = 0.0;
     if (j < g.n_wall)
-        for (int k = lane; k < nk; k += 64) s += wbuf[(size_t)j * nk + k];
+        for (int b = lane; b < nparts; b += 64) s += wpart[(size_t)b * g.n_wall + j];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if (lane == 0 && j < g.n_wall) {
         double d = -s / g.w_den[j];

@@ -81,6 +81,8 @@ struct miugks_ctx {
     // the fine wall list under it and its inverse fluid volume; the change of
     // the wall densities since the last sweep
     std::vector<int4*> cwall;
+    // number of wall-product partial sums the last sweep of each level left
+    std::vector<int> wparts;
     std::vector<double*> civol, ddrho;
     std::vector<char> last_from_zero;
     CoefSet coefset{};
@@ -328,8 +330,8 @@ struct Path {
         const Geo& g = c->geo[l];
         c->last_from_zero[l] = from_zero && c->wave[l].W;
         if (!drho_current && g.n_wall)
-            LAUNCH(c, "drho", (double)g.n_wall * c->nk * 8, k_drho, dim3((g.n_wall + 3) / 4), dim3(256), g, c->nk,
-                   c->wbuf[l], c->drho[l]);
+            LAUNCH(c, "drho", (double)g.n_wall * c->wparts[l] * 8, k_drho, dim3((g.n_wall + 3) / 4), dim3(256), g,
+                   c->wparts[l], c->wbuf[l], c->drho[l]);
         static const char* const names[] = {"sweep/l0", "sweep/l1", "sweep/l2", "sweep/l3",
                                             "sweep/l4", "sweep/l5", "sweep/l6", "sweep/l7"};
         const char* name = names[l < 8 ? l : 7];
@@ -339,6 +341,7 @@ struct Path {
     LAUNCH_SH(c, name, (NP) * arr(c, l), wc.lds, (k_sweep_wave<T, RR, NP>), dim3(wc.blocks), dim3(64 * wc.W), g, \
               c->vel, c->gas.K_int, (const T*)c->r[l], (T*)c->df[l], (const T*)c->coefT[l], c->stype[l],        \
               from_zero ? (const double*)nullptr : (const double*)c->drho[l], c->wbuf[l], wc.I)
+            c->wparts[l] = wc.blocks;
             if (np == 1) {
                 switch (wc.R) {
                     case 1: MIUGKS_WAVE_LAUNCH(1, 1); break;
@@ -356,12 +359,14 @@ struct Path {
             }
 #undef MIUGKS_WAVE_LAUNCH
         } else if (c->sweep_lds[l]) {
+            c->wparts[l] = c->nk;
             int npad = ((g.ny + 63) / 64) * 64, P = c->sweep_lds[l];
             int blocks = (2 * c->nk + P - 1) / P;
             LAUNCH_SH(c, name, 2 * arr(c, l), sweep_lds_bytes<T>(g, P), k_sweep_lds<T>, dim3(blocks), dim3(P * npad),
                       g, c->vel, c->gas.K_int, (const T*)c->r[l], (T*)c->df[l], c->tau_inv[l], c->dtn_inv[l],
                       c->flags[l], c->drho[l], c->wbuf[l], npad, P);
         } else {
+            c->wparts[l] = c->nk;
             int threads = ((g.ny + 63) / 64) * 64;
             LAUNCH(c, name, 2 * arr(c, l), k_sweep<T>, dim3(c->nk), dim3(threads), g, c->vel, c->gas.K_int,
                    (const T*)c->r[l], (T*)c->df[l], c->tau_inv[l], c->dtn_inv[l], c->flags[l], c->drho[l],
@@ -386,8 +391,8 @@ struct Path {
             LAUNCH(c, "zero", arr(c, l), k_zero<T>, dim3(nblk((int)std::min<size_t>(n, 1 << 24))), dim3(256),
                    (T*)c->df[l], n);
         } else if (g.n_wall) {
-            LAUNCH(c, "drho", (double)g.n_wall * c->nk * 8, k_drho_delta, dim3((g.n_wall + 3) / 4), dim3(256), g,
-                   c->nk, c->wbuf[l], c->drho[l], c->ddrho[l], (int)c->last_from_zero[l]);
+            LAUNCH(c, "drho", (double)g.n_wall * c->wparts[l] * 8, k_drho_delta, dim3((g.n_wall + 3) / 4),
+                   dim3(256), g, c->wparts[l], c->wbuf[l], c->drho[l], c->ddrho[l], (int)c->last_from_zero[l]);
         }
         const Geo& gc = c->geo[l + 1];
         if (pre > 0) {
@@ -441,8 +446,8 @@ struct Path {
         if (coarsest) return;
         const Geo& gc = c->geo[l + 1];
         if (g.n_wall) {
-            LAUNCH(c, "drho", (double)g.n_wall * c->nk * 8, k_drho_delta, dim3((g.n_wall + 3) / 4), dim3(256), g,
-                   c->nk, c->wbuf[l], c->drho[l], c->ddrho[l], (int)c->last_from_zero[l]);
+            LAUNCH(c, "drho", (double)g.n_wall * c->wparts[l] * 8, k_drho_delta, dim3((g.n_wall + 3) / 4),
+                   dim3(256), g, c->wparts[l], c->wbuf[l], c->drho[l], c->ddrho[l], (int)c->last_from_zero[l]);
             LAUNCH(c, "defect_walls", arr(c, l + 1) / 2, k_defect_walls<T>, dim3(ntiles(gc.nc), nchunks(c->nk)),
                    dim3(256), g, gc, c->vel, c->gas.K_int, (const int4*)c->cwall[l + 1],
                    (const double*)c->civol[l + 1], (const double*)c->ddrho[l], (T*)c->r[l + 1], 1);
@@ -790,7 +795,7 @@ int build_device(miugks_ctx* ctx) {
         }
         // wavefront sweep: W wavefronts of I velocities per block, W taken
         // for the fewest rounds of blocks over the chip (ties: smaller W)
-        if (!getenv("MIUGKS_NO_WAVE_SWEEP") && h.ny <= 256) {
+        if (!getenv("MIUGKS_NO_WAVE_SWEEP") && h.ny <= 256 && (int)h.w_cell.size() <= SWEEP_WAVE_MAX_WALLS) {
             for (int np = 1; np <= 2; ++np) {
                 miugks_ctx::WaveCfg wc;
                 wc.I = h.ny <= 32 ? 64 / h.ny : 1;
@@ -808,7 +813,8 @@ int build_device(miugks_ctx* ctx) {
                     long per_cu = std::min<long>((long)max_lds / (long)need, 8);
                     long cap = (long)cus * per_cu * W;
                     long rounds = (nwaves + cap - 1) / cap;
-                    if (!wc.W || rounds < best_rounds) {
+                    // ties: more wavefronts per block (fewer blocks, smaller partial sums)
+                    if (!wc.W || rounds <= best_rounds) {
                         wc.W = W;
                         wc.lds = need;
                         best_rounds = rounds;
@@ -969,6 +975,7 @@ int build_device(miugks_ctx* ctx) {
         ctx->cwall[l] = cwp;
         ctx->civol[l] = ivp;
     }
+    ctx->wparts.assign(ctx->L, ctx->nk);
     ctx->coefT.assign(ctx->L, nullptr);
     ctx->coefset.L = std::min(ctx->L, FAS_MAXL);
     for (int l = 0; l < ctx->L; ++l) {
