@@ -2244,7 +2244,7 @@ __device__ __forceinline__ double fas_gamma_side(const Geo& g, const Gas& gas, c
 
 // side-s term of sum_j S_ij F_ij(W) (the split flux of Sec. II A 1)
 __device__ __forceinline__ void fas_rsplit_side(const Geo& g, const Gas& gas, const double* __restrict__ W,
-                                                const double* __restrict__ Gam, int c, int s, double* acc) {
+                                                double G, int c, int s, double* acc) {
     double Wi[4], Wj[4], Fi[4], Fj[4];
     for (int m = 0; m < 4; ++m) Wi[m] = W[m * g.nc + c];
     int wall = -1;
@@ -2253,7 +2253,7 @@ __device__ __forceinline__ void fas_rsplit_side(const Geo& g, const Gas& gas, co
     double sign = (s & 1) ? 1.0 : -1.0;
     euler_flux_r(Wi, d, sign, gas.K, Fi);
     euler_flux_r(Wj, d, sign, gas.K, Fj);
-    double S = d == 0 ? g.dy[c / g.nx] : g.dx[c % g.nx], G = Gam[s * g.nc + c];
+    double S = d == 0 ? g.dy[c / g.nx] : g.dx[c % g.nx];
     for (int m = 0; m < 4; ++m) acc[m] = S * 0.5 * (Fi[m] + Fj[m] + G * (Wi[m] - Wj[m]));
 }
 
@@ -2301,26 +2301,59 @@ __device__ __forceinline__ void fas_half_side(const Geo& g, const Gas& gas, cons
 }
 
 // phases with four lanes per cell: item t = 4 c + s over [0, 4 nc)
-__device__ __forceinline__ void fas4_gamma(const Geo& g, const Gas& gas, const double* __restrict__ W,
-                                           double* __restrict__ W0, double* __restrict__ Gam, int t) {
+
+// entering a level: W0 := W, the frozen Gamma of every side and the forcing
+// P = R - R_split(W0) (lane s uses the Gamma of side s it has just formed)
+__device__ __forceinline__ void fas4_enter(const Geo& g, const Gas& gas, const double* __restrict__ W,
+                                           double* __restrict__ W0, double* __restrict__ Gam,
+                                           const double* __restrict__ R, double* __restrict__ P, int t) {
     int c = t >> 2, s = t & 3;
-    if (W0) W0[s * g.nc + c] = W[s * g.nc + c];
-    Gam[s * g.nc + c] = g.solid[c] ? 0.0 : fas_gamma_side(g, gas, W, c, s);
+    bool solid = g.solid[c];
+    W0[s * g.nc + c] = W[s * g.nc + c];
+    double G = solid ? 0.0 : fas_gamma_side(g, gas, W, c, s);
+    Gam[s * g.nc + c] = G;
+    double acc[4] = {0, 0, 0, 0};
+    if (!solid) fas_rsplit_side(g, gas, W, G, c, s, acc);
+    double tot[4];
+    for (int m = 0; m < 4; ++m) tot[m] = quad_sum(acc[m]);
+    double iv = 1.0 / (g.dx[c % g.nx] * g.dy[c / g.nx]);
+    double mine = s == 0 ? tot[0] : s == 1 ? tot[1] : s == 2 ? tot[2] : tot[3];
+    P[s * g.nc + c] = solid ? 0.0 : R[s * g.nc + c] + mine * iv;
 }
 
-// out = base + sgn * R_split(W), R_split_i = -(1/V_i) sum_j S_ij F_ij(W)
+// out = base + sgn * R_split(W), R_split_i = -(1/V_i) sum_j S_ij F_ij(W);
+// E != nullptr: also clear E (a smoothing restarts its correction from zero)
 __device__ __forceinline__ void fas4_rsplit(const Geo& g, const Gas& gas, const double* __restrict__ W,
                                             const double* __restrict__ Gam, const double* __restrict__ base,
-                                            double sgn, double* __restrict__ out, int t) {
+                                            double sgn, double* __restrict__ out, double* __restrict__ E, int t) {
     int c = t >> 2, s = t & 3;
     bool solid = g.solid[c];
     double acc[4] = {0, 0, 0, 0};
-    if (!solid) fas_rsplit_side(g, gas, W, Gam, c, s, acc);
+    if (!solid) fas_rsplit_side(g, gas, W, Gam[s * g.nc + c], c, s, acc);
     double tot[4];
     for (int m = 0; m < 4; ++m) tot[m] = quad_sum(acc[m]);
     double iv = 1.0 / (g.dx[c % g.nx] * g.dy[c / g.nx]);
     double mine = s == 0 ? tot[0] : s == 1 ? tot[1] : s == 2 ? tot[2] : tot[3];
     out[s * g.nc + c] = solid ? 0.0 : base[s * g.nc + c] + sgn * (-mine * iv);
+    if (E) E[s * g.nc + c] = 0.0;
+}
+
+// new correction of a cell of the given colour from the linearised defect
+// equation (lanes of the cell only; the caller guarantees the colour)
+__device__ __forceinline__ double fas4_half_value(const Geo& g, const Gas& gas, const double* __restrict__ W,
+                                                  const double* __restrict__ E, const double* __restrict__ Rm,
+                                                  const double* __restrict__ Gam,
+                                                  const double* __restrict__ dtn_inv, int c, int s) {
+    int ix = c % g.nx, iy = c / g.nx;
+    double acc[4], sg;
+    fas_half_side(g, gas, W, E, Gam, c, s, acc, sg);
+    double tot[4];
+    for (int m = 0; m < 4; ++m) tot[m] = quad_sum(acc[m]);
+    double Dsum = quad_sum(sg);
+    double V = g.dx[ix] * g.dy[iy];
+    double D = Dsum / (2.0 * V) + dtn_inv[c];
+    double mine = s == 0 ? tot[0] : s == 1 ? tot[1] : s == 2 ? tot[2] : tot[3];
+    return (Rm[s * g.nc + c] - mine / (2.0 * V)) / D;
 }
 
 // one red-black half-sweep on the cells of the given colour
@@ -2331,33 +2364,37 @@ __device__ __forceinline__ void fas4_halfsweep(const Geo& g, const Gas& gas, con
     int c = t >> 2, s = t & 3;
     int ix = c % g.nx, iy = c / g.nx;
     if (((ix + iy) & 1) != colour || g.solid[c]) return;   // all four lanes of the cell alike
-    double acc[4], sg;
-    fas_half_side(g, gas, W, E, Gam, c, s, acc, sg);
-    double tot[4];
-    for (int m = 0; m < 4; ++m) tot[m] = quad_sum(acc[m]);
-    double Dsum = quad_sum(sg);
-    double V = g.dx[ix] * g.dy[iy];
-    double D = Dsum / (2.0 * V) + dtn_inv[c];
-    double mine = s == 0 ? tot[0] : s == 1 ? tot[1] : s == 2 ? tot[2] : tot[3];
-    E[s * g.nc + c] = (Rm[s * g.nc + c] - mine / (2.0 * V)) / D;
+    double e = fas4_half_value(g, gas, W, E, Rm, Gam, dtn_inv, c, s);
+    E[s * g.nc + c] = e;
 }
 
-__device__ __forceinline__ void fas4_apply(const Geo& g, double* __restrict__ W, double* __restrict__ E, int t) {
-    int c = t >> 2, m = t & 3;
-    if (!g.solid[c]) W[m * g.nc + c] += E[m * g.nc + c];
-    E[m * g.nc + c] = 0.0;
+// the last half-sweep of a smoothing (colour 0) together with W += E: the
+// result goes to Wout (neighbours still read W, the linearisation point)
+__device__ __forceinline__ void fas4_halfsweep_apply(const Geo& g, const Gas& gas, const double* __restrict__ W,
+                                                     const double* __restrict__ E, const double* __restrict__ Rm,
+                                                     const double* __restrict__ Gam,
+                                                     const double* __restrict__ dtn_inv,
+                                                     double* __restrict__ Wout, int t) {
+    int c = t >> 2, s = t & 3;
+    int ix = c % g.nx, iy = c / g.nx;
+    bool solid = g.solid[c];
+    double e = E[s * g.nc + c];
+    if (((ix + iy) & 1) == 0 && !solid) e = fas4_half_value(g, gas, W, E, Rm, Gam, dtn_inv, c, s);
+    Wout[s * g.nc + c] = W[s * g.nc + c] + (solid ? 0.0 : e);
 }
 
+// Wout = W + I_H^h (W_coarse - W0_coarse) (fluid cells; solid cells copied)
 __device__ __forceinline__ void fas4_prolong(const Geo& g, int ncc, const double* __restrict__ Wc,
-                                             const double* __restrict__ Wc0, double* __restrict__ W, int t) {
+                                             const double* __restrict__ Wc0, const double* __restrict__ W,
+                                             double* __restrict__ Wout, int t) {
     int c = t >> 2, m = t & 3;
-    if (g.solid[c]) return;
     double s = 0.0;
-    for (int a = 0; a < 4; ++a) {
-        int id = g.p_idx[a * g.nc + c];
-        s += g.p_w[a * g.nc + c] * (Wc[(size_t)m * ncc + id] - Wc0[(size_t)m * ncc + id]);
-    }
-    W[m * g.nc + c] += s;
+    if (!g.solid[c])
+        for (int a = 0; a < 4; ++a) {
+            int id = g.p_idx[a * g.nc + c];
+            s += g.p_w[a * g.nc + c] * (Wc[(size_t)m * ncc + id] - Wc0[(size_t)m * ncc + id]);
+        }
+    Wout[m * g.nc + c] = W[m * g.nc + c] + s;
 }
 
 // component m of coarse cell C: volume-weighted mean over fluid children
@@ -2380,16 +2417,17 @@ __device__ __forceinline__ void restrict_comp(const Geo& g, const Geo& gc, const
     int t = blockIdx.x * blockDim.x + threadIdx.x;      \
     if (t >= 4 * g.nc) return;
 
-__global__ void k_fas4_gamma(Geo g, Gas gas, const double* __restrict__ W, double* __restrict__ W0,
-                             double* __restrict__ Gam) {
+__global__ void k_fas4_enter(Geo g, Gas gas, const double* __restrict__ W, double* __restrict__ W0,
+                             double* __restrict__ Gam, const double* __restrict__ R, double* __restrict__ P) {
     ITEM4_KERNEL_INDEX
-    fas4_gamma(g, gas, W, W0, Gam, t);
+    fas4_enter(g, gas, W, W0, Gam, R, P, t);
 }
 
 __global__ void k_fas4_rsplit(Geo g, Gas gas, const double* __restrict__ W, const double* __restrict__ Gam,
-                              const double* __restrict__ base, double sgn, double* __restrict__ out) {
+                              const double* __restrict__ base, double sgn, double* __restrict__ out,
+                              double* __restrict__ E) {
     ITEM4_KERNEL_INDEX
-    fas4_rsplit(g, gas, W, Gam, base, sgn, out, t);
+    fas4_rsplit(g, gas, W, Gam, base, sgn, out, E, t);
 }
 
 __global__ void k_fas4_halfsweep(Geo g, Gas gas, const double* __restrict__ W, double* __restrict__ E,
@@ -2399,15 +2437,17 @@ __global__ void k_fas4_halfsweep(Geo g, Gas gas, const double* __restrict__ W, d
     fas4_halfsweep(g, gas, W, E, Rm, Gam, dtn_inv, colour, t);
 }
 
-__global__ void k_fas4_apply(Geo g, double* __restrict__ W, double* __restrict__ E) {
+__global__ void k_fas4_halfsweep_apply(Geo g, Gas gas, const double* __restrict__ W, const double* __restrict__ E,
+                                       const double* __restrict__ Rm, const double* __restrict__ Gam,
+                                       const double* __restrict__ dtn_inv, double* __restrict__ Wout) {
     ITEM4_KERNEL_INDEX
-    fas4_apply(g, W, E, t);
+    fas4_halfsweep_apply(g, gas, W, E, Rm, Gam, dtn_inv, Wout, t);
 }
 
 __global__ void k_fas4_prolong(Geo g, int ncc, const double* __restrict__ Wc, const double* __restrict__ Wc0,
-                               double* __restrict__ W) {
+                               const double* __restrict__ W, double* __restrict__ Wout) {
     ITEM4_KERNEL_INDEX
-    fas4_prolong(g, ncc, Wc, Wc0, W, t);
+    fas4_prolong(g, ncc, Wc, Wc0, W, Wout, t);
 }
 
 // W and R of level l + 1 from level l (fine W and the renewed residual)
@@ -2463,33 +2503,47 @@ struct FasSet {
     int l0, L, nu1, nu2, nuc;
     Geo geo[FAS_MAXL];
     double *W[FAS_MAXL], *W0[FAS_MAXL], *R[FAS_MAXL], *P[FAS_MAXL], *E[FAS_MAXL], *Gam[FAS_MAXL],
-        *Rm[FAS_MAXL], *dtn[FAS_MAXL];
+        *Rm[FAS_MAXL], *dtn[FAS_MAXL], *W2[FAS_MAXL];
 };
 
-__device__ __forceinline__ void fas_block_smooth(const FasSet& F, const Gas& gas, int l, int count) {
+// current W of level l: W[l] or W2[l] by bit l of par (every thread swaps
+// alike, so the choice needs no shared state)
+__device__ __forceinline__ double* fas_w(const FasSet& F, unsigned par, int l) {
+    return ((par >> l) & 1u) ? F.W2[l] : F.W[l];
+}
+__device__ __forceinline__ double* fas_walt(const FasSet& F, unsigned par, int l) {
+    return ((par >> l) & 1u) ? F.W[l] : F.W2[l];
+}
+
+// smoothings of Sec. II C 2: renewed residual (E cleared), half-sweeps of
+// colours 0 and 1, and the last colour-0 half-sweep with W += E into the
+// other W buffer
+__device__ __forceinline__ void fas_block_smooth(const FasSet& F, const Gas& gas, int l, int count,
+                                                 unsigned& par) {
     const Geo& g = F.geo[l];
     const int n4 = 4 * g.nc;
     for (int it = 0; it < count; ++it) {
+        const double* W = fas_w(F, par, l);
         for (int t = threadIdx.x; t < n4; t += blockDim.x)
-            fas4_rsplit(g, gas, F.W[l], F.Gam[l], F.P[l], 1.0, F.Rm[l], t);
+            fas4_rsplit(g, gas, W, F.Gam[l], F.P[l], 1.0, F.Rm[l], F.E[l], t);
         __syncthreads();
-        for (int col : {0, 1, 0}) {
+        for (int col : {0, 1}) {
             for (int t = threadIdx.x; t < n4; t += blockDim.x)
-                fas4_halfsweep(g, gas, F.W[l], F.E[l], F.Rm[l], F.Gam[l], F.dtn[l], col, t);
+                fas4_halfsweep(g, gas, W, F.E[l], F.Rm[l], F.Gam[l], F.dtn[l], col, t);
             __syncthreads();
         }
-        for (int t = threadIdx.x; t < n4; t += blockDim.x) fas4_apply(g, F.W[l], F.E[l], t);
+        for (int t = threadIdx.x; t < n4; t += blockDim.x)
+            fas4_halfsweep_apply(g, gas, W, F.E[l], F.Rm[l], F.Gam[l], F.dtn[l], fas_walt(F, par, l), t);
         __syncthreads();
+        par ^= 1u << l;
     }
 }
 
-__device__ __forceinline__ void fas_block_enter(const FasSet& F, const Gas& gas, int l) {
+__device__ __forceinline__ void fas_block_enter(const FasSet& F, const Gas& gas, int l, unsigned par) {
     const Geo& g = F.geo[l];
     const int n4 = 4 * g.nc;
-    for (int t = threadIdx.x; t < n4; t += blockDim.x) fas4_gamma(g, gas, F.W[l], F.W0[l], F.Gam[l], t);
-    __syncthreads();
     for (int t = threadIdx.x; t < n4; t += blockDim.x)
-        fas4_rsplit(g, gas, F.W[l], F.Gam[l], F.R[l], -1.0, F.P[l], t);
+        fas4_enter(g, gas, fas_w(F, par, l), F.W0[l], F.Gam[l], F.R[l], F.P[l], t);
     __syncthreads();
 }
 
@@ -2501,7 +2555,7 @@ __host__ __device__ inline size_t fas_lds_align(size_t b) { return (b + 15) & ~(
 
 __host__ __device__ inline size_t fas_level_lds_bytes(int nx, int ny) {
     size_t nc = (size_t)nx * ny;
-    return 7 * fas_lds_align(4 * nc * 8) + fas_lds_align(nc * 8) + fas_lds_align(4 * nc * 4) +
+    return 8 * fas_lds_align(4 * nc * 8) + fas_lds_align(nc * 8) + fas_lds_align(4 * nc * 4) +
            fas_lds_align(4 * nc * 8) + fas_lds_align(nx * 8) + fas_lds_align(ny * 8) + fas_lds_align(nc) +
            fas_lds_align(4 * nc * 4) + fas_lds_align(4 * nc * 8);
 }
@@ -2526,6 +2580,7 @@ __global__ void __launch_bounds__(1024) k_fas_cycle_block(FasSet G, Gas gas) {
             const Geo& g = G.geo[l];
             size_t nc = g.nc;
             F.W[l] = (double*)take(4 * nc * 8);
+            F.W2[l] = (double*)take(4 * nc * 8);
             F.W0[l] = (double*)take(4 * nc * 8);
             F.R[l] = (double*)take(4 * nc * 8);
             F.P[l] = (double*)take(4 * nc * 8);
@@ -2561,32 +2616,36 @@ __global__ void __launch_bounds__(1024) k_fas_cycle_block(FasSet G, Gas gas) {
     __syncthreads();
 
     const int L = F.L;
+    unsigned par = 0;   // bit l: W of level l currently in W2[l]
     for (int l = F.l0; l < L - 1; ++l) {
         const Geo& g = F.geo[l];
         const Geo& gc = F.geo[l + 1];
-        fas_block_enter(F, gas, l);
-        fas_block_smooth(F, gas, l, F.nu1);
+        fas_block_enter(F, gas, l, par);
+        fas_block_smooth(F, gas, l, F.nu1, par);
+        const double* W = fas_w(F, par, l);
         for (int t = threadIdx.x; t < 4 * g.nc; t += blockDim.x)
-            fas4_rsplit(g, gas, F.W[l], F.Gam[l], F.P[l], 1.0, F.Rm[l], t);
+            fas4_rsplit(g, gas, W, F.Gam[l], F.P[l], 1.0, F.Rm[l], (double*)nullptr, t);
         __syncthreads();
         for (int t = threadIdx.x; t < 4 * gc.nc; t += blockDim.x) {
-            restrict_comp(g, gc, F.W[l], F.W[l + 1], t >> 2, t & 3);
+            restrict_comp(g, gc, W, fas_w(F, par, l + 1), t >> 2, t & 3);
             restrict_comp(g, gc, F.Rm[l], F.R[l + 1], t >> 2, t & 3);
         }
         __syncthreads();
     }
-    fas_block_enter(F, gas, L - 1);
-    fas_block_smooth(F, gas, L - 1, F.nuc);
+    fas_block_enter(F, gas, L - 1, par);
+    fas_block_smooth(F, gas, L - 1, F.nuc, par);
     for (int l = L - 2; l >= F.l0; --l) {
         const Geo& g = F.geo[l];
         for (int t = threadIdx.x; t < 4 * g.nc; t += blockDim.x)
-            fas4_prolong(g, F.geo[l + 1].nc, F.W[l + 1], F.W0[l + 1], F.W[l], t);
+            fas4_prolong(g, F.geo[l + 1].nc, fas_w(F, par, l + 1), F.W0[l + 1], fas_w(F, par, l),
+                         fas_walt(F, par, l), t);
         __syncthreads();
-        fas_block_smooth(F, gas, l, F.nu2);
+        par ^= 1u << l;
+        fas_block_smooth(F, gas, l, F.nu2, par);
     }
     // result and the state the parent level prolongs from
-    block_copy(G.W[G.l0], F.W[G.l0], 4 * (size_t)G.geo[G.l0].nc);
-    block_copy(G.W0[G.l0], F.W0[G.l0], 4 * (size_t)G.geo[G.l0].nc);
+    block_copy(G.W[G.l0], (const double*)fas_w(F, par, G.l0), 4 * (size_t)G.geo[G.l0].nc);
+    block_copy(G.W0[G.l0], (const double*)F.W0[G.l0], 4 * (size_t)G.geo[G.l0].nc);
 }
 
 // ---------------------------------------------------------------------------

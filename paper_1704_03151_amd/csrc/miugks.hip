@@ -59,7 +59,7 @@ struct miugks_ctx {
     // per level
     std::vector<void*> r, df;
     std::vector<double*> tau_inv, dtn_inv, drho;
-    std::vector<double*> fW, fW0, fR, fP, fE, fGam, fRm;
+    std::vector<double*> fW, fW0, fR, fP, fE, fGam, fRm, fW2;
     double* h_norms = nullptr;   // pinned
     double M0 = 1.0;
     int cycle = 0;
@@ -496,19 +496,22 @@ struct Path {
 // ---------------------------------------------------------------------------
 // FAS cycle (precision independent, FP64)
 
-// one smoothing of Sec. II C 2: renewed residual, red-black half-sweeps of
-// colours 0, 1, 0, then W += E (four lanes per cell in every phase)
-void fas_smooth(miugks_ctx* c, int l) {
+// one smoothing of Sec. II C 2: renewed residual (E cleared), red-black
+// half-sweeps of colours 0, 1 and 0, the last one with W += E into the other
+// W buffer (four lanes per cell in every phase); W and Walt swap
+void fas_smooth(miugks_ctx* c, int l, double*& W, double*& Walt) {
     const Geo& g = c->geo[l];
     int nb = nblk(4 * g.nc);
     double nc8 = g.nc * 8.0;
-    LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas4_rsplit, dim3(nb), dim3(256), g, c->gas, (const double*)c->fW[l],
-           (const double*)c->fGam[l], (const double*)c->fP[l], 1.0, c->fRm[l]);
-    for (int col : {0, 1, 0})
-        LAUNCH(c, "fas_halfsweep", 18 * nc8, k_fas4_halfsweep, dim3(nb), dim3(256), g, c->gas,
-               (const double*)c->fW[l], c->fE[l], (const double*)c->fRm[l], (const double*)c->fGam[l],
-               (const double*)c->dtn_inv[l], col);
-    LAUNCH(c, "fas_apply", 16 * nc8, k_fas4_apply, dim3(nb), dim3(256), g, c->fW[l], c->fE[l]);
+    LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas4_rsplit, dim3(nb), dim3(256), g, c->gas, (const double*)W,
+           (const double*)c->fGam[l], (const double*)c->fP[l], 1.0, c->fRm[l], c->fE[l]);
+    for (int col : {0, 1})
+        LAUNCH(c, "fas_halfsweep", 18 * nc8, k_fas4_halfsweep, dim3(nb), dim3(256), g, c->gas, (const double*)W,
+               c->fE[l], (const double*)c->fRm[l], (const double*)c->fGam[l], (const double*)c->dtn_inv[l], col);
+    LAUNCH(c, "fas_halfsweep", 26 * nc8, k_fas4_halfsweep_apply, dim3(nb), dim3(256), g, c->gas, (const double*)W,
+           (const double*)c->fE[l], (const double*)c->fRm[l], (const double*)c->fGam[l],
+           (const double*)c->dtn_inv[l], Walt);
+    std::swap(W, Walt);
 }
 
 // W_l^{n+1} = FAS(l, W_l^n, R_l^n): fW[l] holds W_l^n on entry and the result
@@ -526,25 +529,28 @@ void fas(miugks_ctx* c, int l) {
     const Geo& g = c->geo[l];
     int nb = nblk(4 * g.nc);
     double nc8 = g.nc * 8.0;
-    // W0 := W and the frozen Gamma, then the forcing P = R - R_split(W0)
-    LAUNCH(c, "fas_gamma", 16 * nc8, k_fas4_gamma, dim3(nb), dim3(256), g, c->gas, (const double*)c->fW[l],
-           c->fW0[l], c->fGam[l]);
-    LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas4_rsplit, dim3(nb), dim3(256), g, c->gas, (const double*)c->fW[l],
-           (const double*)c->fGam[l], (const double*)c->fR[l], -1.0, c->fP[l]);
+    double *W = c->fW[l], *Walt = c->fW2[l];
+    // W0 := W, the frozen Gamma, the forcing P = R - R_split(W0)
+    LAUNCH(c, "fas_enter", 28 * nc8, k_fas4_enter, dim3(nb), dim3(256), g, c->gas, (const double*)W, c->fW0[l],
+           c->fGam[l], (const double*)c->fR[l], c->fP[l]);
     if (l == c->L - 1) {
-        for (int i = 0; i < c->nuc; ++i) fas_smooth(c, l);
-        return;
+        for (int i = 0; i < c->nuc; ++i) fas_smooth(c, l, W, Walt);
+    } else {
+        for (int i = 0; i < c->nu1; ++i) fas_smooth(c, l, W, Walt);
+        const Geo& gc = c->geo[l + 1];
+        LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas4_rsplit, dim3(nb), dim3(256), g, c->gas, (const double*)W,
+               (const double*)c->fGam[l], (const double*)c->fP[l], 1.0, c->fRm[l], (double*)nullptr);
+        LAUNCH(c, "fas_restrict", 10 * nc8, k_fas4_restrict, dim3(nblk(4 * gc.nc)), dim3(256), g, gc,
+               (const double*)W, (const double*)c->fRm[l], c->fW[l + 1], c->fR[l + 1]);
+        fas(c, l + 1);
+        LAUNCH(c, "fas_prolong", 10 * nc8, k_fas4_prolong, dim3(nb), dim3(256), g, gc.nc,
+               (const double*)c->fW[l + 1], (const double*)c->fW0[l + 1], (const double*)W, Walt);
+        std::swap(W, Walt);
+        for (int i = 0; i < c->nu2; ++i) fas_smooth(c, l, W, Walt);
     }
-    for (int i = 0; i < c->nu1; ++i) fas_smooth(c, l);
-    const Geo& gc = c->geo[l + 1];
-    LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas4_rsplit, dim3(nb), dim3(256), g, c->gas, (const double*)c->fW[l],
-           (const double*)c->fGam[l], (const double*)c->fP[l], 1.0, c->fRm[l]);
-    LAUNCH(c, "fas_restrict", 10 * nc8, k_fas4_restrict, dim3(nblk(4 * gc.nc)), dim3(256), g, gc,
-           (const double*)c->fW[l], (const double*)c->fRm[l], c->fW[l + 1], c->fR[l + 1]);
-    fas(c, l + 1);
-    LAUNCH(c, "fas_prolong", 10 * nc8, k_fas4_prolong, dim3(nb), dim3(256), g, gc.nc, (const double*)c->fW[l + 1],
-           (const double*)c->fW0[l + 1], c->fW[l]);
-    for (int i = 0; i < c->nu2; ++i) fas_smooth(c, l);
+    if (W != c->fW[l])
+        LAUNCH(c, "copy", 8 * nc8, k_copy2, dim3(nblk(4 * g.nc)), dim3(256), (const double*)W, c->fW[l],
+               (double*)nullptr, (const double*)nullptr, (double*)nullptr, 4 * (size_t)g.nc);
 }
 
 // pseudo step of the current cycle: the host writes a^{-n} to device memory
@@ -927,7 +933,7 @@ int build_device(miugks_ctx* ctx) {
     ctx->r.resize(ctx->L);
     ctx->df.resize(ctx->L);
     for (auto* v2 : {&ctx->tau_inv, &ctx->dtn_inv, &ctx->drho, &ctx->fW, &ctx->fW0, &ctx->fR, &ctx->fP, &ctx->fE,
-                     &ctx->fGam, &ctx->fRm})
+                     &ctx->fGam, &ctx->fRm, &ctx->fW2})
         v2->resize(ctx->L);
     for (int l = 0; l < ctx->L; ++l) {
         size_t nc = ctx->hl[l].nc;
@@ -937,7 +943,8 @@ int build_device(miugks_ctx* ctx) {
             (rc = dalloc(&ctx->drho[l], ctx->hl[l].w_cell.size() + 1)) || (rc = dalloc(&ctx->fW[l], 4 * nc)) ||
             (rc = dalloc(&ctx->fW0[l], 4 * nc)) || (rc = dalloc(&ctx->fR[l], 4 * nc)) ||
             (rc = dalloc(&ctx->fP[l], 4 * nc)) || (rc = dalloc(&ctx->fE[l], 4 * nc)) ||
-            (rc = dalloc(&ctx->fGam[l], 4 * nc)) || (rc = dalloc(&ctx->fRm[l], 4 * nc)))
+            (rc = dalloc(&ctx->fGam[l], 4 * nc)) || (rc = dalloc(&ctx->fRm[l], 4 * nc)) ||
+            (rc = dalloc(&ctx->fW2[l], 4 * nc)))
             return rc;
         HIP_TRY(hipMemset(ctx->fE[l], 0, 4 * nc * sizeof(double)));
         HIP_TRY(hipMemset(ctx->dtn_inv[l], 0, nc * sizeof(double)));
@@ -1027,6 +1034,7 @@ int build_device(miugks_ctx* ctx) {
             F.Gam[l] = ctx->fGam[l];
             F.Rm[l] = ctx->fRm[l];
             F.dtn[l] = ctx->dtn_inv[l];
+            F.W2[l] = ctx->fW2[l];
         }
     }
     HIP_TRY(hipHostMalloc((void**)&ctx->h_norms, 4 * sizeof(double), hipHostMallocDefault));
