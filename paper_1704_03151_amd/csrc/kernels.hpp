@@ -439,6 +439,17 @@ __device__ __forceinline__ float rcp_refined(float x) {
     float r = __builtin_amdgcn_rcpf(x);
     return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
+// prim_of with the reciprocals refined instead of divided
+__device__ __forceinline__ void prim_of_r(const double* W, double K, double& rho, double& U, double& V,
+                                          double& lam) {
+    rho = W[0];
+    double ir = rcp_refined(rho);
+    U = W[1] * ir;
+    V = W[2] * ir;
+    double e = W[3] - 0.5 * rho * (U * U + V * V);
+    lam = K * rho * rcp_refined(4.0 * e);
+}
+
 template <typename T> __device__ __forceinline__ T van_leer_fast(T a, T b) {
     T s = a * b;
     return s > T(0) ? T(2) * s * rcp_refined(a + b) : T(0);
@@ -2071,8 +2082,8 @@ __device__ __forceinline__ int side_state(const Geo& g, const Gas& gas, const do
     }
     wall = wall_of(code);
     double rho, U, V, lam;
-    prim_of(Wi, gas.K, rho, U, V, lam);
-    cons_of(rho, 2.0 * g.w_U[wall] - U, 2.0 * g.w_V[wall] - V, 2.0 / g.w_T[wall] - lam, gas.K, Wj);
+    prim_of_r(Wi, gas.K, rho, U, V, lam);
+    cons_of(rho, 2.0 * g.w_U[wall] - U, 2.0 * g.w_V[wall] - V, 2.0 * rcp_refined(g.w_T[wall]) - lam, gas.K, Wj);
     return 3;
 }
 
@@ -2206,11 +2217,22 @@ __device__ __forceinline__ void fas_prolong_cell(const Geo& g, int ncc, const do
 // shuffles.  Used by the kernels below: a cell's dependent chain of FP64
 // work is a quarter as long, which is what bounds these small levels.
 
+// lane i of every group of four takes lane i ^ m (m = 1, 2) by a DPP quad
+// permutation (quad_perm [1,0,3,2] = 0xB1, [2,3,0,1] = 0x4E)
+template <int CTRL>
+__device__ __forceinline__ double quad_perm(double x) {
+    unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+    int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
 __device__ __forceinline__ double quad_sum(double x) {
-    x += __shfl_xor(x, 1, 64);
-    x += __shfl_xor(x, 2, 64);
+    x += quad_perm<0xB1>(x);
+    x += quad_perm<0x4E>(x);
     return x;
 }
+
 
 // Euler flux of W through a side of normal sign * e_d (division-free: the
 // reciprocal density is refined to full precision)
@@ -2282,14 +2304,14 @@ __device__ __forceinline__ void fas_half_side(const Geo& g, const Gas& gas, cons
     } else {
         // linearised wall ghost dW_j = J dW_i (Sec. III B), K total degrees of freedom
         double rho, U, V2, lam;
-        prim_of(Wi, gas.K, rho, U, V2, lam);
-        double Uw = g.w_U[wall], Vw = g.w_V[wall], lw = 1.0 / g.w_T[wall];
-        double Y = lam / (lam - 2.0 * lw);
+        prim_of_r(Wi, gas.K, rho, U, V2, lam);
+        double Uw = g.w_U[wall], Vw = g.w_V[wall], lw = rcp_refined(g.w_T[wall]);
+        double Y = lam * rcp_refined(lam - 2.0 * lw);
         Ej[0] = Ei[0];
         Ej[1] = 2.0 * Uw * Ei[0] - Ei[1];
         Ej[2] = 2.0 * Vw * Ei[0] - Ei[2];
         Ej[3] = (2.0 * (Uw * Uw + Vw * Vw) - 0.5 * (U * U + V2 * V2) * (1.0 + Y * Y) +
-                 gas.K / (4.0 * lam) * (Y * Y - Y)) * Ei[0] +
+                 gas.K * rcp_refined(4.0 * lam) * (Y * Y - Y)) * Ei[0] +
                 (U - 2.0 * Uw + U * Y * Y) * Ei[1] + (V2 - 2.0 * Vw + V2 * Y * Y) * Ei[2] - Y * Y * Ei[3];
     }
     double WE[4];
@@ -2350,10 +2372,10 @@ __device__ __forceinline__ double fas4_half_value(const Geo& g, const Gas& gas, 
     double tot[4];
     for (int m = 0; m < 4; ++m) tot[m] = quad_sum(acc[m]);
     double Dsum = quad_sum(sg);
-    double V = g.dx[ix] * g.dy[iy];
-    double D = Dsum / (2.0 * V) + dtn_inv[c];
+    double ih = rcp_refined(2.0 * g.dx[ix] * g.dy[iy]);   // 1 / (2 V)
+    double D = Dsum * ih + dtn_inv[c];
     double mine = s == 0 ? tot[0] : s == 1 ? tot[1] : s == 2 ? tot[2] : tot[3];
-    return (Rm[s * g.nc + c] - mine / (2.0 * V)) / D;
+    return (Rm[s * g.nc + c] - mine * ih) * rcp_refined(D);
 }
 
 // one red-black half-sweep on the cells of the given colour
