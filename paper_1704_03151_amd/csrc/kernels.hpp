@@ -1668,7 +1668,8 @@ __host__ __device__ inline size_t sweep_wave_tiles_elems(int nc, int nw, int W, 
 
 template <typename T>
 size_t sweep_wave_lds_bytes(int nc, int nx, int nw, int W, int I, int NP) {
-    size_t b = (sweep_wave_tiles_elems<T>(nc, nw, W, I, NP) + nc + nx + 5 * (size_t)nw) * sizeof(T) +
+    size_t b = 64 * (size_t)W * sizeof(double) +
+               (sweep_wave_tiles_elems<T>(nc, nw, W, I, NP) + nc + nx + 5 * (size_t)nw) * sizeof(T) +
                4 * (size_t)nw + (size_t)nc;
     return (b + 15) & ~(size_t)15;
 }
@@ -1681,19 +1682,24 @@ size_t sweep_wave_lds_bytes(int nc, int nx, int nw, int W, int I, int NP) {
 // overwritten before use needs only G.
 // Epilogue: the block's sums over its velocities of w_k u_n dG_k at every
 // wall side (u_n > 0) go to wpart[block][j], the partial sums of the next
-// wall densities.
+// wall densities.  wprev != nullptr: the wall densities of this sweep are
+// formed in the prologue from the nprev partial sums of the previous sweep
+// (every block alike, in a fixed order; block 0 also stores them to
+// drho_out); otherwise they are read from drho (nullptr: zero).
 template <typename T, int R, int NP>
 __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, const T* __restrict__ r,
                                                     T* __restrict__ df, const T* __restrict__ coef_g,
                                                     const unsigned char* __restrict__ stype,
                                                     const double* __restrict__ drho, double* __restrict__ wpart,
-                                                    int I) {
+                                                    int I, const double* __restrict__ wprev, int nprev,
+                                                    double* __restrict__ drho_out) {
     // (no static LDS in this kernel: the tiles must start 16-byte aligned
     // for the direct global-to-LDS loads)
     extern __shared__ __attribute__((aligned(16))) double smem_d[];
     const int nc = g.nc, nx = g.nx, ny = g.ny, nw = g.n_wall, nk = vel.nk;
     const int W = blockDim.x >> 6, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    T* tiles = (T*)smem_d;                                  // [W][NP][I][nc]
+    double* dsum = smem_d;                                  // [64 W]  partial sums of the wall densities
+    T* tiles = (T*)(smem_d + 64 * W);                       // [W][NP][I][nc]
     T* coef = tiles + sweep_wave_tiles_elems<T>(nc, nw, W, I, NP);   // [nc]
     T* invdx = coef + nc;                                   // [nx]
     T* wl = invdx + nx;                                     // [5][n_wall]  1/d, lam_w, U_w, V_w, drho
@@ -1718,12 +1724,31 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
         wl[4 * nw + j] = drho ? T(drho[j]) : T(0);
         wsc[j] = g.w_side[j] + 4 * g.w_cell[j];
     }
+    // wall densities from the previous sweep's partial sums: thread t adds
+    // the sums b = grp, grp + ng, ... of wall j = t mod nw (grp = t / nw)
+    const int ng = nw > 0 ? max(1, (int)blockDim.x / nw) : 1;
+    if (wprev && threadIdx.x < ng * nw) {
+        int j = threadIdx.x % nw, grp = threadIdx.x / nw;
+        double sacc = 0.0;
+        for (int b = grp; b < nprev; b += ng) sacc += wprev[(size_t)b * nw + j];
+        dsum[threadIdx.x] = sacc;
+    }
     // velocities of this wavefront: lane q < nq holds velocity k0 + q
     const T uq_l = lane < nq ? vel_u<T>(vel, k0 + lane) : T(0);
     const T vq_l = lane < nq ? vel_v<T>(vel, k0 + lane) : T(0);
     __syncthreads();
+    if (wprev) {
+        for (int j = threadIdx.x; j < nw; j += blockDim.x) {
+            double sacc = 0.0;
+            for (int grp = 0; grp < ng; ++grp) sacc += dsum[grp * nw + j];
+            double dj = -sacc / g.w_den[j];
+            wl[4 * nw + j] = T(dj);
+            if (blockIdx.x == 0) drho_out[j] = dj;
+        }
+        __syncthreads();
+    }
     // upwind wall-ghost terms into r (x-sides, then y-sides)
-    if (drho) {
+    if (drho || wprev) {
         for (int jb = 0; jb < nw; jb += 64) {
             const int j = jb + lane;
             const bool ok = j < nw;

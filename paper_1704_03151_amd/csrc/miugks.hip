@@ -67,7 +67,7 @@ struct miugks_ctx {
     struct miugks_timing_state* timing = nullptr;
     // ordered-sweep support per level
     std::vector<unsigned*> flags;
-    std::vector<double*> wbuf;
+    std::vector<double*> wbuf, wbuf_alt;   // wall-product partial sums; sweeps alternate between the two
     std::vector<char> sweep_lds;
     // wavefront sweep (k_sweep_wave): side types and launch shape per level
     // (W = 0: not used on that level)
@@ -329,19 +329,25 @@ struct Path {
     static void smooth(miugks_ctx* c, int l, bool drho_current, bool from_zero = false, int np = 2) {
         const Geo& g = c->geo[l];
         c->last_from_zero[l] = from_zero && c->wave[l].W;
-        if (!drho_current && g.n_wall)
+        const miugks_ctx::WaveCfg& wc = np == 1 ? c->wave1[l] : c->wave[l];
+        // the wall densities from the last sweep's partial sums: inside the
+        // wavefront sweep where they are few, else by k_drho
+        const bool in_sweep = !drho_current && g.n_wall && wc.W &&
+                              (long)c->wparts[l] * g.n_wall <= 16L * 64 * wc.W && !getenv("MIUGKS_DRHO_KERNEL");
+        if (!drho_current && g.n_wall && !in_sweep)
             LAUNCH(c, "drho", (double)g.n_wall * c->wparts[l] * 8, k_drho, dim3((g.n_wall + 3) / 4), dim3(256), g,
                    c->wparts[l], c->wbuf[l], c->drho[l]);
         static const char* const names[] = {"sweep/l0", "sweep/l1", "sweep/l2", "sweep/l3",
                                             "sweep/l4", "sweep/l5", "sweep/l6", "sweep/l7"};
         const char* name = names[l < 8 ? l : 7];
-        const miugks_ctx::WaveCfg& wc = np == 1 ? c->wave1[l] : c->wave[l];
+        // the sweep leaves its partial sums in the other buffer
+        std::swap(c->wbuf[l], c->wbuf_alt[l]);
         if (wc.W) {
 #define MIUGKS_WAVE_LAUNCH(RR, NP)                                                                              \
     LAUNCH_SH(c, name, (NP) * arr(c, l), wc.lds, (k_sweep_wave<T, RR, NP>), dim3(wc.blocks), dim3(64 * wc.W), g, \
               c->vel, c->gas.K_int, (const T*)c->r[l], (T*)c->df[l], (const T*)c->coefT[l], c->stype[l],        \
-              from_zero ? (const double*)nullptr : (const double*)c->drho[l], c->wbuf[l], wc.I)
-            c->wparts[l] = wc.blocks;
+              from_zero ? (const double*)nullptr : (const double*)c->drho[l], c->wbuf[l], wc.I,                 \
+              in_sweep ? (const double*)c->wbuf_alt[l] : (const double*)nullptr, c->wparts[l], c->drho[l])
             if (np == 1) {
                 switch (wc.R) {
                     case 1: MIUGKS_WAVE_LAUNCH(1, 1); break;
@@ -358,6 +364,7 @@ struct Path {
                 }
             }
 #undef MIUGKS_WAVE_LAUNCH
+            c->wparts[l] = wc.blocks;
         } else if (c->sweep_lds[l]) {
             c->wparts[l] = c->nk;
             int npad = ((g.ny + 63) / 64) * 64, P = c->sweep_lds[l];
@@ -738,6 +745,7 @@ int build_device(miugks_ctx* ctx) {
     (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     ctx->flags.resize(ctx->L);
     ctx->wbuf.resize(ctx->L);
+    ctx->wbuf_alt.resize(ctx->L);
     ctx->sweep_lds.assign(ctx->L, 0);
     ctx->stype.assign(ctx->L, nullptr);
     ctx->wave.assign(ctx->L, miugks_ctx::WaveCfg());
@@ -776,9 +784,12 @@ int build_device(miugks_ctx* ctx) {
             if ((rc = upload(ctx, &sp, st))) return rc;
             ctx->stype[l] = sp;
         }
-        void* wb;
-        if ((rc = dev_alloc(ctx, &wb, std::max<size_t>(1, h.w_cell.size()) * ctx->nk * sizeof(double)))) return rc;
+        void *wb, *wb2;
+        if ((rc = dev_alloc(ctx, &wb, std::max<size_t>(1, h.w_cell.size()) * ctx->nk * sizeof(double))) ||
+            (rc = dev_alloc(ctx, &wb2, std::max<size_t>(1, h.w_cell.size()) * ctx->nk * sizeof(double))))
+            return rc;
         ctx->wbuf[l] = (double*)wb;
+        ctx->wbuf_alt[l] = (double*)wb2;
         // pipelines per block: as many as fit in LDS and 1024 threads, but
         // no more than needed to cover every item in one round of blocks
         int npad = ((h.ny + 63) / 64) * 64;
