@@ -35,9 +35,6 @@ HBM_PEAK_GBS = 8000.0
 # same run (--copy-calibration).  Keyed by (workload, precision, kernel); an
 # entry is dropped whenever that kernel changes.
 MEASURED_TRAFFIC = {
-    # profiles/sweep_wave_cavity64_fp32f_hbm_traffic.md: 133 dispatches of the
-    # sweep (18 G-only and 1 G+H per cycle), scaled FETCH_SIZE + WRITE_SIZE
-    ("cavity64_kn0.075", "fp32f", "sweep"): 8.04e6,
 }
 
 

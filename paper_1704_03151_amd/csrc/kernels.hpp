@@ -1796,8 +1796,11 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
     T by[R], cG[R], cH[R];
     T nf_cf[R], nf_idx[R], nf_rG[R], nf_rH[R];              // data of the slot's next cell
     unsigned nf_sc[R];
+    // a lane outside the current diagonal fetches the dummy column t mod nx:
+    // a clamped column would put every such lane on one LDS bank
+    const int dcol = t0 % nx;
     auto fetch = [&](int p, int jx) {
-        int jc = jx < 0 ? 0 : (jx >= nx ? nx - 1 : jx);
+        int jc = (jx < 0 || jx >= nx) ? dcol : jx;
         int ix = px ? jc : nx - 1 - jc;
         int c = rowc[p] + ix;
         nf_cf[p] = coef[c];
