@@ -103,13 +103,16 @@ typedef struct {
  * (pre), nu2 (post), nu_coarse (coarsest level), Courant number of the
  * physical step, growth a of the pseudo step dt_n = a^n dt_p (0 = off,
  * Sec. III D), mass_renorm: 1 = keep total mass, 0 = off, -1 = on iff the
- * domain has walls only. */
+ * domain has walls only; fas_levels: levels of the FAS prediction, from the
+ * finest (0 or more than n_levels: all of them; the CS correction always
+ * uses n_levels). */
 typedef struct {
     int precision;
     int nu1, nu2, nu_coarse;
     double cfl;
     double dtn_growth;
     int mass_renorm;
+    int fas_levels;
 } miugks_solver_desc;
 
 /* Nodes and weights of a 1-D rule on [lo, hi] (ignored for Gauss-Hermite,

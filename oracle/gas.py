@@ -81,21 +81,28 @@ def maxwellian(rho, U, V, lam, u, v, K_int):
 
 
 def shakhov(rho, U, V, lam, qx, qy, u, v, K_int, Pr):
-    """Shakhov equilibrium for the reduced pair (Sec. II A, Eq. of the steady
-    kinetic equation, Prandtl-number correction).
+    """Shakhov equilibrium for the reduced pair (Sec. II A, Shakhov-type model
+    with the Prandtl-number correction).
 
-    g+ = 0.8 (1 - Pr) lam^2 (c.q) / rho * (2 lam |c|^2 + K_int - 5) G_eq   (G part)
-    g+ = 0.8 (1 - Pr) lam^2 (c.q) / rho * (2 lam |c|^2 + K_int - 3) H_eq   (H part)
-    obtained by integrating the 3-D Shakhov factor (c^2/(RT) - 5) over the
-    K_int extra velocity components.
+    The gas has N = 2 + K_int degrees of freedom, the K_int beyond the plane
+    velocity entering like extra velocity components xi.  The Shakhov factor
+    over all of them is 1 + (1 - Pr) (c.q) / ((N + 2) p R T) (s / (R T) - (N + 2))
+    with s = |c|^2 + |xi|^2; integrating it over xi (and xi^2 for H) gives
+
+    g+ = 4/(K_int + 4) (1 - Pr) lam^2 (c.q) / rho * (2 lam |c|^2 - 4) G_eq   (G part)
+    g+ = 4/(K_int + 4) (1 - Pr) lam^2 (c.q) / rho * (2 lam |c|^2 - 2) H_eq   (H part)
+
+    The correction carries no mass, momentum or energy and the heat flux of
+    the pair is (1 - Pr) q, for any K_int (for K_int = 1 it is the 3-D
+    factor (c^2/(RT) - 5) / (5 p R T) of a monatomic gas).
     """
     G, H = maxwellian(rho, U, V, lam, u, v, K_int)
     cx = u - U
     cy = v - V
     c2 = cx * cx + cy * cy
-    fac = 0.8 * (1.0 - Pr) * lam * lam * (cx * qx + cy * qy) / rho
-    Gp = fac * (2.0 * lam * c2 + K_int - 5.0) * G
-    Hp = fac * (2.0 * lam * c2 + K_int - 3.0) * H
+    fac = 4.0 / (K_int + 4.0) * (1.0 - Pr) * lam * lam * (cx * qx + cy * qy) / rho
+    Gp = fac * (2.0 * lam * c2 - 4.0) * G
+    Hp = fac * (2.0 * lam * c2 - 2.0) * H
     return G + Gp, H + Hp
 
 

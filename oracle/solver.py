@@ -37,7 +37,9 @@ class Oracle:
         self.levels = build_levels(case, self.vel)
         self.prolongs = [Prolongation(self.levels[l], self.levels[l + 1])
                          for l in range(len(self.levels) - 1)]
-        self.fas_levels = [MacroLevel(lev, self.gas, case.farfield) for lev in self.levels]
+        # the FAS prediction may stop above the coarsest level of the CS cycle
+        nfas = case.fas_levels if case.fas_levels > 0 else len(self.levels)
+        self.fas_levels = [MacroLevel(lev, self.gas, case.farfield) for lev in self.levels[:nfas]]
         self.cs_levels = [MicroLevel(lev, self.vel, self.gas.K_int) for lev in self.levels]
         self.params = (case.nu1, case.nu2, case.nu_coarse)
         self.closed = case.closed()

@@ -68,6 +68,15 @@ template <> __device__ __forceinline__ float vel_u<float>(const Vel& v, int k) {
 template <> __device__ __forceinline__ float vel_v<float>(const Vel& v, int k) { return v.vf[k]; }
 template <> __device__ __forceinline__ float vel_w<float>(const Vel& v, int k) { return v.wf[k]; }
 
+// Shakhov-type correction over the 2 + K_int degrees of freedom of the gas
+// (Sec. II A), reduced to the pair (G, H):
+//   G+ = s (c.q) (2 lam |c|^2 - 4) G_eq,  H+ = s (c.q) (2 lam |c|^2 - 2) H_eq,
+//   s = 4 / (K_int + 4) (1 - Pr) lam^2 / rho,
+// which carries no mass, momentum or energy and gives the heat flux (1 - Pr) q
+__host__ __device__ inline double shakhov_prefactor(const Gas& gas) {
+    return 4.0 / (gas.K_int + 4.0) * (1.0 - gas.Pr);
+}
+
 __device__ __forceinline__ double dexp(double x) { return exp(x); }
 __device__ __forceinline__ float dexp(float x) { return expf(x); }
 
@@ -682,7 +691,7 @@ __device__ __forceinline__ void block_sum_waves(double* acc, double* sh) {
 }
 
 // Interface record, per (direction d, cell c) = the face on side 2d of c:
-//  0 rho0  1 U0  2 V0  3 lam0  4,5 Shakhov coefficients 0.8(1-Pr) lam0^2 q0 / rho0
+//  0 rho0  1 U0  2 V0  3 lam0  4,5 Shakhov coefficients 4/(K_int+4) (1-Pr) lam0^2 q0 / rho0
 //  6-9 abar left  10-13 abar right  14-17 Abar  18-22 q1..q5 / dt  23 interior flag
 __global__ void k_face_finalize(Geo g, Gas gas, const double* __restrict__ part, int nkc,
                                 const double* __restrict__ W, double* __restrict__ fp) {
@@ -719,7 +728,7 @@ __global__ void k_face_finalize(Geo g, Gas gas, const double* __restrict__ part,
         }
         micro_slope(bL, U, V, lam, gas.K, aL);
         micro_slope(bR, U, V, lam, gas.K, aR);
-        double sh = 0.8 * (1.0 - gas.Pr) * lam * lam / rho;
+        double sh = shakhov_prefactor(gas) * lam * lam / rho;
         double vals[NFP] = {rho, U, V, lam, sh * q0[0], sh * q0[1],
                             aL[0], aL[1], aL[2], aL[3], aR[0], aR[1], aR[2], aR[3],
                             0, 0, 0, 0,
@@ -756,7 +765,7 @@ __device__ __forceinline__ void face_record(const Geo& g, const Gas& gas, const 
     }
     micro_slope(bL, U, V, lam, gas.K, aL);
     micro_slope(bR, U, V, lam, gas.K, aR);
-    double sh = 0.8 * (1.0 - gas.Pr) * lam * lam / rho;
+    double sh = shakhov_prefactor(gas) * lam * lam / rho;
     double vals[NFP] = {rho, U, V, lam, sh * q0[0], sh * q0[1],
                         aL[0], aL[1], aL[2], aL[3], aR[0], aR[1], aR[2], aR[3],
                         0, 0, 0, 0,
@@ -1045,8 +1054,8 @@ __device__ __forceinline__ void face_flux(const T* P, T u, T v, T un, T Gup, T H
     T G0 = rho * lam / T(M_PI) * dexp(-lam * c2);
     T H0 = T(K_int) / (T(2) * lam) * G0;
     T sk = P[4] * cx + P[5] * cy;
-    T Geq = G0 * (T(1) + sk * (T(2) * lam * c2 + T(K_int) - T(5)));
-    T Heq = H0 * (T(1) + sk * (T(2) * lam * c2 + T(K_int) - T(3)));
+    T Geq = G0 * (T(1) + sk * (T(2) * lam * c2 - T(4)));
+    T Heq = H0 * (T(1) + sk * (T(2) * lam * c2 - T(2)));
     T aG, aH, bG, bH;
     if (un > T(0)) {
         slope_poly<T>(P + 6, u, v, lam, K_int, aG, aH);
@@ -1253,7 +1262,7 @@ __global__ void k_cell_prep(Geo g, Gas gas, double* __restrict__ Wt, const doubl
         prim_of(w, gas.K, rho, U, V, lam);
     }
     double ti = (rho / (2.0 * lam)) / mu_of(gas, 1.0 / lam);
-    double sh = 0.8 * (1.0 - gas.Pr) * lam * lam / rho;
+    double sh = shakhov_prefactor(gas) * lam * lam / rho;
     double vals[NCP] = {rho * lam / M_PI, U, V, lam, sh * q[c], sh * q[g.nc + c], ti};
     for (int m = 0; m < NCP; ++m) cp[m * g.nc + c] = vals[m];
     tau_inv[c] = ti;
@@ -1282,8 +1291,8 @@ __global__ void __launch_bounds__(256) k_micro_residual(Geo g, Vel vel, Gas gas,
         T G0 = pref * dexp(-lam * c2);
         T H0 = T(gas.K_int) / (T(2) * lam) * G0;
         T sk = shx * cx + shy * cy;
-        T Gt = G0 * (T(1) + sk * (T(2) * lam * c2 + T(gas.K_int) - T(5)));
-        T Ht = H0 * (T(1) + sk * (T(2) * lam * c2 + T(gas.K_int) - T(3)));
+        T Gt = G0 * (T(1) + sk * (T(2) * lam * c2 - T(4)));
+        T Ht = H0 * (T(1) + sk * (T(2) * lam * c2 - T(2)));
         r[ig] = (Gt - f[ig]) * ti - div[ig];
         r[ho + ig] = (Ht - f[ho + ig]) * ti - div[ho + ig];
     }
@@ -1685,7 +1694,8 @@ size_t sweep_wave_lds_bytes(int nc, int nx, int nw, int W, int I, int NP) {
 // wall densities.  wprev != nullptr: the wall densities of this sweep are
 // formed in the prologue from the nprev partial sums of the previous sweep
 // (every block alike, in a fixed order; block 0 also stores them to
-// drho_out); otherwise they are read from drho (nullptr: zero).
+// drho_out; one thread per wall side, so n_wall <= blockDim.x); otherwise
+// they are read from drho (nullptr: zero).
 template <typename T, int R, int NP>
 __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, const T* __restrict__ r,
                                                     T* __restrict__ df, const T* __restrict__ coef_g,
@@ -1897,6 +1907,224 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
     for (int j = threadIdx.x; j < nw; j += blockDim.x) {
         double s = 0.0;
         for (int ww = 0; ww < W; ++ww) s += red[(size_t)ww * nw + j];
+        wpart[(size_t)blockIdx.x * nw + j] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Ordered sweep with the distributions streamed through the cache hierarchy,
+// for levels whose tiles do not fit in LDS next to enough wavefronts.
+//
+// One wavefront per velocity, lane = row and R row slots per lane as in
+// k_sweep_wave, with the same one-lane rotation for the y-upwind neighbour.
+// Each lane walks its own rows, so the cells it reads at successive steps are
+// adjacent in memory: it loads r, the cell coefficient and the cell flags of
+// the cell it will reach SD steps later into a register ring (the cache
+// lines it touches are reused over the following steps) and stores each
+// result directly.  The wall ghosts C_k drho_w of the velocity are formed
+// once per wavefront in LDS and added when the sweep reaches their cell; the
+// G values at wall cells are kept in LDS for the wall sums of the epilogue.
+// No tile lives in LDS, so the footprint does not grow with the level.
+// Arguments as for k_sweep_wave (wprev: n_wall <= blockDim.x).
+
+// prefetch distance in steps (the ring takes SD x R x (NP + 2) registers)
+template <typename T>
+constexpr int sweep_stream_sd() {
+    return sizeof(T) == 8 ? 4 : 8;
+}
+
+// LDS bytes of k_sweep_stream for W wavefronts and NP planes
+template <typename T>
+size_t sweep_stream_lds_bytes(int nx, int nw, int W, int NP) {
+    size_t b = 64 * (size_t)W * sizeof(double)                          // dsum
+               + ((size_t)nx + 5 * (size_t)nw + (size_t)W * (NP + 1) * nw) * sizeof(T) + 4 * (size_t)nw;
+    return (b + 15) & ~(size_t)15;
+}
+
+template <typename T, int R, int NP>
+__global__ void __launch_bounds__(512) k_sweep_stream(Geo g, Vel vel, int K_int, const T* __restrict__ r,
+                                                      T* __restrict__ df, const T* __restrict__ coef_g,
+                                                      const unsigned* __restrict__ flags_g,
+                                                      const double* __restrict__ drho, double* __restrict__ wpart,
+                                                      const double* __restrict__ wprev, int nprev,
+                                                      double* __restrict__ drho_out) {
+    extern __shared__ __attribute__((aligned(16))) double smem_d[];
+    constexpr int SD = sweep_stream_sd<T>();
+    const int nc = g.nc, nx = g.nx, ny = g.ny, nw = g.n_wall, nk = vel.nk;
+    const int W = blockDim.x >> 6, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double* dsum = smem_d;                                  // [64 W]
+    T* invdx = (T*)(dsum + 64 * W);                         // [nx]
+    T* wl = invdx + nx;                                     // [5][n_wall]  1/d, lam_w, U_w, V_w, drho
+    T* gw = wl + 5 * (size_t)nw;                            // [W][NP][n_wall]  ghost terms per wavefront
+    T* wv = gw + (size_t)W * NP * nw;                       // [W][n_wall]  G at the wall cells
+    int* wsc = (int*)(wv + (size_t)W * nw);                 // [n_wall]  side + 4 cell
+    const int k = blockIdx.x * W + w;
+    const bool kok = k < nk;
+    const int kk = kok ? k : 0;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) invdx[i] = T(1.0 / g.dx[i]);
+    for (int j = threadIdx.x; j < nw; j += blockDim.x) {
+        wl[j] = T(g.w_invd[j]);
+        wl[nw + j] = T(1.0 / g.w_T[j]);
+        wl[2 * nw + j] = T(g.w_U[j]);
+        wl[3 * nw + j] = T(g.w_V[j]);
+        wl[4 * nw + j] = drho ? T(drho[j]) : T(0);
+        wsc[j] = g.w_side[j] + 4 * g.w_cell[j];
+    }
+    const int ng = nw > 0 ? max(1, (int)blockDim.x / nw) : 1;
+    if (wprev && threadIdx.x < ng * nw) {
+        int j = threadIdx.x % nw, grp = threadIdx.x / nw;
+        double sacc = 0.0;
+        for (int b = grp; b < nprev; b += ng) sacc += wprev[(size_t)b * nw + j];
+        dsum[threadIdx.x] = sacc;
+    }
+    const T u = vel_u<T>(vel, kk), v = vel_v<T>(vel, kk);
+    __syncthreads();
+    if (wprev) {
+        for (int j = threadIdx.x; j < nw; j += blockDim.x) {
+            double sacc = 0.0;
+            for (int grp = 0; grp < ng; ++grp) sacc += dsum[grp * nw + j];
+            double dj = -sacc / g.w_den[j];
+            wl[4 * nw + j] = T(dj);
+            if (blockIdx.x == 0) drho_out[j] = dj;
+        }
+        __syncthreads();
+    }
+    // ghost terms of this velocity: |u_n| / d * C_k drho_w at upwind wall sides
+    T* gwG = gw + (size_t)w * NP * nw;
+    T* gwH = gwG + (NP == 2 ? nw : 0);
+    T* wvw = wv + (size_t)w * nw;
+    for (int j = lane; j < nw; j += 64) {
+        const int sd = wsc[j] & 3;
+        const T un = ((sd & 1) ? T(1) : T(-1)) * (sd < 2 ? u : v);
+        T a = T(0), aH = T(0);
+        if (un < T(0) && (drho || wprev)) {
+            const T lam = wl[nw + j], du = u - wl[2 * nw + j], dv = v - wl[3 * nw + j];
+            const T C = lam / T(M_PI) * dexp(-lam * (du * du + dv * dv));
+            a = -un * wl[j] * (C * wl[4 * nw + j]);
+            aH = -un * wl[j] * (C * T(K_int) / (T(2) * lam) * wl[4 * nw + j]);
+        }
+        gwG[j] = a;
+        if constexpr (NP == 2) gwH[j] = aH;
+        wvw[j] = T(0);
+    }
+    __syncthreads();
+
+    const bool px = u >= T(0), py = v >= T(0);
+    const int shx = px ? 0 : 2, shy = py ? 4 : 6;           // bit offset of the upwind x / y side type
+    const T au = px ? u : -u, av = py ? v : -v;
+    const size_t kc = (size_t)kk * nc, hc = ((size_t)nk + kk) * nc;
+    int rowc[R];
+    bool rowok[R];
+    T by[R], cG[R], cH[R];
+    // ring of the data of steps s .. s + SD - 1
+    T qG[SD][R], qH[SD][R], qc[SD][R];
+    unsigned qf[SD][R];
+#pragma unroll
+    for (int p = 0; p < R; ++p) {
+        const int row = lane + 64 * p;
+        rowok[p] = kok && row < ny;
+        const int iy = rowok[p] ? (py ? row : ny - 1 - row) : 0;
+        rowc[p] = iy * nx;
+        by[p] = rowok[p] ? av * T(1.0 / g.dy[iy]) : T(0);
+        cG[p] = T(0);
+        cH[p] = T(0);
+    }
+    auto load = [&](int p, int s, T& rg, T& rh, T& cf, unsigned& fl) {
+        const int jx = s - (lane + 64 * p);
+        if (rowok[p] && (unsigned)jx < (unsigned)nx) {
+            const int c = rowc[p] + (px ? jx : nx - 1 - jx);
+            rg = r[kc + c];
+            if constexpr (NP == 2) rh = r[hc + c];
+            cf = coef_g[c];
+            fl = flags_g[c];
+        }
+    };
+#pragma unroll
+    for (int i = 0; i < SD; ++i)
+#pragma unroll
+        for (int p = 0; p < R; ++p) {
+            qG[i][p] = T(0);
+            qH[i][p] = T(0);
+            qc[i][p] = T(-1);
+            qf[i][p] = 0u;
+            load(p, i, qG[i][p], qH[i][p], qc[i][p], qf[i][p]);
+        }
+    const int nsteps = nx + ny - 1;
+    for (int s0 = 0; s0 < nsteps; s0 += SD) {
+#pragma unroll
+        for (int i = 0; i < SD; ++i) {
+            const int s = s0 + i;
+            T rotG[R], rotH[R];
+#pragma unroll
+            for (int p = 0; p < R; ++p) {
+                rotG[p] = lane_rotate1(cG[p]);
+                if constexpr (NP == 2) rotH[p] = lane_rotate1(cH[p]);
+            }
+#pragma unroll
+            for (int p = 0; p < R; ++p) {
+                const int jx = s - (lane + 64 * p);
+                const bool valid = rowok[p] && (unsigned)jx < (unsigned)nx;
+                const int c = rowc[p] + (px ? jx : nx - 1 - jx);
+                T rG = qG[i][p], rH = qH[i][p], cf = qc[i][p];
+                const unsigned fl = qf[i][p];
+                load(p, s + SD, qG[i][p], qH[i][p], qc[i][p], qf[i][p]);
+                T nbG = rotG[p], nbH = NP == 2 ? rotH[p] : T(0);
+                if (R > 1 && lane == 0) {
+                    nbG = p > 0 ? rotG[p > 0 ? p - 1 : 0] : T(0);
+                    if constexpr (NP == 2) nbH = p > 0 ? rotH[p > 0 ? p - 1 : 0] : T(0);
+                }
+                const unsigned tpx = (fl >> shx) & 3u, tpy = (fl >> shy) & 3u;
+                const int ix = px ? jx : nx - 1 - jx;
+                const T idx = invdx[valid ? ix : 0];
+                const T bx = au * idx, byp = by[p];
+                if (valid && (tpx == 1u || tpy == 1u)) {
+                    // upwind wall sides: their ghost terms (wall sides of a
+                    // cell are numbered in side order from fl >> 9)
+                    int j = (int)(fl >> FLAG_WALL_SHIFT);
+                    for (int q = 0; q < 4; ++q) {
+                        if (((fl >> (2 * q)) & 3u) != 1u) continue;
+                        if (2 * q == shx || 2 * q == shy) {
+                            rG += gwG[j];
+                            if constexpr (NP == 2) rH += gwH[j];
+                        }
+                        ++j;
+                    }
+                }
+                const T D = cf + (tpx == 3u ? T(0) : bx) + (tpy == 3u ? T(0) : byp);
+                const T inv = sweep_rcp(D);
+                const T exG = tpx == 0u ? cG[p] : T(0), eyG = tpy == 0u ? nbG : T(0);
+                T vG = (rG + bx * exG + byp * eyG) * inv;
+                vG = cf < T(0) ? T(0) : vG;
+                cG[p] = vG;
+                if (valid) {
+                    df[kc + c] = vG;
+                    if (fl & (0x55u)) {   // a side of type 1 (wall): keep G there
+                        int j = (int)(fl >> FLAG_WALL_SHIFT);
+                        for (int q = 0; q < 4; ++q)
+                            if (((fl >> (2 * q)) & 3u) == 1u) wvw[j++] = vG;
+                    }
+                }
+                if constexpr (NP == 2) {
+                    const T exH = tpx == 0u ? cH[p] : T(0), eyH = tpy == 0u ? nbH : T(0);
+                    T vH = (rH + bx * exH + byp * eyH) * inv;
+                    vH = cf < T(0) ? T(0) : vH;
+                    cH[p] = vH;
+                    if (valid) df[hc + c] = vH;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // the block's sums over its velocities of w_k u_n dG_k at the wall sides
+    for (int j = threadIdx.x; j < nw; j += blockDim.x) {
+        const int sd = wsc[j] & 3;
+        double s = 0.0;
+        for (int ww = 0; ww < W; ++ww) {
+            const int kw = blockIdx.x * W + ww;
+            if (kw >= nk) break;
+            const double un = ((sd & 1) ? 1.0 : -1.0) * (sd < 2 ? vel.u[kw] : vel.v[kw]);
+            if (un > 0.0) s += vel.w[kw] * un * double(wv[(size_t)ww * nw + j]);
+        }
         wpart[(size_t)blockIdx.x * nw + j] = s;
     }
 }

@@ -43,6 +43,7 @@ struct miugks_ctx {
     size_t esize = 8;
     int nk = 0, nu = 0, nv = 0, L = 1;
     int nu1 = 2, nu2 = 1, nuc = 10;
+    int FL = 1;   // levels of the FAS prediction (the first FL of the L levels)
     double dtn_growth = 0.0;
     bool renorm = false;
     HostVel hv;
@@ -71,9 +72,11 @@ struct miugks_ctx {
     std::vector<char> sweep_lds;
     // wavefront sweep (k_sweep_wave): side types and launch shape per level
     // (W = 0: not used on that level)
+    // (stream: k_sweep_stream, one velocity per wavefront, instead)
     struct WaveCfg {
         int W = 0, I = 1, R = 1, blocks = 0;
         size_t lds = 0;
+        bool stream = false;
     };
     std::vector<unsigned char*> stype;
     std::vector<void*> coefT;   // 1/tau + 1/dt_n per level in the distribution's type
@@ -249,6 +252,25 @@ hipError_t set_wave_lds_t(int R, int bytes) {
     }
 }
 
+template <typename T, int NP>
+hipError_t set_stream_lds_t(int R, int bytes) {
+    auto set = [bytes](const void* f) {
+        return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    };
+    switch (R) {
+        case 1: return set((const void*)k_sweep_stream<T, 1, NP>);
+        case 2: return set((const void*)k_sweep_stream<T, 2, NP>);
+        case 3: return set((const void*)k_sweep_stream<T, 3, NP>);
+        default: return set((const void*)k_sweep_stream<T, 4, NP>);
+    }
+}
+
+hipError_t set_stream_lds(int prec, int R, int np, int bytes) {
+    if (prec == MIUGKS_FP64)
+        return np == 1 ? set_stream_lds_t<double, 1>(R, bytes) : set_stream_lds_t<double, 2>(R, bytes);
+    return np == 1 ? set_stream_lds_t<float, 1>(R, bytes) : set_stream_lds_t<float, 2>(R, bytes);
+}
+
 hipError_t set_wave_lds(int prec, int R, int np, int bytes) {
     if (prec == MIUGKS_FP64) return np == 1 ? set_wave_lds_t<double, 1>(R, bytes) : set_wave_lds_t<double, 2>(R, bytes);
     return np == 1 ? set_wave_lds_t<float, 1>(R, bytes) : set_wave_lds_t<float, 2>(R, bytes);
@@ -332,7 +354,8 @@ struct Path {
         const miugks_ctx::WaveCfg& wc = np == 1 ? c->wave1[l] : c->wave[l];
         // the wall densities from the last sweep's partial sums: inside the
         // wavefront sweep where they are few, else by k_drho
-        const bool in_sweep = !drho_current && g.n_wall && wc.W &&
+        // (the sweep's prologue takes one thread per wall side)
+        const bool in_sweep = !drho_current && g.n_wall && wc.W && g.n_wall <= 64 * wc.W &&
                               (long)c->wparts[l] * g.n_wall <= 16L * 64 * wc.W && !getenv("MIUGKS_DRHO_KERNEL");
         if (!drho_current && g.n_wall && !in_sweep)
             LAUNCH(c, "drho", (double)g.n_wall * c->wparts[l] * 8, k_drho, dim3((g.n_wall + 3) / 4), dim3(256), g,
@@ -342,7 +365,31 @@ struct Path {
         const char* name = names[l < 8 ? l : 7];
         // the sweep leaves its partial sums in the other buffer
         std::swap(c->wbuf[l], c->wbuf_alt[l]);
-        if (wc.W) {
+        if (wc.W && wc.stream) {
+#define MIUGKS_STREAM_LAUNCH(RR, NP)                                                                            \
+    LAUNCH_SH(c, name, (NP) * arr(c, l), wc.lds, (k_sweep_stream<T, RR, NP>), dim3(wc.blocks), dim3(64 * wc.W),   \
+              g, c->vel, c->gas.K_int, (const T*)c->r[l], (T*)c->df[l], (const T*)c->coefT[l],                 \
+              (const unsigned*)c->flags[l], from_zero ? (const double*)nullptr : (const double*)c->drho[l],    \
+              c->wbuf[l], in_sweep ? (const double*)c->wbuf_alt[l] : (const double*)nullptr, c->wparts[l],      \
+              c->drho[l])
+            if (np == 1) {
+                switch (wc.R) {
+                    case 1: MIUGKS_STREAM_LAUNCH(1, 1); break;
+                    case 2: MIUGKS_STREAM_LAUNCH(2, 1); break;
+                    case 3: MIUGKS_STREAM_LAUNCH(3, 1); break;
+                    default: MIUGKS_STREAM_LAUNCH(4, 1); break;
+                }
+            } else {
+                switch (wc.R) {
+                    case 1: MIUGKS_STREAM_LAUNCH(1, 2); break;
+                    case 2: MIUGKS_STREAM_LAUNCH(2, 2); break;
+                    case 3: MIUGKS_STREAM_LAUNCH(3, 2); break;
+                    default: MIUGKS_STREAM_LAUNCH(4, 2); break;
+                }
+            }
+#undef MIUGKS_STREAM_LAUNCH
+            c->wparts[l] = wc.blocks;
+        } else if (wc.W) {
 #define MIUGKS_WAVE_LAUNCH(RR, NP)                                                                              \
     LAUNCH_SH(c, name, (NP) * arr(c, l), wc.lds, (k_sweep_wave<T, RR, NP>), dim3(wc.blocks), dim3(64 * wc.W), g, \
               c->vel, c->gas.K_int, (const T*)c->r[l], (T*)c->df[l], (const T*)c->coefT[l], c->stype[l],        \
@@ -540,7 +587,7 @@ void fas(miugks_ctx* c, int l) {
     // W0 := W, the frozen Gamma, the forcing P = R - R_split(W0)
     LAUNCH(c, "fas_enter", 28 * nc8, k_fas4_enter, dim3(nb), dim3(256), g, c->gas, (const double*)W, c->fW0[l],
            c->fGam[l], (const double*)c->fR[l], c->fP[l]);
-    if (l == c->L - 1) {
+    if (l == c->FL - 1) {
         for (int i = 0; i < c->nuc; ++i) fas_smooth(c, l, W, Walt);
     } else {
         for (int i = 0; i < c->nu1; ++i) fas_smooth(c, l, W, Walt);
@@ -845,7 +892,37 @@ int build_device(miugks_ctx* ctx) {
             }
             // both forms or neither
             if (!ctx->wave[l].W || !ctx->wave1[l].W) ctx->wave[l].W = ctx->wave1[l].W = 0;
+            // the streamed sweep where the tiles do not fit in LDS (reading
+            // rows lane by lane misses the L1 cache, so an LDS tile is faster
+            // even at one wavefront per CU; MIUGKS_SWEEP_STREAM=1/0 forces it
+            // on/off for every level of more than 32 rows)
+            const char* se = getenv("MIUGKS_SWEEP_STREAM");
+            if (h.ny > 32 && (!se || atoi(se) != 0)) {
+                int sw = getenv("MIUGKS_STREAM_W") ? atoi(getenv("MIUGKS_STREAM_W")) : 4;
+                sw = std::max(1, std::min(sw, 8));
+                for (int np = 1; np <= 2; ++np) {
+                    miugks_ctx::WaveCfg& wc = (np == 2 ? ctx->wave : ctx->wave1)[l];
+                    if (!se && wc.W) continue;
+                    miugks_ctx::WaveCfg sc;
+                    sc.stream = true;
+                    sc.W = sw;
+                    sc.I = 1;
+                    sc.R = (h.ny + 63) / 64;
+                    sc.lds = ctx->prec == MIUGKS_FP64
+                                 ? sweep_stream_lds_bytes<double>(h.nx, (int)h.w_cell.size(), sw, np)
+                                 : sweep_stream_lds_bytes<float>(h.nx, (int)h.w_cell.size(), sw, np);
+                    sc.blocks = (ctx->nk + sw - 1) / sw;
+                    if (sc.lds > (size_t)max_lds) continue;
+                    wc = sc;
+                }
+                if (!ctx->wave[l].W || !ctx->wave1[l].W) ctx->wave[l].W = ctx->wave1[l].W = 0;
+            }
         }
+    }
+    size_t stream_need_max = 0;
+    for (int l = 0; l < ctx->L; ++l) {
+        if (ctx->wave[l].stream) stream_need_max = std::max(stream_need_max, ctx->wave[l].lds);
+        if (ctx->wave1[l].stream) stream_need_max = std::max(stream_need_max, ctx->wave1[l].lds);
     }
     if (wave_need_max > 65536) {
         hipError_t e = hipSuccess;
@@ -853,7 +930,20 @@ int build_device(miugks_ctx* ctx) {
             for (int np = 1; np <= 2 && e == hipSuccess; ++np) e = set_wave_lds(ctx->prec, R, np, (int)wave_need_max);
         if (e != hipSuccess)
             for (int l = 0; l < ctx->L; ++l)
-                if (ctx->wave[l].lds > 65536 || ctx->wave1[l].lds > 65536) ctx->wave[l].W = ctx->wave1[l].W = 0;
+                if ((!ctx->wave[l].stream && ctx->wave[l].lds > 65536) ||
+                    (!ctx->wave1[l].stream && ctx->wave1[l].lds > 65536))
+                    ctx->wave[l].W = ctx->wave1[l].W = 0;
+    }
+    if (stream_need_max > 65536) {
+        hipError_t e = hipSuccess;
+        for (int R = 1; R <= 4 && e == hipSuccess; ++R)
+            for (int np = 1; np <= 2 && e == hipSuccess; ++np)
+                e = set_stream_lds(ctx->prec, R, np, (int)stream_need_max);
+        if (e != hipSuccess)
+            for (int l = 0; l < ctx->L; ++l)
+                if ((ctx->wave[l].stream && ctx->wave[l].lds > 65536) ||
+                    (ctx->wave1[l].stream && ctx->wave1[l].lds > 65536))
+                    ctx->wave[l].W = ctx->wave1[l].W = 0;
     }
     if (need_max > 65536) {
         hipError_t e = ctx->prec == MIUGKS_FP64
@@ -874,7 +964,8 @@ int build_device(miugks_ctx* ctx) {
                     "[miugks] level %d: %dx%d cells, %d wall sides, sweep: %s (wavefronts/block %d, velocities/"
                     "wavefront %d, rows/lane %d, blocks %d, LDS %zu; pipelines/block %d)\n",
                     l, ctx->hl[l].nx, ctx->hl[l].ny, (int)ctx->hl[l].w_cell.size(),
-                    ctx->wave[l].W ? "wavefront" : (ctx->sweep_lds[l] ? "LDS pipelines" : "global memory"),
+                    ctx->wave[l].W ? (ctx->wave[l].stream ? "streamed wavefront" : "wavefront")
+                                   : (ctx->sweep_lds[l] ? "LDS pipelines" : "global memory"),
                     ctx->wave[l].W, ctx->wave[l].I, ctx->wave[l].R, ctx->wave[l].blocks, ctx->wave[l].lds,
                     (int)ctx->sweep_lds[l]);
     {
@@ -1017,8 +1108,8 @@ int build_device(miugks_ctx* ctx) {
         (void)hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device);
         ctx->fas_block_lds.assign(ctx->L, 0);
         size_t acc = 0;
-        if (ctx->L <= FAS_MAXL)
-            for (int l = ctx->L - 1; l >= 0 && ctx->hl[l].nc <= lim; --l) {
+        if (ctx->FL <= FAS_MAXL)
+            for (int l = ctx->FL - 1; l >= 0 && ctx->hl[l].nc <= lim; --l) {
                 size_t need = acc + fas_level_lds_bytes(ctx->hl[l].nx, ctx->hl[l].ny);
                 if (need + sizeof(FasSet) + 1024 > (size_t)max_lds) break;   // static LDS beside it
                 acc = need;
@@ -1031,7 +1122,7 @@ int build_device(miugks_ctx* ctx) {
             for (int l = 0; l < ctx->L; ++l)
                 if (ctx->fas_block_lds[l] > 65536) ctx->fas_block_l0 = std::max(ctx->fas_block_l0, l + 1);
         FasSet& F = ctx->fasset;
-        F.L = ctx->L;
+        F.L = ctx->FL;
         F.nu1 = ctx->nu1;
         F.nu2 = ctx->nu2;
         F.nuc = ctx->nuc;
@@ -1230,6 +1321,7 @@ int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgri
     ctx->nv = v->nv;
     ctx->nk = v->nu * v->nv;
     ctx->L = m->n_levels;
+    ctx->FL = s->fas_levels > 0 ? std::min(s->fas_levels, m->n_levels) : m->n_levels;
     ctx->nu1 = s->nu1;
     ctx->nu2 = s->nu2;
     ctx->nuc = s->nu_coarse;

@@ -191,3 +191,100 @@ def test_config1_converges_with_the_oracle():
     err = field_errors(gpu.macro(), orc.primitive(), orc.lev0.fluid)
     print(f"[parity] cavity16 converged in {n} cycles: {err}", flush=True)
     assert max(err.values()) < 1e-10, err
+
+
+def _correct_vs_oracle(case, seed):
+    """One CS V-cycle of a fresh FP64 context against the oracle."""
+    from paper_1704_03151_amd import Solver
+    gpu = Solver(case, precision="fp64")
+    orc = Oracle(case)
+    fl = orc.lev0.fluid
+    r = wl.random_field((2, case.n_vel, case.ny, case.nx), seed=seed) * fl.reshape(case.ny, case.nx)
+    ti = wl.random_field((case.ny, case.nx), seed=seed + 2, lo=0.5, hi=3.0)
+    orc.cycle = 0
+    gpu.init_macro(case.init)
+    out = gpu.correct(r, ti)
+    gpu.close()
+    rG, rH = to_oracle(r)
+    dG, dH = cs_cycle(orc.cs_levels, orc.levels, orc.prolongs, 0, rG, rH,
+                      orc.level_tau_inv(ti.ravel() * fl), orc.dtn_inv(), orc.params)
+    gG, gH = to_oracle(out)
+    return rel_max(gG, dG), rel_max(gH, dH)
+
+
+@pytest.mark.parametrize("mode", ["lds_pipelines", "global"])
+@pytest.mark.parametrize("name", ["cavity16_kn10", "square20x20", "plate32x24"])
+def test_step5_other_sweep_kernels(name, mode, monkeypatch):
+    """The sweep kernels for levels the wavefront sweep does not take (its
+    tiles exceed LDS): LDS pipelines, and global memory."""
+    monkeypatch.setenv("MIUGKS_NO_WAVE_SWEEP", "1")
+    if mode == "global":
+        monkeypatch.setenv("MIUGKS_NO_LDS_SWEEP", "1")
+    print(f"[parity] {name} sweeps by {mode}", flush=True)
+    eG, eH = _correct_vs_oracle(CASES[name], 47)
+    assert eG < 1e-11 and eH < 1e-11, (eG, eH)
+
+
+def test_step5_fine_level_beyond_wavefront_lds():
+    """Flat plate at its full 128x96 mesh in FP64 (few velocities): the fine
+    level's tiles do not fit LDS, so it sweeps by another kernel while the
+    coarse level uses the wavefront sweep."""
+    case = wl.flat_plate(scale=1, quad="trapezoid", nu=4, nv=4, vlo=-5.0, vhi=5.0, n_levels=2,
+                         precision="fp64", Kn=0.2, nu_coarse=3)
+    print("[parity] plate128x96 with 16 velocities", flush=True)
+    eG, eH = _correct_vs_oracle(case, 53)
+    assert eG < 1e-11 and eH < 1e-11, (eG, eH)
+
+
+STREAM_CASES = {
+    # one row slot per lane, walls on every side
+    "cavity48x40": lambda: wl.cavity(n=48, ny=40, Kn=0.3, n_levels=2, nvel=6, vlo=-4.0, vhi=4.0,
+                                     name="cavity48x40"),
+    # three row slots per lane (the last one ragged)
+    "cavity20x140": lambda: wl.cavity(n=20, ny=140, Kn=0.5, n_levels=2, nvel=5, vlo=-4.0, vhi=4.0,
+                                      name="cavity20x140"),
+    # two row slots, solid body, farfield and outflow boundaries
+    "square80x80": lambda: wl.square_cylinder(scale=2, quad="trapezoid", nu=4, nv=4, vlo=-12.0, vhi=12.0,
+                                              n_levels=2, precision="fp64", nu_coarse=3),
+}
+
+
+@pytest.mark.parametrize("name", list(STREAM_CASES))
+def test_step5_streamed_sweep(name, monkeypatch):
+    """The sweep that streams the distributions through the caches (levels
+    of more than 32 rows), forced on every such level."""
+    monkeypatch.setenv("MIUGKS_SWEEP_STREAM", "1")
+    print(f"[parity] {name} with the streamed sweep", flush=True)
+    eG, eH = _correct_vs_oracle(STREAM_CASES[name](), 59)
+    assert eG < 1e-11 and eH < 1e-11, (eG, eH)
+
+
+@pytest.mark.parametrize("name,levels,fas_levels", [("square20x20", 2, 1), ("cavity16_kn10", 3, 2)])
+def test_step2_fas_on_fewer_levels(name, levels, fas_levels):
+    """The FAS prediction on fewer levels than the CS cycle: one prediction,
+    then three outer cycles."""
+    from paper_1704_03151_amd import Solver
+    case = CASES[name].with_(n_levels=levels, fas_levels=fas_levels)
+    print(f"[parity] {name}: {levels} levels, FAS on {fas_levels}", flush=True)
+    gpu = Solver(case, precision="fp64")
+    orc = Oracle(case)
+    prim, pert = perturbed_state(case, 7)
+    gpu.init_macro(prim)
+    orc.init_macro(prim)
+    W = orc.W.copy()
+    Rt = 0.02 * wl.random_field(W.shape, seed=17) * orc.lev0.fluid
+    out = gpu.predict(W.reshape(4, case.ny, case.nx), Rt.reshape(4, case.ny, case.nx))
+    assert len(orc.fas_levels) == fas_levels
+    ref = fas_cycle(orc.fas_levels, orc.levels, orc.prolongs, 0, W, Rt, orc.params, orc.dtn_inv())
+    for m in range(4):
+        e = rel_max(out[m].ravel(), ref[m])
+        assert e < 1e-11, (m, e)
+    gpu.init_macro(case.init)
+    orc.init_macro(case.init)
+    orc.cycle = 0
+    orc.history = []
+    gpu.iterate(3, tol=0.0)
+    orc.iterate(3, tol=0.0)
+    err = field_errors(gpu.macro(), orc.primitive(), orc.lev0.fluid)
+    assert max(err.values()) < 1e-10, err
+    gpu.close()

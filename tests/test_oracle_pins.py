@@ -68,31 +68,45 @@ def test_mu_ref_hard_sphere_limit():
     assert abs(gm.mu_ref_vhs(1.0, 0.5) - 5.0 * math.sqrt(math.pi) / 16.0) < 1e-15
 
 
-def test_shakhov_reduction_and_heat_flux():
-    """Reduced Shakhov pair = integral of the 3-D Shakhov factor over the extra
-    component (K_int = 1), and its heat flux is (1 - Pr) q."""
-    rho, U, V, T, Pr = 1.2, 0.3, -0.2, 0.9, 2.0 / 3.0
+def _shakhov_by_integration(rho, U, V, lam, q, Pr, K, cx, cy):
+    """G and H of the Shakhov-type distribution over 2 + K degrees of
+    freedom, by Gauss-Hermite integration over the K extra components xi:
+    f = g (1 + (1 - Pr) (c.q) / ((N + 2) p R T) (s / (R T) - (N + 2))),
+    s = |c|^2 + |xi|^2, N = 2 + K, R T = 1 / (2 lam), p = rho R T."""
+    x, wx = np.polynomial.hermite.hermgauss(24)
+    z = x / math.sqrt(lam)                        # weight exp(-lam z^2) per component
+    wz = wx / math.sqrt(lam)
+    grids = np.meshgrid(*([z] * K), indexing="ij")
+    wts = np.ones_like(grids[0])
+    for wk in np.meshgrid(*([wz] * K), indexing="ij"):
+        wts = wts * wk
+    xi2 = sum(gk * gk for gk in grids)
+    N = 2 + K
+    RT = 0.5 / lam
+    p = rho * RT
+    g = rho * (lam / math.pi) ** (N / 2) * np.exp(-lam * (cx * cx + cy * cy))
+    fac = 1 + (1 - Pr) * (cx * q[0] + cy * q[1]) / ((N + 2) * p * RT) * ((cx * cx + cy * cy + xi2) / RT - (N + 2))
+    return float(np.sum(wts * g * fac)), float(np.sum(wts * g * fac * xi2))
+
+
+@pytest.mark.parametrize("K", [1, 3])
+def test_shakhov_reduction_and_heat_flux(K):
+    """Reduced Shakhov pair = integral of the Shakhov factor over 2 + K_int
+    degrees of freedom; its discrete moments are the conservative variables
+    and its heat flux is (1 - Pr) q (the correction conserves momentum for
+    every K_int, not only for the monatomic K_int = 1)."""
+    rho, U, V, T, Pr = 1.2, 0.3, -0.2, 0.9, 0.72
     lam = 1.0 / T
     q = np.array([0.05, -0.03])
     u, v = np.array([0.7, -0.4, 1.3]), np.array([0.2, 0.9, -1.1])
-    Gs, Hs = gm.shakhov(rho, U, V, lam, q[0], q[1], u, v, 1, Pr)
-    # 3-D: f = g (1 + (1-Pr) c.q / (5 p R T) (c^2/(RT) - 5)), R T = 1/(2 lam), p = rho/(2 lam)
-    xi, wxi = np.polynomial.hermite.hermgauss(40)
-    z = xi / math.sqrt(lam)                       # integrate over z with weight exp(-lam z^2)
-    RT = 0.5 / lam
-    p = rho / (2 * lam)
+    Gs, Hs = gm.shakhov(rho, U, V, lam, q[0], q[1], u, v, K, Pr)
     for j in range(3):
-        cx, cy = u[j] - U, v[j] - V
-        c2 = cx * cx + cy * cy + z * z
-        g = rho * (lam / math.pi) ** 1.5 * np.exp(-lam * (cx * cx + cy * cy))
-        fac = 1 + (1 - Pr) * (cx * q[0] + cy * q[1]) / (5 * p * RT) * (c2 / RT - 5)
-        G = np.sum(wxi * g * fac) / math.sqrt(lam)
-        H = np.sum(wxi * g * fac * z * z) / math.sqrt(lam)
-        assert abs(G - Gs[j]) < 1e-13 and abs(H - Hs[j]) < 1e-13
+        G, H = _shakhov_by_integration(rho, U, V, lam, q, Pr, K, u[j] - U, v[j] - V)
+        assert abs(G - Gs[j]) < 1e-13 and abs(H - Hs[j]) < 1e-13, (K, j, G - Gs[j], H - Hs[j])
     vel = VelocityGrid("trapezoid", 64, 64, -9, 9)
-    G, H = gm.shakhov(rho, U, V, lam, q[0], q[1], vel.u, vel.v, 1, Pr)
+    G, H = gm.shakhov(rho, U, V, lam, q[0], q[1], vel.u, vel.v, K, Pr)
     W = gm.moments(G, H, vel)
-    assert np.allclose(W, gm.conservative(rho, U, V, lam, 3), atol=1e-12)
+    assert np.allclose(W, gm.conservative(rho, U, V, lam, 2 + K), atol=1e-12)
     qq = gm.heat_flux(G, H, vel, U, V)
     assert np.allclose(qq, (1 - Pr) * q, atol=1e-12)
 
@@ -289,6 +303,22 @@ def test_fas_fixed_point_and_convergence():
     assert np.max(np.abs(P + ml.rsplit(W))) < 1e-12
 
 
+def test_fas_on_fewer_levels_is_the_shallower_hierarchy():
+    """A prediction on the first k levels of an L-level case equals the
+    prediction of the same case built with k levels (the coarse levels the
+    FAS cycle does not visit change nothing)."""
+    case = _small_cavity(n=8, n_levels=3, lid=0.15, Kn=0.2)
+    prim = wl.random_macro(case, seed=11, amp=0.05)
+    for k in (1, 2):
+        deep = Oracle(case.with_(fas_levels=k))
+        flat = Oracle(case.with_(n_levels=k))
+        assert len(deep.fas_levels) == k
+        for o in (deep, flat):
+            o.init_macro(prim)
+        R = 0.01 * wl.random_field(deep.W.shape, seed=12) * deep.lev0.fluid
+        assert np.array_equal(deep.predict(R), flat.predict(R))
+
+
 # --------------------------------------------------------------------------- micro correction
 def _cs_setup(case, seed):
     vel = VelocityGrid.from_case(case)
@@ -368,3 +398,14 @@ def test_multigrid_steady_state_equals_single_grid(Kn):
     for s in sols[1:]:
         err = np.max(np.abs(s - sols[0]), axis=1) / np.max(np.abs(sols[0]), axis=1)
         assert np.all(err < 2e-8), err
+
+
+def test_plate_residual_falls_to_round_off():
+    """The flat plate in air (K_int = 3): MIUGKS cycles drive every residual
+    component far below 1e-6 (a Shakhov correction that carried momentum
+    would stall it near 1e-4 at the cells beside the plate)."""
+    case = wl.flat_plate(scale=4, quad="trapezoid", nu=16, nv=16, vlo=-5.0, vhi=5.0, n_levels=2,
+                         precision="fp64", Kn=0.2)
+    o = Oracle(case)
+    ok, res = o.iterate(60, tol=1e-7)
+    assert ok, res

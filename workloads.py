@@ -69,6 +69,7 @@ class Case:
     nu2: int = 1
     nu_coarse: int = 10
     cfl: float = 0.8
+    fas_levels: int = 0           # levels of the FAS prediction (0: all n_levels)
 
     @property
     def nx(self) -> int:
@@ -302,7 +303,7 @@ def square_cylinder(scale=1, **kw) -> Case:
                 wall_x=wx, wall_y=wy, solid=solid, n_levels=5, quad=QUAD_SIMPSON38,
                 nu=100, nv=100, vlo=-15.0, vhi=15.0, Kn=0.1,
                 farfield=(1.0, uinf, 0.0, 1.0), init=init, precision="fp32f",
-                dtn_growth=3.0, **ARGON)
+                dtn_growth=3.0, fas_levels=2, **ARGON)
     args.update(kw)
     return Case(**args)
 
