@@ -105,7 +105,8 @@ typedef struct {
  * Sec. III D), mass_renorm: 1 = keep total mass, 0 = off, -1 = on iff the
  * domain has walls only; fas_levels: levels of the FAS prediction, from the
  * finest (0 or more than n_levels: all of them; the CS correction always
- * uses n_levels). */
+ * uses n_levels); nu_coarse_cs: smoothings of the CS correction on its
+ * coarsest level (0: nu_coarse, which then counts for both cycles). */
 typedef struct {
     int precision;
     int nu1, nu2, nu_coarse;
@@ -113,6 +114,7 @@ typedef struct {
     double dtn_growth;
     int mass_renorm;
     int fas_levels;
+    int nu_coarse_cs;
 } miugks_solver_desc;
 
 /* Nodes and weights of a 1-D rule on [lo, hi] (ignored for Gauss-Hermite,

@@ -42,6 +42,9 @@ class Oracle:
         self.fas_levels = [MacroLevel(lev, self.gas, case.farfield) for lev in self.levels[:nfas]]
         self.cs_levels = [MicroLevel(lev, self.vel, self.gas.K_int) for lev in self.levels]
         self.params = (case.nu1, case.nu2, case.nu_coarse)
+        # the CS cycle may take its own number of coarsest-level smoothings
+        nuc_cs = case.nu_coarse_cs if case.nu_coarse_cs > 0 else case.nu_coarse
+        self.cs_params = (case.nu1, case.nu2, nuc_cs)
         self.closed = case.closed()
         self.cycle = 0
         self.history = []
@@ -127,7 +130,7 @@ class Oracle:
     def correct(self, rG, rH, tau_inv):
         """Step 5: CS V-cycle of the correction equation."""
         return cs_cycle(self.cs_levels, self.levels, self.prolongs, 0, rG, rH,
-                        self.level_tau_inv(tau_inv), self.dtn_inv(), self.params)
+                        self.level_tau_inv(tau_inv), self.dtn_inv(), self.cs_params)
 
     def update(self, dG, dH):
         """Steps 6-7 (+ mass renormalisation in closed domains)."""

@@ -44,7 +44,8 @@ class GasDesc(ctypes.Structure):
 class SolverDesc(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
                 ("nu_coarse", ctypes.c_int), ("cfl", ctypes.c_double),
-                ("dtn_growth", ctypes.c_double), ("mass_renorm", ctypes.c_int), ("fas_levels", ctypes.c_int)]
+                ("dtn_growth", ctypes.c_double), ("mass_renorm", ctypes.c_int), ("fas_levels", ctypes.c_int),
+                ("nu_coarse_cs", ctypes.c_int)]
 
 
 _SIGS = {

@@ -43,6 +43,7 @@ struct miugks_ctx {
     size_t esize = 8;
     int nk = 0, nu = 0, nv = 0, L = 1;
     int nu1 = 2, nu2 = 1, nuc = 10;
+    int nuc_cs = 10;   // smoothings of the CS cycle on its coarsest level
     int FL = 1;   // levels of the FAS prediction (the first FL of the L levels)
     double dtn_growth = 0.0;
     bool renorm = false;
@@ -433,7 +434,7 @@ struct Path {
     // sweep itself needs no initial correction).
     static void cs(miugks_ctx* c, int l) {
         const Geo& g = c->geo[l];
-        int pre = l == c->L - 1 ? c->nuc : c->nu1;
+        int pre = l == c->L - 1 ? c->nuc_cs : c->nu1;
         // the wavefront sweep starts from zero wall densities by itself
         if (g.n_wall && (!c->wave[l].W || pre == 0))
             LAUNCH(c, "zero", (double)g.n_wall * 8, k_zero<double>, dim3(1), dim3(256), c->drho[l],
@@ -482,7 +483,7 @@ struct Path {
     // prolonged coarse correction enters only the wall densities of the next
     // sweep, so it is evaluated at the wall cells only.
     static bool cs_reduced_ok(miugks_ctx* c) {
-        if (c->nu1 < 1 || c->nu2 < 1 || c->nuc < 1 || getenv("MIUGKS_FULL_CS")) return false;
+        if (c->nu1 < 1 || c->nu2 < 1 || c->nuc_cs < 1 || getenv("MIUGKS_FULL_CS")) return false;
         for (int l = 0; l < c->L; ++l)
             if (!c->wave[l].W) return false;
         return true;
@@ -491,7 +492,7 @@ struct Path {
     static void cs_reduced(miugks_ctx* c, int l) {
         const Geo& g = c->geo[l];
         const bool coarsest = l == c->L - 1;
-        int pre = coarsest ? c->nuc : c->nu1;
+        int pre = coarsest ? c->nuc_cs : c->nu1;
         for (int i = 0; i < pre; ++i) {
             // the finest level's last sweep is final only if it is also the coarsest
             int np = (l == 0 && coarsest && i == pre - 1) ? 2 : 1;
@@ -1305,7 +1306,7 @@ int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgri
         return MIUGKS_EINVAL;
     }
     if (v->nu < 1 || v->nv < 1 || !v->u || !v->v || !v->wu || !v->wv || s->nu1 < 0 || s->nu2 < 0 ||
-        s->nu_coarse < 1 || !(s->cfl > 0) || g->K_int < 0 || !(g->Kn > 0) || !(g->T_inf > 0)) {
+        s->nu_coarse < 1 || s->nu_coarse_cs < 0 || s->fas_levels < 0 || !(s->cfl > 0) || g->K_int < 0 || !(g->Kn > 0) || !(g->T_inf > 0)) {
         g_create_error = "bad velocity grid, gas or solver description";
         delete ctx;
         return MIUGKS_EINVAL;
@@ -1325,6 +1326,7 @@ int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgri
     ctx->nu1 = s->nu1;
     ctx->nu2 = s->nu2;
     ctx->nuc = s->nu_coarse;
+    ctx->nuc_cs = s->nu_coarse_cs > 0 ? s->nu_coarse_cs : s->nu_coarse;
     ctx->dtn_growth = s->dtn_growth;
     HostVel& hv = ctx->hv;
     hv.nu = v->nu;

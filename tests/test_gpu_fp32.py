@@ -51,7 +51,7 @@ def test_fp32_steps(name):
     out = gpu.correct(r.astype(np.float32), ti)
     rG, rH = to_oracle(r.astype(np.float32))
     cG, cH = cs_cycle(orc.cs_levels, orc.levels, orc.prolongs, 0, rG, rH, orc.level_tau_inv(ti.ravel() * fl),
-                      orc.dtn_inv(), orc.params)
+                      orc.dtn_inv(), orc.cs_params)
     gG, gH = to_oracle(out)
     assert rel_max(gG, cG) < 2e-5 and rel_max(gH, cH) < 2e-5, (rel_max(gG, cG), rel_max(gH, cH))
     gpu.close()

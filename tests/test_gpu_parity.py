@@ -113,7 +113,7 @@ def test_step5_cs_correction(name):
     out = gpu.correct(r, ti)
     rG, rH = to_oracle(r)
     dG, dH = cs_cycle(orc.cs_levels, orc.levels, orc.prolongs, 0, rG, rH,
-                      orc.level_tau_inv(ti.ravel() * fl), orc.dtn_inv(), orc.params)
+                      orc.level_tau_inv(ti.ravel() * fl), orc.dtn_inv(), orc.cs_params)
     gG, gH = to_oracle(out)
     assert rel_max(gG, dG) < 1e-11 and rel_max(gH, dH) < 1e-11, (rel_max(gG, dG), rel_max(gH, dH))
 
@@ -152,7 +152,7 @@ def test_step5_other_smoothing_counts(nu1, nu2):
     out = gpu.correct(r, ti)
     rG, rH = to_oracle(r)
     dG, dH = cs_cycle(orc.cs_levels, orc.levels, orc.prolongs, 0, rG, rH,
-                      orc.level_tau_inv(ti.ravel() * fl), orc.dtn_inv(), orc.params)
+                      orc.level_tau_inv(ti.ravel() * fl), orc.dtn_inv(), orc.cs_params)
     gG, gH = to_oracle(out)
     assert rel_max(gG, dG) < 1e-11 and rel_max(gH, dH) < 1e-11, (rel_max(gG, dG), rel_max(gH, dH))
     gpu.close()
@@ -207,7 +207,7 @@ def _correct_vs_oracle(case, seed):
     gpu.close()
     rG, rH = to_oracle(r)
     dG, dH = cs_cycle(orc.cs_levels, orc.levels, orc.prolongs, 0, rG, rH,
-                      orc.level_tau_inv(ti.ravel() * fl), orc.dtn_inv(), orc.params)
+                      orc.level_tau_inv(ti.ravel() * fl), orc.dtn_inv(), orc.cs_params)
     gG, gH = to_oracle(out)
     return rel_max(gG, dG), rel_max(gH, dH)
 

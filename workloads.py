@@ -70,6 +70,7 @@ class Case:
     nu_coarse: int = 10
     cfl: float = 0.8
     fas_levels: int = 0           # levels of the FAS prediction (0: all n_levels)
+    nu_coarse_cs: int = 0         # CS smoothings on the coarsest level (0: nu_coarse)
 
     @property
     def nx(self) -> int:
@@ -206,7 +207,7 @@ def config1(**kw) -> Case:
 def config2(**kw) -> Case:
     """Cavity 64x64 tanh-clustered (first cell 0.005), 28x28 Gauss-Hermite, Kn 0.075, 4 levels."""
     args = dict(n=64, first=0.005, Kn=0.075, n_levels=4, quad=QUAD_GAUSS_HERMITE, nvel=28,
-                vlo=0.0, vhi=0.0, precision="fp32f", name="cavity64_kn0.075")
+                vlo=0.0, vhi=0.0, precision="fp32f", name="cavity64_kn0.075", nu_coarse_cs=2)
     args.update(kw)
     return cavity(**args)
 
@@ -248,7 +249,7 @@ def flat_plate(scale=1, **kw) -> Case:
     args = dict(name=f"plate{nx}x{ny}", x=x, y=y, face_type_x=ftx, face_type_y=fty,
                 wall_x=wx, wall_y=wy, solid=np.zeros((ny, nx), np.uint8), n_levels=4,
                 quad=QUAD_SIMPSON38, nu=40, nv=40, vlo=-5.0, vhi=5.0, Kn=0.1,
-                farfield=(1.0, uinf, 0.0, 1.0), init=init, precision="fp32f", **AIR)
+                farfield=(1.0, uinf, 0.0, 1.0), init=init, precision="fp32f", nu_coarse_cs=2, **AIR)
     args.update(kw)
     return Case(**args)
 
@@ -303,7 +304,7 @@ def square_cylinder(scale=1, **kw) -> Case:
                 wall_x=wx, wall_y=wy, solid=solid, n_levels=5, quad=QUAD_SIMPSON38,
                 nu=100, nv=100, vlo=-15.0, vhi=15.0, Kn=0.1,
                 farfield=(1.0, uinf, 0.0, 1.0), init=init, precision="fp32f",
-                dtn_growth=3.0, fas_levels=2, **ARGON)
+                dtn_growth=3.0, fas_levels=2, nu_coarse_cs=2, **ARGON)
     args.update(kw)
     return Case(**args)
 
