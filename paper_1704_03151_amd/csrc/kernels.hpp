@@ -1804,21 +1804,31 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
     int rowc[R];                                            // first cell of the slot's row
     bool rowok[R];
     T by[R], cG[R], cH[R];
-    T nf_cf[R], nf_idx[R], nf_rG[R], nf_rH[R];              // data of the slot's next cell
-    unsigned nf_sc[R];
+    // data of a cell the slot reaches later, in a ring of three buffers: a
+    // step reads one and fills the one read the step before (for two steps
+    // on), so an LDS read has a whole step to return
+    struct Ahead {
+        T cf, idx, rG, rH;
+        unsigned sc;
+    };
+    Ahead nA[R], nB[R], nC[R];
     // a lane outside the current diagonal fetches the dummy column t mod nx:
     // a clamped column would put every such lane on one LDS bank
     const int dcol = t0 % nx;
-    auto fetch = [&](int p, int jx) {
+    auto fetch = [&](Ahead& n, int p, int jx) {
         int jc = (jx < 0 || jx >= nx) ? dcol : jx;
         int ix = px ? jc : nx - 1 - jc;
         int c = rowc[p] + ix;
-        nf_cf[p] = coef[c];
-        nf_sc[p] = st[c];
-        nf_idx[p] = invdx[ix];
-        nf_rG[p] = tG[c];
-        if constexpr (NP == 2) nf_rH[p] = tH[c];
+        n.cf = coef[c];
+        n.sc = st[c];
+        n.idx = invdx[ix];
+        n.rG = tG[c];
+        n.rH = T(0);
+        if constexpr (NP == 2) n.rH = tH[c];
     };
+    // results of lanes off the diagonal go to a word of their own (the
+    // prologue's partial sums are no longer needed): no branch per step
+    T* dump = (T*)dsum + 64 * w + lane;
 #pragma unroll
     for (int p = 0; p < R; ++p) {
         int row = t0 + 64 * p;
@@ -1828,11 +1838,11 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
         by[p] = rowok[p] ? av * T(1.0 / g.dy[iy]) : T(0);
         cG[p] = T(0);
         cH[p] = T(0);
-        nf_rH[p] = T(0);
-        fetch(p, -row);
+        fetch(nA[p], p, -row);
+        fetch(nB[p], p, 1 - row);
     }
-    const int nsteps = nx + ny - 1;
-    for (int s = 0; s < nsteps; ++s) {
+    // step s with the data in cur; fill receives those of step s + 2
+    auto step = [&](int s, const Ahead(&cur)[R], Ahead(&fill)[R]) {
         T rotG[R], rotH[R];
 #pragma unroll
         for (int p = 0; p < R; ++p) {
@@ -1843,35 +1853,43 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
         for (int p = 0; p < R; ++p) {
             int jx = s - (t0 + 64 * p);
             bool valid = rowok[p] && (unsigned)jx < (unsigned)nx;
-            T cf = nf_cf[p], idx = nf_idx[p], rG = nf_rG[p], rH = nf_rH[p];
-            unsigned sc = nf_sc[p];
+            const Ahead& d = cur[p];
             int c = rowc[p] + (px ? jx : nx - 1 - jx);
-            fetch(p, jx + 1);
+            fetch(fill[p], p, jx + 2);
             T nbG = rotG[p], nbH = NP == 2 ? rotH[p] : T(0);
             if (R > 1 && lane == 0) {
                 nbG = p > 0 ? rotG[p > 0 ? p - 1 : 0] : T(0);
                 if constexpr (NP == 2) nbH = p > 0 ? rotH[p > 0 ? p - 1 : 0] : T(0);
             }
-            unsigned tpx = (sc >> shx) & 3u, tpy = (sc >> shy) & 3u;
-            T bx = au * idx, byp = by[p];
+            unsigned tpx = (d.sc >> shx) & 3u, tpy = (d.sc >> shy) & 3u;
+            T bx = au * d.idx, byp = by[p];
             // transport diagonal: every downwind side, and an upwind side
             // only if it is an outflow (where the two cancel)
-            T D = cf + (tpx == 3u ? T(0) : bx) + (tpy == 3u ? T(0) : byp);
+            T D = d.cf + (tpx == 3u ? T(0) : bx) + (tpy == 3u ? T(0) : byp);
             T inv = sweep_rcp(D);
             T exG = tpx == 0u ? cG[p] : T(0), eyG = tpy == 0u ? nbG : T(0);
-            T vG = (rG + bx * exG + byp * eyG) * inv;
-            vG = cf < T(0) ? T(0) : vG;
-            if (valid) tG[c] = vG;
+            T vG = (d.rG + bx * exG + byp * eyG) * inv;
+            vG = d.cf < T(0) ? T(0) : vG;
+            *(valid ? tG + c : dump) = vG;
             cG[p] = vG;
             if constexpr (NP == 2) {
                 T exH = tpx == 0u ? cH[p] : T(0), eyH = tpy == 0u ? nbH : T(0);
-                T vH = (rH + bx * exH + byp * eyH) * inv;
-                vH = cf < T(0) ? T(0) : vH;
-                if (valid) tH[c] = vH;
+                T vH = (d.rH + bx * exH + byp * eyH) * inv;
+                vH = d.cf < T(0) ? T(0) : vH;
+                *(valid ? tH + c : dump) = vH;
                 cH[p] = vH;
             }
         }
+    };
+    const int nsteps = nx + ny - 1;
+    int s = 0;
+    for (; s + 2 < nsteps; s += 3) {
+        step(s, nA, nC);
+        step(s + 1, nB, nA);
+        step(s + 2, nC, nB);
     }
+    if (s < nsteps) step(s, nA, nC);
+    if (s + 1 < nsteps) step(s + 1, nB, nA);
     __syncthreads();
     if (nq > 0) {
         wave_store<T>(df + (size_t)k0 * nc, tw, nq * nc, lane);
