@@ -1044,27 +1044,59 @@ __global__ void k_wall_finalize(Geo g, const double* __restrict__ part, int nkc,
     out[j] = -s / g.w_den[j];
 }
 
+// The velocity-independent parts of an interface record, formed once per
+// face: the Maxwellian prefactor, K_int/(2 lam), and each micro-slope as
+// a0' + a1 u + a2 v + a3 (u^2 + v^2)/2 for G with a0' = a0 + a3 K_int/(4 lam),
+// plus a3/(2 lam) for H (the slope polynomials of slope_poly)
+template <typename T>
+struct FaceConst {
+    T pre, U, V, lam, shx, shy, hK;
+    T a[3][4];   // left, right and time slopes, constant term folded
+    T dH[3];
+    T q[5];
+};
+
+template <typename T>
+__device__ __forceinline__ void face_const(const T* P, int K_int, FaceConst<T>& F) {
+    T lam = P[3];
+    T inv2l = T(1) / (T(2) * lam);
+    F.pre = P[0] * lam / T(M_PI);
+    F.U = P[1];
+    F.V = P[2];
+    F.lam = lam;
+    F.shx = P[4];
+    F.shy = P[5];
+    F.hK = T(K_int) * inv2l;
+    for (int i = 0; i < 3; ++i) {
+        const T* a = P + 6 + 4 * i;
+        F.a[i][0] = a[0] + T(0.5) * a[3] * F.hK;
+        F.a[i][1] = a[1];
+        F.a[i][2] = a[2];
+        F.a[i][3] = T(0.5) * a[3];
+        F.dH[i] = a[3] * inv2l;
+    }
+    for (int m = 0; m < 5; ++m) F.q[m] = P[18 + m];
+}
+
 // UGKS time-averaged flux of G and H through an interior face for one
 // velocity, normal pointing from L to R (Sec. II A 1; see the interface record)
 template <typename T>
-__device__ __forceinline__ void face_flux(const T* P, T u, T v, T un, T Gup, T Hup, T sGup, T sHup,
-                                          int K_int, T& PG, T& PH) {
-    T rho = P[0], U = P[1], V = P[2], lam = P[3];
-    T cx = u - U, cy = v - V, c2 = cx * cx + cy * cy;
-    T G0 = rho * lam / T(M_PI) * dexp(-lam * c2);
-    T H0 = T(K_int) / (T(2) * lam) * G0;
-    T sk = P[4] * cx + P[5] * cy;
-    T Geq = G0 * (T(1) + sk * (T(2) * lam * c2 - T(4)));
-    T Heq = H0 * (T(1) + sk * (T(2) * lam * c2 - T(2)));
-    T aG, aH, bG, bH;
-    if (un > T(0)) {
-        slope_poly<T>(P + 6, u, v, lam, K_int, aG, aH);
-    } else {
-        slope_poly<T>(P + 10, u, v, lam, K_int, aG, aH);
-    }
-    slope_poly<T>(P + 14, u, v, lam, K_int, bG, bH);
-    PG = un * (P[18] * Geq + P[19] * un * aG * G0 + P[20] * bG * G0 + P[21] * Gup + P[22] * un * sGup);
-    PH = un * (P[18] * Heq + P[19] * un * aH * H0 + P[20] * bH * H0 + P[21] * Hup + P[22] * un * sHup);
+__device__ __forceinline__ void face_flux(const FaceConst<T>& F, T u, T v, T un, T Gup, T Hup, T sGup, T sHup,
+                                          T& PG, T& PH) {
+    T cx = u - F.U, cy = v - F.V, c2 = cx * cx + cy * cy;
+    T G0 = F.pre * dexp(-F.lam * c2);
+    T H0 = F.hK * G0;
+    T sk = F.shx * cx + F.shy * cy;
+    T Geq = G0 * (T(1) + sk * (T(2) * F.lam * c2 - T(4)));
+    T Heq = H0 * (T(1) + sk * (T(2) * F.lam * c2 - T(2)));
+    T q2 = u * u + v * v;
+    const int side = un > T(0) ? 0 : 1;
+    T aG = F.a[side][0] + F.a[side][1] * u + F.a[side][2] * v + F.a[side][3] * q2;
+    T aH = aG + F.dH[side];
+    T bG = F.a[2][0] + F.a[2][1] * u + F.a[2][2] * v + F.a[2][3] * q2;
+    T bH = bG + F.dH[2];
+    PG = un * (F.q[0] * Geq + F.q[1] * un * aG * G0 + F.q[2] * bG * G0 + F.q[3] * Gup + F.q[4] * un * sGup);
+    PH = un * (F.q[0] * Heq + F.q[1] * un * aH * H0 + F.q[2] * bH * H0 + F.q[3] * Hup + F.q[4] * un * sHup);
 }
 
 // Step 1: div_ik = (1/V_i) sum_faces S u_n ftilde (outward) for G and H, and
@@ -1106,6 +1138,8 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
                     size_t stride = 2 * nc;
                     A P[23];
                     for (int m = 0; m < 23; ++m) P[m] = A(rec[m * stride]);
+                    FaceConst<A> FC;
+                    face_const<A>(P, gas.K_int, FC);
                     FaceGeom<T> fg;
                     face_geom<T>(g, R, d, fg);
                     // the stencil values of the next velocity load while this one computes
@@ -1120,7 +1154,7 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
                         T Gu, Hu, sGt, sHt;
                         face_upwind_vals<T, T>(fg, cur, T(un), Gu, Hu, sGt, sHt);
                         A Gup = Gu, Hup = Hu, sGu = sGt, sHu = sHt, PG, PH;
-                        face_flux<A>(P, u, v, un, Gup, Hup, sGu, sHu, gas.K_int, PG, PH);
+                        face_flux<A>(FC, u, v, un, Gup, Hup, sGu, sHu, PG, PH);
                         dG[j] += sign * sv * PG;
                         dH[j] += sign * sv * PH;
                     }
@@ -1811,7 +1845,7 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
         T cf, idx, rG, rH;
         unsigned sc;
     };
-    Ahead nA[R], nB[R], nC[R];
+    Ahead nA[R], nB[R], nC[R], nD[R];
     // a lane outside the current diagonal fetches the dummy column t mod nx:
     // a clamped column would put every such lane on one LDS bank
     const int dcol = t0 % nx;
@@ -1840,6 +1874,7 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
         cH[p] = T(0);
         fetch(nA[p], p, -row);
         fetch(nB[p], p, 1 - row);
+        fetch(nC[p], p, 2 - row);
     }
     // step s with the data in cur; fill receives those of step s + 2
     auto step = [&](int s, const Ahead(&cur)[R], Ahead(&fill)[R]) {
@@ -1855,7 +1890,7 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
             bool valid = rowok[p] && (unsigned)jx < (unsigned)nx;
             const Ahead& d = cur[p];
             int c = rowc[p] + (px ? jx : nx - 1 - jx);
-            fetch(fill[p], p, jx + 2);
+            fetch(fill[p], p, jx + 3);
             T nbG = rotG[p], nbH = NP == 2 ? rotH[p] : T(0);
             if (R > 1 && lane == 0) {
                 nbG = p > 0 ? rotG[p > 0 ? p - 1 : 0] : T(0);
@@ -1883,13 +1918,15 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
     };
     const int nsteps = nx + ny - 1;
     int s = 0;
-    for (; s + 2 < nsteps; s += 3) {
-        step(s, nA, nC);
+    for (; s + 3 < nsteps; s += 4) {
+        step(s, nA, nD);
         step(s + 1, nB, nA);
         step(s + 2, nC, nB);
+        step(s + 3, nD, nC);
     }
-    if (s < nsteps) step(s, nA, nC);
+    if (s < nsteps) step(s, nA, nD);
     if (s + 1 < nsteps) step(s + 1, nB, nA);
+    if (s + 2 < nsteps) step(s + 2, nC, nB);
     __syncthreads();
     if (nq > 0) {
         wave_store<T>(df + (size_t)k0 * nc, tw, nq * nc, lane);
