@@ -35,6 +35,9 @@ HBM_PEAK_GBS = 8000.0
 # same run (--copy-calibration).  Keyed by (workload, precision, kernel); an
 # entry is dropped whenever that kernel changes.
 MEASURED_TRAFFIC = {
+    # profiles/sweep_wave_cavity64_fp32f_hbm_traffic.md: 77 dispatches of the
+    # sweep (every level, G-only and G+H forms), scaled FETCH_SIZE + WRITE_SIZE
+    ("cavity64_kn0.075", "fp32f", "sweep"): 12.19e6,
 }
 
 # what each workload recipe is (the sizes are printed from the case itself)
