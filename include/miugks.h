@@ -146,6 +146,20 @@ int miugks_init_macro(miugks_ctx* ctx, const double* rho, const double* U, const
  * NULL) the four RMS residuals of the last check.  Synchronises the stream. */
 int miugks_iterate(miugks_ctx* ctx, int max_cycles, double tol, int* cycles_done, double res[4]);
 
+/* Full-multigrid start (Sec. III C, the FMG method): the current state
+ * (normally the one miugks_init_macro set) is restricted to the coarsest
+ * level by volume-weighted means; then each level from the coarsest up to
+ * level 1 runs up to cycles_per_level outer cycles as the finest level of
+ * its own sub-hierarchy (stopping early when every RMS residual is below tol),
+ * and its distribution itself, not a correction, is interpolated bilinearly
+ * to the next finer level.  Ends with the state on level 0, the cycle counter
+ * (and so the pseudo step) restarted; the reference mass of a closed domain
+ * is kept.  Follow with miugks_iterate.  cycles_done (may be NULL) receives
+ * the cycles run on the coarse levels.  Returns MIUGKS_OK, or the status of a
+ * level whose cycles diverged (MIUGKS_EDIVERGED): f is then undefined until
+ * miugks_init_macro or miugks_set_f.  Synchronises the stream. */
+int miugks_fmg(miugks_ctx* ctx, int cycles_per_level, double tol, int* cycles_done);
+
 /* Host outputs [ny][nx] (each may be NULL): primitive fields and heat flux of
  * the current distribution. */
 int miugks_get_macro(miugks_ctx* ctx, double* rho, double* U, double* V, double* T, double* qx,

@@ -19,6 +19,8 @@ level.
 """
 from __future__ import annotations
 
+import copy
+
 import numpy as np
 
 from . import gas as gm
@@ -152,6 +154,57 @@ class Oracle:
         dG, dH = self.correct(rG, rH, tau_inv)
         self.update(dG, dH)
         self.cycle += 1
+
+    def _stage(self, top):
+        """The same problem with level `top` as its finest level (a stage of
+        the full-multigrid start): the levels below are dropped, the FAS depth
+        counts from `top`, the pseudo-step counter restarts and the reference
+        mass of a closed domain is kept."""
+        st = copy.copy(self)
+        st.levels = self.levels[top:]
+        st.prolongs = self.prolongs[top:]
+        nfas = self.case.fas_levels if self.case.fas_levels > 0 else len(st.levels)
+        st.fas_levels = [MacroLevel(lev, self.gas, self.case.farfield) for lev in st.levels[:nfas]]
+        st.cs_levels = self.cs_levels[top:]
+        st.cycle = 0
+        st.history = []
+        return st
+
+    def fmg_interpolate(self, l, qc):
+        """FMG interpolation of a full distribution from level l + 1 to level
+        l: the bilinear prolongation where its stencil interpolates (every
+        weight non-negative), the parent cell's value where it would
+        extrapolate, so that a positive distribution stays positive; zero on
+        solid cells."""
+        P = self.prolongs[l]
+        w = np.array(P.w)
+        inside = np.all(w >= 0.0, axis=0)
+        out = np.where(inside, sum(w[a] * qc[..., P.idx[a]] for a in range(4)), qc[..., P.idx[0]])
+        return out * self.levels[l].fluid
+
+    def fmg(self, cycles, tol=1e-6):
+        """Full-multigrid start (Sec. III C, FMG): the current distribution is
+        restricted to the coarsest level (volume-weighted means); each level
+        from the coarsest up to level 1 then runs up to `cycles` outer cycles
+        as the finest level of its own sub-hierarchy, and the distribution it
+        reaches (not a correction) is interpolated bilinearly to the next
+        finer level.  Returns the number of cycles run on the coarse levels."""
+        G, H = self.G, self.H
+        for l in range(len(self.levels) - 1):
+            G = restrict(self.levels[l], G)
+            H = restrict(self.levels[l], H)
+        done = 0
+        for top in range(len(self.levels) - 1, 0, -1):
+            st = self._stage(top)
+            st.set_f(G, H)
+            ok, _ = st.iterate(cycles, tol)
+            done += len(st.history) - (1 if ok else 0)
+            G = self.fmg_interpolate(top - 1, st.G)
+            H = self.fmg_interpolate(top - 1, st.H)
+        self.set_f(G, H)
+        self.cycle = 0
+        self.history = []
+        return done
 
     def iterate(self, max_cycles, tol=1e-6):
         """Run outer cycles until max_c R_rms,c < tol; returns (converged, norms)."""

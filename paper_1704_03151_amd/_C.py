@@ -57,6 +57,7 @@ _SIGS = {
     "miugks_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "miugks_init_macro": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp, _dp]),
     "miugks_iterate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _ip, _dp]),
+    "miugks_fmg": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _ip]),
     "miugks_get_macro": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp]),
     "miugks_get_f": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "miugks_set_f": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),

@@ -2313,6 +2313,75 @@ __global__ void __launch_bounds__(256) k_defect_walls(Geo g, Geo gc, Vel vel, in
     }
 }
 
+// Full-multigrid start (Sec. III C): the distribution itself, not a
+// correction, moves between levels.
+//
+// fc = volume-weighted mean of f over the fluid children of every coarse
+// cell (the restriction of Sec. II C 1; zero where no child is fluid), both
+// planes, level layout [2][Nk][nc]
+template <typename T>
+__global__ void __launch_bounds__(256) k_restrict_full(Geo g, Geo gc, Vel vel, const T* __restrict__ f,
+                                                       T* __restrict__ fc) {
+    Chunk ch = chunk_of(gc.nc, vel.nk);
+    if (!ch.valid) return;
+    const int C = ch.c, I = C % gc.nx, J = C / gc.nx;
+    const size_t nc = g.nc, ho = (size_t)vel.nk * nc, ncc = gc.nc, hoc = (size_t)vel.nk * ncc;
+    int cc[4];
+    double V[4], vol = 0.0;
+    for (int a = 0; a < 4; ++a) {
+        int c = (2 * J + (a >> 1)) * g.nx + 2 * I + (a & 1);
+        cc[a] = c;
+        V[a] = g.solid[c] ? 0.0 : g.dx[c % g.nx] * g.dy[c / g.nx];
+        vol += V[a];
+    }
+    const double iv = vol > 0.0 ? 1.0 / vol : 0.0;
+    for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
+        size_t kc = (size_t)k * nc;
+        double sG = 0.0, sH = 0.0;
+        for (int a = 0; a < 4; ++a) {
+            sG += V[a] * double(f[kc + cc[a]]);
+            sH += V[a] * double(f[ho + kc + cc[a]]);
+        }
+        fc[(size_t)k * ncc + C] = T(sG * iv);
+        fc[hoc + (size_t)k * ncc + C] = T(sH * iv);
+    }
+}
+
+// f = FMG interpolation of fc on every fluid cell of the fine level: the
+// bilinear prolongation (Sec. II C 3) where its stencil interpolates (every
+// weight non-negative), the parent cell's value where it would extrapolate,
+// so that a positive distribution stays positive; zero on solid cells; both
+// planes
+template <typename T>
+__global__ void __launch_bounds__(256) k_prolong_full(Geo g, Vel vel, int ncc, const T* __restrict__ fc,
+                                                      T* __restrict__ f) {
+    Chunk ch = chunk_of(g.nc, vel.nk);
+    if (!ch.valid) return;
+    const int c = ch.c;
+    const size_t nc = g.nc, ho = (size_t)vel.nk * nc, hoc = (size_t)vel.nk * ncc;
+    const bool solid = g.solid[c];
+    int id[4];
+    double w[4];
+    bool inside = true;
+    for (int a = 0; a < 4; ++a) {
+        id[a] = solid ? 0 : g.p_idx[a * g.nc + c];
+        w[a] = solid ? 0.0 : g.p_w[a * g.nc + c];
+        inside = inside && w[a] >= 0.0;
+    }
+    if (!inside)   // the parent alone (stencil entry 0)
+        for (int a = 0; a < 4; ++a) w[a] = a == 0 ? 1.0 : 0.0;
+    for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
+        size_t kc = (size_t)k * ncc;
+        double aG = 0.0, aH = 0.0;
+        for (int a = 0; a < 4; ++a) {
+            aG += w[a] * double(fc[kc + id[a]]);
+            aH += w[a] * double(fc[hoc + kc + id[a]]);
+        }
+        f[(size_t)k * nc + c] = T(aG);
+        f[ho + (size_t)k * nc + c] = T(aH);
+    }
+}
+
 // df_fine += I_H^h df_coarse (bilinear with extrapolation, Sec. II C 3)
 template <typename T>
 __global__ void __launch_bounds__(256) k_prolong_add(Geo g, Vel vel, int ncc, const T* __restrict__ dfc,

@@ -44,7 +44,10 @@ struct miugks_ctx {
     int nk = 0, nu = 0, nv = 0, L = 1;
     int nu1 = 2, nu2 = 1, nuc = 10;
     int nuc_cs = 10;   // smoothings of the CS cycle on its coarsest level
-    int FL = 1;   // levels of the FAS prediction (the first FL of the L levels)
+    int FL = 1;   // levels of the FAS prediction, counted from the finest one in use
+    // finest level the cycles run on: 0, except during a full-multigrid start,
+    // whose stages treat a coarse level as the finest (f then holds that level)
+    int top = 0;
     double dtn_growth = 0.0;
     bool renorm = false;
     HostVel hv;
@@ -288,10 +291,10 @@ struct Path {
 
     // Step 7: W, q of f (optionally after f += df, Step 6)
     static void moments(miugks_ctx* c, const T* df) {
-        const Geo& g = c->geo[0];
+        const Geo& g = c->geo[c->top];
         int nkc = nchunks(c->nk);
         double nc8 = g.nc * 8.0;
-        LAUNCH(c, df ? "update_moments" : "moments", (df ? 3 : 1) * arr(c, 0) + NRAW * nkc * nc8,
+        LAUNCH(c, df ? "update_moments" : "moments", (df ? 3 : 1) * arr(c, c->top) + NRAW * nkc * nc8,
                k_moments_partial<T>, dim3(ntiles(g.nc), nkc), dim3(256), g, c->vel, F(c), df, c->part);
         LAUNCH(c, "chunk_sum", NRAW * (nkc + 1.0) * nc8, k_chunk_sum, dim3(nblk(NRAW * g.nc)), dim3(256),
                (const double*)c->part, nkc, NRAW, g.nc, 1.0, (const unsigned char*)nullptr, c->msum);
@@ -308,12 +311,13 @@ struct Path {
 
     // Step 1: interface records, div, R and the RMS norms (into c->norms)
     static void residual(miugks_ctx* c) {
-        const Geo& g = c->geo[0];
+        const int top = c->top;
+        const Geo& g = c->geo[top];
         int nkc = nchunks(c->nk), nt = ntiles(g.nc);
         double nc8 = g.nc * 8.0;
         // raw moments of the upwind interface distributions, per velocity
         // chunk, summed in chunk order; interface records
-        LAUNCH(c, "face_moments", arr(c, 0) + 2.0 * NRAW * nkc * nc8, k_face_moments_partial<T>, dim3(nt, nkc),
+        LAUNCH(c, "face_moments", arr(c, top) + 2.0 * NRAW * nkc * nc8, k_face_moments_partial<T>, dim3(nt, nkc),
                dim3(256), g, c->vel, F(c), c->part);
         LAUNCH(c, "chunk_sum", 2.0 * NRAW * (nkc + 1) * nc8, k_chunk_sum, dim3(nblk(2 * NRAW * g.nc)), dim3(256),
                (const double*)c->part, nkc, 2 * NRAW, g.nc, 1.0, (const unsigned char*)nullptr, c->msum);
@@ -326,24 +330,25 @@ struct Path {
                (const double*)c->part, nkc, 8, g.nc, 1.0, (const unsigned char*)nullptr, c->msum);
         LAUNCH(c, "timeslope_records", (8.0 + 2 * 8) * nc8, k_face_timeslope_records, dim3(nblk(2 * g.nc)),
                dim3(256), g, c->gas, (const double*)c->msum, c->fp);
-        wall_sums(c, 0, F(c), c->rho_w);
-        LAUNCH(c, "flux_div", 2 * arr(c, 0) + (2.0 * NFP + 4.0 * nkc) * nc8, k_flux_div<T>, dim3(nt, nkc),
+        wall_sums(c, top, F(c), c->rho_w);
+        LAUNCH(c, "flux_div", 2 * arr(c, top) + (2.0 * NFP + 4.0 * nkc) * nc8, k_flux_div<T>, dim3(nt, nkc),
                dim3(256), g, c->vel, c->gas, F(c), c->fp, c->rho_w, (const T*)c->finf, (T*)c->div, c->part);
         LAUNCH(c, "chunk_sum", 4.0 * (nkc + 1) * nc8, k_chunk_sum, dim3(nblk(4 * g.nc)), dim3(256),
                (const double*)c->part, nkc, 4, g.nc, -1.0, g.solid, c->R);
-        LAUNCH(c, "residual_norm", 4 * nc8, k_residual_norm, dim3(1), dim3(256), g, c->hl[0].n_fluid, c->R,
+        LAUNCH(c, "residual_norm", 4 * nc8, k_residual_norm, dim3(1), dim3(256), g, c->hl[top].n_fluid, c->R,
                c->norms);
         c->have_div = true;
     }
 
     // Steps 3-4 (with the positivity guard on c->Wt)
     static void micro_residual(miugks_ctx* c) {
-        const Geo& g = c->geo[0];
+        const int top = c->top;
+        const Geo& g = c->geo[top];
         LAUNCH(c, "cell_prep", (14.0 + NCP) * g.nc * 8, k_cell_prep, dim3(nblk(g.nc)), dim3(256), g, c->gas, c->Wt,
-               c->W, c->q, c->cp, c->tau_inv[0]);
-        LAUNCH(c, "micro_residual", 3 * arr(c, 0) + NCP * g.nc * 8.0, k_micro_residual<T>,
+               c->W, c->q, c->cp, c->tau_inv[top]);
+        LAUNCH(c, "micro_residual", 3 * arr(c, top) + NCP * g.nc * 8.0, k_micro_residual<T>,
                dim3(ntiles(g.nc), nchunks(c->nk)), dim3(256), g, c->vel, c->gas, F(c), (const T*)c->div, c->cp,
-               (T*)c->r[0]);
+               (T*)c->r[top]);
     }
 
     // one smoothing on level l: wall densities from the current correction
@@ -495,7 +500,7 @@ struct Path {
         int pre = coarsest ? c->nuc_cs : c->nu1;
         for (int i = 0; i < pre; ++i) {
             // the finest level's last sweep is final only if it is also the coarsest
-            int np = (l == 0 && coarsest && i == pre - 1) ? 2 : 1;
+            int np = (l == c->top && coarsest && i == pre - 1) ? 2 : 1;
             smooth(c, l, i == 0, i == 0, np);
         }
         if (coarsest) return;
@@ -516,29 +521,29 @@ struct Path {
             LAUNCH(c, "wall_density", (double)g.n_wall * c->nk * 5 * sizeof(T), k_wall_density_prolonged<T>,
                    dim3((g.n_wall + 3) / 4), dim3(256), g, c->vel, (const T*)c->df[l], gc.nc,
                    (const T*)c->df[l + 1], c->drho[l]);
-        for (int i = 0; i < c->nu2; ++i) smooth(c, l, i == 0, false, (l == 0 && i == c->nu2 - 1) ? 2 : 1);
+        for (int i = 0; i < c->nu2; ++i) smooth(c, l, i == 0, false, (l == c->top && i == c->nu2 - 1) ? 2 : 1);
     }
 
     static void correct(miugks_ctx* c) {
-        for (int l = 0; l + 1 < c->L; ++l)
+        for (int l = c->top; l + 1 < c->L; ++l)
             LAUNCH(c, "restrict_cells", (c->geo[l].nc + c->geo[l + 1].nc) * 8.0, k_restrict_cells,
                    dim3(nblk(c->geo[l + 1].nc)), dim3(256), c->geo[l], c->geo[l + 1], 1, c->tau_inv[l],
                    c->tau_inv[l + 1]);
         LAUNCH(c, "sweep_coef", 0.0, k_sweep_coef<T>, dim3(nblk(c->geo[0].nc)), dim3(256), c->coefset);
         if (cs_reduced_ok(c))
-            cs_reduced(c, 0);
+            cs_reduced(c, c->top);
         else
-            cs(c, 0);
+            cs(c, c->top);
     }
 
     // Steps 6-7 and the closed-domain renormalisation
     static void update(miugks_ctx* c) {
-        moments(c, (const T*)c->df[0]);
+        moments(c, (const T*)c->df[c->top]);
         if (c->renorm) {
-            const Geo& g = c->geo[0];
+            const Geo& g = c->geo[c->top];
             LAUNCH(c, "mass", 4.0 * g.nc * 8, k_mass, dim3(1), dim3(1024), g, c->W, c->mass);
             size_t n = 2 * (size_t)c->nk * g.nc;
-            LAUNCH(c, "scale_f", 2 * arr(c, 0), k_scale_f<T>, dim3(nblk((int)std::min<size_t>(n, 1 << 24))),
+            LAUNCH(c, "scale_f", 2 * arr(c, c->top), k_scale_f<T>, dim3(nblk((int)std::min<size_t>(n, 1 << 24))),
                    dim3(256), F(c), n, c->mass, c->M0);
             LAUNCH(c, "scale_moments", 12.0 * g.nc * 8, k_scale_d, dim3(nblk(6 * g.nc)), dim3(256), c->W,
                    4 * (size_t)g.nc, c->mass, c->M0);
@@ -571,8 +576,11 @@ void fas_smooth(miugks_ctx* c, int l, double*& W, double*& Walt) {
 
 // W_l^{n+1} = FAS(l, W_l^n, R_l^n): fW[l] holds W_l^n on entry and the result
 // on exit; fR[l] holds the target residual
+// coarsest level the FAS prediction visits
+int fas_last(const miugks_ctx* c) { return std::min(c->top + c->FL, c->L) - 1; }
+
 void fas(miugks_ctx* c, int l) {
-    if (l >= c->fas_block_l0) {
+    if (l >= c->fas_block_l0 && fas_last(c) == c->fasset.L - 1) {
         FasSet F = c->fasset;
         F.l0 = l;
         double cells = 0;
@@ -588,7 +596,7 @@ void fas(miugks_ctx* c, int l) {
     // W0 := W, the frozen Gamma, the forcing P = R - R_split(W0)
     LAUNCH(c, "fas_enter", 28 * nc8, k_fas4_enter, dim3(nb), dim3(256), g, c->gas, (const double*)W, c->fW0[l],
            c->fGam[l], (const double*)c->fR[l], c->fP[l]);
-    if (l == c->FL - 1) {
+    if (l == fas_last(c)) {
         for (int i = 0; i < c->nuc; ++i) fas_smooth(c, l, W, Walt);
     } else {
         for (int i = 0; i < c->nu1; ++i) fas_smooth(c, l, W, Walt);
@@ -625,11 +633,12 @@ void set_dtn(miugks_ctx* c) {
 
 // Step 2 on the device arrays: fW[0] := W^n, fR[0] := R, result into Wt
 void predict(miugks_ctx* c) {
-    size_t n = 4 * (size_t)c->geo[0].nc;
-    LAUNCH(c, "copy", 24.0 * n, k_copy2, dim3(nblk((int)n)), dim3(256), (const double*)c->W, c->fW[0],
-           (double*)nullptr, (const double*)c->R, c->fR[0], n);
-    fas(c, 0);
-    LAUNCH(c, "copy", 16.0 * n, k_copy2, dim3(nblk((int)n)), dim3(256), (const double*)c->fW[0], c->Wt,
+    const int top = c->top;
+    size_t n = 4 * (size_t)c->geo[top].nc;
+    LAUNCH(c, "copy", 24.0 * n, k_copy2, dim3(nblk((int)n)), dim3(256), (const double*)c->W, c->fW[top],
+           (double*)nullptr, (const double*)c->R, c->fR[top], n);
+    fas(c, top);
+    LAUNCH(c, "copy", 16.0 * n, k_copy2, dim3(nblk((int)n)), dim3(256), (const double*)c->fW[top], c->Wt,
            (double*)nullptr, (const double*)nullptr, (double*)nullptr, n);
 }
 
@@ -676,7 +685,7 @@ int run_cycles(miugks_ctx* c, int max_cycles, double tol, int* done, double* res
     double last[4] = {0, 0, 0, 0};
     double first_max = -1.0;
     int rc = MIUGKS_ENOTCONVERGED;
-    bool graphs = c->use_graphs && !timing(c).on;
+    bool graphs = c->use_graphs && !timing(c).on && c->top == 0;
     if (graphs && (rc = ensure_graphs<T>(c))) return rc;
     for (int it = 0; it < max_cycles; ++it) {
         if (graphs) {
@@ -738,6 +747,53 @@ int run_cycles(miugks_ctx* c, int max_cycles, double tol, int* done, double* res
     if (res)
         for (int m = 0; m < 4; ++m) res[m] = last[m];
     return rc;
+}
+
+// Full-multigrid start (Sec. III C): the state is restricted to the coarsest
+// level; each level from there up to level 1 runs the outer cycles as the
+// finest level of its own sub-hierarchy, and the distribution it reaches is
+// interpolated to the next finer level.  The div buffer is the scratch of
+// the transfers (f holds one level at a time, in that level's layout).
+template <typename T>
+int run_fmg(miugks_ctx* c, int cycles, double tol, int* done) {
+    T* f = (T*)c->f;
+    T* tmp = (T*)c->div;
+    const size_t nk = c->nk;
+    for (int l = 0; l + 1 < c->L; ++l) {
+        const Geo &g = c->geo[l], &gc = c->geo[l + 1];
+        hipLaunchKernelGGL(k_restrict_full<T>, dim3(ntiles(gc.nc), nchunks(c->nk)), dim3(256), 0, c->stream, g, gc,
+                           c->vel, (const T*)f, tmp);
+        (void)hipMemcpyAsync(f, tmp, 2 * nk * gc.nc * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
+    }
+    int total = 0, rc = MIUGKS_OK;
+    for (int top = c->L - 1; top >= 1; --top) {
+        c->top = top;
+        c->cycle = 0;
+        c->have_div = false;
+        Path<T>::moments(c, nullptr);
+        int n = 0;
+        double res[4];
+        rc = run_cycles<T>(c, cycles, tol, &n, res);
+        total += n;
+        if (rc != MIUGKS_OK && rc != MIUGKS_ENOTCONVERGED) break;
+        rc = MIUGKS_OK;
+        const Geo& gf = c->geo[top - 1];
+        (void)hipMemcpyAsync(tmp, f, 2 * nk * c->geo[top].nc * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
+        hipLaunchKernelGGL(k_prolong_full<T>, dim3(ntiles(gf.nc), nchunks(c->nk)), dim3(256), 0, c->stream, gf,
+                           c->vel, c->geo[top].nc, (const T*)tmp, f);
+    }
+    c->top = 0;
+    c->cycle = 0;
+    c->have_div = false;
+    if (done) *done = total;
+    if (rc != MIUGKS_OK) return rc;
+    Path<T>::moments(c, nullptr);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        c->err = std::string("fmg: ") + hipGetErrorString(e);
+        return MIUGKS_EDEVICE;
+    }
+    return check_launch(c);
 }
 
 int build_device(miugks_ctx* ctx) {
@@ -1153,7 +1209,7 @@ void init_f(miugks_ctx* c, const double* dprim) {
 }
 
 int reset_mass(miugks_ctx* c) {
-    hipLaunchKernelGGL(k_mass, dim3(1), dim3(1024), 0, c->stream, c->geo[0], c->W, c->mass);
+    hipLaunchKernelGGL(k_mass, dim3(1), dim3(1024), 0, c->stream, c->geo[c->top], c->W, c->mass);
     double m = 0;
     hipError_t e = hipMemcpyAsync(&m, c->mass, sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1425,6 +1481,7 @@ int miugks_init_macro(miugks_ctx* ctx, const double* rho, const double* U, const
     for (size_t c = 0; c < nc; ++c)
         if (ctx->hl[0].solid[c]) prim[3 * nc + c] = 1.0;
     HIP_TRY(hipMemcpy(ctx->Wt, prim.data(), 4 * nc * sizeof(double), hipMemcpyHostToDevice));
+    ctx->top = 0;
     if (ctx->prec == MIUGKS_FP64)
         init_f<double>(ctx, ctx->Wt);
     else
@@ -1432,6 +1489,16 @@ int miugks_init_macro(miugks_ctx* ctx, const double* rho, const double* U, const
     ctx->cycle = 0;
     ctx->have_div = false;
     return reset_mass(ctx);
+}
+
+int miugks_fmg(miugks_ctx* ctx, int cycles_per_level, double tol, int* cycles_done) {
+    if (!ctx) return MIUGKS_EINVAL;
+    if (cycles_per_level < 0) {
+        ctx->err = "cycles_per_level must be >= 0";
+        return MIUGKS_EINVAL;
+    }
+    if (ctx->prec == MIUGKS_FP64) return run_fmg<double>(ctx, cycles_per_level, tol, cycles_done);
+    return run_fmg<float>(ctx, cycles_per_level, tol, cycles_done);
 }
 
 int miugks_iterate(miugks_ctx* ctx, int max_cycles, double tol, int* cycles_done, double res[4]) {
@@ -1479,6 +1546,7 @@ int miugks_set_f(miugks_ctx* ctx, const void* src, int dtype, int on_device) {
     if (!ctx) return MIUGKS_EINVAL;
     int rc = copy_in(ctx, src, ctx->f, dtype, on_device);
     if (rc) return rc;
+    ctx->top = 0;
     if (ctx->prec == MIUGKS_FP64)
         Path<double>::moments(ctx, nullptr);
     else

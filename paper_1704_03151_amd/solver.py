@@ -107,6 +107,13 @@ class Solver:
         self._check(rc, allow=(_C.ENOTCONVERGED, _C.EDIVERGED))
         return rc, n.value, res
 
+    def fmg(self, cycles_per_level, tol=1e-6):
+        """Full-multigrid start from the current state; returns (status, cycles run)."""
+        n = ctypes.c_int()
+        rc = _C.lib.miugks_fmg(self.h, int(cycles_per_level), float(tol), ctypes.byref(n))
+        self._check(rc, allow=(_C.EDIVERGED,))
+        return rc, n.value
+
     def macro(self):
         shape = (self.case.ny, self.case.nx)
         out = {k: np.zeros(shape) for k in ("rho", "U", "V", "T", "qx", "qy")}

@@ -288,3 +288,25 @@ def test_step2_fas_on_fewer_levels(name, levels, fas_levels):
     err = field_errors(gpu.macro(), orc.primitive(), orc.lev0.fluid)
     assert max(err.values()) < 1e-10, err
     gpu.close()
+
+
+@pytest.mark.parametrize("name,levels", [("cavity16_kn10", 3), ("square20x20", 2), ("plate32x24", 2)])
+def test_fmg_start_against_oracle(name, levels):
+    """Full-multigrid start: the state restricted to the coarsest level,
+    cycles on each coarse level, the full distribution interpolated upward;
+    then two ordinary cycles on the finest level."""
+    from paper_1704_03151_amd import Solver
+    case = CASES[name].with_(n_levels=levels)
+    print(f"[parity] {name}: FMG start over {levels} levels", flush=True)
+    gpu = Solver(case, precision="fp64")
+    orc = Oracle(case)
+    rc, n = gpu.fmg(3, tol=0.0)
+    n_ref = orc.fmg(3, tol=0.0)
+    assert rc == 0 and n == n_ref, (rc, n, n_ref)
+    G, H = to_oracle(gpu.get_f())
+    assert rel_max(G, orc.G) < 1e-10 and rel_max(H, orc.H) < 1e-10, (rel_max(G, orc.G), rel_max(H, orc.H))
+    gpu.iterate(2, tol=0.0)
+    orc.iterate(2, tol=0.0)
+    err = field_errors(gpu.macro(), orc.primitive(), orc.lev0.fluid)
+    assert max(err.values()) < 1e-10, err
+    gpu.close()

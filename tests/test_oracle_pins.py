@@ -409,3 +409,28 @@ def test_plate_residual_falls_to_round_off():
     o = Oracle(case)
     ok, res = o.iterate(60, tol=1e-7)
     assert ok, res
+
+
+def test_fmg_keeps_a_fixed_point():
+    """The full-multigrid start leaves a discrete steady state unchanged: the
+    restriction and interpolation of the full distribution reproduce a
+    uniform field and every stage's cycles keep it."""
+    case = _small_cavity(n=8, nvel=48, vlo=-8, vhi=8, n_levels=3)
+    o = Oracle(case)
+    G0, H0 = o.G.copy(), o.H.copy()
+    n = o.fmg(2, tol=0.0)
+    assert n == 4
+    assert np.max(np.abs(o.G - G0)) < 1e-12 and np.max(np.abs(o.H - H0)) < 1e-12
+
+
+def test_fmg_reaches_the_plain_steady_state():
+    """Started by FMG or from rest, the cycles converge to the same steady
+    state (the start changes the path, not the discrete solution)."""
+    case = _small_cavity(n=8, nvel=24, vlo=-6, vhi=6, n_levels=3, lid=0.2, Kn=0.5)
+    a, b = Oracle(case), Oracle(case)
+    assert a.iterate(200, tol=1e-10)[0]
+    b.fmg(5, tol=1e-8)
+    assert b.iterate(200, tol=1e-10)[0]
+    pa, pb = a.primitive(), b.primitive()
+    for x, y in zip(pa, pb):
+        assert np.max(np.abs(x - y)) < 1e-8 * max(1.0, np.max(np.abs(x)))
