@@ -106,7 +106,10 @@ typedef struct {
  * domain has walls only; fas_levels: levels of the FAS prediction, from the
  * finest (0 or more than n_levels: all of them; the CS correction always
  * uses n_levels); nu_coarse_cs: smoothings of the CS correction on its
- * coarsest level (0: nu_coarse, which then counts for both cycles). */
+ * coarsest level (0: nu_coarse, which then counts for both cycles);
+ * cycle_gamma: coarse-grid corrections per visit of a level in the FAS
+ * cycle, 1 (or 0) for V-cycles, 2 for W-cycles, at most 3; cycle_gamma_cs:
+ * the same for the CS cycle (0: cycle_gamma). */
 typedef struct {
     int precision;
     int nu1, nu2, nu_coarse;
@@ -115,6 +118,8 @@ typedef struct {
     int mass_renorm;
     int fas_levels;
     int nu_coarse_cs;
+    int cycle_gamma;
+    int cycle_gamma_cs;
 } miugks_solver_desc;
 
 /* Nodes and weights of a 1-D rule on [lo, hi] (ignored for Gauss-Hermite,

@@ -169,19 +169,21 @@ def cs_cycle(mlevels, meshes, prolongs, l, rG, rH, tau_inv, dtn_inv, params):
     D = ml.diagonal(tau_inv[l], dtn_inv[l])
     dG = np.zeros_like(rG)
     dH = np.zeros_like(rH)
-    nu1, nu2, nuc = params
+    nu1, nu2, nuc = params[:3]
+    gamma = params[3] if len(params) > 3 else 1   # coarse corrections per visit (2: W-cycle)
     if l == len(mlevels) - 1:
         for _ in range(nuc):
             dG, dH = ml.smooth(dG, dH, rG, rH, D)
         return dG, dH
     for _ in range(nu1):
         dG, dH = ml.smooth(dG, dH, rG, rH, D)
-    eG, eH = ml.defect(dG, dH, rG, rH, D)
-    cG, cH = cs_cycle(mlevels, meshes, prolongs, l + 1, restrict(meshes[l], eG),
-                      restrict(meshes[l], eH), tau_inv, dtn_inv, params)
     fl = meshes[l].fluid
-    dG = dG + prolongs[l].apply(cG) * fl
-    dH = dH + prolongs[l].apply(cH) * fl
+    for _ in range(gamma):
+        eG, eH = ml.defect(dG, dH, rG, rH, D)
+        cG, cH = cs_cycle(mlevels, meshes, prolongs, l + 1, restrict(meshes[l], eG),
+                          restrict(meshes[l], eH), tau_inv, dtn_inv, params)
+        dG = dG + prolongs[l].apply(cG) * fl
+        dH = dH + prolongs[l].apply(cH) * fl
     for _ in range(nu2):
         dG, dH = ml.smooth(dG, dH, rG, rH, D)
     return dG, dH

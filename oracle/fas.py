@@ -162,23 +162,28 @@ class MacroLevel:
 
 
 def fas_cycle(mlevels, meshes, prolongs, l, W0, Rt, params, dtn_inv):
-    """W_l^{n+1} = FAS(l, W_l^n, R_l^n) (Sec. II D, recursive FAS cycle)."""
+    """W_l^{n+1} = FAS(l, W_l^n, R_l^n) (Sec. II D, recursive FAS cycle).
+
+    params = (nu1, nu2, nu_coarse[, gamma]): gamma coarse-grid corrections per
+    visit of a level (1: V-cycle, 2: W-cycle)."""
     ml = mlevels[l]
     ml.freeze_gamma(W0)
     P = Rt - ml.rsplit(W0)
     W = W0.copy()
-    nu1, nu2, nuc = params
+    nu1, nu2, nuc = params[:3]
+    gamma = params[3] if len(params) > 3 else 1
     if l == len(mlevels) - 1:
         for _ in range(nuc):
             W = ml.smooth(W, P, dtn_inv[l])
         return W
     for _ in range(nu1):
         W = ml.smooth(W, P, dtn_inv[l])
-    Rm = P + ml.rsplit(W)
-    Wc0 = restrict(meshes[l], W)
-    Rc = restrict(meshes[l], Rm)
-    Wc = fas_cycle(mlevels, meshes, prolongs, l + 1, Wc0, Rc, params, dtn_inv)
-    W = W + prolongs[l].apply(Wc - Wc0) * meshes[l].fluid
+    for _ in range(gamma):
+        Rm = P + ml.rsplit(W)
+        Wc0 = restrict(meshes[l], W)
+        Rc = restrict(meshes[l], Rm)
+        Wc = fas_cycle(mlevels, meshes, prolongs, l + 1, Wc0, Rc, params, dtn_inv)
+        W = W + prolongs[l].apply(Wc - Wc0) * meshes[l].fluid
     for _ in range(nu2):
         W = ml.smooth(W, P, dtn_inv[l])
     return W

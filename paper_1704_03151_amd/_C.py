@@ -45,7 +45,8 @@ class SolverDesc(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("nu1", ctypes.c_int), ("nu2", ctypes.c_int),
                 ("nu_coarse", ctypes.c_int), ("cfl", ctypes.c_double),
                 ("dtn_growth", ctypes.c_double), ("mass_renorm", ctypes.c_int), ("fas_levels", ctypes.c_int),
-                ("nu_coarse_cs", ctypes.c_int)]
+                ("nu_coarse_cs", ctypes.c_int), ("cycle_gamma", ctypes.c_int),
+                ("cycle_gamma_cs", ctypes.c_int)]
 
 
 _SIGS = {

@@ -44,6 +44,8 @@ struct miugks_ctx {
     int nk = 0, nu = 0, nv = 0, L = 1;
     int nu1 = 2, nu2 = 1, nuc = 10;
     int nuc_cs = 10;   // smoothings of the CS cycle on its coarsest level
+    int gamma = 1;     // coarse corrections per level visit (1: V-cycle, 2: W-cycle), FAS
+    int gamma_cs = 1;  // the same for the CS cycle
     int FL = 1;   // levels of the FAS prediction, counted from the finest one in use
     // finest level the cycles run on: 0, except during a full-multigrid start,
     // whose stages treat a coarse level as the finest (f then holds that level)
@@ -455,27 +457,31 @@ struct Path {
                    dim3(256), g, c->wparts[l], c->wbuf[l], c->drho[l], c->ddrho[l], (int)c->last_from_zero[l]);
         }
         const Geo& gc = c->geo[l + 1];
-        if (pre > 0) {
-            // after an ordered sweep the defect lives on the wall cells only
-            if (!g.n_wall)
-                LAUNCH(c, "zero", arr(c, l + 1), k_zero<T>, dim3(nblk((int)std::min<size_t>(2 * (size_t)c->nk * gc.nc,
-                                                                                           1 << 24))),
-                       dim3(256), (T*)c->r[l + 1], 2 * (size_t)c->nk * gc.nc);
-            else
-                LAUNCH(c, "defect_walls", arr(c, l + 1), k_defect_walls<T>, dim3(ntiles(gc.nc), nchunks(c->nk)),
-                       dim3(256), g, gc, c->vel, c->gas.K_int, (const int4*)c->cwall[l + 1],
-                       (const double*)c->civol[l + 1], (const double*)c->ddrho[l], (T*)c->r[l + 1], 2);
-        } else {
-            LAUNCH(c, "defect_restrict", 2 * arr(c, l) + arr(c, l + 1), k_defect_restrict<T>,
-                   dim3(ntiles(gc.nc), nchunks(c->nk)), dim3(256), g, gc, c->vel, c->gas.K_int, (const T*)c->r[l],
-                   (const T*)c->df[l], c->tau_inv[l], c->dtn_inv[l], c->drho[l], (T*)c->r[l + 1]);
+        // gamma coarse corrections (1: V-cycle, 2: W-cycle)
+        for (int gi = 0; gi < c->gamma_cs; ++gi) {
+            if (gi == 0 && pre > 0) {
+                // after an ordered sweep the defect lives on the wall cells only
+                if (!g.n_wall)
+                    LAUNCH(c, "zero", arr(c, l + 1), k_zero<T>,
+                           dim3(nblk((int)std::min<size_t>(2 * (size_t)c->nk * gc.nc, 1 << 24))), dim3(256),
+                           (T*)c->r[l + 1], 2 * (size_t)c->nk * gc.nc);
+                else
+                    LAUNCH(c, "defect_walls", arr(c, l + 1), k_defect_walls<T>, dim3(ntiles(gc.nc), nchunks(c->nk)),
+                           dim3(256), g, gc, c->vel, c->gas.K_int, (const int4*)c->cwall[l + 1],
+                           (const double*)c->civol[l + 1], (const double*)c->ddrho[l], (T*)c->r[l + 1], 2);
+            } else {
+                LAUNCH(c, "defect_restrict", 2 * arr(c, l) + arr(c, l + 1), k_defect_restrict<T>,
+                       dim3(ntiles(gc.nc), nchunks(c->nk)), dim3(256), g, gc, c->vel, c->gas.K_int,
+                       (const T*)c->r[l], (const T*)c->df[l], c->tau_inv[l], c->dtn_inv[l], c->drho[l],
+                       (T*)c->r[l + 1]);
+            }
+            cs(c, l + 1);
+            LAUNCH(c, "prolong_add", 2 * arr(c, l) + arr(c, l + 1), k_prolong_add<T>,
+                   dim3(ntiles(g.nc), nchunks(c->nk)), dim3(256), g, c->vel, gc.nc, (const T*)c->df[l + 1],
+                   (T*)c->df[l]);
+            // the prolongation changed the correction: wall densities from it
+            if (c->nu2 > 0 || gi + 1 < c->gamma_cs) wall_sums(c, l, (const T*)c->df[l], c->drho[l]);
         }
-        cs(c, l + 1);
-        LAUNCH(c, "prolong_add", 2 * arr(c, l) + arr(c, l + 1), k_prolong_add<T>,
-               dim3(ntiles(g.nc), nchunks(c->nk)), dim3(256), g, c->vel, gc.nc, (const T*)c->df[l + 1],
-               (T*)c->df[l]);
-        // the prolongation changed the correction: wall densities from it
-        if (c->nu2 > 0) wall_sums(c, l, (const T*)c->df[l], c->drho[l]);
         for (int i = 0; i < c->nu2; ++i) smooth(c, l, i == 0);
     }
 
@@ -488,7 +494,7 @@ struct Path {
     // prolonged coarse correction enters only the wall densities of the next
     // sweep, so it is evaluated at the wall cells only.
     static bool cs_reduced_ok(miugks_ctx* c) {
-        if (c->nu1 < 1 || c->nu2 < 1 || c->nuc_cs < 1 || getenv("MIUGKS_FULL_CS")) return false;
+        if (c->nu1 < 1 || c->nu2 < 1 || c->nuc_cs < 1 || c->gamma_cs != 1 || getenv("MIUGKS_FULL_CS")) return false;
         for (int l = 0; l < c->L; ++l)
             if (!c->wave[l].W) return false;
         return true;
@@ -580,7 +586,7 @@ void fas_smooth(miugks_ctx* c, int l, double*& W, double*& Walt) {
 int fas_last(const miugks_ctx* c) { return std::min(c->top + c->FL, c->L) - 1; }
 
 void fas(miugks_ctx* c, int l) {
-    if (l >= c->fas_block_l0 && fas_last(c) == c->fasset.L - 1) {
+    if (c->gamma == 1 && l >= c->fas_block_l0 && fas_last(c) == c->fasset.L - 1) {
         FasSet F = c->fasset;
         F.l0 = l;
         double cells = 0;
@@ -601,14 +607,17 @@ void fas(miugks_ctx* c, int l) {
     } else {
         for (int i = 0; i < c->nu1; ++i) fas_smooth(c, l, W, Walt);
         const Geo& gc = c->geo[l + 1];
-        LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas4_rsplit, dim3(nb), dim3(256), g, c->gas, (const double*)W,
-               (const double*)c->fGam[l], (const double*)c->fP[l], 1.0, c->fRm[l], (double*)nullptr);
-        LAUNCH(c, "fas_restrict", 10 * nc8, k_fas4_restrict, dim3(nblk(4 * gc.nc)), dim3(256), g, gc,
-               (const double*)W, (const double*)c->fRm[l], c->fW[l + 1], c->fR[l + 1]);
-        fas(c, l + 1);
-        LAUNCH(c, "fas_prolong", 10 * nc8, k_fas4_prolong, dim3(nb), dim3(256), g, gc.nc,
-               (const double*)c->fW[l + 1], (const double*)c->fW0[l + 1], (const double*)W, Walt);
-        std::swap(W, Walt);
+        // gamma coarse corrections (1: V-cycle, 2: W-cycle)
+        for (int gi = 0; gi < c->gamma; ++gi) {
+            LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas4_rsplit, dim3(nb), dim3(256), g, c->gas, (const double*)W,
+                   (const double*)c->fGam[l], (const double*)c->fP[l], 1.0, c->fRm[l], (double*)nullptr);
+            LAUNCH(c, "fas_restrict", 10 * nc8, k_fas4_restrict, dim3(nblk(4 * gc.nc)), dim3(256), g, gc,
+                   (const double*)W, (const double*)c->fRm[l], c->fW[l + 1], c->fR[l + 1]);
+            fas(c, l + 1);
+            LAUNCH(c, "fas_prolong", 10 * nc8, k_fas4_prolong, dim3(nb), dim3(256), g, gc.nc,
+                   (const double*)c->fW[l + 1], (const double*)c->fW0[l + 1], (const double*)W, Walt);
+            std::swap(W, Walt);
+        }
         for (int i = 0; i < c->nu2; ++i) fas_smooth(c, l, W, Walt);
     }
     if (W != c->fW[l])
@@ -1362,7 +1371,9 @@ int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgri
         return MIUGKS_EINVAL;
     }
     if (v->nu < 1 || v->nv < 1 || !v->u || !v->v || !v->wu || !v->wv || s->nu1 < 0 || s->nu2 < 0 ||
-        s->nu_coarse < 1 || s->nu_coarse_cs < 0 || s->fas_levels < 0 || !(s->cfl > 0) || g->K_int < 0 || !(g->Kn > 0) || !(g->T_inf > 0)) {
+        s->nu_coarse < 1 || s->nu_coarse_cs < 0 || s->fas_levels < 0 || s->cycle_gamma < 0 || s->cycle_gamma > 3 ||
+        s->cycle_gamma_cs < 0 || s->cycle_gamma_cs > 3 ||
+        !(s->cfl > 0) || g->K_int < 0 || !(g->Kn > 0) || !(g->T_inf > 0)) {
         g_create_error = "bad velocity grid, gas or solver description";
         delete ctx;
         return MIUGKS_EINVAL;
@@ -1383,6 +1394,8 @@ int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgri
     ctx->nu2 = s->nu2;
     ctx->nuc = s->nu_coarse;
     ctx->nuc_cs = s->nu_coarse_cs > 0 ? s->nu_coarse_cs : s->nu_coarse;
+    ctx->gamma = s->cycle_gamma > 0 ? s->cycle_gamma : 1;
+    ctx->gamma_cs = s->cycle_gamma_cs > 0 ? s->cycle_gamma_cs : ctx->gamma;
     ctx->dtn_growth = s->dtn_growth;
     HostVel& hv = ctx->hv;
     hv.nu = v->nu;

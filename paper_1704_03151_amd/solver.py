@@ -53,7 +53,8 @@ class Solver:
         rho, U, V, T = case.farfield
         gas = _C.GasDesc(case.K_int, case.Pr, case.omega, case.Kn, rho, U, V, T)
         sd = _C.SolverDesc(prec, case.nu1, case.nu2, case.nu_coarse, case.cfl, case.dtn_growth,
-                           mass_renorm, getattr(case, "fas_levels", 0), getattr(case, "nu_coarse_cs", 0))
+                           mass_renorm, getattr(case, "fas_levels", 0), getattr(case, "nu_coarse_cs", 0),
+                           getattr(case, "cycle_gamma", 1), getattr(case, "cycle_gamma_cs", 0))
         h = ctypes.c_void_p()
         rc = _C.lib.miugks_create(ctypes.byref(h), ctypes.byref(mesh), ctypes.byref(vg),
                                   ctypes.byref(gas), ctypes.byref(sd), ctypes.c_void_p(_stream_handle(stream)))

@@ -310,3 +310,43 @@ def test_fmg_start_against_oracle(name, levels):
     err = field_errors(gpu.macro(), orc.primitive(), orc.lev0.fluid)
     assert max(err.values()) < 1e-10, err
     gpu.close()
+
+
+@pytest.mark.parametrize("name,levels,gcs", [("cavity16_kn10", 3, 0), ("square20x20", 2, 0), ("cavity16_kn10", 3, 1)])
+def test_w_cycles_against_oracle(name, levels, gcs):
+    """W-cycles (two coarse corrections per level visit) in the FAS
+    prediction, the CS correction (or V-cycles there) and three outer cycles."""
+    from paper_1704_03151_amd import Solver
+    case = CASES[name].with_(n_levels=levels, cycle_gamma=2, cycle_gamma_cs=gcs)
+    print(f"[parity] {name}: W-cycles over {levels} levels, CS gamma {gcs}", flush=True)
+    gpu = Solver(case, precision="fp64")
+    orc = Oracle(case)
+    prim, pert = perturbed_state(case, 7)
+    gpu.init_macro(prim)
+    orc.init_macro(prim)
+    W = orc.W.copy()
+    Rt = 0.02 * wl.random_field(W.shape, seed=17) * orc.lev0.fluid
+    out = gpu.predict(W.reshape(4, case.ny, case.nx), Rt.reshape(4, case.ny, case.nx))
+    ref = fas_cycle(orc.fas_levels, orc.levels, orc.prolongs, 0, W, Rt, orc.params, orc.dtn_inv())
+    assert max(rel_max(out[m].ravel(), ref[m]) for m in range(4)) < 1e-11
+    fl = orc.lev0.fluid
+    r = wl.random_field((2, case.n_vel, case.ny, case.nx), seed=61) * fl.reshape(case.ny, case.nx)
+    ti = wl.random_field((case.ny, case.nx), seed=63, lo=0.5, hi=3.0)
+    gpu.init_macro(case.init)
+    orc.init_macro(case.init)
+    orc.cycle = 0
+    got = gpu.correct(r, ti)
+    rG, rH = to_oracle(r)
+    dG, dH = cs_cycle(orc.cs_levels, orc.levels, orc.prolongs, 0, rG, rH,
+                      orc.level_tau_inv(ti.ravel() * fl), orc.dtn_inv(), orc.cs_params)
+    gG, gH = to_oracle(got)
+    assert rel_max(gG, dG) < 1e-11 and rel_max(gH, dH) < 1e-11, (rel_max(gG, dG), rel_max(gH, dH))
+    gpu.init_macro(case.init)
+    orc.init_macro(case.init)
+    orc.cycle = 0
+    orc.history = []
+    gpu.iterate(3, tol=0.0)
+    orc.iterate(3, tol=0.0)
+    err = field_errors(gpu.macro(), orc.primitive(), orc.lev0.fluid)
+    assert max(err.values()) < 1e-10, err
+    gpu.close()

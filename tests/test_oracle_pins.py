@@ -291,6 +291,10 @@ def test_fas_fixed_point_and_convergence():
     Wt = fa.fas_cycle(o.fas_levels, o.levels, o.prolongs, 0, W0, np.zeros_like(W0), o.params,
                       [np.zeros(l.nc) for l in o.levels])
     assert np.array_equal(Wt, W0)
+    # a W-cycle keeps the fixed point as well
+    Wt = fa.fas_cycle(o.fas_levels, o.levels, o.prolongs, 0, W0, np.zeros_like(W0), o.params[:3] + (2,),
+                      [np.zeros(l.nc) for l in o.levels])
+    assert np.array_equal(Wt, W0)
     Rt = 0.01 * wl.random_field(W0.shape, seed=8)
     # a closed box conserves mass: the target must carry zero total mass
     Rt[0] -= np.sum(o.lev0.V * Rt[0]) / np.sum(o.lev0.V)
@@ -348,14 +352,17 @@ def test_sweep_is_exact_without_walls():
     assert np.allclose(np.concatenate([dG.ravel(), dH.ravel()]), x, rtol=1e-12, atol=1e-13)
 
 
-def test_cs_cycle_converges_to_sparse_direct_solve():
-    case = _small_cavity(n=4, nvel=6, vlo=-3, vhi=3, n_levels=2, lid=0.2)
+@pytest.mark.parametrize("n,levels,gamma", [(4, 2, 1), (8, 3, 2)])
+def test_cs_cycle_converges_to_sparse_direct_solve(n, levels, gamma):
+    """CS cycles as an iteration on the correction equation converge to its
+    direct sparse solution (V-cycle, and W-cycle over three levels)."""
+    case = _small_cavity(n=n, nvel=6, vlo=-3, vhi=3, n_levels=levels, lid=0.2)
     vel, g, lv, pro, mls, tau_inv, rG, rH = _cs_setup(case, 12)
     A = assemble(lv[0], vel, g.K_int, tau_inv[0])
     x = spla.spsolve(A.tocsc(), np.concatenate([rG.ravel(), rH.ravel()]))
     dG = np.zeros_like(rG)
     dH = np.zeros_like(rH)
-    params = (2, 1, 10)
+    params = (2, 1, 10, gamma)
     dtn = [np.zeros(l.nc) for l in lv]
     D = mls[0].diagonal(tau_inv[0], 0.0)
     for _ in range(60):

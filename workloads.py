@@ -71,6 +71,8 @@ class Case:
     cfl: float = 0.8
     fas_levels: int = 0           # levels of the FAS prediction (0: all n_levels)
     nu_coarse_cs: int = 0         # CS smoothings on the coarsest level (0: nu_coarse)
+    cycle_gamma: int = 1          # coarse corrections per level visit (1: V-cycle, 2: W-cycle), FAS
+    cycle_gamma_cs: int = 0       # the same for the CS cycle (0: cycle_gamma)
 
     @property
     def nx(self) -> int:
