@@ -69,6 +69,40 @@ def cpu_baseline(case, cycles):
                       f"numpy FP64 oracle, one thread, {dt:.2f} s per cycle"}
 
 
+def explicit_bench(args, case, solver, pts):
+    """Explicit time-accurate UGKS steps: K timed after W warm-up steps, then
+    the per-kernel pass; the roofline is that of the interface-flux kernel."""
+    import torch
+    solver.explicit(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dt, res = solver.explicit(args.steps)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    print(f"[bench] {args.steps} explicit steps (dt {dt:.3e}): {sec * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+    solver.set_timing(True)
+    solver.explicit(args.steps)
+    stats = solver.timing()
+    solver.set_timing(False)
+    n_l, ms, by = stats["flux_div"]
+    achieved = by / n_l / (ms / n_l * 1e-3) / 1e9
+    line = {
+        "metric": "cell·velocity updates/s per explicit UGKS step",
+        "value": pts / sec, "unit": "cell*velocity updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if args.precision == "fp32f" else "f64", "data": "synthetic",
+        "config": {"workload": f"{case.name}: {RECIPES.get(args.config, 'synthetic case')}, explicit steps of "
+                               f"{dt:.3e}", "cells": case.n_cells, "velocities": case.n_vel,
+                   "precision": args.precision},
+        "roofline": {"bound": "hbm", "kernel": "flux_div", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": by / n_l, "mean_launch_ms": ms / n_l},
+        "kernel_ms_per_step": {k: v[1] / args.steps for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])},
+        "residual": [float(x) for x in res],
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +110,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32f", choices=["fp32f", "fp64"])
     ap.add_argument("--config", type=int, default=2, help="workload recipe (2 = the headline cavity)")
+    ap.add_argument("--explicit", action="store_true",
+                    help="time explicit time-accurate UGKS steps instead of MG cycles (the interface flux, the "
+                         "collision update and the moments, once per step)")
     ap.add_argument("--dtn-growth", type=float, default=None,
                     help="override the workload's pseudo-step growth a (dt_n = a^n dt_p; 0: off)")
     ap.add_argument("--cpu-cycles", type=int, default=1)
@@ -104,6 +141,8 @@ def main():
     print(f"[bench] {case.name}: {case.nx}x{case.ny} cells ({case.n_fluid} fluid) x {case.n_vel} velocities, "
           f"{case.n_levels} levels, {args.precision}", file=sys.stderr, flush=True)
 
+    if args.explicit:
+        return explicit_bench(args, case, solver, pts)
     # warm-up, then exactly K timed cycles
     solver.iterate(args.warmup, tol=0.0)
     torch.cuda.synchronize()

@@ -165,6 +165,20 @@ int miugks_iterate(miugks_ctx* ctx, int max_cycles, double tol, int* cycles_done
  * miugks_init_macro or miugks_set_f.  Synchronises the stream. */
 int miugks_fmg(miugks_ctx* ctx, int cycles_per_level, double tol, int* cycles_done);
 
+/* Explicit, time-accurate UGKS steps on the finest level: the scheme whose
+ * time-averaged interface fluxes the residuals of Sec. II A use, marched
+ * with one global step dt = the smallest CFL step of the mesh (cells and
+ * faces alike).  Per step: the fluxes and R of the current state, the
+ * macroscopic update W* = W^n + dt R (a cell whose W* has non-positive
+ * density or temperature keeps W^n), the Shakhov equilibria g^n of W^n and
+ * g_s of W* with the heat flux q^n, and the trapezoidal update
+ * f = [f - dt div + dt/2 (g_s / tau_s + (g^n - f) / tau^n)] / (1 + dt / (2 tau_s)),
+ * then the moments of f (and the closed-domain mass renormalisation).
+ * dt (may be NULL) receives the step, res (may be NULL) the RMS residuals of
+ * the last step's fluxes.  MIUGKS_ESTATE inside a full-multigrid start.
+ * Synchronises the stream. */
+int miugks_explicit(miugks_ctx* ctx, int steps, double* dt, double res[4]);
+
 /* Host outputs [ny][nx] (each may be NULL): primitive fields and heat flux of
  * the current distribution. */
 int miugks_get_macro(miugks_ctx* ctx, double* rho, double* U, double* V, double* T, double* qx,

@@ -210,6 +210,52 @@ class Oracle:
         self.history = []
         return done
 
+    def explicit_step(self):
+        """One explicit, time-accurate UGKS step (the scheme behind the
+        residuals of Sec. II A): the global step dt is the smallest CFL step of
+        the finest level, used by every face; W* = W^n + dt R (cells with
+        non-positive density or temperature keep W^n); Shakhov equilibria of
+        W^n and W* with q^n; the trapezoidal collision update
+        f = [f - dt div + dt/2 (g*/tau* + (g^n - f)/tau^n)] / (1 + dt/(2 tau*));
+        the moments of the new f (and the closed-domain renormalisation).
+        Returns dt and the RMS residuals of the step's fluxes."""
+        lev = copy.copy(self.lev0)
+        dt = float(np.min(lev.dt))
+        lev.dt = np.full_like(lev.dt, dt)
+        lev.fdt = np.full_like(lev.fdt, dt)
+        divG, divH, R = residuals(self.G, self.H, self.W, lev, self.vel, self.gas, self.case.farfield)
+        norms = residual_norm(R, lev)
+        fl = lev.fluid
+        Ws = np.where(fl, self.W + dt * R, self.W)
+        with np.errstate(all="ignore"):
+            rho, U, V, lam = gm.primitive(Ws, self.gas.K)
+        bad = ~((rho > 0) & (lam > 0) & np.isfinite(lam))
+        Ws = np.where(bad & fl, self.W, Ws)
+
+        def equilibrium(W):
+            with np.errstate(all="ignore"):
+                rho, U, V, lam = gm.primitive(W, self.gas.K)
+                ti = np.where(fl, 1.0 / self.gas.tau(rho, lam), 0.0)
+                G, H = gm.shakhov(rho, U, V, lam, self.q[0], self.q[1], self.vel.u[:, None],
+                                  self.vel.v[:, None], self.gas.K_int, self.gas.Pr)
+            return G, H, ti
+
+        G0, H0, t0 = equilibrium(self.W)
+        G1, H1, t1 = equilibrium(Ws)
+        den = 1.0 / (1.0 + 0.5 * dt * t1)
+        G = np.where(fl, (self.G - dt * divG + 0.5 * dt * (G1 * t1 + (G0 - self.G) * t0)) * den, 0.0)
+        H = np.where(fl, (self.H - dt * divH + 0.5 * dt * (H1 * t1 + (H0 - self.H) * t0)) * den, 0.0)
+        self.G, self.H = G, H
+        self._moments()
+        if self.closed:
+            M = float(np.sum(self.lev0.V * self.W[0] * fl))
+            s = self.M0 / M
+            self.G *= s
+            self.H *= s
+            self.W *= s
+            self.q *= s
+        return dt, norms
+
     def iterate(self, max_cycles, tol=1e-6):
         """Run outer cycles until max_c R_rms,c < tol; returns (converged, norms)."""
         norms = None

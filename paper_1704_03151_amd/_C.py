@@ -59,6 +59,7 @@ _SIGS = {
     "miugks_init_macro": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp, _dp]),
     "miugks_iterate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _ip, _dp]),
     "miugks_fmg": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_double, _ip]),
+    "miugks_explicit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _dp]),
     "miugks_get_macro": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp]),
     "miugks_get_f": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "miugks_set_f": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),

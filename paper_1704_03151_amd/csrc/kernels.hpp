@@ -1333,6 +1333,63 @@ __global__ void __launch_bounds__(256) k_micro_residual(Geo g, Vel vel, Gas gas,
 }
 
 // ---------------------------------------------------------------------------
+// Explicit, time-accurate UGKS (the scheme the paper's residuals come from):
+// one global step dt, the interface fluxes integrated over it.
+
+// out = W + dt R on every fluid cell (the macroscopic update), W elsewhere
+__global__ void k_macro_step(Geo g, const double* __restrict__ W, const double* __restrict__ R, double dt,
+                             double* __restrict__ out) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * g.nc) return;
+    int c = t % g.nc;
+    out[t] = g.solid[c] ? W[t] : W[t] + dt * R[t];
+}
+
+// f = [f - dt div + dt/2 (g1/tau1 + (g0 - f)/tau0)] / (1 + dt/(2 tau1)): the
+// trapezoidal collision term with the Shakhov equilibria g0 of W^n and g1 of
+// the updated W (both with the heat flux q^n; cell records of k_cell_prep)
+template <typename T>
+__global__ void __launch_bounds__(256) k_explicit_update(Geo g, Vel vel, Gas gas, T* __restrict__ f,
+                                                         const T* __restrict__ div, const double* __restrict__ cp0,
+                                                         const double* __restrict__ cp1, double dt) {
+    Chunk ch = chunk_of(g.nc, vel.nk);
+    if (!ch.valid) return;
+    const int c = ch.c;
+    const size_t nc = g.nc, ho = (size_t)vel.nk * nc;
+    const bool fluid = !g.solid[c];
+    double P0[NCP], P1[NCP];
+    for (int m = 0; m < NCP; ++m) {
+        P0[m] = cp0[m * nc + c];
+        P1[m] = cp1[m * nc + c];
+    }
+    auto shakhov = [&](const double* P, double u, double v, double& G, double& H) {
+        double cx = u - P[1], cy = v - P[2], c2 = cx * cx + cy * cy, lam = P[3];
+        double G0 = P[0] * exp(-lam * c2);
+        double H0 = double(gas.K_int) / (2.0 * lam) * G0;
+        double sk = P[4] * cx + P[5] * cy;
+        G = G0 * (1.0 + sk * (2.0 * lam * c2 - 4.0));
+        H = H0 * (1.0 + sk * (2.0 * lam * c2 - 2.0));
+    };
+    const double den = 1.0 / (1.0 + 0.5 * dt * P1[6]);
+    for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
+        size_t ig = (size_t)k * nc + c;
+        if (!fluid) {
+            f[ig] = T(0);
+            f[ho + ig] = T(0);
+            continue;
+        }
+        double u = vel.u[k], v = vel.v[k], G0, H0, G1, H1;
+        shakhov(P0, u, v, G0, H0);
+        shakhov(P1, u, v, G1, H1);
+        double fG = f[ig], fH = f[ho + ig];
+        fG = (fG - dt * double(div[ig]) + 0.5 * dt * (G1 * P1[6] + (G0 - fG) * P0[6])) * den;
+        fH = (fH - dt * double(div[ho + ig]) + 0.5 * dt * (H1 * P1[6] + (H0 - fH) * P0[6])) * den;
+        f[ig] = T(fG);
+        f[ho + ig] = T(fH);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Step 5: correction equation (Sec. II A 2) on one level.
 
 // transport part of the diagonal D_ik (outgoing normal speeds over the

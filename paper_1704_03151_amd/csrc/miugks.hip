@@ -62,6 +62,10 @@ struct miugks_ctx {
     void *f = nullptr, *div = nullptr, *finf = nullptr;
     double *W = nullptr, *q = nullptr, *R = nullptr, *Wt = nullptr, *fp = nullptr, *cp = nullptr;
     double *part = nullptr, *norms = nullptr, *rho_w = nullptr, *mass = nullptr, *msum = nullptr;
+    // explicit time-accurate steps: cell records of W^n, the global step per
+    // cell (the level-0 geometry points at it during those steps), W^n scratch
+    double *cp0 = nullptr, *dt_glob = nullptr, *Wtmp = nullptr, *tau_tmp = nullptr;
+    double dt_global = 0.0;
     size_t part_bytes = 0;
     // per level
     std::vector<void*> r, df;
@@ -805,6 +809,65 @@ int run_fmg(miugks_ctx* c, int cycles, double tol, int* done) {
     return check_launch(c);
 }
 
+// Explicit time-accurate UGKS steps (Sec. II A: the scheme whose fluxes the
+// residuals use): one global step, the smallest CFL step of the mesh, for
+// every cell and face.  Per step: Step 1 with that step, W* = W^n + dt R,
+// the Shakhov equilibria of W^n and W* (heat flux q^n), the trapezoidal
+// update of f, and the moments of the new f.
+template <typename T>
+int run_explicit(miugks_ctx* c, int steps, double* res) {
+    const Geo g0 = c->geo[0];
+    const Geo& g = c->geo[0];
+    const double dt = c->dt_global;
+    int rc = MIUGKS_OK;
+    c->geo[0].dt = c->dt_glob;
+    for (int s = 0; s < steps; ++s) {
+        Path<T>::residual(c);
+        size_t n = 4 * (size_t)g.nc;
+        LAUNCH(c, "copy", 16.0 * n, k_copy2, dim3(nblk((int)n)), dim3(256), (const double*)c->W, c->Wtmp,
+               (double*)nullptr, (const double*)nullptr, (double*)nullptr, n);
+        LAUNCH(c, "cell_prep", (14.0 + NCP) * g.nc * 8, k_cell_prep, dim3(nblk(g.nc)), dim3(256), g, c->gas,
+               c->Wtmp, (const double*)c->W, (const double*)c->q, c->cp0, c->tau_tmp);
+        LAUNCH(c, "macro_step", 12.0 * n, k_macro_step, dim3(nblk((int)n)), dim3(256), g, (const double*)c->W,
+               (const double*)c->R, dt, c->Wt);
+        LAUNCH(c, "cell_prep", (14.0 + NCP) * g.nc * 8, k_cell_prep, dim3(nblk(g.nc)), dim3(256), g, c->gas, c->Wt,
+               (const double*)c->W, (const double*)c->q, c->cp, c->tau_inv[0]);
+        LAUNCH(c, "explicit_update", 3 * Path<T>::arr(c, 0) + 2 * NCP * g.nc * 8.0, k_explicit_update<T>,
+               dim3(ntiles(g.nc), nchunks(c->nk)), dim3(256), g, c->vel, c->gas, (T*)c->f, (const T*)c->div,
+               (const double*)c->cp0, (const double*)c->cp, dt);
+        Path<T>::moments(c, nullptr);
+        if (c->renorm) {
+            LAUNCH(c, "mass", 4.0 * g.nc * 8, k_mass, dim3(1), dim3(1024), g, c->W, c->mass);
+            size_t nf = 2 * (size_t)c->nk * g.nc;
+            LAUNCH(c, "scale_f", 2 * Path<T>::arr(c, 0), k_scale_f<T>,
+                   dim3(nblk((int)std::min<size_t>(nf, 1 << 24))), dim3(256), (T*)c->f, nf, c->mass, c->M0);
+            LAUNCH(c, "scale_moments", 12.0 * g.nc * 8, k_scale_d, dim3(nblk(6 * g.nc)), dim3(256), c->W,
+                   4 * (size_t)g.nc, c->mass, c->M0);
+            LAUNCH(c, "scale_moments", 4.0 * g.nc * 8, k_scale_d, dim3(nblk(2 * g.nc)), dim3(256), c->q,
+                   2 * (size_t)g.nc, c->mass, c->M0);
+        }
+    }
+    c->geo[0] = g0;
+    c->have_div = false;
+    if (res) {
+        hipError_t e = hipMemcpyAsync(c->h_norms, c->norms, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            c->err = std::string("explicit: ") + hipGetErrorString(e);
+            return MIUGKS_EDEVICE;
+        }
+        for (int m = 0; m < 4; ++m) res[m] = c->h_norms[m];
+    }
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        c->err = std::string("explicit: ") + hipGetErrorString(e);
+        return MIUGKS_EDEVICE;
+    }
+    if ((rc = check_launch(c))) return rc;
+    timing_harvest(c);
+    return MIUGKS_OK;
+}
+
 int build_device(miugks_ctx* ctx) {
     int rc;
     ctx->geo.resize(ctx->L);
@@ -1089,9 +1152,19 @@ int build_device(miugks_ctx* ctx) {
     if ((rc = dalloc(&ctx->W, 4 * nc0)) || (rc = dalloc(&ctx->q, 2 * nc0)) || (rc = dalloc(&ctx->R, 4 * nc0)) ||
         (rc = dalloc(&ctx->Wt, 4 * nc0)) || (rc = dalloc(&ctx->fp, NFP * 2 * nc0)) ||
         (rc = dalloc(&ctx->cp, NCP * nc0)) || (rc = dalloc(&ctx->norms, 4)) ||
+        (rc = dalloc(&ctx->cp0, NCP * nc0)) || (rc = dalloc(&ctx->dt_glob, nc0)) ||
+        (rc = dalloc(&ctx->Wtmp, 4 * nc0)) || (rc = dalloc(&ctx->tau_tmp, nc0)) ||
         (rc = dalloc(&ctx->rho_w, ctx->hl[0].w_cell.size() + 1)) || (rc = dalloc(&ctx->mass, 1)) ||
         (rc = dalloc(&ctx->msum, 2 * NRAW * nc0)))
         return rc;
+    {
+        // the global explicit step: the smallest CFL step of the finest level
+        const std::vector<double>& dt0 = ctx->hl[0].dt;
+        double m = dt0.empty() ? 0.0 : *std::min_element(dt0.begin(), dt0.end());
+        ctx->dt_global = m;
+        std::vector<double> all(nc0, m);
+        HIP_TRY(hipMemcpy(ctx->dt_glob, all.data(), nc0 * sizeof(double), hipMemcpyHostToDevice));
+    }
     // partial sums: the largest is 2 * NRAW per cell per chunk
     size_t maxw = 1;
     for (auto& h : ctx->hl) maxw = std::max(maxw, h.w_cell.size());
@@ -1502,6 +1575,21 @@ int miugks_init_macro(miugks_ctx* ctx, const double* rho, const double* U, const
     ctx->cycle = 0;
     ctx->have_div = false;
     return reset_mass(ctx);
+}
+
+int miugks_explicit(miugks_ctx* ctx, int steps, double* dt, double res[4]) {
+    if (!ctx) return MIUGKS_EINVAL;
+    if (steps < 0) {
+        ctx->err = "steps must be >= 0";
+        return MIUGKS_EINVAL;
+    }
+    if (ctx->top != 0) {
+        ctx->err = "the state is not on the finest level";
+        return MIUGKS_ESTATE;
+    }
+    if (dt) *dt = ctx->dt_global;
+    if (ctx->prec == MIUGKS_FP64) return run_explicit<double>(ctx, steps, res);
+    return run_explicit<float>(ctx, steps, res);
 }
 
 int miugks_fmg(miugks_ctx* ctx, int cycles_per_level, double tol, int* cycles_done) {

@@ -115,6 +115,13 @@ class Solver:
         self._check(rc, allow=(_C.EDIVERGED,))
         return rc, n.value
 
+    def explicit(self, steps):
+        """Explicit time-accurate UGKS steps; returns (dt, RMS residuals of the last step)."""
+        dt = np.zeros(1)
+        res = np.zeros(4)
+        self._check(_C.lib.miugks_explicit(self.h, int(steps), _C.dptr(dt), _C.dptr(res)))
+        return float(dt[0]), res
+
     def macro(self):
         shape = (self.case.ny, self.case.nx)
         out = {k: np.zeros(shape) for k in ("rho", "U", "V", "T", "qx", "qy")}

@@ -350,3 +350,19 @@ def test_w_cycles_against_oracle(name, levels, gcs):
     err = field_errors(gpu.macro(), orc.primitive(), orc.lev0.fluid)
     assert max(err.values()) < 1e-10, err
     gpu.close()
+
+
+@pytest.mark.parametrize("name", ["cavity16_kn10", "square20x20", "plate32x24"])
+def test_explicit_steps_against_oracle(name):
+    """Explicit time-accurate UGKS steps (global step, trapezoidal collision
+    term) from a perturbed state."""
+    case, gpu, orc = perturbed_pair(name, 13)
+    dt, res = gpu.explicit(3)
+    for _ in range(3):
+        dt_ref, res_ref = orc.explicit_step()
+    assert dt == dt_ref
+    assert np.allclose(res, res_ref, rtol=1e-10, atol=0)
+    G, H = to_oracle(gpu.get_f())
+    assert rel_max(G, orc.G) < 1e-10 and rel_max(H, orc.H) < 1e-10, (rel_max(G, orc.G), rel_max(H, orc.H))
+    err = field_errors(gpu.macro(), orc.primitive(), orc.lev0.fluid)
+    assert max(err.values()) < 1e-10, err
