@@ -2797,6 +2797,38 @@ __device__ __forceinline__ void fas4_rsplit(const Geo& g, const Gas& gas, const 
     if (E) E[s * g.nc + c] = 0.0;
 }
 
+// the first phase of a smoothing: the renewed residual Rm = P + R_split(W)
+// and the first half-sweep (colour 0) together.  E starts from zero, so in
+// that half-sweep every side term F(W_j + E_j) - F(W_j) - Gam E_j is zero and
+// a colour-0 cell's correction is Rm / D (D = sum S Gam / (2 V) + 1/dt_n);
+// colour-1 and solid cells get E = 0
+__device__ __forceinline__ void fas4_rsplit_first(const Geo& g, const Gas& gas, const double* __restrict__ W,
+                                                  const double* __restrict__ Gam, const double* __restrict__ P,
+                                                  const double* __restrict__ dtn_inv, double* __restrict__ Rm,
+                                                  double* __restrict__ E, int t) {
+    int c = t >> 2, s = t & 3;
+    int ix = c % g.nx, iy = c / g.nx;
+    bool solid = g.solid[c];
+    double G = Gam[s * g.nc + c];
+    double acc[4] = {0, 0, 0, 0};
+    if (!solid) fas_rsplit_side(g, gas, W, G, c, s, acc);
+    double tot[4];
+    for (int m = 0; m < 4; ++m) tot[m] = quad_sum(acc[m]);
+    double S = (s >> 1) == 0 ? g.dy[iy] : g.dx[ix];
+    double Dsum = quad_sum(S * G);
+    double iv = 1.0 / (g.dx[ix] * g.dy[iy]);
+    double mine = s == 0 ? tot[0] : s == 1 ? tot[1] : s == 2 ? tot[2] : tot[3];
+    double rm = solid ? 0.0 : P[s * g.nc + c] + 1.0 * (-mine * iv);
+    Rm[s * g.nc + c] = rm;
+    double e = 0.0;
+    if (!solid && ((ix + iy) & 1) == 0) {
+        double ih = rcp_refined(2.0 * g.dx[ix] * g.dy[iy]);
+        double D = Dsum * ih + dtn_inv[c];
+        e = rm * rcp_refined(D);
+    }
+    E[s * g.nc + c] = e;
+}
+
 // new correction of a cell of the given colour from the linearised defect
 // equation (lanes of the cell only; the caller guarantees the colour)
 __device__ __forceinline__ double fas4_half_value(const Geo& g, const Gas& gas, const double* __restrict__ W,
@@ -2887,6 +2919,13 @@ __global__ void k_fas4_rsplit(Geo g, Gas gas, const double* __restrict__ W, cons
                               double* __restrict__ E) {
     ITEM4_KERNEL_INDEX
     fas4_rsplit(g, gas, W, Gam, base, sgn, out, E, t);
+}
+
+__global__ void k_fas4_rsplit_first(Geo g, Gas gas, const double* __restrict__ W, const double* __restrict__ Gam,
+                                    const double* __restrict__ P, const double* __restrict__ dtn_inv,
+                                    double* __restrict__ Rm, double* __restrict__ E) {
+    ITEM4_KERNEL_INDEX
+    fas4_rsplit_first(g, gas, W, Gam, P, dtn_inv, Rm, E, t);
 }
 
 __global__ void k_fas4_halfsweep(Geo g, Gas gas, const double* __restrict__ W, double* __restrict__ E,
@@ -2984,13 +3023,11 @@ __device__ __forceinline__ void fas_block_smooth(const FasSet& F, const Gas& gas
     for (int it = 0; it < count; ++it) {
         const double* W = fas_w(F, par, l);
         for (int t = threadIdx.x; t < n4; t += blockDim.x)
-            fas4_rsplit(g, gas, W, F.Gam[l], F.P[l], 1.0, F.Rm[l], F.E[l], t);
+            fas4_rsplit_first(g, gas, W, F.Gam[l], F.P[l], F.dtn[l], F.Rm[l], F.E[l], t);
         __syncthreads();
-        for (int col : {0, 1}) {
-            for (int t = threadIdx.x; t < n4; t += blockDim.x)
-                fas4_halfsweep(g, gas, W, F.E[l], F.Rm[l], F.Gam[l], F.dtn[l], col, t);
-            __syncthreads();
-        }
+        for (int t = threadIdx.x; t < n4; t += blockDim.x)
+            fas4_halfsweep(g, gas, W, F.E[l], F.Rm[l], F.Gam[l], F.dtn[l], 1, t);
+        __syncthreads();
         for (int t = threadIdx.x; t < n4; t += blockDim.x)
             fas4_halfsweep_apply(g, gas, W, F.E[l], F.Rm[l], F.Gam[l], F.dtn[l], fas_walt(F, par, l), t);
         __syncthreads();

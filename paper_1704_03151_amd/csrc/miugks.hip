@@ -566,18 +566,18 @@ struct Path {
 // ---------------------------------------------------------------------------
 // FAS cycle (precision independent, FP64)
 
-// one smoothing of Sec. II C 2: renewed residual (E cleared), red-black
-// half-sweeps of colours 0, 1 and 0, the last one with W += E into the other
-// W buffer (four lanes per cell in every phase); W and Walt swap
+// one smoothing of Sec. II C 2: renewed residual with the first half-sweep
+// (colour 0 from E = 0), red-black half-sweeps of colours 1 and 0, the last
+// one with W += E into the other W buffer (four lanes per cell in every
+// phase); W and Walt swap
 void fas_smooth(miugks_ctx* c, int l, double*& W, double*& Walt) {
     const Geo& g = c->geo[l];
     int nb = nblk(4 * g.nc);
     double nc8 = g.nc * 8.0;
-    LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas4_rsplit, dim3(nb), dim3(256), g, c->gas, (const double*)W,
-           (const double*)c->fGam[l], (const double*)c->fP[l], 1.0, c->fRm[l], c->fE[l]);
-    for (int col : {0, 1})
-        LAUNCH(c, "fas_halfsweep", 18 * nc8, k_fas4_halfsweep, dim3(nb), dim3(256), g, c->gas, (const double*)W,
-               c->fE[l], (const double*)c->fRm[l], (const double*)c->fGam[l], (const double*)c->dtn_inv[l], col);
+    LAUNCH(c, "fas_rsplit", 22 * nc8, k_fas4_rsplit_first, dim3(nb), dim3(256), g, c->gas, (const double*)W,
+           (const double*)c->fGam[l], (const double*)c->fP[l], (const double*)c->dtn_inv[l], c->fRm[l], c->fE[l]);
+    LAUNCH(c, "fas_halfsweep", 18 * nc8, k_fas4_halfsweep, dim3(nb), dim3(256), g, c->gas, (const double*)W,
+           c->fE[l], (const double*)c->fRm[l], (const double*)c->fGam[l], (const double*)c->dtn_inv[l], 1);
     LAUNCH(c, "fas_halfsweep", 26 * nc8, k_fas4_halfsweep_apply, dim3(nb), dim3(256), g, c->gas, (const double*)W,
            (const double*)c->fE[l], (const double*)c->fRm[l], (const double*)c->fGam[l],
            (const double*)c->dtn_inv[l], Walt);
