@@ -60,6 +60,11 @@ extern "C" {
 #define MIUGKS_QUAD_SIMPSON38 1  /* composite Simpson 3/8, needs (n-1) % 3 == 0 */
 #define MIUGKS_QUAD_GAUSS_HERMITE 2
 
+/* cycle_gamma / cycle_gamma_cs value that selects F-cycles (Sec. II D): one
+ * visit of a level makes an F-cycle and then a V-cycle on the next coarser
+ * level, so level l (0 = finest) is visited l + 1 times per cycle */
+#define MIUGKS_CYCLE_F (-1)
+
 typedef struct miugks_ctx miugks_ctx;
 
 /* Structured mesh (Sec. III A).  Cell (ix, iy) spans [x[ix], x[ix+1]] x
@@ -108,8 +113,8 @@ typedef struct {
  * uses n_levels); nu_coarse_cs: smoothings of the CS correction on its
  * coarsest level (0: nu_coarse, which then counts for both cycles);
  * cycle_gamma: coarse-grid corrections per visit of a level in the FAS
- * cycle, 1 (or 0) for V-cycles, 2 for W-cycles, at most 3; cycle_gamma_cs:
- * the same for the CS cycle (0: cycle_gamma). */
+ * cycle, 1 (or 0) for V-cycles, 2 for W-cycles, at most 3, or MIUGKS_CYCLE_F
+ * for F-cycles; cycle_gamma_cs: the same for the CS cycle (0: cycle_gamma). */
 typedef struct {
     int precision;
     int nu1, nu2, nu_coarse;

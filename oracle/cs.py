@@ -32,6 +32,7 @@ import numpy as np
 
 from workloads import FACE_WALL, FACE_OUTFLOW
 from .flux import wall_maxwellian
+from .fas import coarse_visits
 from .mesh import restrict
 
 
@@ -170,7 +171,6 @@ def cs_cycle(mlevels, meshes, prolongs, l, rG, rH, tau_inv, dtn_inv, params):
     dG = np.zeros_like(rG)
     dH = np.zeros_like(rH)
     nu1, nu2, nuc = params[:3]
-    gamma = params[3] if len(params) > 3 else 1   # coarse corrections per visit (2: W-cycle)
     if l == len(mlevels) - 1:
         for _ in range(nuc):
             dG, dH = ml.smooth(dG, dH, rG, rH, D)
@@ -178,10 +178,11 @@ def cs_cycle(mlevels, meshes, prolongs, l, rG, rH, tau_inv, dtn_inv, params):
     for _ in range(nu1):
         dG, dH = ml.smooth(dG, dH, rG, rH, D)
     fl = meshes[l].fluid
-    for _ in range(gamma):
+    # coarse corrections per visit: V-, W- or F-cycle (coarse_visits)
+    for sub in coarse_visits(params):
         eG, eH = ml.defect(dG, dH, rG, rH, D)
         cG, cH = cs_cycle(mlevels, meshes, prolongs, l + 1, restrict(meshes[l], eG),
-                          restrict(meshes[l], eH), tau_inv, dtn_inv, params)
+                          restrict(meshes[l], eH), tau_inv, dtn_inv, sub)
         dG = dG + prolongs[l].apply(cG) * fl
         dH = dH + prolongs[l].apply(cH) * fl
     for _ in range(nu2):

@@ -30,7 +30,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from workloads import FACE_WALL, FACE_FARFIELD, FACE_OUTFLOW
+from workloads import CYCLE_F, FACE_WALL, FACE_FARFIELD, FACE_OUTFLOW
 from . import gas as gm
 from .mesh import restrict
 
@@ -161,28 +161,39 @@ class MacroLevel:
         return W + E
 
 
+def coarse_visits(params):
+    """Parameters of the coarse-level cycles that one visit of a level makes,
+    in order.  params = (nu1, nu2, nu_coarse[, gamma]): gamma > 0 gives gamma
+    cycles of the same kind (1: V-cycle, 2: W-cycle); CYCLE_F gives the
+    F-cycle, whose visit makes an F-cycle and then a V-cycle on the coarser
+    level (each starting from the level's current iterate, as in a W-cycle)."""
+    gamma = params[3] if len(params) > 3 else 1
+    if gamma == CYCLE_F:
+        return [params[:3] + (CYCLE_F,), params[:3] + (1,)]
+    return [params] * gamma
+
+
 def fas_cycle(mlevels, meshes, prolongs, l, W0, Rt, params, dtn_inv):
     """W_l^{n+1} = FAS(l, W_l^n, R_l^n) (Sec. II D, recursive FAS cycle).
 
-    params = (nu1, nu2, nu_coarse[, gamma]): gamma coarse-grid corrections per
-    visit of a level (1: V-cycle, 2: W-cycle)."""
+    params = (nu1, nu2, nu_coarse[, gamma]): the coarse-grid corrections per
+    visit of a level are those of coarse_visits (V-, W- or F-cycle)."""
     ml = mlevels[l]
     ml.freeze_gamma(W0)
     P = Rt - ml.rsplit(W0)
     W = W0.copy()
     nu1, nu2, nuc = params[:3]
-    gamma = params[3] if len(params) > 3 else 1
     if l == len(mlevels) - 1:
         for _ in range(nuc):
             W = ml.smooth(W, P, dtn_inv[l])
         return W
     for _ in range(nu1):
         W = ml.smooth(W, P, dtn_inv[l])
-    for _ in range(gamma):
+    for sub in coarse_visits(params):
         Rm = P + ml.rsplit(W)
         Wc0 = restrict(meshes[l], W)
         Rc = restrict(meshes[l], Rm)
-        Wc = fas_cycle(mlevels, meshes, prolongs, l + 1, Wc0, Rc, params, dtn_inv)
+        Wc = fas_cycle(mlevels, meshes, prolongs, l + 1, Wc0, Rc, sub, dtn_inv)
         W = W + prolongs[l].apply(Wc - Wc0) * meshes[l].fluid
     for _ in range(nu2):
         W = ml.smooth(W, P, dtn_inv[l])

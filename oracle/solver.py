@@ -43,13 +43,14 @@ class Oracle:
         nfas = case.fas_levels if case.fas_levels > 0 else len(self.levels)
         self.fas_levels = [MacroLevel(lev, self.gas, case.farfield) for lev in self.levels[:nfas]]
         self.cs_levels = [MicroLevel(lev, self.vel, self.gas.K_int) for lev in self.levels]
-        # gamma coarse corrections per level visit: 1 V-cycle, 2 W-cycle
-        gamma = max(1, case.cycle_gamma)
+        # coarse corrections per level visit: 1 V-cycle, 2 W-cycle, CYCLE_F
+        # F-cycle (0: V-cycle)
+        gamma = case.cycle_gamma if case.cycle_gamma != 0 else 1
         self.params = (case.nu1, case.nu2, case.nu_coarse, gamma)
         # the CS cycle may take its own number of coarsest-level smoothings
         # and of coarse corrections
         nuc_cs = case.nu_coarse_cs if case.nu_coarse_cs > 0 else case.nu_coarse
-        gamma_cs = case.cycle_gamma_cs if case.cycle_gamma_cs > 0 else gamma
+        gamma_cs = case.cycle_gamma_cs if case.cycle_gamma_cs != 0 else gamma
         self.cs_params = (case.nu1, case.nu2, nuc_cs, gamma_cs)
         self.closed = case.closed()
         self.cycle = 0

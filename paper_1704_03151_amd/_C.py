@@ -18,6 +18,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EDIVERGED, ENOTCONVERGED, ESTATE = range(7)
 FACE_INTERIOR, FACE_WALL, FACE_FARFIELD, FACE_OUTFLOW = range(4)
 FP64, FP32F = 0, 1
 QUAD_TRAPEZOID, QUAD_SIMPSON38, QUAD_GAUSS_HERMITE = range(3)
+CYCLE_F = -1
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _u8p = ctypes.POINTER(ctypes.c_uint8)

@@ -44,7 +44,8 @@ struct miugks_ctx {
     int nk = 0, nu = 0, nv = 0, L = 1;
     int nu1 = 2, nu2 = 1, nuc = 10;
     int nuc_cs = 10;   // smoothings of the CS cycle on its coarsest level
-    int gamma = 1;     // coarse corrections per level visit (1: V-cycle, 2: W-cycle), FAS
+    int gamma = 1;     // coarse corrections per level visit (1: V-cycle, 2: W-cycle,
+                       // MIUGKS_CYCLE_F: F-cycle), FAS
     int gamma_cs = 1;  // the same for the CS cycle
     int FL = 1;   // levels of the FAS prediction, counted from the finest one in use
     // finest level the cycles run on: 0, except during a full-multigrid start,
@@ -286,6 +287,12 @@ hipError_t set_wave_lds(int prec, int R, int np, int bytes) {
     return np == 1 ? set_wave_lds_t<float, 1>(R, bytes) : set_wave_lds_t<float, 2>(R, bytes);
 }
 
+// Coarse-level cycles that one visit of a level makes (Sec. II D): gamma > 0
+// gives gamma cycles of the same kind (1: V-cycle, 2: W-cycle), each from the
+// level's current iterate; MIUGKS_CYCLE_F gives an F-cycle then a V-cycle.
+int coarse_visits(int gamma) { return gamma == MIUGKS_CYCLE_F ? 2 : gamma; }
+int visit_kind(int gamma, int i) { return gamma == MIUGKS_CYCLE_F ? (i == 0 ? MIUGKS_CYCLE_F : 1) : gamma; }
+
 // ---------------------------------------------------------------------------
 // the hot path, per precision
 
@@ -443,7 +450,7 @@ struct Path {
     // dF_l = CS(l, r_l) (Sec. II D); r_l, tau_inv_l, dtn_inv_l in place.  The
     // correction starts at zero: zero wall densities for the first sweep (the
     // sweep itself needs no initial correction).
-    static void cs(miugks_ctx* c, int l) {
+    static void cs(miugks_ctx* c, int l, int gamma) {
         const Geo& g = c->geo[l];
         int pre = l == c->L - 1 ? c->nuc_cs : c->nu1;
         // the wavefront sweep starts from zero wall densities by itself
@@ -461,8 +468,8 @@ struct Path {
                    dim3(256), g, c->wparts[l], c->wbuf[l], c->drho[l], c->ddrho[l], (int)c->last_from_zero[l]);
         }
         const Geo& gc = c->geo[l + 1];
-        // gamma coarse corrections (1: V-cycle, 2: W-cycle)
-        for (int gi = 0; gi < c->gamma_cs; ++gi) {
+        const int nvis = coarse_visits(gamma);
+        for (int gi = 0; gi < nvis; ++gi) {
             if (gi == 0 && pre > 0) {
                 // after an ordered sweep the defect lives on the wall cells only
                 if (!g.n_wall)
@@ -479,12 +486,12 @@ struct Path {
                        (const T*)c->r[l], (const T*)c->df[l], c->tau_inv[l], c->dtn_inv[l], c->drho[l],
                        (T*)c->r[l + 1]);
             }
-            cs(c, l + 1);
+            cs(c, l + 1, visit_kind(gamma, gi));
             LAUNCH(c, "prolong_add", 2 * arr(c, l) + arr(c, l + 1), k_prolong_add<T>,
                    dim3(ntiles(g.nc), nchunks(c->nk)), dim3(256), g, c->vel, gc.nc, (const T*)c->df[l + 1],
                    (T*)c->df[l]);
             // the prolongation changed the correction: wall densities from it
-            if (c->nu2 > 0 || gi + 1 < c->gamma_cs) wall_sums(c, l, (const T*)c->df[l], c->drho[l]);
+            if (c->nu2 > 0 || gi + 1 < nvis) wall_sums(c, l, (const T*)c->df[l], c->drho[l]);
         }
         for (int i = 0; i < c->nu2; ++i) smooth(c, l, i == 0);
     }
@@ -543,7 +550,7 @@ struct Path {
         if (cs_reduced_ok(c))
             cs_reduced(c, c->top);
         else
-            cs(c, c->top);
+            cs(c, c->top, c->gamma_cs);
     }
 
     // Steps 6-7 and the closed-domain renormalisation
@@ -589,8 +596,8 @@ void fas_smooth(miugks_ctx* c, int l, double*& W, double*& Walt) {
 // coarsest level the FAS prediction visits
 int fas_last(const miugks_ctx* c) { return std::min(c->top + c->FL, c->L) - 1; }
 
-void fas(miugks_ctx* c, int l) {
-    if (c->gamma == 1 && l >= c->fas_block_l0 && fas_last(c) == c->fasset.L - 1) {
+void fas(miugks_ctx* c, int l, int gamma) {
+    if (gamma == 1 && l >= c->fas_block_l0 && fas_last(c) == c->fasset.L - 1) {
         FasSet F = c->fasset;
         F.l0 = l;
         double cells = 0;
@@ -611,13 +618,13 @@ void fas(miugks_ctx* c, int l) {
     } else {
         for (int i = 0; i < c->nu1; ++i) fas_smooth(c, l, W, Walt);
         const Geo& gc = c->geo[l + 1];
-        // gamma coarse corrections (1: V-cycle, 2: W-cycle)
-        for (int gi = 0; gi < c->gamma; ++gi) {
+        const int nvis = coarse_visits(gamma);
+        for (int gi = 0; gi < nvis; ++gi) {
             LAUNCH(c, "fas_rsplit", 20 * nc8, k_fas4_rsplit, dim3(nb), dim3(256), g, c->gas, (const double*)W,
                    (const double*)c->fGam[l], (const double*)c->fP[l], 1.0, c->fRm[l], (double*)nullptr);
             LAUNCH(c, "fas_restrict", 10 * nc8, k_fas4_restrict, dim3(nblk(4 * gc.nc)), dim3(256), g, gc,
                    (const double*)W, (const double*)c->fRm[l], c->fW[l + 1], c->fR[l + 1]);
-            fas(c, l + 1);
+            fas(c, l + 1, visit_kind(gamma, gi));
             LAUNCH(c, "fas_prolong", 10 * nc8, k_fas4_prolong, dim3(nb), dim3(256), g, gc.nc,
                    (const double*)c->fW[l + 1], (const double*)c->fW0[l + 1], (const double*)W, Walt);
             std::swap(W, Walt);
@@ -650,7 +657,7 @@ void predict(miugks_ctx* c) {
     size_t n = 4 * (size_t)c->geo[top].nc;
     LAUNCH(c, "copy", 24.0 * n, k_copy2, dim3(nblk((int)n)), dim3(256), (const double*)c->W, c->fW[top],
            (double*)nullptr, (const double*)c->R, c->fR[top], n);
-    fas(c, top);
+    fas(c, top, c->gamma);
     LAUNCH(c, "copy", 16.0 * n, k_copy2, dim3(nblk((int)n)), dim3(256), (const double*)c->fW[top], c->Wt,
            (double*)nullptr, (const double*)nullptr, (double*)nullptr, n);
 }
@@ -1444,8 +1451,8 @@ int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgri
         return MIUGKS_EINVAL;
     }
     if (v->nu < 1 || v->nv < 1 || !v->u || !v->v || !v->wu || !v->wv || s->nu1 < 0 || s->nu2 < 0 ||
-        s->nu_coarse < 1 || s->nu_coarse_cs < 0 || s->fas_levels < 0 || s->cycle_gamma < 0 || s->cycle_gamma > 3 ||
-        s->cycle_gamma_cs < 0 || s->cycle_gamma_cs > 3 ||
+        s->nu_coarse < 1 || s->nu_coarse_cs < 0 || s->fas_levels < 0 || s->cycle_gamma < MIUGKS_CYCLE_F ||
+        s->cycle_gamma > 3 || s->cycle_gamma_cs < MIUGKS_CYCLE_F || s->cycle_gamma_cs > 3 ||
         !(s->cfl > 0) || g->K_int < 0 || !(g->Kn > 0) || !(g->T_inf > 0)) {
         g_create_error = "bad velocity grid, gas or solver description";
         delete ctx;
@@ -1467,8 +1474,8 @@ int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgri
     ctx->nu2 = s->nu2;
     ctx->nuc = s->nu_coarse;
     ctx->nuc_cs = s->nu_coarse_cs > 0 ? s->nu_coarse_cs : s->nu_coarse;
-    ctx->gamma = s->cycle_gamma > 0 ? s->cycle_gamma : 1;
-    ctx->gamma_cs = s->cycle_gamma_cs > 0 ? s->cycle_gamma_cs : ctx->gamma;
+    ctx->gamma = s->cycle_gamma != 0 ? s->cycle_gamma : 1;
+    ctx->gamma_cs = s->cycle_gamma_cs != 0 ? s->cycle_gamma_cs : ctx->gamma;
     ctx->dtn_growth = s->dtn_growth;
     HostVel& hv = ctx->hv;
     hv.nu = v->nu;
@@ -1693,7 +1700,7 @@ int miugks_predict(miugks_ctx* ctx, const double* W, const double* R, double* W_
     if ((rc = upload_cells(ctx, ctx->fW[0], W, 4)) || (rc = upload_cells(ctx, ctx->fR[0], R, 4))) return rc;
     set_dtn_factor(ctx);
     set_dtn(ctx);
-    fas(ctx, 0);
+    fas(ctx, 0, ctx->gamma);
     return download_cells(ctx, W_out, ctx->fW[0], 4);
 }
 

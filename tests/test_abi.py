@@ -18,6 +18,22 @@ def _header_symbols():
     return sorted(set(re.findall(r"\b(miugks_[a-z_]+)\s*\(", text)))
 
 
+def test_header_constants_match_the_binding_and_the_inputs():
+    """Every MIUGKS_ constant of the header has the value the Python binding
+    and the case descriptions use."""
+    import workloads as wl
+    from paper_1704_03151_amd import _C
+    with open(os.path.join(ROOT, "include", "miugks.h")) as fh:
+        text = fh.read()
+    consts = {k: int(v) for k, v in re.findall(r"#define MIUGKS_([A-Z0-9_]+) \(?(-?\d+)\)?", text)}
+    for name in ("OK", "EINVAL", "ENOMEM", "EDEVICE", "EDIVERGED", "ENOTCONVERGED", "ESTATE", "FP64", "FP32F",
+                 "QUAD_TRAPEZOID", "QUAD_SIMPSON38", "QUAD_GAUSS_HERMITE", "CYCLE_F",
+                 "FACE_INTERIOR", "FACE_WALL", "FACE_FARFIELD", "FACE_OUTFLOW"):
+        assert consts[name] == getattr(_C, name), name
+    for name in ("FACE_INTERIOR", "FACE_WALL", "FACE_FARFIELD", "FACE_OUTFLOW", "CYCLE_F"):
+        assert consts[name] == getattr(wl, name), name
+
+
 def test_library_exports_every_declared_symbol():
     from paper_1704_03151_amd import _C
     names = _header_symbols()

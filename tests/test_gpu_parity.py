@@ -312,13 +312,18 @@ def test_fmg_start_against_oracle(name, levels):
     gpu.close()
 
 
-@pytest.mark.parametrize("name,levels,gcs", [("cavity16_kn10", 3, 0), ("square20x20", 2, 0), ("cavity16_kn10", 3, 1)])
-def test_w_cycles_against_oracle(name, levels, gcs):
-    """W-cycles (two coarse corrections per level visit) in the FAS
-    prediction, the CS correction (or V-cycles there) and three outer cycles."""
+@pytest.mark.parametrize("name,levels,gam,gcs", [("cavity16_kn10", 3, 2, 0), ("square20x20", 2, 2, 0),
+                                                 ("cavity16_kn10", 3, 2, 1), ("cavity16_kn10", 4, wl.CYCLE_F, 0),
+                                                 ("cavity16_kn10", 3, wl.CYCLE_F, 1),
+                                                 ("cavity16_kn10", 4, 2, wl.CYCLE_F),
+                                                 ("square20x20", 2, wl.CYCLE_F, 0)])
+def test_w_and_f_cycles_against_oracle(name, levels, gam, gcs):
+    """W-cycles (two coarse corrections per level visit) and F-cycles (an
+    F-cycle then a V-cycle on the coarser level) in the FAS prediction, the
+    CS correction (or V-cycles there) and three outer cycles."""
     from paper_1704_03151_amd import Solver
-    case = CASES[name].with_(n_levels=levels, cycle_gamma=2, cycle_gamma_cs=gcs)
-    print(f"[parity] {name}: W-cycles over {levels} levels, CS gamma {gcs}", flush=True)
+    case = CASES[name].with_(n_levels=levels, cycle_gamma=gam, cycle_gamma_cs=gcs)
+    print(f"[parity] {name}: FAS gamma {gam} over {levels} levels, CS gamma {gcs}", flush=True)
     gpu = Solver(case, precision="fp64")
     orc = Oracle(case)
     prim, pert = perturbed_state(case, 7)

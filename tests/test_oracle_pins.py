@@ -291,10 +291,11 @@ def test_fas_fixed_point_and_convergence():
     Wt = fa.fas_cycle(o.fas_levels, o.levels, o.prolongs, 0, W0, np.zeros_like(W0), o.params,
                       [np.zeros(l.nc) for l in o.levels])
     assert np.array_equal(Wt, W0)
-    # a W-cycle keeps the fixed point as well
-    Wt = fa.fas_cycle(o.fas_levels, o.levels, o.prolongs, 0, W0, np.zeros_like(W0), o.params[:3] + (2,),
-                      [np.zeros(l.nc) for l in o.levels])
-    assert np.array_equal(Wt, W0)
+    # W- and F-cycles keep the fixed point as well
+    for gamma in (2, wl.CYCLE_F):
+        Wt = fa.fas_cycle(o.fas_levels, o.levels, o.prolongs, 0, W0, np.zeros_like(W0), o.params[:3] + (gamma,),
+                          [np.zeros(l.nc) for l in o.levels])
+        assert np.array_equal(Wt, W0)
     Rt = 0.01 * wl.random_field(W0.shape, seed=8)
     # a closed box conserves mass: the target must carry zero total mass
     Rt[0] -= np.sum(o.lev0.V * Rt[0]) / np.sum(o.lev0.V)
@@ -352,10 +353,10 @@ def test_sweep_is_exact_without_walls():
     assert np.allclose(np.concatenate([dG.ravel(), dH.ravel()]), x, rtol=1e-12, atol=1e-13)
 
 
-@pytest.mark.parametrize("n,levels,gamma", [(4, 2, 1), (8, 3, 2)])
+@pytest.mark.parametrize("n,levels,gamma", [(4, 2, 1), (8, 3, 2), (8, 3, wl.CYCLE_F)])
 def test_cs_cycle_converges_to_sparse_direct_solve(n, levels, gamma):
     """CS cycles as an iteration on the correction equation converge to its
-    direct sparse solution (V-cycle, and W-cycle over three levels)."""
+    direct sparse solution (V-cycle, and W- and F-cycles over three levels)."""
     case = _small_cavity(n=n, nvel=6, vlo=-3, vhi=3, n_levels=levels, lid=0.2)
     vel, g, lv, pro, mls, tau_inv, rG, rH = _cs_setup(case, 12)
     A = assemble(lv[0], vel, g.K_int, tau_inv[0])
@@ -375,6 +376,56 @@ def test_cs_cycle_converges_to_sparse_direct_solve(n, levels, gamma):
     eG, eH = mls[0].defect(dG * 0 + 0.3 * rG, dH * 0 - 0.2 * rH, rG, rH, D)
     ref = np.concatenate([rG.ravel(), rH.ravel()]) - A @ np.concatenate([0.3 * rG.ravel(), -0.2 * rH.ravel()])
     assert np.allclose(np.concatenate([eG.ravel(), eH.ravel()]), ref, atol=1e-12)
+
+
+def _visit_order(cycle, levels, params):
+    """Levels in the order the recursive cycle smooths them, one smoothing per
+    visit (nu1 = nu_coarse = 1, nu2 = 0): the order in which it visits them."""
+    seen = []
+    for k, lev in enumerate(levels):
+        inner = lev.smooth
+        lev.smooth = (lambda *a, _k=k, _f=inner: (seen.append(_k), _f(*a))[1])
+    cycle(params)
+    return seen
+
+
+@pytest.mark.parametrize("kind", ["fas", "cs"])
+def test_cycle_shapes_visit_levels_in_textbook_order(kind):
+    """Over four levels a V-cycle visits each level once on the way down, a
+    W-cycle visits level l 2^l times, and an F-cycle goes down to the coarsest
+    level and climbs one level higher after each coarsest visit: levels
+    0 1 2 3, 3, 2 3, 1 2 3 (level l visited l + 1 times)."""
+    case = _small_cavity(n=16, nvel=6, vlo=-3, vhi=3, n_levels=4, lid=0.2)
+    o = Oracle(case)
+    assert len(o.levels) == 4
+    dtn = [np.zeros(l.nc) for l in o.levels]
+    W = o.W.copy()
+    rG = 0.01 * wl.random_field(o.G.shape, seed=3) * o.lev0.fluid
+    tau_inv = o.level_tau_inv(np.ones(o.lev0.nc))
+
+    def run(params):
+        if kind == "fas":
+            fa.fas_cycle(o.fas_levels, o.levels, o.prolongs, 0, W, np.zeros_like(W), params, dtn)
+        else:
+            cs_cycle(o.cs_levels, o.levels, o.prolongs, 0, rG, rG, tau_inv, dtn, params)
+
+    levels = o.fas_levels if kind == "fas" else o.cs_levels
+    assert _visit_order(run, levels, (1, 0, 1, 1)) == [0, 1, 2, 3]
+    w = _visit_order(run, levels, (1, 0, 1, 2))
+    assert [w.count(k) for k in range(4)] == [1, 2, 4, 8]
+    assert _visit_order(run, levels, (1, 0, 1, wl.CYCLE_F)) == [0, 1, 2, 3, 3, 2, 3, 1, 2, 3]
+
+
+def test_f_cycle_on_two_levels_is_the_w_cycle():
+    """Below the second-coarsest level an F- and a W-cycle both make two
+    coarsest-level solves, so on two levels they coincide; on three they differ."""
+    for levels, same in ((2, True), (3, False)):
+        case = _small_cavity(n=8, nvel=6, vlo=-3, vhi=3, n_levels=levels, lid=0.2)
+        vel, g, lv, pro, mls, tau_inv, rG, rH = _cs_setup(case, 21)
+        dtn = [np.zeros(l.nc) for l in lv]
+        w = cs_cycle(mls, lv, pro, 0, rG, rH, tau_inv, dtn, (1, 1, 2, 2))
+        f = cs_cycle(mls, lv, pro, 0, rG, rH, tau_inv, dtn, (1, 1, 2, wl.CYCLE_F))
+        assert (np.array_equal(w[0], f[0]) and np.array_equal(w[1], f[1])) == same
 
 
 # --------------------------------------------------------------------------- whole scheme

@@ -29,6 +29,10 @@ FACE_WALL = 1
 FACE_FARFIELD = 2
 FACE_OUTFLOW = 3
 
+# Value of cycle_gamma / cycle_gamma_cs that selects F-cycles (data format
+# shared by the oracle and the library).
+CYCLE_F = -1
+
 QUAD_TRAPEZOID = "trapezoid"
 QUAD_SIMPSON38 = "simpson38"
 QUAD_GAUSS_HERMITE = "gauss_hermite"
@@ -71,7 +75,8 @@ class Case:
     cfl: float = 0.8
     fas_levels: int = 0           # levels of the FAS prediction (0: all n_levels)
     nu_coarse_cs: int = 0         # CS smoothings on the coarsest level (0: nu_coarse)
-    cycle_gamma: int = 1          # coarse corrections per level visit (1: V-cycle, 2: W-cycle), FAS
+    cycle_gamma: int = 1          # coarse corrections per level visit (1: V-cycle, 2: W-cycle,
+                                  # CYCLE_F: F-cycle), FAS
     cycle_gamma_cs: int = 0       # the same for the CS cycle (0: cycle_gamma)
 
     @property
