@@ -29,16 +29,24 @@ from workloads import FACE_WALL, FACE_FARFIELD, FACE_OUTFLOW
 from . import gas as gm
 
 
+def _abs(a):
+    """|a|, with the branch taken on the real part (the same values for real a;
+    for complex a the analytic continuation of each branch, so that a complex
+    step differentiates the limiter where it is smooth)."""
+    return np.where(np.real(a) < 0, -a, a)
+
+
 def van_leer(a, b):
     """(sgn a + sgn b) |a| |b| / (|a| + |b|), zero when both vanish."""
-    den = np.abs(a) + np.abs(b)
-    safe = np.where(den > 0, den, 1.0)
-    return np.where(den > 0, (np.sign(a) + np.sign(b)) * np.abs(a) * np.abs(b) / safe, 0.0)
+    den = _abs(a) + _abs(b)
+    pos = np.real(den) > 0
+    safe = np.where(pos, den, 1.0)
+    return np.where(pos, (np.sign(np.real(a)) + np.sign(np.real(b))) * _abs(a) * _abs(b) / safe, 0.0)
 
 
 def slopes(F, lev):
     """Limited slope of F (Nk, Nc) along x and y; zero difference across non-interior faces."""
-    out = np.zeros((2,) + F.shape)
+    out = np.zeros((2,) + F.shape, dtype=F.dtype)
     for d in (0, 1):
         lo, hi = lev.nb[2 * d], lev.nb[2 * d + 1]
         sm = np.where(lo >= 0, (F - F[:, np.maximum(lo, 0)]) / np.where(lo >= 0, lev.dcent[2 * d], 1.0), 0.0)
@@ -85,7 +93,7 @@ def time_coefficients(dt, tau):
     q5 = dt^2 sum_{m>=2} (-1)^m (1-m) x^(m-2)/m!), 24 terms.
     """
     dt = np.asarray(dt, float)
-    tau = np.asarray(tau, float)
+    tau = np.asarray(tau)
     x = dt / tau
     em1 = -np.expm1(-x)           # 1 - e
     e = np.exp(-x)
@@ -94,7 +102,7 @@ def time_coefficients(dt, tau):
     q3 = 0.5 * dt * dt - tau * dt + tau * tau * em1
     q4 = tau * em1
     q5 = tau * dt * e - tau * tau * em1
-    small = x < 0.5
+    small = np.real(x) < 0.5
     if np.any(small):
         xs = np.where(small, x, 0.0)
         s1 = np.zeros_like(xs)
@@ -123,8 +131,8 @@ def interior_fluxes(G, H, W, lev, vel, gas):
     normal pointing from L to R."""
     sG, sH = slopes(G, lev), slopes(H, lev)
     nf = len(lev.fL)
-    PhiG = np.zeros((vel.n, nf))
-    PhiH = np.zeros((vel.n, nf))
+    PhiG = np.zeros((vel.n, nf), dtype=G.dtype)
+    PhiH = np.zeros((vel.n, nf), dtype=G.dtype)
     K, Ki = gas.K, gas.K_int
     u = vel.u[:, None]
     v = vel.v[:, None]
@@ -184,8 +192,8 @@ def boundary_face_values(G, H, lev, vel, gas, farfield):
     """Distribution on each boundary side of a fluid cell, (Nk, nsides), and u_n outward."""
     nb = len(lev.bcell)
     un = np.zeros((vel.n, nb))
-    Gf = np.zeros((vel.n, nb))
-    Hf = np.zeros((vel.n, nb))
+    Gf = np.zeros((vel.n, nb), dtype=np.result_type(G, lev.wall))
+    Hf = np.zeros((vel.n, nb), dtype=Gf.dtype)
     rho_inf, U_inf, V_inf, T_inf = farfield
     Ginf, Hinf = gm.maxwellian(rho_inf, U_inf, V_inf, 1.0 / T_inf, vel.u, vel.v, gas.K_int)
     for j in range(nb):
