@@ -65,6 +65,11 @@ extern "C" {
  * level, so level l (0 = finest) is visited l + 1 times per cycle */
 #define MIUGKS_CYCLE_F (-1)
 
+/* wall loads (Sec. IV B), per wall side; see miugks_wall_loads */
+#define MIUGKS_LOAD_PRESSURE 0
+#define MIUGKS_LOAD_SHEAR 1
+#define MIUGKS_LOAD_HEAT 2
+
 typedef struct miugks_ctx miugks_ctx;
 
 /* Structured mesh (Sec. III A).  Cell (ix, iy) spans [x[ix], x[ix+1]] x
@@ -195,6 +200,75 @@ int miugks_get_macro(miugks_ctx* ctx, double* rho, double* U, double* V, double*
  * set_f recomputes the moments; it is the checkpoint/restore path. */
 int miugks_get_f(miugks_ctx* ctx, void* dst, int dtype, int on_device);
 int miugks_set_f(miugks_ctx* ctx, const void* src, int dtype, int on_device);
+
+/* --- walls: loads, objectives, temperatures -------------------------------- */
+
+/* Wall sides of the finest level, in the order of their cells (row-major) and
+ * then of the sides (0: -x, 1: +x, 2: -y, 3: +y); an internal wall (a plate)
+ * has one side per adjacent fluid cell.  cell, side (caller-owned, may be
+ * NULL) receive n_walls entries; call with NULLs to get n_walls. */
+int miugks_wall_list(miugks_ctx* ctx, int* cell, int* side, int* n_walls);
+
+/* Loads of the current distribution on every wall side (Sec. IV B: the skin
+ * friction is the momentum the gas hands to the wall).  The distribution on
+ * the wall side of the face is the cell's for velocities leaving the gas and
+ * the diffuse-wall Maxwellian (Sec. III B) for the others; in the frame of
+ * the wall, c = u - U_w, with c_n along the normal out of the gas and c_t
+ * along the face (y on a -x/+x side, x on a -y/+y side):
+ *   p = sum_k w c_n^2 f^G, tau = sum_k w c_t c_n f^G,
+ *   q = 1/2 sum_k w c_n (|c|^2 f^G + f^H),
+ * and S the face area.  Host outputs of n_walls entries each (may be NULL;
+ * all NULL: only n_walls is set).  Synchronises the stream. */
+int miugks_wall_loads(miugks_ctx* ctx, double* p, double* tau, double* q, double* S, int* n_walls);
+
+/* J = sum over the listed wall sides (indices of miugks_wall_list) of S times
+ * the load kind (MIUGKS_LOAD_PRESSURE, _SHEAR or _HEAT); the lid shear of a
+ * cavity or the drag of a plate (both of its sides).  MIUGKS_EINVAL for a bad
+ * kind or index. */
+int miugks_objective(miugks_ctx* ctx, int kind, const int* walls, int n, double* J);
+
+/* Set the temperature of n wall faces of the mesh (Sec. III B, wall
+ * Maxwellian).  Faces are numbered x-faces first (iy (nx + 1) + ix), then
+ * y-faces ((nx + 1) ny + iy nx + ix); both sides of an internal wall face
+ * take the new value.  Coarse levels are rebuilt from the new values (the
+ * area-weighted means of creation).  The distribution is unchanged.
+ * MIUGKS_EINVAL for a face that is not a wall or a temperature <= 0 (nothing
+ * is changed then).  Synchronises the stream. */
+int miugks_set_wall_T(miugks_ctx* ctx, const int* faces, const double* Tw, int n);
+
+/* --- adjoint of the steady state (FP64 contexts) --------------------------- */
+
+/* out = (dr/df)^T v for the steady residual at the current distribution,
+ * r_ik(f) = (g_ik(W_i(f), q_i(f)) - f_ik) / tau_i(W_i(f)) - div_ik(f): the
+ * microscopic residual of Steps 3-4 (Sec. II A) with the equilibrium of the
+ * state itself and the transport of Step 1 (UGKS interface flux, limited
+ * slopes, micro-slopes, compatibility time slope, diffuse walls), reversed
+ * through the same arithmetic; the limiter takes its derivative where it is
+ * smooth.  v and out are laid out as f ([2][Nk][ny][nx]); dtype and on_device
+ * as for miugks_get_f.  MIUGKS_EINVAL for an FP32-f context.  Recomputes
+ * Step 1 of the current f.  Synchronises the stream. */
+int miugks_residual_adjoint(miugks_ctx* ctx, const void* v, void* out, int dtype, int on_device);
+
+/* Sensitivity of J = sum over the wall sides walls[0..n) of S times the load
+ * kind (see miugks_objective) to the temperatures of the mesh faces
+ * param_faces[0..n_param) (numbered as in miugks_set_wall_T; both sides of an
+ * internal wall face count), at a converged steady state:
+ *   dJ/dTw = dJ/dTw|_f - lam^T dr/dTw,  (dr/df)^T lam = dJ/df - mu m.
+ * In a closed domain (mass renormalisation on) the steady states form a
+ * family in the total mass, m is the mass row and mu = dJ/dM along the
+ * family, taken from two steady states at masses M0 (1 +- 1e-4) (up to 300
+ * cycles each towards 1e-13, from the scaled state; f and M0 are restored),
+ * so the result is the sensitivity at fixed mass.  lam is found by defect
+ * correction, lam <- lam - A^-T (dJ/df - mu m - (dr/df)^T lam), with A the
+ * velocity-diagonal part of the correction operator of Step 5 (Sec. II A 2)
+ * solved by one downwind-ordered sweep per velocity, until the residual norm
+ * falls by tol or after max_iter corrections.  dJ_dTw (host, n_param) out;
+ * iters and res (relative final residual norm) may be NULL.  Returns
+ * MIUGKS_OK, MIUGKS_ENOTCONVERGED (max_iter reached; outputs set),
+ * MIUGKS_EDIVERGED, or MIUGKS_EINVAL (FP32-f context, bad kind, wall index
+ * or a parameter face that is not a wall).  Synchronises the stream. */
+int miugks_adjoint(miugks_ctx* ctx, int kind, const int* walls, int n, const int* param_faces, int n_param,
+                   double tol, int max_iter, double* dJ_dTw, int* iters, double* res);
 
 /* --- one call per step of the hot path (parity and profiling) ------------- */
 

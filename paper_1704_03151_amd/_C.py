@@ -19,6 +19,7 @@ FACE_INTERIOR, FACE_WALL, FACE_FARFIELD, FACE_OUTFLOW = range(4)
 FP64, FP32F = 0, 1
 QUAD_TRAPEZOID, QUAD_SIMPSON38, QUAD_GAUSS_HERMITE = range(3)
 CYCLE_F = -1
+LOAD_PRESSURE, LOAD_SHEAR, LOAD_HEAT = range(3)
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -64,6 +65,14 @@ _SIGS = {
     "miugks_get_macro": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp]),
     "miugks_get_f": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "miugks_set_f": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "miugks_wall_list": (ctypes.c_int, [ctypes.c_void_p, _ip, _ip, _ip]),
+    "miugks_wall_loads": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp, _dp, _ip]),
+    "miugks_objective": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _ip, ctypes.c_int, _dp]),
+    "miugks_set_wall_T": (ctypes.c_int, [ctypes.c_void_p, _ip, _dp, ctypes.c_int]),
+    "miugks_residual_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                               ctypes.c_int]),
+    "miugks_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _ip, ctypes.c_int, _ip, ctypes.c_int,
+                                      ctypes.c_double, ctypes.c_int, _dp, _ip, _dp]),
     "miugks_residual": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp]),
     "miugks_get_div": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "miugks_predict": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp]),
@@ -110,6 +119,10 @@ class MiugksError(RuntimeError):
 
 def dptr(a: np.ndarray):
     return a.ctypes.data_as(_dp) if a is not None else None
+
+
+def iptr(a: np.ndarray):
+    return a.ctypes.data_as(_ip) if a is not None else None
 
 
 def u8ptr(a: np.ndarray):

@@ -369,6 +369,61 @@ __global__ void k_wall_density(Geo g, Vel vel, const T* __restrict__ G, double* 
     if (lane == 0 && j < g.n_wall) out[j] = -s / g.w_den[j];
 }
 
+// Loads on the diffuse walls (Sec. IV B: skin friction from the momentum
+// the gas hands to the wall): for wall side j the distribution on the wall
+// side of the face is the cell's for velocities leaving the gas and the wall
+// Maxwellian rho_w C_k for the others (Sec. III B); in the wall's frame,
+// c = u - U_w, with c_n along the normal out of the gas and c_t along the
+// face, out[j] = sum_k w c_n^2 f^G (pressure), out[nw + j] = sum_k w c_t c_n
+// f^G (shear), out[2 nw + j] = 1/2 sum_k w c_n (|c|^2 f^G + f^H) (heat flux),
+// out[3 nw + j] = the face area.  One wavefront per wall side, double sums.
+template <typename T>
+__global__ void k_wall_loads(Geo g, Vel vel, int K_int, const T* __restrict__ f, double* __restrict__ out) {
+    int j = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    int lane = threadIdx.x & 63;
+    if (j >= g.n_wall) return;
+    const int c = g.w_cell[j], sd = g.w_side[j], nw = g.n_wall;
+    const size_t ho = (size_t)vel.nk * g.nc;
+    const double sign = (sd & 1) ? 1.0 : -1.0;
+    const double lam = 1.0 / g.w_T[j], Uw = g.w_U[j], Vw = g.w_V[j];
+    double s = 0.0;
+    for (int k = lane; k < vel.nk; k += 64) {
+        double un = sign * (sd < 2 ? vel.u[k] : vel.v[k]);
+        if (un > 0) s += vel.w[k] * un * double(f[(size_t)k * g.nc + c]);
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    const double rho_w = -s / g.w_den[j];
+    double p = 0.0, t = 0.0, q = 0.0;
+    for (int k = lane; k < vel.nk; k += 64) {
+        double u = vel.u[k], v = vel.v[k], w = vel.w[k];
+        double un = sign * (sd < 2 ? u : v);
+        double cx = u - Uw, cy = v - Vw, c2 = cx * cx + cy * cy;
+        double cn = sign * (sd < 2 ? cx : cy), ct = sd < 2 ? cy : cx;
+        double Gf, Hf;
+        if (un > 0) {
+            Gf = double(f[(size_t)k * g.nc + c]);
+            Hf = double(f[ho + (size_t)k * g.nc + c]);
+        } else {
+            Gf = rho_w * (lam / M_PI) * exp(-lam * c2);
+            Hf = (K_int / (2.0 * lam)) * Gf;
+        }
+        p += w * cn * cn * Gf;
+        t += w * ct * cn * Gf;
+        q += 0.5 * w * cn * (c2 * Gf + Hf);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        p += __shfl_xor(p, off, 64);
+        t += __shfl_xor(t, off, 64);
+        q += __shfl_xor(q, off, 64);
+    }
+    if (lane == 0) {
+        out[j] = p;
+        out[nw + j] = t;
+        out[2 * nw + j] = q;
+        out[3 * nw + j] = sd < 2 ? g.dy[c / g.nx] : g.dx[c % g.nx];
+    }
+}
+
 // Wall densities of df_fine + I_H^h df_coarse from the G planes, evaluated
 // at the wall cells only (the prolonged correction is needed nowhere else
 // when a sweep follows); one wavefront per wall side

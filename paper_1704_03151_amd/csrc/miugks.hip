@@ -16,6 +16,7 @@
 #include <string>
 #include <vector>
 
+#include "adjoint.hpp"
 #include "kernels.hpp"
 #include "miugks.h"
 #include "setup.hpp"
@@ -52,6 +53,7 @@ struct miugks_ctx {
     // whose stages treat a coarse level as the finest (f then holds that level)
     int top = 0;
     double dtn_growth = 0.0;
+    double cfl = 0.5;
     bool renorm = false;
     HostVel hv;
     std::vector<HostLevel> hl;
@@ -63,6 +65,7 @@ struct miugks_ctx {
     void *f = nullptr, *div = nullptr, *finf = nullptr;
     double *W = nullptr, *q = nullptr, *R = nullptr, *Wt = nullptr, *fp = nullptr, *cp = nullptr;
     double *part = nullptr, *norms = nullptr, *rho_w = nullptr, *mass = nullptr, *msum = nullptr;
+    double* loads = nullptr;   // [4][n_wall] wall loads of level 0
     // explicit time-accurate steps: cell records of W^n, the global step per
     // cell (the level-0 geometry points at it during those steps), W^n scratch
     double *cp0 = nullptr, *dt_glob = nullptr, *Wtmp = nullptr, *tau_tmp = nullptr;
@@ -111,6 +114,15 @@ struct miugks_ctx {
     int fas_block_l0 = 1 << 30;
     std::vector<size_t> fas_block_lds;   // LDS of the one-workgroup FAS kernel starting at level l
     FasSet fasset{};
+    // adjoint (allocated on first use): lam, residual, preconditioned step,
+    // right-hand side, product, per-(k, cell) gathers, cell / face / wall
+    // records, objective weights and partial sums
+    double *a_lam = nullptr, *a_res = nullptr, *a_y = nullptr, *a_b = nullptr, *a_out = nullptr;
+    double *a_gbd = nullptr, *a_sb = nullptr, *a_crec = nullptr, *a_fa = nullptr, *a_rws = nullptr;
+    double *a_objw = nullptr, *a_Qj = nullptr, *a_rhow = nullptr, *a_part = nullptr, *a_grad = nullptr;
+    double* a_fsave = nullptr;
+    int* a_sides = nullptr;
+    int a_nparts = 0;
 };
 
 namespace {
@@ -674,6 +686,14 @@ void cycle_rest(miugks_ctx* c) {
 
 // capture Step 1 and Steps 2-7 as two graphs (once per context); timing
 // runs stay eager because each launch is bracketed by events
+// forget the captured graphs (they hold launch arguments by value, such as
+// the reference mass); the next run captures them again
+void drop_graphs(miugks_ctx* c) {
+    if (c->g_step1) (void)hipGraphExecDestroy(c->g_step1);
+    if (c->g_rest) (void)hipGraphExecDestroy(c->g_rest);
+    c->g_step1 = c->g_rest = nullptr;
+}
+
 template <typename T>
 int ensure_graphs(miugks_ctx* c) {
     if (c->g_step1 && c->g_rest) return MIUGKS_OK;
@@ -1162,6 +1182,7 @@ int build_device(miugks_ctx* ctx) {
         (rc = dalloc(&ctx->cp0, NCP * nc0)) || (rc = dalloc(&ctx->dt_glob, nc0)) ||
         (rc = dalloc(&ctx->Wtmp, 4 * nc0)) || (rc = dalloc(&ctx->tau_tmp, nc0)) ||
         (rc = dalloc(&ctx->rho_w, ctx->hl[0].w_cell.size() + 1)) || (rc = dalloc(&ctx->mass, 1)) ||
+        (rc = dalloc(&ctx->loads, 4 * ctx->hl[0].w_cell.size() + 1)) ||
         (rc = dalloc(&ctx->msum, 2 * NRAW * nc0)))
         return rc;
     {
@@ -1307,6 +1328,7 @@ int reset_mass(miugks_ctx* c) {
         return MIUGKS_EDEVICE;
     }
     c->M0 = m;
+    drop_graphs(c);   // the renormalisation kernels take M0 by value
     return MIUGKS_OK;
 }
 
@@ -1477,6 +1499,7 @@ int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgri
     ctx->gamma = s->cycle_gamma != 0 ? s->cycle_gamma : 1;
     ctx->gamma_cs = s->cycle_gamma_cs != 0 ? s->cycle_gamma_cs : ctx->gamma;
     ctx->dtn_growth = s->dtn_growth;
+    ctx->cfl = s->cfl;
     HostVel& hv = ctx->hv;
     hv.nu = v->nu;
     hv.nv = v->nv;
@@ -1643,6 +1666,327 @@ int miugks_get_macro(miugks_ctx* ctx, double* rho, double* U, double* V, double*
         if (qy) qy[c] = q[nc + c];
     }
     return MIUGKS_OK;
+}
+
+int miugks_wall_list(miugks_ctx* ctx, int* cell, int* side, int* n_walls) {
+    if (!ctx || !n_walls) return MIUGKS_EINVAL;
+    const HostLevel& h = ctx->hl[0];
+    *n_walls = (int)h.w_cell.size();
+    for (size_t j = 0; j < h.w_cell.size(); ++j) {
+        if (cell) cell[j] = h.w_cell[j];
+        if (side) side[j] = h.w_side[j];
+    }
+    return MIUGKS_OK;
+}
+
+// pressure, shear, heat flux and area of every wall side of level 0 into the
+// host array out[4][n_wall]
+static int wall_loads_host(miugks_ctx* ctx, std::vector<double>& out) {
+    const Geo& g = ctx->geo[0];
+    out.assign(4 * (size_t)g.n_wall, 0.0);
+    if (g.n_wall == 0) return MIUGKS_OK;
+    double* d = ctx->loads;
+    if (ctx->prec == MIUGKS_FP64)
+        k_wall_loads<double><<<dim3((g.n_wall + 3) / 4), dim3(256), 0, ctx->stream>>>(g, ctx->vel, ctx->gas.K_int,
+                                                                                    (const double*)ctx->f, d);
+    else
+        k_wall_loads<float><<<dim3((g.n_wall + 3) / 4), dim3(256), 0, ctx->stream>>>(g, ctx->vel, ctx->gas.K_int,
+                                                                                   (const float*)ctx->f, d);
+    int rc = check_launch(ctx);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(out.data(), d, out.size() * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return MIUGKS_OK;
+}
+
+int miugks_wall_loads(miugks_ctx* ctx, double* p, double* tau, double* q, double* S, int* n_walls) {
+    if (!ctx || !n_walls) return MIUGKS_EINVAL;
+    int nw = ctx->geo[0].n_wall;
+    *n_walls = nw;
+    if (!p && !tau && !q && !S) return MIUGKS_OK;
+    std::vector<double> ld;
+    int rc = wall_loads_host(ctx, ld);
+    if (rc) return rc;
+    double* dst[4] = {p, tau, q, S};
+    for (int m = 0; m < 4; ++m)
+        if (dst[m]) std::copy(ld.begin() + (size_t)m * nw, ld.begin() + (size_t)(m + 1) * nw, dst[m]);
+    return MIUGKS_OK;
+}
+
+int miugks_objective(miugks_ctx* ctx, int kind, const int* walls, int n, double* J) {
+    if (!ctx || !J || n < 0 || (n > 0 && !walls)) return MIUGKS_EINVAL;
+    if (kind < MIUGKS_LOAD_PRESSURE || kind > MIUGKS_LOAD_HEAT) {
+        ctx->err = "objective kind must be MIUGKS_LOAD_PRESSURE, MIUGKS_LOAD_SHEAR or MIUGKS_LOAD_HEAT";
+        return MIUGKS_EINVAL;
+    }
+    int nw = ctx->geo[0].n_wall;
+    for (int i = 0; i < n; ++i)
+        if (walls[i] < 0 || walls[i] >= nw) {
+            ctx->err = "wall index out of range";
+            return MIUGKS_EINVAL;
+        }
+    std::vector<double> ld;
+    int rc = wall_loads_host(ctx, ld);
+    if (rc) return rc;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += ld[3 * (size_t)nw + walls[i]] * ld[(size_t)kind * nw + walls[i]];
+    *J = s;
+    return MIUGKS_OK;
+}
+
+int miugks_set_wall_T(miugks_ctx* ctx, const int* faces, const double* Tw, int n) {
+    if (!ctx || n < 0 || (n > 0 && (!faces || !Tw))) return MIUGKS_EINVAL;
+    const HostLevel& h0 = ctx->hl[0];
+    const int nfx = (h0.nx + 1) * h0.ny, nfy = h0.nx * (h0.ny + 1);
+    std::vector<double> wx = h0.wallx, wy = h0.wally;
+    for (int i = 0; i < n; ++i) {
+        int f = faces[i];
+        if (f < 0 || f >= nfx + nfy || (f < nfx ? h0.ftx[f] : h0.fty[f - nfx]) != MIUGKS_FACE_WALL) {
+            ctx->err = "face index out of range or not a wall";
+            return MIUGKS_EINVAL;
+        }
+        if (!(Tw[i] > 0)) {
+            ctx->err = "wall temperature must be positive";
+            return MIUGKS_EINVAL;
+        }
+        (f < nfx ? wx[3 * (size_t)f] : wy[3 * (size_t)(f - nfx)]) = Tw[i];
+    }
+    // the coarse levels take area-weighted means of the new fine walls, as at creation
+    std::vector<HostLevel> nh;
+    std::string err;
+    if (!build_levels(h0.nx, h0.ny, ctx->L, h0.xn.data(), h0.yn.data(), h0.ftx.data(), h0.fty.data(), wx.data(),
+                      wy.data(), h0.solid.data(), ctx->hv, ctx->cfl, nh, err)) {
+        ctx->err = err;
+        return MIUGKS_EINVAL;
+    }
+    for (int l = 0; l < ctx->L; ++l) {
+        HostLevel& h = ctx->hl[l];
+        h.wallx = nh[l].wallx;
+        h.wally = nh[l].wally;
+        h.w_T = nh[l].w_T;
+        h.w_den = nh[l].w_den;
+        if (h.w_T.empty()) continue;
+        HIP_TRY(hipMemcpyAsync((double*)ctx->geo[l].w_T, h.w_T.data(), h.w_T.size() * sizeof(double),
+                               hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(hipMemcpyAsync((double*)ctx->geo[l].w_den, h.w_den.data(), h.w_den.size() * sizeof(double),
+                               hipMemcpyHostToDevice, ctx->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return MIUGKS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of the steady state (FP64 contexts)
+
+static int adj_alloc(miugks_ctx* c) {
+    if (c->a_lam) return MIUGKS_OK;
+    const size_t nc = c->hl[0].nc, n = (size_t)c->nk * nc, nw = c->hl[0].w_cell.size() + 1;
+    auto da = [c](double** p, size_t cnt) { return dev_alloc(c, (void**)p, cnt * sizeof(double)); };
+    c->a_nparts = 1024;
+    int rc;
+    if ((rc = da(&c->a_lam, 2 * n)) || (rc = da(&c->a_res, 2 * n)) || (rc = da(&c->a_y, 2 * n)) ||
+        (rc = da(&c->a_b, 2 * n)) || (rc = da(&c->a_out, 2 * n)) || (rc = da(&c->a_gbd, 2 * n)) ||
+        (rc = da(&c->a_sb, 4 * n)) || (rc = da(&c->a_crec, NCA * nc)) || (rc = da(&c->a_fa, NFA * 2 * nc)) ||
+        (rc = da(&c->a_rws, nw)) || (rc = da(&c->a_objw, nw)) || (rc = da(&c->a_Qj, nw)) ||
+        (rc = da(&c->a_rhow, nw)) || (rc = da(&c->a_part, c->a_nparts)) || (rc = da(&c->a_grad, 2 * nw)) ||
+        (rc = da(&c->a_fsave, 2 * n)) || (rc = dev_alloc(c, (void**)&c->a_sides, 2 * nw * sizeof(int))))
+        return rc;
+    return MIUGKS_OK;
+}
+
+static int adj_check(miugks_ctx* c) {
+    if (c->prec != MIUGKS_FP64) {
+        c->err = "the adjoint needs an FP64 context";
+        return MIUGKS_EINVAL;
+    }
+    if (c->top != 0) {
+        c->err = "not during a full-multigrid start";
+        return MIUGKS_ESTATE;
+    }
+    return adj_alloc(c);
+}
+
+// out = (dr/df)^T v at the current f; Step 1 (interface records) and the
+// moments must be those of f
+static void adj_product(miugks_ctx* c, const double* v, double* out) {
+    const Geo& g = c->geo[0];
+    const size_t n = (size_t)c->nk * g.nc;
+    const double* f = (const double*)c->f;
+    const double pass = 2.0 * n * 8;
+    LAUNCH(c, "adj_cell", pass, k_adj_cell, dim3((g.nc + 3) / 4), dim3(256), g, c->vel, c->gas, f,
+           (const double*)c->W, (const double*)c->q, v, c->a_crec);
+    LAUNCH(c, "adj_face", 2 * pass, k_adj_face, dim3((2 * g.nc + 3) / 4), dim3(256), g, c->vel, c->gas, f,
+           (const double*)c->W, (const double*)c->fp, v, c->a_fa);
+    if (g.n_wall)
+        LAUNCH(c, "adj_wall", 0.0, k_adj_wall, dim3((g.n_wall + 3) / 4), dim3(256), g, c->vel, c->gas.K_int, v,
+               c->a_rws);
+    dim3 nb((unsigned)((n + 255) / 256));
+    LAUNCH(c, "adj_gather", 4 * pass, k_adj_gather, nb, dim3(256), g, c->vel, (const double*)c->fp,
+           (const double*)c->a_fa, v, c->a_gbd, c->a_sb);
+    LAUNCH(c, "adj_assemble", 6 * pass, k_adj_assemble, nb, dim3(256), g, c->vel, f, v, (const double*)c->a_crec,
+           (const double*)c->a_fa, (const double*)c->a_rws, (const double*)c->a_gbd, (const double*)c->a_sb, out);
+}
+
+int miugks_residual_adjoint(miugks_ctx* ctx, const void* v, void* out, int dtype, int on_device) {
+    if (!ctx) return MIUGKS_EINVAL;
+    int rc;
+    if ((rc = adj_check(ctx))) return rc;
+    if ((rc = copy_in(ctx, v, ctx->a_y, dtype, on_device))) return rc;
+    Path<double>::residual(ctx);
+    adj_product(ctx, ctx->a_y, ctx->a_out);
+    if ((rc = copy_out(ctx, ctx->a_out, out, dtype, on_device))) return rc;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return check_launch(ctx);
+}
+
+// mesh face of wall side j of level 0 (x-faces first, then y-faces)
+static int wall_face(const HostLevel& h, int j) {
+    int c = h.w_cell[j], s = h.w_side[j], ix = c % h.nx, iy = c / h.nx, nfx = (h.nx + 1) * h.ny;
+    switch (s) {
+        case 0: return iy * (h.nx + 1) + ix;
+        case 1: return iy * (h.nx + 1) + ix + 1;
+        case 2: return nfx + iy * h.nx + ix;
+        default: return nfx + (iy + 1) * h.nx + ix;
+    }
+}
+
+int miugks_adjoint(miugks_ctx* ctx, int kind, const int* walls, int n, const int* param_faces, int n_param,
+                   double tol, int max_iter, double* dJ_dTw, int* iters, double* res_out) {
+    if (!ctx || n < 0 || n_param < 0 || (n > 0 && !walls) || (n_param > 0 && (!param_faces || !dJ_dTw)) ||
+        max_iter < 0)
+        return MIUGKS_EINVAL;
+    int rc;
+    if ((rc = adj_check(ctx))) return rc;
+    if (kind < MIUGKS_LOAD_PRESSURE || kind > MIUGKS_LOAD_HEAT) {
+        ctx->err = "objective kind must be MIUGKS_LOAD_PRESSURE, MIUGKS_LOAD_SHEAR or MIUGKS_LOAD_HEAT";
+        return MIUGKS_EINVAL;
+    }
+    const HostLevel& h0 = ctx->hl[0];
+    const Geo& g = ctx->geo[0];
+    const int nw = g.n_wall;
+    const size_t N = 2 * (size_t)ctx->nk * g.nc;
+    std::vector<double> objw(nw + 1, 0.0);
+    for (int i = 0; i < n; ++i) {
+        if (walls[i] < 0 || walls[i] >= nw) {
+            ctx->err = "wall index out of range";
+            return MIUGKS_EINVAL;
+        }
+        objw[walls[i]] += 1.0;
+    }
+    // parameter faces -> wall sides
+    std::vector<int> sides, owner;
+    for (int p = 0; p < n_param; ++p) {
+        int found = 0;
+        for (int j = 0; j < nw; ++j)
+            if (wall_face(h0, j) == param_faces[p]) {
+                sides.push_back(j);
+                owner.push_back(p);
+                ++found;
+            }
+        if (!found) {
+            ctx->err = "parameter face is not a wall of a fluid cell";
+            return MIUGKS_EINVAL;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->a_objw, objw.data(), objw.size() * sizeof(double), hipMemcpyHostToDevice,
+                           ctx->stream));
+    if (!sides.empty())
+        HIP_TRY(hipMemcpyAsync(ctx->a_sides, sides.data(), sides.size() * sizeof(int), hipMemcpyHostToDevice,
+                               ctx->stream));
+    auto objective = [&](double& J) {
+        std::vector<double> ld;
+        int r = wall_loads_host(ctx, ld);
+        if (r) return r;
+        J = 0.0;
+        for (int i = 0; i < n; ++i) J += ld[3 * (size_t)nw + walls[i]] * ld[(size_t)kind * nw + walls[i]];
+        return (int)MIUGKS_OK;
+    };
+    // a closed domain's steady states form a family in the total mass M and
+    // the residual's Jacobian is singular (the mass row is its left null
+    // vector): the adjoint equation takes the term mu m with mu = dJ/dM along
+    // the family, from two steady states at masses M0 (1 +- delta)
+    double mu = 0.0;
+    if (ctx->renorm) {
+        const double delta = 1e-4, M0 = ctx->M0;
+        double Jpm[2];
+        HIP_TRY(hipMemcpyAsync(ctx->a_fsave, ctx->f, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+        for (int sgn = 0; sgn < 2; ++sgn) {
+            double sc = sgn == 0 ? delta : -delta;
+            HIP_TRY(hipMemcpyAsync(ctx->f, ctx->a_fsave, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+            LAUNCH(ctx, "adj_axpy", 3.0 * N * 8, k_adj_axpy, dim3((unsigned)((N + 255) / 256)), dim3(256),
+                   (double*)ctx->f, (const double*)ctx->f, sc, N);
+            ctx->M0 = M0 * (1.0 + sc);
+            drop_graphs(ctx);
+            Path<double>::moments(ctx, nullptr);
+            int done = 0;
+            double res[4];
+            rc = run_cycles<double>(ctx, 300, 1e-13, &done, res);
+            if (rc == MIUGKS_OK || rc == MIUGKS_ENOTCONVERGED) rc = objective(Jpm[sgn]);
+            if (rc) break;
+        }
+        HIP_TRY(hipMemcpyAsync(ctx->f, ctx->a_fsave, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+        ctx->M0 = M0;
+        drop_graphs(ctx);
+        Path<double>::moments(ctx, nullptr);
+        if (rc) return rc;
+        mu = (Jpm[0] - Jpm[1]) / (2.0 * delta * M0);
+    }
+    Path<double>::residual(ctx);
+    // right-hand side b = dJ/df - mu m
+    if (nw)
+        LAUNCH(ctx, "adj_objwall", 0.0, k_adj_objwall, dim3((nw + 3) / 4), dim3(256), g, ctx->vel, ctx->gas.K_int,
+               kind, (const double*)ctx->f, ctx->a_Qj, ctx->a_rhow);
+    dim3 nbN((unsigned)((N / 2 + 255) / 256));
+    LAUNCH(ctx, "adj_objgrad", N * 8.0, k_adj_objgrad, nbN, dim3(256), g, ctx->vel, kind,
+           (const double*)ctx->a_objw, (const double*)ctx->a_Qj, mu, ctx->a_b);
+    LAUNCH(ctx, "zero", N * 8.0, k_zero<double>, dim3((unsigned)std::min<size_t>((N + 255) / 256, 1 << 16)), dim3(256),
+           ctx->a_lam, N);
+    // defect correction: lam <- lam - A^-T (b - (dr/df)^T lam)
+    const int threads = ((g.ny + 63) / 64) * 64;
+    const size_t lds = 2 * (size_t)g.ny * sizeof(double);
+    std::vector<double> part(ctx->a_nparts);
+    double r0 = 0.0, rn = 0.0;
+    int it = 0;
+    for (;; ++it) {
+        adj_product(ctx, ctx->a_lam, ctx->a_out);
+        LAUNCH(ctx, "adj_residual", 3.0 * N * 8, k_adj_residual, dim3(ctx->a_nparts), dim3(256),
+               (const double*)ctx->a_b, (const double*)ctx->a_out, ctx->a_res, N, ctx->a_part);
+        HIP_TRY(hipMemcpyAsync(part.data(), ctx->a_part, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        if ((rc = check_launch(ctx))) return rc;
+        double ss = 0.0;
+        for (double x : part) ss += x;
+        rn = std::sqrt(ss);
+        if (it == 0) r0 = rn;
+        if (!std::isfinite(rn)) {
+            ctx->err = "adjoint iteration diverged";
+            return MIUGKS_EDIVERGED;
+        }
+        if (rn <= tol * r0 || r0 == 0.0 || it >= max_iter) break;
+        LAUNCH_SH(ctx, "adj_sweep", 4.0 * N * 8, lds, k_adj_sweep, dim3(ctx->nk), dim3(threads), g, ctx->vel,
+                  (const double*)ctx->a_crec, (const double*)ctx->a_res, ctx->a_y);
+        LAUNCH(ctx, "adj_axpy", 3.0 * N * 8, k_adj_axpy, dim3((unsigned)((N + 255) / 256)), dim3(256), ctx->a_lam,
+               (const double*)ctx->a_y, -1.0, N);
+    }
+    // dJ/dT_w = dJ/dT_w|_f - lam^T dr/dT_w, summed over the sides of each face
+    if (!sides.empty()) {
+        LAUNCH(ctx, "adj_paramgrad", 0.0, k_adj_paramgrad, dim3(((int)sides.size() + 3) / 4), dim3(256), g,
+               ctx->vel, ctx->gas.K_int, kind, (const double*)ctx->a_objw, (const double*)ctx->a_Qj,
+               (const double*)ctx->a_rhow, (const double*)ctx->a_lam, (const int*)ctx->a_sides, (int)sides.size(),
+               ctx->a_grad);
+        std::vector<double> gs(sides.size());
+        HIP_TRY(hipMemcpyAsync(gs.data(), ctx->a_grad, gs.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        for (int p = 0; p < n_param; ++p) dJ_dTw[p] = 0.0;
+        for (size_t i = 0; i < sides.size(); ++i) dJ_dTw[owner[i]] += gs[i];
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if ((rc = check_launch(ctx))) return rc;
+    if (iters) *iters = it;
+    if (res_out) *res_out = r0 > 0.0 ? rn / r0 : 0.0;
+    return (r0 == 0.0 || rn <= tol * r0) ? MIUGKS_OK : MIUGKS_ENOTCONVERGED;
 }
 
 int miugks_get_f(miugks_ctx* ctx, void* dst, int dtype, int on_device) {

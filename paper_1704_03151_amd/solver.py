@@ -142,6 +142,59 @@ class Solver:
             raise ValueError(f"f must be float32/float64 shaped {self.fshape}")
         self._check(_C.lib.miugks_set_f(self.h, a.ctypes.data_as(ctypes.c_void_p), code, 0))
 
+    def wall_list(self):
+        """(cell, side) of every wall side of the finest level, in library order."""
+        n = ctypes.c_int()
+        self._check(_C.lib.miugks_wall_list(self.h, None, None, ctypes.byref(n)))
+        cell = np.zeros(n.value, np.int32)
+        side = np.zeros(n.value, np.int32)
+        self._check(_C.lib.miugks_wall_list(self.h, _C.iptr(cell), _C.iptr(side), ctypes.byref(n)))
+        return cell, side
+
+    def wall_loads(self):
+        """Array (4, n_walls): pressure, shear, heat flux, face area per wall side."""
+        n = ctypes.c_int()
+        self._check(_C.lib.miugks_wall_loads(self.h, None, None, None, None, ctypes.byref(n)))
+        out = np.zeros((4, n.value))
+        self._check(_C.lib.miugks_wall_loads(self.h, *(_C.dptr(out[m]) for m in range(4)), ctypes.byref(n)))
+        return out
+
+    def objective(self, kind, walls):
+        ids = np.ascontiguousarray(walls, np.int32)
+        J = np.zeros(1)
+        self._check(_C.lib.miugks_objective(self.h, int(kind), _C.iptr(ids), len(ids), _C.dptr(J)))
+        return float(J[0])
+
+    def set_wall_T(self, faces, Tw):
+        ids = np.ascontiguousarray(faces, np.int32)
+        T = np.ascontiguousarray(Tw, float)
+        if T.shape != ids.shape:
+            raise ValueError("one temperature per face")
+        self._check(_C.lib.miugks_set_wall_T(self.h, _C.iptr(ids), _C.dptr(T), len(ids)))
+
+    def residual_adjoint(self, v):
+        """(dr/df)^T v of the steady residual at the current f (FP64 contexts)."""
+        a = np.ascontiguousarray(v, np.float64)
+        if a.shape != self.fshape:
+            raise ValueError(f"v must be shaped {self.fshape}")
+        out = np.zeros(self.fshape)
+        self._check(_C.lib.miugks_residual_adjoint(self.h, a.ctypes.data_as(ctypes.c_void_p),
+                                                   out.ctypes.data_as(ctypes.c_void_p), _C.FP64, 0))
+        return out
+
+    def adjoint(self, kind, walls, faces, tol=1e-10, max_iter=2000):
+        """dJ/dTw of J = sum_walls S load_kind for the listed mesh faces; returns
+        (status, gradient, corrections, relative residual)."""
+        ids = np.ascontiguousarray(walls, np.int32)
+        fc = np.ascontiguousarray(faces, np.int32)
+        g = np.zeros(len(fc))
+        it = ctypes.c_int()
+        res = np.zeros(1)
+        rc = _C.lib.miugks_adjoint(self.h, int(kind), _C.iptr(ids), len(ids), _C.iptr(fc), len(fc), float(tol),
+                                   int(max_iter), _C.dptr(g), ctypes.byref(it), _C.dptr(res))
+        self._check(rc, allow=(_C.ENOTCONVERGED,))
+        return rc, g, it.value, float(res[0])
+
     def residual(self):
         R = np.zeros((4, self.case.ny, self.case.nx))
         res = np.zeros(4)

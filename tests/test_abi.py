@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _header_symbols():
     with open(os.path.join(ROOT, "include", "miugks.h")) as fh:
         text = fh.read()
-    return sorted(set(re.findall(r"\b(miugks_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(miugks_[A-Za-z_]+)\s*\(", text)))
 
 
 def test_header_constants_match_the_binding_and_the_inputs():
@@ -27,7 +27,7 @@ def test_header_constants_match_the_binding_and_the_inputs():
         text = fh.read()
     consts = {k: int(v) for k, v in re.findall(r"#define MIUGKS_([A-Z0-9_]+) \(?(-?\d+)\)?", text)}
     for name in ("OK", "EINVAL", "ENOMEM", "EDEVICE", "EDIVERGED", "ENOTCONVERGED", "ESTATE", "FP64", "FP32F",
-                 "QUAD_TRAPEZOID", "QUAD_SIMPSON38", "QUAD_GAUSS_HERMITE", "CYCLE_F",
+                 "QUAD_TRAPEZOID", "QUAD_SIMPSON38", "QUAD_GAUSS_HERMITE", "CYCLE_F", "LOAD_PRESSURE", "LOAD_SHEAR", "LOAD_HEAT",
                  "FACE_INTERIOR", "FACE_WALL", "FACE_FARFIELD", "FACE_OUTFLOW"):
         assert consts[name] == getattr(_C, name), name
     for name in ("FACE_INTERIOR", "FACE_WALL", "FACE_FARFIELD", "FACE_OUTFLOW", "CYCLE_F"):

@@ -1,0 +1,116 @@
+"""GPU adjoint (through the C ABI) against the FP64 CPU oracle:
+
+* the transposed residual product (dr/df)^T v element by element against the
+  oracle's dense complex-step Jacobian on tiny cases (1e-11 max-norm
+  relative), and as <(dr/df)^T v, d> = <v, (dr/df) d> on larger ones with the
+  oracle's complex-step directional derivative (1e-10);
+* the wall-temperature gradient of the lid shear at a converged steady state
+  against the oracle's fixed-mass tangent (plain linear solve on the dense
+  Jacobian).  The GPU takes dJ/dM along the mass family from two steady
+  states at masses M0 (1 +- 1e-4), good to about 1e-8 of the gradient, so
+  the gradient is compared at 1e-6."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from _parity import perturbed_state, small_cases, to_oracle
+from oracle import adjoint as ad
+from oracle.solver import Oracle
+
+pytestmark = pytest.mark.gpu
+
+N = 4
+
+
+def _tiny_cavity():
+    case = wl.cavity(n=N, Kn=2.0, n_levels=2, quad="gauss_hermite", nvel=8, vlo=0.0, vhi=0.0, mach=0.3,
+                     precision="fp64")
+    rng = np.random.default_rng(1704)
+    case.wall_y[0, :, 0] = 1.0 + rng.uniform(-0.05, 0.05, N)
+    return case
+
+
+def _tiny_plate():
+    """8 x 6 cells around a plate, farfield sides and an outflow side, 6 x 6
+    velocities on [-3, 3]."""
+    case = wl.flat_plate(scale=16, quad="trapezoid", nu=6, nv=6, vlo=-3.0, vhi=3.0, n_levels=1, precision="fp64",
+                         Kn=0.3)
+    case.face_type_x[:, -1] = wl.FACE_OUTFLOW
+    return case
+
+
+def _pair_at(case, seed):
+    """GPU solver and oracle holding the same perturbed distribution."""
+    from paper_1704_03151_amd import Solver
+    gpu = Solver(case, precision="fp64")
+    prim, pert = perturbed_state(case, seed)
+    gpu.init_macro(prim)
+    gpu.set_f(gpu.get_f() * pert)
+    orc = Oracle(case)
+    orc.init_macro(prim)
+    orc.set_f(*to_oracle(gpu.get_f()))
+    return gpu, orc
+
+
+@pytest.mark.parametrize("which", ["cavity", "plate"])
+def test_residual_adjoint_against_dense_jacobian(which):
+    case = _tiny_cavity() if which == "cavity" else _tiny_plate()
+    print(f"[adjoint] {which}: (dr/df)^T v against the dense Jacobian", flush=True)
+    gpu, orc = _pair_at(case, 71)
+    S = ad.Sensitivity(orc)
+    J = S.jacobian()
+    rng = np.random.default_rng(72)
+    for _ in range(2):
+        vG = rng.standard_normal(orc.G.shape) * orc.lev0.fluid
+        vH = rng.standard_normal(orc.H.shape) * orc.lev0.fluid
+        v = np.stack([vG.reshape(-1, case.ny, case.nx), vH.reshape(-1, case.ny, case.nx)])
+        got = S.pack(*to_oracle(gpu.residual_adjoint(v)))
+        ref = J.T @ S.pack(vG, vH)
+        assert np.max(np.abs(got - ref)) < 1e-11 * np.max(np.abs(ref)), np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    gpu.close()
+
+
+@pytest.mark.parametrize("name", ["cavity16_kn10", "square20x20", "plate32x24", "box12x10_ragged"])
+def test_residual_adjoint_dot_products(name):
+    case = small_cases()[name].with_(precision="fp64")
+    print(f"[adjoint] {name}: dot-product test", flush=True)
+    gpu, orc = _pair_at(case, 73)
+    S = ad.Sensitivity(orc)
+    x0 = S.pack(orc.G, orc.H)
+    rng = np.random.default_rng(74)
+    for _ in range(3):
+        d = rng.standard_normal(x0.size) * np.abs(x0)
+        Jd = S.residual(x0.astype(complex) + 1e-30j * d).imag / 1e-30
+        vG = rng.standard_normal(orc.G.shape) * orc.lev0.fluid
+        vH = rng.standard_normal(orc.H.shape) * orc.lev0.fluid
+        v = np.stack([vG.reshape(-1, case.ny, case.nx), vH.reshape(-1, case.ny, case.nx)])
+        JTv = S.pack(*to_oracle(gpu.residual_adjoint(v)))
+        lhs = JTv @ d
+        rhs = S.pack(vG, vH) @ Jd
+        scale = np.sum(np.abs(JTv * d))
+        assert abs(lhs - rhs) < 1e-10 * scale, (lhs, rhs, scale)
+    gpu.close()
+
+
+def test_adjoint_gradient_against_oracle():
+    """Lid shear of the tiny cavity, gradient with respect to three bottom
+    faces and one side face, at steady states converged on both sides."""
+    from paper_1704_03151_amd import Solver
+    case = _tiny_cavity()
+    print("[adjoint] tiny cavity: dJ/dTw", flush=True)
+    gpu = Solver(case, precision="fp64")
+    orc = Oracle(case)
+    rc, n, res = gpu.iterate(300, tol=2e-13)
+    ok, norms = orc.iterate(300, tol=2e-13)
+    assert rc == 0 and ok, (rc, res, norms)
+    cell, side = gpu.wall_list()
+    lid = list(np.nonzero(side == 3)[0])
+    nfx = (N + 1) * N
+    faces = [nfx + 0, nfx + 1, nfx + 3, 0]
+    st, g, iters, rel = gpu.adjoint(ad.LOAD_SHEAR, lid, faces, tol=1e-9, max_iter=2000)
+    ref = ad.Sensitivity(orc).gradient(ad.LOAD_SHEAR, lid, faces)
+    err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+    print(f"[adjoint] {iters} corrections, relative residual {rel:.2e}, gradient error {err:.2e}", flush=True)
+    assert st == 0
+    assert err < 1e-6, (g, ref)
+    gpu.close()

@@ -83,3 +83,40 @@ def test_square_full_size_fp32_matches_fp64():
     err = field_errors(out["fp32f"], (m64["rho"], m64["U"], m64["V"], m64["T"]), fl)
     print(f"[full] square fp32f against fp64: {err}", flush=True)
     assert max(err.values()) < 1e-5, err
+
+
+def test_adjoint_full_size_against_steady_state_differences():
+    """The adjoint at the size it is meant for: the 64x64 cavity at Kn 0.1
+    with 784 Gauss-Hermite velocities, FP64, converged to 1e-12; the lid-shear
+    gradient over the 64 bottom-face temperatures against central differences
+    (h = 2e-5) of the GPU's own steady states at two faces.  The differences
+    carry about 1e-12 / 2h of convergence noise in J, hence the floor of 1e-2
+    of the largest gradient component in the tolerance scale."""
+    from paper_1704_03151_amd import Solver
+    case = wl.config5(precision="fp64")
+    print("[full] cavity64 Kn 0.1 x 784: adjoint against steady-state differences", flush=True)
+    s = Solver(case, precision="fp64")
+    rc, n, res = s.iterate(600, tol=1e-12)
+    assert rc == 0, res
+    cell, side = s.wall_list()
+    lid = list(np.nonzero(side == 3)[0])
+    nfx = (case.nx + 1) * case.ny
+    faces = [nfx + i for i in range(case.nx)]
+    st, g, iters, rel = s.adjoint(1, lid, faces, tol=1e-8, max_iter=4000)
+    print(f"[full] adjoint: {iters} corrections, relative residual {rel:.2e}", flush=True)
+    assert st == 0
+    f0 = s.get_f()
+    h = 2e-5
+    for fi in (5, 40):
+        vals = []
+        for sg in (1.0, -1.0):
+            s.set_wall_T([faces[fi]], [case.wall_y[0, fi, 0] + sg * h])
+            s.set_f(f0)
+            rc2, _, r2 = s.iterate(400, tol=1e-12)
+            assert rc2 == 0, r2
+            vals.append(s.objective(1, lid))
+        s.set_wall_T([faces[fi]], [case.wall_y[0, fi, 0]])
+        s.set_f(f0)
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(g[fi] - fd) <= 3e-4 * max(abs(fd), 1e-2 * np.max(np.abs(g))), (fi, g[fi], fd)
+    s.close()
