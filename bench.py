@@ -103,6 +103,58 @@ def explicit_bench(args, case, solver, pts):
     print(json.dumps(line), flush=True)
 
 
+def adjoint_bench(args, case, solver):
+    """Wall-temperature gradients of the lid shear on a converged FP64 steady
+    state: W untimed and K timed adjoint solves (each with its two
+    mass-perturbed steady states), then one with per-kernel timing."""
+    import numpy as np
+    import torch
+    rc, n, res = solver.iterate(1000, tol=1e-12)
+    print(f"[bench] steady state: {n} cycles, residual {res.max():.2e} (status {rc})", file=sys.stderr, flush=True)
+    cell, side = solver.wall_list()
+    lid = [int(j) for j in np.nonzero(side == 3)[0]]
+    nfx = (case.nx + 1) * case.ny
+    faces = [nfx + i for i in range(case.nx)]
+    tol = 1e-8
+    for _ in range(args.warmup):
+        solver.adjoint(1, lid, faces, tol=tol, max_iter=5000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st, g, iters, rel = solver.adjoint(1, lid, faces, tol=tol, max_iter=5000)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    print(f"[bench] {args.steps} adjoint solves: {sec:.3f} s each, {iters} corrections, residual {rel:.2e}",
+          file=sys.stderr, flush=True)
+    solver.set_timing(True)
+    solver.adjoint(1, lid, faces, tol=tol, max_iter=5000)
+    stats = solver.timing()
+    solver.set_timing(False)
+    adj = {k: v for k, v in stats.items() if k.startswith("adj_")}
+    dom = max(adj, key=lambda k: adj[k][1])
+    n_l, ms, by = adj[dom]
+    achieved = by / n_l / (ms / n_l * 1e-3) / 1e9
+    pts = case.n_fluid * case.n_vel
+    line = {
+        "metric": "wall-temperature gradients/s (adjoint solves of the steady lid shear)",
+        "value": 1.0 / sec, "unit": "gradients/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{case.name}: {RECIPES.get(args.config, 'synthetic case')}; lid shear, "
+                               f"{len(faces)} bottom-face temperatures, adjoint to a 1e-8 residual drop",
+                   "cells": case.n_cells, "velocities": case.n_vel, "precision": "fp64"},
+        "corrections": iters, "relative_residual": rel,
+        "ms_per_correction": sec * 1e3 / max(iters, 1),
+        "transposed_products_per_s": pts * max(iters, 1) / sec,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": by / n_l,
+                     "mean_launch_ms": ms / n_l},
+        "kernel_ms_per_solve": {k: v[1] for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])[:12]},
+        "gradient_max": float(np.max(np.abs(g))),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +165,9 @@ def main():
     ap.add_argument("--explicit", action="store_true",
                     help="time explicit time-accurate UGKS steps instead of MG cycles (the interface flux, the "
                          "collision update and the moments, once per step)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time adjoint solves (wall-temperature gradients of the lid shear) on a converged FP64 "
+                         "steady state of the adjoint cavity (config 5 unless --config is given)")
     ap.add_argument("--dtn-growth", type=float, default=None,
                     help="override the workload's pseudo-step growth a (dt_n = a^n dt_p; 0: off)")
     ap.add_argument("--cpu-cycles", type=int, default=1)
@@ -133,6 +188,10 @@ def main():
     from paper_1704_03151_amd import Solver
 
     torch.cuda.set_device(0)
+    if args.adjoint:
+        if "--config" not in sys.argv:
+            args.config = 5
+        args.precision = "fp64"
     case = wl.CONFIGS[args.config]()
     if args.dtn_growth is not None:
         case = case.with_(dtn_growth=args.dtn_growth)
@@ -143,6 +202,8 @@ def main():
 
     if args.explicit:
         return explicit_bench(args, case, solver, pts)
+    if args.adjoint:
+        return adjoint_bench(args, case, solver)
     # warm-up, then exactly K timed cycles
     solver.iterate(args.warmup, tol=0.0)
     torch.cuda.synchronize()

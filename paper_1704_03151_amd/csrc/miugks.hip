@@ -1812,8 +1812,11 @@ static void adj_product(miugks_ctx* c, const double* v, double* out) {
     const Geo& g = c->geo[0];
     const size_t n = (size_t)c->nk * g.nc;
     const double* f = (const double*)c->f;
+    // algorithmic bytes: one pass = one distribution-shaped array (2 planes);
+    // cell and face kernels read f and v, the gather reads v and writes 6
+    // planes, the assembly reads f, v and 6 gathered planes and writes out
     const double pass = 2.0 * n * 8;
-    LAUNCH(c, "adj_cell", pass, k_adj_cell, dim3((g.nc + 3) / 4), dim3(256), g, c->vel, c->gas, f,
+    LAUNCH(c, "adj_cell", 2 * pass, k_adj_cell, dim3((g.nc + 3) / 4), dim3(256), g, c->vel, c->gas, f,
            (const double*)c->W, (const double*)c->q, v, c->a_crec);
     LAUNCH(c, "adj_face", 2 * pass, k_adj_face, dim3((2 * g.nc + 3) / 4), dim3(256), g, c->vel, c->gas, f,
            (const double*)c->W, (const double*)c->fp, v, c->a_fa);
@@ -1823,7 +1826,7 @@ static void adj_product(miugks_ctx* c, const double* v, double* out) {
     dim3 nb((unsigned)((n + 255) / 256));
     LAUNCH(c, "adj_gather", 4 * pass, k_adj_gather, nb, dim3(256), g, c->vel, (const double*)c->fp,
            (const double*)c->a_fa, v, c->a_gbd, c->a_sb);
-    LAUNCH(c, "adj_assemble", 6 * pass, k_adj_assemble, nb, dim3(256), g, c->vel, f, v, (const double*)c->a_crec,
+    LAUNCH(c, "adj_assemble", 7 * pass, k_adj_assemble, nb, dim3(256), g, c->vel, f, v, (const double*)c->a_crec,
            (const double*)c->a_fa, (const double*)c->a_rws, (const double*)c->a_gbd, (const double*)c->a_sb, out);
 }
 
@@ -1964,7 +1967,7 @@ int miugks_adjoint(miugks_ctx* ctx, int kind, const int* walls, int n, const int
             return MIUGKS_EDIVERGED;
         }
         if (rn <= tol * r0 || r0 == 0.0 || it >= max_iter) break;
-        LAUNCH_SH(ctx, "adj_sweep", 4.0 * N * 8, lds, k_adj_sweep, dim3(ctx->nk), dim3(threads), g, ctx->vel,
+        LAUNCH_SH(ctx, "adj_sweep", 2.0 * N * 8, lds, k_adj_sweep, dim3(ctx->nk), dim3(threads), g, ctx->vel,
                   (const double*)ctx->a_crec, (const double*)ctx->a_res, ctx->a_y);
         LAUNCH(ctx, "adj_axpy", 3.0 * N * 8, k_adj_axpy, dim3((unsigned)((N + 255) / 256)), dim3(256), ctx->a_lam,
                (const double*)ctx->a_y, -1.0, N);

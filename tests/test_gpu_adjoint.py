@@ -114,3 +114,26 @@ def test_adjoint_gradient_against_oracle():
     assert st == 0
     assert err < 1e-6, (g, ref)
     gpu.close()
+
+
+def test_autograd_wall_load_matches_adjoint():
+    """J(Tw) through torch.autograd: the forward value is the objective of the
+    converged state and the gradient is the adjoint's."""
+    import torch
+    from paper_1704_03151_amd import Solver
+    from paper_1704_03151_amd.autograd import steady_wall_load
+    case = _tiny_cavity()
+    print("[adjoint] tiny cavity: autograd", flush=True)
+    gpu = Solver(case, precision="fp64")
+    cell, side = gpu.wall_list()
+    lid = list(np.nonzero(side == 3)[0])
+    nfx = (N + 1) * N
+    faces = [nfx + i for i in range(N)]
+    Tw = torch.tensor(case.wall_y[0, :, 0], dtype=torch.float64, device="cuda", requires_grad=True)
+    J = steady_wall_load(gpu, Tw, ad.LOAD_SHEAR, lid, faces, tol=2e-13, adj_tol=1e-9)
+    (g,) = torch.autograd.grad(J, Tw)
+    assert abs(J.item() - gpu.objective(ad.LOAD_SHEAR, lid)) == 0.0
+    st, ref, _, _ = gpu.adjoint(ad.LOAD_SHEAR, lid, faces, tol=1e-9)
+    assert st == 0 and g.device.type == "cuda"
+    assert np.max(np.abs(g.cpu().numpy() - ref)) <= 1e-9 * np.max(np.abs(ref))
+    gpu.close()
