@@ -258,12 +258,14 @@ int miugks_residual_adjoint(miugks_ctx* ctx, const void* v, void* out, int dtype
  * family in the total mass, m is the mass row and mu = dJ/dM along the
  * family, taken from two steady states at masses M0 (1 +- 1e-4) (up to 300
  * cycles each towards 1e-13, from the scaled state; f and M0 are restored),
- * so the result is the sensitivity at fixed mass.  lam is found by defect
- * correction, lam <- lam - A^-T (dJ/df - mu m - (dr/df)^T lam), with A the
- * velocity-diagonal part of the correction operator of Step 5 (Sec. II A 2)
- * solved by one downwind-ordered sweep per velocity, until the residual norm
- * falls by tol or after max_iter corrections.  dJ_dTw (host, n_param) out;
- * iters and res (relative final residual norm) may be NULL.  Returns
+ * so the result is the sensitivity at fixed mass.  lam is found by restarted
+ * GMRES (up to 30 basis vectors, fewer when they would exceed 32 GB),
+ * right-preconditioned with -A^-T, A the velocity-diagonal part of the
+ * correction operator of Step 5 (Sec. II A 2) solved by one downwind-ordered
+ * sweep per velocity, until the residual norm falls by tol or after max_iter
+ * Arnoldi steps.  The library allocates the basis on the first call.
+ * dJ_dTw (host, n_param) out; iters (Arnoldi steps) and res (relative final
+ * residual norm) may be NULL.  Returns
  * MIUGKS_OK, MIUGKS_ENOTCONVERGED (max_iter reached; outputs set),
  * MIUGKS_EDIVERGED, or MIUGKS_EINVAL (FP32-f context, bad kind, wall index
  * or a parameter face that is not a wall).  Synchronises the stream. */

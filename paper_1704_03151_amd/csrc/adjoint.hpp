@@ -814,6 +814,50 @@ __global__ void __launch_bounds__(256) k_adj_residual(const double* __restrict__
     if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
+// Krylov support: per-block partial dot products of w with the vectors
+// V[i ldv ...], i < m, into part[i gridDim.x + block] (fixed order); and
+// w += sign sum_i h[i] V[i]
+// (eight vectors per pass over w)
+__global__ void __launch_bounds__(256) k_adj_dots(const double* __restrict__ w, const double* __restrict__ V,
+                                                   size_t ldv, int m, size_t n, double* __restrict__ part) {
+    __shared__ double sh[8][256];
+    for (int i0 = 0; i0 < m; i0 += 8) {
+        const int nv = m - i0 < 8 ? m - i0 : 8;
+        double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (size_t j = (size_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (size_t)gridDim.x * 256) {
+            double x = w[j];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (u < nv) s[u] += x * V[(size_t)(i0 + u) * ldv + j];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sh[u][threadIdx.x] = s[u];
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) sh[u][threadIdx.x] += sh[u][threadIdx.x + o];
+            __syncthreads();
+        }
+        if ((int)threadIdx.x < nv) part[(size_t)(i0 + threadIdx.x) * gridDim.x + blockIdx.x] = sh[threadIdx.x][0];
+        __syncthreads();
+    }
+}
+
+__global__ void k_adj_lincomb(double* __restrict__ w, const double* __restrict__ V, size_t ldv,
+                              const double* __restrict__ h, int m, double sign, size_t n) {
+    size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) s += h[i] * V[(size_t)i * ldv + j];
+    w[j] += sign * s;
+}
+
+__global__ void k_adj_scale(double* __restrict__ y, const double* __restrict__ x, double a, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a * x[i];
+}
+
 __global__ void k_adj_axpy(double* __restrict__ x, const double* __restrict__ y, double a, size_t n) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] += a * y[i];

@@ -123,6 +123,9 @@ struct miugks_ctx {
     double* a_fsave = nullptr;
     int* a_sides = nullptr;
     int a_nparts = 0;
+    // Krylov basis (m + 1 vectors), Hessenberg column, dot-product partials
+    double *a_V = nullptr, *a_h = nullptr, *a_dpart = nullptr;
+    int a_m = 0;
 };
 
 namespace {
@@ -1778,6 +1781,8 @@ int miugks_set_wall_T(miugks_ctx* ctx, const int* faces, const double* Tw, int n
 // ---------------------------------------------------------------------------
 // adjoint of the steady state (FP64 contexts)
 
+constexpr int DOT_BLOCKS = 1024;   // blocks of the Krylov dot products (4 per CU)
+
 static int adj_alloc(miugks_ctx* c) {
     if (c->a_lam) return MIUGKS_OK;
     const size_t nc = c->hl[0].nc, n = (size_t)c->nk * nc, nw = c->hl[0].w_cell.size() + 1;
@@ -1910,6 +1915,13 @@ int miugks_adjoint(miugks_ctx* ctx, int kind, const int* walls, int n, const int
     // the family, from two steady states at masses M0 (1 +- delta)
     double mu = 0.0;
     if (ctx->renorm) {
+        // the perturbed states are converged as far as the given one is
+        // (twice its residual, and no further than 1e-13)
+        double nb[4];
+        Path<double>::residual(ctx);
+        HIP_TRY(hipMemcpyAsync(nb, ctx->norms, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        const double tol_mu = std::max(1e-13, 2.0 * std::max(std::max(nb[0], nb[1]), std::max(nb[2], nb[3])));
         const double delta = 1e-4, M0 = ctx->M0;
         double Jpm[2];
         HIP_TRY(hipMemcpyAsync(ctx->a_fsave, ctx->f, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
@@ -1923,7 +1935,7 @@ int miugks_adjoint(miugks_ctx* ctx, int kind, const int* walls, int n, const int
             Path<double>::moments(ctx, nullptr);
             int done = 0;
             double res[4];
-            rc = run_cycles<double>(ctx, 300, 1e-13, &done, res);
+            rc = run_cycles<double>(ctx, 300, tol_mu, &done, res);
             if (rc == MIUGKS_OK || rc == MIUGKS_ENOTCONVERGED) rc = objective(Jpm[sgn]);
             if (rc) break;
         }
@@ -1944,16 +1956,53 @@ int miugks_adjoint(miugks_ctx* ctx, int kind, const int* walls, int n, const int
            (const double*)ctx->a_objw, (const double*)ctx->a_Qj, mu, ctx->a_b);
     LAUNCH(ctx, "zero", N * 8.0, k_zero<double>, dim3((unsigned)std::min<size_t>((N + 255) / 256, 1 << 16)), dim3(256),
            ctx->a_lam, N);
-    // defect correction: lam <- lam - A^-T (b - (dr/df)^T lam)
+    // (dr/df)^T lam = b by restarted GMRES, right-preconditioned with
+    // M^-1 = -A^-T (A the velocity-diagonal correction operator, solved by one
+    // downwind sweep per velocity); classical Gram-Schmidt applied twice, the
+    // dot products of a step in one launch
     const int threads = ((g.ny + 63) / 64) * 64;
     const size_t lds = 2 * (size_t)g.ny * sizeof(double);
+    const double vb = (double)N * 8;
+    int m = (int)std::min<double>(30.0, std::max(4.0, std::floor(32e9 / vb) - 1.0));
+    if (!ctx->a_V || ctx->a_m != m) {
+        if ((rc = dev_alloc(ctx, (void**)&ctx->a_V, (size_t)(m + 1) * N * sizeof(double))) ||
+            (rc = dev_alloc(ctx, (void**)&ctx->a_h, (size_t)(m + 1) * sizeof(double))) ||
+            (rc = dev_alloc(ctx, (void**)&ctx->a_dpart, (size_t)(m + 1) * DOT_BLOCKS * sizeof(double))))
+            return rc;
+        ctx->a_m = m;
+    }
+    double* V = ctx->a_V;
+    auto vec = [&](int i) { return V + (size_t)i * N; };
+    const dim3 nbv((unsigned)((N + 255) / 256));
+    auto sweep = [&](const double* in, double* out) {
+        LAUNCH_SH(ctx, "adj_sweep", 2.0 * N * 8, lds, k_adj_sweep, dim3(ctx->nk), dim3(threads), g, ctx->vel,
+                  (const double*)ctx->a_crec, in, out);
+    };
+    std::vector<double> dpart((size_t)(m + 1) * DOT_BLOCKS), hv(m + 1);
+    // dot products of w with vec(0..k)
+    auto dots = [&](const double* w, const double* base, int k, double* outd) -> int {
+        // model bytes: the k vectors and w once per group of eight
+        LAUNCH(ctx, "adj_dots", (k + (k + 7) / 8) * (double)N * 8, k_adj_dots, dim3(DOT_BLOCKS), dim3(256), w, base,
+               N, k, N, ctx->a_dpart);
+        HIP_TRY(hipMemcpyAsync(dpart.data(), ctx->a_dpart, (size_t)k * DOT_BLOCKS * sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        for (int i = 0; i < k; ++i) {
+            double t = 0.0;
+            for (int b2 = 0; b2 < DOT_BLOCKS; ++b2) t += dpart[(size_t)i * DOT_BLOCKS + b2];
+            outd[i] = t;
+        }
+        return check_launch(ctx);
+    };
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), yv(m);
     std::vector<double> part(ctx->a_nparts);
     double r0 = 0.0, rn = 0.0;
     int it = 0;
-    for (;; ++it) {
+    for (bool first = true;; first = false) {
+        // true residual b - (dr/df)^T lam into vec(0)
         adj_product(ctx, ctx->a_lam, ctx->a_out);
         LAUNCH(ctx, "adj_residual", 3.0 * N * 8, k_adj_residual, dim3(ctx->a_nparts), dim3(256),
-               (const double*)ctx->a_b, (const double*)ctx->a_out, ctx->a_res, N, ctx->a_part);
+               (const double*)ctx->a_b, (const double*)ctx->a_out, vec(0), N, ctx->a_part);
         HIP_TRY(hipMemcpyAsync(part.data(), ctx->a_part, part.size() * sizeof(double), hipMemcpyDeviceToHost,
                                ctx->stream));
         HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -1961,16 +2010,78 @@ int miugks_adjoint(miugks_ctx* ctx, int kind, const int* walls, int n, const int
         double ss = 0.0;
         for (double x : part) ss += x;
         rn = std::sqrt(ss);
-        if (it == 0) r0 = rn;
+        if (first) r0 = rn;
         if (!std::isfinite(rn)) {
             ctx->err = "adjoint iteration diverged";
             return MIUGKS_EDIVERGED;
         }
         if (rn <= tol * r0 || r0 == 0.0 || it >= max_iter) break;
-        LAUNCH_SH(ctx, "adj_sweep", 2.0 * N * 8, lds, k_adj_sweep, dim3(ctx->nk), dim3(threads), g, ctx->vel,
-                  (const double*)ctx->a_crec, (const double*)ctx->a_res, ctx->a_y);
-        LAUNCH(ctx, "adj_axpy", 3.0 * N * 8, k_adj_axpy, dim3((unsigned)((N + 255) / 256)), dim3(256), ctx->a_lam,
-               (const double*)ctx->a_y, -1.0, N);
+        LAUNCH(ctx, "adj_scale", 2.0 * N * 8, k_adj_scale, nbv, dim3(256), vec(0), (const double*)vec(0), 1.0 / rn, N);
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = rn;
+        int k = 0;
+        for (; k < m && it < max_iter; ++k) {
+            // w = (dr/df)^T M^-1 v_k = -(dr/df)^T A^-T v_k
+            sweep(vec(k), ctx->a_y);
+            adj_product(ctx, ctx->a_y, ctx->a_out);
+            LAUNCH(ctx, "adj_scale", 2.0 * N * 8, k_adj_scale, nbv, dim3(256), vec(k + 1),
+                   (const double*)ctx->a_out, -1.0, N);
+            for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = 0.0;
+            // two projections; the second also takes |w|^2 (w is vec(k + 1),
+            // the next vector of the block), and |w - sum h v|^2 = |w|^2 - sum h^2
+            // for the small second-pass coefficients
+            double nn = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                if ((rc = dots(vec(k + 1), V, k + 1 + pass, hv.data()))) return rc;
+                for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] += hv[i];
+                if (pass == 1) {
+                    nn = hv[k + 1];
+                    for (int i = 0; i <= k; ++i) nn -= hv[i] * hv[i];
+                }
+                HIP_TRY(hipMemcpyAsync(ctx->a_h, hv.data(), (k + 1) * sizeof(double), hipMemcpyHostToDevice,
+                                       ctx->stream));
+                LAUNCH(ctx, "adj_lincomb", (k + 3.0) * N * 8, k_adj_lincomb, nbv, dim3(256), vec(k + 1),
+                       (const double*)V, N, (const double*)ctx->a_h, k + 1, -1.0, N);
+            }
+            double hn = std::sqrt(std::max(nn, 0.0));
+            H[(size_t)(k + 1) * m + k] = hn;
+            if (hn > 0.0)
+                LAUNCH(ctx, "adj_scale", 2.0 * N * 8, k_adj_scale, nbv, dim3(256), vec(k + 1),
+                       (const double*)vec(k + 1), 1.0 / hn, N);
+            // Givens rotations of the Hessenberg column
+            for (int i = 0; i < k; ++i) {
+                double a = H[(size_t)i * m + k], b2 = H[(size_t)(i + 1) * m + k];
+                H[(size_t)i * m + k] = cs[i] * a + sn[i] * b2;
+                H[(size_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * b2;
+            }
+            double a = H[(size_t)k * m + k], b2 = H[(size_t)(k + 1) * m + k];
+            double rr = std::hypot(a, b2);
+            cs[k] = rr > 0.0 ? a / rr : 1.0;
+            sn[k] = rr > 0.0 ? b2 / rr : 0.0;
+            H[(size_t)k * m + k] = rr;
+            H[(size_t)(k + 1) * m + k] = 0.0;
+            gv[k + 1] = -sn[k] * gv[k];
+            gv[k] = cs[k] * gv[k];
+            ++it;
+            if (std::fabs(gv[k + 1]) <= tol * r0 || hn == 0.0) {
+                ++k;
+                break;
+            }
+        }
+        // y from the triangular system, u = V y, lam += M^-1 u = -A^-T u
+        for (int i = k - 1; i >= 0; --i) {
+            double t = gv[i];
+            for (int j = i + 1; j < k; ++j) t -= H[(size_t)i * m + j] * yv[j];
+            yv[i] = H[(size_t)i * m + i] != 0.0 ? t / H[(size_t)i * m + i] : 0.0;
+        }
+        HIP_TRY(hipMemcpyAsync(ctx->a_h, yv.data(), k * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        LAUNCH(ctx, "zero", N * 8.0, k_zero<double>, dim3((unsigned)std::min<size_t>((N + 255) / 256, 1 << 16)),
+               dim3(256), ctx->a_res, N);
+        LAUNCH(ctx, "adj_lincomb", (k + 2.0) * N * 8, k_adj_lincomb, nbv, dim3(256), ctx->a_res, (const double*)V,
+               N, (const double*)ctx->a_h, k, 1.0, N);
+        sweep(ctx->a_res, ctx->a_y);
+        LAUNCH(ctx, "adj_axpy", 3.0 * N * 8, k_adj_axpy, nbv, dim3(256), ctx->a_lam, (const double*)ctx->a_y, -1.0,
+               N);
     }
     // dJ/dT_w = dJ/dT_w|_f - lam^T dr/dT_w, summed over the sides of each face
     if (!sides.empty()) {
