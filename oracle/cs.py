@@ -30,7 +30,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from workloads import FACE_WALL, FACE_OUTFLOW
+from workloads import FACE_WALL, FACE_OUTFLOW, FACE_SYMMETRY
 from .flux import wall_maxwellian
 from .fas import coarse_visits
 from .mesh import restrict
@@ -41,8 +41,9 @@ class MicroLevel:
 
     For velocity k and cell i each axis has one upwind side (the side whose
     outward normal speed is negative).  Across it the correction is the
-    neighbour's (interior face), C_k drho_w (wall), zero (farfield) or the
-    cell's own (outflow, folded into the diagonal).
+    neighbour's (interior face), C_k drho_w (wall), zero (farfield), the
+    cell's own (outflow, folded into the diagonal) or the cell's own at the
+    velocity with the normal component reversed (symmetry face).
     """
 
     def __init__(self, lev, vel, K_int):
@@ -56,6 +57,8 @@ class MicroLevel:
         self.coef = lev.S / lev.V                      # (4, Nc)
         self.outflow = lev.ftype == FACE_OUTFLOW       # (4, Nc)
         self.interior = lev.nb >= 0
+        self.sym = lev.ftype == FACE_SYMMETRY
+        self.mirror = [vel.mirror(0), vel.mirror(1)] if self.sym.any() else None
         # transport part of the diagonal: outgoing normal speeds; outflow faces
         # add their (negative) inflow speeds as well
         diag = np.zeros((nk, lev.nc))
@@ -92,13 +95,17 @@ class MicroLevel:
             out[j] = -np.sum((self.vel.w * un * dG[:, self.wcell[j]])[un > 0]) / self.den[j]
         return out
 
-    def upwind_term(self, kq, c, s, dG, dH, drho):
-        """D_jk times the correction across side s of cell c for velocities kq."""
+    def upwind_term(self, kq, c, s, dG, dH, drho, mG, mH):
+        """D_jk times the correction across side s of cell c for velocities kq;
+        a symmetry ghost reads the mirror velocity's correction in mG, mH."""
         un = self.un[s, kq, 0]
         w = self.coef[s, c] * np.where(un < 0, un, 0.0)
         if self.interior[s, c]:
             o = self.lev.nb[s, c]
             return w * dG[kq, o], w * dH[kq, o]
+        if self.sym[s, c]:
+            mk = self.mirror[s // 2][kq]
+            return w * mG[mk, c], w * mH[mk, c]
         j = self.widx[s, c]
         if j >= 0:
             return w * self.CG[kq, j] * drho[j], w * self.CH[kq, j] * drho[j]
@@ -118,7 +125,8 @@ class MicroLevel:
     def smooth(self, dG, dH, rG, rH, D):
         """One Gauss-Seidel sweep of every velocity in its own upwind order.
 
-        The wall densities are taken from the correction before the sweep;
+        The wall densities and the symmetry ghosts (a cell's own correction at
+        the mirror velocity) are taken from the correction before the sweep;
         each cell then uses its already-updated upwind neighbours, so the
         sweep solves the transport part of the equation exactly.  The cells
         are visited row by row here; any order that visits upwind neighbours
@@ -139,8 +147,8 @@ class MicroLevel:
                     c = iy * lev.nx + ix
                     if lev.solid[c]:
                         continue
-                    txG, txH = self.upwind_term(kq, c, sxs, nG, nH, drho)
-                    tyG, tyH = self.upwind_term(kq, c, sys_, nG, nH, drho)
+                    txG, txH = self.upwind_term(kq, c, sxs, nG, nH, drho, dG, dH)
+                    tyG, tyH = self.upwind_term(kq, c, sys_, nG, nH, drho, dG, dH)
                     nG[kq, c] = (rG[kq, c] - txG - tyG) / D[kq, c]
                     nH[kq, c] = (rH[kq, c] - txH - tyH) / D[kq, c]
         return nG, nH
@@ -157,8 +165,8 @@ class MicroLevel:
             for c in range(lev.nc):
                 if lev.solid[c]:
                     continue
-                txG, txH = self.upwind_term(kq, c, sxs, dG, dH, drho)
-                tyG, tyH = self.upwind_term(kq, c, sys_, dG, dH, drho)
+                txG, txH = self.upwind_term(kq, c, sxs, dG, dH, drho, dG, dH)
+                tyG, tyH = self.upwind_term(kq, c, sys_, dG, dH, drho, dG, dH)
                 eG[kq, c] = rG[kq, c] - D[kq, c] * dG[kq, c] - txG - tyG
                 eH[kq, c] = rH[kq, c] - D[kq, c] * dH[kq, c] - txH - tyH
         return eG, eH

@@ -30,7 +30,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from workloads import CYCLE_F, FACE_WALL, FACE_FARFIELD, FACE_OUTFLOW
+from workloads import CYCLE_F, FACE_WALL, FACE_FARFIELD, FACE_OUTFLOW, FACE_SYMMETRY
 from . import gas as gm
 from .mesh import restrict
 
@@ -96,6 +96,7 @@ class MacroLevel:
         Wj = np.where(nb >= 0, Wn, W)
         Wj = np.where(t == FACE_WALL, Wg, Wj)
         Wj = np.where(t == FACE_FARFIELD, self.Winf[:, None], Wj)
+        Wj = np.where(t == FACE_SYMMETRY, mirror_state(W, s), Wj)
         return Wj
 
     def neighbour_correction(self, W, E, Eold, s):
@@ -107,6 +108,7 @@ class MacroLevel:
         Ej = np.where(nb >= 0, E[:, np.maximum(nb, 0)], Eold)
         Ej = np.where(t == FACE_WALL, Eg, Ej)
         Ej = np.where(t == FACE_FARFIELD, 0.0, Ej)
+        Ej = np.where(t == FACE_SYMMETRY, mirror_state(Eold, s), Ej)
         return Ej
 
     def freeze_gamma(self, W):
@@ -159,6 +161,14 @@ class MacroLevel:
                 m = (lev.colour == col) & lev.fluid
                 E = np.where(m, Enew, E)
         return W + E
+
+
+def mirror_state(W, s):
+    """Mirror image of W (4, ...) across a face on side s: the momentum
+    component normal to the face reversed (symmetry ghost, Sec. III B)."""
+    out = np.array(W, copy=True)
+    out[1 if s < 2 else 2] *= -1.0
+    return out
 
 
 def coarse_visits(params):

@@ -17,15 +17,15 @@ normal direction only:
 with van Leer-limited slopes sigma, the upwind interface value f_up, g0 the
 Maxwellian of the discrete moments of f_up, abar the micro-slope of the side
 the particle comes from and Abar the time slope from the compatibility
-condition.  Walls, farfield and outflow faces carry first-order kinetic
-boundary fluxes (diffuse reflection with the wall density fixed by zero net
-mass flux, Sec. III B).
+condition.  Walls, farfield, outflow and symmetry faces carry first-order
+kinetic boundary fluxes (diffuse reflection with the wall density fixed by
+zero net mass flux; specular reflection at a symmetry face; Sec. III B).
 """
 from __future__ import annotations
 
 import numpy as np
 
-from workloads import FACE_WALL, FACE_FARFIELD, FACE_OUTFLOW
+from workloads import FACE_WALL, FACE_FARFIELD, FACE_OUTFLOW, FACE_SYMMETRY
 from . import gas as gm
 
 
@@ -215,6 +215,12 @@ def boundary_face_values(G, H, lev, vel, gas, farfield):
         elif t == FACE_OUTFLOW:
             Gf[:, j] = G[:, c]
             Hf[:, j] = H[:, c]
+        elif t == FACE_SYMMETRY:
+            # specular reflection: the incoming velocity takes the cell's value
+            # at the velocity with the normal component reversed
+            mk = vel.mirror(s // 2)
+            Gf[:, j] = np.where(out, G[:, c], G[mk, c])
+            Hf[:, j] = np.where(out, H[:, c], H[mk, c])
         else:
             raise ValueError(f"unsupported face tag {t}")
     return un, Gf, Hf

@@ -95,6 +95,19 @@ class VelocityGrid:
     def n(self) -> int:
         return self.nu * self.nv
 
+    def mirror(self, d):
+        """Index of the velocity with component d reversed (d = 0: u, 1: v),
+        for every k; the grid must be symmetric in that component."""
+        a = np.arange(self.n) // self.nv
+        b = np.arange(self.n) % self.nv
+        if d == 0:
+            if not np.allclose(self.u1[::-1], -self.u1, rtol=0, atol=1e-12):
+                raise ValueError("velocity grid not symmetric in u")
+            return (self.nu - 1 - a) * self.nv + b
+        if not np.allclose(self.v1[::-1], -self.v1, rtol=0, atol=1e-12):
+            raise ValueError("velocity grid not symmetric in v")
+        return a * self.nv + (self.nv - 1 - b)
+
     @classmethod
     def from_case(cls, case):
         return cls(case.quad, case.nu, case.nv, case.vlo, case.vhi)

@@ -1,9 +1,10 @@
 """Direct assembly of the correction equation as a sparse matrix (oracle; test infrastructure only).
 
 Written straight from the coefficient definitions of Sec. II A 2 (upwind
-defect equation, D_ik and D_jk) and the diffuse-wall ghost of Sec. III B
+defect equation, D_ik and D_jk), the diffuse-wall ghost of Sec. III B
 (dF_j,k = C_k drho_j with drho_j fixed by zero normal mass flux through the
-wall), independently of the smoother code, so that a direct sparse solve
+wall) and the symmetry ghost (dF_j,k = dF_i,k' at the velocity with the
+normal component reversed), independently of the smoother code, so that a direct sparse solve
 pins the multigrid correction cycle.
 
 Unknown ordering: index (s, k, c) -> (s * Nk + k) * Nc + c, s = 0 for G and
@@ -14,7 +15,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from workloads import FACE_INTERIOR, FACE_WALL, FACE_OUTFLOW
+from workloads import FACE_INTERIOR, FACE_WALL, FACE_OUTFLOW, FACE_SYMMETRY
 from .flux import wall_maxwellian
 
 
@@ -44,6 +45,7 @@ def assemble(lev, vel, K_int, tau_inv, dtn_inv=None):
             diag = tau_inv[c] + dtn_inv[c]
             offd = []            # (column, value) pairs shared by G and H rows
             wall = []            # (side, un, S) of incoming wall sides
+            sym = []             # (mirror velocity, coefficient) of incoming symmetry sides
             for side in range(4):
                 sign = -1.0 if side % 2 == 0 else 1.0
                 un = sign * (vel.u[k] if side < 2 else vel.v[k])
@@ -61,11 +63,16 @@ def assemble(lev, vel, K_int, tau_inv, dtn_inv=None):
                     diag += dj          # ghost copies the cell
                 elif t == FACE_WALL:
                     wall.append((side, dj))
+                elif t == FACE_SYMMETRY:
+                    # ghost correction = the cell's own at the mirror velocity
+                    sym.append((vel.mirror(side // 2)[k], dj))
                 # farfield: the ghost correction vanishes
             for s in range(2):
                 put(idx(s, k, c), idx(s, k, c), diag)
                 for o, dj in offd:
                     put(idx(s, k, c), idx(s, k, o), dj)
+                for km, dj in sym:
+                    put(idx(s, k, c), idx(s, km, c), dj)
             for side, dj in wall:
                 Tw, Uw, Vw = lev.wall[side, c]
                 CG, CH = wall_maxwellian(Tw, Uw, Vw, vel.u, vel.v, K_int)

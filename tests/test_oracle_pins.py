@@ -521,3 +521,73 @@ def test_explicit_steps_conserve_mass_in_a_closed_box():
         o.explicit_step()
     m1 = float(np.sum(o.lev0.V * o.W[0]))
     assert abs(m1 - m0) < 1e-12 * m0
+
+
+# --------------------------------------------------------------------------- symmetry faces
+def test_symmetry_faces_carry_no_mass_shear_or_energy():
+    """Specular reflection: for any distribution the flux through a symmetry
+    face carries no mass, no tangential momentum and no energy (the incoming
+    half is the mirror image of the outgoing half)."""
+    case = wl.sheared_half_box(n=6, quad="trapezoid", nvel=10, vlo=-4, vhi=4)
+    o = Oracle(case)
+    rng = np.random.default_rng(31)
+    G = o.G * rng.uniform(0.5, 1.5, o.G.shape)
+    H = o.H * rng.uniform(0.5, 1.5, o.H.shape)
+    un, Gf, Hf = fx.boundary_face_values(G, H, o.lev0, o.vel, o.gas, case.farfield)
+    sym = o.lev0.btype == wl.FACE_SYMMETRY
+    assert sym.sum() == 12
+    for j in np.nonzero(sym)[0]:
+        s = o.lev0.bside[j]
+        ut = o.vel.v if s < 2 else o.vel.u
+        w = o.vel.w
+        mass = np.sum(w * un[:, j] * Gf[:, j])
+        shear = np.sum(w * un[:, j] * ut * Gf[:, j])
+        energy = 0.5 * np.sum(w * un[:, j] * ((o.vel.u ** 2 + o.vel.v ** 2) * Gf[:, j] + Hf[:, j]))
+        scale = np.sum(w * np.abs(un[:, j]) * Gf[:, j])
+        assert max(abs(mass), abs(shear)) < 1e-14 * scale and abs(energy) < 1e-13 * scale
+    # the walls do transfer shear: the pin is not vacuous
+    wall = np.nonzero(o.lev0.btype == wl.FACE_WALL)[0]
+    assert np.any(np.abs(ad_shear(o, G, H)[wall]) > 1e-3)
+
+
+def ad_shear(o, G, H):
+    un, Gf, Hf = fx.boundary_face_values(G, H, o.lev0, o.vel, o.gas, o.case.farfield)
+    ut = np.where(o.lev0.bside[None, :] < 2, o.vel.v[:, None], o.vel.u[:, None])
+    return np.sum(o.vel.w[:, None] * un * ut * Gf, axis=0)
+
+
+def test_uniform_flow_along_symmetry_planes_is_a_fixed_point():
+    """A freestream parallel to two symmetry planes is steady: zero residuals,
+    and a whole cycle (FAS prediction and CS correction with their symmetry
+    ghosts) leaves f unchanged.  Reflecting the wrong velocity component
+    would send the flow back upstream and break both."""
+    case = wl.symmetric_channel(n=6, U=0.3, quad="trapezoid", nvel=24, vlo=-6, vhi=6, n_levels=2, Kn=0.5)
+    o = Oracle(case)
+    G0, H0 = o.G.copy(), o.H.copy()
+    n = o.step1()
+    assert np.max(n) < 1e-13
+    assert np.max(np.abs(o.divG)) < 1e-12 * np.max(np.abs(o.G))
+    o.advance()
+    assert np.max(np.abs(o.G - G0)) < 1e-13 and np.max(np.abs(o.H - H0)) < 1e-13
+
+
+def test_cs_cycle_with_symmetry_faces_converges_to_direct_solve():
+    """The correction cycle with symmetry ghosts (lagged to the start of each
+    sweep) converges to the direct sparse solution of the correction
+    equation, whose symmetry rows couple each incoming velocity to its mirror."""
+    case = wl.sheared_half_box(n=8, quad="trapezoid", nvel=6, vlo=-3, vhi=3, n_levels=2)
+    vel, g, lv, pro, mls, tau_inv, rG, rH = _cs_setup(case, 32)
+    A = assemble(lv[0], vel, g.K_int, tau_inv[0])
+    x = spla.spsolve(A.tocsc(), np.concatenate([rG.ravel(), rH.ravel()]))
+    dG = np.zeros_like(rG)
+    dH = np.zeros_like(rH)
+    dtn = [np.zeros(l.nc) for l in lv]
+    D = mls[0].diagonal(tau_inv[0], 0.0)
+    for _ in range(60):
+        eG, eH = mls[0].defect(dG, dH, rG, rH, D)
+        cG, cH = cs_cycle(mls, lv, pro, 0, eG, eH, tau_inv, dtn, (2, 1, 10))
+        dG, dH = dG + cG, dH + cH
+    got = np.concatenate([dG.ravel(), dH.ravel()])
+    assert np.allclose(got, x, rtol=1e-10, atol=1e-12 * np.max(np.abs(x)))
+    # the symmetry rows are really there: dropping them changes the solution
+    assert mls[0].sym.sum() == 16

@@ -28,6 +28,7 @@ FACE_INTERIOR = 0
 FACE_WALL = 1
 FACE_FARFIELD = 2
 FACE_OUTFLOW = 3
+FACE_SYMMETRY = 4   # specular reflection: the mirror image of the cell (Sec. III B)
 
 # Value of cycle_gamma / cycle_gamma_cs that selects F-cycles (data format
 # shared by the oracle and the library).
@@ -201,6 +202,33 @@ def cavity(n=16, first=None, Kn=10.0, mach=0.16, n_levels=2, quad=QUAD_TRAPEZOID
                 n_levels=n_levels, quad=quad, nu=nvel, nv=nvel if nvel_y is None else nvel_y,
                 vlo=vlo, vhi=vhi, Kn=Kn, farfield=(1.0, 0.0, 0.0, 1.0), init=init,
                 precision=precision, **ARGON, **kw)
+
+
+def sheared_half_box(n=8, ny=None, Kn=1.0, mach=0.3, **kw) -> Case:
+    """A box with two symmetry planes: specular reflection on the left side
+    and the top, diffuse walls at T = 1 on the right side and the bottom,
+    which moves in +x (the cavity builder's cells and velocity grids)."""
+    case = cavity(n=n, ny=ny, Kn=Kn, mach=mach, name=kw.pop("name", None) or "sheared_half_box", **kw)
+    gamma = (ARGON["K_int"] + 4.0) / (ARGON["K_int"] + 2.0)
+    case.face_type_x[:, 0] = FACE_SYMMETRY
+    case.face_type_y[case.ny, :] = FACE_SYMMETRY
+    case.wall_x[:, 0] = 0.0
+    case.wall_y[case.ny] = 0.0
+    case.wall_y[0, :, 1] = lid_speed(mach, gamma)
+    return case
+
+
+def symmetric_channel(n=6, ny=None, U=0.3, **kw) -> Case:
+    """A straight channel in a uniform freestream (rho 1, U, 0, T 1): farfield
+    ends, symmetry planes on both sides; the freestream is its steady state."""
+    case = cavity(n=n, ny=ny, name=kw.pop("name", None) or "symmetric_channel", **kw)
+    case.face_type_x[:, 0] = case.face_type_x[:, case.nx] = FACE_FARFIELD
+    case.face_type_y[0, :] = case.face_type_y[case.ny, :] = FACE_SYMMETRY
+    case.wall_x[:] = 0.0
+    case.wall_y[:] = 0.0
+    case.farfield = (1.0, U, 0.0, 1.0)
+    case.init[1] = U
+    return case
 
 
 def config1(**kw) -> Case:
