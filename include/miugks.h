@@ -49,6 +49,8 @@ extern "C" {
 #define MIUGKS_FACE_WALL 1       /* diffuse isothermal wall, full accommodation */
 #define MIUGKS_FACE_FARFIELD 2   /* freestream Maxwellian enters, the cell's distribution leaves */
 #define MIUGKS_FACE_OUTFLOW 3    /* zero gradient */
+#define MIUGKS_FACE_SYMMETRY 4   /* specular reflection: the cell's own distribution at the velocity with the
+                                    normal component reversed (the grid must be symmetric in it) */
 
 /* precision of the distribution and of the per-velocity arithmetic */
 #define MIUGKS_FP64 0            /* everything in double */

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmiugks.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EDIVERGED, ENOTCONVERGED, ESTATE = range(7)
-FACE_INTERIOR, FACE_WALL, FACE_FARFIELD, FACE_OUTFLOW = range(4)
+FACE_INTERIOR, FACE_WALL, FACE_FARFIELD, FACE_OUTFLOW, FACE_SYMMETRY = range(5)
 FP64, FP32F = 0, 1
 QUAD_TRAPEZOID, QUAD_SIMPSON38, QUAD_GAUSS_HERMITE = range(3)
 CYCLE_F = -1

@@ -117,11 +117,12 @@ __device__ inline void prim_rev(const double* W, double K, double rb, double Ub,
 }
 
 // one velocity's share of the reverse of the Shakhov pair (G, H) with output
-// adjoints gb, hb: adds to acc = (rho, U, V, lam, qx, qy) bar
+// adjoints gb, hb: adds to acc = (rho, U, V, lam, qx, qy) bar; G0 is the
+// Maxwellian rho (lam/pi) exp(-lam |c|^2) of this velocity
 __device__ inline void shakhov_rev_k(double rho, double U, double V, double lam, double qx, double qy, double u,
-                                     double v, int Ki, double s, double gb, double hb, double* acc) {
+                                     double v, int Ki, double s, double G0, double gb, double hb, double* acc) {
     double cx = u - U, cy = v - V, c2 = cx * cx + cy * cy;
-    double G0 = rho * (lam / M_PI) * exp(-lam * c2), H0 = (Ki / (2.0 * lam)) * G0;
+    double H0 = (Ki / (2.0 * lam)) * G0;
     double F = s * lam * lam * (cx * qx + cy * qy) / rho;
     double PG = 1.0 + F * (2.0 * lam * c2 - 4.0), PH = 1.0 + F * (2.0 * lam * c2 - 2.0);
     double G0b = gb * PG + hb * PH * Ki / (2.0 * lam);
@@ -207,7 +208,7 @@ __global__ void __launch_bounds__(256) k_adj_cell(Geo g, Vel vel, Gas gas, const
         double Fs = s * lam * lam * (cx * qx + cy * qy) / rho;
         double Gt = G0 * (1.0 + Fs * (2.0 * lam * c2 - 4.0)), Ht = H0 * (1.0 + Fs * (2.0 * lam * c2 - 2.0));
         acc[6] += vG * (Gt - G) + vH * (Ht - H);
-        shakhov_rev_k(rho, U, V, lam, qx, qy, u, vv, Ki, s, vG * tinv, vH * tinv, acc);
+        shakhov_rev_k(rho, U, V, lam, qx, qy, u, vv, Ki, s, G0, vG * tinv, vH * tinv, acc);
         acc[7] += w * (c2 * G + H);
         acc[8] += w * cx * cx * G;
         acc[9] += w * cy * cy * G;
@@ -287,7 +288,7 @@ __global__ void __launch_bounds__(256) k_adj_face(Geo g, Vel vel, Gas gas, const
         a[2] += phG * GA + phH * HA;
         a[3] += phG * Gup + phH * Hup;
         a[4] += un * (phG * sGup + phH * sHup);
-        shakhov_rev_k(rho0, U0, V0, lam0, q0x, q0y, u, vv, Ki, s, qc[0] * phG, qc[0] * phH, a + 5);
+        shakhov_rev_k(rho0, U0, V0, lam0, q0x, q0y, u, vv, Ki, s, G0, qc[0] * phG, qc[0] * phH, a + 5);
         double g0b, h0b;
         slope_rev_k(A, u, vv, lam0, Ki, G0, H0, qc[2] * phG, qc[2] * phH, a + 11, a[15], g0b, h0b);
         g0_fold(G0, cx, cy, rho0, lam0, Ki, g0b, h0b, a + 16);
@@ -572,6 +573,14 @@ __global__ void __launch_bounds__(256) k_adj_assemble(Geo g, Vel vel, const doub
         } else if (code == NB_OUTFLOW) {
             oG += pG * un;
             oH += pH * un;
+        } else if (code == NB_SYMMETRY) {
+            // the outgoing value is also the incoming ghost of the mirror velocity
+            // (whose normal speed is -u_n)
+            if (un > 0.0) {
+                size_t im = (size_t)mirror_of(vel, s >> 1, k) * nc + c;
+                oG += pG * un + v[im] * cb * un;
+                oH += pH * un + v[n + im] * cb * un;
+            }
         }
     }
     out[i] = oG;

@@ -46,7 +46,11 @@ struct Vel {
     int nk;
     const double *u, *v, *w;
     const float *uf, *vf, *wf;
+    const int *mx, *my;   // the velocity with u (mx) or v (my) reversed (symmetry faces)
 };
+
+// the velocity with the component normal to side direction d reversed
+__device__ __forceinline__ int mirror_of(const Vel& vel, int d, int k) { return d == 0 ? vel.mx[k] : vel.my[k]; }
 
 struct Gas {
     int K_int;
@@ -1235,7 +1239,7 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
                         dH[j] += sv * un * Hf;
                     }
                 } else {
-                    bool far = code == NB_FARFIELD;
+                    bool far = code == NB_FARFIELD, sym = code == NB_SYMMETRY;
                     for (int j = 0; j < nmine; ++j) {
                         int k = kk[j];
                         A un = sign * (d == 0 ? A(vel.u[k]) : A(vel.v[k]));
@@ -1243,6 +1247,11 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
                         if (far && un <= A(0)) {
                             Gf = A(finf[k]);
                             Hf = A(finf[nk + k]);
+                        } else if (sym && un <= A(0)) {
+                            // specular reflection: the cell's own value at the mirror velocity
+                            int km = mirror_of(vel, d, k);
+                            Gf = A(f[(size_t)km * nc + c]);
+                            Hf = A(f[ho + (size_t)km * nc + c]);
                         } else {
                             Gf = A(f[(size_t)k * nc + c]);
                             Hf = A(f[ho + (size_t)k * nc + c]);
@@ -1270,7 +1279,8 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
 
 // outward flux u_n ftilde through the non-interior side s (code < 0) of a
 // fluid cell c for velocity k: at a wall the outgoing f and the incoming
-// rho_w C_k, at a farfield side the incoming freestream, else f
+// rho_w C_k, at a farfield side the incoming freestream, at a symmetry side
+// the incoming mirror-velocity value, else f
 template <typename T, typename A>
 __device__ __forceinline__ void boundary_flux(const Geo& g, const Vel& vel, const Gas& gas, const T* __restrict__ f,
                                               const double* __restrict__ rho_w, const T* __restrict__ finf, int c,
@@ -1291,6 +1301,10 @@ __device__ __forceinline__ void boundary_flux(const Geo& g, const Vel& vel, cons
     } else if (code == NB_FARFIELD && un <= A(0)) {
         Gf = A(finf[k]);
         Hf = A(finf[vel.nk + k]);
+    } else if (code == NB_SYMMETRY && un <= A(0)) {
+        int km = mirror_of(vel, d, k);
+        Gf = A(f[(size_t)km * nc + c]);
+        Hf = A(f[ho + (size_t)km * nc + c]);
     } else {
         Gf = A(f[(size_t)k * nc + c]);
         Hf = A(f[ho + (size_t)k * nc + c]);
@@ -1462,15 +1476,16 @@ __device__ __forceinline__ T transport_diag(const Geo& g, int c, T u, T v) {
 }
 
 // D_jk times the correction across the upwind side s of cell c (the side
-// with negative normal speed): neighbour value (passed in), wall ghost
-// C_k drho_w, or zero (farfield; outflow lives on the diagonal)
+// with negative normal speed): neighbour value or, at a symmetry side, the
+// cell's own at the mirror velocity (passed in), wall ghost C_k drho_w, or
+// zero (farfield; outflow lives on the diagonal)
 template <typename T>
 __device__ __forceinline__ void upwind_term(const Geo& g, int c, int s, T u, T v, int K_int, T nbG, T nbH,
                                             const double* __restrict__ drho, T& tG, T& tH) {
     int code = g.nb[s * g.nc + c];
     T un = ((s & 1) ? T(1) : T(-1)) * (s < 2 ? u : v);
     T coef = (un < T(0) ? un : T(0)) * T(1.0 / (s < 2 ? g.dx[c % g.nx] : g.dy[c / g.nx]));
-    if (code >= 0) {
+    if (code >= 0 || code == NB_SYMMETRY) {   // neighbour, or the cell's own at the mirror velocity
         tG = coef * nbG;
         tH = coef * nbH;
     } else if (is_wall(code)) {
@@ -1679,7 +1694,7 @@ template <typename T>
 __global__ void k_sweep(Geo g, Vel vel, int K_int, const T* __restrict__ r, T* __restrict__ df,
                         const double* __restrict__ tau_inv, const double* __restrict__ dtn_inv,
                         const unsigned* __restrict__ flags, const double* __restrict__ drho,
-                        double* __restrict__ wbuf) {
+                        double* __restrict__ wbuf, const T* __restrict__ msnap) {
     int k = blockIdx.x, t = threadIdx.x;
     int nx = g.nx, ny = g.ny;
     size_t nc = g.nc, ho = (size_t)vel.nk * nc, kc = (size_t)k * nc;
@@ -1713,6 +1728,10 @@ __global__ void k_sweep(Geo g, Vel vel, int K_int, const T* __restrict__ r, T* _
                     int j = wall_index_fl(fl, upx);
                     txG = cx * wall_ghost_j<T>(g, j, u, v, K_int, 0, drho);
                     txH = cx * wall_ghost_j<T>(g, j, u, v, K_int, 1, drho);
+                } else if (msnap && g.nb[upx * nc + c] == NB_SYMMETRY) {
+                    size_t m = (size_t)vel.mx[k] * nc + c;   // mirror velocity, correction before the sweep
+                    txG = cx * msnap[m];
+                    txH = cx * msnap[ho + m];
                 }
                 if (tpy == 0) {
                     tyG = cy * G[c - sy * nx];
@@ -1721,6 +1740,10 @@ __global__ void k_sweep(Geo g, Vel vel, int K_int, const T* __restrict__ r, T* _
                     int j = wall_index_fl(fl, upy);
                     tyG = cy * wall_ghost_j<T>(g, j, u, v, K_int, 0, drho);
                     tyH = cy * wall_ghost_j<T>(g, j, u, v, K_int, 1, drho);
+                } else if (msnap && g.nb[upy * nc + c] == NB_SYMMETRY) {
+                    size_t m = (size_t)vel.my[k] * nc + c;
+                    tyG = cy * msnap[m];
+                    tyH = cy * msnap[ho + m];
                 }
                 nG = (r[kc + c] - txG - tyG) / D;
                 nH = (r[ho + kc + c] - txH - tyH) / D;
@@ -2332,8 +2355,12 @@ __global__ void __launch_bounds__(256) k_defect_restrict(Geo g, Geo gc, Vel vel,
                 T D = T(tau_inv[c]) + T(dtn_inv[c]) + transport_diag<T>(g, c, u, v);
                 int sx = u >= T(0) ? 0 : 1, sy = v >= T(0) ? 2 : 3;
                 int ox = g.nb[sx * g.nc + c], oy = g.nb[sy * g.nc + c];
-                T xnG = ox >= 0 ? df[kc + ox] : T(0), xnH = ox >= 0 ? df[ho + kc + ox] : T(0);
-                T ynG = oy >= 0 ? df[kc + oy] : T(0), ynH = oy >= 0 ? df[ho + kc + oy] : T(0);
+                // across a symmetry side: the cell's own correction at the mirror velocity
+                size_t xo = ox >= 0 ? kc + ox : (ox == NB_SYMMETRY ? (size_t)vel.mx[k] * nc + c : 0);
+                size_t yo = oy >= 0 ? kc + oy : (oy == NB_SYMMETRY ? (size_t)vel.my[k] * nc + c : 0);
+                bool xs = ox >= 0 || ox == NB_SYMMETRY, ys = oy >= 0 || oy == NB_SYMMETRY;
+                T xnG = xs ? df[xo] : T(0), xnH = xs ? df[ho + xo] : T(0);
+                T ynG = ys ? df[yo] : T(0), ynH = ys ? df[ho + yo] : T(0);
                 T xG, xH, yG, yH;
                 upwind_term<T>(g, c, sx, u, v, K_int, xnG, xnH, drho, xG, xH);
                 upwind_term<T>(g, c, sy, u, v, K_int, ynG, ynH, drho, yG, yH);
@@ -2556,7 +2583,8 @@ __device__ __forceinline__ void euler_flux(const double* W, int d, double sign, 
 }
 
 // state across side s of cell c: neighbour, wall ghost (Sec. III B wall
-// relation), freestream or copy; kind 0 interior, 1 farfield, 2 outflow, 3 wall
+// relation), freestream, copy or mirror image; kind 0 interior, 1 farfield,
+// 2 outflow, 3 wall, 4 symmetry
 __device__ __forceinline__ int side_state(const Geo& g, const Gas& gas, const double* W, int c, int s,
                                           const double* Wi, double* Wj, int& wall) {
     int code = g.nb[s * g.nc + c];
@@ -2571,6 +2599,11 @@ __device__ __forceinline__ int side_state(const Geo& g, const Gas& gas, const do
     if (code == NB_OUTFLOW) {
         for (int m = 0; m < 4; ++m) Wj[m] = Wi[m];
         return 2;
+    }
+    if (code == NB_SYMMETRY) {   // mirror image: the normal momentum reversed
+        for (int m = 0; m < 4; ++m) Wj[m] = Wi[m];
+        Wj[1 + (s >> 1)] = -Wi[1 + (s >> 1)];
+        return 4;
     }
     wall = wall_of(code);
     double rho, U, V, lam;
@@ -2657,6 +2690,9 @@ __device__ __forceinline__ void fas_halfsweep_cell(const Geo& g, const Gas& gas,
             for (int m = 0; m < 4; ++m) Ej[m] = 0.0;
         } else if (kind == 2) {
             for (int m = 0; m < 4; ++m) Ej[m] = Ei[m];
+        } else if (kind == 4) {
+            for (int m = 0; m < 4; ++m) Ej[m] = Ei[m];
+            Ej[1 + d] = -Ei[1 + d];
         } else {
             // linearised wall ghost dW_j = J dW_i (Sec. III B), K total degrees of freedom
             double rho, U, V2, lam;
@@ -2793,6 +2829,9 @@ __device__ __forceinline__ void fas_half_side(const Geo& g, const Gas& gas, cons
         for (int m = 0; m < 4; ++m) Ej[m] = 0.0;
     } else if (kind == 2) {
         for (int m = 0; m < 4; ++m) Ej[m] = Ei[m];
+    } else if (kind == 4) {
+        for (int m = 0; m < 4; ++m) Ej[m] = Ei[m];
+        Ej[1 + d] = -Ei[1 + d];
     } else {
         // linearised wall ghost dW_j = J dW_i (Sec. III B), K total degrees of freedom
         double rho, U, V2, lam;
@@ -3206,6 +3245,12 @@ template <typename T>
 __global__ void k_zero(T* __restrict__ a, size_t n) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         a[i] = T(0);
+}
+
+template <typename T>
+__global__ void k_copy_t(const T* __restrict__ a, T* __restrict__ b, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
 }
 
 template <typename A, typename B>

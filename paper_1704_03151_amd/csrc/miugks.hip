@@ -55,6 +55,10 @@ struct miugks_ctx {
     double dtn_growth = 0.0;
     double cfl = 0.5;
     bool renorm = false;
+    // symmetry faces present: the cycles take the general CS path, whose
+    // sweep reads the mirror ghosts from a snapshot of the correction (msnap)
+    bool has_sym = false;
+    std::vector<void*> msnap;
     HostVel hv;
     std::vector<HostLevel> hl;
     std::vector<Geo> geo;
@@ -456,9 +460,20 @@ struct Path {
         } else {
             c->wparts[l] = c->nk;
             int threads = ((g.ny + 63) / 64) * 64;
+            const T* ms = nullptr;
+            if (c->has_sym) {   // the mirror ghosts read the correction before the sweep
+                size_t n = 2 * (size_t)c->nk * g.nc;
+                if (from_zero)
+                    LAUNCH(c, "zero", arr(c, l), k_zero<T>, dim3(nblk((int)std::min<size_t>(n, 1 << 24))), dim3(256),
+                           (T*)c->msnap[l], n);
+                else
+                    LAUNCH(c, "copy", 2 * arr(c, l), k_copy_t<T>, dim3(nblk((int)std::min<size_t>(n, 1 << 24))),
+                           dim3(256), (const T*)c->df[l], (T*)c->msnap[l], n);
+                ms = (const T*)c->msnap[l];
+            }
             LAUNCH(c, name, 2 * arr(c, l), k_sweep<T>, dim3(c->nk), dim3(threads), g, c->vel, c->gas.K_int,
                    (const T*)c->r[l], (T*)c->df[l], c->tau_inv[l], c->dtn_inv[l], c->flags[l], c->drho[l],
-                   c->wbuf[l]);
+                   c->wbuf[l], ms);
         }
     }
 
@@ -485,7 +500,7 @@ struct Path {
         const Geo& gc = c->geo[l + 1];
         const int nvis = coarse_visits(gamma);
         for (int gi = 0; gi < nvis; ++gi) {
-            if (gi == 0 && pre > 0) {
+            if (gi == 0 && pre > 0 && !c->has_sym) {
                 // after an ordered sweep the defect lives on the wall cells only
                 if (!g.n_wall)
                     LAUNCH(c, "zero", arr(c, l + 1), k_zero<T>,
@@ -520,7 +535,8 @@ struct Path {
     // prolonged coarse correction enters only the wall densities of the next
     // sweep, so it is evaluated at the wall cells only.
     static bool cs_reduced_ok(miugks_ctx* c) {
-        if (c->nu1 < 1 || c->nu2 < 1 || c->nuc_cs < 1 || c->gamma_cs != 1 || getenv("MIUGKS_FULL_CS")) return false;
+        if (c->nu1 < 1 || c->nu2 < 1 || c->nuc_cs < 1 || c->gamma_cs != 1 || c->has_sym || getenv("MIUGKS_FULL_CS"))
+            return false;
         for (int l = 0; l < c->L; ++l)
             if (!c->wave[l].W) return false;
         return true;
@@ -969,7 +985,10 @@ int build_device(miugks_ctx* ctx) {
             int first_wall = -1;
             for (int s = 0; s < 4; ++s) {
                 int code = h.nb[s * h.nc + c];
-                int t = code >= 0 ? 0 : (code <= NB_WALL0 ? 1 : (code == NB_FARFIELD ? 2 : 3));
+                // symmetry sides count as zero-ghost sides here; the general
+                // sweep adds their mirror ghosts itself
+                int t = code >= 0 ? 0
+                                  : (code <= NB_WALL0 ? 1 : (code == NB_FARFIELD || code == NB_SYMMETRY ? 2 : 3));
                 if (t == 1 && first_wall < 0) first_wall = NB_WALL0 - code;
                 f |= (unsigned)(t << (2 * s));
             }
@@ -1117,6 +1136,11 @@ int build_device(miugks_ctx* ctx) {
                                               : sweep_lds_bytes<float>(ctx->geo[l], ctx->sweep_lds[l])) > 65536)
                     ctx->sweep_lds[l] = 0;
     }
+    if (ctx->has_sym)   // the mirror ghosts are read by the general sweep only
+        for (int l = 0; l < ctx->L; ++l) {
+            ctx->wave[l].W = ctx->wave1[l].W = 0;
+            ctx->sweep_lds[l] = 0;
+        }
     if (getenv("MIUGKS_DEBUG"))
         for (int l = 0; l < ctx->L; ++l)
             fprintf(stderr,
@@ -1139,9 +1163,13 @@ int build_device(miugks_ctx* ctx) {
         wf(ctx->hv.w.begin(), ctx->hv.w.end());
     double *u, *v, *w;
     float *uu, *vv, *ww;
+    int *mxd, *myd;
     if ((rc = upload(ctx, &u, ctx->hv.u)) || (rc = upload(ctx, &v, ctx->hv.v)) || (rc = upload(ctx, &w, ctx->hv.w)) ||
-        (rc = upload(ctx, &uu, uf)) || (rc = upload(ctx, &vv, vf)) || (rc = upload(ctx, &ww, wf)))
+        (rc = upload(ctx, &uu, uf)) || (rc = upload(ctx, &vv, vf)) || (rc = upload(ctx, &ww, wf)) ||
+        (rc = upload(ctx, &mxd, ctx->hv.mx)) || (rc = upload(ctx, &myd, ctx->hv.my)))
         return rc;
+    ctx->vel.mx = mxd;
+    ctx->vel.my = myd;
     ctx->vel.nk = ctx->nk;
     ctx->vel.u = u;
     ctx->vel.v = v;
@@ -1204,6 +1232,7 @@ int build_device(miugks_ctx* ctx) {
     ctx->part = (double*)p;
     ctx->r.resize(ctx->L);
     ctx->df.resize(ctx->L);
+    ctx->msnap.assign(ctx->L, nullptr);
     for (auto* v2 : {&ctx->tau_inv, &ctx->dtn_inv, &ctx->drho, &ctx->fW, &ctx->fW0, &ctx->fR, &ctx->fP, &ctx->fE,
                      &ctx->fGam, &ctx->fRm, &ctx->fW2})
         v2->resize(ctx->L);
@@ -1211,6 +1240,7 @@ int build_device(miugks_ctx* ctx) {
         size_t nc = ctx->hl[l].nc;
         if ((rc = dev_alloc(ctx, &ctx->r[l], 2 * nk * nc * es)) || (rc = dev_alloc(ctx, &ctx->df[l], 2 * nk * nc * es)))
             return rc;
+        if (ctx->has_sym && (rc = dev_alloc(ctx, &ctx->msnap[l], 2 * nk * nc * es))) return rc;
         if ((rc = dalloc(&ctx->tau_inv[l], nc)) || (rc = dalloc(&ctx->dtn_inv[l], nc)) ||
             (rc = dalloc(&ctx->drho[l], ctx->hl[l].w_cell.size() + 1)) || (rc = dalloc(&ctx->fW[l], 4 * nc)) ||
             (rc = dalloc(&ctx->fW0[l], 4 * nc)) || (rc = dalloc(&ctx->fR[l], 4 * nc)) ||
@@ -1519,6 +1549,30 @@ int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgri
         }
     for (int a = 0; a < v->nu; ++a) hv.umax = std::fmax(hv.umax, std::fabs(v->u[a]));
     for (int b = 0; b < v->nv; ++b) hv.vmax = std::fmax(hv.vmax, std::fabs(v->v[b]));
+    // mirror velocities of the symmetry faces (-1 where the grid lacks the reversed node)
+    {
+        bool symu = true, symv = true;
+        for (int a = 0; a < v->nu; ++a)
+            symu = symu && std::fabs(v->u[v->nu - 1 - a] + v->u[a]) <= 1e-12 * std::fmax(1.0, hv.umax);
+        for (int b = 0; b < v->nv; ++b)
+            symv = symv && std::fabs(v->v[v->nv - 1 - b] + v->v[b]) <= 1e-12 * std::fmax(1.0, hv.vmax);
+        hv.mx.assign(hv.nk, -1);
+        hv.my.assign(hv.nk, -1);
+        for (int a = 0; a < v->nu; ++a)
+            for (int b = 0; b < v->nv; ++b) {
+                if (symu) hv.mx[a * v->nv + b] = (v->nu - 1 - a) * v->nv + b;
+                if (symv) hv.my[a * v->nv + b] = a * v->nv + (v->nv - 1 - b);
+            }
+        bool symx = false, symy = false;
+        for (int i = 0; i < (m->nx + 1) * m->ny; ++i) symx = symx || m->face_type_x[i] == MIUGKS_FACE_SYMMETRY;
+        for (int i = 0; i < m->nx * (m->ny + 1); ++i) symy = symy || m->face_type_y[i] == MIUGKS_FACE_SYMMETRY;
+        if ((symx && !symu) || (symy && !symv)) {
+            g_create_error = "symmetry faces need a velocity grid symmetric in the normal component";
+            delete ctx;
+            return MIUGKS_EINVAL;
+        }
+        ctx->has_sym = symx || symy;
+    }
     // gas constants; mu_ref from the VHS mean free path (alpha = 1)
     Gas& gas = ctx->gas;
     gas.K_int = g->K_int;

@@ -205,6 +205,9 @@ bool make_level(HostLevel& L, const HostVel& vel, double cfl, std::string& err) 
                 } else if (tag == MIUGKS_FACE_FARFIELD) {
                     L.nb[at] = NB_FARFIELD;
                     L.dcent[at] = 2.0 * dface;
+                } else if (tag == MIUGKS_FACE_SYMMETRY) {
+                    L.nb[at] = NB_SYMMETRY;
+                    L.dcent[at] = 2.0 * dface;
                 } else if (tag == MIUGKS_FACE_OUTFLOW) {
                     L.nb[at] = NB_OUTFLOW;
                     L.dcent[at] = 2.0 * dface;

@@ -13,6 +13,7 @@ namespace miugks {
 constexpr int NB_FARFIELD = -1;
 constexpr int NB_OUTFLOW = -2;
 constexpr int NB_NONE = -3;       // side of a solid cell
+constexpr int NB_SYMMETRY = -4;   // symmetry face (specular reflection)
 constexpr int NB_WALL0 = -16;     // wall side j is encoded as NB_WALL0 - j
 
 inline bool nb_is_wall(int code) { return code <= NB_WALL0; }
@@ -37,6 +38,7 @@ struct HostLevel {
 struct HostVel {
     int nu = 0, nv = 0, nk = 0;
     std::vector<double> u, v, w;   // [nk], k = ku * nv + kv
+    std::vector<int> mx, my;       // [nk] the velocity with u (mx) or v (my) reversed, -1 if the grid lacks it
     double umax = 0, vmax = 0;
 };
 

@@ -28,9 +28,9 @@ def test_header_constants_match_the_binding_and_the_inputs():
     consts = {k: int(v) for k, v in re.findall(r"#define MIUGKS_([A-Z0-9_]+) \(?(-?\d+)\)?", text)}
     for name in ("OK", "EINVAL", "ENOMEM", "EDEVICE", "EDIVERGED", "ENOTCONVERGED", "ESTATE", "FP64", "FP32F",
                  "QUAD_TRAPEZOID", "QUAD_SIMPSON38", "QUAD_GAUSS_HERMITE", "CYCLE_F", "LOAD_PRESSURE", "LOAD_SHEAR", "LOAD_HEAT",
-                 "FACE_INTERIOR", "FACE_WALL", "FACE_FARFIELD", "FACE_OUTFLOW"):
+                 "FACE_INTERIOR", "FACE_WALL", "FACE_FARFIELD", "FACE_OUTFLOW", "FACE_SYMMETRY"):
         assert consts[name] == getattr(_C, name), name
-    for name in ("FACE_INTERIOR", "FACE_WALL", "FACE_FARFIELD", "FACE_OUTFLOW", "CYCLE_F"):
+    for name in ("FACE_INTERIOR", "FACE_WALL", "FACE_FARFIELD", "FACE_OUTFLOW", "FACE_SYMMETRY", "CYCLE_F"):
         assert consts[name] == getattr(wl, name), name
 
 
