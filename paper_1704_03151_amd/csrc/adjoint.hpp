@@ -230,11 +230,19 @@ __global__ void __launch_bounds__(256) k_adj_cell(Geo g, Vel vel, Gas gas, const
 
 // Interior faces, one wavefront per (direction d, cell c) = the face on side
 // 2d of c (c is R, its neighbour L), reading the forward interface record of
-// the face (Step 1 of the same f).  fa[(m * 2 + d) nc + c], m < NFA.
+// the face (Step 1 of the same f).  Two launches: PART 0 forms the 28 sums
+// over the velocities of pass A into fsum[(m * 2 + d) nc + c]; PART 1 runs
+// the scalar reverse chain, pass B and the final chain into
+// fa[(m * 2 + d) nc + c], m < NFA (the split halves the registers live at once).
+constexpr int NFS = 28;
+template <int PART>
 __global__ void __launch_bounds__(256) k_adj_face(Geo g, Vel vel, Gas gas, const double* __restrict__ f,
                                                    const double* __restrict__ W, const double* __restrict__ fp,
-                                                   const double* __restrict__ v, double* __restrict__ fa) {
-    int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+                                                   const double* __restrict__ v, double* __restrict__ fsum,
+                                                   double* __restrict__ fa) {
+    // the face is the same across the wavefront: its record, geometry and
+    // scalars live in scalar registers
+    int t = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)), lane = threadIdx.x & 63;
     if (t >= 2 * g.nc) return;
     const int nc = g.nc, d = t / nc, c = t - d * nc;
     const size_t stride = 2 * (size_t)nc;
@@ -242,7 +250,7 @@ __global__ void __launch_bounds__(256) k_adj_face(Geo g, Vel vel, Gas gas, const
     double* out = fa + (size_t)d * nc + c;
     FaceGeom<double> fg;
     if (g.solid[c] || rec[23 * stride] == 0.0 || !face_geom<double>(g, c, d, fg)) {
-        if (lane < NFA) out[lane * stride] = 0.0;
+        if (PART == 1 && lane < NFA) out[lane * stride] = 0.0;
         return;
     }
     const int L = fg.L, Ki = gas.K_int;
@@ -262,10 +270,16 @@ __global__ void __launch_bounds__(256) k_adj_face(Geo g, Vel vel, Gas gas, const
     const double tau0 = mu_of(gas, 1.0 / lam0) / (rho0 / (2.0 * lam0));
     const double cL = 0.5 / fg.dL, cR = 0.5 / fg.dR;   // S / V of the two cells
     const size_t ho = (size_t)vel.nk * nc;
-    // pass A: q1..q5 bar, Shakhov, time slope, G0 folds, compatibility sums, heat-flux sums
-    double a[28] = {0};
+    // pass A: q1..q5 bar, Shakhov, time slope, G0 folds, compatibility sums,
+    // heat-flux sums, in two loops over the velocities (fewer live values)
+    double a[NFS] = {0};
     // 0-4 qbar, 5-10 shakhov, 11-14 Abar, 15 lam (A), 16-19 G0 fold, 20-23 Mb, 24 S0 25 Sxx 26 Syy 27 Sxy
-    for (int k = lane; k < vel.nk; k += 64) {
+    double* sums = fsum + (size_t)d * nc + c;
+    if constexpr (PART == 1) {
+        for (int m = 0; m < NFS; ++m) a[m] = sums[m * stride];
+    } else {
+#pragma unroll 1
+    for (int k = lane; k < vel.nk; k += 64) {   // A1: needs the interface values
         double u = vel.u[k], vv = vel.v[k], w = vel.w[k], un = d == 0 ? u : vv;
         size_t kc = (size_t)k * nc;
         double Gup, Hup, sGup, sHup;
@@ -282,16 +296,11 @@ __global__ void __launch_bounds__(256) k_adj_face(Geo g, Vel vel, Gas gas, const
         slope_poly<double>(A, u, vv, lam0, Ki, pGA, pHA);
         double hL = un > 0.0 ? 1.0 : (un < 0.0 ? 0.0 : 0.5), hR = 1.0 - hL;
         double Gs = (hL * pGL + hR * pGR) * G0, Hs = (hL * pHL + hR * pHR) * H0;
-        double GA = pGA * G0, HA = pHA * H0;
         a[0] += phG * Geq + phH * Heq;
         a[1] += un * (phG * Gs + phH * Hs);
-        a[2] += phG * GA + phH * HA;
+        a[2] += phG * pGA * G0 + phH * pHA * H0;
         a[3] += phG * Gup + phH * Hup;
         a[4] += un * (phG * sGup + phH * sHup);
-        shakhov_rev_k(rho0, U0, V0, lam0, q0x, q0y, u, vv, Ki, s, G0, qc[0] * phG, qc[0] * phH, a + 5);
-        double g0b, h0b;
-        slope_rev_k(A, u, vv, lam0, Ki, G0, H0, qc[2] * phG, qc[2] * phH, a + 11, a[15], g0b, h0b);
-        g0_fold(G0, cx, cy, rho0, lam0, Ki, g0b, h0b, a + 16);
         a[20] += w * un * Gs;
         a[21] += w * un * u * Gs;
         a[22] += w * un * vv * Gs;
@@ -301,7 +310,24 @@ __global__ void __launch_bounds__(256) k_adj_face(Geo g, Vel vel, Gas gas, const
         a[26] += w * cy * cy * Gup;
         a[27] += w * cx * cy * Gup;
     }
-    wave_allsum<28>(a);
+#pragma unroll 1
+    for (int k = lane; k < vel.nk; k += 64) {   // A2: the equilibrium and time-slope reverses
+        double u = vel.u[k], vv = vel.v[k], un = d == 0 ? u : vv;
+        size_t kc = (size_t)k * nc;
+        double phG = (-v[kc + L] * cL + v[kc + c] * cR) * un / dt;
+        double phH = (-v[ho + kc + L] * cL + v[ho + kc + c] * cR) * un / dt;
+        double cx = u - U0, cy = vv - V0, c2 = cx * cx + cy * cy;
+        double G0 = rho0 * (lam0 / M_PI) * exp(-lam0 * c2), H0 = (Ki / (2.0 * lam0)) * G0;
+        shakhov_rev_k(rho0, U0, V0, lam0, q0x, q0y, u, vv, Ki, s, G0, qc[0] * phG, qc[0] * phH, a + 5);
+        double g0b, h0b;
+        slope_rev_k(A, u, vv, lam0, Ki, G0, H0, qc[2] * phG, qc[2] * phH, a + 11, a[15], g0b, h0b);
+        g0_fold(G0, cx, cy, rho0, lam0, Ki, g0b, h0b, a + 16);
+    }
+    wave_allsum<NFS>(a);
+    if (lane == 0)
+        for (int m = 0; m < NFS; ++m) sums[m * stride] = a[m];
+    return;
+    }
     double rho0b = a[16], U0b = a[17], V0b = a[18], lam0b = a[15] + a[19];
     rho0b += a[5];
     U0b += a[6];
@@ -319,6 +345,7 @@ __global__ void __launch_bounds__(256) k_adj_face(Geo g, Vel vel, Gas gas, const
     }
     // pass B: the spatial micro-slopes through Gs
     double e[13] = {0};   // 0-3 aL bar, 4-7 aR bar, 8 lam, 9-12 G0 fold
+#pragma unroll 1
     for (int k = lane; k < vel.nk; k += 64) {
         double u = vel.u[k], vv = vel.v[k], w = vel.w[k], un = d == 0 ? u : vv;
         size_t kc = (size_t)k * nc;

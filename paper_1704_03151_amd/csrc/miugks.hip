@@ -124,7 +124,7 @@ struct miugks_ctx {
     double *a_lam = nullptr, *a_res = nullptr, *a_y = nullptr, *a_b = nullptr, *a_out = nullptr;
     double *a_gbd = nullptr, *a_sb = nullptr, *a_crec = nullptr, *a_fa = nullptr, *a_rws = nullptr;
     double *a_objw = nullptr, *a_Qj = nullptr, *a_rhow = nullptr, *a_part = nullptr, *a_grad = nullptr;
-    double* a_fsave = nullptr;
+    double *a_fsave = nullptr, *a_fsum = nullptr;
     int* a_sides = nullptr;
     int a_nparts = 0;
     // Krylov basis (m + 1 vectors), Hessenberg column, dot-product partials
@@ -1848,7 +1848,8 @@ static int adj_alloc(miugks_ctx* c) {
         (rc = da(&c->a_sb, 4 * n)) || (rc = da(&c->a_crec, NCA * nc)) || (rc = da(&c->a_fa, NFA * 2 * nc)) ||
         (rc = da(&c->a_rws, nw)) || (rc = da(&c->a_objw, nw)) || (rc = da(&c->a_Qj, nw)) ||
         (rc = da(&c->a_rhow, nw)) || (rc = da(&c->a_part, c->a_nparts)) || (rc = da(&c->a_grad, 2 * nw)) ||
-        (rc = da(&c->a_fsave, 2 * n)) || (rc = dev_alloc(c, (void**)&c->a_sides, 2 * nw * sizeof(int))))
+        (rc = da(&c->a_fsave, 2 * n)) || (rc = da(&c->a_fsum, NFS * 2 * nc)) ||
+        (rc = dev_alloc(c, (void**)&c->a_sides, 2 * nw * sizeof(int))))
         return rc;
     return MIUGKS_OK;
 }
@@ -1877,8 +1878,10 @@ static void adj_product(miugks_ctx* c, const double* v, double* out) {
     const double pass = 2.0 * n * 8;
     LAUNCH(c, "adj_cell", 2 * pass, k_adj_cell, dim3((g.nc + 3) / 4), dim3(256), g, c->vel, c->gas, f,
            (const double*)c->W, (const double*)c->q, v, c->a_crec);
-    LAUNCH(c, "adj_face", 2 * pass, k_adj_face, dim3((2 * g.nc + 3) / 4), dim3(256), g, c->vel, c->gas, f,
-           (const double*)c->W, (const double*)c->fp, v, c->a_fa);
+    LAUNCH(c, "adj_face_sums", 2 * pass, k_adj_face<0>, dim3((2 * g.nc + 3) / 4), dim3(256), g, c->vel, c->gas, f,
+           (const double*)c->W, (const double*)c->fp, v, c->a_fsum, c->a_fa);
+    LAUNCH(c, "adj_face", 2 * pass, k_adj_face<1>, dim3((2 * g.nc + 3) / 4), dim3(256), g, c->vel, c->gas, f,
+           (const double*)c->W, (const double*)c->fp, v, c->a_fsum, c->a_fa);
     if (g.n_wall)
         LAUNCH(c, "adj_wall", 0.0, k_adj_wall, dim3((g.n_wall + 3) / 4), dim3(256), g, c->vel, c->gas.K_int, v,
                c->a_rws);
@@ -1981,9 +1984,20 @@ int miugks_adjoint(miugks_ctx* ctx, int kind, const int* walls, int n, const int
         HIP_TRY(hipMemcpyAsync(ctx->a_fsave, ctx->f, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
         for (int sgn = 0; sgn < 2; ++sgn) {
             double sc = sgn == 0 ? delta : -delta;
-            HIP_TRY(hipMemcpyAsync(ctx->f, ctx->a_fsave, N * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-            LAUNCH(ctx, "adj_axpy", 3.0 * N * 8, k_adj_axpy, dim3((unsigned)((N + 255) / 256)), dim3(256),
-                   (double*)ctx->f, (const double*)ctx->f, sc, N);
+            const dim3 nbN((unsigned)((N + 255) / 256));
+            if (sgn == 0) {   // start from the scaled state
+                HIP_TRY(hipMemcpyAsync(ctx->f, ctx->a_fsave, N * sizeof(double), hipMemcpyDeviceToDevice,
+                                       ctx->stream));
+                LAUNCH(ctx, "adj_axpy", 3.0 * N * 8, k_adj_axpy, nbN, dim3(256), (double*)ctx->f,
+                       (const double*)ctx->f, sc, N);
+            } else {          // 2 f* - f+: the reflection of the first state, of mass M0 (1 - delta)
+                HIP_TRY(hipMemcpyAsync(ctx->a_res, ctx->f, N * sizeof(double), hipMemcpyDeviceToDevice,
+                                       ctx->stream));
+                LAUNCH(ctx, "adj_scale", 2.0 * N * 8, k_adj_scale, nbN, dim3(256), (double*)ctx->f,
+                       (const double*)ctx->a_fsave, 2.0, N);
+                LAUNCH(ctx, "adj_axpy", 3.0 * N * 8, k_adj_axpy, nbN, dim3(256), (double*)ctx->f,
+                       (const double*)ctx->a_res, -1.0, N);
+            }
             ctx->M0 = M0 * (1.0 + sc);
             drop_graphs(ctx);
             Path<double>::moments(ctx, nullptr);
