@@ -29,6 +29,7 @@
 #ifndef MIUGKS_H
 #define MIUGKS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -73,6 +74,11 @@ extern "C" {
 #define MIUGKS_LOAD_HEAT 2
 
 typedef struct miugks_ctx miugks_ctx;
+
+/* Device allocator callbacks: alloc returns `bytes` of device memory on the
+ * current device (NULL when it cannot), free releases a pointer alloc gave. */
+typedef void* (*miugks_alloc_fn)(size_t bytes, void* user);
+typedef void (*miugks_free_fn)(void* ptr, void* user);
 
 /* Structured mesh (Sec. III A).  Cell (ix, iy) spans [x[ix], x[ix+1]] x
  * [y[iy], y[iy+1]].  x-face (ix, iy), index iy*(nx+1)+ix, lies on x = x[ix];
@@ -138,6 +144,16 @@ typedef struct {
  * whose weights integrate plain functions: w = w_GH * exp(u^2)).  nodes and
  * weights are host arrays of n doubles.  Sec. IV (trapezoid, Newton-Cotes). */
 int miugks_quadrature(int kind, int n, double lo, double hi, double* nodes, double* weights);
+
+/* Allocator of the contexts created from now on (process-wide; not to be
+ * called while another thread creates a context): every device buffer a
+ * context allocates, at creation, for the adjoint or for conversions, comes
+ * from alloc and goes back through free when the context is destroyed (or
+ * sooner for temporaries).  Lets a caller back the library's memory by its own
+ * pool, such as PyTorch's caching allocator.  (NULL, NULL) restores hipMalloc
+ * / hipFree; MIUGKS_EINVAL when only one of the two is NULL.  A context keeps
+ * the pair it was created with. */
+int miugks_set_allocator(miugks_alloc_fn alloc, miugks_free_fn free_fn, void* user);
 
 /* Build the level hierarchy and allocate device memory.  hip_stream is a
  * hipStream_t (e.g. torch.cuda.current_stream().cuda_stream) or NULL for the

@@ -51,7 +51,11 @@ class SolverDesc(ctypes.Structure):
                 ("cycle_gamma_cs", ctypes.c_int)]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
 _SIGS = {
+    "miugks_set_allocator": (ctypes.c_int, [ALLOC_FN, FREE_FN, ctypes.c_void_p]),
     "miugks_quadrature": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp]),
     "miugks_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(MeshDesc),
                                      ctypes.POINTER(VGridDesc), ctypes.POINTER(GasDesc),

@@ -8,6 +8,6 @@ the adjoint).  Importing the package loads the library and fails loudly when
 it has not been built.
 """
 from . import _C  # noqa: F401  (loads libmiugks.so)
-from .solver import Solver  # noqa: F401
+from .solver import Solver, use_torch_allocator  # noqa: F401
 
-__all__ = ["Solver"]
+__all__ = ["Solver", "use_torch_allocator"]

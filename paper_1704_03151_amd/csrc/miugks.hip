@@ -26,6 +26,10 @@ using namespace miugks;
 namespace {
 
 std::string g_create_error;
+// device allocator for the contexts created next (null: hipMalloc / hipFree)
+miugks_alloc_fn g_alloc = nullptr;
+miugks_free_fn g_free = nullptr;
+void* g_alloc_user = nullptr;
 
 struct DevLevel {
     Geo geo;
@@ -38,6 +42,10 @@ struct miugks_timing_state;
 
 struct miugks_ctx {
     std::string err;
+    // the device allocator of this context (null: hipMalloc / hipFree)
+    miugks_alloc_fn alloc = nullptr;
+    miugks_free_fn free_fn = nullptr;
+    void* alloc_user = nullptr;
     hipStream_t stream = nullptr;
     int device = 0;
     int prec = MIUGKS_FP64;
@@ -143,13 +151,36 @@ namespace {
         }                                                                                      \
     } while (0)
 
-int dev_alloc(miugks_ctx* ctx, void** p, size_t bytes) {
+// device memory through the context's allocator; not recorded for destroy
+int raw_alloc(miugks_ctx* ctx, void** p, size_t bytes) {
     if (bytes == 0) bytes = 8;
+    if (ctx->alloc) {
+        *p = ctx->alloc(bytes, ctx->alloc_user);
+        if (!*p) {
+            ctx->err = "the caller's allocator returned no memory";
+            return MIUGKS_ENOMEM;
+        }
+        return MIUGKS_OK;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         ctx->err = std::string("hipMalloc: ") + hipGetErrorString(e);
         return MIUGKS_ENOMEM;
     }
+    return MIUGKS_OK;
+}
+
+void raw_free(miugks_ctx* ctx, void* p) {
+    if (!p) return;
+    if (ctx->free_fn)
+        ctx->free_fn(p, ctx->alloc_user);
+    else
+        (void)hipFree(p);
+}
+
+int dev_alloc(miugks_ctx* ctx, void** p, size_t bytes) {
+    int rc = raw_alloc(ctx, p, bytes);
+    if (rc) return rc;
     ctx->allocs.push_back(*p);
     return MIUGKS_OK;
 }
@@ -1380,7 +1411,7 @@ int copy_out(miugks_ctx* ctx, const void* src, void* dst, int dtype, int on_devi
     void* tmp = nullptr;
     void* target = dst;
     if (!on_device) {
-        HIP_TRY(hipMalloc(&tmp, n * des));
+        if (int r = raw_alloc(ctx, &tmp, n * des)) return r;
         target = tmp;
     }
     if (dtype == ctx->prec) {
@@ -1394,7 +1425,7 @@ int copy_out(miugks_ctx* ctx, const void* src, void* dst, int dtype, int on_devi
     }
     if (!on_device) hipMemcpyAsync(dst, tmp, n * des, hipMemcpyDeviceToHost, ctx->stream);
     hipError_t e = hipStreamSynchronize(ctx->stream);
-    if (tmp) hipFree(tmp);
+    raw_free(ctx, tmp);
     if (e != hipSuccess) {
         ctx->err = std::string("copy: ") + hipGetErrorString(e);
         return MIUGKS_EDEVICE;
@@ -1416,7 +1447,7 @@ int copy_in(miugks_ctx* ctx, const void* src, void* dst, int dtype, int on_devic
     void* tmp = nullptr;
     const void* from = src;
     if (!on_device) {
-        HIP_TRY(hipMalloc(&tmp, n * des));
+        if (int r = raw_alloc(ctx, &tmp, n * des)) return r;
         hipMemcpyAsync(tmp, src, n * des, hipMemcpyHostToDevice, ctx->stream);
         from = tmp;
     }
@@ -1430,7 +1461,7 @@ int copy_in(miugks_ctx* ctx, const void* src, void* dst, int dtype, int on_devic
                            (float*)dst, n);
     }
     hipError_t e = hipStreamSynchronize(ctx->stream);
-    if (tmp) hipFree(tmp);
+    raw_free(ctx, tmp);
     if (e != hipSuccess) {
         ctx->err = std::string("copy: ") + hipGetErrorString(e);
         return MIUGKS_EDEVICE;
@@ -1478,11 +1509,19 @@ void miugks_destroy(miugks_ctx* ctx) {
     }
     if (ctx->g_step1) (void)hipGraphExecDestroy(ctx->g_step1);
     if (ctx->g_rest) (void)hipGraphExecDestroy(ctx->g_rest);
-    for (void* p : ctx->allocs) (void)hipFree(p);
+    for (void* p : ctx->allocs) raw_free(ctx, p);
     if (ctx->h_norms) (void)hipHostFree(ctx->h_norms);
     if (ctx->h_factor) (void)hipHostFree(ctx->h_factor);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
+}
+
+int miugks_set_allocator(miugks_alloc_fn alloc, miugks_free_fn free_fn, void* user) {
+    if ((alloc == nullptr) != (free_fn == nullptr)) return MIUGKS_EINVAL;
+    g_alloc = alloc;
+    g_free = free_fn;
+    g_alloc_user = user;
+    return MIUGKS_OK;
 }
 
 int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgrid_desc* v, const miugks_gas_desc* g,
@@ -1499,6 +1538,9 @@ int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgri
         return MIUGKS_ENOMEM;
     }
     ctx->stream = (hipStream_t)hip_stream;
+    ctx->alloc = g_alloc;
+    ctx->free_fn = g_free;
+    ctx->alloc_user = g_alloc_user;
     ctx->use_graphs = getenv("MIUGKS_NO_GRAPH") == nullptr;
     if (s->precision != MIUGKS_FP64 && s->precision != MIUGKS_FP32F) {
         g_create_error = "precision must be MIUGKS_FP64 or MIUGKS_FP32F";

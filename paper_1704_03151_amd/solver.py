@@ -28,6 +28,31 @@ def _stream_handle(stream):
     return 0
 
 
+_ALLOCATORS = []   # every callback pair handed to the library: a context uses its pair until destroyed
+
+
+def use_torch_allocator(on=True):
+    """Back the device memory of the contexts created from now on by PyTorch's
+    caching allocator (on=False: hipMalloc again).  The callbacks only forward
+    to torch.cuda.caching_allocator_alloc / caching_allocator_delete."""
+    if not on:
+        return _C.lib.miugks_set_allocator(_C.ALLOC_FN(), _C.FREE_FN(), None)
+    import torch
+
+    def alloc(nbytes, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except RuntimeError:
+            return None
+
+    def free(ptr, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    pair = (_C.ALLOC_FN(alloc), _C.FREE_FN(free))
+    _ALLOCATORS.append(pair)
+    return _C.lib.miugks_set_allocator(pair[0], pair[1], None)
+
+
 class Solver:
     """One context: create from a case, iterate, read fields."""
 

@@ -62,3 +62,13 @@ def test_quadrature_rejects_bad_arguments():
         _C.quadrature(7, 10, -1, 1)          # unknown rule
     with pytest.raises(_C.MiugksError):
         _C.quadrature(0, 10, 1, -1)          # empty range
+
+
+def test_allocator_pair_must_be_complete():
+    """miugks_set_allocator refuses an allocator without its free (and the
+    reverse) and accepts restoring hipMalloc / hipFree.  No GPU calls."""
+    from paper_1704_03151_amd import _C
+    alloc = _C.ALLOC_FN(lambda n, u: None)
+    assert _C.lib.miugks_set_allocator(alloc, _C.FREE_FN(), None) == _C.EINVAL
+    assert _C.lib.miugks_set_allocator(_C.ALLOC_FN(), _C.FREE_FN(lambda p, u: None), None) == _C.EINVAL
+    assert _C.lib.miugks_set_allocator(_C.ALLOC_FN(), _C.FREE_FN(), None) == _C.OK
