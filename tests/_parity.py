@@ -3,6 +3,7 @@ tag, ragged sizes, and the comparison metrics."""
 import numpy as np
 
 import workloads as wl
+from oracle import flux as fx
 
 
 def small_cases():
@@ -57,3 +58,22 @@ def to_oracle(f):
 
 def from_oracle(G, H, case):
     return np.stack([G.reshape(-1, case.ny, case.nx), H.reshape(-1, case.ny, case.nx)])
+
+
+def free_molecular_closed_form(case, vel, K_int, M0, area):
+    """Heat transfer through a free-molecular gap: every point holds the bottom
+    plate's half-range Maxwellian rho_b C_b for upward velocities and the top
+    plate's rho_t C_t for downward ones; zero net mass flux and the total mass
+    fix rho_b and rho_t (discrete sums over the velocity grid)."""
+    Cb, Hb = fx.wall_maxwellian(case.wall_y[0, 0, 0], 0.0, 0.0, vel.u, vel.v, K_int)
+    Ct, Ht = fx.wall_maxwellian(case.wall_y[case.ny, 0, 0], 0.0, 0.0, vel.u, vel.v, K_int)
+    up, dn = vel.v > 0, vel.v < 0
+    # rho_b Fb = rho_t Ft (flux balance), area (rho_b Mb + rho_t Mt) = M0 (mass)
+    Fb = np.sum((vel.w * vel.v * Cb)[up])
+    Ft = -np.sum((vel.w * vel.v * Ct)[dn])
+    Mb = np.sum((vel.w * Cb)[up])
+    Mt = np.sum((vel.w * Ct)[dn])
+    rb, rt = np.linalg.solve([[Fb, -Ft], [area * Mb, area * Mt]], [0.0, M0])
+    G = np.where(up, rb * Cb, rt * Ct)
+    H = np.where(up, rb * Hb, rt * Ht)
+    return G, H

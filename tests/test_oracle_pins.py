@@ -19,6 +19,7 @@ from oracle.mesh import Level, Prolongation, build_levels, restrict
 from oracle.quadrature import VelocityGrid, gauss_hermite, simpson38, trapezoid
 from oracle.solver import Oracle
 from oracle.sparse import assemble
+from _parity import free_molecular_closed_form
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -591,3 +592,23 @@ def test_cs_cycle_with_symmetry_faces_converges_to_direct_solve():
     assert np.allclose(got, x, rtol=1e-10, atol=1e-12 * np.max(np.abs(x)))
     # the symmetry rows are really there: dropping them changes the solution
     assert mls[0].sym.sum() == 16
+
+
+def test_free_molecular_gap_reaches_the_closed_form():
+    """Survey pin 'free-molecular limit', as heat transfer between plates at
+    rest: with collisions vanishing (Kn 1e12) the scheme's steady state is
+    the uniform pair of half-range wall Maxwellians, and the heat flux is
+    the closed form's."""
+    case = wl.free_molecular_gap(quad="trapezoid", nvel=16, vlo=-5.0, vhi=5.0, n_levels=2)
+    o = Oracle(case)
+    ok, norms = o.iterate(200, tol=1e-13)
+    assert ok, norms
+    area = float(np.sum(o.lev0.V))
+    G, H = free_molecular_closed_form(case, o.vel, o.gas.K_int, o.M0, area)
+    assert np.max(np.abs(o.G - G[:, None])) < 1e-10 * np.max(G)
+    assert np.max(np.abs(o.H - H[:, None])) < 1e-10 * np.max(H)
+    # the bottom plate, hotter, heats the gap: upward heat flux everywhere
+    qy = o.q[1]
+    v, u, w = o.vel.v, o.vel.u, o.vel.w
+    q_ref = 0.5 * np.sum(w * v * ((u * u + v * v) * G + H))
+    assert q_ref > 0 and np.max(np.abs(qy - q_ref)) < 1e-10 * q_ref

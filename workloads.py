@@ -231,6 +231,18 @@ def symmetric_channel(n=6, ny=None, U=0.3, **kw) -> Case:
     return case
 
 
+def free_molecular_gap(n=6, ny=4, T_bottom=1.1, T_top=0.9, Kn=1e12, **kw) -> Case:
+    """Gas at rest between two diffuse plates at different temperatures
+    (bottom and top), specular sides, Kn so large that collisions vanish."""
+    case = cavity(n=n, ny=ny, Kn=Kn, mach=0.0, name=kw.pop("name", None) or "free_molecular_gap", **kw)
+    case.face_type_x[:, 0] = case.face_type_x[:, case.nx] = FACE_SYMMETRY
+    case.wall_x[:] = 0.0
+    case.wall_y[0, :, 0] = T_bottom
+    case.wall_y[case.ny, :, 0] = T_top
+    case.wall_y[:, :, 1:] = 0.0
+    return case
+
+
 def config1(**kw) -> Case:
     """Cavity 16x16 uniform, 16x16 trapezoid on [-4,4]^2, Kn 10, lid Mach 0.16, 2 levels."""
     args = dict(n=16, Kn=10.0, n_levels=2, quad=QUAD_TRAPEZOID, nvel=16, vlo=-4.0, vhi=4.0,
