@@ -8,6 +8,7 @@ import pytest
 import workloads as wl
 from oracle import adjoint as ad
 from oracle.solver import Oracle
+from _parity import tiny_open_plate
 
 N = 4
 
@@ -119,3 +120,34 @@ def test_objective_gradient_matches_steady_state_differences(steady):
     # a face of the lid itself also moves J directly (the partial at fixed f)
     direct = S.dJ_dT(ad.LOAD_SHEAR, lid, [nfx + N * N + 1])
     assert abs(direct[0]) > 0
+
+
+def test_open_domain_gradient_matches_steady_state_differences():
+    """Open domain (plate in a farfield, no mass constraint, so the tangent is
+    a plain solve): dJ/dTw of the plate's pressure, shear and heat loads,
+    summed over both of its sides, with respect to the plate face's one
+    temperature, against central differences (h = 2e-5) of J over FP64
+    steady states converged to 2e-13."""
+    case, face = tiny_open_plate()
+    o = Oracle(case)
+    ok, norms = o.iterate(200, tol=2e-13)
+    assert ok and not o.closed, norms
+    S = ad.Sensitivity(o)
+    walls = list(range(len(ad.wall_list(o.lev0))))
+    assert len(walls) == 2
+    T = S.tangent(S.jacobian(), S.dr_dT([face]))
+    kinds = (ad.LOAD_PRESSURE, ad.LOAD_SHEAR, ad.LOAD_HEAT)
+    g = np.array([(S.dJ_df(k, walls) @ T + S.dJ_dT(k, walls, [face]))[0] for k in kinds])
+    h = 2e-5
+    vals = []
+    for sgn in (1.0, -1.0):
+        c2 = case.with_(wall_y=case.wall_y.copy())
+        j, i = divmod(face - (case.nx + 1) * case.ny, case.nx)
+        c2.wall_y[j, i, 0] += sgn * h
+        o2 = Oracle(c2)
+        o2.set_f(o.G, o.H)
+        ok, norms = o2.iterate(300, tol=2e-13)
+        assert ok, norms
+        vals.append([ad.objective(o2.G, o2.H, o2.lev0, o2.vel, o2.gas, c2.farfield, k, walls) for k in kinds])
+    fd = (np.array(vals[0]) - np.array(vals[1])) / (2 * h)
+    assert np.max(np.abs(g - fd)) < 1e-5 * np.max(np.abs(fd)), (g, fd)
