@@ -1185,7 +1185,80 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
         bool fluid = !g.solid[c];
         int ix = c % g.nx, iy = c / g.nx;
         if (fluid) {
-            for (int s = 0; s < 4; ++s) {
+            // The -x side first.  Its face is also the +x face of the cell on
+            // the left, which is the previous lane's cell whenever both lie in
+            // this tile: the face flux is formed once and handed down a lane.
+            // (An interior neighbour is a fluid cell whose face across is
+            // interior too, so the lane on the right always forms it.)
+            const A sv_x = A(1.0 / g.dx[ix]);
+            const bool take1 = g.nb[g.nc + c] == c + 1 && ch.lane < TILE - 1;
+            {
+                const int code = g.nb[c];
+                FaceConst<A> FC;
+                FaceGeom<T> fg;
+                FaceVals<T> cur{}, nxt{};
+                A lam = A(1), Uw = A(0), Vw = A(0), rw = A(0);
+                const bool far = code == NB_FARFIELD, sym = code == NB_SYMMETRY, wall = is_wall(code);
+                if (code >= 0) {
+                    const double* rec = fp + c;
+                    size_t stride = 2 * nc;
+                    A P[23];
+                    for (int m = 0; m < 23; ++m) P[m] = A(rec[m * stride]);
+                    face_const<A>(P, gas.K_int, FC);
+                    face_geom<T>(g, c, 0, fg);
+                    face_load<T, T>(fg, c, f, ho, (size_t)kk[0] * nc, nxt);
+                } else if (wall) {
+                    int jw = wall_of(code);
+                    lam = A(1.0 / g.w_T[jw]);
+                    Uw = A(g.w_U[jw]);
+                    Vw = A(g.w_V[jw]);
+                    rw = A(rho_w[jw]);
+                }
+                for (int j = 0; j < nmine; ++j) {
+                    int k = kk[j];
+                    A u = vel.u[k], v = vel.v[k];
+                    A PG = A(0), PH = A(0);
+                    if (code >= 0) {
+                        cur = nxt;
+                        if (j + 1 < nmine) face_load<T, T>(fg, c, f, ho, (size_t)kk[j + 1] * nc, nxt);
+                        T Gu, Hu, sGt, sHt;
+                        face_upwind_vals<T, T>(fg, cur, T(u), Gu, Hu, sGt, sHt);
+                        A Gup = Gu, Hup = Hu, sGu = sGt, sHu = sHt;
+                        face_flux<A>(FC, u, v, u, Gup, Hup, sGu, sHu, PG, PH);
+                        dG[j] += A(-1) * sv_x * PG;
+                        dH[j] += A(-1) * sv_x * PH;
+                    } else {
+                        A un = A(-1) * u;
+                        A Gf, Hf;
+                        if (wall && !(un > A(0))) {
+                            A du = u - Uw, dv = v - Vw;
+                            A C = lam / A(M_PI) * dexp(-lam * (du * du + dv * dv));
+                            Gf = rw * C;
+                            Hf = rw * A(gas.K_int) / (A(2) * lam) * C;
+                        } else if (far && un <= A(0)) {
+                            Gf = A(finf[k]);
+                            Hf = A(finf[nk + k]);
+                        } else if (sym && un <= A(0)) {
+                            int km = mirror_of(vel, 0, k);
+                            Gf = A(f[(size_t)km * nc + c]);
+                            Hf = A(f[ho + (size_t)km * nc + c]);
+                        } else {
+                            Gf = A(f[(size_t)k * nc + c]);
+                            Hf = A(f[ho + (size_t)k * nc + c]);
+                        }
+                        dG[j] += sv_x * un * Gf;
+                        dH[j] += sv_x * un * Hf;
+                    }
+                    // the +x side: the face flux of the lane on the right
+                    A nG = __shfl_down(PG, 1, TILE), nH = __shfl_down(PH, 1, TILE);
+                    if (take1) {
+                        dG[j] += A(1) * sv_x * nG;
+                        dH[j] += A(1) * sv_x * nH;
+                    }
+                }
+            }
+            for (int s = 1; s < 4; ++s) {
+                if (s == 1 && take1) continue;
                 int code = g.nb[s * g.nc + c];
                 int d = s >> 1;
                 A sign = (s & 1) ? A(1) : A(-1);
