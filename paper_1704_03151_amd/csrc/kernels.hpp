@@ -1177,7 +1177,10 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
     if (ch.valid) {
         size_t nc = g.nc, ho = (size_t)vel.nk * nc;
         int nk = vel.nk;
+        // a wave of the last chunk may hold no velocity (nk mod KCH < WAVES):
+        // its slots keep a valid one for the first prefetch
         int kk[MK];
+        for (int j = 0; j < MK; ++j) kk[j] = ch.k0;
         int nmine = 0;
         for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) kk[nmine++] = k;
         A dG[MK], dH[MK];

@@ -74,6 +74,35 @@ def test_step1_flux_residual(name):
     assert np.allclose(norms, norms_ref, rtol=1e-11, atol=0)
 
 
+@pytest.mark.parametrize("nu,nv", [(13, 5), (11, 3)])
+def test_velocity_counts_leaving_waves_without_a_velocity(nu, nv):
+    """65 and 33 velocities: the last 32-velocity chunk holds one velocity, so
+    three of the four waves of its blocks hold none.  Step 1 and two whole
+    cycles against the oracle."""
+    from paper_1704_03151_amd import Solver
+    case = wl.cavity(n=8, Kn=0.3, n_levels=2, quad="gauss_hermite", nvel=nu, nvel_y=nv, vlo=0.0, vhi=0.0,
+                     mach=0.3, name=f"box8_vel{nu * nv}")
+    print(f"[parity] {case.name}: {case.nx}x{case.ny} cells, {case.n_vel} velocities", flush=True)
+    gpu, orc = Solver(case, precision="fp64"), Oracle(case)
+    prim, pert = perturbed_state(case, 9)
+    gpu.init_macro(prim)
+    orc.init_macro(prim)
+    gpu.set_f(gpu.get_f() * pert)
+    orc.set_f(*to_oracle(gpu.get_f()))
+    R, norms = gpu.residual()
+    norms_ref = orc.step1()
+    dG, dH = to_oracle(gpu.div())
+    assert rel_max(dG, orc.divG) < 1e-11 and rel_max(dH, orc.divH) < 1e-11
+    Rref = orc.R.reshape(4, case.ny, case.nx)
+    for m in range(4):
+        assert rel_max(R[m], Rref[m]) < 1e-11, (m, rel_max(R[m], Rref[m]))
+    gpu.iterate(2, tol=0.0)
+    orc.iterate(2, tol=0.0)
+    err = field_errors(gpu.macro(), orc.primitive(), orc.lev0.fluid)
+    assert max(err.values()) < 1e-10, err
+    gpu.close()
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_step2_fas_prediction(name):
     """Row a3: FAS V-cycle of the macroscopic prediction."""
