@@ -8,7 +8,8 @@ from oracle import flux as fx
 
 def small_cases():
     """Cases the oracle finishes in seconds, spanning several 64-cell tiles and
-    32-velocity chunks, with ragged tails, and every boundary tag."""
+    32-velocity chunks, with ragged tails (down to a one-velocity chunk), and
+    every boundary tag."""
     c = {}
     c["cavity16_kn10"] = wl.config1()
     c["box12x10_ragged"] = wl.cavity(n=12, ny=10, Kn=0.3, n_levels=2, quad="gauss_hermite", nvel=9, nvel_y=10,
@@ -17,6 +18,10 @@ def small_cases():
                                     precision="fp64", Kn=0.2)
     c["square20x20"] = wl.square_cylinder(scale=8, quad="trapezoid", nu=16, nv=16, vlo=-12.0, vhi=12.0,
                                           n_levels=2, precision="fp64", nu_coarse=4)
+    # 65 velocities: the last 32-velocity chunk holds one, and three of the
+    # four waves of its blocks hold none
+    c["box8_vel65"] = wl.cavity(n=8, Kn=0.3, n_levels=2, quad="gauss_hermite", nvel=13, nvel_y=5, vlo=0.0,
+                                vhi=0.0, mach=0.3, name="box8_vel65")
     return c
 
 

@@ -73,7 +73,7 @@ def test_residual_adjoint_against_dense_jacobian(which):
     gpu.close()
 
 
-@pytest.mark.parametrize("name", ["cavity16_kn10", "square20x20", "plate32x24", "box12x10_ragged"])
+@pytest.mark.parametrize("name", ["cavity16_kn10", "square20x20", "plate32x24", "box12x10_ragged", "box8_vel65"])
 def test_residual_adjoint_dot_products(name):
     case = small_cases()[name].with_(precision="fp64")
     print(f"[adjoint] {name}: dot-product test", flush=True)

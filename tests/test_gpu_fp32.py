@@ -22,7 +22,7 @@ def _solver(case):
     return Solver(case, precision="fp32f")
 
 
-@pytest.mark.parametrize("name", ["cavity16_kn10", "plate32x24", "square20x20"])
+@pytest.mark.parametrize("name", ["cavity16_kn10", "plate32x24", "square20x20", "box8_vel65"])
 def test_fp32_steps(name):
     case = small_cases()[name]
     print(f"[fp32] case {name}", flush=True)
