@@ -1163,15 +1163,25 @@ __device__ __forceinline__ void face_flux(const FaceConst<T>& F, T u, T v, T un,
 // flux arithmetic runs in double on the stored (T) distribution: R is a
 // difference of fluxes scaled by S/V, and single-precision products would
 // leave ~1e-6 of rounding noise in it; div is stored in T.
+//
+// A cell's +x face is the -x face of the next cell: every interior +x face
+// flux is handed down a lane rather than formed again (a quarter fewer face
+// evaluations).  Tiles step by tstride cells (flux_stride): 64 when rows
+// pack whole into a tile (64 mod nx = 0, so a tile's last cell ends a row);
+// otherwise 63, and lane 63 forms only the -x face flux of the next tile's
+// first cell, for lane 62.
 template <typename T>
 __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const T* __restrict__ f,
                                                   const double* __restrict__ fp,
                                                   const double* __restrict__ rho_w,
                                                   const T* __restrict__ finf, T* __restrict__ div,
-                                                  double* __restrict__ part) {
+                                                  double* __restrict__ part, int tstride) {
     typedef double A;
     __shared__ double sh[4 * WAVES * TILE];
     Chunk ch = chunk_of(g.nc, vel.nk);
+    ch.c = blockIdx.x * tstride + ch.lane;
+    ch.valid = ch.c < g.nc;
+    const bool own = ch.valid && ch.lane < tstride;
     double acc[4] = {0, 0, 0, 0};
     int c = ch.c;
     if (ch.valid) {
@@ -1189,10 +1199,10 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
         int ix = c % g.nx, iy = c / g.nx;
         if (fluid) {
             // The -x side first.  Its face is also the +x face of the cell on
-            // the left, which is the previous lane's cell whenever both lie in
-            // this tile: the face flux is formed once and handed down a lane.
-            // (An interior neighbour is a fluid cell whose face across is
-            // interior too, so the lane on the right always forms it.)
+            // the left, the previous lane's: the face flux is formed once and
+            // handed down a lane.  (An interior neighbour is a fluid cell
+            // whose face across is interior too, so the lane on the right,
+            // always present for an owned lane, forms it.)
             const A sv_x = A(1.0 / g.dx[ix]);
             const bool take1 = g.nb[g.nc + c] == c + 1 && ch.lane < TILE - 1;
             {
@@ -1260,7 +1270,7 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
                     }
                 }
             }
-            for (int s = 1; s < 4; ++s) {
+            for (int s = 1; s < 4 && own; ++s) {
                 if (s == 1 && take1) continue;
                 int code = g.nb[s * g.nc + c];
                 int d = s >> 1;
@@ -1338,7 +1348,7 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
                 }
             }
         }
-        for (int j = 0; j < nmine; ++j) {
+        for (int j = 0; j < nmine && own; ++j) {
             int k = kk[j];
             div[(size_t)k * nc + c] = T(dG[j]);
             div[ho + (size_t)k * nc + c] = T(dH[j]);
@@ -1350,8 +1360,12 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
             acc[3] += 0.5 * w * ((u * u + v * v) * gd + hd);
         }
     }
-    reduce_store<4>(acc, sh, part, g.nc, c, ch.valid);
+    reduce_store<4>(acc, sh, part, g.nc, c, own);
 }
+
+// tile stride of k_flux_div and its blocks along the cells
+inline int flux_stride(const Geo& g) { return TILE % g.nx == 0 ? TILE : TILE - 1; }
+inline int flux_tiles(const Geo& g) { return (g.nc + flux_stride(g) - 1) / flux_stride(g); }
 
 // outward flux u_n ftilde through the non-interior side s (code < 0) of a
 // fluid cell c for velocity k: at a wall the outgoing f and the incoming

@@ -394,8 +394,8 @@ struct Path {
         LAUNCH(c, "timeslope_records", (8.0 + 2 * 8) * nc8, k_face_timeslope_records, dim3(nblk(2 * g.nc)),
                dim3(256), g, c->gas, (const double*)c->msum, c->fp);
         wall_sums(c, top, F(c), c->rho_w);
-        LAUNCH(c, "flux_div", 2 * arr(c, top) + (2.0 * NFP + 4.0 * nkc) * nc8, k_flux_div<T>, dim3(nt, nkc),
-               dim3(256), g, c->vel, c->gas, F(c), c->fp, c->rho_w, (const T*)c->finf, (T*)c->div, c->part);
+        LAUNCH(c, "flux_div", 2 * arr(c, top) + (2.0 * NFP + 4.0 * nkc) * nc8, k_flux_div<T>, dim3(flux_tiles(g), nkc),
+               dim3(256), g, c->vel, c->gas, F(c), c->fp, c->rho_w, (const T*)c->finf, (T*)c->div, c->part, flux_stride(g));
         LAUNCH(c, "chunk_sum", 4.0 * (nkc + 1) * nc8, k_chunk_sum, dim3(nblk(4 * g.nc)), dim3(256),
                (const double*)c->part, nkc, 4, g.nc, -1.0, g.solid, c->R);
         LAUNCH(c, "residual_norm", 4 * nc8, k_residual_norm, dim3(1), dim3(256), g, c->hl[top].n_fluid, c->R,
