@@ -1201,8 +1201,8 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
             // The -x side first.  Its face is also the +x face of the cell on
             // the left, the previous lane's: the face flux is formed once and
             // handed down a lane.  (An interior neighbour is a fluid cell
-            // whose face across is interior too, so the lane on the right,
-            // always present for an owned lane, forms it.)
+            // whose face across is interior too, so the lane on the right
+            // forms it; with 64-cell tiles, lane 63's +x side ends a row.)
             const A sv_x = A(1.0 / g.dx[ix]);
             const bool take1 = g.nb[g.nc + c] == c + 1 && ch.lane < TILE - 1;
             {
