@@ -126,6 +126,67 @@ def time_coefficients(dt, tau):
     return q1, q2, q3, q4, q5
 
 
+class InterfaceState:
+    """Per-face quantities of the UGKS interface distribution for the faces of
+    one direction (velocity axis first where a quantity depends on k)."""
+
+
+def interface_state(G, H, W, lev, vel, gas, d, sG=None, sH=None):
+    """Interface states of the interior faces of direction d (0: x, 1: y),
+    normal from L to R: the reconstructed values and limited slopes on both
+    sides, the upwind pair, the interface equilibrium (moments W0, heat flux
+    q0, collision time tau0, Maxwellian g0 and Shakhov g0+), the
+    micro-slopes of both sides and the time slope, as the flux uses them."""
+    if sG is None:
+        sG, sH = slopes(G, lev), slopes(H, lev)
+    K, Ki = gas.K, gas.K_int
+    u = vel.u[:, None]
+    v = vel.v[:, None]
+    st = InterfaceState()
+    m = lev.fdir == d
+    st.mask = m
+    L, R = lev.fL[m], lev.fR[m]
+    dL, dR, dt = lev.fdL[m], lev.fdR[m], lev.fdt[m]
+    st.L, st.R, st.dL, st.dR, st.dt = L, R, dL, dR, dt
+    un = u if d == 0 else v
+    st.un = un
+    pos, neg = un > 0, un < 0
+
+    def upwind(a, b):
+        return np.where(pos, a, np.where(neg, b, 0.5 * (a + b)))
+
+    st.GL = G[:, L] + sG[d][:, L] * dL
+    st.GR = G[:, R] - sG[d][:, R] * dR
+    st.HL = H[:, L] + sH[d][:, L] * dL
+    st.HR = H[:, R] - sH[d][:, R] * dR
+    st.sGL, st.sGR, st.sHL, st.sHR = sG[d][:, L], sG[d][:, R], sH[d][:, L], sH[d][:, R]
+    st.Gup, st.Hup = upwind(st.GL, st.GR), upwind(st.HL, st.HR)
+    st.sGup, st.sHup = upwind(st.sGL, st.sGR), upwind(st.sHL, st.sHR)
+
+    # interface equilibrium from the discrete moments of the upwind distribution
+    st.W0 = gm.moments(st.Gup, st.Hup, vel)
+    rho0, U0, V0, lam0 = gm.primitive(st.W0, K)
+    st.prim0 = (rho0, U0, V0, lam0)
+    st.q0 = gm.heat_flux(st.Gup, st.Hup, vel, U0, V0)
+    st.tau0 = gas.tau(rho0, lam0)
+    st.G0, st.H0 = gm.maxwellian(rho0, U0, V0, lam0, u, v, Ki)
+    st.Geq, st.Heq = gm.shakhov(rho0, U0, V0, lam0, st.q0[0], st.q0[1], u, v, Ki, gas.Pr)
+
+    # spatial micro-slopes from the macroscopic slopes on each side
+    st.aL = micro_slope((st.W0 - W[:, L]) / dL / rho0, U0, V0, lam0, K)
+    st.aR = micro_slope((W[:, R] - st.W0) / dR / rho0, U0, V0, lam0, K)
+    st.GaL, st.HaL = slope_times_g0(st.aL, st.G0, st.H0, u, v, lam0, Ki)
+    st.GaR, st.HaR = slope_times_g0(st.aR, st.G0, st.H0, u, v, lam0, Ki)
+    st.Gs, st.Hs = upwind(st.GaL, st.GaR), upwind(st.HaL, st.HaR)
+
+    # time slope from the compatibility condition, in discrete form
+    b = -gm.moments(un * st.Gs, un * st.Hs, vel) / rho0
+    st.A = micro_slope(b, U0, V0, lam0, K)
+    st.GA, st.HA = slope_times_g0(st.A, st.G0, st.H0, u, v, lam0, Ki)
+    st.q = time_coefficients(dt, st.tau0)
+    return st
+
+
 def interior_fluxes(G, H, W, lev, vel, gas):
     """Time-averaged flux (Nk, nfaces) of G and H through every interior face,
     normal pointing from L to R."""
@@ -133,51 +194,14 @@ def interior_fluxes(G, H, W, lev, vel, gas):
     nf = len(lev.fL)
     PhiG = np.zeros((vel.n, nf), dtype=G.dtype)
     PhiH = np.zeros((vel.n, nf), dtype=G.dtype)
-    K, Ki = gas.K, gas.K_int
-    u = vel.u[:, None]
-    v = vel.v[:, None]
     for d in (0, 1):
-        m = lev.fdir == d
-        if not m.any():
+        if not (lev.fdir == d).any():
             continue
-        L, R = lev.fL[m], lev.fR[m]
-        dL, dR, dt = lev.fdL[m], lev.fdR[m], lev.fdt[m]
-        un = u if d == 0 else v
-        pos, neg = un > 0, un < 0
-
-        def upwind(a, b):
-            return np.where(pos, a, np.where(neg, b, 0.5 * (a + b)))
-
-        GL = G[:, L] + sG[d][:, L] * dL
-        GR = G[:, R] - sG[d][:, R] * dR
-        HL = H[:, L] + sH[d][:, L] * dL
-        HR = H[:, R] - sH[d][:, R] * dR
-        Gup, Hup = upwind(GL, GR), upwind(HL, HR)
-        sGup, sHup = upwind(sG[d][:, L], sG[d][:, R]), upwind(sH[d][:, L], sH[d][:, R])
-
-        # interface equilibrium from the discrete moments of the upwind distribution
-        W0 = gm.moments(Gup, Hup, vel)
-        rho0, U0, V0, lam0 = gm.primitive(W0, K)
-        q0 = gm.heat_flux(Gup, Hup, vel, U0, V0)
-        tau0 = gas.tau(rho0, lam0)
-        G0, H0 = gm.maxwellian(rho0, U0, V0, lam0, u, v, Ki)
-        Geq, Heq = gm.shakhov(rho0, U0, V0, lam0, q0[0], q0[1], u, v, Ki, gas.Pr)
-
-        # spatial micro-slopes from the macroscopic slopes on each side
-        aL = micro_slope((W0 - W[:, L]) / dL / rho0, U0, V0, lam0, K)
-        aR = micro_slope((W[:, R] - W0) / dR / rho0, U0, V0, lam0, K)
-        GaL, HaL = slope_times_g0(aL, G0, H0, u, v, lam0, Ki)
-        GaR, HaR = slope_times_g0(aR, G0, H0, u, v, lam0, Ki)
-        Gs, Hs = upwind(GaL, GaR), upwind(HaL, HaR)
-
-        # time slope from the compatibility condition, in discrete form
-        b = -gm.moments(un * Gs, un * Hs, vel) / rho0
-        A = micro_slope(b, U0, V0, lam0, K)
-        GA, HA = slope_times_g0(A, G0, H0, u, v, lam0, Ki)
-
-        q1, q2, q3, q4, q5 = time_coefficients(dt, tau0)
-        PhiG[:, m] = un * (q1 * Geq + q2 * un * Gs + q3 * GA + q4 * Gup + q5 * un * sGup) / dt
-        PhiH[:, m] = un * (q1 * Heq + q2 * un * Hs + q3 * HA + q4 * Hup + q5 * un * sHup) / dt
+        st = interface_state(G, H, W, lev, vel, gas, d, sG, sH)
+        m, un, dt = st.mask, st.un, st.dt
+        q1, q2, q3, q4, q5 = st.q
+        PhiG[:, m] = un * (q1 * st.Geq + q2 * un * st.Gs + q3 * st.GA + q4 * st.Gup + q5 * un * st.sGup) / dt
+        PhiH[:, m] = un * (q1 * st.Heq + q2 * un * st.Hs + q3 * st.HA + q4 * st.Hup + q5 * un * st.sHup) / dt
     return PhiG, PhiH
 
 
