@@ -1,20 +1,25 @@
 """Benchmark of the MIUGKS hot path on one MI355X.
 
-Workload: lid-driven cavity, 64x64 tanh-clustered cells (first cell 0.005),
-28x28 Gauss-Hermite velocities, Kn 0.075, lid Mach 0.16, 4-level V-cycles,
-FP32 distribution with FP64 moments / macroscopic prediction / norms.  A step
-is one outer MIUGKS cycle (Steps 1-8: UGKS flux and residuals, FAS
-prediction, micro residual, CS correction, update and moments).  The input
-is synthetic (no dataset); every array lives in HBM before timing starts.
+Workload (default): Mach-5 argon past a square cylinder, 160x160 stretched
+cells (24 576 fluid), 100x100 trapezoid velocities on [-15, 15]^2, Kn 0.1,
+5-level V-cycles (FAS prediction on the two finest), pseudo step 3^n dt_p
+capped at 300 dt_p, FP32 distribution with FP64 moments / macroscopic
+prediction / norms.  A step is one outer MIUGKS cycle (Steps 1-8: UGKS flux
+and residuals, FAS prediction, micro residual, CS correction, update and
+moments).  The input is synthetic (no dataset); every array lives in HBM
+before timing starts.
 
 Prints one JSON line:
   value      cell-velocity updates per second per MG cycle
              (fluid cells x velocities / seconds per cycle)
   roofline   dominant kernel: algorithmic bytes per launch / mean launch time
-             (HIP events on the library's stream) against 8 TB/s
+             (HIP events on the library's stream) against 8 TB/s; the flux
+             and smoother kernels under roofline_kernels
   cpu_baseline  the FP64 CPU oracle timed on this host on a bounded sample
-plus the wall time and cycle count to an RMS residual of 1e-6 for the
-FP32-f form and the FP64 form.
+plus the other precision form's cycle time, and the wall time and cycle
+count to an RMS residual of 1e-6 for the FP32-f and FP64 forms (and, where
+the FP32-f form stalls at the resolution of its storage, FP32-f cycles
+followed by FP64 cycles from their state).
 """
 from __future__ import annotations
 
@@ -50,23 +55,50 @@ RECIPES = {
 }
 
 
-def cpu_baseline(case, cycles):
-    """The oracle (numpy FP64) on the same case: setup untimed, then `cycles`
-    full outer cycles timed, single thread."""
+def host_cpu():
+    """(model string, logical CPUs) of this host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(case, cycles, nvel=None):
+    """The oracle (numpy FP64) on a bounded sample of the same case: the same
+    mesh, levels, boundaries and flow, with the velocity grid cut to nvel x
+    nvel nodes on the same range when it is larger (the oracle's work per
+    cycle is proportional to the number of velocities, so the rate per
+    cell-velocity update carries over); setup untimed, then `cycles` full
+    outer cycles timed on one thread."""
     from threadpoolctl import threadpool_limits
 
     from oracle.solver import Oracle
+    sample = case.with_(precision="fp64")
+    cut = nvel is not None and case.nu * case.nv > nvel * nvel
+    if cut:
+        sample = sample.with_(nu=nvel, nv=nvel)
     with threadpool_limits(limits=1):
-        o = Oracle(case.with_(precision="fp64"))
+        o = Oracle(sample)
         t0 = time.perf_counter()
         for _ in range(cycles):
             o.step1()
             o.advance()
         dt = (time.perf_counter() - t0) / cycles
-    return {"value": case.n_fluid * case.n_vel / dt, "unit": "cell*velocity updates/s", "cores": 1,
+    model, ncpu = host_cpu()
+    what = (f"the same {case.nx}x{case.ny} mesh and {case.n_levels}-level cycle with {sample.nu}x{sample.nv} of "
+            f"the {case.nu}x{case.nv} velocity nodes (same range)" if cut else
+            f"the same {case.nx}x{case.ny}x{case.n_vel} case")
+    return {"value": sample.n_fluid * sample.n_vel / dt, "unit": "cell*velocity updates/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"{cycles} full outer cycle(s) of the same {case.nx}x{case.ny}x{case.n_vel} cavity, "
-                      f"numpy FP64 oracle, one thread, {dt:.2f} s per cycle"}
+            "sample": f"{cycles} full outer cycle(s) of {what}, numpy FP64 oracle, one thread, "
+                      f"{dt:.2f} s per cycle",
+            "host_cpu": model, "host_logical_cpus": ncpu}
 
 
 def explicit_bench(args, case, solver, pts):
@@ -155,13 +187,76 @@ def adjoint_bench(args, case, solver):
     print(json.dumps(line), flush=True)
 
 
+def kernel_roofline(stats, kernel):
+    """Roofline entry of one kernel (all its labels kernel or kernel/level):
+    algorithmic bytes per launch over the mean HIP-event launch time."""
+    n_l, ms, by = 0, 0.0, 0.0
+    for k, (a, b, c) in stats.items():
+        if k == kernel or k.startswith(kernel + "/"):
+            n_l, ms, by = n_l + a, ms + b, by + c
+    if n_l == 0 or ms <= 0:
+        return None
+    achieved = by / n_l / (ms / n_l * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "launches": n_l, "bytes_per_launch": by / n_l,
+            "mean_launch_ms": ms / n_l}
+
+
+def time_cycles(solver, steps, warmup):
+    """Seconds per outer cycle over `steps` cycles after `warmup` (tol 0: every
+    cycle runs)."""
+    import torch
+    solver.iterate(warmup, tol=0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, n, res = solver.iterate(steps, tol=0.0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if n != steps:
+        sys.exit(f"bench: the timed cycles stopped after {n} of {steps} (status {rc}: "
+                 f"{'diverged' if rc == 4 else 'error'}); residuals {res}")
+    return (t1 - t0) / steps
+
+
+def to_tolerance(case, solver, prec, tol=1e-6, max_cycles=600, chunk=10):
+    """Wall time and cycles from the initial state to every RMS residual below
+    tol.  Runs in chunks of `chunk` cycles (one host check per chunk) and
+    stops early when the residual stalls: no halving over 40 cycles once
+    below 1e-3 (the FP32-f form meets the resolution of its storage there).
+    Returns the record and the solver left at the last state."""
+    import numpy as np
+    import torch
+    solver.init_macro(case.init)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, hist, rc, res = 0, [], 5, None
+    while done < max_cycles:
+        rc, n, res = solver.iterate(chunk, tol=tol)
+        done += n
+        hist.append(float(np.max(res)))
+        if rc != 5:
+            break
+        if len(hist) > 4 and hist[-1] < 1e-3 and hist[-1] > 0.5 * hist[-5]:
+            rc = "stalled"
+            break
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rec = {"converged": rc == 0, "cycles": done, "wall_s": wall, "final_residual": [float(x) for x in res]}
+    if rc == "stalled":
+        rec["stalled_at"] = float(np.max(res))
+    print(f"[bench] {prec}: {'residual 1e-6' if rc == 0 else 'stopped'} after {done} cycles, {wall:.3f} s, "
+          f"max residual {np.max(res):.2e}", file=sys.stderr, flush=True)
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32f", choices=["fp32f", "fp64"])
-    ap.add_argument("--config", type=int, default=2, help="workload recipe (2 = the headline cavity)")
+    ap.add_argument("--config", type=int, default=4,
+                    help="workload recipe (4 = the Mach-5 square cylinder, the largest one-GPU case)")
     ap.add_argument("--explicit", action="store_true",
                     help="time explicit time-accurate UGKS steps instead of MG cycles (the interface flux, the "
                          "collision update and the moments, once per step)")
@@ -171,6 +266,8 @@ def main():
     ap.add_argument("--dtn-growth", type=float, default=None,
                     help="override the workload's pseudo-step growth a (dt_n = a^n dt_p; 0: off)")
     ap.add_argument("--cpu-cycles", type=int, default=1)
+    ap.add_argument("--cpu-velocities", type=int, default=16,
+                    help="velocity nodes per axis of the oracle's sample (the case's own grid when smaller)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true", help="skip the time-to-1e-6 runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -182,6 +279,7 @@ def main():
               "(the design notes describe how it would shard over velocities).", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     import workloads as wl
@@ -205,16 +303,7 @@ def main():
     if args.adjoint:
         return adjoint_bench(args, case, solver)
     # warm-up, then exactly K timed cycles
-    solver.iterate(args.warmup, tol=0.0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rc, n, res = solver.iterate(args.steps, tol=0.0)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    if n != args.steps:
-        sys.exit(f"bench: the timed cycles stopped after {n} of {args.steps} (status {rc}: "
-                 f"{'diverged' if rc == 4 else 'error'}); residuals {res}")
-    sec = (t1 - t0) / args.steps
+    sec = time_cycles(solver, args.steps, args.warmup)
     value = pts / sec
     print(f"[bench] {args.steps} cycles: {sec * 1e3:.3f} ms/cycle", file=sys.stderr, flush=True)
 
@@ -233,35 +322,56 @@ def main():
         a[1] += ms_l
         a[2] += by_l
     dom = max(per_kernel, key=lambda k: per_kernel[k][1])
-    launches, ms, by = per_kernel[dom]
-    achieved = by / launches / (ms / launches * 1e-3) / 1e9
-    cycle_bytes = sum(v[2] for v in stats.values()) / args.steps
-    kernels = {k: {"launches": v[0], "ms_per_cycle": v[1] / args.steps,
-                   "gbs": (v[2] / (v[1] * 1e-3) / 1e9 if v[1] > 0 else None)}
-               for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
+    roofline = kernel_roofline(stats, dom)
     traffic = MEASURED_TRAFFIC.get((case.name, args.precision, dom))
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "bytes_per_launch": by / launches, "mean_launch_ms": ms / launches,
-                "traffic_over_algorithmic": (traffic / (by / launches)) if traffic else None}
-    print(f"[bench] dominant kernel {dom}: {ms / launches * 1e3:.1f} us/launch, {achieved:.0f} GB/s",
-          file=sys.stderr, flush=True)
+    roofline["traffic"] = traffic
+    roofline["traffic_over_algorithmic"] = (traffic / roofline["bytes_per_launch"]) if traffic else None
+    print(f"[bench] dominant kernel {dom}: {roofline['mean_launch_ms'] * 1e3:.1f} us/launch, "
+          f"{roofline['achieved']:.0f} GB/s", file=sys.stderr, flush=True)
+    # the flux and the smoother, each against the HBM roofline (and the
+    # smoother's finest level alone)
+    others = {}
+    for kname in ("flux_div", "sweep", "sweep/l0"):
+        r = kernel_roofline(stats, kname) if "/" not in kname else (
+            None if kname not in stats else kernel_roofline({kname: stats[kname]}, kname))
+        if r is not None:
+            t = MEASURED_TRAFFIC.get((case.name, args.precision, kname))
+            r["traffic"] = t
+            others[kname] = r
+    cycle_bytes = sum(v[2] for v in stats.values()) / args.steps
+    kernels = {k: {"launches": v[0], "ms_per_cycle": v[1] / args.steps}
+               for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
+
+    # the other precision form's cycle time on the same workload
+    other_prec = "fp64" if args.precision != "fp64" else "fp32f"
+    s_other = Solver(case, precision=other_prec)
+    sec_other = time_cycles(s_other, args.steps, args.warmup)
+    print(f"[bench] {other_prec}: {sec_other * 1e3:.3f} ms/cycle", file=sys.stderr, flush=True)
 
     extra = {}
     if not args.no_converge:
-        for prec in (args.precision, "fp64" if args.precision != "fp64" else None):
-            if prec is None:
-                continue
-            s = solver if prec == args.precision else Solver(case, precision=prec)
-            s.init_macro(case.init)
-            torch.cuda.synchronize()
+        solvers = {args.precision: solver, other_prec: s_other}
+        s32, s64 = solvers["fp32f"], solvers["fp64"]
+        extra["fp32f"] = to_tolerance(case, s32, "fp32f")
+        # where the FP32-f form stalls at the resolution of FP32 storage: FP64
+        # cycles from the state it reached (the distribution converted on the
+        # device), the wall time counted from the initial state
+        if not extra["fp32f"]["converged"]:
             t0 = time.perf_counter()
-            rc, cyc, res = s.iterate(1000, tol=1e-6)
+            f64 = torch.empty(s64.fshape, dtype=torch.float64, device="cuda")
+            s32.get_f(out=f64)
+            s64.set_f(f64)
+            del f64
+            rc, n64, res = s64.iterate(600, tol=1e-6)
             torch.cuda.synchronize()
-            wall = time.perf_counter() - t0
-            extra[prec] = {"converged": rc == 0, "cycles": cyc, "wall_s": wall,
-                           "final_residual": [float(x) for x in res]}
-            print(f"[bench] {prec}: residual 1e-6 after {cyc} cycles, {wall:.3f} s", file=sys.stderr, flush=True)
+            wall = extra["fp32f"]["wall_s"] + time.perf_counter() - t0
+            extra["fp32f_then_fp64"] = {"converged": rc == 0, "cycles_fp32f": extra["fp32f"]["cycles"],
+                                        "cycles_fp64": n64, "wall_s": wall,
+                                        "final_residual": [float(x) for x in res]}
+            print(f"[bench] fp32f then fp64: {extra['fp32f']['cycles']} + {n64} cycles, {wall:.3f} s",
+                  file=sys.stderr, flush=True)
+        extra["fp64"] = to_tolerance(case, s64, "fp64")
+    s_other.close()
 
     line = {
         "metric": METRIC,
@@ -282,6 +392,9 @@ def main():
                    "cells": case.n_cells, "fluid_cells": case.n_fluid, "velocities": case.n_vel,
                    "levels": case.n_levels, "precision": args.precision},
         "roofline": roofline,
+        "roofline_kernels": others,
+        f"{other_prec}_ms_per_step": sec_other * 1e3,
+        f"{other_prec}_value": pts / sec_other,
         "cycle_algorithmic_gbs": cycle_bytes / (total_ms / args.steps * 1e-3) / 1e9,
         "kernel_ms_per_cycle": {k: v["ms_per_cycle"] for k, v in kernels.items()},
         "kernel_us_per_launch": {k: 1e3 * v[1] / v[0] for k, v in
@@ -297,8 +410,9 @@ def main():
         torch.cuda.synchronize()
         line["copy_calibration_bytes"] = n * 4
         del src, dst
+    solver.close()
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(case, args.cpu_cycles)
+        line["cpu_baseline"] = cpu_baseline(case, args.cpu_cycles, args.cpu_velocities)
     print(json.dumps(line), flush=True)
 
 

@@ -127,7 +127,10 @@ typedef struct {
  * coarsest level (0: nu_coarse, which then counts for both cycles);
  * cycle_gamma: coarse-grid corrections per visit of a level in the FAS
  * cycle, 1 (or 0) for V-cycles, 2 for W-cycles, at most 3, or MIUGKS_CYCLE_F
- * for F-cycles; cycle_gamma_cs: the same for the CS cycle (0: cycle_gamma). */
+ * for F-cycles; cycle_gamma_cs: the same for the CS cycle (0: cycle_gamma);
+ * dtn_max: cap of the pseudo-step growth, dt_n = min(a^n, dtn_max) dt_p
+ * (0: no cap; only read when dtn_growth > 0; the pseudo step leaves the fixed
+ * point unchanged, the cap keeps its damping once a^n is large). */
 typedef struct {
     int precision;
     int nu1, nu2, nu_coarse;
@@ -138,6 +141,7 @@ typedef struct {
     int nu_coarse_cs;
     int cycle_gamma;
     int cycle_gamma_cs;
+    double dtn_max;
 } miugks_solver_desc;
 
 /* Nodes and weights of a 1-D rule on [lo, hi] (ignored for Gauss-Hermite,
@@ -167,8 +171,13 @@ void miugks_destroy(miugks_ctx* ctx);
 /* Text of the last error on ctx (NULL ctx: last creation error). */
 const char* miugks_last_error(const miugks_ctx* ctx);
 
-/* f := cell Maxwellian of host fields rho, U, V, T [ny][nx] (solid cells: 0);
- * resets the cycle counter and the reference mass. */
+/* Initial state of the outer iteration (Sec. IV: the cavity starts at rest,
+ * the plate and the square from the freestream, the square with the region
+ * behind it at a tenth of the freestream density and at rest): f := the
+ * reduced Maxwellian pair (G, H) of the host fields rho, U, V, T [ny][nx]
+ * (Sec. II A equilibrium; solid cells: 0).  Resets the cycle counter (the
+ * pseudo step of Sec. III D restarts) and the reference mass of a closed
+ * domain.  MIUGKS_EINVAL for a NULL field. */
 int miugks_init_macro(miugks_ctx* ctx, const double* rho, const double* U, const double* V,
                       const double* T);
 
@@ -207,15 +216,25 @@ int miugks_fmg(miugks_ctx* ctx, int cycles_per_level, double tol, int* cycles_do
  * Synchronises the stream. */
 int miugks_explicit(miugks_ctx* ctx, int steps, double* dt, double res[4]);
 
-/* Host outputs [ny][nx] (each may be NULL): primitive fields and heat flux of
- * the current distribution. */
+/* Macroscopic fields of the current distribution (Sec. II A: the
+ * conservative variables W are the velocity moments of f; Sec. IV reports the
+ * flow fields as density, velocity and temperature): rho, U, V and
+ * T = 4 (rho eps - rho |U|^2 / 2) / (K rho) per cell, and the heat flux
+ * qx, qy of the Shakhov model (the moment that enters its equilibrium).
+ * Host outputs [ny][nx], caller-owned, each may be NULL; solid cells give 0.
+ * Synchronises the stream. */
 int miugks_get_macro(miugks_ctx* ctx, double* rho, double* U, double* V, double* T, double* qx,
                      double* qy);
 
-/* Copy the distribution [2][Nk][ny][nx] out of / into the context.  dtype is
- * MIUGKS_FP64 (double) or MIUGKS_FP32F (float); it is converted as needed.
- * on_device = 1: dst/src is a device pointer on the context's device.
- * set_f recomputes the moments; it is the checkpoint/restore path. */
+/* Copy the discrete distribution (Sec. II A: f at every cell and discrete
+ * velocity, here the reduced pair of Sec. III B) out of / into the context,
+ * layout [2][Nk][ny][nx].  dtype is MIUGKS_FP64 (double) or MIUGKS_FP32F
+ * (float); it is converted as needed.  on_device = 1: dst/src is a device
+ * pointer on the context's device; 0: a host pointer (the library stages it
+ * through a device buffer it allocates for the call).  The caller owns dst /
+ * src.  set_f recomputes the moments; together they are the
+ * checkpoint/restore path.  MIUGKS_EINVAL for a bad dtype or a NULL
+ * pointer.  Synchronise the stream. */
 int miugks_get_f(miugks_ctx* ctx, void* dst, int dtype, int on_device);
 int miugks_set_f(miugks_ctx* ctx, const void* src, int dtype, int on_device);
 
@@ -239,10 +258,13 @@ int miugks_wall_list(miugks_ctx* ctx, int* cell, int* side, int* n_walls);
  * all NULL: only n_walls is set).  Synchronises the stream. */
 int miugks_wall_loads(miugks_ctx* ctx, double* p, double* tau, double* q, double* S, int* n_walls);
 
-/* J = sum over the listed wall sides (indices of miugks_wall_list) of S times
- * the load kind (MIUGKS_LOAD_PRESSURE, _SHEAR or _HEAT); the lid shear of a
- * cavity or the drag of a plate (both of its sides).  MIUGKS_EINVAL for a bad
- * kind or index. */
+/* Integrated wall load (Sec. IV B: the skin friction and drag of the plate
+ * are the momentum the gas hands to the wall, integrated over it):
+ * J = sum over the listed wall sides (indices of miugks_wall_list) of S times
+ * the load kind (MIUGKS_LOAD_PRESSURE, _SHEAR or _HEAT) of miugks_wall_loads;
+ * the lid shear of a cavity or the drag of a plate (both of its sides).
+ * walls is a host array of n indices; *J (host) out.  MIUGKS_EINVAL for a
+ * bad kind or index.  Synchronises the stream. */
 int miugks_objective(miugks_ctx* ctx, int kind, const int* walls, int n, double* J);
 
 /* Set the temperature of n wall faces of the mesh (Sec. III B, wall

@@ -96,6 +96,9 @@ class Oracle:
         if a <= 0:
             return [np.zeros(lev.nc) for lev in self.levels]
         f = float(a) ** (-self.cycle)
+        cap = getattr(self.case, "dtn_max", 0.0)
+        if cap > 0:
+            f = max(f, 1.0 / cap)
         return [f / lev.dt for lev in self.levels]
 
     # ---------------------------------------------------------------- steps

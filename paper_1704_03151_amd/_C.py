@@ -48,7 +48,7 @@ class SolverDesc(ctypes.Structure):
                 ("nu_coarse", ctypes.c_int), ("cfl", ctypes.c_double),
                 ("dtn_growth", ctypes.c_double), ("mass_renorm", ctypes.c_int), ("fas_levels", ctypes.c_int),
                 ("nu_coarse_cs", ctypes.c_int), ("cycle_gamma", ctypes.c_int),
-                ("cycle_gamma_cs", ctypes.c_int)]
+                ("cycle_gamma_cs", ctypes.c_int), ("dtn_max", ctypes.c_double)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)

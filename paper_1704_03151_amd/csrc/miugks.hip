@@ -61,6 +61,7 @@ struct miugks_ctx {
     // whose stages treat a coarse level as the finest (f then holds that level)
     int top = 0;
     double dtn_growth = 0.0;
+    double dtn_max = 0.0;   // cap of a^n (0: none)
     double cfl = 0.5;
     bool renorm = false;
     // symmetry faces present: the cycles take the general CS path, whose
@@ -702,7 +703,9 @@ void fas(miugks_ctx* c, int l, int gamma) {
 // (outside any graph), the dtn kernels scale it by each level's 1/dt_p
 void set_dtn_factor(miugks_ctx* c) {
     if (!(c->dtn_growth > 0.0)) return;
-    c->h_factor[0] = std::pow(c->dtn_growth, -(double)c->cycle);
+    double f = std::pow(c->dtn_growth, -(double)c->cycle);
+    if (c->dtn_max > 0.0) f = std::fmax(f, 1.0 / c->dtn_max);
+    c->h_factor[0] = f;
     (void)hipMemcpyAsync(c->d_factor, c->h_factor, sizeof(double), hipMemcpyHostToDevice, c->stream);
 }
 
@@ -1550,7 +1553,7 @@ int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgri
     if (v->nu < 1 || v->nv < 1 || !v->u || !v->v || !v->wu || !v->wv || s->nu1 < 0 || s->nu2 < 0 ||
         s->nu_coarse < 1 || s->nu_coarse_cs < 0 || s->fas_levels < 0 || s->cycle_gamma < MIUGKS_CYCLE_F ||
         s->cycle_gamma > 3 || s->cycle_gamma_cs < MIUGKS_CYCLE_F || s->cycle_gamma_cs > 3 ||
-        !(s->cfl > 0) || g->K_int < 0 || !(g->Kn > 0) || !(g->T_inf > 0)) {
+        !(s->cfl > 0) || !(s->dtn_max >= 0) || g->K_int < 0 || !(g->Kn > 0) || !(g->T_inf > 0)) {
         g_create_error = "bad velocity grid, gas or solver description";
         delete ctx;
         return MIUGKS_EINVAL;
@@ -1574,6 +1577,7 @@ int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgri
     ctx->gamma = s->cycle_gamma != 0 ? s->cycle_gamma : 1;
     ctx->gamma_cs = s->cycle_gamma_cs != 0 ? s->cycle_gamma_cs : ctx->gamma;
     ctx->dtn_growth = s->dtn_growth;
+    ctx->dtn_max = s->dtn_max;
     ctx->cfl = s->cfl;
     HostVel& hv = ctx->hv;
     hv.nu = v->nu;

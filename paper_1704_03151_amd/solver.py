@@ -79,7 +79,8 @@ class Solver:
         gas = _C.GasDesc(case.K_int, case.Pr, case.omega, case.Kn, rho, U, V, T)
         sd = _C.SolverDesc(prec, case.nu1, case.nu2, case.nu_coarse, case.cfl, case.dtn_growth,
                            mass_renorm, getattr(case, "fas_levels", 0), getattr(case, "nu_coarse_cs", 0),
-                           getattr(case, "cycle_gamma", 1), getattr(case, "cycle_gamma_cs", 0))
+                           getattr(case, "cycle_gamma", 1), getattr(case, "cycle_gamma_cs", 0),
+                           getattr(case, "dtn_max", 0.0))
         h = ctypes.c_void_p()
         rc = _C.lib.miugks_create(ctypes.byref(h), ctypes.byref(mesh), ctypes.byref(vg),
                                   ctypes.byref(gas), ctypes.byref(sd), ctypes.c_void_p(_stream_handle(stream)))
@@ -153,7 +154,22 @@ class Solver:
         self._check(_C.lib.miugks_get_macro(self.h, *(_C.dptr(out[k]) for k in ("rho", "U", "V", "T", "qx", "qy"))))
         return out
 
-    def get_f(self, dtype=None):
+    def _device_f(self, t):
+        """(pointer, dtype code) of a contiguous torch tensor on the GPU shaped like f."""
+        import torch
+        if t.dtype not in (torch.float32, torch.float64) or tuple(t.shape) != self.fshape:
+            raise ValueError(f"f must be float32/float64 shaped {self.fshape}")
+        if not (t.is_cuda and t.is_contiguous()):
+            raise ValueError("a device f must be a contiguous tensor on the GPU")
+        return ctypes.c_void_p(t.data_ptr()), (_C.FP64 if t.dtype == torch.float64 else _C.FP32F)
+
+    def get_f(self, dtype=None, out=None):
+        """The distribution [2][Nk][ny][nx] as a host array of dtype, or into
+        `out`, a torch tensor on the GPU (converted there by the library)."""
+        if out is not None and not isinstance(out, np.ndarray):
+            ptr, code = self._device_f(out)
+            self._check(_C.lib.miugks_get_f(self.h, ptr, code, 1))
+            return out
         dt = np.dtype(dtype or self.dtype)
         out = np.zeros(self.fshape, dt)
         code = _C.FP64 if dt == np.float64 else _C.FP32F
@@ -161,6 +177,11 @@ class Solver:
         return out
 
     def set_f(self, f):
+        """Set the distribution from a host array or a torch tensor on the GPU."""
+        if not isinstance(f, np.ndarray) and hasattr(f, "data_ptr"):
+            ptr, code = self._device_f(f)
+            self._check(_C.lib.miugks_set_f(self.h, ptr, code, 1))
+            return
         a = np.ascontiguousarray(f)
         code = _C.FP64 if a.dtype == np.float64 else _C.FP32F
         if a.dtype not in (np.float64, np.float32) or a.shape != self.fshape:

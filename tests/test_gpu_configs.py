@@ -1,0 +1,148 @@
+"""The workloads' own meshes against the oracle: the square cylinder's full
+160x160 mesh with all five levels (160-row level, three row slots per lane,
+solid body, farfield and outflow sides, the capped pseudo step) on a small
+velocity grid; the bench cavity in FP64 at its full size; the plate's
+steady state against the oracle's FP64 steady state (tests/golden); the
+capped pseudo step against the oracle.  Tolerances as elsewhere: FP64 1e-11
+per step and 1e-10 on fields after cycles, FP32-f 2e-5 per step and 1e-5 on
+fields."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from _parity import field_errors, perturbed_state, rel_max, to_oracle
+from oracle.cs import cs_cycle
+from oracle.solver import Oracle
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _square_small_velocities():
+    """config 4's mesh, levels, boundaries, flow and cycle with 6x6 trapezoid
+    velocities on [-10, 10]^2 (so that the oracle finishes in seconds)."""
+    return wl.config4(nu=6, nv=6, vlo=-10.0, vhi=10.0, precision="fp64")
+
+
+@pytest.fixture(scope="module")
+def square_oracle():
+    """The oracle's Step 1 of a perturbed state, one CS cycle on seeded input,
+    and two outer cycles from the recipe's initial state."""
+    case = _square_small_velocities()
+    orc = Oracle(case)
+    prim, pert = perturbed_state(case, 61)
+    orc.init_macro(prim)
+    orc.set_f(orc.G * pert[0].reshape(orc.G.shape), orc.H * pert[1].reshape(orc.H.shape))
+    G1, H1 = orc.G.copy(), orc.H.copy()
+    orc.step1()
+    step1 = (G1, H1, orc.divG.copy(), orc.divH.copy(), orc.R.copy())
+    fl = orc.lev0.fluid
+    r = wl.random_field((2, case.n_vel, case.ny, case.nx), seed=67) * fl.reshape(case.ny, case.nx)
+    ti = wl.random_field((case.ny, case.nx), seed=69, lo=0.5, hi=3.0)
+    orc.cycle = 0
+    rG, rH = to_oracle(r)
+    cs = (r, ti) + cs_cycle(orc.cs_levels, orc.levels, orc.prolongs, 0, rG, rH,
+                            orc.level_tau_inv(ti.ravel() * fl), orc.dtn_inv(), orc.cs_params)
+    orc.init_macro(case.init)
+    orc.cycle = 0
+    orc.history = []
+    orc.iterate(2, tol=0.0)
+    return case, step1, cs, orc.primitive(), fl, (orc.G.copy(), orc.H.copy())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32f"])
+def test_square_full_mesh_against_oracle(square_oracle, prec):
+    from paper_1704_03151_amd import Solver
+    case, (G1, H1, dG1, dH1, R1), (r, ti, cG, cH), prim2, fl, (G2, H2) = square_oracle
+    step_tol, field_tol = (1e-11, 1e-10) if prec == "fp64" else (2e-5, 1e-5)
+    print(f"[configs] square160x160 x 36 velocities, 5 levels, {prec}", flush=True)
+    gpu = Solver(case, precision=prec)
+    # Step 1 of the oracle's distribution (rounded to float in FP32-f: the
+    # oracle's own input is then not the GPU's, which the tolerance covers)
+    f = np.stack([G1.reshape(-1, case.ny, case.nx), H1.reshape(-1, case.ny, case.nx)])
+    gpu.set_f(f.astype(gpu.dtype))
+    R, _ = gpu.residual()
+    dG, dH = to_oracle(gpu.div(np.float64))
+    eG, eH = rel_max(dG, dG1), rel_max(dH, dH1)
+    eR = max(rel_max(R[m], R1[m].reshape(case.ny, case.nx)) for m in range(4))
+    print(f"[configs] step 1: div {eG:.2e} {eH:.2e}, R {eR:.2e}", flush=True)
+    assert eG < step_tol and eH < step_tol and eR < step_tol, (eG, eH, eR)
+    # one CS V-cycle (five levels, the 160-row level's ordered sweep)
+    gpu.init_macro(case.init)
+    out = gpu.correct(r.astype(gpu.dtype), ti)
+    gG, gH = to_oracle(out)
+    eG, eH = rel_max(gG, cG), rel_max(gH, cH)
+    print(f"[configs] CS cycle: {eG:.2e} {eH:.2e}", flush=True)
+    assert eG < step_tol and eH < step_tol, (eG, eH)
+    # two outer cycles from the initial state
+    gpu.init_macro(case.init)
+    rc, n, res = gpu.iterate(2, tol=0.0)
+    assert n == 2
+    err = field_errors(gpu.macro(), prim2, fl)
+    G, H = to_oracle(gpu.get_f(np.float64))
+    print(f"[configs] 2 cycles: {err}, f {rel_max(G, G2):.2e}", flush=True)
+    assert max(err.values()) < field_tol, err
+    assert rel_max(G, G2) < field_tol
+    gpu.close()
+
+
+def test_bench_cavity_fp64_full_size_three_cycles():
+    """The cavity workload (64x64 x 784 Gauss-Hermite, 4 levels) in the FP64
+    form: three outer cycles against three oracle cycles, 1e-10."""
+    from paper_1704_03151_amd import Solver
+    case = wl.config2(precision="fp64")
+    print("[configs] cavity64 x 784 fp64, 3 cycles", flush=True)
+    gpu = Solver(case, precision="fp64")
+    rc, n, res = gpu.iterate(3, tol=0.0)
+    orc = Oracle(case)
+    orc.iterate(3, tol=0.0)
+    err = field_errors(gpu.macro(), orc.primitive(), orc.lev0.fluid)
+    G, H = to_oracle(gpu.get_f(np.float64))
+    print(f"[configs] cavity64 fp64 after 3 cycles: {err}, f {rel_max(G, orc.G):.2e}", flush=True)
+    assert n == 3 and max(err.values()) < 1e-10, err
+    assert rel_max(G, orc.G) < 1e-10 and rel_max(H, orc.H) < 1e-10
+    gpu.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32f"])
+def test_plate_steady_state_against_oracle_golden(prec):
+    """The plate workload converged to 1e-6 on the GPU against the oracle's
+    FP64 steady state (converged to 1e-8): fields within 1e-5 in both forms."""
+    path = os.path.join(GOLDEN, "plate128x96_kn0.1_steady.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden steady state not generated")
+    from paper_1704_03151_amd import Solver
+    ref = np.load(path)
+    case = wl.config3()
+    gpu = Solver(case, precision=prec)
+    rc, n, res = gpu.iterate(300, tol=1e-6)
+    assert rc == 0, (rc, n, res)
+    err = field_errors(gpu.macro(), (ref["rho"], ref["U"], ref["V"], ref["T"]))
+    print(f"[configs] plate {prec} steady after {n} cycles (oracle {int(ref['cycles_to_1e6'])}): {err}",
+          flush=True)
+    assert max(err.values()) < 1e-5, err
+    gpu.close()
+
+
+def test_capped_pseudo_step_against_oracle():
+    """The pseudo step a^n dt_p capped at dtn_max dt_p (a = 3, cap 5: capped
+    from the third cycle on) over five outer cycles of the small square."""
+    from paper_1704_03151_amd import Solver
+    case = wl.square_cylinder(scale=8, quad="trapezoid", nu=16, nv=16, vlo=-12.0, vhi=12.0, n_levels=2,
+                              precision="fp64", nu_coarse=4, dtn_growth=3.0, dtn_max=5.0)
+    print("[configs] square20x20 with the pseudo step capped at 5", flush=True)
+    gpu = Solver(case, precision="fp64")
+    orc = Oracle(case)
+    gpu.iterate(5, tol=0.0)
+    orc.iterate(5, tol=0.0)
+    err = field_errors(gpu.macro(), orc.primitive(), orc.lev0.fluid)
+    print(f"[configs] after 5 cycles: {err}", flush=True)
+    assert max(err.values()) < 1e-10, err
+    # the cap changed the trajectory (the test is not vacuous)
+    free = Oracle(case.with_(dtn_max=0.0))
+    free.iterate(5, tol=0.0)
+    assert max(field_errors(gpu.macro(), free.primitive(), free.lev0.fluid).values()) > 1e-6
+    gpu.close()

@@ -73,8 +73,10 @@ def test_fp32_bench_case_three_cycles():
 
 
 def test_fp32_bench_case_steady_state():
-    """FP32-f steady state of the bench workload against the oracle's FP64
-    steady state (converged to 5e-9, tests/golden)."""
+    """FP32-f steady state of the bench cavity against the oracle's FP64
+    steady state (converged to 5e-9, tests/golden).  The first state below
+    residual 1e-6 lies within the convergence level of the fixed point (its
+    fields within 5e-5); converged on to 2e-7 the fields are within 1e-5."""
     path = os.path.join(GOLDEN, "cavity64_kn0.075_steady.npz")
     if not os.path.exists(path):
         pytest.skip("golden steady state not generated")
@@ -83,10 +85,12 @@ def test_fp32_bench_case_steady_state():
     gpu = _solver(case)
     rc, n, res = gpu.iterate(400, tol=1e-6)
     assert rc == 0, (rc, n, res)
+    err1 = field_errors(gpu.macro(), (ref["rho"], ref["U"], ref["V"], ref["T"]))
     rc2, n2, res2 = gpu.iterate(400, tol=2e-7)
-    m = gpu.macro()
-    err = field_errors(m, (ref["rho"], ref["U"], ref["V"], ref["T"]))
-    print(f"[fp32] cavity64 steady: 1e-6 after {n} cycles (oracle {int(ref['cycles_to_1e6'])}), "
-          f"then {n2} more to {res2.max():.2e}; field errors {err}", flush=True)
-    assert max(err.values()) < 1e-5, err
+    err2 = field_errors(gpu.macro(), (ref["rho"], ref["U"], ref["V"], ref["T"]))
+    print(f"[fp32] cavity64 steady: 1e-6 after {n} cycles (oracle {int(ref['cycles_to_1e6'])}), field errors "
+          f"{err1}; 2e-7 after {n2} more (status {rc2}, {res2.max():.2e}), field errors {err2}", flush=True)
+    assert max(err1.values()) < 5e-5, err1
+    assert rc2 == 0, (n2, res2)
+    assert max(err2.values()) < 1e-5, err2
     gpu.close()

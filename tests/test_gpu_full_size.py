@@ -64,25 +64,37 @@ def test_plate_full_size_steady_fp32_matches_fp64():
     assert max(err.values()) < 1e-5, err
 
 
-def test_square_full_size_fp32_matches_fp64():
-    """The Mach-5 square: 120 cycles of both forms reach the residual level
-    set by the Simpson 3/8 velocity rule (below 1e-4) with the same fields."""
+def test_square_full_size_fp64_converges_and_fp32_reaches_its_floor():
+    """The Mach-5 square (trapezoid velocity grid, capped pseudo step): the
+    FP64 form converges to 1e-6 within 200 cycles.  The FP32-f form, run as
+    many cycles, stalls at the resolution of FP32 storage (below 3e-5, with
+    the same fields within 1e-5), and that floor is not the iteration's: the
+    FP64 steady state itself, rounded to FP32, already has a residual above
+    1e-6 (fluxes of order 20 through the 0.01-wide cells at the front face)."""
     from paper_1704_03151_amd import Solver
     case = wl.config4()
-    out = {}
-    for prec in ("fp64", "fp32f"):
-        s = Solver(case, precision=prec)
-        rc, n, res = s.iterate(120, tol=1e-6)
-        m = s.macro()
-        s.close()
-        print(f"[full] square {prec}: status {rc}, {n} cycles, residuals {res}", flush=True)
-        assert np.all(np.isfinite(res)) and np.max(res) < 1e-4, (prec, res)
-        out[prec] = m
+    print("[full] square160x160 x 10000: FP64 to 1e-6, FP32-f as many cycles", flush=True)
+    s64 = Solver(case, precision="fp64")
+    rc, n, res = s64.iterate(200, tol=1e-6)
+    print(f"[full] square fp64: status {rc}, {n} cycles, residuals {res}", flush=True)
+    assert rc == 0, (n, res)
+    m64 = s64.macro()
+    f64 = s64.get_f(np.float64)
+    s64.close()
+    s32 = Solver(case, precision="fp32f")
+    rc32, n32, res32 = s32.iterate(n, tol=1e-6)
+    m32 = s32.macro()
+    print(f"[full] square fp32f: status {rc32}, {n32} cycles, residuals {res32}", flush=True)
+    assert np.all(np.isfinite(res32)) and np.max(res32) < 3e-5, res32
     fl = case.solid == 0
-    m64 = out["fp64"]
-    err = field_errors(out["fp32f"], (m64["rho"], m64["U"], m64["V"], m64["T"]), fl)
+    err = field_errors(m32, (m64["rho"], m64["U"], m64["V"], m64["T"]), fl)
     print(f"[full] square fp32f against fp64: {err}", flush=True)
     assert max(err.values()) < 1e-5, err
+    s32.set_f(f64.astype(np.float32))
+    _, res_round = s32.residual()
+    s32.close()
+    print(f"[full] the FP64 steady state rounded to FP32: residuals {res_round}", flush=True)
+    assert np.max(res_round) > 1e-6
 
 
 def test_adjoint_full_size_against_steady_state_differences():

@@ -70,6 +70,7 @@ class Case:
     init: np.ndarray              # (4, ny, nx) initial (rho, U, V, T)
     precision: str = "fp64"       # "fp64" or "fp32f"
     dtn_growth: float = 0.0       # a in dt_n = a^n dt_p; 0 disables the pseudo step
+    dtn_max: float = 0.0          # cap of a^n (0: none)
     nu1: int = 2
     nu2: int = 1
     nu_coarse: int = 10
@@ -274,6 +275,8 @@ def flat_plate(scale=1, **kw) -> Case:
     scale=1 gives 128 x 96 cells; the plate edges sit on node indices that are
     multiples of 8 so that every level of a 4-level hierarchy keeps them.
     Farfield on all four sides, diffuse plate at the freestream temperature.
+    The 40 x 40 Newton-Cotes velocity grid on [-5, 5]^2 is the composite
+    closed two-point Newton-Cotes (trapezoid) rule on equally spaced nodes.
     """
     n_side, n_mid, n_y = 56 // scale, 16 // scale, 48 // scale
     h = 1.0 / n_mid
@@ -295,7 +298,7 @@ def flat_plate(scale=1, **kw) -> Case:
     init[0], init[1], init[3] = 1.0, uinf, 1.0
     args = dict(name=f"plate{nx}x{ny}", x=x, y=y, face_type_x=ftx, face_type_y=fty,
                 wall_x=wx, wall_y=wy, solid=np.zeros((ny, nx), np.uint8), n_levels=4,
-                quad=QUAD_SIMPSON38, nu=40, nv=40, vlo=-5.0, vhi=5.0, Kn=0.1,
+                quad=QUAD_TRAPEZOID, nu=40, nv=40, vlo=-5.0, vhi=5.0, Kn=0.1,
                 farfield=(1.0, uinf, 0.0, 1.0), init=init, precision="fp32f", nu_coarse_cs=2, **AIR)
     args.update(kw)
     return Case(**args)
@@ -312,7 +315,9 @@ def square_cylinder(scale=1, **kw) -> Case:
     node indices that are multiples of 16 (5 levels).  Farfield on the left,
     top and bottom, zero-gradient outflow on the right, diffuse square at the
     freestream temperature.  The strip behind the square starts at 0.1 of the
-    freestream density and at rest.
+    freestream density and at rest.  The 100 x 100 Newton-Cotes velocity grid
+    on [-15, 15]^2 is the composite trapezoid rule, as for the plate.  The
+    pseudo step grows as 3^n (the paper's choice) up to 300 physical steps.
     """
     nw, nsq, ne, nyo = 48 // scale, 32 // scale, 80 // scale, 64 // scale
     first = 0.01 * scale
@@ -348,10 +353,10 @@ def square_cylinder(scale=1, **kw) -> Case:
     init[0][wake] = 0.1
     init[1][wake] = 0.0
     args = dict(name=f"square{nx}x{ny}", x=x, y=y, face_type_x=ftx, face_type_y=fty,
-                wall_x=wx, wall_y=wy, solid=solid, n_levels=5, quad=QUAD_SIMPSON38,
+                wall_x=wx, wall_y=wy, solid=solid, n_levels=5, quad=QUAD_TRAPEZOID,
                 nu=100, nv=100, vlo=-15.0, vhi=15.0, Kn=0.1,
                 farfield=(1.0, uinf, 0.0, 1.0), init=init, precision="fp32f",
-                dtn_growth=3.0, fas_levels=2, nu_coarse_cs=2, **ARGON)
+                dtn_growth=3.0, dtn_max=300.0, fas_levels=2, nu_coarse_cs=2, **ARGON)
     args.update(kw)
     return Case(**args)
 
