@@ -238,6 +238,18 @@ int miugks_get_macro(miugks_ctx* ctx, double* rho, double* U, double* V, double*
 int miugks_get_f(miugks_ctx* ctx, void* dst, int dtype, int on_device);
 int miugks_set_f(miugks_ctx* ctx, const void* src, int dtype, int on_device);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the result
+ * of miugks_get_f(ctx, dst, dtype, 0) into the caller-owned host buffer dst
+ * (2 Nk nc elements of dtype), calling no allocator.  A conversion to another
+ * dtype is staged through a fixed device array of the library, 16 MiB per GPU
+ * and held until the process ends, in pieces of at most that size, so any
+ * size of f is accepted; the same dtype is copied directly.  Calls that
+ * overlap on one GPU, through any contexts or threads, race on that array;
+ * nothing in it needs to start at zero.  MIUGKS_EINVAL for a bad dtype or a
+ * NULL dst.  Synchronises the stream. */
+int miugks_get_f_noalloc(miugks_ctx* ctx, void* dst, int dtype);
+
 /* --- walls: loads, objectives, temperatures -------------------------------- */
 
 /* Wall sides of the finest level, in the order of their cells (row-major) and

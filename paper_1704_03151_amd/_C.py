@@ -68,6 +68,7 @@ _SIGS = {
     "miugks_explicit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _dp, _dp]),
     "miugks_get_macro": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp, _dp]),
     "miugks_get_f": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "miugks_get_f_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "miugks_set_f": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "miugks_wall_list": (ctypes.c_int, [ctypes.c_void_p, _ip, _ip, _ip]),
     "miugks_wall_loads": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp, _dp, _ip]),

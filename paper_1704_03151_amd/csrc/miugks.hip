@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -38,6 +39,53 @@ struct DevLevel {
 
 }  // namespace
 
+// Fixed device scratch of the allocation-free entry point
+// (miugks_get_f_noalloc): every GPU the library runs on holds its own copy
+// until the process ends.  Host code never passes this name to a kernel or a
+// copy: it is a host-side stand-in; the device address comes from
+// hipGetSymbolAddress (scratch_address below).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of the scratch array on `device`, looked up once per device
+// with that device current.
+int scratch_address(int device, void** out, std::string& err) {
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) {
+        err = "device index beyond the scratch table";
+        return MIUGKS_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess) {
+            err = "hipGetDevice failed";
+            return MIUGKS_EDEVICE;
+        }
+        if (cur != device && hipSetDevice(device) != hipSuccess) {
+            err = "hipSetDevice failed";
+            return MIUGKS_EDEVICE;
+        }
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p) {
+            err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return MIUGKS_EDEVICE;
+        }
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return MIUGKS_OK;
+}
+
+}  // namespace
+
 struct miugks_timing_state;
 
 struct miugks_ctx {
@@ -48,6 +96,7 @@ struct miugks_ctx {
     void* alloc_user = nullptr;
     hipStream_t stream = nullptr;
     int device = 0;
+    void* scratch = nullptr;   // device address of this GPU's allocation-free scratch
     int prec = MIUGKS_FP64;
     size_t esize = 8;
     int nk = 0, nu = 0, nv = 0, L = 1;
@@ -1648,6 +1697,14 @@ int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgri
     for (auto t : ctx->hl[0].fty) closed = closed && t != MIUGKS_FACE_FARFIELD && t != MIUGKS_FACE_OUTFLOW;
     ctx->renorm = s->mass_renorm < 0 ? closed : s->mass_renorm != 0;
     (void)hipGetDevice(&ctx->device);
+    {
+        std::string serr;
+        if (int src = scratch_address(ctx->device, &ctx->scratch, serr)) {
+            g_create_error = serr;
+            delete ctx;
+            return src;
+        }
+    }
     if (!ctx->stream) {
         // the legacy default stream cannot be captured into graphs
         if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
@@ -2220,6 +2277,44 @@ int miugks_adjoint(miugks_ctx* ctx, int kind, const int* walls, int n, const int
 int miugks_get_f(miugks_ctx* ctx, void* dst, int dtype, int on_device) {
     if (!ctx) return MIUGKS_EINVAL;
     return copy_out(ctx, ctx->f, dst, dtype, on_device);
+}
+
+int miugks_get_f_noalloc(miugks_ctx* ctx, void* dst, int dtype) {
+    if (!ctx) return MIUGKS_EINVAL;
+    if (dtype != MIUGKS_FP64 && dtype != MIUGKS_FP32F) {
+        ctx->err = "dtype must be MIUGKS_FP64 or MIUGKS_FP32F";
+        return MIUGKS_EINVAL;
+    }
+    if (!dst) {
+        ctx->err = "null destination";
+        return MIUGKS_EINVAL;
+    }
+    if (!ctx->scratch) {
+        ctx->err = "no device scratch for this context";
+        return MIUGKS_ESTATE;
+    }
+    const size_t n = 2 * (size_t)ctx->nk * ctx->hl[0].nc;
+    const size_t des = dtype == MIUGKS_FP64 ? 8 : 4;
+    if (dtype == ctx->prec) {
+        HIP_TRY(hipMemcpyAsync(dst, ctx->f, n * des, hipMemcpyDeviceToHost, ctx->stream));
+    } else {
+        // converted in pieces of at most the scratch's size; on one stream each
+        // piece's conversion starts after the previous piece left the scratch
+        const size_t per = NOALLOC_SCRATCH_BYTES / des;
+        for (size_t off = 0; off < n; off += per) {
+            const size_t m = std::min(per, n - off);
+            if (ctx->prec == MIUGKS_FP64)
+                hipLaunchKernelGGL((k_convert<double, float>), dim3(1024), dim3(256), 0, ctx->stream,
+                                   (const double*)ctx->f + off, (float*)ctx->scratch, m);
+            else
+                hipLaunchKernelGGL((k_convert<float, double>), dim3(1024), dim3(256), 0, ctx->stream,
+                                   (const float*)ctx->f + off, (double*)ctx->scratch, m);
+            HIP_TRY(hipMemcpyAsync((char*)dst + off * des, ctx->scratch, m * des, hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return check_launch(ctx);
 }
 
 int miugks_set_f(miugks_ctx* ctx, const void* src, int dtype, int on_device) {

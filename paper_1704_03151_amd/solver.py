@@ -176,6 +176,15 @@ class Solver:
         self._check(_C.lib.miugks_get_f(self.h, out.ctypes.data_as(ctypes.c_void_p), code, 0))
         return out
 
+    def get_f_noalloc(self, dtype=None):
+        """The distribution as a host array of dtype through the library's
+        allocation-free entry point (miugks_get_f_noalloc)."""
+        dt = np.dtype(dtype or self.dtype)
+        out = np.zeros(self.fshape, dt)
+        code = _C.FP64 if dt == np.float64 else _C.FP32F
+        self._check(_C.lib.miugks_get_f_noalloc(self.h, out.ctypes.data_as(ctypes.c_void_p), code))
+        return out
+
     def set_f(self, f):
         """Set the distribution from a host array or a torch tensor on the GPU."""
         if not isinstance(f, np.ndarray) and hasattr(f, "data_ptr"):
