@@ -1934,11 +1934,13 @@ __host__ __device__ inline size_t sweep_wave_tiles_elems(int nc, int nw, int W, 
     return t > red ? t : red;
 }
 
+// (GC: the per-cell coefficients and side types are read through the
+// caches, not staged)
 template <typename T>
-size_t sweep_wave_lds_bytes(int nc, int nx, int nw, int W, int I, int NP) {
+size_t sweep_wave_lds_bytes(int nc, int nx, int nw, int W, int I, int NP, bool GC = false) {
     size_t b = 64 * (size_t)W * sizeof(double) +
-               (sweep_wave_tiles_elems<T>(nc, nw, W, I, NP) + nc + nx + 5 * (size_t)nw) * sizeof(T) +
-               4 * (size_t)nw + (size_t)nc;
+               (sweep_wave_tiles_elems<T>(nc, nw, W, I, NP) + (GC ? 0 : nc) + nx + 5 * (size_t)nw) * sizeof(T) +
+               4 * (size_t)nw + (GC ? 0 : (size_t)nc);
     return (b + 15) & ~(size_t)15;
 }
 
@@ -1955,13 +1957,19 @@ size_t sweep_wave_lds_bytes(int nc, int nx, int nw, int W, int I, int NP) {
 // (every block alike, in a fixed order; block 0 also stores them to
 // drho_out; one thread per wall side, so n_wall <= blockDim.x); otherwise
 // they are read from drho (nullptr: zero).
-template <typename T, int R, int NP>
+// GC: the per-cell coefficients and side types are read through the caches
+// by each lane one step ahead instead of being staged in LDS (levels whose
+// tile alone fills the LDS).  split (with NP = 1): the grid's first half of
+// blocks sweeps the G plane, the second half the H plane (each wall ghost
+// term then takes the H factor K_int / (2 lam)); the H blocks leave no wall
+// partial sums (nprev and the next sweep count the G blocks only).
+template <typename T, int R, int NP, bool GC>
 __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, const T* __restrict__ r,
                                                     T* __restrict__ df, const T* __restrict__ coef_g,
                                                     const unsigned char* __restrict__ stype,
                                                     const double* __restrict__ drho, double* __restrict__ wpart,
                                                     int I, const double* __restrict__ wprev, int nprev,
-                                                    double* __restrict__ drho_out) {
+                                                    double* __restrict__ drho_out, int split) {
     // (no static LDS in this kernel: the tiles must start 16-byte aligned
     // for the direct global-to-LDS loads)
     extern __shared__ __attribute__((aligned(16))) double smem_d[];
@@ -1969,21 +1977,29 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
     const int W = blockDim.x >> 6, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     double* dsum = smem_d;                                  // [64 W]  partial sums of the wall densities
     T* tiles = (T*)(smem_d + 64 * W);                       // [W][NP][I][nc]
-    T* coef = tiles + sweep_wave_tiles_elems<T>(nc, nw, W, I, NP);   // [nc]
-    T* invdx = coef + nc;                                   // [nx]
+    T* coef = tiles + sweep_wave_tiles_elems<T>(nc, nw, W, I, NP);   // [nc] (not with GC)
+    T* invdx = coef + (GC ? 0 : nc);                        // [nx]
     T* wl = invdx + nx;                                     // [5][n_wall]  1/d, lam_w, U_w, V_w, drho
     int* wsc = (int*)(wl + 5 * (size_t)nw);                 // [n_wall]  side + 4 cell
-    unsigned char* st = (unsigned char*)(wsc + nw);         // [nc]  side types, 2 bits per side
-    const int k0 = (blockIdx.x * W + w) * I;                // first velocity of this wavefront
+    unsigned char* st = (unsigned char*)(wsc + nw);         // [nc]  side types, 2 bits per side (not with GC)
+    // plane of this block (split: G blocks first, then H blocks)
+    const int nbG = split ? (int)(gridDim.x >> 1) : (int)gridDim.x;
+    const int plane = (int)blockIdx.x >= nbG ? 1 : 0;
+    const int blk = (int)blockIdx.x - plane * nbG;
+    const T* rp = r + (size_t)plane * nk * nc;
+    T* dfp = df + (size_t)plane * nk * nc;
+    const int k0 = (blk * W + w) * I;                       // first velocity of this wavefront
     const int nq = max(0, min(I, nk - k0));                 // velocities it holds
     T* tw = tiles + (size_t)w * NP * I * nc;
     // every load of the prologue is issued before the first wait
     if (nq > 0) {
-        wave_load_lds<T>(tw, r + (size_t)k0 * nc, nq * nc, lane);
+        wave_load_lds<T>(tw, rp + (size_t)k0 * nc, nq * nc, lane);
         if constexpr (NP == 2) wave_load_lds<T>(tw + (size_t)I * nc, r + ((size_t)nk + k0) * nc, nq * nc, lane);
     }
-    if (w == 0) wave_load_lds<T>(coef, coef_g, nc, lane);
-    if (w == W - 1) wave_load_lds<unsigned char>(st, stype, nc, lane);
+    if constexpr (!GC) {
+        if (w == 0) wave_load_lds<T>(coef, coef_g, nc, lane);
+        if (w == W - 1) wave_load_lds<unsigned char>(st, stype, nc, lane);
+    }
     for (int i = threadIdx.x; i < nx; i += blockDim.x) invdx[i] = T(1.0 / g.dx[i]);
     for (int j = threadIdx.x; j < nw; j += blockDim.x) {
         wl[j] = T(g.w_invd[j]);
@@ -2039,6 +2055,7 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
                     if (ok && (sd >> 1) == dir && un < T(0)) {
                         T du = u - wu, dv = v - wv;
                         T C = lam / T(M_PI) * dexp(-lam * (du * du + dv * dv));
+                        if (plane) C = C * (T(K_int) / (T(2) * lam));
                         T a = -un * invd;
                         tw[(size_t)q * nc + cell] += a * (C * dr);
                         if constexpr (NP == 2)
@@ -2078,8 +2095,13 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
         int jc = (jx < 0 || jx >= nx) ? dcol : jx;
         int ix = px ? jc : nx - 1 - jc;
         int c = rowc[p] + ix;
-        n.cf = coef[c];
-        n.sc = st[c];
+        if constexpr (GC) {
+            n.cf = coef_g[c];
+            n.sc = stype[c];
+        } else {
+            n.cf = coef[c];
+            n.sc = st[c];
+        }
         n.idx = invdx[ix];
         n.rG = tG[c];
         n.rH = T(0);
@@ -2154,9 +2176,11 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
     if (s + 2 < nsteps) step(s + 2, nC, nB);
     __syncthreads();
     if (nq > 0) {
-        wave_store<T>(df + (size_t)k0 * nc, tw, nq * nc, lane);
+        wave_store<T>(dfp + (size_t)k0 * nc, tw, nq * nc, lane);
         if constexpr (NP == 2) wave_store<T>(df + ((size_t)nk + k0) * nc, tw + (size_t)I * nc, nq * nc, lane);
     }
+    // the H plane leaves no wall partial sums (uniform over the block)
+    if (plane) return;
     // per-wavefront sums over its velocities of w_k u_n dG_k at the wall sides
     const double ud = lane < nq ? vel.u[k0 + lane] : 0.0, vd = lane < nq ? vel.v[k0 + lane] : 0.0,
                  wd = lane < nq ? vel.w[k0 + lane] : 0.0;
@@ -2187,7 +2211,289 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
     for (int j = threadIdx.x; j < nw; j += blockDim.x) {
         double s = 0.0;
         for (int ww = 0; ww < W; ++ww) s += red[(size_t)ww * nw + j];
-        wpart[(size_t)blockIdx.x * nw + j] = s;
+        wpart[(size_t)blk * nw + j] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Ordered sweep of one plane in x-strips, for levels whose tile alone would
+// fill the LDS (one wavefront per velocity, as k_sweep_wave with I = 1).
+//
+// The level is cut into nstrip strips of columns, taken in the upwind order
+// of the velocity; only one strip's tile (all rows, sw columns) is resident,
+// so several wavefronts share a CU.  A lane owns the same rows in every
+// strip and keeps its last result of each row in a register (it is updated
+// on valid steps only): at a strip's first column that register is the
+// x-upwind value of the strip before, so the strips join without any
+// exchange.  The W wavefronts of a block take consecutive velocities of one
+// row of the grid (index k = ku nvrow + kv, one ku per block): they share
+// the sign of u and so the order of the strips, and the strip's per-cell
+// coefficients and side types are staged once for the block.  Each strip's
+// tiles are staged by direct global-to-LDS loads where rows are 16-byte
+// aligned, the wall ghost terms added, swept in nx_s + ny - 1 steps and
+// stored; the wall sums of the G plane accumulate over the strips.  split
+// as in k_sweep_wave (with the velocity mapping above per plane).
+template <typename T>
+__host__ __device__ inline int sweep_strip_width(int nx, int nstrip) {
+    int sw = (nx + nstrip - 1) / nstrip;
+    return (sw + 3) & ~3;   // 16-byte rows in float (8-byte multiples in double)
+}
+
+template <typename T>
+__host__ __device__ inline size_t sweep_strip_tile_elems(int ny, int sw, int nw, int W) {
+    size_t t = (size_t)W * ny * sw, red = ((size_t)W * nw * sizeof(double) + sizeof(T) - 1) / sizeof(T);
+    return t > red ? t : red;
+}
+
+template <typename T>
+size_t sweep_strip_lds_bytes(int nx, int ny, int nw, int W, int nstrip) {
+    int sw = sweep_strip_width<T>(nx, nstrip);
+    size_t b = 64 * (size_t)W * sizeof(double) +
+               (sweep_strip_tile_elems<T>(ny, sw, nw, W) + (size_t)ny * sw + nx + 5 * (size_t)nw) * sizeof(T) +
+               4 * (size_t)nw + (size_t)ny * sw;
+    return (b + 15) & ~(size_t)15;
+}
+
+// rows x cols elements (row strides sstride in global memory, cols in LDS)
+// from global memory into LDS by the 64 lanes of one wavefront: 16-byte
+// direct loads when every row start is 16-byte aligned, element by element
+// otherwise
+template <typename T>
+__device__ __forceinline__ void wave_load_lds_2d(T* dst, const T* __restrict__ src, int rows, int cols,
+                                                 size_t sstride, int lane) {
+    const size_t rb = (size_t)cols * sizeof(T);
+    if (((((size_t)dst) | ((size_t)src) | rb | (sstride * sizeof(T))) & 15) == 0) {
+        const int per = (int)(rb >> 4);   // 16-byte pieces per row
+        const int n = rows * per;
+        for (int i = lane; i - lane < n; i += 64) {
+            // a wavefront-wide loop: lanes past the end issue nothing
+            if (i < n) {
+                int rr = i / per, cc = i - rr * per;
+                __builtin_amdgcn_global_load_lds(
+                    (gbl_void_t*)((const char*)src + rr * sstride * sizeof(T) + ((size_t)cc << 4)),
+                    (lds_void_t*)((char*)dst + (size_t)(i - lane) * 16), 16, 0, 0);
+            }
+        }
+    } else {
+        const int n = rows * cols;
+        for (int i = lane; i < n; i += 64) {
+            int rr = i / cols, cc = i - rr * cols;
+            dst[i] = src[rr * sstride + cc];
+        }
+    }
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(256) k_sweep_strips(Geo g, Vel vel, int K_int, const T* __restrict__ r,
+                                                      T* __restrict__ df, const T* __restrict__ coef_g,
+                                                      const unsigned char* __restrict__ stype,
+                                                      const double* __restrict__ drho,
+                                                      double* __restrict__ wpart, int nstrip,
+                                                      const double* __restrict__ wprev, int nprev,
+                                                      double* __restrict__ drho_out, int split, int nvrow) {
+    extern __shared__ __attribute__((aligned(16))) double smem_d[];
+    const int nc = g.nc, nx = g.nx, ny = g.ny, nw = g.n_wall, nk = vel.nk;
+    const int W = blockDim.x >> 6, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int sw = sweep_strip_width<T>(nx, nstrip);
+    double* dsum = smem_d;                                  // [64 W]
+    T* tiles = (T*)(smem_d + 64 * W);                       // [W][ny][sw]
+    T* cs = tiles + sweep_strip_tile_elems<T>(ny, sw, nw, W);   // [ny][sw]  the strip's coefficients
+    T* invdx = cs + (size_t)ny * sw;                        // [nx]
+    T* wl = invdx + nx;                                     // [5][n_wall]  1/d, lam_w, U_w, V_w, drho
+    int* wsc = (int*)(wl + 5 * (size_t)nw);                 // [n_wall]  side + 4 cell
+    unsigned char* ss = (unsigned char*)(wsc + nw);         // [ny][sw]  the strip's side types
+    const int nbG = split ? (int)(gridDim.x >> 1) : (int)gridDim.x;
+    const int plane = (int)blockIdx.x >= nbG ? 1 : 0;
+    const int blk = (int)blockIdx.x - plane * nbG;
+    // one row of the velocity grid per block (bpr blocks per row)
+    const int bpr = (nvrow + W - 1) / W;
+    const int ku = blk / bpr, kv = (blk - ku * bpr) * W + w;
+    const int k = ku * nvrow + kv;
+    const bool kok = kv < nvrow && k < nk;
+    // a wavefront without a velocity takes its row's first one (the same
+    // sign of u as the block's others); it loads, stores and sums nothing
+    const int kk = kok ? k : ku * nvrow;
+    const T* rk = r + ((size_t)plane * nk + kk) * nc;
+    T* dk = df + ((size_t)plane * nk + kk) * nc;
+    T* tw = tiles + (size_t)w * ny * sw;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) invdx[i] = T(1.0 / g.dx[i]);
+    for (int j = threadIdx.x; j < nw; j += blockDim.x) {
+        wl[j] = T(g.w_invd[j]);
+        wl[nw + j] = T(1.0 / g.w_T[j]);
+        wl[2 * nw + j] = T(g.w_U[j]);
+        wl[3 * nw + j] = T(g.w_V[j]);
+        wl[4 * nw + j] = drho ? T(drho[j]) : T(0);
+        wsc[j] = g.w_side[j] + 4 * g.w_cell[j];
+    }
+    const int ng = nw > 0 ? max(1, (int)blockDim.x / nw) : 1;
+    if (wprev && threadIdx.x < ng * nw) {
+        int j = threadIdx.x % nw, grp = threadIdx.x / nw;
+        double sacc = 0.0;
+        for (int b = grp; b < nprev; b += ng) sacc += wprev[(size_t)b * nw + j];
+        dsum[threadIdx.x] = sacc;
+    }
+    __syncthreads();
+    if (wprev) {
+        for (int j = threadIdx.x; j < nw; j += blockDim.x) {
+            double sacc = 0.0;
+            for (int grp = 0; grp < ng; ++grp) sacc += dsum[grp * nw + j];
+            double dj = -sacc / g.w_den[j];
+            wl[4 * nw + j] = T(dj);
+            if (blockIdx.x == 0) drho_out[j] = dj;
+        }
+        __syncthreads();
+    }
+    const bool ghosts = drho || wprev;
+    const T u = vel_u<T>(vel, kk), v = vel_v<T>(vel, kk);
+    const bool px = u >= T(0), py = v >= T(0);
+    const int shx = px ? 0 : 2, shy = py ? 4 : 6;           // bit offset of the upwind x / y side type
+    const T au = px ? u : -u, av = py ? v : -v;
+    int iyr[R];                                             // cell row of each slot
+    bool rowok[R];
+    T by[R], cG[R];
+#pragma unroll
+    for (int p = 0; p < R; ++p) {
+        int row = lane + 64 * p;
+        rowok[p] = kok && row < ny;
+        iyr[p] = rowok[p] ? (py ? row : ny - 1 - row) : 0;
+        by[p] = rowok[p] ? av * T(1.0 / g.dy[iyr[p]]) : T(0);
+        cG[p] = T(0);
+    }
+    // per-wavefront sums over its velocity of w_k u_n dG_k at the wall sides
+    const double ud = vel.u[kk], vd = vel.v[kk], wd = kok ? vel.w[kk] : 0.0;
+    double wsum[SWEEP_WAVE_MAX_WALLS / 64];
+#pragma unroll
+    for (int jc = 0; jc < SWEEP_WAVE_MAX_WALLS / 64; ++jc) wsum[jc] = 0.0;
+    // results of lanes off the diagonal go to a word of their own
+    T* dump = (T*)dsum + 64 * w + lane;
+    struct Ahead {
+        T cf, idx, rG;
+        unsigned sc;
+    };
+    for (int b = 0; b < nstrip; ++b) {
+        const int x0 = b * sw;
+        if (x0 >= nx) break;
+        const int wb = min(sw, nx - x0);                    // columns of this strip
+        const int pc0 = px ? x0 : nx - x0 - wb;             // its first physical column
+        __syncthreads();   // the previous strip's tile is stored and summed
+        if (kok) wave_load_lds_2d<T>(tw, rk + pc0, ny, wb, (size_t)nx, lane);
+        if (w == 0) wave_load_lds_2d<T>(cs, coef_g + pc0, ny, wb, (size_t)nx, lane);
+        if (w == W - 1) wave_load_lds_2d<unsigned char>(ss, stype + pc0, ny, wb, (size_t)nx, lane);
+        __syncthreads();
+        // upwind wall-ghost terms of the strip's wall cells (x-sides, then
+        // y-sides; the barriers are reached by every wavefront of the block)
+        if (ghosts) {
+            for (int jb = 0; jb < nw; jb += 64) {
+                const int j = jb + lane;
+                int sd = 0, cell = 0;
+                bool ok = kok && j < nw;
+                if (ok) {
+                    sd = wsc[j] & 3;
+                    cell = wsc[j] >> 2;
+                    const int ix = cell % nx;
+                    ok = ix >= pc0 && ix < pc0 + wb;
+                }
+                for (int dir = 0; dir < 2; ++dir) {
+                    const T un = ((sd & 1) ? T(1) : T(-1)) * (sd < 2 ? u : v);
+                    if (ok && (sd >> 1) == dir && un < T(0)) {
+                        const T lam = wl[nw + j], du = u - wl[2 * nw + j], dv = v - wl[3 * nw + j];
+                        T C = lam / T(M_PI) * dexp(-lam * (du * du + dv * dv));
+                        if (plane) C = C * (T(K_int) / (T(2) * lam));
+                        const int ti = (cell / nx) * wb + (cell % nx - pc0);
+                        tw[ti] += (-un * wl[j]) * (C * wl[4 * nw + j]);
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+        const int dcol = lane % wb;
+        auto fetch = [&](Ahead& n, int p, int jx) {
+            int jc = (jx < 0 || jx >= wb) ? dcol : jx;
+            int ixl = px ? jc : wb - 1 - jc;
+            int ti = iyr[p] * wb + ixl;
+            n.cf = cs[ti];
+            n.sc = ss[ti];
+            n.idx = invdx[pc0 + ixl];
+            n.rG = tw[ti];
+        };
+        Ahead nA[R], nB[R], nC[R], nD[R];
+#pragma unroll
+        for (int p = 0; p < R; ++p) {
+            int row = lane + 64 * p;
+            fetch(nA[p], p, -row);
+            fetch(nB[p], p, 1 - row);
+            fetch(nC[p], p, 2 - row);
+        }
+        auto step = [&](int s, const Ahead(&cur)[R], Ahead(&fill)[R]) {
+            T rotG[R];
+#pragma unroll
+            for (int p = 0; p < R; ++p) rotG[p] = lane_rotate1(cG[p]);
+#pragma unroll
+            for (int p = 0; p < R; ++p) {
+                int jx = s - (lane + 64 * p);
+                bool valid = rowok[p] && (unsigned)jx < (unsigned)wb;
+                const Ahead& d = cur[p];
+                int ixl = px ? jx : wb - 1 - jx;
+                fetch(fill[p], p, jx + 3);
+                T nbG = rotG[p];
+                if (R > 1 && lane == 0) nbG = p > 0 ? rotG[p > 0 ? p - 1 : 0] : T(0);
+                unsigned tpx = (d.sc >> shx) & 3u, tpy = (d.sc >> shy) & 3u;
+                T bx = au * d.idx, byp = by[p];
+                T D = d.cf + (tpx == 3u ? T(0) : bx) + (tpy == 3u ? T(0) : byp);
+                T inv = sweep_rcp(D);
+                T exG = tpx == 0u ? cG[p] : T(0), eyG = tpy == 0u ? nbG : T(0);
+                T vG = (d.rG + bx * exG + byp * eyG) * inv;
+                vG = d.cf < T(0) ? T(0) : vG;
+                *(valid ? tw + iyr[p] * wb + ixl : dump) = vG;
+                cG[p] = valid ? vG : cG[p];
+            }
+        };
+        const int nsteps = wb + ny - 1;
+        int s = 0;
+        for (; s + 3 < nsteps; s += 4) {
+            step(s, nA, nD);
+            step(s + 1, nB, nA);
+            step(s + 2, nC, nB);
+            step(s + 3, nD, nC);
+        }
+        if (s < nsteps) step(s, nA, nD);
+        if (s + 1 < nsteps) step(s + 1, nB, nA);
+        if (s + 2 < nsteps) step(s + 2, nC, nB);
+        __syncthreads();
+        if (kok) {
+            // the strip's rows back to global memory
+            const int n = ny * wb;
+            for (int i = lane; i < n; i += 64) {
+                int rr = i / wb, cc = i - rr * wb;
+                dk[(size_t)rr * nx + pc0 + cc] = tw[i];
+            }
+            if (!plane) {
+#pragma unroll
+                for (int jc = 0; jc < SWEEP_WAVE_MAX_WALLS / 64; ++jc) {
+                    const int j = jc * 64 + lane;
+                    if (jc * 64 < nw && j < nw) {
+                        const int sd = wsc[j] & 3, cell = wsc[j] >> 2, ix = cell % nx;
+                        const double un = ((sd & 1) ? 1.0 : -1.0) * (sd < 2 ? ud : vd);
+                        if (un > 0.0 && ix >= pc0 && ix < pc0 + wb)
+                            wsum[jc] += wd * un * double(tw[(cell / nx) * wb + (ix - pc0)]);
+                    }
+                }
+            }
+        }
+    }
+    if (plane) return;
+    __syncthreads();   // every tile is read: the sums go where the tiles were
+    double* red = (double*)tiles;   // [W][n_wall]
+#pragma unroll
+    for (int jc = 0; jc < SWEEP_WAVE_MAX_WALLS / 64; ++jc) {
+        const int j = jc * 64 + lane;
+        if (j < nw) red[(size_t)w * nw + j] = wsum[jc];
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < nw; j += blockDim.x) {
+        double sacc = 0.0;
+        for (int ww = 0; ww < W; ++ww) sacc += red[(size_t)ww * nw + j];
+        wpart[(size_t)blk * nw + j] = sacc;
     }
 }
 

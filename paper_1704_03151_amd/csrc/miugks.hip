@@ -153,6 +153,10 @@ struct miugks_ctx {
         int W = 0, I = 1, R = 1, blocks = 0;
         size_t lds = 0;
         bool stream = false;
+        // per-cell data read through the caches (the tile alone fills the
+        // LDS); split: the G and H planes as separate blocks of a one-plane sweep
+        bool gc = false, split = false;
+        int strips = 0;   // > 0: k_sweep_strips over that many strips of columns
     };
     std::vector<unsigned char*> stype;
     std::vector<void*> coefT;   // 1/tau + 1/dt_n per level in the distribution's type
@@ -350,16 +354,16 @@ size_t sweep_lds_bytes(const Geo& g, int P) {
     return (b + 15) & ~(size_t)15;
 }
 
-template <typename T, int NP>
+template <typename T, int NP, bool GC>
 hipError_t set_wave_lds_t(int R, int bytes) {
     auto set = [bytes](const void* f) {
         return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     };
     switch (R) {
-        case 1: return set((const void*)k_sweep_wave<T, 1, NP>);
-        case 2: return set((const void*)k_sweep_wave<T, 2, NP>);
-        case 3: return set((const void*)k_sweep_wave<T, 3, NP>);
-        default: return set((const void*)k_sweep_wave<T, 4, NP>);
+        case 1: return set((const void*)k_sweep_wave<T, 1, NP, GC>);
+        case 2: return set((const void*)k_sweep_wave<T, 2, NP, GC>);
+        case 3: return set((const void*)k_sweep_wave<T, 3, NP, GC>);
+        default: return set((const void*)k_sweep_wave<T, 4, NP, GC>);
     }
 }
 
@@ -382,9 +386,33 @@ hipError_t set_stream_lds(int prec, int R, int np, int bytes) {
     return np == 1 ? set_stream_lds_t<float, 1>(R, bytes) : set_stream_lds_t<float, 2>(R, bytes);
 }
 
+template <typename T>
+hipError_t set_strips_lds_t(int R, int bytes) {
+    auto set = [bytes](const void* f) {
+        return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    };
+    switch (R) {
+        case 1: return set((const void*)k_sweep_strips<T, 1>);
+        case 2: return set((const void*)k_sweep_strips<T, 2>);
+        case 3: return set((const void*)k_sweep_strips<T, 3>);
+        default: return set((const void*)k_sweep_strips<T, 4>);
+    }
+}
+
+hipError_t set_strips_lds(int prec, int R, int bytes) {
+    return prec == MIUGKS_FP64 ? set_strips_lds_t<double>(R, bytes) : set_strips_lds_t<float>(R, bytes);
+}
+
 hipError_t set_wave_lds(int prec, int R, int np, int bytes) {
-    if (prec == MIUGKS_FP64) return np == 1 ? set_wave_lds_t<double, 1>(R, bytes) : set_wave_lds_t<double, 2>(R, bytes);
-    return np == 1 ? set_wave_lds_t<float, 1>(R, bytes) : set_wave_lds_t<float, 2>(R, bytes);
+    hipError_t e;
+    if (prec == MIUGKS_FP64) {
+        e = np == 1 ? set_wave_lds_t<double, 1, false>(R, bytes) : set_wave_lds_t<double, 2, false>(R, bytes);
+        if (e == hipSuccess && np == 1) e = set_wave_lds_t<double, 1, true>(R, bytes);
+        return e;
+    }
+    e = np == 1 ? set_wave_lds_t<float, 1, false>(R, bytes) : set_wave_lds_t<float, 2, false>(R, bytes);
+    if (e == hipSuccess && np == 1) e = set_wave_lds_t<float, 1, true>(R, bytes);
+    return e;
 }
 
 // Coarse-level cycles that one visit of a level makes (Sec. II D): gamma > 0
@@ -508,13 +536,34 @@ struct Path {
             }
 #undef MIUGKS_STREAM_LAUNCH
             c->wparts[l] = wc.blocks;
+        } else if (wc.W && wc.strips) {
+#define MIUGKS_STRIPS_LAUNCH(RR)                                                                                 \
+    LAUNCH_SH(c, name, (wc.split ? 2 : 1) * arr(c, l), wc.lds, (k_sweep_strips<T, RR>), dim3(wc.blocks),           \
+              dim3(64 * wc.W), g, c->vel, c->gas.K_int, (const T*)c->r[l], (T*)c->df[l], (const T*)c->coefT[l],      \
+              c->stype[l], from_zero ? (const double*)nullptr : (const double*)c->drho[l], c->wbuf[l], wc.strips,    \
+              in_sweep ? (const double*)c->wbuf_alt[l] : (const double*)nullptr, c->wparts[l], c->drho[l],          \
+              wc.split ? 1 : 0, c->nv)
+            switch (wc.R) {
+                case 1: MIUGKS_STRIPS_LAUNCH(1); break;
+                case 2: MIUGKS_STRIPS_LAUNCH(2); break;
+                case 3: MIUGKS_STRIPS_LAUNCH(3); break;
+                default: MIUGKS_STRIPS_LAUNCH(4); break;
+            }
+#undef MIUGKS_STRIPS_LAUNCH
+            c->wparts[l] = wc.split ? wc.blocks / 2 : wc.blocks;
         } else if (wc.W) {
-#define MIUGKS_WAVE_LAUNCH(RR, NP)                                                                              \
-    LAUNCH_SH(c, name, (NP) * arr(c, l), wc.lds, (k_sweep_wave<T, RR, NP>), dim3(wc.blocks), dim3(64 * wc.W), g, \
-              c->vel, c->gas.K_int, (const T*)c->r[l], (T*)c->df[l], (const T*)c->coefT[l], c->stype[l],        \
-              from_zero ? (const double*)nullptr : (const double*)c->drho[l], c->wbuf[l], wc.I,                 \
-              in_sweep ? (const double*)c->wbuf_alt[l] : (const double*)nullptr, c->wparts[l], c->drho[l])
-            if (np == 1) {
+#define MIUGKS_WAVE_LAUNCH_G(RR, NP, GC)                                                                        \
+    LAUNCH_SH(c, name, (wc.split ? 2 : (NP)) * arr(c, l), wc.lds, (k_sweep_wave<T, RR, NP, GC>), dim3(wc.blocks),   \
+              dim3(64 * wc.W), g, c->vel, c->gas.K_int, (const T*)c->r[l], (T*)c->df[l], (const T*)c->coefT[l],      \
+              c->stype[l], from_zero ? (const double*)nullptr : (const double*)c->drho[l], c->wbuf[l], wc.I,         \
+              in_sweep ? (const double*)c->wbuf_alt[l] : (const double*)nullptr, c->wparts[l], c->drho[l],          \
+              wc.split ? 1 : 0)
+#define MIUGKS_WAVE_LAUNCH(RR, NP)                \
+    if (wc.gc)                                    \
+        MIUGKS_WAVE_LAUNCH_G(RR, 1, true);        \
+    else                                          \
+        MIUGKS_WAVE_LAUNCH_G(RR, NP, false)
+            if (np == 1 || wc.split) {
                 switch (wc.R) {
                     case 1: MIUGKS_WAVE_LAUNCH(1, 1); break;
                     case 2: MIUGKS_WAVE_LAUNCH(2, 1); break;
@@ -530,7 +579,8 @@ struct Path {
                 }
             }
 #undef MIUGKS_WAVE_LAUNCH
-            c->wparts[l] = wc.blocks;
+#undef MIUGKS_WAVE_LAUNCH_G
+            c->wparts[l] = wc.split ? wc.blocks / 2 : wc.blocks;
         } else if (c->sweep_lds[l]) {
             c->wparts[l] = c->nk;
             int npad = ((g.ny + 63) / 64) * 64, P = c->sweep_lds[l];
@@ -1145,8 +1195,83 @@ int build_device(miugks_ctx* ctx) {
                         best_rounds = rounds;
                     }
                 }
+                // where the tile and the per-cell data do not fit together:
+                // the sweep in strips of columns (one velocity per
+                // wavefront, a row of the velocity grid per block), the
+                // configuration with the most wavefronts per CU (at most 8),
+                // then the fewest steps.  Each step is bound by instruction
+                // issue, and a narrow strip wastes more lanes on the
+                // pipeline's fill and drain, but more wavefronts keep every
+                // SIMD busy (measured on the 160-row level: 8 strips of 4
+                // wavefronts 4.9 ms per launch, the whole tile at one
+                // wavefront per CU 6.7 ms).  Without any strip that fits (or
+                // MIUGKS_GC_SWEEP=1): the whole tile, the per-cell data read
+                // through the caches.  MIUGKS_SWEEP_STRIPS=n and
+                // MIUGKS_STRIP_W=w force a strip count and block width.
+                const char* gce = getenv("MIUGKS_GC_SWEEP");
+                const bool force_gc = gce && atoi(gce) == 1;
+                const char* se2 = getenv("MIUGKS_SWEEP_STRIPS");
+                const int force_s = se2 ? atoi(se2) : 0;
+                const char* sw2 = getenv("MIUGKS_STRIP_W");
+                const int force_sw = sw2 ? atoi(sw2) : 0;
+                if ((!wc.W || force_gc) && !(gce && atoi(gce) == 0)) {
+                    miugks_ctx::WaveCfg gw = wc;
+                    gw.W = 0;
+                    gw.gc = true;
+                    gw.split = np == 2;
+                    gw.I = 1;
+                    long best_waves = 0, best_steps = 0;
+                    for (int S = 2; S <= 8 && (!force_gc || force_s > 0); ++S) {
+                        if (force_s > 0 && S != force_s) continue;
+                        const int sw = ctx->prec == MIUGKS_FP64 ? sweep_strip_width<double>(h.nx, S)
+                                                                : sweep_strip_width<float>(h.nx, S);
+                        if (force_s <= 0 && (S - 1) * sw >= h.nx) continue;   // fewer strips than S
+                        long steps = 0;
+                        for (int x0 = 0; x0 < h.nx; x0 += sw) steps += std::min(sw, h.nx - x0) + h.ny - 1;
+                        for (int W : {4, 2, 1}) {
+                            if (force_sw && W != force_sw) continue;
+                            size_t need = ctx->prec == MIUGKS_FP64
+                                              ? sweep_strip_lds_bytes<double>(h.nx, h.ny, (int)h.w_cell.size(), W, S)
+                                              : sweep_strip_lds_bytes<float>(h.nx, h.ny, (int)h.w_cell.size(), W, S);
+                            if (need > (size_t)max_lds) continue;
+                            long waves = std::min<long>(8, (long)(max_lds / need) * W);
+                            if (!gw.W || waves > best_waves || (waves == best_waves && steps < best_steps)) {
+                                gw.W = W;
+                                gw.lds = need;
+                                gw.strips = S;
+                                best_waves = waves;
+                                best_steps = steps;
+                            }
+                        }
+                    }
+                    if (!gw.W && force_s <= 0) {
+                        // the whole tile, per-cell data through the caches
+                        gw.I = wc.I;
+                        const long items = gw.split ? 2L * nwaves : nwaves;
+                        long best = 0;
+                        for (int W : {1, 2, 4}) {
+                            if (force_w && W != force_w) continue;
+                            size_t need =
+                                ctx->prec == MIUGKS_FP64
+                                    ? sweep_wave_lds_bytes<double>(h.nc, h.nx, (int)h.w_cell.size(), W, gw.I, 1, true)
+                                    : sweep_wave_lds_bytes<float>(h.nc, h.nx, (int)h.w_cell.size(), W, gw.I, 1, true);
+                            if (need > (size_t)max_lds) continue;
+                            long per_cu = std::min<long>((long)max_lds / (long)need, 8);
+                            long cap = (long)cus * per_cu * W;
+                            long rounds = (items + cap - 1) / cap;
+                            if (!gw.W || rounds <= best) {
+                                gw.W = W;
+                                gw.lds = need;
+                                best = rounds;
+                            }
+                        }
+                    }
+                    if (gw.W) wc = gw;
+                }
                 if (wc.W) {
-                    wc.blocks = (nwaves + wc.W - 1) / wc.W;
+                    // strips: one row of the velocity grid per block
+                    wc.blocks = wc.strips ? ctx->nu * ((ctx->nv + wc.W - 1) / wc.W) * (wc.split ? 2 : 1)
+                                          : (nwaves + wc.W - 1) / wc.W * (wc.split ? 2 : 1);
                     (np == 2 ? ctx->wave : ctx->wave1)[l] = wc;
                     wave_need_max = std::max(wave_need_max, wc.lds);
                 }
@@ -1187,8 +1312,10 @@ int build_device(miugks_ctx* ctx) {
     }
     if (wave_need_max > 65536) {
         hipError_t e = hipSuccess;
-        for (int R = 1; R <= 4 && e == hipSuccess; ++R)
+        for (int R = 1; R <= 4 && e == hipSuccess; ++R) {
             for (int np = 1; np <= 2 && e == hipSuccess; ++np) e = set_wave_lds(ctx->prec, R, np, (int)wave_need_max);
+            if (e == hipSuccess) e = set_strips_lds(ctx->prec, R, (int)wave_need_max);
+        }
         if (e != hipSuccess)
             for (int l = 0; l < ctx->L; ++l)
                 if ((!ctx->wave[l].stream && ctx->wave[l].lds > 65536) ||
