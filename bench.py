@@ -40,9 +40,17 @@ HBM_PEAK_GBS = 8000.0
 # same run (--copy-calibration).  Keyed by (workload, precision, kernel); an
 # entry is dropped whenever that kernel changes.
 MEASURED_TRAFFIC = {
-    # profiles/sweep_wave_cavity64_fp32f_hbm_traffic.md: 77 dispatches of the
-    # sweep (every level, G-only and G+H forms), scaled FETCH_SIZE + WRITE_SIZE
-    ("cavity64_kn0.075", "fp32f", "sweep"): 12.19e6,
+    # profiles/square160x160_kernel_trace_and_hbm_traffic.md: the ordered
+    # sweep over all its launches (every level; the level-0 strips and the
+    # coarse levels' wavefront form), its level-0 strips alone, the flux
+    ("square160x160", "fp32f", "sweep"): 1.2097e9,
+    ("square160x160", "fp32f", "sweep/l0"): 4.9575e9,
+    ("square160x160", "fp32f", "flux_div"): 2.4691e10,
+    ("square160x160", "fp64", "sweep"): 1.8281e9,
+    ("square160x160", "fp64", "flux_div"): 4.7119e10,
+    # profiles/plate128x96_kernel_trace_and_hbm_traffic.md
+    ("plate128x96", "fp32f", "sweep"): 7.2284e7,
+    ("plate128x96", "fp32f", "flux_div"): 2.3049e9,
 }
 
 # what each workload recipe is (the sizes are printed from the case itself)
