@@ -45,12 +45,9 @@ MEASURED_TRAFFIC = {
     # coarse levels' wavefront form), its level-0 strips alone, the flux
     ("square160x160", "fp32f", "sweep"): 1.2097e9,
     ("square160x160", "fp32f", "sweep/l0"): 4.9575e9,
-    ("square160x160", "fp32f", "flux_div"): 2.4691e10,
     ("square160x160", "fp64", "sweep"): 1.8281e9,
-    ("square160x160", "fp64", "flux_div"): 4.7119e10,
     # profiles/plate128x96_kernel_trace_and_hbm_traffic.md
     ("plate128x96", "fp32f", "sweep"): 7.2284e7,
-    ("plate128x96", "fp32f", "flux_div"): 2.3049e9,
 }
 
 # what each workload recipe is (the sizes are printed from the case itself)

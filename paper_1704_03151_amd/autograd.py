@@ -5,8 +5,11 @@ faces, converges the steady state on the GPU and returns the objective
 J = sum S load over the given wall sides as a torch scalar; its backward pass
 calls the library's adjoint (dJ/dTw at fixed mass in a closed domain), so
 J.backward() or torch.autograd.grad give the gradient over all faces for the
-cost of one adjoint solve.  Argument marshalling only: the solves run in
-libmiugks.so.
+cost of one adjoint solve.  Forward keeps its temperatures and converged
+distribution (on the GPU); when the solver has been used since (another
+forward, a line search), backward puts that state back before the adjoint,
+so every J is differentiated at its own steady state.  Argument marshalling
+only: the solves run in libmiugks.so.
 """
 from __future__ import annotations
 
@@ -26,12 +29,20 @@ class _SteadyWallLoad(torch.autograd.Function):
             raise _C.MiugksError(rc, f"steady state not reached in {max_cycles} cycles (residual {res.max():.3e})")
         ctx.args = (solver, kind, walls, faces, adj_tol, adj_iter)
         ctx.device = Tw.device
+        # the state this J belongs to
+        ctx.Tw = T.copy()
+        ctx.f = solver.get_f(out=torch.empty(solver.fshape, dtype=torch.float64, device="cuda"))
+        ctx.version = solver.state_version
         return torch.tensor(solver.objective(kind, walls), dtype=torch.float64, device=Tw.device)
 
     @staticmethod
     def backward(ctx, gJ):
         solver, kind, walls, faces, adj_tol, adj_iter = ctx.args
+        if solver.state_version != ctx.version:
+            solver.set_wall_T(faces, ctx.Tw)
+            solver.set_f(ctx.f)
         st, g, iters, rel = solver.adjoint(kind, walls, faces, tol=adj_tol, max_iter=adj_iter)
+        ctx.version = solver.state_version
         if st != _C.OK:
             raise _C.MiugksError(st, f"adjoint not converged after {iters} corrections (residual {rel:.3e})")
         grad = torch.as_tensor(np.asarray(g), dtype=torch.float64, device=ctx.device) * gJ

@@ -1178,8 +1178,18 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
                                                   double* __restrict__ part, int tstride) {
     typedef double A;
     __shared__ double sh[4 * WAVES * TILE];
+    // XCD-contiguous logical blocks: each XCD takes whole velocity chunks,
+    // so the rows of a tile's y-stencil are read by tiles of the same L2
     Chunk ch = chunk_of(g.nc, vel.nk);
-    ch.c = blockIdx.x * tstride + ch.lane;
+    {
+        const int nt = gridDim.x, nb = gridDim.x * gridDim.y;
+        const int Lb = xcd_swizzle(blockIdx.x + nt * blockIdx.y, nb);
+        const int tile = Lb % nt, chunk = Lb / nt;
+        ch.c = tile * tstride + ch.lane;
+        ch.k0 = chunk * KCH;
+        ch.k1 = min(vel.nk, ch.k0 + KCH);
+        ch.chunk = chunk;
+    }
     ch.valid = ch.c < g.nc;
     const bool own = ch.valid && ch.lane < tstride;
     double acc[4] = {0, 0, 0, 0};
@@ -1360,7 +1370,7 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
             acc[3] += 0.5 * w * ((u * u + v * v) * gd + hd);
         }
     }
-    reduce_store<4>(acc, sh, part, g.nc, c, own);
+    reduce_store<4>(acc, sh, part, g.nc, c, own, ch.chunk);
 }
 
 // tile stride of k_flux_div and its blocks along the cells

@@ -87,6 +87,9 @@ class Solver:
         if rc:
             raise _C.MiugksError(rc, _C.lib.miugks_last_error(None).decode())
         self.h = h
+        # bumped by every call that changes the distribution or the wall
+        # temperatures (lets a saved state be recognised as current)
+        self.state_version = 0
         nc, nf, nk, nl = (ctypes.c_int() for _ in range(4))
         _C.lib.miugks_sizes(h, ctypes.byref(nc), ctypes.byref(nf), ctypes.byref(nk), ctypes.byref(nl))
         self.nc, self.n_fluid, self.nk, self.n_levels = nc.value, nf.value, nk.value, nl.value
@@ -123,11 +126,13 @@ class Solver:
 
     # ------------------------------------------------------------------ API
     def init_macro(self, prim):
+        self.state_version += 1
         p = [self._cells(a) for a in prim]
         self._check(_C.lib.miugks_init_macro(self.h, *(_C.dptr(a) for a in p)))
 
     def iterate(self, max_cycles, tol=1e-6):
         """Returns (status, cycles_done, residual norms); status OK, ENOTCONVERGED or EDIVERGED."""
+        self.state_version += 1
         n = ctypes.c_int()
         res = np.zeros(4)
         rc = _C.lib.miugks_iterate(self.h, int(max_cycles), float(tol), ctypes.byref(n), _C.dptr(res))
@@ -136,6 +141,7 @@ class Solver:
 
     def fmg(self, cycles_per_level, tol=1e-6):
         """Full-multigrid start from the current state; returns (status, cycles run)."""
+        self.state_version += 1
         n = ctypes.c_int()
         rc = _C.lib.miugks_fmg(self.h, int(cycles_per_level), float(tol), ctypes.byref(n))
         self._check(rc, allow=(_C.EDIVERGED,))
@@ -143,6 +149,7 @@ class Solver:
 
     def explicit(self, steps):
         """Explicit time-accurate UGKS steps; returns (dt, RMS residuals of the last step)."""
+        self.state_version += 1
         dt = np.zeros(1)
         res = np.zeros(4)
         self._check(_C.lib.miugks_explicit(self.h, int(steps), _C.dptr(dt), _C.dptr(res)))
@@ -187,6 +194,7 @@ class Solver:
 
     def set_f(self, f):
         """Set the distribution from a host array or a torch tensor on the GPU."""
+        self.state_version += 1
         if not isinstance(f, np.ndarray) and hasattr(f, "data_ptr"):
             ptr, code = self._device_f(f)
             self._check(_C.lib.miugks_set_f(self.h, ptr, code, 1))
@@ -221,6 +229,7 @@ class Solver:
         return float(J[0])
 
     def set_wall_T(self, faces, Tw):
+        self.state_version += 1
         ids = np.ascontiguousarray(faces, np.int32)
         T = np.ascontiguousarray(Tw, float)
         if T.shape != ids.shape:

@@ -168,3 +168,37 @@ def test_autograd_wall_load_matches_adjoint():
     assert st == 0 and g.device.type == "cuda"
     assert np.max(np.abs(g.cpu().numpy() - ref)) <= 1e-9 * np.max(np.abs(ref))
     gpu.close()
+
+
+def test_autograd_backward_after_another_forward():
+    """Two forwards at different wall temperatures, then the backward of the
+    first: its gradient is the one at its own steady state (equal to a fresh
+    forward and backward there), not at the state the second forward left."""
+    import torch
+    from paper_1704_03151_amd import Solver
+    from paper_1704_03151_amd.autograd import steady_wall_load
+    case = _tiny_cavity()
+    print("[adjoint] tiny cavity: backward after another forward", flush=True)
+    gpu = Solver(case, precision="fp64")
+    cell, side = gpu.wall_list()
+    lid = list(np.nonzero(side == 3)[0])
+    nfx = (N + 1) * N
+    faces = [nfx + i for i in range(N)]
+    T1 = torch.tensor(case.wall_y[0, :, 0], dtype=torch.float64, device="cuda", requires_grad=True)
+    T2 = torch.tensor(case.wall_y[0, :, 0] * 1.02, dtype=torch.float64, device="cuda", requires_grad=True)
+    J1 = steady_wall_load(gpu, T1, ad.LOAD_SHEAR, lid, faces, tol=1e-12, adj_tol=1e-10)
+    J2 = steady_wall_load(gpu, T2, ad.LOAD_SHEAR, lid, faces, tol=1e-12, adj_tol=1e-10)
+    assert abs(J1.item() - J2.item()) > 1e-6 * abs(J1.item())
+    (g1,) = torch.autograd.grad(J1, T1)
+    (g2,) = torch.autograd.grad(J2, T2)
+    ref = Solver(case, precision="fp64")
+    T1r = T1.detach().clone().requires_grad_(True)
+    Jr = steady_wall_load(ref, T1r, ad.LOAD_SHEAR, lid, faces, tol=1e-12, adj_tol=1e-10)
+    (gr,) = torch.autograd.grad(Jr, T1r)
+    e1 = float(torch.max(torch.abs(g1 - gr)) / torch.max(torch.abs(gr)))
+    e12 = float(torch.max(torch.abs(g2 - gr)) / torch.max(torch.abs(gr)))
+    print(f"[adjoint] first gradient against a fresh one {e1:.2e}; the second differs by {e12:.2e}", flush=True)
+    assert abs(J1.item() - Jr.item()) <= 1e-12 * abs(Jr.item())
+    assert e1 < 1e-8 and e12 > 1e-4
+    gpu.close()
+    ref.close()
