@@ -40,19 +40,9 @@ HBM_PEAK_GBS = 8000.0
 # same run (--copy-calibration).  Keyed by (workload, precision, kernel); an
 # entry is dropped whenever that kernel changes.
 MEASURED_TRAFFIC = {
-    # profiles/square160x160_kernel_trace_and_hbm_traffic.md: the ordered
-    # sweep over all its launches (every level; the level-0 strips and the
-    # coarse levels' wavefront form), its level-0 strips alone, the flux
-    ("square160x160", "fp32f", "sweep"): 1.2096e9,
-    ("square160x160", "fp32f", "sweep/l0"): 4.9573e9,
-    ("square160x160", "fp32f", "flux_div"): 7.6482e9,
-    ("square160x160", "fp64", "sweep"): 1.8282e9,
-    ("square160x160", "fp64", "flux_div"): 1.2395e10,
-    # profiles/plate128x96_kernel_trace_and_hbm_traffic.md (the sweep)
-    ("plate128x96", "fp32f", "sweep"): 7.2284e7,
-    # profiles/cavity64_kn0.075_kernel_trace_and_hbm_traffic.md
-    ("cavity64_kn0.075", "fp32f", "sweep"): 1.2186e7,
-    ("cavity64_kn0.075", "fp32f", "flux_div"): 8.1993e7,
+    # (workload, precision form, kernel): FETCH_SIZE + WRITE_SIZE per launch
+    # from the profiles under profiles/; empty until the flux (buffer loads,
+    # unrolled velocities) and the banded sweep have been measured again
 }
 
 # what each workload recipe is (the sizes are printed from the case itself)

@@ -1158,11 +1158,163 @@ __device__ __forceinline__ void face_flux(const FaceConst<T>& F, T u, T v, T un,
     PH = un * (F.q[0] * Heq + F.q[1] * un * aH * H0 + F.q[2] * bH * H0 + F.q[3] * Hup + F.q[4] * un * sHup);
 }
 
+// Raw buffer resource over `bytes` bytes from p.  The stencil loads of the
+// interface flux go through one per distribution plane and velocity chunk:
+// a lane's byte offset (a cell) in a vector register, the velocity's row
+// offset in a scalar one, so a load costs no vector address arithmetic.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
+// A face's reconstruction stencil as byte offsets within a plane row: L and
+// the cell R on either side, L's far neighbour LL and R's far neighbour RR
+// (an absent far neighbour reads its near one, with its inverse distance
+// zero, so that the one-sided difference vanishes)
+template <typename T>
+struct FaceStencil {
+    unsigned oL, oR, oLL, oRR;
+    T idc, idcL, idcR, dL, dR;
+};
+
+template <typename T>
+__device__ __forceinline__ void face_stencil(const Geo& g, int c, int d, FaceStencil<T>& s) {
+    FaceGeom<T> fg;
+    face_geom<T>(g, c, d, fg);
+    s.oL = (unsigned)fg.L * sizeof(T);
+    s.oR = (unsigned)c * sizeof(T);
+    s.oLL = (unsigned)(fg.LL >= 0 ? fg.LL : fg.L) * sizeof(T);
+    s.oRR = (unsigned)(fg.RR >= 0 ? fg.RR : c) * sizeof(T);
+    s.idc = fg.idc;
+    s.idcL = fg.idcL;
+    s.idcR = fg.idcR;
+    s.dL = fg.dL;
+    s.dR = fg.dR;
+}
+
+template <typename T>
+__device__ __forceinline__ void stencil_load(const FaceStencil<T>& s, __amdgpu_buffer_rsrc_t RG,
+                                             __amdgpu_buffer_rsrc_t RH, unsigned so, FaceVals<T>& q) {
+    q.GL = buf_ld<T>(RG, s.oL, so);
+    q.GR = buf_ld<T>(RG, s.oR, so);
+    q.HL = buf_ld<T>(RH, s.oL, so);
+    q.HR = buf_ld<T>(RH, s.oR, so);
+    q.GLL = buf_ld<T>(RG, s.oLL, so);
+    q.HLL = buf_ld<T>(RH, s.oLL, so);
+    q.GRR = buf_ld<T>(RG, s.oRR, so);
+    q.HRR = buf_ld<T>(RH, s.oRR, so);
+}
+
+// side of a face's upwind cell for a normal velocity un (the same in every
+// lane): 0 for un > 0 (L), 1 for un < 0 (R), 2 for un = 0
+__device__ __forceinline__ int upwind_side(double un) {
+    return __builtin_amdgcn_readfirstlane(un > 0.0 ? 0 : (un < 0.0 ? 1 : 2));
+}
+
+// limited slope and interface value on the upwind side (face_upwind_vals
+// with the side known for the whole wavefront: only that side's slope is
+// formed)
+template <typename T>
+__device__ __forceinline__ void upwind_on_side(const FaceStencil<T>& s, const FaceVals<T>& q, int side, T& Gup,
+                                               T& Hup, T& sGup, T& sHup) {
+    T gLR = (q.GR - q.GL) * s.idc, hLR = (q.HR - q.HL) * s.idc;
+    if (side == 0) {
+        T gm = (q.GL - q.GLL) * s.idcL, hm = (q.HL - q.HLL) * s.idcL;
+        sGup = van_leer_fast(gm, gLR);
+        sHup = van_leer_fast(hm, hLR);
+        Gup = q.GL + sGup * s.dL;
+        Hup = q.HL + sHup * s.dL;
+    } else if (side == 1) {
+        T gp = (q.GRR - q.GR) * s.idcR, hp = (q.HRR - q.HR) * s.idcR;
+        sGup = van_leer_fast(gLR, gp);
+        sHup = van_leer_fast(hLR, hp);
+        Gup = q.GR - sGup * s.dR;
+        Hup = q.HR - sHup * s.dR;
+    } else {
+        T gm = (q.GL - q.GLL) * s.idcL, hm = (q.HL - q.HLL) * s.idcL;
+        T gp = (q.GRR - q.GR) * s.idcR, hp = (q.HRR - q.HR) * s.idcR;
+        T sGL = van_leer_fast(gm, gLR), sHL = van_leer_fast(hm, hLR);
+        T sGR = van_leer_fast(gLR, gp), sHR = van_leer_fast(hLR, hp);
+        Gup = T(0.5) * (q.GL + sGL * s.dL + q.GR - sGR * s.dR);
+        Hup = T(0.5) * (q.HL + sHL * s.dL + q.HR - sHR * s.dR);
+        sGup = T(0.5) * (sGL + sGR);
+        sHup = T(0.5) * (sHL + sHR);
+    }
+}
+
+// Table of 2^(j/64), j < 64, for exp_tab (filled by the block that uses it)
+constexpr int EXP_TAB = 64;
+__device__ __forceinline__ void exp_tab_fill(double* tab) {
+    if (threadIdx.x < EXP_TAB) tab[threadIdx.x] = exp2(double(threadIdx.x) / EXP_TAB);
+}
+
+// exp(x) by Tang's table-driven method (ACM TOMS 15(2), 1989): x = (64 m +
+// j) ln2/64 + r with |r| <= ln2/128, exp(x) = 2^m 2^(j/64) e^r, e^r - 1 from
+// its degree-5 Taylor polynomial (truncation below 4e-17 relative).  The
+// reduction subtracts n ln2/64 in two fused steps (ln2/64 split into its
+// nearest double and the remainder).  Underflows to zero below about -745;
+// a NaN argument gives NaN.
+__device__ __forceinline__ double exp_tab(double x, const double* __restrict__ tab) {
+    const double n = __builtin_rint(x * 92.33248261689366);   // 64 / ln2
+    double r = fma(-n, 0.010830424696249145, x);
+    r = fma(-n, 3.623510646634843e-19, r);
+    const int ni = int(n);
+    double p = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+    p = fma(r, p, 1.0 / 6.0);
+    p = fma(r, p, 0.5);
+    p = fma(r, p, 1.0);
+    p *= r;
+    const double t = tab[ni & (EXP_TAB - 1)];
+    return __builtin_amdgcn_ldexp(fma(t, p, t), ni >> 6);
+}
+
+// face_flux with the upwind side known for the whole wavefront (side 0 or
+// 1; a face with zero normal velocity carries no flux), the Maxwellian by
+// exp_tab
+template <typename T>
+__device__ __forceinline__ void face_flux_side(const FaceConst<T>& F, int side, T u, T v, T un, T Gup, T Hup,
+                                               T sGup, T sHup, const double* __restrict__ etab, T& PG, T& PH) {
+    T cx = u - F.U, cy = v - F.V, c2 = cx * cx + cy * cy;
+    T G0 = F.pre * T(exp_tab(double(-F.lam * c2), etab));
+    T H0 = F.hK * G0;
+    T sk = F.shx * cx + F.shy * cy;
+    T Geq = G0 * (T(1) + sk * (T(2) * F.lam * c2 - T(4)));
+    T Heq = H0 * (T(1) + sk * (T(2) * F.lam * c2 - T(2)));
+    T q2 = u * u + v * v;
+    T aG, aH;
+    if (side == 0) {
+        aG = F.a[0][0] + F.a[0][1] * u + F.a[0][2] * v + F.a[0][3] * q2;
+        aH = aG + F.dH[0];
+    } else {
+        aG = F.a[1][0] + F.a[1][1] * u + F.a[1][2] * v + F.a[1][3] * q2;
+        aH = aG + F.dH[1];
+    }
+    T bG = F.a[2][0] + F.a[2][1] * u + F.a[2][2] * v + F.a[2][3] * q2;
+    T bH = bG + F.dH[2];
+    PG = un * (F.q[0] * Geq + F.q[1] * un * aG * G0 + F.q[2] * bG * G0 + F.q[3] * Gup + F.q[4] * un * sGup);
+    PH = un * (F.q[0] * Heq + F.q[1] * un * aH * H0 + F.q[2] * bH * H0 + F.q[3] * Hup + F.q[4] * un * sHup);
+}
+
 // Step 1: div_ik = (1/V_i) sum_faces S u_n ftilde (outward) for G and H, and
 // partial sums of the macroscopic residual R_i = -sum_k w psi div_ik.  The
 // flux arithmetic runs in double on the stored (T) distribution: R is a
 // difference of fluxes scaled by S/V, and single-precision products would
 // leave ~1e-6 of rounding noise in it; div is stored in T.
+//
+// A block is a tile of cells (lanes) by a chunk of KCH velocities, wave w
+// taking velocities k0 + w + WAVES j.  The velocity is the same in every
+// lane, so the upwind side of a face is a scalar branch, the stencil loads
+// take scalar row offsets, and a thread's MK velocities are unrolled into
+// registers.
 //
 // A cell's +x face is the -x face of the next cell: every interior +x face
 // flux is handed down a lane rather than formed again (a quarter fewer face
@@ -1178,199 +1330,215 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
                                                   double* __restrict__ part, int tstride) {
     typedef double A;
     __shared__ double sh[4 * WAVES * TILE];
+    __shared__ double etab[EXP_TAB];
+    exp_tab_fill(etab);
+    __syncthreads();
     // XCD-contiguous logical blocks: each XCD takes whole velocity chunks,
     // so the rows of a tile's y-stencil are read by tiles of the same L2
-    Chunk ch = chunk_of(g.nc, vel.nk);
-    {
-        const int nt = gridDim.x, nb = gridDim.x * gridDim.y;
-        const int Lb = xcd_swizzle(blockIdx.x + nt * blockIdx.y, nb);
-        const int tile = Lb % nt, chunk = Lb / nt;
-        ch.c = tile * tstride + ch.lane;
-        ch.k0 = chunk * KCH;
-        ch.k1 = min(vel.nk, ch.k0 + KCH);
-        ch.chunk = chunk;
-    }
-    ch.valid = ch.c < g.nc;
-    const bool own = ch.valid && ch.lane < tstride;
+    const int nt = gridDim.x, nb = gridDim.x * gridDim.y;
+    const int Lb = xcd_swizzle(blockIdx.x + nt * blockIdx.y, nb);
+    const int tile = Lb % nt, chunk = Lb / nt;
+    const int lane = threadIdx.x & (TILE - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / TILE);
+    const int nk = vel.nk, k0 = chunk * KCH, k1 = min(nk, k0 + KCH);
+    // this wave's velocities k0 + wave + WAVES j, j < nmine
+    const int nmine = k1 - k0 > wave ? (k1 - k0 - wave + WAVES - 1) / WAVES : 0;
+    const int c = tile * tstride + lane;
+    const bool valid = c < g.nc, own = valid && lane < tstride;
+    const size_t nc = g.nc, ho = (size_t)nk * nc;
+    const unsigned rowb = (unsigned)(nc * sizeof(T));
+    const unsigned chunkb = (unsigned)(k1 - k0) * rowb;
+    const __amdgpu_buffer_rsrc_t RG = buf_rsrc(f + (size_t)k0 * nc, chunkb);
+    const __amdgpu_buffer_rsrc_t RH = buf_rsrc(f + ho + (size_t)k0 * nc, chunkb);
+    const unsigned so0 = (unsigned)wave * rowb, sostep = (unsigned)WAVES * rowb;
     double acc[4] = {0, 0, 0, 0};
-    int c = ch.c;
-    if (ch.valid) {
-        size_t nc = g.nc, ho = (size_t)vel.nk * nc;
-        int nk = vel.nk;
-        // a wave of the last chunk may hold no velocity (nk mod KCH < WAVES):
-        // its slots keep a valid one for the first prefetch
-        int kk[MK];
-        for (int j = 0; j < MK; ++j) kk[j] = ch.k0;
-        int nmine = 0;
-        for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) kk[nmine++] = k;
-        A dG[MK], dH[MK];
-        for (int j = 0; j < MK; ++j) dG[j] = dH[j] = A(0);
-        bool fluid = !g.solid[c];
-        int ix = c % g.nx, iy = c / g.nx;
-        if (fluid) {
-            // The -x side first.  Its face is also the +x face of the cell on
-            // the left, the previous lane's: the face flux is formed once and
-            // handed down a lane.  (An interior neighbour is a fluid cell
-            // whose face across is interior too, so the lane on the right
-            // forms it; with 64-cell tiles, lane 63's +x side ends a row.)
-            const A sv_x = A(1.0 / g.dx[ix]);
-            const bool take1 = g.nb[g.nc + c] == c + 1 && ch.lane < TILE - 1;
-            {
-                const int code = g.nb[c];
-                FaceConst<A> FC;
-                FaceGeom<T> fg;
-                FaceVals<T> cur{}, nxt{};
-                A lam = A(1), Uw = A(0), Vw = A(0), rw = A(0);
-                const bool far = code == NB_FARFIELD, sym = code == NB_SYMMETRY, wall = is_wall(code);
-                if (code >= 0) {
-                    const double* rec = fp + c;
-                    size_t stride = 2 * nc;
-                    A P[23];
-                    for (int m = 0; m < 23; ++m) P[m] = A(rec[m * stride]);
-                    face_const<A>(P, gas.K_int, FC);
-                    face_geom<T>(g, c, 0, fg);
-                    face_load<T, T>(fg, c, f, ho, (size_t)kk[0] * nc, nxt);
-                } else if (wall) {
-                    int jw = wall_of(code);
-                    lam = A(1.0 / g.w_T[jw]);
-                    Uw = A(g.w_U[jw]);
-                    Vw = A(g.w_V[jw]);
-                    rw = A(rho_w[jw]);
-                }
-                for (int j = 0; j < nmine; ++j) {
-                    int k = kk[j];
-                    A u = vel.u[k], v = vel.v[k];
-                    A PG = A(0), PH = A(0);
-                    if (code >= 0) {
-                        cur = nxt;
-                        if (j + 1 < nmine) face_load<T, T>(fg, c, f, ho, (size_t)kk[j + 1] * nc, nxt);
-                        T Gu, Hu, sGt, sHt;
-                        face_upwind_vals<T, T>(fg, cur, T(u), Gu, Hu, sGt, sHt);
-                        A Gup = Gu, Hup = Hu, sGu = sGt, sHu = sHt;
-                        face_flux<A>(FC, u, v, u, Gup, Hup, sGu, sHu, PG, PH);
-                        dG[j] += A(-1) * sv_x * PG;
-                        dH[j] += A(-1) * sv_x * PH;
-                    } else {
-                        A un = A(-1) * u;
-                        A Gf, Hf;
-                        if (wall && !(un > A(0))) {
-                            A du = u - Uw, dv = v - Vw;
-                            A C = lam / A(M_PI) * dexp(-lam * (du * du + dv * dv));
-                            Gf = rw * C;
-                            Hf = rw * A(gas.K_int) / (A(2) * lam) * C;
-                        } else if (far && un <= A(0)) {
-                            Gf = A(finf[k]);
-                            Hf = A(finf[nk + k]);
-                        } else if (sym && un <= A(0)) {
-                            int km = mirror_of(vel, 0, k);
-                            Gf = A(f[(size_t)km * nc + c]);
-                            Hf = A(f[ho + (size_t)km * nc + c]);
-                        } else {
-                            Gf = A(f[(size_t)k * nc + c]);
-                            Hf = A(f[ho + (size_t)k * nc + c]);
-                        }
-                        dG[j] += sv_x * un * Gf;
-                        dH[j] += sv_x * un * Hf;
-                    }
-                    // the +x side: the face flux of the lane on the right
-                    A nG = __shfl_down(PG, 1, TILE), nH = __shfl_down(PH, 1, TILE);
-                    if (take1) {
-                        dG[j] += A(1) * sv_x * nG;
-                        dH[j] += A(1) * sv_x * nH;
-                    }
-                }
+    A dG[MK], dH[MK];
+#pragma unroll
+    for (int j = 0; j < MK; ++j) dG[j] = dH[j] = A(0);
+    if (valid && !g.solid[c]) {
+        const int ix = c % g.nx, iy = c / g.nx;
+        const unsigned oc = (unsigned)c * sizeof(T);
+        // The -x side first.  Its face is also the +x face of the cell on
+        // the left, the previous lane's: the face flux is formed once and
+        // handed down a lane.  (An interior neighbour is a fluid cell whose
+        // face across is interior too, so the lane on the right forms it;
+        // with 64-cell tiles, lane 63's +x side ends a row.)
+        const A sv_x = A(1.0 / g.dx[ix]);
+        const bool take1 = g.nb[g.nc + c] == c + 1 && lane < TILE - 1;
+        {
+            const int code = g.nb[c];
+            FaceConst<A> FC;
+            FaceStencil<T> st;
+            FaceVals<T> cur{}, nxt{};
+            A lam = A(1), Uw = A(0), Vw = A(0), rw = A(0);
+            const bool far = code == NB_FARFIELD, sym = code == NB_SYMMETRY, wall = is_wall(code);
+            if (code >= 0) {
+                const double* rec = fp + c;
+                const size_t stride = 2 * nc;
+                A P[23];
+                for (int m = 0; m < 23; ++m) P[m] = A(rec[m * stride]);
+                face_const<A>(P, gas.K_int, FC);
+                face_stencil<T>(g, c, 0, st);
+                if (nmine > 0) stencil_load<T>(st, RG, RH, so0, nxt);
+            } else if (wall) {
+                const int jw = wall_of(code);
+                lam = A(1.0 / g.w_T[jw]);
+                Uw = A(g.w_U[jw]);
+                Vw = A(g.w_V[jw]);
+                rw = A(rho_w[jw]);
             }
-            for (int s = 1; s < 4 && own; ++s) {
-                if (s == 1 && take1) continue;
-                int code = g.nb[s * g.nc + c];
-                int d = s >> 1;
-                A sign = (s & 1) ? A(1) : A(-1);
-                A sv = A(1.0 / (d == 0 ? g.dx[ix] : g.dy[iy]));   // S / V
+#pragma unroll
+            for (int j = 0; j < MK; ++j) {
+                if (j >= nmine) break;
+                const int k = k0 + wave + WAVES * j;
+                const unsigned so = so0 + j * sostep;
+                const A u = vel.u[k], v = vel.v[k];
+                const int side = upwind_side(u);
+                A PG = A(0), PH = A(0);
                 if (code >= 0) {
-                    // face record: the -d face of the cell on the positive side
-                    int R = (s & 1) ? code : c;
-                    const double* rec = fp + (size_t)d * g.nc + R;
-                    size_t stride = 2 * nc;
-                    A P[23];
-                    for (int m = 0; m < 23; ++m) P[m] = A(rec[m * stride]);
-                    FaceConst<A> FC;
-                    face_const<A>(P, gas.K_int, FC);
-                    FaceGeom<T> fg;
-                    face_geom<T>(g, R, d, fg);
-                    // the stencil values of the next velocity load while this one computes
-                    FaceVals<T> cur{}, nxt{};
-                    face_load<T, T>(fg, R, f, ho, (size_t)kk[0] * nc, nxt);
-                    for (int j = 0; j < nmine; ++j) {
-                        int k = kk[j];
-                        cur = nxt;
-                        if (j + 1 < nmine) face_load<T, T>(fg, R, f, ho, (size_t)kk[j + 1] * nc, nxt);
-                        A u = vel.u[k], v = vel.v[k];
-                        A un = d == 0 ? u : v;
+                    cur = nxt;
+                    if (j + 1 < nmine) stencil_load<T>(st, RG, RH, so + sostep, nxt);
+                    if (side != 2) {
                         T Gu, Hu, sGt, sHt;
-                        face_upwind_vals<T, T>(fg, cur, T(un), Gu, Hu, sGt, sHt);
-                        A Gup = Gu, Hup = Hu, sGu = sGt, sHu = sHt, PG, PH;
-                        face_flux<A>(FC, u, v, un, Gup, Hup, sGu, sHu, PG, PH);
-                        dG[j] += sign * sv * PG;
-                        dH[j] += sign * sv * PH;
+                        upwind_on_side<T>(st, cur, side, Gu, Hu, sGt, sHt);
+                        face_flux_side<A>(FC, side, u, v, u, A(Gu), A(Hu), A(sGt), A(sHt), etab, PG, PH);
                     }
-                } else if (is_wall(code)) {
-                    int jw = wall_of(code);
-                    A lam = A(1.0 / g.w_T[jw]), Uw = A(g.w_U[jw]), Vw = A(g.w_V[jw]);
-                    A rw = A(rho_w[jw]);
-                    for (int j = 0; j < nmine; ++j) {
-                        int k = kk[j];
-                        A u = vel.u[k], v = vel.v[k];
-                        A un = sign * (d == 0 ? u : v);
-                        A Gf, Hf;
-                        if (un > A(0)) {
-                            Gf = A(f[(size_t)k * nc + c]);
-                            Hf = A(f[ho + (size_t)k * nc + c]);
-                        } else {
-                            A du = u - Uw, dv = v - Vw;
-                            A C = lam / A(M_PI) * dexp(-lam * (du * du + dv * dv));
-                            Gf = rw * C;
-                            Hf = rw * A(gas.K_int) / (A(2) * lam) * C;
-                        }
-                        dG[j] += sv * un * Gf;
-                        dH[j] += sv * un * Hf;
-                    }
+                    dG[j] += A(-1) * sv_x * PG;
+                    dH[j] += A(-1) * sv_x * PH;
                 } else {
-                    bool far = code == NB_FARFIELD, sym = code == NB_SYMMETRY;
-                    for (int j = 0; j < nmine; ++j) {
-                        int k = kk[j];
-                        A un = sign * (d == 0 ? A(vel.u[k]) : A(vel.v[k]));
-                        A Gf, Hf;
-                        if (far && un <= A(0)) {
-                            Gf = A(finf[k]);
-                            Hf = A(finf[nk + k]);
-                        } else if (sym && un <= A(0)) {
-                            // specular reflection: the cell's own value at the mirror velocity
-                            int km = mirror_of(vel, d, k);
-                            Gf = A(f[(size_t)km * nc + c]);
-                            Hf = A(f[ho + (size_t)km * nc + c]);
-                        } else {
-                            Gf = A(f[(size_t)k * nc + c]);
-                            Hf = A(f[ho + (size_t)k * nc + c]);
-                        }
-                        dG[j] += sv * un * Gf;
-                        dH[j] += sv * un * Hf;
+                    const A un = A(-1) * u;
+                    A Gf, Hf;
+                    if (wall && !(un > A(0))) {
+                        const A du = u - Uw, dv = v - Vw;
+                        const A C = lam / A(M_PI) * dexp(-lam * (du * du + dv * dv));
+                        Gf = rw * C;
+                        Hf = rw * A(gas.K_int) / (A(2) * lam) * C;
+                    } else if (far && un <= A(0)) {
+                        Gf = A(finf[k]);
+                        Hf = A(finf[nk + k]);
+                    } else if (sym && un <= A(0)) {
+                        const int km = mirror_of(vel, 0, k);
+                        Gf = A(f[(size_t)km * nc + c]);
+                        Hf = A(f[ho + (size_t)km * nc + c]);
+                    } else {
+                        Gf = A(buf_ld<T>(RG, oc, so));
+                        Hf = A(buf_ld<T>(RH, oc, so));
                     }
+                    dG[j] += sv_x * un * Gf;
+                    dH[j] += sv_x * un * Hf;
+                }
+                // the +x side: the face flux of the lane on the right
+                const A nG = __shfl_down(PG, 1, TILE), nH = __shfl_down(PH, 1, TILE);
+                if (take1) {
+                    dG[j] += A(1) * sv_x * nG;
+                    dH[j] += A(1) * sv_x * nH;
                 }
             }
         }
-        for (int j = 0; j < nmine && own; ++j) {
-            int k = kk[j];
+        for (int s = 1; s < 4 && own; ++s) {
+            if (s == 1 && take1) continue;
+            const int code = g.nb[s * g.nc + c];
+            const int d = s >> 1;
+            const A sign = (s & 1) ? A(1) : A(-1);
+            const A sv = A(1.0 / (d == 0 ? g.dx[ix] : g.dy[iy]));   // S / V
+            if (code >= 0) {
+                // face record: the -d face of the cell on the positive side
+                const int R = (s & 1) ? code : c;
+                const double* rec = fp + (size_t)d * g.nc + R;
+                const size_t stride = 2 * nc;
+                A P[23];
+                for (int m = 0; m < 23; ++m) P[m] = A(rec[m * stride]);
+                FaceConst<A> FC;
+                face_const<A>(P, gas.K_int, FC);
+                FaceStencil<T> st;
+                face_stencil<T>(g, R, d, st);
+                // the stencil values of the next velocity load while this one computes
+                FaceVals<T> cur{}, nxt{};
+                if (nmine > 0) stencil_load<T>(st, RG, RH, so0, nxt);
+#pragma unroll
+                for (int j = 0; j < MK; ++j) {
+                    if (j >= nmine) break;
+                    const int k = k0 + wave + WAVES * j;
+                    const unsigned so = so0 + j * sostep;
+                    cur = nxt;
+                    if (j + 1 < nmine) stencil_load<T>(st, RG, RH, so + sostep, nxt);
+                    const A u = vel.u[k], v = vel.v[k];
+                    const A un = d == 0 ? u : v;
+                    const int side = upwind_side(un);
+                    if (side != 2) {
+                        T Gu, Hu, sGt, sHt;
+                        upwind_on_side<T>(st, cur, side, Gu, Hu, sGt, sHt);
+                        A PG, PH;
+                        face_flux_side<A>(FC, side, u, v, un, A(Gu), A(Hu), A(sGt), A(sHt), etab, PG, PH);
+                        dG[j] += sign * sv * PG;
+                        dH[j] += sign * sv * PH;
+                    }
+                }
+            } else if (is_wall(code)) {
+                const int jw = wall_of(code);
+                const A lam = A(1.0 / g.w_T[jw]), Uw = A(g.w_U[jw]), Vw = A(g.w_V[jw]);
+                const A rw = A(rho_w[jw]);
+#pragma unroll
+                for (int j = 0; j < MK; ++j) {
+                    if (j >= nmine) break;
+                    const int k = k0 + wave + WAVES * j;
+                    const A u = vel.u[k], v = vel.v[k];
+                    const A un = sign * (d == 0 ? u : v);
+                    A Gf, Hf;
+                    if (un > A(0)) {
+                        Gf = A(buf_ld<T>(RG, oc, so0 + j * sostep));
+                        Hf = A(buf_ld<T>(RH, oc, so0 + j * sostep));
+                    } else {
+                        const A du = u - Uw, dv = v - Vw;
+                        const A C = lam / A(M_PI) * dexp(-lam * (du * du + dv * dv));
+                        Gf = rw * C;
+                        Hf = rw * A(gas.K_int) / (A(2) * lam) * C;
+                    }
+                    dG[j] += sv * un * Gf;
+                    dH[j] += sv * un * Hf;
+                }
+            } else {
+                const bool far = code == NB_FARFIELD, sym = code == NB_SYMMETRY;
+#pragma unroll
+                for (int j = 0; j < MK; ++j) {
+                    if (j >= nmine) break;
+                    const int k = k0 + wave + WAVES * j;
+                    const A un = sign * (d == 0 ? A(vel.u[k]) : A(vel.v[k]));
+                    A Gf, Hf;
+                    if (far && un <= A(0)) {
+                        Gf = A(finf[k]);
+                        Hf = A(finf[nk + k]);
+                    } else if (sym && un <= A(0)) {
+                        // specular reflection: the cell's own value at the mirror velocity
+                        const int km = mirror_of(vel, d, k);
+                        Gf = A(f[(size_t)km * nc + c]);
+                        Hf = A(f[ho + (size_t)km * nc + c]);
+                    } else {
+                        Gf = A(buf_ld<T>(RG, oc, so0 + j * sostep));
+                        Hf = A(buf_ld<T>(RH, oc, so0 + j * sostep));
+                    }
+                    dG[j] += sv * un * Gf;
+                    dH[j] += sv * un * Hf;
+                }
+            }
+        }
+    }
+    if (own) {
+#pragma unroll
+        for (int j = 0; j < MK; ++j) {
+            if (j >= nmine) break;
+            const int k = k0 + wave + WAVES * j;
             div[(size_t)k * nc + c] = T(dG[j]);
             div[ho + (size_t)k * nc + c] = T(dH[j]);
-            double w = vel.w[k], u = vel.u[k], v = vel.v[k];
-            double gd = double(dG[j]), hd = double(dH[j]);
+            const double w = vel.w[k], u = vel.u[k], v = vel.v[k];
+            const double gd = double(dG[j]), hd = double(dH[j]);
             acc[0] += w * gd;
             acc[1] += w * u * gd;
             acc[2] += w * v * gd;
             acc[3] += 0.5 * w * ((u * u + v * v) * gd + hd);
         }
     }
-    reduce_store<4>(acc, sh, part, g.nc, c, own, ch.chunk);
+    reduce_store<4>(acc, sh, part, g.nc, c, own, chunk);
 }
 
 // tile stride of k_flux_div and its blocks along the cells
@@ -2504,6 +2672,249 @@ __global__ void __launch_bounds__(256) k_sweep_strips(Geo g, Vel vel, int K_int,
         double sacc = 0.0;
         for (int ww = 0; ww < W; ++ww) sacc += red[(size_t)ww * nw + j];
         wpart[(size_t)blk * nw + j] = sacc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Ordered sweep of one plane in bands of rows, one launch per band.
+//
+// Band b holds the rows b h .. b h + hb - 1 (hb = min(h, ny - b h)) counted in
+// the y-upwind order of each velocity, so a velocity's bands are taken in its
+// own upwind order by successive launches.  Within a band the sweep is that
+// of k_sweep_wave with I = 64 / h velocities per wavefront: lane q h + t0
+// holds row t0 of velocity q, which updates column s - t0 at step s, the
+// y-upwind value carried by the one-lane rotation.  The first row of a band
+// after the first takes its y-upwind value from the last row of the band
+// before, which the launch before stored to df; that row is staged with the
+// band.  A band of one velocity is hb whole rows, contiguous in memory, so
+// it is staged by direct global-to-LDS loads and stored back in one piece.
+// Short bands keep every lane of a wavefront on a cell of the anti-diagonal
+// for all but hb - 1 of the nx + hb - 1 steps (a tall level swept by one
+// wavefront per velocity keeps ny lanes busy only near the middle of its
+// nx + ny - 1 steps).  The per-cell coefficients and side types are read
+// through the caches: the I velocities of a wavefront are consecutive ones
+// of one row of the velocity grid (the same sign of u), so their lanes read
+// the same cells.  Wall ghosts are added to the staged band as in
+// k_sweep_wave; the G plane's wall sums of a block accumulate over the
+// bands in wpart[blk] (the first band writes them).  split as in
+// k_sweep_wave.
+template <typename T>
+__host__ __device__ inline size_t sweep_band_tile_elems(int nx, int h, int nw, int W, int I) {
+    size_t t = (size_t)W * I * h * nx, red = ((size_t)W * nw * sizeof(double) + sizeof(T) - 1) / sizeof(T);
+    return t > red ? t : red;
+}
+
+template <typename T>
+size_t sweep_band_lds_bytes(int nx, int h, int nw, int W, int I) {
+    size_t b = 64 * (size_t)W * sizeof(double) +
+               (sweep_band_tile_elems<T>(nx, h, nw, W, I) + (size_t)W * I * nx + nx + 5 * (size_t)nw) * sizeof(T) +
+               4 * (size_t)nw;
+    return (b + 15) & ~(size_t)15;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_sweep_band(Geo g, Vel vel, int K_int, const T* __restrict__ r,
+                                                    T* __restrict__ df, const T* __restrict__ coef_g,
+                                                    const unsigned char* __restrict__ stype,
+                                                    const double* __restrict__ drho, double* __restrict__ wpart,
+                                                    int I, int h, int b, int nvrow, int split) {
+    extern __shared__ __attribute__((aligned(16))) double smem_d[];
+    const int nc = g.nc, nx = g.nx, ny = g.ny, nw = g.n_wall, nk = vel.nk;
+    const int W = blockDim.x >> 6, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int hb = min(h, ny - b * h);                      // rows of this band
+    const size_t tsz = (size_t)h * nx;                      // tile elements per velocity
+    double* dsum = smem_d;                                  // [64 W]  words of lanes off the diagonal
+    T* tiles = (T*)(smem_d + 64 * W);                       // [W][I][h][nx]
+    T* edge = tiles + sweep_band_tile_elems<T>(nx, h, nw, W, I);   // [W][I][nx]  the row before the band
+    T* invdx = edge + (size_t)W * I * nx;                   // [nx]
+    T* wl = invdx + nx;                                     // [5][n_wall]  1/d, lam_w, U_w, V_w, drho
+    int* wsc = (int*)(wl + 5 * (size_t)nw);                 // [n_wall]  side + 4 cell
+    const int nbG = split ? (int)(gridDim.x >> 1) : (int)gridDim.x;
+    const int plane = (int)blockIdx.x >= nbG ? 1 : 0;
+    const int blk = (int)blockIdx.x - plane * nbG;
+    // velocities: wavefronts of I consecutive ones along a row of the
+    // velocity grid (wpr wavefronts, bpr blocks per row)
+    const int wpr = (nvrow + I - 1) / I, bpr = (wpr + W - 1) / W;
+    const int ku = blk / bpr, wi = (blk - ku * bpr) * W + w;
+    const int kv0 = wi * I, k0 = ku * nvrow + kv0;
+    const int nq = wi < wpr ? min(I, nvrow - kv0) : 0;      // velocities this wavefront holds
+    const T* rp = r + (size_t)plane * nk * nc;
+    T* dfp = df + (size_t)plane * nk * nc;
+    T* tw = tiles + (size_t)w * I * tsz;
+    T* ew = edge + (size_t)w * I * nx;
+    // first physical row of the band of a velocity whose v has sign py, and
+    // the physical row before it in that velocity's order
+    auto band_y0 = [&](bool py) { return py ? b * h : ny - b * h - hb; };
+    auto prev_y = [&](bool py) { return py ? b * h - 1 : ny - b * h; };
+    // every load of the prologue is issued before the first wait
+    for (int q = 0; q < nq; ++q) {
+        const bool pyq = vel_v<T>(vel, k0 + q) >= T(0);
+        const size_t kq = (size_t)(k0 + q) * nc;
+        wave_load_lds<T>(tw + q * tsz, rp + kq + (size_t)band_y0(pyq) * nx, hb * nx, lane);
+        if (b > 0) wave_load_lds<T>(ew + (size_t)q * nx, dfp + kq + (size_t)prev_y(pyq) * nx, nx, lane);
+    }
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) invdx[i] = T(1.0 / g.dx[i]);
+    for (int j = threadIdx.x; j < nw; j += blockDim.x) {
+        wl[j] = T(g.w_invd[j]);
+        wl[nw + j] = T(1.0 / g.w_T[j]);
+        wl[2 * nw + j] = T(g.w_U[j]);
+        wl[3 * nw + j] = T(g.w_V[j]);
+        wl[4 * nw + j] = drho ? T(drho[j]) : T(0);
+        wsc[j] = g.w_side[j] + 4 * g.w_cell[j];
+    }
+    // velocities of this wavefront: lane q < nq holds velocity k0 + q
+    const T uq_l = lane < nq ? vel_u<T>(vel, k0 + lane) : T(0);
+    const T vq_l = lane < nq ? vel_v<T>(vel, k0 + lane) : T(0);
+    __syncthreads();
+    // upwind wall-ghost terms of the band's wall cells into r (x-sides, then
+    // y-sides; the barriers are reached by every wavefront of the block)
+    if (drho) {
+        for (int jb = 0; jb < nw; jb += 64) {
+            const int j = jb + lane;
+            const bool ok = j < nw;
+            int sd = 0, cell = 0;
+            T invd = T(0), lam = T(1), wu = T(0), wv = T(0), dr = T(0);
+            if (ok) {
+                sd = wsc[j] & 3;
+                cell = wsc[j] >> 2;
+                invd = wl[j];
+                lam = wl[nw + j];
+                wu = wl[2 * nw + j];
+                wv = wl[3 * nw + j];
+                dr = wl[4 * nw + j];
+            }
+            const int iyc = cell / nx;
+            for (int dir = 0; dir < 2; ++dir) {
+                for (int q = 0; q < nq; ++q) {
+                    const T u = __shfl(uq_l, q, 64), v = __shfl(vq_l, q, 64);
+                    const T un = ((sd & 1) ? T(1) : T(-1)) * (sd < 2 ? u : v);
+                    const int y0 = band_y0(v >= T(0));
+                    if (ok && (sd >> 1) == dir && un < T(0) && iyc >= y0 && iyc < y0 + hb) {
+                        const T du = u - wu, dv = v - wv;
+                        T C = lam / T(M_PI) * dexp(-lam * (du * du + dv * dv));
+                        if (plane) C = C * (T(K_int) / (T(2) * lam));
+                        tw[(size_t)q * tsz + (size_t)(iyc - y0) * nx + cell % nx] += (-un * invd) * (C * dr);
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+
+    const int q = lane / h;
+    const bool live = q < nq;
+    const int qq = live ? q : 0;
+    const int t0 = lane - q * h;                            // row within the band
+    const T u = __shfl(uq_l, qq, 64), v = __shfl(vq_l, qq, 64);
+    const bool px = u >= T(0), py = v >= T(0);
+    const int shx = px ? 0 : 2, shy = py ? 4 : 6;           // bit offset of the upwind x / y side type
+    const T au = px ? u : -u, av = py ? v : -v;
+    const bool rowok = live && t0 < hb;
+    const int y0 = band_y0(py);
+    const int iy = rowok ? (py ? b * h + t0 : ny - 1 - b * h - t0) : y0;   // physical row
+    const int trow = iy - y0;                               // its tile row
+    const T by = rowok ? av * T(1.0 / g.dy[iy]) : T(0);
+    // the band's first row takes its y-upwind value from the row before
+    const bool first = t0 == 0 && b > 0;
+    T* tG = tw + (size_t)qq * tsz + (size_t)trow * nx;
+    const T* eG = ew + (size_t)qq * nx;
+    const unsigned char* srow = stype + (size_t)iy * nx;
+    const T* crow = coef_g + (size_t)iy * nx;
+    T cG = T(0);
+    struct Ahead {
+        T cf, idx, rG, ey;
+        unsigned sc;
+    };
+    // a lane outside the current diagonal fetches the dummy column t0 mod nx
+    const int dcol = t0 % nx;
+    auto fetch = [&](Ahead& n, int jx) {
+        const int jc = (jx < 0 || jx >= nx) ? dcol : jx;
+        const int ix = px ? jc : nx - 1 - jc;
+        n.cf = crow[ix];
+        n.sc = srow[ix];
+        n.idx = invdx[ix];
+        n.rG = tG[ix];
+        n.ey = eG[ix];
+    };
+    T* dump = (T*)dsum + 64 * w + lane;
+    Ahead nA, nB, nC, nD;
+    fetch(nA, -t0);
+    fetch(nB, 1 - t0);
+    fetch(nC, 2 - t0);
+    // step s with the data in d; fill receives those of step s + 3
+    auto step = [&](int s, const Ahead& d, Ahead& fill) {
+        const T rot = lane_rotate1(cG);
+        const int jx = s - t0;
+        const bool valid = rowok && (unsigned)jx < (unsigned)nx;
+        const int ix = px ? jx : nx - 1 - jx;
+        fetch(fill, jx + 3);
+        const T nbG = first ? d.ey : rot;
+        const unsigned tpx = (d.sc >> shx) & 3u, tpy = (d.sc >> shy) & 3u;
+        const T bx = au * d.idx;
+        // transport diagonal: every downwind side, and an upwind side only if
+        // it is an outflow (where the two cancel)
+        const T D = d.cf + (tpx == 3u ? T(0) : bx) + (tpy == 3u ? T(0) : by);
+        const T inv = sweep_rcp(D);
+        const T exG = tpx == 0u ? cG : T(0), eyG = tpy == 0u ? nbG : T(0);
+        T vG = (d.rG + bx * exG + by * eyG) * inv;
+        vG = d.cf < T(0) ? T(0) : vG;
+        *(valid ? tG + ix : dump) = vG;
+        cG = vG;
+    };
+    const int nsteps = nx + hb - 1;
+    int s = 0;
+    for (; s + 3 < nsteps; s += 4) {
+        step(s, nA, nD);
+        step(s + 1, nB, nA);
+        step(s + 2, nC, nB);
+        step(s + 3, nD, nC);
+    }
+    if (s < nsteps) step(s, nA, nD);
+    if (s + 1 < nsteps) step(s + 1, nB, nA);
+    if (s + 2 < nsteps) step(s + 2, nC, nB);
+    __syncthreads();
+    for (int qv = 0; qv < nq; ++qv) {
+        const bool pyq = vel_v<T>(vel, k0 + qv) >= T(0);
+        wave_store<T>(dfp + (size_t)(k0 + qv) * nc + (size_t)band_y0(pyq) * nx, tw + qv * tsz, hb * nx, lane);
+    }
+    // the H plane leaves no wall partial sums (uniform over the block)
+    if (plane) return;
+    // per-wavefront sums over its velocities of w_k u_n dG_k at the wall
+    // sides of its bands
+    const double ud = lane < nq ? vel.u[k0 + lane] : 0.0, vd = lane < nq ? vel.v[k0 + lane] : 0.0,
+                 wd = lane < nq ? vel.w[k0 + lane] : 0.0;
+    double wsum[SWEEP_WAVE_MAX_WALLS / 64];
+#pragma unroll
+    for (int jc = 0; jc < SWEEP_WAVE_MAX_WALLS / 64; ++jc) {
+        const int j = jc * 64 + lane;
+        const bool ok = j < nw;
+        const int sd = ok ? wsc[j] & 3 : 0, cell = ok ? wsc[j] >> 2 : 0;
+        const int iyc = cell / nx;
+        double sum = 0.0;
+        if (jc * 64 < nw)
+            for (int qv = 0; qv < nq; ++qv) {
+                const double uu = __shfl(ud, qv, 64), vv = __shfl(vd, qv, 64), ww = __shfl(wd, qv, 64);
+                const double un = ((sd & 1) ? 1.0 : -1.0) * (sd < 2 ? uu : vv);
+                const int yq = band_y0(__shfl(vq_l, qv, 64) >= T(0));
+                if (ok && un > 0.0 && iyc >= yq && iyc < yq + hb)
+                    sum += ww * un * double(tw[(size_t)qv * tsz + (size_t)(iyc - yq) * nx + cell % nx]);
+            }
+        wsum[jc] = sum;
+    }
+    __syncthreads();   // every tile is read: the sums go where the tiles were
+    double* red = (double*)tiles;   // [W][n_wall]
+#pragma unroll
+    for (int jc = 0; jc < SWEEP_WAVE_MAX_WALLS / 64; ++jc) {
+        const int j = jc * 64 + lane;
+        if (j < nw) red[(size_t)w * nw + j] = wsum[jc];
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < nw; j += blockDim.x) {
+        double sacc = 0.0;
+        for (int ww = 0; ww < W; ++ww) sacc += red[(size_t)ww * nw + j];
+        // a block's sums accumulate over the bands (launches in order)
+        double* wp = wpart + (size_t)blk * nw + j;
+        *wp = (b > 0 ? *wp : 0.0) + sacc;
     }
 }
 

@@ -157,6 +157,7 @@ struct miugks_ctx {
         // LDS); split: the G and H planes as separate blocks of a one-plane sweep
         bool gc = false, split = false;
         int strips = 0;   // > 0: k_sweep_strips over that many strips of columns
+        int bands = 0, bh = 0;   // > 0: k_sweep_band, that many bands of bh rows (one launch each)
     };
     std::vector<unsigned char*> stype;
     std::vector<void*> coefT;   // 1/tau + 1/dt_n per level in the distribution's type
@@ -403,6 +404,11 @@ hipError_t set_strips_lds(int prec, int R, int bytes) {
     return prec == MIUGKS_FP64 ? set_strips_lds_t<double>(R, bytes) : set_strips_lds_t<float>(R, bytes);
 }
 
+hipError_t set_band_lds(int prec, int bytes) {
+    return hipFuncSetAttribute(prec == MIUGKS_FP64 ? (const void*)k_sweep_band<double> : (const void*)k_sweep_band<float>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
 hipError_t set_wave_lds(int prec, int R, int np, int bytes) {
     hipError_t e;
     if (prec == MIUGKS_FP64) {
@@ -502,7 +508,7 @@ struct Path {
         // the wall densities from the last sweep's partial sums: inside the
         // wavefront sweep where they are few, else by k_drho
         // (the sweep's prologue takes one thread per wall side)
-        const bool in_sweep = !drho_current && g.n_wall && wc.W && g.n_wall <= 64 * wc.W &&
+        const bool in_sweep = !drho_current && g.n_wall && wc.W && !wc.bands && g.n_wall <= 64 * wc.W &&
                               (long)c->wparts[l] * g.n_wall <= 16L * 64 * wc.W && !getenv("MIUGKS_DRHO_KERNEL");
         if (!drho_current && g.n_wall && !in_sweep)
             LAUNCH(c, "drho", (double)g.n_wall * c->wparts[l] * 8, k_drho, dim3((g.n_wall + 3) / 4), dim3(256), g,
@@ -536,6 +542,19 @@ struct Path {
             }
 #undef MIUGKS_STREAM_LAUNCH
             c->wparts[l] = wc.blocks;
+        } else if (wc.W && wc.bands) {
+            // one launch per band, in every velocity's upwind order; each
+            // reads the last row of the band before from df
+            const int nblk = wc.split ? wc.blocks / 2 : wc.blocks;
+            for (int b = 0; b < wc.bands; ++b) {
+                const int hb = std::min(wc.bh, g.ny - b * wc.bh);
+                LAUNCH_SH(c, name, (wc.split ? 2 : 1) * arr(c, l) * hb / g.ny, wc.lds, k_sweep_band<T>,
+                          dim3(wc.blocks), dim3(64 * wc.W), g, c->vel, c->gas.K_int, (const T*)c->r[l],
+                          (T*)c->df[l], (const T*)c->coefT[l], c->stype[l],
+                          from_zero ? (const double*)nullptr : (const double*)c->drho[l], c->wbuf[l], wc.I, wc.bh,
+                          b, c->nv, wc.split ? 1 : 0);
+            }
+            c->wparts[l] = nblk;
         } else if (wc.W && wc.strips) {
 #define MIUGKS_STRIPS_LAUNCH(RR)                                                                                 \
     LAUNCH_SH(c, name, (wc.split ? 2 : 1) * arr(c, l), wc.lds, (k_sweep_strips<T, RR>), dim3(wc.blocks),           \
@@ -1268,10 +1287,59 @@ int build_device(miugks_ctx* ctx) {
                     }
                     if (gw.W) wc = gw;
                 }
+                // levels of more than 32 rows: the sweep in bands of rows
+                // (k_sweep_band, one launch per band), I = 64 / bh velocities
+                // per wavefront.  Band height and block width are taken for
+                // the fewest steps over all rounds of blocks, each step
+                // counted alike (a step of one row slot).  MIUGKS_SWEEP_BANDS=0
+                // keeps the forms above, =h forces the band height on every
+                // level of more than h rows (forcing strips or the cached
+                // whole tile keeps those).
+                const char* be = getenv("MIUGKS_SWEEP_BANDS");
+                const int force_h = be ? atoi(be) : -1;
+                if (((h.ny > 32 && force_h != 0) || (force_h > 0 && force_h <= 64 && h.ny > force_h)) && !force_gc &&
+                    force_s <= 0) {
+                    miugks_ctx::WaveCfg bw;
+                    long best_cost = 0;
+                    std::vector<int> heights = {32, 21, 16, 13, 12, 10, 8};
+                    if (force_h > 0) heights = {force_h};
+                    for (int bh : heights) {
+                        if (bh >= h.ny) continue;
+                        const int I = 64 / bh, nb = (h.ny + bh - 1) / bh;
+                        const long wpr = (ctx->nv + I - 1) / I;
+                        for (int W : {1, 2, 4}) {
+                            if (force_w && W != force_w) continue;
+                            size_t need =
+                                ctx->prec == MIUGKS_FP64
+                                    ? sweep_band_lds_bytes<double>(h.nx, bh, (int)h.w_cell.size(), W, I)
+                                    : sweep_band_lds_bytes<float>(h.nx, bh, (int)h.w_cell.size(), W, I);
+                            if (need > (size_t)max_lds) continue;
+                            const long per_cu = std::min<long>((long)max_lds / (long)need, 32 / W);
+                            const long nblk = (long)ctx->nu * ((wpr + W - 1) / W) * (np == 2 ? 2 : 1);
+                            const long rounds = (nblk + (long)cus * per_cu - 1) / ((long)cus * per_cu);
+                            const long cost = (long)nb * rounds * (h.nx + bh - 1);
+                            if (!bw.W || cost < best_cost) {
+                                bw = miugks_ctx::WaveCfg();
+                                bw.W = W;
+                                bw.I = I;
+                                bw.R = 1;
+                                bw.gc = true;
+                                bw.split = np == 2;
+                                bw.bands = nb;
+                                bw.bh = bh;
+                                bw.lds = need;
+                                bw.blocks = (int)nblk;
+                                best_cost = cost;
+                            }
+                        }
+                    }
+                    if (bw.W) wc = bw;
+                }
                 if (wc.W) {
                     // strips: one row of the velocity grid per block
-                    wc.blocks = wc.strips ? ctx->nu * ((ctx->nv + wc.W - 1) / wc.W) * (wc.split ? 2 : 1)
-                                          : (nwaves + wc.W - 1) / wc.W * (wc.split ? 2 : 1);
+                    if (!wc.bands)
+                        wc.blocks = wc.strips ? ctx->nu * ((ctx->nv + wc.W - 1) / wc.W) * (wc.split ? 2 : 1)
+                                              : (nwaves + wc.W - 1) / wc.W * (wc.split ? 2 : 1);
                     (np == 2 ? ctx->wave : ctx->wave1)[l] = wc;
                     wave_need_max = std::max(wave_need_max, wc.lds);
                 }
@@ -1316,6 +1384,7 @@ int build_device(miugks_ctx* ctx) {
             for (int np = 1; np <= 2 && e == hipSuccess; ++np) e = set_wave_lds(ctx->prec, R, np, (int)wave_need_max);
             if (e == hipSuccess) e = set_strips_lds(ctx->prec, R, (int)wave_need_max);
         }
+        if (e == hipSuccess) e = set_band_lds(ctx->prec, (int)wave_need_max);
         if (e != hipSuccess)
             for (int l = 0; l < ctx->L; ++l)
                 if ((!ctx->wave[l].stream && ctx->wave[l].lds > 65536) ||
@@ -1736,6 +1805,12 @@ int miugks_create(miugks_ctx** out, const miugks_mesh_desc* m, const miugks_vgri
     }
     if (m->ny > 1024) {
         g_create_error = "ny > 1024 is not supported by the ordered sweep";
+        delete ctx;
+        return MIUGKS_EINVAL;
+    }
+    // the interface flux addresses a velocity chunk's rows with 32-bit byte offsets
+    if (m->nx < 1 || m->ny < 1 || (size_t)m->nx * m->ny * miugks::KCH * sizeof(double) >= (size_t(1) << 31)) {
+        g_create_error = "mesh too large: nx * ny must stay below 2^23 cells";
         delete ctx;
         return MIUGKS_EINVAL;
     }
