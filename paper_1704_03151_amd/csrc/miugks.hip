@@ -1287,51 +1287,51 @@ int build_device(miugks_ctx* ctx) {
                     }
                     if (gw.W) wc = gw;
                 }
-                // levels of more than 32 rows: the sweep in bands of rows
-                // (k_sweep_band, one launch per band), I = 64 / bh velocities
-                // per wavefront.  Band height and block width are taken for
-                // the fewest steps over all rounds of blocks, each step
-                // counted alike (a step of one row slot).  MIUGKS_SWEEP_BANDS=0
-                // keeps the forms above, =h forces the band height on every
-                // level of more than h rows (forcing strips or the cached
-                // whole tile keeps those).
+                // tall levels: the sweep in bands of rows (k_sweep_band, one
+                // launch per band), I = 64 / bh velocities per wavefront, one
+                // wavefront per block.  Measured on the three workloads: the
+                // tallest band whose tile leaves room for at least three
+                // blocks per CU in FP32 (two in FP64) is the fastest (a taller
+                // band means fewer launches and fewer steps per velocity, but
+                // fewer resident wavefronts); levels of at most 64 rows sweep
+                // faster as one tile in FP32 (in FP64 from 64 rows the bands
+                // win).  MIUGKS_SWEEP_BANDS=0 keeps the forms above, =h forces
+                // the band height on every level of more than h rows (forcing
+                // strips or the cached whole tile keeps those).
                 const char* be = getenv("MIUGKS_SWEEP_BANDS");
                 const int force_h = be ? atoi(be) : -1;
-                if (((h.ny > 32 && force_h != 0) || (force_h > 0 && force_h <= 64 && h.ny > force_h)) && !force_gc &&
-                    force_s <= 0) {
+                const int band_min_ny = ctx->prec == MIUGKS_FP64 ? 64 : 65;
+                if (((h.ny >= band_min_ny && force_h != 0) || (force_h > 0 && force_h <= 64 && h.ny > force_h)) &&
+                    !force_gc && force_s <= 0) {
                     miugks_ctx::WaveCfg bw;
-                    long best_cost = 0;
+                    long best_per_cu = 0;
+                    const long want_per_cu = ctx->prec == MIUGKS_FP64 ? 2 : 3;
                     std::vector<int> heights = {32, 21, 16, 13, 12, 10, 8};
                     if (force_h > 0) heights = {force_h};
                     for (int bh : heights) {
                         if (bh >= h.ny) continue;
                         const int I = 64 / bh, nb = (h.ny + bh - 1) / bh;
                         const long wpr = (ctx->nv + I - 1) / I;
-                        for (int W : {1, 2, 4}) {
-                            if (force_w && W != force_w) continue;
-                            size_t need =
-                                ctx->prec == MIUGKS_FP64
-                                    ? sweep_band_lds_bytes<double>(h.nx, bh, (int)h.w_cell.size(), W, I)
-                                    : sweep_band_lds_bytes<float>(h.nx, bh, (int)h.w_cell.size(), W, I);
-                            if (need > (size_t)max_lds) continue;
-                            const long per_cu = std::min<long>((long)max_lds / (long)need, 32 / W);
-                            const long nblk = (long)ctx->nu * ((wpr + W - 1) / W) * (np == 2 ? 2 : 1);
-                            const long rounds = (nblk + (long)cus * per_cu - 1) / ((long)cus * per_cu);
-                            const long cost = (long)nb * rounds * (h.nx + bh - 1);
-                            if (!bw.W || cost < best_cost) {
-                                bw = miugks_ctx::WaveCfg();
-                                bw.W = W;
-                                bw.I = I;
-                                bw.R = 1;
-                                bw.gc = true;
-                                bw.split = np == 2;
-                                bw.bands = nb;
-                                bw.bh = bh;
-                                bw.lds = need;
-                                bw.blocks = (int)nblk;
-                                best_cost = cost;
-                            }
+                        const int W = force_w ? force_w : 1;
+                        size_t need = ctx->prec == MIUGKS_FP64
+                                          ? sweep_band_lds_bytes<double>(h.nx, bh, (int)h.w_cell.size(), W, I)
+                                          : sweep_band_lds_bytes<float>(h.nx, bh, (int)h.w_cell.size(), W, I);
+                        if (need > (size_t)max_lds) continue;
+                        const long per_cu = (long)max_lds / (long)need;
+                        if (!bw.W || per_cu > best_per_cu) {
+                            bw = miugks_ctx::WaveCfg();
+                            bw.W = W;
+                            bw.I = I;
+                            bw.R = 1;
+                            bw.gc = true;
+                            bw.split = np == 2;
+                            bw.bands = nb;
+                            bw.bh = bh;
+                            bw.lds = need;
+                            bw.blocks = (int)((long)ctx->nu * ((wpr + W - 1) / W) * (np == 2 ? 2 : 1));
+                            best_per_cu = per_cu;
                         }
+                        if (per_cu >= want_per_cu) break;
                     }
                     if (bw.W) wc = bw;
                 }
