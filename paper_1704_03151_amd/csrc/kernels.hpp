@@ -696,24 +696,134 @@ __device__ __forceinline__ bool face_upwind(const Geo& g, int c, int d, const T*
     return true;
 }
 
+// Raw buffer resource over `bytes` bytes from p.  The stencil loads of the
+// interface flux go through one per distribution plane and velocity chunk:
+// a lane's byte offset (a cell) in a vector register, the velocity's row
+// offset in a scalar one, so a load costs no vector address arithmetic.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
+// A face's reconstruction stencil as byte offsets within a plane row: L and
+// the cell R on either side, L's far neighbour LL and R's far neighbour RR
+// (an absent far neighbour reads its near one, with its inverse distance
+// zero, so that the one-sided difference vanishes)
+template <typename T>
+struct FaceStencil {
+    unsigned oL, oR, oLL, oRR;
+    T idc, idcL, idcR, dL, dR;
+};
+
+template <typename T, typename A = T>
+__device__ __forceinline__ void face_stencil(const Geo& g, int c, int d, FaceStencil<A>& s) {
+    FaceGeom<A> fg;
+    face_geom<A>(g, c, d, fg);
+    s.oL = (unsigned)fg.L * sizeof(T);
+    s.oR = (unsigned)c * sizeof(T);
+    s.oLL = (unsigned)(fg.LL >= 0 ? fg.LL : fg.L) * sizeof(T);
+    s.oRR = (unsigned)(fg.RR >= 0 ? fg.RR : c) * sizeof(T);
+    s.idc = fg.idc;
+    s.idcL = fg.idcL;
+    s.idcR = fg.idcR;
+    s.dL = fg.dL;
+    s.dR = fg.dR;
+}
+
+template <typename T, typename A = T>
+__device__ __forceinline__ void stencil_load(const FaceStencil<A>& s, __amdgpu_buffer_rsrc_t RG,
+                                             __amdgpu_buffer_rsrc_t RH, unsigned so, FaceVals<T>& q) {
+    q.GL = buf_ld<T>(RG, s.oL, so);
+    q.GR = buf_ld<T>(RG, s.oR, so);
+    q.HL = buf_ld<T>(RH, s.oL, so);
+    q.HR = buf_ld<T>(RH, s.oR, so);
+    q.GLL = buf_ld<T>(RG, s.oLL, so);
+    q.HLL = buf_ld<T>(RH, s.oLL, so);
+    q.GRR = buf_ld<T>(RG, s.oRR, so);
+    q.HRR = buf_ld<T>(RH, s.oRR, so);
+}
+
+// side of a face's upwind cell for a normal velocity un (the same in every
+// lane): 0 for un > 0 (L), 1 for un < 0 (R), 2 for un = 0
+__device__ __forceinline__ int upwind_side(double un) {
+    return __builtin_amdgcn_readfirstlane(un > 0.0 ? 0 : (un < 0.0 ? 1 : 2));
+}
+
+// limited slope and interface value on the upwind side (face_upwind_vals
+// with the side known for the whole wavefront: only that side's slope is
+// formed), in A from the stored values
+template <typename T, typename A = T>
+__device__ __forceinline__ void upwind_on_side(const FaceStencil<A>& s, const FaceVals<T>& q, int side, A& Gup,
+                                               A& Hup, A& sGup, A& sHup) {
+    const A GL = A(q.GL), GR = A(q.GR), HL = A(q.HL), HR = A(q.HR);
+    A gLR = (GR - GL) * s.idc, hLR = (HR - HL) * s.idc;
+    if (side == 0) {
+        A gm = (GL - A(q.GLL)) * s.idcL, hm = (HL - A(q.HLL)) * s.idcL;
+        sGup = van_leer_fast(gm, gLR);
+        sHup = van_leer_fast(hm, hLR);
+        Gup = GL + sGup * s.dL;
+        Hup = HL + sHup * s.dL;
+    } else if (side == 1) {
+        A gp = (A(q.GRR) - GR) * s.idcR, hp = (A(q.HRR) - HR) * s.idcR;
+        sGup = van_leer_fast(gLR, gp);
+        sHup = van_leer_fast(hLR, hp);
+        Gup = GR - sGup * s.dR;
+        Hup = HR - sHup * s.dR;
+    } else {
+        A gm = (GL - A(q.GLL)) * s.idcL, hm = (HL - A(q.HLL)) * s.idcL;
+        A gp = (A(q.GRR) - GR) * s.idcR, hp = (A(q.HRR) - HR) * s.idcR;
+        A sGL = van_leer_fast(gm, gLR), sHL = van_leer_fast(hm, hLR);
+        A sGR = van_leer_fast(gLR, gp), sHR = van_leer_fast(hLR, hp);
+        Gup = A(0.5) * (GL + sGL * s.dL + GR - sGR * s.dR);
+        Hup = A(0.5) * (HL + sHL * s.dL + HR - sHR * s.dR);
+        sGup = A(0.5) * (sGL + sGR);
+        sHup = A(0.5) * (sHL + sHR);
+    }
+}
+
 // raw moments of the upwind interface distribution of the -x and -y faces
-// (interface values formed in double from the stored distribution)
+// (interface values formed in double from the stored distribution).  The
+// velocity is the same in every lane: the upwind side is a scalar branch and
+// the stencil loads take scalar row offsets (as in k_flux_div).
 template <typename T>
 __global__ void __launch_bounds__(256) k_face_moments_partial(Geo g, Vel vel, const T* __restrict__ f,
                                                               double* __restrict__ part) {
     __shared__ double sh[2 * NRAW * WAVES * TILE];
     Chunk ch = chunk_of_xcd(g.nc, vel.nk);
+    const int wave = __builtin_amdgcn_readfirstlane(ch.wave);
+    const int k0 = __builtin_amdgcn_readfirstlane(ch.k0), k1 = __builtin_amdgcn_readfirstlane(ch.k1);
+    const size_t nc = g.nc, ho = (size_t)vel.nk * nc;
+    const unsigned rowb = (unsigned)(nc * sizeof(T));
+    const unsigned chunkb = (unsigned)(k1 - k0) * rowb;
+    const __amdgpu_buffer_rsrc_t RG = buf_rsrc(f + (size_t)k0 * nc, chunkb);
+    const __amdgpu_buffer_rsrc_t RH = buf_rsrc(f + ho + (size_t)k0 * nc, chunkb);
     double a[2 * NRAW];
     for (int m = 0; m < 2 * NRAW; ++m) a[m] = 0.0;
     if (ch.valid && !g.solid[ch.c]) {
-        const size_t ho = (size_t)vel.nk * g.nc;
         for (int d = 0; d < 2; ++d) {
-            FaceGeom<double> fg;
-            if (!face_geom<double>(g, ch.c, d, fg)) continue;
-            for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
-                double u = vel.u[k], v = vel.v[k], w = vel.w[k];
+            if (g.nb[(2 * d) * g.nc + ch.c] < 0) continue;   // not an interior face
+            FaceStencil<double> st;
+            face_stencil<T, double>(g, ch.c, d, st);
+            // the stencil values of the next velocity load while this one computes
+            FaceVals<T> cur{}, nxt{};
+            int k = k0 + wave;
+            if (k < k1) stencil_load<T, double>(st, RG, RH, (unsigned)(k - k0) * rowb, nxt);
+            for (; k < k1; k += WAVES) {
+                cur = nxt;
+                if (k + WAVES < k1) stencil_load<T, double>(st, RG, RH, (unsigned)(k + WAVES - k0) * rowb, nxt);
+                const double u = vel.u[k], v = vel.v[k], w = vel.w[k];
+                const int side = upwind_side(d == 0 ? u : v);
                 double Gup, Hup, sG, sH;
-                face_upwind_k<T, double>(fg, ch.c, f, ho, (size_t)k * g.nc, d == 0 ? u : v, Gup, Hup, sG, sH);
+                upwind_on_side<T, double>(st, cur, side, Gup, Hup, sG, sH);
                 raw_accumulate(a + d * NRAW, w, u, v, Gup, Hup);
             }
         }
@@ -1156,99 +1266,6 @@ __device__ __forceinline__ void face_flux(const FaceConst<T>& F, T u, T v, T un,
     T bH = bG + F.dH[2];
     PG = un * (F.q[0] * Geq + F.q[1] * un * aG * G0 + F.q[2] * bG * G0 + F.q[3] * Gup + F.q[4] * un * sGup);
     PH = un * (F.q[0] * Heq + F.q[1] * un * aH * H0 + F.q[2] * bH * H0 + F.q[3] * Hup + F.q[4] * un * sHup);
-}
-
-// Raw buffer resource over `bytes` bytes from p.  The stencil loads of the
-// interface flux go through one per distribution plane and velocity chunk:
-// a lane's byte offset (a cell) in a vector register, the velocity's row
-// offset in a scalar one, so a load costs no vector address arithmetic.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, unsigned bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
-}
-template <typename T>
-__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
-template <>
-__device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
-}
-template <>
-__device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
-}
-
-// A face's reconstruction stencil as byte offsets within a plane row: L and
-// the cell R on either side, L's far neighbour LL and R's far neighbour RR
-// (an absent far neighbour reads its near one, with its inverse distance
-// zero, so that the one-sided difference vanishes)
-template <typename T>
-struct FaceStencil {
-    unsigned oL, oR, oLL, oRR;
-    T idc, idcL, idcR, dL, dR;
-};
-
-template <typename T>
-__device__ __forceinline__ void face_stencil(const Geo& g, int c, int d, FaceStencil<T>& s) {
-    FaceGeom<T> fg;
-    face_geom<T>(g, c, d, fg);
-    s.oL = (unsigned)fg.L * sizeof(T);
-    s.oR = (unsigned)c * sizeof(T);
-    s.oLL = (unsigned)(fg.LL >= 0 ? fg.LL : fg.L) * sizeof(T);
-    s.oRR = (unsigned)(fg.RR >= 0 ? fg.RR : c) * sizeof(T);
-    s.idc = fg.idc;
-    s.idcL = fg.idcL;
-    s.idcR = fg.idcR;
-    s.dL = fg.dL;
-    s.dR = fg.dR;
-}
-
-template <typename T>
-__device__ __forceinline__ void stencil_load(const FaceStencil<T>& s, __amdgpu_buffer_rsrc_t RG,
-                                             __amdgpu_buffer_rsrc_t RH, unsigned so, FaceVals<T>& q) {
-    q.GL = buf_ld<T>(RG, s.oL, so);
-    q.GR = buf_ld<T>(RG, s.oR, so);
-    q.HL = buf_ld<T>(RH, s.oL, so);
-    q.HR = buf_ld<T>(RH, s.oR, so);
-    q.GLL = buf_ld<T>(RG, s.oLL, so);
-    q.HLL = buf_ld<T>(RH, s.oLL, so);
-    q.GRR = buf_ld<T>(RG, s.oRR, so);
-    q.HRR = buf_ld<T>(RH, s.oRR, so);
-}
-
-// side of a face's upwind cell for a normal velocity un (the same in every
-// lane): 0 for un > 0 (L), 1 for un < 0 (R), 2 for un = 0
-__device__ __forceinline__ int upwind_side(double un) {
-    return __builtin_amdgcn_readfirstlane(un > 0.0 ? 0 : (un < 0.0 ? 1 : 2));
-}
-
-// limited slope and interface value on the upwind side (face_upwind_vals
-// with the side known for the whole wavefront: only that side's slope is
-// formed)
-template <typename T>
-__device__ __forceinline__ void upwind_on_side(const FaceStencil<T>& s, const FaceVals<T>& q, int side, T& Gup,
-                                               T& Hup, T& sGup, T& sHup) {
-    T gLR = (q.GR - q.GL) * s.idc, hLR = (q.HR - q.HL) * s.idc;
-    if (side == 0) {
-        T gm = (q.GL - q.GLL) * s.idcL, hm = (q.HL - q.HLL) * s.idcL;
-        sGup = van_leer_fast(gm, gLR);
-        sHup = van_leer_fast(hm, hLR);
-        Gup = q.GL + sGup * s.dL;
-        Hup = q.HL + sHup * s.dL;
-    } else if (side == 1) {
-        T gp = (q.GRR - q.GR) * s.idcR, hp = (q.HRR - q.HR) * s.idcR;
-        sGup = van_leer_fast(gLR, gp);
-        sHup = van_leer_fast(hLR, hp);
-        Gup = q.GR - sGup * s.dR;
-        Hup = q.HR - sHup * s.dR;
-    } else {
-        T gm = (q.GL - q.GLL) * s.idcL, hm = (q.HL - q.HLL) * s.idcL;
-        T gp = (q.GRR - q.GR) * s.idcR, hp = (q.HRR - q.HR) * s.idcR;
-        T sGL = van_leer_fast(gm, gLR), sHL = van_leer_fast(hm, hLR);
-        T sGR = van_leer_fast(gLR, gp), sHR = van_leer_fast(hLR, hp);
-        Gup = T(0.5) * (q.GL + sGL * s.dL + q.GR - sGR * s.dR);
-        Hup = T(0.5) * (q.HL + sHL * s.dL + q.HR - sHR * s.dR);
-        sGup = T(0.5) * (sGL + sGR);
-        sHup = T(0.5) * (sHL + sHR);
-    }
 }
 
 // Table of 2^(j/64), j < 64, for exp_tab (filled by the block that uses it)
