@@ -1027,6 +1027,9 @@ __global__ void __launch_bounds__(256) k_face_timeslope_partial(Geo g, Vel vel, 
                                                                 double* __restrict__ part) {
     __shared__ double sh[8 * WAVES * TILE];
     Chunk ch = chunk_of(g.nc, vel.nk);
+    // the velocity is the same in every lane: the upwind side is a scalar branch
+    const int wave = __builtin_amdgcn_readfirstlane(ch.wave);
+    const int k0 = __builtin_amdgcn_readfirstlane(ch.k0), k1 = __builtin_amdgcn_readfirstlane(ch.k1);
     double a[8];
     for (int m = 0; m < 8; ++m) a[m] = 0.0;
     if (ch.valid && !g.solid[ch.c]) {
@@ -1041,15 +1044,19 @@ __global__ void __launch_bounds__(256) k_face_timeslope_partial(Geo g, Vel vel, 
                 aR[m] = T(rec[(10 + m) * stride]);
             }
             T pref = rho * lam / T(M_PI);
-            for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
+            for (int k = k0 + wave; k < k1; k += WAVES) {
                 T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
                 T un = d == 0 ? u : v;
                 T du = u - U, dv = v - V;
                 T G0 = pref * dexp(-lam * (du * du + dv * dv));
                 T H0 = T(gas.K_int) / (T(2) * lam) * G0;
                 T pG, pH, qG, qH;
-                slope_poly<T>(un > T(0) ? aL : aR, u, v, lam, gas.K_int, pG, pH);
-                if (un == T(0)) {
+                const int side = upwind_side(double(un));
+                if (side == 0) {
+                    slope_poly<T>(aL, u, v, lam, gas.K_int, pG, pH);
+                } else if (side == 1) {
+                    slope_poly<T>(aR, u, v, lam, gas.K_int, pG, pH);
+                } else {
                     slope_poly<T>(aL, u, v, lam, gas.K_int, pG, pH);
                     slope_poly<T>(aR, u, v, lam, gas.K_int, qG, qH);
                     pG = T(0.5) * (pG + qG);
