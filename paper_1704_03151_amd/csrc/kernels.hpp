@@ -353,26 +353,6 @@ __global__ void k_moments_records(Geo g, const double* __restrict__ Msum, double
     q[g.nc + c] = q2[1];
 }
 
-// diffuse-wall density from zero mass flux, out[j] = -sum_{u_n>0} w u_n G / den_j
-// (Sec. III B), one wavefront per wall side summing over all velocities in
-// lane order; G is the first (G) plane of f or of a correction
-template <typename T>
-__global__ void k_wall_density(Geo g, Vel vel, const T* __restrict__ G, double* __restrict__ out) {
-    int j = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-    int lane = threadIdx.x & 63;
-    double s = 0.0;
-    if (j < g.n_wall) {
-        int c = g.w_cell[j], sd = g.w_side[j];
-        double sign = (sd & 1) ? 1.0 : -1.0;
-        for (int k = lane; k < vel.nk; k += 64) {
-            double un = sign * (sd < 2 ? vel.u[k] : vel.v[k]);
-            if (un > 0) s += vel.w[k] * un * double(G[(size_t)k * g.nc + c]);
-        }
-    }
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if (lane == 0 && j < g.n_wall) out[j] = -s / g.w_den[j];
-}
-
 // Loads on the diffuse walls (Sec. IV B: skin friction from the momentum
 // the gas hands to the wall): for wall side j the distribution on the wall
 // side of the face is the cell's for velocities leaving the gas and the wall
@@ -428,38 +408,63 @@ __global__ void k_wall_loads(Geo g, Vel vel, int K_int, const T* __restrict__ f,
     }
 }
 
-// Wall densities of df_fine + I_H^h df_coarse from the G planes, evaluated
-// at the wall cells only (the prolonged correction is needed nowhere else
-// when a sweep follows); one wavefront per wall side
-template <typename T>
-__global__ void k_wall_density_prolonged(Geo g, Vel vel, const T* __restrict__ Gf, int ncc,
-                                         const T* __restrict__ Gc, double* __restrict__ out) {
-    int j = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
-    int lane = threadIdx.x & 63;
+// Diffuse-wall densities from zero mass flux (Sec. III B):
+// out[j] = -sum_{u_n > 0} w u_n G / den_j, with G the first (G) plane of f or
+// of a correction, or (PRO) the wall densities of df_fine + I_H^h df_coarse
+// evaluated at the wall cells only (the prolonged correction is needed
+// nowhere else when a sweep follows).  A lane per wall side, the velocities
+// in slices of WD_K (blockIdx.y): consecutive sides of a wall lie along
+// consecutive cells, so the loads of one velocity coalesce, and
+// n_wall / 64 x nk / WD_K wavefronts share the chip.  part[slice][j] = the
+// slice's sum; k_wall_density_fin adds the slices in order.
+constexpr int WD_K = 32;
+inline int wall_density_slices(int nk) { return (nk + WD_K - 1) / WD_K; }
+
+template <typename T, bool PRO>
+__global__ void __launch_bounds__(64) k_wall_density_part(Geo g, Vel vel, const T* __restrict__ Gf, int ncc,
+                                                          const T* __restrict__ Gc, double* __restrict__ part) {
+    const int j = blockIdx.x * 64 + threadIdx.x;
+    const int k0 = blockIdx.y * WD_K, k1 = min(vel.nk, k0 + WD_K);
     double s = 0.0;
     if (j < g.n_wall) {
-        int c = g.w_cell[j], sd = g.w_side[j];
-        double sign = (sd & 1) ? 1.0 : -1.0;
-        int id[4];
-        T pw[4];
-        for (int a = 0; a < 4; ++a) {
-            id[a] = g.p_idx[a * g.nc + c];
-            pw[a] = T(g.p_w[a * g.nc + c]);
-        }
-        for (int k = lane; k < vel.nk; k += 64) {
-            double un = sign * (sd < 2 ? vel.u[k] : vel.v[k]);
+        const int c = g.w_cell[j], sd = g.w_side[j];
+        const double sign = (sd & 1) ? 1.0 : -1.0;
+        int id[4] = {0, 0, 0, 0};
+        T pw[4] = {T(0), T(0), T(0), T(0)};
+        if constexpr (PRO)
+            for (int a = 0; a < 4; ++a) {
+                id[a] = g.p_idx[a * g.nc + c];
+                pw[a] = T(g.p_w[a * g.nc + c]);
+            }
+        for (int k = k0; k < k1; ++k) {
+            const double un = sign * (sd < 2 ? vel.u[k] : vel.v[k]);
             if (un > 0) {
-                size_t kc = (size_t)k * ncc;
-                T add = pw[0] * Gc[kc + id[0]] + pw[1] * Gc[kc + id[1]] + pw[2] * Gc[kc + id[2]] +
-                        pw[3] * Gc[kc + id[3]];
-                T G = Gf[(size_t)k * g.nc + c] + add;
+                T G = Gf[(size_t)k * g.nc + c];
+                if constexpr (PRO) {
+                    const size_t kc = (size_t)k * ncc;
+                    const T add = pw[0] * Gc[kc + id[0]] + pw[1] * Gc[kc + id[1]] + pw[2] * Gc[kc + id[2]] +
+                                  pw[3] * Gc[kc + id[3]];
+                    G = G + add;
+                }
                 s += vel.w[k] * un * double(G);
             }
         }
+        part[(size_t)blockIdx.y * g.n_wall + j] = s;
     }
+}
+
+// rho_w = -(sum of the slices) / w_den, one wavefront per wall side: lane l
+// adds slices l, l + 64, ..., then the lanes in a fixed tree (a fixed order)
+__global__ void __launch_bounds__(256) k_wall_density_fin(Geo g, int nslices, const double* __restrict__ part,
+                                                          double* __restrict__ out) {
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    double s = 0.0;
+    if (j < g.n_wall)
+        for (int b = lane; b < nslices; b += 64) s += part[(size_t)b * g.n_wall + j];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if (lane == 0 && j < g.n_wall) out[j] = -s / g.w_den[j];
 }
+
 
 // total mass sum_c V_c rho_c over fluid cells (one block)
 __global__ void k_mass(Geo g, const double* __restrict__ W, double* __restrict__ out) {

@@ -145,6 +145,7 @@ struct miugks_ctx {
     // ordered-sweep support per level
     std::vector<unsigned*> flags;
     std::vector<double*> wbuf, wbuf_alt;   // wall-product partial sums; sweeps alternate between the two
+    std::vector<double*> wdpart;           // partial sums of the wall densities per velocity slice
     std::vector<char> sweep_lds;
     // wavefront sweep (k_sweep_wave): side types and launch shape per level
     // (W = 0: not used on that level)
@@ -452,8 +453,11 @@ struct Path {
     static void wall_sums(miugks_ctx* c, int l, const T* G, double* out) {
         const Geo& g = c->geo[l];
         if (g.n_wall == 0) return;
-        LAUNCH(c, "wall_density", (double)g.n_wall * c->nk * sizeof(T), k_wall_density<T>,
-               dim3((g.n_wall + 3) / 4), dim3(256), g, c->vel, G, out);
+        const int ns = wall_density_slices(c->nk);
+        LAUNCH(c, "wall_density", (double)g.n_wall * c->nk * sizeof(T), (k_wall_density_part<T, false>),
+               dim3((g.n_wall + 63) / 64, ns), dim3(64), g, c->vel, G, g.nc, (const T*)nullptr, c->wdpart[l]);
+        LAUNCH(c, "wall_density", (double)g.n_wall * ns * 8.0, k_wall_density_fin, dim3((g.n_wall + 3) / 4),
+               dim3(256), g, ns, (const double*)c->wdpart[l], out);
     }
 
     // Step 1: interface records, div, R and the RMS norms (into c->norms)
@@ -715,10 +719,14 @@ struct Path {
                    (T*)c->r[l + 1], n);
         }
         cs_reduced(c, l + 1);
-        if (g.n_wall)
-            LAUNCH(c, "wall_density", (double)g.n_wall * c->nk * 5 * sizeof(T), k_wall_density_prolonged<T>,
-                   dim3((g.n_wall + 3) / 4), dim3(256), g, c->vel, (const T*)c->df[l], gc.nc,
-                   (const T*)c->df[l + 1], c->drho[l]);
+        if (g.n_wall) {
+            const int ns = wall_density_slices(c->nk);
+            LAUNCH(c, "wall_density", (double)g.n_wall * c->nk * 5 * sizeof(T), (k_wall_density_part<T, true>),
+                   dim3((g.n_wall + 63) / 64, ns), dim3(64), g, c->vel, (const T*)c->df[l], gc.nc,
+                   (const T*)c->df[l + 1], c->wdpart[l]);
+            LAUNCH(c, "wall_density", (double)g.n_wall * ns * 8.0, k_wall_density_fin, dim3((g.n_wall + 3) / 4),
+                   dim3(256), g, ns, (const double*)c->wdpart[l], c->drho[l]);
+        }
         for (int i = 0; i < c->nu2; ++i) smooth(c, l, i == 0, false, (l == c->top && i == c->nu2 - 1) ? 2 : 1);
     }
 
@@ -1120,6 +1128,7 @@ int build_device(miugks_ctx* ctx) {
     ctx->flags.resize(ctx->L);
     ctx->wbuf.resize(ctx->L);
     ctx->wbuf_alt.resize(ctx->L);
+    ctx->wdpart.resize(ctx->L);
     ctx->sweep_lds.assign(ctx->L, 0);
     ctx->stype.assign(ctx->L, nullptr);
     ctx->wave.assign(ctx->L, miugks_ctx::WaveCfg());
@@ -1167,6 +1176,11 @@ int build_device(miugks_ctx* ctx) {
             return rc;
         ctx->wbuf[l] = (double*)wb;
         ctx->wbuf_alt[l] = (double*)wb2;
+        void* wdp;
+        if ((rc = dev_alloc(ctx, &wdp, std::max<size_t>(1, h.w_cell.size()) * wall_density_slices(ctx->nk) *
+                                           sizeof(double))))
+            return rc;
+        ctx->wdpart[l] = (double*)wdp;
         // pipelines per block: as many as fit in LDS and 1024 threads, but
         // no more than needed to cover every item in one round of blocks
         int npad = ((h.ny + 63) / 64) * 64;
