@@ -170,14 +170,14 @@ struct Chunk {
     bool valid;
 };
 
-__device__ __forceinline__ Chunk chunk_of(int nc, int nk) {
+__device__ __forceinline__ Chunk chunk_of(int nc, int nk, int kch = KCH) {
     Chunk ch;
     ch.lane = threadIdx.x & (TILE - 1);
     ch.wave = threadIdx.x / TILE;
     ch.c = blockIdx.x * TILE + ch.lane;
     ch.valid = ch.c < nc;
-    ch.k0 = blockIdx.y * KCH;
-    ch.k1 = min(nk, ch.k0 + KCH);
+    ch.k0 = blockIdx.y * kch;
+    ch.k1 = min(nk, ch.k0 + kch);
     ch.chunk = blockIdx.y;
     return ch;
 }
@@ -195,7 +195,7 @@ __device__ __forceinline__ int xcd_swizzle(int b, int nb) {
 // chunk_of for kernels whose stencil reaches the rows above and below: the
 // tiles of one velocity chunk are spread over as few XCDs as possible, so
 // the neighbouring rows of a tile are found in the same L2
-__device__ __forceinline__ Chunk chunk_of_xcd(int nc, int nk) {
+__device__ __forceinline__ Chunk chunk_of_xcd(int nc, int nk, int kch = KCH) {
     int nt = gridDim.x, nb = gridDim.x * gridDim.y;
     int Lb = xcd_swizzle(blockIdx.x + nt * blockIdx.y, nb);
     int tile = Lb % nt, chunk = Lb / nt;
@@ -204,8 +204,8 @@ __device__ __forceinline__ Chunk chunk_of_xcd(int nc, int nk) {
     ch.wave = threadIdx.x / TILE;
     ch.c = tile * TILE + ch.lane;
     ch.valid = ch.c < nc;
-    ch.k0 = chunk * KCH;
-    ch.k1 = min(nk, ch.k0 + KCH);
+    ch.k0 = chunk * kch;
+    ch.k1 = min(nk, ch.k0 + kch);
     ch.chunk = chunk;
     return ch;
 }
@@ -289,9 +289,9 @@ __global__ void __launch_bounds__(256) k_init(Geo g, Vel vel, Gas gas, const dou
 template <typename T>
 __global__ void __launch_bounds__(256) k_moments_partial(Geo g, Vel vel, T* __restrict__ f,
                                                          const T* __restrict__ df,
-                                                         double* __restrict__ part) {
+                                                         double* __restrict__ part, int kch) {
     __shared__ double sh[NRAW * WAVES * TILE];
-    Chunk ch = chunk_of(g.nc, vel.nk);
+    Chunk ch = chunk_of(g.nc, vel.nk, kch);
     double a[NRAW];
     for (int m = 0; m < NRAW; ++m) a[m] = 0.0;
     if (ch.valid) {
@@ -801,9 +801,9 @@ __device__ __forceinline__ void upwind_on_side(const FaceStencil<A>& s, const Fa
 // the stencil loads take scalar row offsets (as in k_flux_div).
 template <typename T>
 __global__ void __launch_bounds__(256) k_face_moments_partial(Geo g, Vel vel, const T* __restrict__ f,
-                                                              double* __restrict__ part) {
+                                                              double* __restrict__ part, int kch) {
     __shared__ double sh[2 * NRAW * WAVES * TILE];
-    Chunk ch = chunk_of_xcd(g.nc, vel.nk);
+    Chunk ch = chunk_of_xcd(g.nc, vel.nk, kch);
     const int wave = __builtin_amdgcn_readfirstlane(ch.wave);
     const int k0 = __builtin_amdgcn_readfirstlane(ch.k0), k1 = __builtin_amdgcn_readfirstlane(ch.k1);
     const size_t nc = g.nc, ho = (size_t)vel.nk * nc;
@@ -1029,9 +1029,9 @@ __device__ __forceinline__ void slope_poly(const T* a, T u, T v, T lam, int K_in
 template <typename T>
 __global__ void __launch_bounds__(256) k_face_timeslope_partial(Geo g, Vel vel, Gas gas,
                                                                 const double* __restrict__ fp,
-                                                                double* __restrict__ part) {
+                                                                double* __restrict__ part, int kch) {
     __shared__ double sh[8 * WAVES * TILE];
-    Chunk ch = chunk_of(g.nc, vel.nk);
+    Chunk ch = chunk_of(g.nc, vel.nk, kch);
     // the velocity is the same in every lane: the upwind side is a scalar branch
     const int wave = __builtin_amdgcn_readfirstlane(ch.wave);
     const int k0 = __builtin_amdgcn_readfirstlane(ch.k0), k1 = __builtin_amdgcn_readfirstlane(ch.k1);
@@ -2129,6 +2129,40 @@ __device__ __forceinline__ void wave_store(T* __restrict__ dst, const T* src, in
     }
 }
 
+// dst[i] += src[i] for n elements, dst in global memory and src in LDS, by
+// one wavefront: 16-byte accesses when aligned, U loads of dst in flight per
+// lane (the sweep kernels run few wavefronts per CU)
+template <typename T, int U = 16>
+__device__ __forceinline__ void wave_add_store(T* __restrict__ dst, const T* src, int n, int lane) {
+    size_t bytes = (size_t)n * sizeof(T);
+    if (((((size_t)dst) | ((size_t)src) | bytes) & 15) == 0) {
+        constexpr int E = 16 / sizeof(T);
+        typedef __attribute__((ext_vector_type(E))) T v4;
+        const int nv = (int)(bytes >> 4);
+        const v4* s = (const v4*)src;
+        v4* d = (v4*)dst;
+        for (int i0 = lane; i0 < nv; i0 += 64 * U) {
+            v4 a[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i0 + 64 * u < nv) a[u] = d[i0 + 64 * u];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i0 + 64 * u < nv) d[i0 + 64 * u] = a[u] + s[i0 + 64 * u];
+        }
+    } else {
+        for (int i0 = lane; i0 < n; i0 += 64 * U) {
+            T a[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i0 + 64 * u < n) a[u] = dst[i0 + 64 * u];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i0 + 64 * u < n) dst[i0 + 64 * u] = a[u] + src[i0 + 64 * u];
+        }
+    }
+}
+
 // wall sides of a level that k_sweep_wave handles
 constexpr int SWEEP_WAVE_MAX_WALLS = 512;
 
@@ -2727,6 +2761,10 @@ __global__ void __launch_bounds__(256) k_sweep_strips(Geo g, Vel vel, int K_int,
 // k_sweep_wave; the G plane's wall sums of a block accumulate over the
 // bands in wpart[blk] (the first band writes them).  split as in
 // k_sweep_wave.
+//
+// fout (null: unused) makes the sweep the last one of a correction that is
+// applied at once (Step 6): the band's values are added to the distribution
+// fout, f += df, and df receives only the row that the next band reads.
 template <typename T>
 __host__ __device__ inline size_t sweep_band_tile_elems(int nx, int h, int nw, int W, int I) {
     size_t t = (size_t)W * I * h * nx, red = ((size_t)W * nw * sizeof(double) + sizeof(T) - 1) / sizeof(T);
@@ -2746,7 +2784,8 @@ __global__ void __launch_bounds__(256) k_sweep_band(Geo g, Vel vel, int K_int, c
                                                     T* __restrict__ df, const T* __restrict__ coef_g,
                                                     const unsigned char* __restrict__ stype,
                                                     const double* __restrict__ drho, double* __restrict__ wpart,
-                                                    int I, int h, int b, int nvrow, int split) {
+                                                    int I, int h, int b, int nvrow, int split,
+                                                    T* __restrict__ fout) {
     extern __shared__ __attribute__((aligned(16))) double smem_d[];
     const int nc = g.nc, nx = g.nx, ny = g.ny, nw = g.n_wall, nk = vel.nk;
     const int W = blockDim.x >> 6, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -2902,9 +2941,26 @@ __global__ void __launch_bounds__(256) k_sweep_band(Geo g, Vel vel, int K_int, c
     if (s + 1 < nsteps) step(s + 1, nB, nA);
     if (s + 2 < nsteps) step(s + 2, nC, nB);
     __syncthreads();
-    for (int qv = 0; qv < nq; ++qv) {
-        const bool pyq = vel_v<T>(vel, k0 + qv) >= T(0);
-        wave_store<T>(dfp + (size_t)(k0 + qv) * nc + (size_t)band_y0(pyq) * nx, tw + qv * tsz, hb * nx, lane);
+    if (!fout) {
+        for (int qv = 0; qv < nq; ++qv) {
+            const bool pyq = vel_v<T>(vel, k0 + qv) >= T(0);
+            wave_store<T>(dfp + (size_t)(k0 + qv) * nc + (size_t)band_y0(pyq) * nx, tw + qv * tsz, hb * nx, lane);
+        }
+    } else {
+        // f += df over the band; df only for the band's last row in the
+        // velocity's order (tile row hb - 1 upward, 0 downward), which the
+        // next band reads
+        T* fp = fout + (size_t)plane * nk * nc;
+        const bool more = (b + 1) * h < ny;
+        for (int qv = 0; qv < nq; ++qv) {
+            const bool pyq = vel_v<T>(vel, k0 + qv) >= T(0);
+            const size_t off = (size_t)(k0 + qv) * nc + (size_t)band_y0(pyq) * nx;
+            wave_add_store<T>(fp + off, tw + qv * tsz, hb * nx, lane);
+            if (more) {
+                const size_t tr = pyq ? (size_t)(hb - 1) * nx : 0;
+                wave_store<T>(dfp + off + tr, tw + qv * tsz + tr, nx, lane);
+            }
+        }
     }
     // the H plane leaves no wall partial sums (uniform over the block)
     if (plane) return;

@@ -109,6 +109,12 @@ struct miugks_ctx {
     // finest level the cycles run on: 0, except during a full-multigrid start,
     // whose stages treat a coarse level as the finest (f then holds that level)
     int top = 0;
+    int kch_force = 0;   // > 0: velocities per block of the chunked reductions (chunk_len)
+    // set around a correction whose result is applied at once (Step 6): the
+    // finest level's last sweep, if in bands, adds df to f itself (fused)
+    void* fuse_f = nullptr;
+    bool fused = false;
+    bool no_fuse = false;   // MIUGKS_NO_FUSED_UPDATE: keep Step 6 in the moments kernel
     double dtn_growth = 0.0;
     double dtn_max = 0.0;   // cap of a^n (0: none)
     double cfl = 0.5;
@@ -249,8 +255,31 @@ int upload(miugks_ctx* ctx, P** dst, const std::vector<P>& src) {
     return MIUGKS_OK;
 }
 
-inline int nchunks(int nk) { return (nk + KCH - 1) / KCH; }
+inline int nchunks(int nk, int kch = KCH) { return (nk + kch - 1) / kch; }
 inline int ntiles(int n) { return (n + TILE - 1) / TILE; }
+// Velocities per block of the kernels that reduce over the velocities into
+// per-chunk partial sums (moments, face moments, time slopes): KCH
+// doubled while the launch keeps at least 2048 blocks (eight per CU), up to
+// 8 KCH.  Longer chunks write fewer partial sums (NRAW doubles per cell and
+// chunk) and spread each block's per-face set-up over more velocities; below
+// about 2048 blocks the last round of blocks leaves CUs idle.  Measured on
+// the 160x160 square (10 000 velocities: 8 KCH, 19.3 ms per cycle against
+// 20.8 with KCH) and the 128x96 plate (1600 velocities: 4 KCH, 2.01 against
+// 2.10 ms); the 64x64 cavity (784 velocities) keeps KCH.  A chunk's rows of one
+// plane stay below 2^31 bytes (the range of a buffer resource).  force > 0
+// (MIUGKS_CHUNK_LEN, at least KCH) sets the length instead, within that range.
+inline int chunk_len(int nc, int nk, int force) {
+    if (force > 0) {
+        int kch = force;
+        while (kch > KCH && (size_t)kch * nc * sizeof(double) >= (size_t(1) << 31)) kch /= 2;
+        return std::max(kch, KCH);
+    }
+    int kch = KCH;
+    while (kch < 8 * KCH && (long)ntiles(nc) * nchunks(nk, 2 * kch) >= 2048 &&
+           (size_t)2 * kch * nc * sizeof(double) < (size_t(1) << 31))
+        kch *= 2;
+    return kch;
+}
 inline int nblk(int n, int b = 256) { return (n + b - 1) / b; }
 
 int check_launch(miugks_ctx* ctx) {
@@ -440,10 +469,10 @@ struct Path {
     // Step 7: W, q of f (optionally after f += df, Step 6)
     static void moments(miugks_ctx* c, const T* df) {
         const Geo& g = c->geo[c->top];
-        int nkc = nchunks(c->nk);
+        const int kch = chunk_len(g.nc, c->nk, c->kch_force), nkc = nchunks(c->nk, kch);
         double nc8 = g.nc * 8.0;
         LAUNCH(c, df ? "update_moments" : "moments", (df ? 3 : 1) * arr(c, c->top) + NRAW * nkc * nc8,
-               k_moments_partial<T>, dim3(ntiles(g.nc), nkc), dim3(256), g, c->vel, F(c), df, c->part);
+               k_moments_partial<T>, dim3(ntiles(g.nc), nkc), dim3(256), g, c->vel, F(c), df, c->part, kch);
         LAUNCH(c, "chunk_sum", NRAW * (nkc + 1.0) * nc8, k_chunk_sum, dim3(nblk(NRAW * g.nc)), dim3(256),
                (const double*)c->part, nkc, NRAW, g.nc, 1.0, (const unsigned char*)nullptr, c->msum);
         LAUNCH(c, "moments_records", (NRAW + 6.0) * nc8, k_moments_records, dim3(nblk(g.nc)), dim3(256), g,
@@ -464,28 +493,31 @@ struct Path {
     static void residual(miugks_ctx* c) {
         const int top = c->top;
         const Geo& g = c->geo[top];
-        int nkc = nchunks(c->nk), nt = ntiles(g.nc);
+        const int kch = chunk_len(g.nc, c->nk, c->kch_force), nkc = nchunks(c->nk, kch), nt = ntiles(g.nc);
         double nc8 = g.nc * 8.0;
         // raw moments of the upwind interface distributions, per velocity
         // chunk, summed in chunk order; interface records
         LAUNCH(c, "face_moments", arr(c, top) + 2.0 * NRAW * nkc * nc8, k_face_moments_partial<T>, dim3(nt, nkc),
-               dim3(256), g, c->vel, F(c), c->part);
+               dim3(256), g, c->vel, F(c), c->part, kch);
         LAUNCH(c, "chunk_sum", 2.0 * NRAW * (nkc + 1) * nc8, k_chunk_sum, dim3(nblk(2 * NRAW * g.nc)), dim3(256),
                (const double*)c->part, nkc, 2 * NRAW, g.nc, 1.0, (const unsigned char*)nullptr, c->msum);
         LAUNCH(c, "face_records", (2.0 * NRAW + 8 + 2 * NFP) * nc8, k_face_records, dim3(nblk(2 * g.nc)),
                dim3(256), g, c->gas, (const double*)c->msum, (const double*)c->W, c->fp);
         // time slopes from the discrete compatibility condition
         LAUNCH(c, "face_timeslope", (2.0 * NFP + 8.0 * nkc) * nc8, k_face_timeslope_partial<T>, dim3(nt, nkc),
-               dim3(256), g, c->vel, c->gas, (const double*)c->fp, c->part);
+               dim3(256), g, c->vel, c->gas, (const double*)c->fp, c->part, kch);
         LAUNCH(c, "chunk_sum", 8.0 * (nkc + 1) * nc8, k_chunk_sum, dim3(nblk(8 * g.nc)), dim3(256),
                (const double*)c->part, nkc, 8, g.nc, 1.0, (const unsigned char*)nullptr, c->msum);
         LAUNCH(c, "timeslope_records", (8.0 + 2 * 8) * nc8, k_face_timeslope_records, dim3(nblk(2 * g.nc)),
                dim3(256), g, c->gas, (const double*)c->msum, c->fp);
         wall_sums(c, top, F(c), c->rho_w);
-        LAUNCH(c, "flux_div", 2 * arr(c, top) + (2.0 * NFP + 4.0 * nkc) * nc8, k_flux_div<T>, dim3(flux_tiles(g), nkc),
+        // the flux keeps chunks of KCH velocities: a block holds a thread's MK
+        // velocities of div in registers, and its partial sums are 4 per cell
+        const int nkf = nchunks(c->nk);
+        LAUNCH(c, "flux_div", 2 * arr(c, top) + (2.0 * NFP + 4.0 * nkf) * nc8, k_flux_div<T>, dim3(flux_tiles(g), nkf),
                dim3(256), g, c->vel, c->gas, F(c), c->fp, c->rho_w, (const T*)c->finf, (T*)c->div, c->part, flux_stride(g));
-        LAUNCH(c, "chunk_sum", 4.0 * (nkc + 1) * nc8, k_chunk_sum, dim3(nblk(4 * g.nc)), dim3(256),
-               (const double*)c->part, nkc, 4, g.nc, -1.0, g.solid, c->R);
+        LAUNCH(c, "chunk_sum", 4.0 * (nkf + 1) * nc8, k_chunk_sum, dim3(nblk(4 * g.nc)), dim3(256),
+               (const double*)c->part, nkf, 4, g.nc, -1.0, g.solid, c->R);
         LAUNCH(c, "residual_norm", 4 * nc8, k_residual_norm, dim3(1), dim3(256), g, c->hl[top].n_fluid, c->R,
                c->norms);
         c->have_div = true;
@@ -548,17 +580,22 @@ struct Path {
             c->wparts[l] = wc.blocks;
         } else if (wc.W && wc.bands) {
             // one launch per band, in every velocity's upwind order; each
-            // reads the last row of the band before from df
+            // reads the last row of the band before from df.  The finest
+            // level's last sweep of a correction applied at once adds df to
+            // f instead of storing it (then Step 6 only takes the moments).
             const int nblk = wc.split ? wc.blocks / 2 : wc.blocks;
+            T* fout = (np == 2 && l == c->top && c->fuse_f) ? (T*)c->fuse_f : nullptr;
+            const double planes = (wc.split ? 2 : 1) * (fout ? 1.5 : 1.0);
             for (int b = 0; b < wc.bands; ++b) {
                 const int hb = std::min(wc.bh, g.ny - b * wc.bh);
-                LAUNCH_SH(c, name, (wc.split ? 2 : 1) * arr(c, l) * hb / g.ny, wc.lds, k_sweep_band<T>,
+                LAUNCH_SH(c, name, planes * arr(c, l) * hb / g.ny, wc.lds, k_sweep_band<T>,
                           dim3(wc.blocks), dim3(64 * wc.W), g, c->vel, c->gas.K_int, (const T*)c->r[l],
                           (T*)c->df[l], (const T*)c->coefT[l], c->stype[l],
                           from_zero ? (const double*)nullptr : (const double*)c->drho[l], c->wbuf[l], wc.I, wc.bh,
-                          b, c->nv, wc.split ? 1 : 0);
+                          b, c->nv, wc.split ? 1 : 0, fout);
             }
             c->wparts[l] = nblk;
+            if (fout) c->fused = true;
         } else if (wc.W && wc.strips) {
 #define MIUGKS_STRIPS_LAUNCH(RR)                                                                                 \
     LAUNCH_SH(c, name, (wc.split ? 2 : 1) * arr(c, l), wc.lds, (k_sweep_strips<T, RR>), dim3(wc.blocks),           \
@@ -742,9 +779,11 @@ struct Path {
             cs(c, c->top, c->gamma_cs);
     }
 
-    // Steps 6-7 and the closed-domain renormalisation
+    // Steps 6-7 and the closed-domain renormalisation (f += df already done
+    // if the correction's last sweep was fused with it)
     static void update(miugks_ctx* c) {
-        moments(c, (const T*)c->df[c->top]);
+        moments(c, c->fused ? (const T*)nullptr : (const T*)c->df[c->top]);
+        c->fused = false;
         if (c->renorm) {
             const Geo& g = c->geo[c->top];
             LAUNCH(c, "mass", 4.0 * g.nc * 8, k_mass, dim3(1), dim3(1024), g, c->W, c->mass);
@@ -859,7 +898,10 @@ void cycle_rest(miugks_ctx* c) {
     set_dtn(c);
     predict(c);
     Path<T>::micro_residual(c);
+    c->fuse_f = c->no_fuse ? nullptr : c->f;
+    c->fused = false;
     Path<T>::correct(c);
+    c->fuse_f = nullptr;
     Path<T>::update(c);
 }
 
@@ -1517,7 +1559,9 @@ int build_device(miugks_ctx* ctx) {
         std::vector<double> all(nc0, m);
         HIP_TRY(hipMemcpy(ctx->dt_glob, all.data(), nc0 * sizeof(double), hipMemcpyHostToDevice));
     }
-    // partial sums: the largest is 2 * NRAW per cell per chunk
+    if (const char* e = getenv("MIUGKS_CHUNK_LEN")) ctx->kch_force = std::max(KCH, atoi(e));
+    ctx->no_fuse = getenv("MIUGKS_NO_FUSED_UPDATE") != nullptr;
+    // partial sums: the largest is 2 * NRAW per cell per chunk of KCH (the shortest)
     size_t maxw = 1;
     for (auto& h : ctx->hl) maxw = std::max(maxw, h.w_cell.size());
     ctx->part_bytes = (size_t)nchunks(ctx->nk) * std::max<size_t>(2 * NRAW * nc0, maxw) * sizeof(double);

@@ -103,6 +103,41 @@ def test_velocity_counts_leaving_waves_without_a_velocity(nu, nv):
     gpu.close()
 
 
+@pytest.mark.parametrize("kch", [64, 96, 512])
+@pytest.mark.parametrize("name", ["square20x20", "plate32x24", "box8_vel65"])
+def test_long_velocity_chunks(name, kch, monkeypatch):
+    """The velocity reductions (moments, face moments, time slopes) in
+    chunks of kch velocities per block, as large meshes take them: 256 and
+    168 velocities in ragged chunks of 64 and 96 and in one chunk of 512;
+    65 velocities in a chunk of 64 plus one.  Step 1 and two whole cycles
+    against the oracle."""
+    from paper_1704_03151_amd import Solver
+    monkeypatch.setenv("MIUGKS_CHUNK_LEN", str(kch))
+    case = CASES[name]
+    print(f"[parity] {name} with velocity chunks of {kch}", flush=True)
+    gpu, orc = Solver(case, precision="fp64"), Oracle(case)
+    prim, pert = perturbed_state(case, 13)
+    gpu.init_macro(prim)
+    orc.init_macro(prim)
+    gpu.set_f(gpu.get_f() * pert)
+    orc.set_f(*to_oracle(gpu.get_f()))
+    err = field_errors(gpu.macro(), orc.primitive(), orc.lev0.fluid)
+    assert max(err.values()) < 1e-12, err
+    R, norms = gpu.residual()
+    norms_ref = orc.step1()
+    dG, dH = to_oracle(gpu.div())
+    assert rel_max(dG, orc.divG) < 1e-11 and rel_max(dH, orc.divH) < 1e-11
+    Rref = orc.R.reshape(4, case.ny, case.nx)
+    for m in range(4):
+        assert rel_max(R[m], Rref[m]) < 1e-11, (m, rel_max(R[m], Rref[m]))
+    assert np.allclose(norms, norms_ref, rtol=1e-11, atol=0)
+    gpu.iterate(2, tol=0.0)
+    orc.iterate(2, tol=0.0)
+    err = field_errors(gpu.macro(), orc.primitive(), orc.lev0.fluid)
+    gpu.close()
+    assert max(err.values()) < 1e-10, err
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_step2_fas_prediction(name):
     """Row a3: FAS V-cycle of the macroscopic prediction."""
@@ -382,6 +417,31 @@ def test_step5_sweep_in_bands(name, height, monkeypatch):
     err = field_errors(gpu.macro(), orc.primitive(), orc.lev0.fluid)
     gpu.close()
     assert max(err.values()) < 1e-10, err
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32f"])
+@pytest.mark.parametrize("name", ["square20x20", "plate32x24", "box13x9"])
+def test_last_sweep_fused_with_step6(name, prec, monkeypatch):
+    """Step 6 (f += df) done by the finest level's last sweep, in bands of 3
+    rows (df kept only for the row the next band reads; odd widths add
+    element by element), against Step 6 in the moments kernel: the same
+    additions in the storage type, so three outer cycles agree bit for
+    bit."""
+    from paper_1704_03151_amd import Solver
+    monkeypatch.setenv("MIUGKS_SWEEP_BANDS", "3")
+    case = STRIP_CASES[name]()
+    print(f"[parity] {name} {prec}: last sweep fused with Step 6", flush=True)
+    out = []
+    for fuse in (True, False):
+        if not fuse:
+            monkeypatch.setenv("MIUGKS_NO_FUSED_UPDATE", "1")
+        gpu = Solver(case, precision=prec)
+        gpu.iterate(3, tol=0.0)
+        out.append((gpu.get_f(), gpu.macro()))
+        gpu.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    for k in out[0][1]:
+        assert np.array_equal(out[0][1][k], out[1][1][k]), k
 
 
 @pytest.mark.parametrize("name", list(STREAM_CASES))
