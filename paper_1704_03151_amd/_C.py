@@ -78,6 +78,8 @@ _SIGS = {
                                                ctypes.c_int]),
     "miugks_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _ip, ctypes.c_int, _ip, ctypes.c_int,
                                       ctypes.c_double, ctypes.c_int, _dp, _ip, _dp]),
+    "miugks_adjoint_ex": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _ip, ctypes.c_int, _ip, ctypes.c_int,
+                                         ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _ip, _dp]),
     "miugks_residual": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp]),
     "miugks_get_div": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "miugks_predict": (ctypes.c_int, [ctypes.c_void_p, _dp, _dp, _dp]),

@@ -1,5 +1,8 @@
 // Transposed linearisation of the steady residual, the preconditioner of the
-// adjoint iteration and the wall-temperature sensitivities (double only).
+// adjoint iteration and the wall-temperature sensitivities.  The state f,
+// the records and every sum are double; the vectors of the Krylov iteration
+// (its basis, the preconditioner's input and output) have the storage type
+// VT, double or float, and are read into and formed in double.
 //
 // The steady state solves the microscopic residual of Steps 3-4 with the
 // equilibrium of the state itself (Sec. II A):
@@ -180,9 +183,10 @@ __device__ __forceinline__ void wave_allsum(double* a) {
 
 // Collision term, one wavefront per cell: the adjoint moments Wbar (through
 // g and tau), the heat-flux adjoint, U, V and 1/tau into rec[m nc + c]
+template <typename VT>
 __global__ void __launch_bounds__(256) k_adj_cell(Geo g, Vel vel, Gas gas, const double* __restrict__ f,
                                                    const double* __restrict__ W, const double* __restrict__ q,
-                                                   const double* __restrict__ v, double* __restrict__ rec) {
+                                                   const VT* __restrict__ v, double* __restrict__ rec) {
     int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (c >= g.nc) return;
     const int nc = g.nc;
@@ -235,10 +239,10 @@ __global__ void __launch_bounds__(256) k_adj_cell(Geo g, Vel vel, Gas gas, const
 // the scalar reverse chain, pass B and the final chain into
 // fa[(m * 2 + d) nc + c], m < NFA (the split halves the registers live at once).
 constexpr int NFS = 28;
-template <int PART>
+template <int PART, typename VT>
 __global__ void __launch_bounds__(256) k_adj_face(Geo g, Vel vel, Gas gas, const double* __restrict__ f,
                                                    const double* __restrict__ W, const double* __restrict__ fp,
-                                                   const double* __restrict__ v, double* __restrict__ fsum,
+                                                   const VT* __restrict__ v, double* __restrict__ fsum,
                                                    double* __restrict__ fa) {
     // the face is the same across the wavefront: its record, geometry and
     // scalars live in scalar registers
@@ -406,7 +410,8 @@ __global__ void __launch_bounds__(256) k_adj_face(Geo g, Vel vel, Gas gas, const
 // Diffuse walls, one wavefront per wall side: the adjoint of the wall density
 // divided by its denominator, rws[j] = (sum_{u_n<0} (Phibar^G u_n C^G +
 // Phibar^H u_n C^H)) / den_j with Phibar = -v S/V of the wall's cell
-__global__ void __launch_bounds__(256) k_adj_wall(Geo g, Vel vel, int K_int, const double* __restrict__ v,
+template <typename VT>
+__global__ void __launch_bounds__(256) k_adj_wall(Geo g, Vel vel, int K_int, const VT* __restrict__ v,
                                                    double* __restrict__ rws) {
     int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (j >= g.n_wall) return;
@@ -433,8 +438,9 @@ __global__ void __launch_bounds__(256) k_adj_wall(Geo g, Vel vel, int K_int, con
 // Per (k, cell), first part: the direct adjoints of the cell's values from
 // the interface values of its faces (gbd, 2 planes) and the adjoints of the
 // cell's limited slopes (sb[(2 d + plane) Nk nc + k nc + c]).
+template <typename VT>
 __global__ void __launch_bounds__(256) k_adj_gather(Geo g, Vel vel, const double* __restrict__ fp,
-                                                     const double* __restrict__ fa, const double* __restrict__ v,
+                                                     const double* __restrict__ fa, const VT* __restrict__ v,
                                                      double* __restrict__ gbd, double* __restrict__ sb) {
     const int nc = g.nc;
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -536,19 +542,20 @@ __device__ inline double slope_adjoint(const Geo& g, int d, int c, const double*
 }
 
 // Per (k, cell), second part: out = (dr/df)^T v for both planes
+template <typename VT>
 __global__ void __launch_bounds__(256) k_adj_assemble(Geo g, Vel vel, const double* __restrict__ f,
-                                                       const double* __restrict__ v, const double* __restrict__ crec,
+                                                       const VT* __restrict__ v, const double* __restrict__ crec,
                                                        const double* __restrict__ fa, const double* __restrict__ rws,
                                                        const double* __restrict__ gbd, const double* __restrict__ sb,
-                                                       double* __restrict__ out) {
+                                                       VT* __restrict__ out) {
     const int nc = g.nc;
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t n = (size_t)vel.nk * nc;
     if (i >= n) return;
     const int k = (int)(i / nc), c = (int)(i - (size_t)k * nc);
     if (g.solid[c]) {
-        out[i] = 0.0;
-        out[n + i] = 0.0;
+        out[i] = VT(0);
+        out[n + i] = VT(0);
         return;
     }
     const size_t stride = 2 * (size_t)nc, kc = (size_t)k * nc;
@@ -610,8 +617,8 @@ __global__ void __launch_bounds__(256) k_adj_assemble(Geo g, Vel vel, const doub
             }
         }
     }
-    out[i] = oG;
-    out[n + i] = oH;
+    out[i] = VT(oG);
+    out[n + i] = VT(oH);
 }
 
 // Preconditioner of the adjoint iteration: y = A^-T r for the velocity-
@@ -623,8 +630,9 @@ __global__ void __launch_bounds__(256) k_adj_assemble(Geo g, Vel vel, const doub
 // order: y_c = (r_c + sum over downwind neighbours d of u_n y_d / h_d) / D_c.
 // One block per velocity, one thread per row, anti-diagonal wavefronts; both
 // planes share the operator.  Requires ny <= blockDim.x.
-__global__ void k_adj_sweep(Geo g, Vel vel, const double* __restrict__ crec, const double* __restrict__ r,
-                            double* __restrict__ y) {
+template <typename VT>
+__global__ void k_adj_sweep(Geo g, Vel vel, const double* __restrict__ crec, const VT* __restrict__ r,
+                            VT* __restrict__ y) {
     extern __shared__ double lds[];   // [2][ny]: the last value of each row
     const int k = blockIdx.x, j = threadIdx.x, nx = g.nx, ny = g.ny, nc = g.nc;
     const size_t n = (size_t)vel.nk * nc, kc = (size_t)k * nc;
@@ -671,8 +679,8 @@ __global__ void k_adj_sweep(Geo g, Vel vel, const double* __restrict__ crec, con
                 yg = sg / D;
                 yh = sh / D;
             }
-            y[kc + c] = yg;
-            y[n + kc + c] = yh;
+            y[kc + c] = VT(yg);
+            y[n + kc + c] = VT(yh);
         }
         __syncthreads();
         if (act) {
@@ -774,11 +782,12 @@ __global__ void __launch_bounds__(256) k_adj_objgrad(Geo g, Vel vel, int kind, c
 // dJ/dT_w - lam^T dr/dT_w for each listed wall side (one wavefront each):
 // the wall temperature enters through the wall Maxwellian of the incoming
 // velocities and its density rho_w (zero net mass flux; Sec. III B)
+template <typename VT>
 __global__ void __launch_bounds__(256) k_adj_paramgrad(Geo g, Vel vel, int K_int, int kind,
                                                         const double* __restrict__ objw,
                                                         const double* __restrict__ Qj,
                                                         const double* __restrict__ rhow,
-                                                        const double* __restrict__ lam_adj,
+                                                        const VT* __restrict__ lam_adj,
                                                         const int* __restrict__ sides, int n_sides,
                                                         double* __restrict__ out) {
     int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -831,14 +840,16 @@ __global__ void __launch_bounds__(256) k_adj_paramgrad(Geo g, Vel vel, int K_int
     }
 }
 
-// x = a - b elementwise; per-block sums of x^2 (fixed order) into part
+// x = a - b elementwise; per-block sums of x^2 (fixed order, of the double
+// difference) into part
+template <typename VT>
 __global__ void __launch_bounds__(256) k_adj_residual(const double* __restrict__ a, const double* __restrict__ b,
-                                                       double* __restrict__ x, size_t n, double* __restrict__ part) {
+                                                       VT* __restrict__ x, size_t n, double* __restrict__ part) {
     __shared__ double sh[256];
     double s = 0.0;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
         double d = a[i] - b[i];
-        x[i] = d;
+        x[i] = VT(d);
         s += d * d;
     }
     sh[threadIdx.x] = s;
@@ -853,8 +864,9 @@ __global__ void __launch_bounds__(256) k_adj_residual(const double* __restrict__
 // Krylov support: per-block partial dot products of w with the vectors
 // V[i ldv ...], i < m, into part[i gridDim.x + block] (fixed order); and
 // w += sign sum_i h[i] V[i]
-// (eight vectors per pass over w)
-__global__ void __launch_bounds__(256) k_adj_dots(const double* __restrict__ w, const double* __restrict__ V,
+// (eight vectors per pass over w; products and sums in double)
+template <typename VT>
+__global__ void __launch_bounds__(256) k_adj_dots(const VT* __restrict__ w, const VT* __restrict__ V,
                                                    size_t ldv, int m, size_t n, double* __restrict__ part) {
     __shared__ double sh[8][256];
     for (int i0 = 0; i0 < m; i0 += 8) {
@@ -880,23 +892,26 @@ __global__ void __launch_bounds__(256) k_adj_dots(const double* __restrict__ w, 
     }
 }
 
-__global__ void k_adj_lincomb(double* __restrict__ w, const double* __restrict__ V, size_t ldv,
+template <typename VT>
+__global__ void k_adj_lincomb(VT* __restrict__ w, const VT* __restrict__ V, size_t ldv,
                               const double* __restrict__ h, int m, double sign, size_t n) {
     size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     double s = 0.0;
-    for (int i = 0; i < m; ++i) s += h[i] * V[(size_t)i * ldv + j];
-    w[j] += sign * s;
+    for (int i = 0; i < m; ++i) s += h[i] * double(V[(size_t)i * ldv + j]);
+    w[j] = VT(double(w[j]) + sign * s);
 }
 
-__global__ void k_adj_scale(double* __restrict__ y, const double* __restrict__ x, double a, size_t n) {
+template <typename VT>
+__global__ void k_adj_scale(VT* __restrict__ y, const VT* __restrict__ x, double a, size_t n) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = a * x[i];
+    if (i < n) y[i] = VT(a * double(x[i]));
 }
 
-__global__ void k_adj_axpy(double* __restrict__ x, const double* __restrict__ y, double a, size_t n) {
+template <typename TX, typename TY>
+__global__ void k_adj_axpy(TX* __restrict__ x, const TY* __restrict__ y, double a, size_t n) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] += a * y[i];
+    if (i < n) x[i] = TX(double(x[i]) + a * double(y[i]));
 }
 
 }  // namespace miugks

@@ -2229,31 +2229,35 @@ static int adj_check(miugks_ctx* c) {
     return adj_alloc(c);
 }
 
+extern "C++" {
 // out = (dr/df)^T v at the current f; Step 1 (interface records) and the
-// moments must be those of f
-static void adj_product(miugks_ctx* c, const double* v, double* out) {
+// moments must be those of f.  v and out are stored as VT
+template <typename VT>
+static void adj_product(miugks_ctx* c, const VT* v, VT* out) {
     const Geo& g = c->geo[0];
     const size_t n = (size_t)c->nk * g.nc;
     const double* f = (const double*)c->f;
     // algorithmic bytes: one pass = one distribution-shaped array (2 planes);
     // cell and face kernels read f and v, the gather reads v and writes 6
     // planes, the assembly reads f, v and 6 gathered planes and writes out
-    const double pass = 2.0 * n * 8;
-    LAUNCH(c, "adj_cell", 2 * pass, k_adj_cell, dim3((g.nc + 3) / 4), dim3(256), g, c->vel, c->gas, f,
+    const double pass = 2.0 * n * 8, vpass = 2.0 * n * sizeof(VT);
+    LAUNCH(c, "adj_cell", pass + vpass, k_adj_cell<VT>, dim3((g.nc + 3) / 4), dim3(256), g, c->vel, c->gas, f,
            (const double*)c->W, (const double*)c->q, v, c->a_crec);
-    LAUNCH(c, "adj_face_sums", 2 * pass, k_adj_face<0>, dim3((2 * g.nc + 3) / 4), dim3(256), g, c->vel, c->gas, f,
-           (const double*)c->W, (const double*)c->fp, v, c->a_fsum, c->a_fa);
-    LAUNCH(c, "adj_face", 2 * pass, k_adj_face<1>, dim3((2 * g.nc + 3) / 4), dim3(256), g, c->vel, c->gas, f,
-           (const double*)c->W, (const double*)c->fp, v, c->a_fsum, c->a_fa);
+    LAUNCH(c, "adj_face_sums", pass + vpass, (k_adj_face<0, VT>), dim3((2 * g.nc + 3) / 4), dim3(256), g, c->vel,
+           c->gas, f, (const double*)c->W, (const double*)c->fp, v, c->a_fsum, c->a_fa);
+    LAUNCH(c, "adj_face", pass + vpass, (k_adj_face<1, VT>), dim3((2 * g.nc + 3) / 4), dim3(256), g, c->vel, c->gas,
+           f, (const double*)c->W, (const double*)c->fp, v, c->a_fsum, c->a_fa);
     if (g.n_wall)
-        LAUNCH(c, "adj_wall", 0.0, k_adj_wall, dim3((g.n_wall + 3) / 4), dim3(256), g, c->vel, c->gas.K_int, v,
+        LAUNCH(c, "adj_wall", 0.0, k_adj_wall<VT>, dim3((g.n_wall + 3) / 4), dim3(256), g, c->vel, c->gas.K_int, v,
                c->a_rws);
     dim3 nb((unsigned)((n + 255) / 256));
-    LAUNCH(c, "adj_gather", 4 * pass, k_adj_gather, nb, dim3(256), g, c->vel, (const double*)c->fp,
+    LAUNCH(c, "adj_gather", 3 * pass + vpass, k_adj_gather<VT>, nb, dim3(256), g, c->vel, (const double*)c->fp,
            (const double*)c->a_fa, v, c->a_gbd, c->a_sb);
-    LAUNCH(c, "adj_assemble", 7 * pass, k_adj_assemble, nb, dim3(256), g, c->vel, f, v, (const double*)c->a_crec,
-           (const double*)c->a_fa, (const double*)c->a_rws, (const double*)c->a_gbd, (const double*)c->a_sb, out);
+    LAUNCH(c, "adj_assemble", 5 * pass + 2 * vpass, k_adj_assemble<VT>, nb, dim3(256), g, c->vel, f, v,
+           (const double*)c->a_crec, (const double*)c->a_fa, (const double*)c->a_rws, (const double*)c->a_gbd,
+           (const double*)c->a_sb, out);
 }
+}  // extern "C++"
 
 int miugks_residual_adjoint(miugks_ctx* ctx, const void* v, void* out, int dtype, int on_device) {
     if (!ctx) return MIUGKS_EINVAL;
@@ -2261,7 +2265,7 @@ int miugks_residual_adjoint(miugks_ctx* ctx, const void* v, void* out, int dtype
     if ((rc = adj_check(ctx))) return rc;
     if ((rc = copy_in(ctx, v, ctx->a_y, dtype, on_device))) return rc;
     Path<double>::residual(ctx);
-    adj_product(ctx, ctx->a_y, ctx->a_out);
+    adj_product<double>(ctx, ctx->a_y, ctx->a_out);
     if ((rc = copy_out(ctx, ctx->a_out, out, dtype, on_device))) return rc;
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return check_launch(ctx);
@@ -2278,13 +2282,188 @@ static int wall_face(const HostLevel& h, int j) {
     }
 }
 
-int miugks_adjoint(miugks_ctx* ctx, int kind, const int* walls, int n, const int* param_faces, int n_param,
-                   double tol, int max_iter, double* dJ_dTw, int* iters, double* res_out) {
+extern "C++" {
+// (dr/df)^T lam = b (b in ctx->a_b) by restarted GMRES with the Krylov basis
+// and the preconditioner's vectors stored as VT; every product, dot product
+// and the Hessenberg arithmetic in double.  lam itself is double: each
+// restart forms the true residual b - (dr/df)^T lam in double and solves for
+// a correction in VT, so with float vectors the restarts refine lam like
+// mixed-precision iterative refinement rather than stalling at the float
+// rounding of lam.  Then dJ/dT_w per parameter face from the sides (wall
+// side, owning parameter) listed.
+template <typename VT>
+static int adj_gmres(miugks_ctx* ctx, int kind, double tol, int max_iter, const std::vector<int>& sides,
+                     const std::vector<int>& owner, int n_param, double* dJ_dTw, int* iters, double* res_out) {
+    const Geo& g = ctx->geo[0];
+    const size_t N = 2 * (size_t)ctx->nk * g.nc;
+    int rc;
+    const double vs = sizeof(VT);
+    double* lam = ctx->a_lam;
+    VT* a_out = (VT*)ctx->a_out;
+    VT* a_y = (VT*)ctx->a_y;
+    VT* a_res = (VT*)ctx->a_res;
+    LAUNCH(ctx, "zero", N * 8.0, k_zero<double>, dim3((unsigned)std::min<size_t>((N + 255) / 256, 1 << 16)),
+           dim3(256), lam, N);
+    // (dr/df)^T lam = b by restarted GMRES, right-preconditioned with
+    // M^-1 = -A^-T (A the velocity-diagonal correction operator, solved by one
+    // downwind sweep per velocity); classical Gram-Schmidt applied twice, the
+    // dot products of a step in one launch
+    const int threads = ((g.ny + 63) / 64) * 64;
+    const size_t lds = 2 * (size_t)g.ny * sizeof(double);
+    const double vb = (double)N * 8;
+    int m = (int)std::min<double>(30.0, std::max(4.0, std::floor(32e9 / vb) - 1.0));
+    if (!ctx->a_V || ctx->a_m != m) {
+        if ((rc = dev_alloc(ctx, (void**)&ctx->a_V, (size_t)(m + 1) * N * sizeof(double))) ||
+            (rc = dev_alloc(ctx, (void**)&ctx->a_h, (size_t)(m + 1) * sizeof(double))) ||
+            (rc = dev_alloc(ctx, (void**)&ctx->a_dpart, (size_t)(m + 1) * DOT_BLOCKS * sizeof(double))))
+            return rc;
+        ctx->a_m = m;
+    }
+    VT* V = (VT*)ctx->a_V;
+    auto vec = [&](int i) { return V + (size_t)i * N; };
+    const dim3 nbv((unsigned)((N + 255) / 256));
+    auto sweep = [&](const VT* in, VT* out) {
+        LAUNCH_SH(ctx, "adj_sweep", 2.0 * N * vs, lds, k_adj_sweep<VT>, dim3(ctx->nk), dim3(threads), g, ctx->vel,
+                  (const double*)ctx->a_crec, in, out);
+    };
+    std::vector<double> dpart((size_t)(m + 1) * DOT_BLOCKS), hv(m + 1);
+    // dot products of w with vec(0..k)
+    auto dots = [&](const VT* w, const VT* base, int k, double* outd) -> int {
+        // model bytes: the k vectors and w once per group of eight
+        LAUNCH(ctx, "adj_dots", (k + (k + 7) / 8) * (double)N * vs, k_adj_dots<VT>, dim3(DOT_BLOCKS), dim3(256), w,
+               base, N, k, N, ctx->a_dpart);
+        HIP_TRY(hipMemcpyAsync(dpart.data(), ctx->a_dpart, (size_t)k * DOT_BLOCKS * sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        for (int i = 0; i < k; ++i) {
+            double t = 0.0;
+            for (int b2 = 0; b2 < DOT_BLOCKS; ++b2) t += dpart[(size_t)i * DOT_BLOCKS + b2];
+            outd[i] = t;
+        }
+        return check_launch(ctx);
+    };
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), yv(m);
+    std::vector<double> part(ctx->a_nparts);
+    double r0 = 0.0, rn = 0.0;
+    int it = 0;
+    for (bool first = true;; first = false) {
+        // true residual b - (dr/df)^T lam into vec(0)
+        adj_product<double>(ctx, lam, ctx->a_out);
+        LAUNCH(ctx, "adj_residual", N * (16.0 + vs), k_adj_residual<VT>, dim3(ctx->a_nparts), dim3(256),
+               (const double*)ctx->a_b, (const double*)ctx->a_out, vec(0), N, ctx->a_part);
+        HIP_TRY(hipMemcpyAsync(part.data(), ctx->a_part, part.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        if ((rc = check_launch(ctx))) return rc;
+        double ss = 0.0;
+        for (double x : part) ss += x;
+        rn = std::sqrt(ss);
+        if (first) r0 = rn;
+        if (!std::isfinite(rn)) {
+            ctx->err = "adjoint iteration diverged";
+            return MIUGKS_EDIVERGED;
+        }
+        if (rn <= tol * r0 || r0 == 0.0 || it >= max_iter) break;
+        LAUNCH(ctx, "adj_scale", 2.0 * N * vs, k_adj_scale<VT>, nbv, dim3(256), vec(0), (const VT*)vec(0), 1.0 / rn,
+               N);
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = rn;
+        int k = 0;
+        for (; k < m && it < max_iter; ++k) {
+            // w = (dr/df)^T M^-1 v_k = -(dr/df)^T A^-T v_k
+            sweep(vec(k), a_y);
+            adj_product<VT>(ctx, a_y, a_out);
+            LAUNCH(ctx, "adj_scale", 2.0 * N * vs, k_adj_scale<VT>, nbv, dim3(256), vec(k + 1), (const VT*)a_out,
+                   -1.0, N);
+            for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = 0.0;
+            // two projections; the second also takes |w|^2 (w is vec(k + 1),
+            // the next vector of the block), and |w - sum h v|^2 = |w|^2 - sum h^2
+            // for the small second-pass coefficients
+            double nn = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                if ((rc = dots(vec(k + 1), V, k + 1 + pass, hv.data()))) return rc;
+                for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] += hv[i];
+                if (pass == 1) {
+                    nn = hv[k + 1];
+                    for (int i = 0; i <= k; ++i) nn -= hv[i] * hv[i];
+                }
+                HIP_TRY(hipMemcpyAsync(ctx->a_h, hv.data(), (k + 1) * sizeof(double), hipMemcpyHostToDevice,
+                                       ctx->stream));
+                LAUNCH(ctx, "adj_lincomb", (k + 3.0) * N * vs, k_adj_lincomb<VT>, nbv, dim3(256), vec(k + 1),
+                       (const VT*)V, N, (const double*)ctx->a_h, k + 1, -1.0, N);
+            }
+            double hn = std::sqrt(std::max(nn, 0.0));
+            H[(size_t)(k + 1) * m + k] = hn;
+            if (hn > 0.0)
+                LAUNCH(ctx, "adj_scale", 2.0 * N * vs, k_adj_scale<VT>, nbv, dim3(256), vec(k + 1),
+                       (const VT*)vec(k + 1), 1.0 / hn, N);
+            // Givens rotations of the Hessenberg column
+            for (int i = 0; i < k; ++i) {
+                double a = H[(size_t)i * m + k], b2 = H[(size_t)(i + 1) * m + k];
+                H[(size_t)i * m + k] = cs[i] * a + sn[i] * b2;
+                H[(size_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * b2;
+            }
+            double a = H[(size_t)k * m + k], b2 = H[(size_t)(k + 1) * m + k];
+            double rr = std::hypot(a, b2);
+            cs[k] = rr > 0.0 ? a / rr : 1.0;
+            sn[k] = rr > 0.0 ? b2 / rr : 0.0;
+            H[(size_t)k * m + k] = rr;
+            H[(size_t)(k + 1) * m + k] = 0.0;
+            gv[k + 1] = -sn[k] * gv[k];
+            gv[k] = cs[k] * gv[k];
+            ++it;
+            if (std::fabs(gv[k + 1]) <= tol * r0 || hn == 0.0) {
+                ++k;
+                break;
+            }
+        }
+        // y from the triangular system, u = V y, lam += M^-1 u = -A^-T u
+        for (int i = k - 1; i >= 0; --i) {
+            double t = gv[i];
+            for (int j = i + 1; j < k; ++j) t -= H[(size_t)i * m + j] * yv[j];
+            yv[i] = H[(size_t)i * m + i] != 0.0 ? t / H[(size_t)i * m + i] : 0.0;
+        }
+        HIP_TRY(hipMemcpyAsync(ctx->a_h, yv.data(), k * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        LAUNCH(ctx, "zero", N * vs, k_zero<VT>, dim3((unsigned)std::min<size_t>((N + 255) / 256, 1 << 16)),
+               dim3(256), a_res, N);
+        LAUNCH(ctx, "adj_lincomb", (k + 2.0) * N * vs, k_adj_lincomb<VT>, nbv, dim3(256), a_res, (const VT*)V, N,
+               (const double*)ctx->a_h, k, 1.0, N);
+        sweep(a_res, a_y);
+        LAUNCH(ctx, "adj_axpy", N * (16.0 + vs), (k_adj_axpy<double, VT>), nbv, dim3(256), lam, (const VT*)a_y,
+               -1.0, N);
+    }
+    // dJ/dT_w = dJ/dT_w|_f - lam^T dr/dT_w, summed over the sides of each face
+    if (!sides.empty()) {
+        LAUNCH(ctx, "adj_paramgrad", 0.0, k_adj_paramgrad<double>, dim3(((int)sides.size() + 3) / 4), dim3(256),
+               g, ctx->vel, ctx->gas.K_int, kind, (const double*)ctx->a_objw, (const double*)ctx->a_Qj,
+               (const double*)ctx->a_rhow, (const double*)lam, (const int*)ctx->a_sides, (int)sides.size(),
+               ctx->a_grad);
+        std::vector<double> gs(sides.size());
+        HIP_TRY(hipMemcpyAsync(gs.data(), ctx->a_grad, gs.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        for (int p = 0; p < n_param; ++p) dJ_dTw[p] = 0.0;
+        for (size_t i = 0; i < sides.size(); ++i) dJ_dTw[owner[i]] += gs[i];
+    }
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if ((rc = check_launch(ctx))) return rc;
+    if (iters) *iters = it;
+    if (res_out) *res_out = r0 > 0.0 ? rn / r0 : 0.0;
+    return (r0 == 0.0 || rn <= tol * r0) ? MIUGKS_OK : MIUGKS_ENOTCONVERGED;
+}
+}  // extern "C++"
+
+int miugks_adjoint_ex(miugks_ctx* ctx, int kind, const int* walls, int n, const int* param_faces, int n_param,
+                      double tol, int max_iter, int krylov_dtype, double* dJ_dTw, int* iters, double* res_out) {
     if (!ctx || n < 0 || n_param < 0 || (n > 0 && !walls) || (n_param > 0 && (!param_faces || !dJ_dTw)) ||
         max_iter < 0)
         return MIUGKS_EINVAL;
     int rc;
     if ((rc = adj_check(ctx))) return rc;
+    if (krylov_dtype != MIUGKS_FP64 && krylov_dtype != MIUGKS_FP32F) {
+        ctx->err = "krylov_dtype must be MIUGKS_FP64 or MIUGKS_FP32F";
+        return MIUGKS_EINVAL;
+    }
     if (kind < MIUGKS_LOAD_PRESSURE || kind > MIUGKS_LOAD_HEAT) {
         ctx->err = "objective kind must be MIUGKS_LOAD_PRESSURE, MIUGKS_LOAD_SHEAR or MIUGKS_LOAD_HEAT";
         return MIUGKS_EINVAL;
@@ -2351,14 +2530,14 @@ int miugks_adjoint(miugks_ctx* ctx, int kind, const int* walls, int n, const int
             if (sgn == 0) {   // start from the scaled state
                 HIP_TRY(hipMemcpyAsync(ctx->f, ctx->a_fsave, N * sizeof(double), hipMemcpyDeviceToDevice,
                                        ctx->stream));
-                LAUNCH(ctx, "adj_axpy", 3.0 * N * 8, k_adj_axpy, nbN, dim3(256), (double*)ctx->f,
+                LAUNCH(ctx, "adj_axpy", 3.0 * N * 8, (k_adj_axpy<double, double>), nbN, dim3(256), (double*)ctx->f,
                        (const double*)ctx->f, sc, N);
             } else {          // 2 f* - f+: the reflection of the first state, of mass M0 (1 - delta)
                 HIP_TRY(hipMemcpyAsync(ctx->a_res, ctx->f, N * sizeof(double), hipMemcpyDeviceToDevice,
                                        ctx->stream));
-                LAUNCH(ctx, "adj_scale", 2.0 * N * 8, k_adj_scale, nbN, dim3(256), (double*)ctx->f,
+                LAUNCH(ctx, "adj_scale", 2.0 * N * 8, k_adj_scale<double>, nbN, dim3(256), (double*)ctx->f,
                        (const double*)ctx->a_fsave, 2.0, N);
-                LAUNCH(ctx, "adj_axpy", 3.0 * N * 8, k_adj_axpy, nbN, dim3(256), (double*)ctx->f,
+                LAUNCH(ctx, "adj_axpy", 3.0 * N * 8, (k_adj_axpy<double, double>), nbN, dim3(256), (double*)ctx->f,
                        (const double*)ctx->a_res, -1.0, N);
             }
             ctx->M0 = M0 * (1.0 + sc);
@@ -2385,153 +2564,15 @@ int miugks_adjoint(miugks_ctx* ctx, int kind, const int* walls, int n, const int
     dim3 nbN((unsigned)((N / 2 + 255) / 256));
     LAUNCH(ctx, "adj_objgrad", N * 8.0, k_adj_objgrad, nbN, dim3(256), g, ctx->vel, kind,
            (const double*)ctx->a_objw, (const double*)ctx->a_Qj, mu, ctx->a_b);
-    LAUNCH(ctx, "zero", N * 8.0, k_zero<double>, dim3((unsigned)std::min<size_t>((N + 255) / 256, 1 << 16)), dim3(256),
-           ctx->a_lam, N);
-    // (dr/df)^T lam = b by restarted GMRES, right-preconditioned with
-    // M^-1 = -A^-T (A the velocity-diagonal correction operator, solved by one
-    // downwind sweep per velocity); classical Gram-Schmidt applied twice, the
-    // dot products of a step in one launch
-    const int threads = ((g.ny + 63) / 64) * 64;
-    const size_t lds = 2 * (size_t)g.ny * sizeof(double);
-    const double vb = (double)N * 8;
-    int m = (int)std::min<double>(30.0, std::max(4.0, std::floor(32e9 / vb) - 1.0));
-    if (!ctx->a_V || ctx->a_m != m) {
-        if ((rc = dev_alloc(ctx, (void**)&ctx->a_V, (size_t)(m + 1) * N * sizeof(double))) ||
-            (rc = dev_alloc(ctx, (void**)&ctx->a_h, (size_t)(m + 1) * sizeof(double))) ||
-            (rc = dev_alloc(ctx, (void**)&ctx->a_dpart, (size_t)(m + 1) * DOT_BLOCKS * sizeof(double))))
-            return rc;
-        ctx->a_m = m;
-    }
-    double* V = ctx->a_V;
-    auto vec = [&](int i) { return V + (size_t)i * N; };
-    const dim3 nbv((unsigned)((N + 255) / 256));
-    auto sweep = [&](const double* in, double* out) {
-        LAUNCH_SH(ctx, "adj_sweep", 2.0 * N * 8, lds, k_adj_sweep, dim3(ctx->nk), dim3(threads), g, ctx->vel,
-                  (const double*)ctx->a_crec, in, out);
-    };
-    std::vector<double> dpart((size_t)(m + 1) * DOT_BLOCKS), hv(m + 1);
-    // dot products of w with vec(0..k)
-    auto dots = [&](const double* w, const double* base, int k, double* outd) -> int {
-        // model bytes: the k vectors and w once per group of eight
-        LAUNCH(ctx, "adj_dots", (k + (k + 7) / 8) * (double)N * 8, k_adj_dots, dim3(DOT_BLOCKS), dim3(256), w, base,
-               N, k, N, ctx->a_dpart);
-        HIP_TRY(hipMemcpyAsync(dpart.data(), ctx->a_dpart, (size_t)k * DOT_BLOCKS * sizeof(double),
-                               hipMemcpyDeviceToHost, ctx->stream));
-        HIP_TRY(hipStreamSynchronize(ctx->stream));
-        for (int i = 0; i < k; ++i) {
-            double t = 0.0;
-            for (int b2 = 0; b2 < DOT_BLOCKS; ++b2) t += dpart[(size_t)i * DOT_BLOCKS + b2];
-            outd[i] = t;
-        }
-        return check_launch(ctx);
-    };
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), yv(m);
-    std::vector<double> part(ctx->a_nparts);
-    double r0 = 0.0, rn = 0.0;
-    int it = 0;
-    for (bool first = true;; first = false) {
-        // true residual b - (dr/df)^T lam into vec(0)
-        adj_product(ctx, ctx->a_lam, ctx->a_out);
-        LAUNCH(ctx, "adj_residual", 3.0 * N * 8, k_adj_residual, dim3(ctx->a_nparts), dim3(256),
-               (const double*)ctx->a_b, (const double*)ctx->a_out, vec(0), N, ctx->a_part);
-        HIP_TRY(hipMemcpyAsync(part.data(), ctx->a_part, part.size() * sizeof(double), hipMemcpyDeviceToHost,
-                               ctx->stream));
-        HIP_TRY(hipStreamSynchronize(ctx->stream));
-        if ((rc = check_launch(ctx))) return rc;
-        double ss = 0.0;
-        for (double x : part) ss += x;
-        rn = std::sqrt(ss);
-        if (first) r0 = rn;
-        if (!std::isfinite(rn)) {
-            ctx->err = "adjoint iteration diverged";
-            return MIUGKS_EDIVERGED;
-        }
-        if (rn <= tol * r0 || r0 == 0.0 || it >= max_iter) break;
-        LAUNCH(ctx, "adj_scale", 2.0 * N * 8, k_adj_scale, nbv, dim3(256), vec(0), (const double*)vec(0), 1.0 / rn, N);
-        std::fill(gv.begin(), gv.end(), 0.0);
-        gv[0] = rn;
-        int k = 0;
-        for (; k < m && it < max_iter; ++k) {
-            // w = (dr/df)^T M^-1 v_k = -(dr/df)^T A^-T v_k
-            sweep(vec(k), ctx->a_y);
-            adj_product(ctx, ctx->a_y, ctx->a_out);
-            LAUNCH(ctx, "adj_scale", 2.0 * N * 8, k_adj_scale, nbv, dim3(256), vec(k + 1),
-                   (const double*)ctx->a_out, -1.0, N);
-            for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = 0.0;
-            // two projections; the second also takes |w|^2 (w is vec(k + 1),
-            // the next vector of the block), and |w - sum h v|^2 = |w|^2 - sum h^2
-            // for the small second-pass coefficients
-            double nn = 0.0;
-            for (int pass = 0; pass < 2; ++pass) {
-                if ((rc = dots(vec(k + 1), V, k + 1 + pass, hv.data()))) return rc;
-                for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] += hv[i];
-                if (pass == 1) {
-                    nn = hv[k + 1];
-                    for (int i = 0; i <= k; ++i) nn -= hv[i] * hv[i];
-                }
-                HIP_TRY(hipMemcpyAsync(ctx->a_h, hv.data(), (k + 1) * sizeof(double), hipMemcpyHostToDevice,
-                                       ctx->stream));
-                LAUNCH(ctx, "adj_lincomb", (k + 3.0) * N * 8, k_adj_lincomb, nbv, dim3(256), vec(k + 1),
-                       (const double*)V, N, (const double*)ctx->a_h, k + 1, -1.0, N);
-            }
-            double hn = std::sqrt(std::max(nn, 0.0));
-            H[(size_t)(k + 1) * m + k] = hn;
-            if (hn > 0.0)
-                LAUNCH(ctx, "adj_scale", 2.0 * N * 8, k_adj_scale, nbv, dim3(256), vec(k + 1),
-                       (const double*)vec(k + 1), 1.0 / hn, N);
-            // Givens rotations of the Hessenberg column
-            for (int i = 0; i < k; ++i) {
-                double a = H[(size_t)i * m + k], b2 = H[(size_t)(i + 1) * m + k];
-                H[(size_t)i * m + k] = cs[i] * a + sn[i] * b2;
-                H[(size_t)(i + 1) * m + k] = -sn[i] * a + cs[i] * b2;
-            }
-            double a = H[(size_t)k * m + k], b2 = H[(size_t)(k + 1) * m + k];
-            double rr = std::hypot(a, b2);
-            cs[k] = rr > 0.0 ? a / rr : 1.0;
-            sn[k] = rr > 0.0 ? b2 / rr : 0.0;
-            H[(size_t)k * m + k] = rr;
-            H[(size_t)(k + 1) * m + k] = 0.0;
-            gv[k + 1] = -sn[k] * gv[k];
-            gv[k] = cs[k] * gv[k];
-            ++it;
-            if (std::fabs(gv[k + 1]) <= tol * r0 || hn == 0.0) {
-                ++k;
-                break;
-            }
-        }
-        // y from the triangular system, u = V y, lam += M^-1 u = -A^-T u
-        for (int i = k - 1; i >= 0; --i) {
-            double t = gv[i];
-            for (int j = i + 1; j < k; ++j) t -= H[(size_t)i * m + j] * yv[j];
-            yv[i] = H[(size_t)i * m + i] != 0.0 ? t / H[(size_t)i * m + i] : 0.0;
-        }
-        HIP_TRY(hipMemcpyAsync(ctx->a_h, yv.data(), k * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-        LAUNCH(ctx, "zero", N * 8.0, k_zero<double>, dim3((unsigned)std::min<size_t>((N + 255) / 256, 1 << 16)),
-               dim3(256), ctx->a_res, N);
-        LAUNCH(ctx, "adj_lincomb", (k + 2.0) * N * 8, k_adj_lincomb, nbv, dim3(256), ctx->a_res, (const double*)V,
-               N, (const double*)ctx->a_h, k, 1.0, N);
-        sweep(ctx->a_res, ctx->a_y);
-        LAUNCH(ctx, "adj_axpy", 3.0 * N * 8, k_adj_axpy, nbv, dim3(256), ctx->a_lam, (const double*)ctx->a_y, -1.0,
-               N);
-    }
-    // dJ/dT_w = dJ/dT_w|_f - lam^T dr/dT_w, summed over the sides of each face
-    if (!sides.empty()) {
-        LAUNCH(ctx, "adj_paramgrad", 0.0, k_adj_paramgrad, dim3(((int)sides.size() + 3) / 4), dim3(256), g,
-               ctx->vel, ctx->gas.K_int, kind, (const double*)ctx->a_objw, (const double*)ctx->a_Qj,
-               (const double*)ctx->a_rhow, (const double*)ctx->a_lam, (const int*)ctx->a_sides, (int)sides.size(),
-               ctx->a_grad);
-        std::vector<double> gs(sides.size());
-        HIP_TRY(hipMemcpyAsync(gs.data(), ctx->a_grad, gs.size() * sizeof(double), hipMemcpyDeviceToHost,
-                               ctx->stream));
-        HIP_TRY(hipStreamSynchronize(ctx->stream));
-        for (int p = 0; p < n_param; ++p) dJ_dTw[p] = 0.0;
-        for (size_t i = 0; i < sides.size(); ++i) dJ_dTw[owner[i]] += gs[i];
-    }
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    if ((rc = check_launch(ctx))) return rc;
-    if (iters) *iters = it;
-    if (res_out) *res_out = r0 > 0.0 ? rn / r0 : 0.0;
-    return (r0 == 0.0 || rn <= tol * r0) ? MIUGKS_OK : MIUGKS_ENOTCONVERGED;
+    if (krylov_dtype == MIUGKS_FP32F)
+        return adj_gmres<float>(ctx, kind, tol, max_iter, sides, owner, n_param, dJ_dTw, iters, res_out);
+    return adj_gmres<double>(ctx, kind, tol, max_iter, sides, owner, n_param, dJ_dTw, iters, res_out);
+}
+
+int miugks_adjoint(miugks_ctx* ctx, int kind, const int* walls, int n, const int* param_faces, int n_param,
+                   double tol, int max_iter, double* dJ_dTw, int* iters, double* res_out) {
+    return miugks_adjoint_ex(ctx, kind, walls, n, param_faces, n_param, tol, max_iter, MIUGKS_FP64, dJ_dTw, iters,
+                             res_out);
 }
 
 int miugks_get_f(miugks_ctx* ctx, void* dst, int dtype, int on_device) {

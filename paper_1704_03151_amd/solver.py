@@ -246,16 +246,21 @@ class Solver:
                                                    out.ctypes.data_as(ctypes.c_void_p), _C.FP64, 0))
         return out
 
-    def adjoint(self, kind, walls, faces, tol=1e-10, max_iter=2000):
+    def adjoint(self, kind, walls, faces, tol=1e-10, max_iter=2000, krylov_precision="fp64"):
         """dJ/dTw of J = sum_walls S load_kind for the listed mesh faces; returns
-        (status, gradient, corrections, relative residual)."""
+        (status, gradient, corrections, relative residual).  krylov_precision
+        "fp32" keeps the Krylov basis and the preconditioner's vectors in float
+        (miugks_adjoint_ex)."""
+        if krylov_precision not in ("fp64", "fp32"):
+            raise ValueError("krylov_precision must be 'fp64' or 'fp32'")
         ids = np.ascontiguousarray(walls, np.int32)
         fc = np.ascontiguousarray(faces, np.int32)
         g = np.zeros(len(fc))
         it = ctypes.c_int()
         res = np.zeros(1)
-        rc = _C.lib.miugks_adjoint(self.h, int(kind), _C.iptr(ids), len(ids), _C.iptr(fc), len(fc), float(tol),
-                                   int(max_iter), _C.dptr(g), ctypes.byref(it), _C.dptr(res))
+        code = _C.FP32F if krylov_precision == "fp32" else _C.FP64
+        rc = _C.lib.miugks_adjoint_ex(self.h, int(kind), _C.iptr(ids), len(ids), _C.iptr(fc), len(fc), float(tol),
+                                      int(max_iter), code, _C.dptr(g), ctypes.byref(it), _C.dptr(res))
         self._check(rc, allow=(_C.ENOTCONVERGED,))
         return rc, g, it.value, float(res[0])
 

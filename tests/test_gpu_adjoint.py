@@ -11,7 +11,8 @@
   the gradient is compared at 1e-6;
 * the same in an open domain (a plate in a farfield: no mass term, and both
   sides of the plate take the one face temperature) for the pressure, shear
-  and heat loads."""
+  and heat loads;
+* both again with the Krylov basis stored in float."""
 import numpy as np
 import pytest
 
@@ -144,6 +145,57 @@ def test_open_domain_adjoint_gradient_against_oracle():
               flush=True)
         assert st == 0
         assert err < 1e-7, (kind, g, ref)
+    gpu.close()
+
+
+def test_fp32_krylov_adjoint_against_oracle():
+    """The adjoint with the Krylov basis and the preconditioner's vectors
+    stored in float (the multiplier, dot products and the contraction in
+    double, each restart refining the multiplier from the true residual): the
+    tiny cavity's lid-shear gradient against the oracle's fixed-mass tangent,
+    and the open plate's three loads, to the double form's tolerances.  (With
+    the multiplier itself in float the residual stalled at 3e-7 on the plate,
+    where the shear gradient, a near cancellation of its two sides, then
+    erred by 2e-5.)"""
+    from paper_1704_03151_amd import Solver
+    case = _tiny_cavity()
+    print("[adjoint] tiny cavity: dJ/dTw with a float Krylov basis", flush=True)
+    gpu = Solver(case, precision="fp64")
+    orc = Oracle(case)
+    rc, n, res = gpu.iterate(300, tol=2e-13)
+    ok, norms = orc.iterate(300, tol=2e-13)
+    assert rc == 0 and ok, (rc, res, norms)
+    cell, side = gpu.wall_list()
+    lid = list(np.nonzero(side == 3)[0])
+    nfx = (N + 1) * N
+    faces = [nfx + 0, nfx + 1, nfx + 3, 0]
+    ref = ad.Sensitivity(orc).gradient(ad.LOAD_SHEAR, lid, faces)
+    st, g, iters, rel = gpu.adjoint(ad.LOAD_SHEAR, lid, faces, tol=1e-9, max_iter=2000, krylov_precision="fp32")
+    err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+    print(f"[adjoint] float basis: {iters} corrections, relative residual {rel:.2e}, error {err:.2e}",
+          flush=True)
+    assert st == 0 and err < 1e-8, (st, rel, g, ref)
+    gpu.close()
+
+    case, face = tiny_open_plate()
+    print("[adjoint] tiny open plate: dJ/dTw with a float Krylov basis", flush=True)
+    gpu = Solver(case, precision="fp64")
+    orc = Oracle(case)
+    rc, n, res = gpu.iterate(300, tol=2e-13)
+    ok, norms = orc.iterate(300, tol=2e-13)
+    assert rc == 0 and ok, (rc, res, norms)
+    walls = list(range(len(gpu.wall_list()[0])))
+    S = ad.Sensitivity(orc)
+    T = S.tangent(S.jacobian(), S.dr_dT([face]))
+    for kind in (ad.LOAD_PRESSURE, ad.LOAD_SHEAR, ad.LOAD_HEAT):
+        ref = S.dJ_df(kind, walls) @ T + S.dJ_dT(kind, walls, [face])
+        st, g, iters, rel = gpu.adjoint(kind, walls, [face], tol=1e-9, max_iter=2000, krylov_precision="fp32")
+        err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+        print(f"[adjoint] kind {kind}, float basis: {iters} corrections, relative residual {rel:.2e}, "
+              f"error {err:.2e}", flush=True)
+        assert st == 0 and err < 1e-7, (kind, rel, g, ref)
+    with pytest.raises(ValueError):
+        gpu.adjoint(ad.LOAD_SHEAR, walls, [face], krylov_precision="fp16")
     gpu.close()
 
 

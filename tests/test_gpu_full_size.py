@@ -103,7 +103,9 @@ def test_adjoint_full_size_against_steady_state_differences():
     gradient over the 64 bottom-face temperatures against central differences
     (h = 1e-4, the step of the survey's C17) of the GPU's own steady states,
     each converged to 1e-13 at the same mass, on 8 seeded faces.  Every face
-    agrees within 2.5e-4 of the largest gradient component.  The per-face
+    agrees within 2.5e-4 of the largest gradient component.  The adjoint with
+    its Krylov basis in float matches the double one to 1e-7 of the largest.
+    The per-face
     ratios of C17's scale 1e-4 max(|g_FD|, 1e-3 max|g|) are printed: the
     differences do not shrink with h (central or 4-point stencils), so they
     are the finite differences' own uncertainty at this convergence level."""
@@ -121,6 +123,13 @@ def test_adjoint_full_size_against_steady_state_differences():
     print(f"[full] adjoint: {iters} corrections, relative residual {rel:.2e}", flush=True)
     assert st == 0
     gmax = np.max(np.abs(g))
+    # the float Krylov basis reaches the same tolerance, and every face then
+    # agrees with the double form to 1e-7 of the largest
+    st32, g32, it32, rel32 = s.adjoint(1, lid, faces, tol=2e-10, max_iter=6000, krylov_precision="fp32")
+    e32 = np.max(np.abs(g32 - g)) / gmax
+    print(f"[full] adjoint with a float Krylov basis: {it32} corrections, relative residual {rel32:.2e}, "
+          f"against the double form {e32:.1e} of max|g|", flush=True)
+    assert st32 == 0 and e32 < 1e-7, (st32, rel32, e32)
     f0 = s.get_f()
     h = 1e-4
     pick = sorted(np.random.default_rng(1704).choice(case.nx, 8, replace=False))
