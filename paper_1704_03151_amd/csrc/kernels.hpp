@@ -1339,10 +1339,10 @@ __device__ __forceinline__ void face_flux_side(const FaceConst<T>& F, int side, 
 // difference of fluxes scaled by S/V, and single-precision products would
 // leave ~1e-6 of rounding noise in it; div is stored in T.
 //
-// A block is a tile of cells (lanes) by a chunk of KCH velocities, wave w
+// A block is a tile of cells (lanes) by a chunk of KCHF velocities, wave w
 // taking velocities k0 + w + WAVES j.  The velocity is the same in every
 // lane, so the upwind side of a face is a scalar branch, the stencil loads
-// take scalar row offsets, and a thread's MK velocities are unrolled into
+// take scalar row offsets, and a thread's MKF velocities are unrolled into
 // registers.
 //
 // A cell's +x face is the -x face of the next cell: every interior +x face
@@ -1351,6 +1351,14 @@ __device__ __forceinline__ void face_flux_side(const FaceConst<T>& F, int side, 
 // pack whole into a tile (64 mod nx = 0, so a tile's last cell ends a row);
 // otherwise 63, and lane 63 forms only the -x face flux of the next tile's
 // first cell, for lane 62.
+//
+// MKF = 16 velocities per thread (two of the other kernels' MK): the 23-word
+// face records and the stencil set-up of each face are loaded once per 16
+// velocities, and the chunk partials of R halve; 219 (FP32) / 235 (FP64)
+// registers keep two wavefronts per SIMD (24 no longer unrolls).
+constexpr int MKF = 16;                // velocities per thread of the flux
+constexpr int KCHF = WAVES * MKF;      // velocities per flux chunk
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const T* __restrict__ f,
                                                   const double* __restrict__ fp,
@@ -1369,7 +1377,7 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
     const int tile = Lb % nt, chunk = Lb / nt;
     const int lane = threadIdx.x & (TILE - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / TILE);
-    const int nk = vel.nk, k0 = chunk * KCH, k1 = min(nk, k0 + KCH);
+    const int nk = vel.nk, k0 = chunk * KCHF, k1 = min(nk, k0 + KCHF);
     // this wave's velocities k0 + wave + WAVES j, j < nmine
     const int nmine = k1 - k0 > wave ? (k1 - k0 - wave + WAVES - 1) / WAVES : 0;
     const int c = tile * tstride + lane;
@@ -1381,9 +1389,9 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
     const __amdgpu_buffer_rsrc_t RH = buf_rsrc(f + ho + (size_t)k0 * nc, chunkb);
     const unsigned so0 = (unsigned)wave * rowb, sostep = (unsigned)WAVES * rowb;
     double acc[4] = {0, 0, 0, 0};
-    A dG[MK], dH[MK];
+    A dG[MKF], dH[MKF];
 #pragma unroll
-    for (int j = 0; j < MK; ++j) dG[j] = dH[j] = A(0);
+    for (int j = 0; j < MKF; ++j) dG[j] = dH[j] = A(0);
     if (valid && !g.solid[c]) {
         const int ix = c % g.nx, iy = c / g.nx;
         const unsigned oc = (unsigned)c * sizeof(T);
@@ -1417,7 +1425,7 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
                 rw = A(rho_w[jw]);
             }
 #pragma unroll
-            for (int j = 0; j < MK; ++j) {
+            for (int j = 0; j < MKF; ++j) {
                 if (j >= nmine) break;
                 const int k = k0 + wave + WAVES * j;
                 const unsigned so = so0 + j * sostep;
@@ -1485,7 +1493,7 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
                 FaceVals<T> cur{}, nxt{};
                 if (nmine > 0) stencil_load<T>(st, RG, RH, so0, nxt);
 #pragma unroll
-                for (int j = 0; j < MK; ++j) {
+                for (int j = 0; j < MKF; ++j) {
                     if (j >= nmine) break;
                     const int k = k0 + wave + WAVES * j;
                     const unsigned so = so0 + j * sostep;
@@ -1508,7 +1516,7 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
                 const A lam = A(1.0 / g.w_T[jw]), Uw = A(g.w_U[jw]), Vw = A(g.w_V[jw]);
                 const A rw = A(rho_w[jw]);
 #pragma unroll
-                for (int j = 0; j < MK; ++j) {
+                for (int j = 0; j < MKF; ++j) {
                     if (j >= nmine) break;
                     const int k = k0 + wave + WAVES * j;
                     const A u = vel.u[k], v = vel.v[k];
@@ -1529,7 +1537,7 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
             } else {
                 const bool far = code == NB_FARFIELD, sym = code == NB_SYMMETRY;
 #pragma unroll
-                for (int j = 0; j < MK; ++j) {
+                for (int j = 0; j < MKF; ++j) {
                     if (j >= nmine) break;
                     const int k = k0 + wave + WAVES * j;
                     const A un = sign * (d == 0 ? A(vel.u[k]) : A(vel.v[k]));
@@ -1554,7 +1562,7 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
     }
     if (own) {
 #pragma unroll
-        for (int j = 0; j < MK; ++j) {
+        for (int j = 0; j < MKF; ++j) {
             if (j >= nmine) break;
             const int k = k0 + wave + WAVES * j;
             div[(size_t)k * nc + c] = T(dG[j]);

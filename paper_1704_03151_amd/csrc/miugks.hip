@@ -513,7 +513,7 @@ struct Path {
         wall_sums(c, top, F(c), c->rho_w);
         // the flux keeps chunks of KCH velocities: a block holds a thread's MK
         // velocities of div in registers, and its partial sums are 4 per cell
-        const int nkf = nchunks(c->nk);
+        const int nkf = nchunks(c->nk, KCHF);
         LAUNCH(c, "flux_div", 2 * arr(c, top) + (2.0 * NFP + 4.0 * nkf) * nc8, k_flux_div<T>, dim3(flux_tiles(g), nkf),
                dim3(256), g, c->vel, c->gas, F(c), c->fp, c->rho_w, (const T*)c->finf, (T*)c->div, c->part, flux_stride(g));
         LAUNCH(c, "chunk_sum", 4.0 * (nkf + 1) * nc8, k_chunk_sum, dim3(nblk(4 * g.nc)), dim3(256),
