@@ -211,19 +211,27 @@ __device__ __forceinline__ Chunk chunk_of_xcd(int nc, int nk, int kch = KCH) {
 }
 
 // sum M partial values across the 4 waves of the block and store them as
-// part[(chunk * M + m) * n + i]
-template <int M>
+// part[(chunk * M + m) * n + i]; sh holds ceil(M / R) * WAVES * TILE doubles
+// and the values pass through it in R rounds (less LDS per block)
+template <int M, int R = 1>
 __device__ __forceinline__ void reduce_store(double* acc, double* sh, double* part, int n, int i,
                                              bool valid, int chunk = -1) {
     if (chunk < 0) chunk = blockIdx.y;
+    constexpr int Q = (M + R - 1) / R;
     int lane = threadIdx.x & (TILE - 1), wave = threadIdx.x / TILE;
-    for (int m = 0; m < M; ++m) sh[(m * WAVES + wave) * TILE + lane] = acc[m];
-    __syncthreads();
-    if (wave == 0 && valid) {
-        for (int m = 0; m < M; ++m) {
-            double s = sh[(m * WAVES + 0) * TILE + lane];
-            for (int w = 1; w < WAVES; ++w) s += sh[(m * WAVES + w) * TILE + lane];
-            part[((size_t)chunk * M + m) * n + i] = s;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (r > 0) __syncthreads();   // the previous round is read
+#pragma unroll
+        for (int m = r * Q; m < M && m < (r + 1) * Q; ++m) sh[((m - r * Q) * WAVES + wave) * TILE + lane] = acc[m];
+        __syncthreads();
+        if (wave == 0 && valid) {
+#pragma unroll
+            for (int m = r * Q; m < M && m < (r + 1) * Q; ++m) {
+                double s = sh[((m - r * Q) * WAVES + 0) * TILE + lane];
+                for (int w = 1; w < WAVES; ++w) s += sh[((m - r * Q) * WAVES + w) * TILE + lane];
+                part[((size_t)chunk * M + m) * n + i] = s;
+            }
         }
     }
 }
@@ -795,14 +803,17 @@ __device__ __forceinline__ void upwind_on_side(const FaceStencil<A>& s, const Fa
     }
 }
 
-// raw moments of the upwind interface distribution of the -x and -y faces
-// (interface values formed in double from the stored distribution).  The
-// velocity is the same in every lane: the upwind side is a scalar branch and
-// the stencil loads take scalar row offsets (as in k_flux_div).
+// raw moments of the upwind interface distribution of the -x and -y faces.
+// The interface values are formed in T from the stored distribution, with
+// the same arithmetic as k_flux_div's (so the equilibrium of a face is built
+// from the very values its flux transports); the moments are summed in
+// double.  The velocity is the same in every lane: the upwind side is a
+// scalar branch and the stencil loads take scalar row offsets.
 template <typename T>
 __global__ void __launch_bounds__(256) k_face_moments_partial(Geo g, Vel vel, const T* __restrict__ f,
                                                               double* __restrict__ part, int kch) {
-    __shared__ double sh[2 * NRAW * WAVES * TILE];
+    // the 22 sums leave through LDS in two rounds: 22.5 KB per block
+    __shared__ double sh[NRAW * WAVES * TILE];
     Chunk ch = chunk_of_xcd(g.nc, vel.nk, kch);
     const int wave = __builtin_amdgcn_readfirstlane(ch.wave);
     const int k0 = __builtin_amdgcn_readfirstlane(ch.k0), k1 = __builtin_amdgcn_readfirstlane(ch.k1);
@@ -816,24 +827,24 @@ __global__ void __launch_bounds__(256) k_face_moments_partial(Geo g, Vel vel, co
     if (ch.valid && !g.solid[ch.c]) {
         for (int d = 0; d < 2; ++d) {
             if (g.nb[(2 * d) * g.nc + ch.c] < 0) continue;   // not an interior face
-            FaceStencil<double> st;
-            face_stencil<T, double>(g, ch.c, d, st);
+            FaceStencil<T> st;
+            face_stencil<T>(g, ch.c, d, st);
             // the stencil values of the next velocity load while this one computes
             FaceVals<T> cur{}, nxt{};
             int k = k0 + wave;
-            if (k < k1) stencil_load<T, double>(st, RG, RH, (unsigned)(k - k0) * rowb, nxt);
+            if (k < k1) stencil_load<T>(st, RG, RH, (unsigned)(k - k0) * rowb, nxt);
             for (; k < k1; k += WAVES) {
                 cur = nxt;
-                if (k + WAVES < k1) stencil_load<T, double>(st, RG, RH, (unsigned)(k + WAVES - k0) * rowb, nxt);
+                if (k + WAVES < k1) stencil_load<T>(st, RG, RH, (unsigned)(k + WAVES - k0) * rowb, nxt);
                 const double u = vel.u[k], v = vel.v[k], w = vel.w[k];
                 const int side = upwind_side(d == 0 ? u : v);
-                double Gup, Hup, sG, sH;
-                upwind_on_side<T, double>(st, cur, side, Gup, Hup, sG, sH);
-                raw_accumulate(a + d * NRAW, w, u, v, Gup, Hup);
+                T Gup, Hup, sG, sH;
+                upwind_on_side<T>(st, cur, side, Gup, Hup, sG, sH);
+                raw_accumulate(a + d * NRAW, w, u, v, double(Gup), double(Hup));
             }
         }
     }
-    reduce_store<2 * NRAW>(a, sh, part, g.nc, ch.c, ch.valid, ch.chunk);
+    reduce_store<2 * NRAW, 2>(a, sh, part, g.nc, ch.c, ch.valid, ch.chunk);
 }
 
 // Reductions over all velocities inside one block: 64 lanes (consecutive
@@ -1039,6 +1050,8 @@ __global__ void __launch_bounds__(256) k_face_timeslope_partial(Geo g, Vel vel, 
     for (int m = 0; m < 8; ++m) a[m] = 0.0;
     if (ch.valid && !g.solid[ch.c]) {
         size_t stride = 2 * (size_t)g.nc;
+        // unrolled: a[4 d + m] in fixed registers (a runtime d indexed them)
+#pragma unroll
         for (int d = 0; d < 2; ++d) {
             const double* rec = fp + (size_t)d * g.nc + ch.c;
             if (rec[23 * stride] == 0.0) continue;
