@@ -300,18 +300,56 @@ __global__ void __launch_bounds__(256) k_moments_partial(Geo g, Vel vel, T* __re
                                                          double* __restrict__ part, int kch) {
     __shared__ double sh[NRAW * WAVES * TILE];
     Chunk ch = chunk_of(g.nc, vel.nk, kch);
+    const int wave = __builtin_amdgcn_readfirstlane(ch.wave);
+    const int k0 = __builtin_amdgcn_readfirstlane(ch.k0), k1 = __builtin_amdgcn_readfirstlane(ch.k1);
     double a[NRAW];
     for (int m = 0; m < NRAW; ++m) a[m] = 0.0;
     if (ch.valid) {
-        size_t nc = g.nc;
-        for (int k = ch.k0 + ch.wave; k < ch.k1; k += WAVES) {
-            size_t ig = (size_t)k * nc + ch.c, ih = (size_t)(vel.nk + k) * nc + ch.c;
-            T G = f[ig], H = f[ih];
+        const size_t nc = g.nc, ho = (size_t)vel.nk * nc;
+        // UM velocities per step: their loads are issued together (a wave
+        // reads 256 bytes per plane and velocity, so one at a time leaves
+        // the memory system idle); the sums keep the velocity order
+        constexpr int UM = 4;
+        int k = k0 + wave;
+        for (; k + WAVES * (UM - 1) < k1; k += WAVES * UM) {
+            T G[UM], H[UM];
+#pragma unroll
+            for (int u = 0; u < UM; ++u) {
+                const size_t ig = (size_t)(k + WAVES * u) * nc + ch.c;
+                G[u] = f[ig];
+                H[u] = f[ho + ig];
+            }
+            if (df) {
+                T dG[UM], dH[UM];
+#pragma unroll
+                for (int u = 0; u < UM; ++u) {
+                    const size_t ig = (size_t)(k + WAVES * u) * nc + ch.c;
+                    dG[u] = df[ig];
+                    dH[u] = df[ho + ig];
+                }
+#pragma unroll
+                for (int u = 0; u < UM; ++u) {
+                    const size_t ig = (size_t)(k + WAVES * u) * nc + ch.c;
+                    G[u] += dG[u];
+                    H[u] += dH[u];
+                    f[ig] = G[u];
+                    f[ho + ig] = H[u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UM; ++u) {
+                const int ku = k + WAVES * u;
+                raw_accumulate(a, vel.w[ku], vel.u[ku], vel.v[ku], double(G[u]), double(H[u]));
+            }
+        }
+        for (; k < k1; k += WAVES) {
+            const size_t ig = (size_t)k * nc + ch.c;
+            T G = f[ig], H = f[ho + ig];
             if (df) {
                 G += df[ig];
-                H += df[ih];
+                H += df[ho + ig];
                 f[ig] = G;
-                f[ih] = H;
+                f[ho + ig] = H;
             }
             raw_accumulate(a, vel.w[k], vel.u[k], vel.v[k], double(G), double(H));
         }
