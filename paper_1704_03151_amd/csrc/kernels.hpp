@@ -1286,6 +1286,9 @@ struct FaceConst {
     T a[3][4];   // left, right and time slopes, constant term folded
     T dH[3];
     T q[5];
+    T lam2;      // 2 lam
+    T q1dH[2];   // q1 dH of the left and right slopes
+    T q2dH2;     // q2 dH of the time slope
 };
 
 template <typename T>
@@ -1308,6 +1311,10 @@ __device__ __forceinline__ void face_const(const T* P, int K_int, FaceConst<T>& 
         F.dH[i] = a[3] * inv2l;
     }
     for (int m = 0; m < 5; ++m) F.q[m] = P[18 + m];
+    F.lam2 = T(2) * lam;
+    F.q1dH[0] = F.q[1] * F.dH[0];
+    F.q1dH[1] = F.q[1] * F.dH[1];
+    F.q2dH2 = F.q[2] * F.dH[2];
 }
 
 // UGKS time-averaged flux of G and H through an interior face for one
@@ -1359,29 +1366,36 @@ __device__ __forceinline__ double exp_tab(double x, const double* __restrict__ t
 
 // face_flux with the upwind side known for the whole wavefront (side 0 or
 // 1; a face with zero normal velocity carries no flux), the Maxwellian by
-// exp_tab
+// exp_tab.  The same terms as face_flux, grouped so that G and H share them:
+// with H0 = hK G0, Heq = hK G0 (1 + sk (2 lam c2 - 4) + 2 sk), and the H
+// slopes those of G plus dH,
+//   PG = un (q0 Geq + G0 (q1 un aG + q2 bG) + q3 Gup + q4 un sGup)
+//   PH = un (hK (q0 Heq/hK + G0 (q1 un aG + q2 bG + un q1 dH_s + q2 dH_t))
+//            + q3 Hup + q4 un sHup)
 template <typename T>
 __device__ __forceinline__ void face_flux_side(const FaceConst<T>& F, int side, T u, T v, T un, T Gup, T Hup,
                                                T sGup, T sHup, const double* __restrict__ etab, T& PG, T& PH) {
-    T cx = u - F.U, cy = v - F.V, c2 = cx * cx + cy * cy;
-    T G0 = F.pre * T(exp_tab(double(-F.lam * c2), etab));
-    T H0 = F.hK * G0;
-    T sk = F.shx * cx + F.shy * cy;
-    T Geq = G0 * (T(1) + sk * (T(2) * F.lam * c2 - T(4)));
-    T Heq = H0 * (T(1) + sk * (T(2) * F.lam * c2 - T(2)));
-    T q2 = u * u + v * v;
-    T aG, aH;
+    const T cx = u - F.U, cy = v - F.V, c2 = cx * cx + cy * cy;
+    const T G0 = F.pre * T(exp_tab(double(-F.lam * c2), etab));
+    const T sk = F.shx * cx + F.shy * cy;
+    const T eG = T(1) + sk * (F.lam2 * c2 - T(4));
+    const T Geq = G0 * eG, HeqK = G0 * (eG + (sk + sk));   // Heq / hK
+    const T q2 = u * u + v * v;
+    // (side is uniform: a scalar branch, and the slopes stay in registers)
+    T aG, qdH;
     if (side == 0) {
         aG = F.a[0][0] + F.a[0][1] * u + F.a[0][2] * v + F.a[0][3] * q2;
-        aH = aG + F.dH[0];
+        qdH = F.q1dH[0];
     } else {
         aG = F.a[1][0] + F.a[1][1] * u + F.a[1][2] * v + F.a[1][3] * q2;
-        aH = aG + F.dH[1];
+        qdH = F.q1dH[1];
     }
-    T bG = F.a[2][0] + F.a[2][1] * u + F.a[2][2] * v + F.a[2][3] * q2;
-    T bH = bG + F.dH[2];
-    PG = un * (F.q[0] * Geq + F.q[1] * un * aG * G0 + F.q[2] * bG * G0 + F.q[3] * Gup + F.q[4] * un * sGup);
-    PH = un * (F.q[0] * Heq + F.q[1] * un * aH * H0 + F.q[2] * bH * H0 + F.q[3] * Hup + F.q[4] * un * sHup);
+    const T bG = F.a[2][0] + F.a[2][1] * u + F.a[2][2] * v + F.a[2][3] * q2;
+    const T t1 = F.q[1] * un, t4 = F.q[4] * un;
+    const T inG = t1 * aG + F.q[2] * bG;
+    const T inH = inG + (un * qdH + F.q2dH2);
+    PG = un * (F.q[0] * Geq + G0 * inG + F.q[3] * Gup + t4 * sGup);
+    PH = un * (F.hK * (F.q[0] * HeqK + G0 * inH) + F.q[3] * Hup + t4 * sHup);
 }
 
 // Step 1: div_ik = (1/V_i) sum_faces S u_n ftilde (outward) for G and H, and
