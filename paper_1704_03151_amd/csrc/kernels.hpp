@@ -1419,8 +1419,10 @@ __device__ __forceinline__ void face_flux_side(const FaceConst<T>& F, int side, 
 //
 // MKF = 16 velocities per thread (two of the other kernels' MK): the 23-word
 // face records and the stencil set-up of each face are loaded once per 16
-// velocities, and the chunk partials of R halve; 219 (FP32) / 235 (FP64)
-// registers keep two wavefronts per SIMD (24 no longer unrolls).
+// velocities, and the chunk partials of R halve.  The velocity loops run as
+// two unrolled halves of 8 (a single loop of 16 is left rolled by the
+// compiler, which then indexes the running sums with indexed register
+// moves); 216 (FP32) / 228 (FP64) registers keep two wavefronts per SIMD.
 constexpr int MKF = 16;                // velocities per thread of the flux
 constexpr int KCHF = WAVES * MKF;      // velocities per flux chunk
 
@@ -1490,7 +1492,9 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
                 rw = A(rho_w[jw]);
             }
 #pragma unroll
-            for (int j = 0; j < MKF; ++j) {
+            for (int jh = 0; jh < MKF; jh += 8)
+#pragma unroll
+                for (int j = jh; j < jh + 8; ++j) {
                 if (j >= nmine) break;
                 const int k = k0 + wave + WAVES * j;
                 const unsigned so = so0 + j * sostep;
@@ -1558,7 +1562,9 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
                 FaceVals<T> cur{}, nxt{};
                 if (nmine > 0) stencil_load<T>(st, RG, RH, so0, nxt);
 #pragma unroll
-                for (int j = 0; j < MKF; ++j) {
+                for (int jh = 0; jh < MKF; jh += 8)
+#pragma unroll
+                    for (int j = jh; j < jh + 8; ++j) {
                     if (j >= nmine) break;
                     const int k = k0 + wave + WAVES * j;
                     const unsigned so = so0 + j * sostep;
@@ -1581,7 +1587,9 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
                 const A lam = A(1.0 / g.w_T[jw]), Uw = A(g.w_U[jw]), Vw = A(g.w_V[jw]);
                 const A rw = A(rho_w[jw]);
 #pragma unroll
-                for (int j = 0; j < MKF; ++j) {
+                for (int jh = 0; jh < MKF; jh += 8)
+#pragma unroll
+                    for (int j = jh; j < jh + 8; ++j) {
                     if (j >= nmine) break;
                     const int k = k0 + wave + WAVES * j;
                     const A u = vel.u[k], v = vel.v[k];
@@ -1602,7 +1610,9 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
             } else {
                 const bool far = code == NB_FARFIELD, sym = code == NB_SYMMETRY;
 #pragma unroll
-                for (int j = 0; j < MKF; ++j) {
+                for (int jh = 0; jh < MKF; jh += 8)
+#pragma unroll
+                    for (int j = jh; j < jh + 8; ++j) {
                     if (j >= nmine) break;
                     const int k = k0 + wave + WAVES * j;
                     const A un = sign * (d == 0 ? A(vel.u[k]) : A(vel.v[k]));
@@ -1627,7 +1637,9 @@ __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const
     }
     if (own) {
 #pragma unroll
-        for (int j = 0; j < MKF; ++j) {
+        for (int jh = 0; jh < MKF; jh += 8)
+#pragma unroll
+            for (int j = jh; j < jh + 8; ++j) {
             if (j >= nmine) break;
             const int k = k0 + wave + WAVES * j;
             div[(size_t)k * nc + c] = T(dG[j]);
