@@ -1417,22 +1417,28 @@ __device__ __forceinline__ void face_flux_side(const FaceConst<T>& F, int side, 
 // otherwise 63, and lane 63 forms only the -x face flux of the next tile's
 // first cell, for lane 62.
 //
-// MKF = 16 velocities per thread (two of the other kernels' MK): the 23-word
-// face records and the stencil set-up of each face are loaded once per 16
-// velocities, and the chunk partials of R halve.  The velocity loops run as
-// two unrolled halves of 8 (a single loop of 16 is left rolled by the
-// compiler, which then indexes the running sums with indexed register
-// moves); 216 (FP32) / 228 (FP64) registers keep two wavefronts per SIMD.
-constexpr int MKF = 16;                // velocities per thread of the flux
-constexpr int KCHF = WAVES * MKF;      // velocities per flux chunk
+// MKF velocities per thread (16 or 24, against the other kernels' 8): the
+// 23-word face records and the stencil set-up of each face are loaded once
+// per MKF velocities, and the chunk partials of R shrink.  The velocity loops
+// run as unrolled groups of 8 (a single loop of 16 is left rolled by the
+// compiler, which then reaches the running sums by indexed register moves).
+// Registers: 216 (float, 16), 250 (float, 24), 228 (double, 16): two
+// wavefronts per SIMD; double with 24 would not fit.  flux_mk picks 24 for
+// float where the launch keeps 4096 blocks with it; force (16, or 24 for
+// float; MIUGKS_FLUX_MK) overrides the choice.
+inline int flux_mk(bool is_float, int ntiles, int nk, int force = 0) {
+    if (force == 16 || (force == 24 && is_float)) return force;
+    return is_float && (long)ntiles * ((nk + WAVES * 24 - 1) / (WAVES * 24)) >= 4096 ? 24 : 16;
+}
 
-template <typename T>
+template <typename T, int MKF>
 __global__ void __launch_bounds__(256) k_flux_div(Geo g, Vel vel, Gas gas, const T* __restrict__ f,
                                                   const double* __restrict__ fp,
                                                   const double* __restrict__ rho_w,
                                                   const T* __restrict__ finf, T* __restrict__ div,
                                                   double* __restrict__ part, int tstride) {
     typedef double A;
+    constexpr int KCHF = WAVES * MKF;   // velocities per chunk
     __shared__ double sh[4 * WAVES * TILE];
     __shared__ double etab[EXP_TAB];
     exp_tab_fill(etab);

@@ -110,6 +110,7 @@ struct miugks_ctx {
     // whose stages treat a coarse level as the finest (f then holds that level)
     int top = 0;
     int kch_force = 0;   // > 0: velocities per block of the chunked reductions (chunk_len)
+    int flux_mk_force = 0;   // 16 or 24: velocities per thread of the flux (flux_mk)
     // set around a correction whose result is applied at once (Step 6): the
     // finest level's last sweep, if in bands, adds df to f itself (fused)
     void* fuse_f = nullptr;
@@ -511,11 +512,22 @@ struct Path {
         LAUNCH(c, "timeslope_records", (8.0 + 2 * 8) * nc8, k_face_timeslope_records, dim3(nblk(2 * g.nc)),
                dim3(256), g, c->gas, (const double*)c->msum, c->fp);
         wall_sums(c, top, F(c), c->rho_w);
-        // the flux keeps chunks of KCH velocities: a block holds a thread's MK
-        // velocities of div in registers, and its partial sums are 4 per cell
-        const int nkf = nchunks(c->nk, KCHF);
-        LAUNCH(c, "flux_div", 2 * arr(c, top) + (2.0 * NFP + 4.0 * nkf) * nc8, k_flux_div<T>, dim3(flux_tiles(g), nkf),
-               dim3(256), g, c->vel, c->gas, F(c), c->fp, c->rho_w, (const T*)c->finf, (T*)c->div, c->part, flux_stride(g));
+        // the flux takes chunks of WAVES * mk velocities: a thread holds its mk
+        // velocities of div in registers, and the partial sums are 4 per cell
+        const int mk = flux_mk(sizeof(T) == 4, flux_tiles(g), c->nk, c->flux_mk_force);
+        const int nkf = nchunks(c->nk, WAVES * mk);
+        const double fbytes = 2 * arr(c, top) + (2.0 * NFP + 4.0 * nkf) * nc8;
+        bool launched = false;
+        if constexpr (sizeof(T) == 4) {
+            if (mk == 24) {
+                LAUNCH(c, "flux_div", fbytes, (k_flux_div<T, 24>), dim3(flux_tiles(g), nkf), dim3(256), g, c->vel,
+                       c->gas, F(c), c->fp, c->rho_w, (const T*)c->finf, (T*)c->div, c->part, flux_stride(g));
+                launched = true;
+            }
+        }
+        if (!launched)
+            LAUNCH(c, "flux_div", fbytes, (k_flux_div<T, 16>), dim3(flux_tiles(g), nkf), dim3(256), g, c->vel, c->gas,
+                   F(c), c->fp, c->rho_w, (const T*)c->finf, (T*)c->div, c->part, flux_stride(g));
         LAUNCH(c, "chunk_sum", 4.0 * (nkf + 1) * nc8, k_chunk_sum, dim3(nblk(4 * g.nc)), dim3(256),
                (const double*)c->part, nkf, 4, g.nc, -1.0, g.solid, c->R);
         LAUNCH(c, "residual_norm", 4 * nc8, k_residual_norm, dim3(1), dim3(256), g, c->hl[top].n_fluid, c->R,
@@ -1561,6 +1573,7 @@ int build_device(miugks_ctx* ctx) {
     }
     if (const char* e = getenv("MIUGKS_CHUNK_LEN")) ctx->kch_force = std::max(KCH, atoi(e));
     ctx->no_fuse = getenv("MIUGKS_NO_FUSED_UPDATE") != nullptr;
+    if (const char* e = getenv("MIUGKS_FLUX_MK")) ctx->flux_mk_force = atoi(e);
     // partial sums: the largest is 2 * NRAW per cell per chunk of KCH (the shortest)
     size_t maxw = 1;
     for (auto& h : ctx->hl) maxw = std::max(maxw, h.w_cell.size());

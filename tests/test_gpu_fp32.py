@@ -57,6 +57,41 @@ def test_fp32_steps(name):
     gpu.close()
 
 
+@pytest.mark.parametrize("name", ["plate32x24", "square20x20", "box8_vel65"])
+def test_fp32_flux_with_24_velocities_per_thread(name, monkeypatch):
+    """The FP32-f flux with 24 velocities per thread (the square's choice;
+    forced here): Step 1 against the oracle at 2e-5, and div bit for bit
+    equal to the 16-velocity form (each velocity's sum over its faces is the
+    same arithmetic), R to 1e-12 (only the grouping of its velocity sums
+    differs)."""
+    from paper_1704_03151_amd import Solver
+    case = small_cases()[name]
+    print(f"[fp32] case {name}: flux with 24 velocities per thread", flush=True)
+    prim, pert = perturbed_state(case, 5)
+    out = {}
+    for mk in ("24", "16"):
+        monkeypatch.setenv("MIUGKS_FLUX_MK", mk)
+        gpu = Solver(case, precision="fp32f")
+        gpu.init_macro(prim)
+        gpu.set_f((gpu.get_f(np.float64) * pert).astype(np.float32))
+        R, norms = gpu.residual()
+        out[mk] = (gpu.get_f(np.float64), gpu.div(np.float32), R)
+        gpu.close()
+    assert np.array_equal(out["24"][0], out["16"][0])
+    assert np.array_equal(out["24"][1], out["16"][1])
+    for m in range(4):
+        assert rel_max(out["24"][2][m], out["16"][2][m]) < 1e-12, m
+    orc = Oracle(case)
+    orc.init_macro(prim)
+    orc.set_f(*to_oracle(out["24"][0]))
+    orc.step1()
+    dG, dH = to_oracle(out["24"][1].astype(np.float64))
+    assert rel_max(dG, orc.divG) < 2e-5 and rel_max(dH, orc.divH) < 2e-5
+    Rref = orc.R.reshape(4, case.ny, case.nx)
+    for m in range(4):
+        assert rel_max(out["24"][2][m], Rref[m]) < 2e-5, m
+
+
 def test_fp32_bench_case_three_cycles():
     """The bench workload at full size (64x64 x 784, 4 levels): three outer
     cycles of the FP32-f form against three FP64 oracle cycles."""
