@@ -181,6 +181,15 @@ def adjoint_bench(args, case, solver):
     sec = (time.perf_counter() - t0) / args.steps
     print(f"[bench] {args.steps} adjoint solves: {sec:.3f} s each, {iters} corrections, residual {rel:.2e}",
           file=sys.stderr, flush=True)
+    # the same solve with the Krylov basis in FP32 (miugks_adjoint_ex)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st32, g32, iters32, rel32 = solver.adjoint(1, lid, faces, tol=tol, max_iter=5000, krylov_precision="fp32")
+    torch.cuda.synchronize()
+    sec32 = (time.perf_counter() - t0) / args.steps
+    dev32 = float(np.max(np.abs(g32 - g)) / np.max(np.abs(g)))
+    print(f"[bench] with an FP32 Krylov basis: {sec32:.3f} s each, {iters32} corrections, residual {rel32:.2e}, "
+          f"gradient within {dev32:.1e} of the FP64 one", file=sys.stderr, flush=True)
     solver.set_timing(True)
     solver.adjoint(1, lid, faces, tol=tol, max_iter=5000)
     stats = solver.timing()
@@ -206,6 +215,8 @@ def adjoint_bench(args, case, solver):
                      "mean_launch_ms": ms / n_l},
         "kernel_ms_per_solve": {k: v[1] for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])[:12]},
         "gradient_max": float(np.max(np.abs(g))),
+        "fp32_krylov": {"ms_per_step": sec32 * 1e3, "corrections": iters32, "relative_residual": rel32,
+                        "gradient_deviation": dev32},
     }
     print(json.dumps(line), flush=True)
 
