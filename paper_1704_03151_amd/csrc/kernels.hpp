@@ -9,10 +9,10 @@
 //
 // Most per-(cell, velocity) kernels use one launch shape: a block of 256
 // threads = 64 lanes (consecutive cells) x 4 waves, the waves taking
-// interleaved velocities of a chunk of KCH = 4 * MK velocities; each thread
-// keeps MK velocities in registers, and reductions over the velocities are
-// written as per-chunk partial sums that a finalize kernel adds in a fixed
-// order (deterministic, no floating-point atomics).
+// interleaved velocities of a chunk (KCH = 4 * MK velocities, or a multiple
+// of it for the reductions, or 4 * MKF for the flux); reductions over the
+// velocities are written as per-chunk partial sums that a finalize kernel
+// adds in a fixed order (deterministic, no floating-point atomics).
 #pragma once
 
 #include <hip/hip_runtime.h>
