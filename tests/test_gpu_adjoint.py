@@ -196,6 +196,15 @@ def test_fp32_krylov_adjoint_against_oracle():
         assert st == 0 and err < 1e-7, (kind, rel, g, ref)
     with pytest.raises(ValueError):
         gpu.adjoint(ad.LOAD_SHEAR, walls, [face], krylov_precision="fp16")
+    # the C entry point itself refuses another storage type, before any work
+    import ctypes
+    from paper_1704_03151_amd import _C
+    ids = np.ascontiguousarray(walls, np.int32)
+    fc = np.ascontiguousarray([face], np.int32)
+    g = np.zeros(1)
+    rc = _C.lib.miugks_adjoint_ex(gpu.h, ad.LOAD_SHEAR, _C.iptr(ids), len(ids), _C.iptr(fc), 1, 1e-9, 10, 7,
+                                  _C.dptr(g), None, None)
+    assert rc == _C.EINVAL and b"krylov_dtype" in _C.lib.miugks_last_error(gpu.h)
     gpu.close()
 
 
