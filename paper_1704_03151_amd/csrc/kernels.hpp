@@ -84,6 +84,32 @@ __host__ __device__ inline double shakhov_prefactor(const Gas& gas) {
 __device__ __forceinline__ double dexp(double x) { return exp(x); }
 __device__ __forceinline__ float dexp(float x) { return expf(x); }
 
+// Table of 2^(j/64), j < 64, for exp_tab (filled by the block that uses it)
+constexpr int EXP_TAB = 64;
+__device__ __forceinline__ void exp_tab_fill(double* tab) {
+    if (threadIdx.x < EXP_TAB) tab[threadIdx.x] = exp2(double(threadIdx.x) / EXP_TAB);
+}
+
+// exp(x) by Tang's table-driven method (ACM TOMS 15(2), 1989): x = (64 m +
+// j) ln2/64 + r with |r| <= ln2/128, exp(x) = 2^m 2^(j/64) e^r, e^r - 1 from
+// its degree-5 Taylor polynomial (truncation below 4e-17 relative).  The
+// reduction subtracts n ln2/64 in two fused steps (ln2/64 split into its
+// nearest double and the remainder).  Underflows to zero below about -745;
+// a NaN argument gives NaN.
+__device__ __forceinline__ double exp_tab(double x, const double* __restrict__ tab) {
+    const double n = __builtin_rint(x * 92.33248261689366);   // 64 / ln2
+    double r = fma(-n, 0.010830424696249145, x);
+    r = fma(-n, 3.623510646634843e-19, r);
+    const int ni = int(n);
+    double p = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+    p = fma(r, p, 1.0 / 6.0);
+    p = fma(r, p, 0.5);
+    p = fma(r, p, 1.0);
+    p *= r;
+    const double t = tab[ni & (EXP_TAB - 1)];
+    return __builtin_amdgcn_ldexp(fma(t, p, t), ni >> 6);
+}
+
 // van Leer limiter: harmonic mean of one-sided slopes of equal sign, else 0
 template <typename T> __device__ __forceinline__ T van_leer(T a, T b) {
     T s = a * b;
@@ -1080,6 +1106,11 @@ __global__ void __launch_bounds__(256) k_face_timeslope_partial(Geo g, Vel vel, 
                                                                 const double* __restrict__ fp,
                                                                 double* __restrict__ part, int kch) {
     __shared__ double sh[8 * WAVES * TILE];
+    __shared__ double etab[EXP_TAB];   // double: the Maxwellian by Tang's exp (as the flux)
+    if constexpr (sizeof(T) == 8) {
+        exp_tab_fill(etab);
+        __syncthreads();
+    }
     Chunk ch = chunk_of(g.nc, vel.nk, kch);
     // the velocity is the same in every lane: the upwind side is a scalar branch
     const int wave = __builtin_amdgcn_readfirstlane(ch.wave);
@@ -1104,7 +1135,11 @@ __global__ void __launch_bounds__(256) k_face_timeslope_partial(Geo g, Vel vel, 
                 T u = vel_u<T>(vel, k), v = vel_v<T>(vel, k);
                 T un = d == 0 ? u : v;
                 T du = u - U, dv = v - V;
-                T G0 = pref * dexp(-lam * (du * du + dv * dv));
+                T G0;
+                if constexpr (sizeof(T) == 8)
+                    G0 = pref * exp_tab(-lam * (du * du + dv * dv), etab);
+                else
+                    G0 = pref * dexp(-lam * (du * du + dv * dv));
                 T H0 = T(gas.K_int) / (T(2) * lam) * G0;
                 T pG, pH, qG, qH;
                 const int side = upwind_side(double(un));
@@ -1336,32 +1371,6 @@ __device__ __forceinline__ void face_flux(const FaceConst<T>& F, T u, T v, T un,
     T bH = bG + F.dH[2];
     PG = un * (F.q[0] * Geq + F.q[1] * un * aG * G0 + F.q[2] * bG * G0 + F.q[3] * Gup + F.q[4] * un * sGup);
     PH = un * (F.q[0] * Heq + F.q[1] * un * aH * H0 + F.q[2] * bH * H0 + F.q[3] * Hup + F.q[4] * un * sHup);
-}
-
-// Table of 2^(j/64), j < 64, for exp_tab (filled by the block that uses it)
-constexpr int EXP_TAB = 64;
-__device__ __forceinline__ void exp_tab_fill(double* tab) {
-    if (threadIdx.x < EXP_TAB) tab[threadIdx.x] = exp2(double(threadIdx.x) / EXP_TAB);
-}
-
-// exp(x) by Tang's table-driven method (ACM TOMS 15(2), 1989): x = (64 m +
-// j) ln2/64 + r with |r| <= ln2/128, exp(x) = 2^m 2^(j/64) e^r, e^r - 1 from
-// its degree-5 Taylor polynomial (truncation below 4e-17 relative).  The
-// reduction subtracts n ln2/64 in two fused steps (ln2/64 split into its
-// nearest double and the remainder).  Underflows to zero below about -745;
-// a NaN argument gives NaN.
-__device__ __forceinline__ double exp_tab(double x, const double* __restrict__ tab) {
-    const double n = __builtin_rint(x * 92.33248261689366);   // 64 / ln2
-    double r = fma(-n, 0.010830424696249145, x);
-    r = fma(-n, 3.623510646634843e-19, r);
-    const int ni = int(n);
-    double p = fma(r, 1.0 / 120.0, 1.0 / 24.0);
-    p = fma(r, p, 1.0 / 6.0);
-    p = fma(r, p, 0.5);
-    p = fma(r, p, 1.0);
-    p *= r;
-    const double t = tab[ni & (EXP_TAB - 1)];
-    return __builtin_amdgcn_ldexp(fma(t, p, t), ni >> 6);
 }
 
 // face_flux with the upwind side known for the whole wavefront (side 0 or
