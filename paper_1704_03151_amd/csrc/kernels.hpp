@@ -491,6 +491,9 @@ __global__ void k_wall_loads(Geo g, Vel vel, int K_int, const T* __restrict__ f,
 // slice's sum; k_wall_density_fin adds the slices in order.
 constexpr int WD_K = 32;
 inline int wall_density_slices(int nk) { return (nk + WD_K - 1) / WD_K; }
+// velocity sets up to this size take k_wall_density_wave (one launch) instead
+constexpr int WD_WAVE_MAX_NK = 2048;
+
 
 template <typename T, bool PRO>
 __global__ void __launch_bounds__(64) k_wall_density_part(Geo g, Vel vel, const T* __restrict__ Gf, int ncc,
@@ -523,6 +526,42 @@ __global__ void __launch_bounds__(64) k_wall_density_part(Geo g, Vel vel, const 
         }
         part[(size_t)blockIdx.y * g.n_wall + j] = s;
     }
+}
+
+// The same density in one launch for small velocity sets: one wavefront per
+// wall side, lane l taking the velocities l, l + 64, ..., then the lanes in a
+// fixed tree; out[j] = rho_w
+template <typename T, bool PRO>
+__global__ void __launch_bounds__(256) k_wall_density_wave(Geo g, Vel vel, const T* __restrict__ Gf, int ncc,
+                                                           const T* __restrict__ Gc, double* __restrict__ out) {
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    double s = 0.0;
+    if (j < g.n_wall) {
+        const int c = g.w_cell[j], sd = g.w_side[j];
+        const double sign = (sd & 1) ? 1.0 : -1.0;
+        int id[4] = {0, 0, 0, 0};
+        T pw[4] = {T(0), T(0), T(0), T(0)};
+        if constexpr (PRO)
+            for (int a = 0; a < 4; ++a) {
+                id[a] = g.p_idx[a * g.nc + c];
+                pw[a] = T(g.p_w[a * g.nc + c]);
+            }
+        for (int k = lane; k < vel.nk; k += 64) {
+            const double un = sign * (sd < 2 ? vel.u[k] : vel.v[k]);
+            if (un > 0) {
+                T G = Gf[(size_t)k * g.nc + c];
+                if constexpr (PRO) {
+                    const size_t kc = (size_t)k * ncc;
+                    const T add = pw[0] * Gc[kc + id[0]] + pw[1] * Gc[kc + id[1]] + pw[2] * Gc[kc + id[2]] +
+                                  pw[3] * Gc[kc + id[3]];
+                    G = G + add;
+                }
+                s += vel.w[k] * un * double(G);
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0 && j < g.n_wall) out[j] = -s / g.w_den[j];
 }
 
 // rho_w = -(sum of the slices) / w_den, one wavefront per wall side: lane l

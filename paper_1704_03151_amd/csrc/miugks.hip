@@ -483,6 +483,11 @@ struct Path {
     static void wall_sums(miugks_ctx* c, int l, const T* G, double* out) {
         const Geo& g = c->geo[l];
         if (g.n_wall == 0) return;
+        if (c->nk <= WD_WAVE_MAX_NK) {
+            LAUNCH(c, "wall_density", (double)g.n_wall * c->nk * sizeof(T), (k_wall_density_wave<T, false>),
+                   dim3((g.n_wall + 3) / 4), dim3(256), g, c->vel, G, g.nc, (const T*)nullptr, out);
+            return;
+        }
         const int ns = wall_density_slices(c->nk);
         LAUNCH(c, "wall_density", (double)g.n_wall * c->nk * sizeof(T), (k_wall_density_part<T, false>),
                dim3((g.n_wall + 63) / 64, ns), dim3(64), g, c->vel, G, g.nc, (const T*)nullptr, c->wdpart[l]);
@@ -768,7 +773,11 @@ struct Path {
                    (T*)c->r[l + 1], n);
         }
         cs_reduced(c, l + 1);
-        if (g.n_wall) {
+        if (g.n_wall && c->nk <= WD_WAVE_MAX_NK) {
+            LAUNCH(c, "wall_density", (double)g.n_wall * c->nk * 5 * sizeof(T), (k_wall_density_wave<T, true>),
+                   dim3((g.n_wall + 3) / 4), dim3(256), g, c->vel, (const T*)c->df[l], gc.nc,
+                   (const T*)c->df[l + 1], c->drho[l]);
+        } else if (g.n_wall) {
             const int ns = wall_density_slices(c->nk);
             LAUNCH(c, "wall_density", (double)g.n_wall * c->nk * 5 * sizeof(T), (k_wall_density_part<T, true>),
                    dim3((g.n_wall + 63) / 64, ns), dim3(64), g, c->vel, (const T*)c->df[l], gc.nc,
