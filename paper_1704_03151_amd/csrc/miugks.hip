@@ -116,6 +116,7 @@ struct miugks_ctx {
     void* fuse_f = nullptr;
     bool fused = false;
     bool no_fuse = false;   // MIUGKS_NO_FUSED_UPDATE: keep Step 6 in the moments kernel
+    bool wall_sliced = false;   // MIUGKS_WALL_SLICED: wall densities by slices for any velocity count
     double dtn_growth = 0.0;
     double dtn_max = 0.0;   // cap of a^n (0: none)
     double cfl = 0.5;
@@ -483,7 +484,7 @@ struct Path {
     static void wall_sums(miugks_ctx* c, int l, const T* G, double* out) {
         const Geo& g = c->geo[l];
         if (g.n_wall == 0) return;
-        if (c->nk <= WD_WAVE_MAX_NK) {
+        if (c->nk <= WD_WAVE_MAX_NK && !c->wall_sliced) {
             LAUNCH(c, "wall_density", (double)g.n_wall * c->nk * sizeof(T), (k_wall_density_wave<T, false>),
                    dim3((g.n_wall + 3) / 4), dim3(256), g, c->vel, G, g.nc, (const T*)nullptr, out);
             return;
@@ -773,7 +774,7 @@ struct Path {
                    (T*)c->r[l + 1], n);
         }
         cs_reduced(c, l + 1);
-        if (g.n_wall && c->nk <= WD_WAVE_MAX_NK) {
+        if (g.n_wall && c->nk <= WD_WAVE_MAX_NK && !c->wall_sliced) {
             LAUNCH(c, "wall_density", (double)g.n_wall * c->nk * 5 * sizeof(T), (k_wall_density_wave<T, true>),
                    dim3((g.n_wall + 3) / 4), dim3(256), g, c->vel, (const T*)c->df[l], gc.nc,
                    (const T*)c->df[l + 1], c->drho[l]);
@@ -1582,6 +1583,7 @@ int build_device(miugks_ctx* ctx) {
     }
     if (const char* e = getenv("MIUGKS_CHUNK_LEN")) ctx->kch_force = std::max(KCH, atoi(e));
     ctx->no_fuse = getenv("MIUGKS_NO_FUSED_UPDATE") != nullptr;
+    ctx->wall_sliced = getenv("MIUGKS_WALL_SLICED") != nullptr;
     if (const char* e = getenv("MIUGKS_FLUX_MK")) ctx->flux_mk_force = atoi(e);
     // partial sums: the largest is 2 * NRAW per cell per chunk of KCH (the shortest)
     size_t maxw = 1;
