@@ -3028,57 +3028,79 @@ __global__ void __launch_bounds__(256) k_sweep_band(Geo g, Vel vel, int K_int, c
     const unsigned char* srow = stype + (size_t)iy * nx;
     const T* crow = coef_g + (size_t)iy * nx;
     T cG = T(0);
-    struct Ahead {
-        T cf, idx, rG, ey;
-        unsigned sc;
+    // The per-cell data of a step depend only on its column, so they are
+    // fetched a batch of SB steps ahead, into two alternating register
+    // batches: a batch's loads are in flight while the batch before is swept
+    // (fetching each step's data a few steps ahead left the compiler free to
+    // hoist the independent part of later steps above the wait, so the wait
+    // came about one step after the load).
+    constexpr int SB = 8;
+    struct Batch {
+        T cf[SB], idx[SB], rG[SB], ey[SB];
+        unsigned sc[SB];
+        int so[SB];   // where the step's value goes: its tile cell, or the lane's dump word
     };
-    // a lane outside the current diagonal fetches the dummy column t0 mod nx
+    // A step's index work is done at fetch time, without lane masks combined
+    // in scalar registers: the column jx = s - t0 of a lane off the grid
+    // becomes the dummy column t0 mod nx (one unsigned compare), so every
+    // read stays inside the lane's row; the cell of the row is (jc ^ xm) + xa
+    // (jc upwind in x, nx - 1 - jc downwind); the store goes to the tile only
+    // where jx < lim (nx on a row of the band, 0 elsewhere).
     const int dcol = t0 % nx;
-    auto fetch = [&](Ahead& n, int jx) {
-        const int jc = (jx < 0 || jx >= nx) ? dcol : jx;
-        const int ix = px ? jc : nx - 1 - jc;
-        n.cf = crow[ix];
-        n.sc = srow[ix];
-        n.idx = invdx[ix];
-        n.rG = tG[ix];
-        n.ey = eG[ix];
+    const int xm = px ? 0 : -1, xa = px ? 0 : nx;
+    const unsigned lim = rowok ? (unsigned)nx : 0u;
+    T* const sbase = (T*)dsum;
+    const int tgo = (int)(tG - sbase), dumpo = 64 * w + lane;   // dump words: [64 W] at the start of dsum
+    auto fetch = [&](Batch& n, int s0) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const int jx = s0 + u - t0;
+            const int jc = (unsigned)jx < (unsigned)nx ? jx : dcol;
+            const int ix = (jc ^ xm) + xa;   // in [0, nx)
+            n.cf[u] = crow[(unsigned)ix];
+            n.sc[u] = srow[(unsigned)ix];
+            n.idx[u] = invdx[ix];
+            n.rG[u] = tG[ix];
+            n.ey[u] = eG[ix];
+            n.so[u] = (unsigned)jx < lim ? tgo + ix : dumpo;
+        }
     };
-    T* dump = (T*)dsum + 64 * w + lane;
-    Ahead nA, nB, nC, nD;
-    fetch(nA, -t0);
-    fetch(nB, 1 - t0);
-    fetch(nC, 2 - t0);
-    // step s with the data in d; fill receives those of step s + 3
-    auto step = [&](int s, const Ahead& d, Ahead& fill) {
-        const T rot = lane_rotate1(cG);
-        const int jx = s - t0;
-        const bool valid = rowok && (unsigned)jx < (unsigned)nx;
-        const int ix = px ? jx : nx - 1 - jx;
-        fetch(fill, jx + 3);
-        const T nbG = first ? d.ey : rot;
-        const unsigned tpx = (d.sc >> shx) & 3u, tpy = (d.sc >> shy) & 3u;
-        const T bx = au * d.idx;
-        // transport diagonal: every downwind side, and an upwind side only if
-        // it is an outflow (where the two cancel)
-        const T D = d.cf + (tpx == 3u ? T(0) : bx) + (tpy == 3u ? T(0) : by);
-        const T inv = sweep_rcp(D);
-        const T exG = tpx == 0u ? cG : T(0), eyG = tpy == 0u ? nbG : T(0);
-        T vG = (d.rG + bx * exG + by * eyG) * inv;
-        vG = d.cf < T(0) ? T(0) : vG;
-        *(valid ? tG + ix : dump) = vG;
-        cG = vG;
+    // SB steps with the data in d
+    auto sweep = [&](const Batch& d) {
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const T rot = lane_rotate1(cG);
+            const T nbG = first ? d.ey[u] : rot;
+            const unsigned tpx = (d.sc[u] >> shx) & 3u, tpy = (d.sc[u] >> shy) & 3u;
+            const T bx = au * d.idx[u];
+            // transport diagonal: every downwind side, and an upwind side only
+            // if it is an outflow (where the two cancel)
+            const T D = d.cf[u] + (tpx == 3u ? T(0) : bx) + (tpy == 3u ? T(0) : by);
+            const T inv = sweep_rcp(D);
+            const T exG = tpx == 0u ? cG : T(0), eyG = tpy == 0u ? nbG : T(0);
+            T vG = (d.rG[u] + bx * exG + by * eyG) * inv;
+            vG = d.cf[u] < T(0) ? T(0) : vG;
+            sbase[d.so[u]] = vG;
+            cG = vG;
+        }
     };
+    // whole pairs of batches: the steps past the last one find every lane
+    // off the grid (their stores go to the dump words).  The loads of a batch
+    // are kept above the steps of the batch before by a scheduling barrier
+    // (the scheduler otherwise moves them down to shorten live ranges), and
+    // there is no exit between the two batches of a pair (with one, the loads
+    // of the second batch were sunk to the block that uses them).
     const int nsteps = nx + hb - 1;
-    int s = 0;
-    for (; s + 3 < nsteps; s += 4) {
-        step(s, nA, nD);
-        step(s + 1, nB, nA);
-        step(s + 2, nC, nB);
-        step(s + 3, nD, nC);
+    Batch bA, bB;
+    fetch(bA, 0);
+    for (int s0 = 0; s0 < nsteps; s0 += 2 * SB) {
+        fetch(bB, s0 + SB);
+        __builtin_amdgcn_sched_barrier(0);
+        sweep(bA);
+        fetch(bA, s0 + 2 * SB);
+        __builtin_amdgcn_sched_barrier(0);
+        sweep(bB);
     }
-    if (s < nsteps) step(s, nA, nD);
-    if (s + 1 < nsteps) step(s + 1, nB, nA);
-    if (s + 2 < nsteps) step(s + 2, nC, nB);
     __syncthreads();
     if (!fout) {
         for (int qv = 0; qv < nq; ++qv) {
