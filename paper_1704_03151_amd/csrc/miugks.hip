@@ -379,6 +379,27 @@ void timing_harvest(miugks_ctx* c) {
 #define LAUNCH(c, name, bytes, kernel, grid, block, ...) \
     LAUNCH_SH(c, name, bytes, 0, kernel, grid, block, __VA_ARGS__)
 
+// A kernel's limit on dynamic LDS (hipFuncAttributeMaxDynamicSharedMemorySize)
+// belongs to the kernel, not to a context: contexts only ever raise it, so a
+// context created later with smaller tiles never sets it below the size an
+// earlier context launches with.
+hipError_t raise_lds_limit(const void* f, int bytes) {
+    static std::mutex m;
+    static std::vector<std::pair<const void*, int>> limits;
+    std::lock_guard<std::mutex> lock(m);
+    int* cur = nullptr;
+    for (auto& p : limits)
+        if (p.first == f) cur = &p.second;
+    if (cur && *cur >= bytes) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    if (cur)
+        *cur = bytes;
+    else
+        limits.emplace_back(f, bytes);
+    return hipSuccess;
+}
+
 // LDS bytes of the staged sweep on a level: r/df tile (G, H), 1/tau + 1/dt_n,
 // 1/dx, side flags
 template <typename T>
@@ -390,7 +411,7 @@ size_t sweep_lds_bytes(const Geo& g, int P) {
 template <typename T, int NP, bool GC>
 hipError_t set_wave_lds_t(int R, int bytes) {
     auto set = [bytes](const void* f) {
-        return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        return raise_lds_limit(f, bytes);
     };
     switch (R) {
         case 1: return set((const void*)k_sweep_wave<T, 1, NP, GC>);
@@ -403,7 +424,7 @@ hipError_t set_wave_lds_t(int R, int bytes) {
 template <typename T, int NP>
 hipError_t set_stream_lds_t(int R, int bytes) {
     auto set = [bytes](const void* f) {
-        return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        return raise_lds_limit(f, bytes);
     };
     switch (R) {
         case 1: return set((const void*)k_sweep_stream<T, 1, NP>);
@@ -422,7 +443,7 @@ hipError_t set_stream_lds(int prec, int R, int np, int bytes) {
 template <typename T>
 hipError_t set_strips_lds_t(int R, int bytes) {
     auto set = [bytes](const void* f) {
-        return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        return raise_lds_limit(f, bytes);
     };
     switch (R) {
         case 1: return set((const void*)k_sweep_strips<T, 1>);
@@ -437,8 +458,8 @@ hipError_t set_strips_lds(int prec, int R, int bytes) {
 }
 
 hipError_t set_band_lds(int prec, int bytes) {
-    return hipFuncSetAttribute(prec == MIUGKS_FP64 ? (const void*)k_sweep_band<double> : (const void*)k_sweep_band<float>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return raise_lds_limit(prec == MIUGKS_FP64 ? (const void*)k_sweep_band<double> : (const void*)k_sweep_band<float>,
+                           bytes);
 }
 
 hipError_t set_wave_lds(int prec, int R, int np, int bytes) {
@@ -1481,11 +1502,8 @@ int build_device(miugks_ctx* ctx) {
                     ctx->wave[l].W = ctx->wave1[l].W = 0;
     }
     if (need_max > 65536) {
-        hipError_t e = ctx->prec == MIUGKS_FP64
-                           ? hipFuncSetAttribute((const void*)k_sweep_lds<double>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)need_max)
-                           : hipFuncSetAttribute((const void*)k_sweep_lds<float>,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)need_max);
+        hipError_t e = ctx->prec == MIUGKS_FP64 ? raise_lds_limit((const void*)k_sweep_lds<double>, (int)need_max)
+                                                : raise_lds_limit((const void*)k_sweep_lds<float>, (int)need_max);
         if (e != hipSuccess)
             for (int l = 0; l < ctx->L; ++l)
                 if (ctx->sweep_lds[l] &&
@@ -1677,9 +1695,7 @@ int build_device(miugks_ctx* ctx) {
                 ctx->fas_block_lds[l] = acc;
                 ctx->fas_block_l0 = l;
             }
-        if (acc > 65536 &&
-            hipFuncSetAttribute((const void*)k_fas_cycle_block, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)acc) != hipSuccess)
+        if (acc > 65536 && raise_lds_limit((const void*)k_fas_cycle_block, (int)acc) != hipSuccess)
             for (int l = 0; l < ctx->L; ++l)
                 if (ctx->fas_block_lds[l] > 65536) ctx->fas_block_l0 = std::max(ctx->fas_block_l0, l + 1);
         FasSet& F = ctx->fasset;
