@@ -2230,6 +2230,17 @@ __device__ __forceinline__ double lane_rotate1(double x) {
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
+// x where the mask m is all ones, +0 where it is zero (m = 0 or -1)
+__device__ __forceinline__ float mask_keep(float x, int m) {
+    return __builtin_bit_cast(float, __builtin_bit_cast(int, x) & m);
+}
+__device__ __forceinline__ double mask_keep(double x, int m) {
+    return __builtin_bit_cast(double, __builtin_bit_cast(long long, x) & (long long)m);
+}
+// -1 where the sign bit of x is set, 0 otherwise
+__device__ __forceinline__ int sign_mask(float x) { return __builtin_bit_cast(int, x) >> 31; }
+__device__ __forceinline__ int sign_mask(double x) { return (int)(__builtin_bit_cast(long long, x) >> 63); }
+
 // 1 / x: the hardware reciprocal (1 ulp) in float, a correctly rounded
 // division in double
 __device__ __forceinline__ float sweep_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -2361,7 +2372,7 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
     T* invdx = coef + (GC ? 0 : nc);                        // [nx]
     T* wl = invdx + nx;                                     // [5][n_wall]  1/d, lam_w, U_w, V_w, drho
     int* wsc = (int*)(wl + 5 * (size_t)nw);                 // [n_wall]  side + 4 cell
-    unsigned char* st = (unsigned char*)(wsc + nw);         // [nc]  side types, 2 bits per side (not with GC)
+    unsigned char* st = (unsigned char*)(wsc + nw);         // [nc]  side predicates, 2 bits per side (not with GC)
     // plane of this block (split: G blocks first, then H blocks)
     const int nbG = split ? (int)(gridDim.x >> 1) : (int)gridDim.x;
     const int plane = (int)blockIdx.x >= nbG ? 1 : 0;
@@ -2453,7 +2464,7 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
     const int t0 = I > 1 ? lane - q * ny : lane;
     const T u = __shfl(uq_l, qq, 64), v = __shfl(vq_l, qq, 64);
     const bool px = u >= T(0), py = v >= T(0);
-    const int shx = px ? 0 : 2, shy = py ? 4 : 6;           // bit offset of the upwind x / y side type
+    const int shx = px ? 0 : 2, shy = py ? 4 : 6;           // bit offset of the upwind x / y side's predicates
     const T au = px ? u : -u, av = py ? v : -v;
     T* tG = tw + (size_t)qq * nc;
     T* tH = tw + ((size_t)(NP == 2 ? I : 0) + qq) * nc;
@@ -2523,19 +2534,21 @@ __global__ void __launch_bounds__(256) k_sweep_wave(Geo g, Vel vel, int K_int, c
                 nbG = p > 0 ? rotG[p > 0 ? p - 1 : 0] : T(0);
                 if constexpr (NP == 2) nbH = p > 0 ? rotH[p > 0 ? p - 1 : 0] : T(0);
             }
-            unsigned tpx = (d.sc >> shx) & 3u, tpy = (d.sc >> shy) & 3u;
+            // the upwind sides' predicates: an interior face, not an outflow
+            const bool x0 = (d.sc >> shx) & 1u, xn3 = (d.sc >> (shx + 1)) & 1u;
+            const bool y0 = (d.sc >> shy) & 1u, yn3 = (d.sc >> (shy + 1)) & 1u;
             T bx = au * d.idx, byp = by[p];
             // transport diagonal: every downwind side, and an upwind side
             // only if it is an outflow (where the two cancel)
-            T D = d.cf + (tpx == 3u ? T(0) : bx) + (tpy == 3u ? T(0) : byp);
+            T D = d.cf + (xn3 ? bx : T(0)) + (yn3 ? byp : T(0));
             T inv = sweep_rcp(D);
-            T exG = tpx == 0u ? cG[p] : T(0), eyG = tpy == 0u ? nbG : T(0);
+            T exG = x0 ? cG[p] : T(0), eyG = y0 ? nbG : T(0);
             T vG = (d.rG + bx * exG + byp * eyG) * inv;
             vG = d.cf < T(0) ? T(0) : vG;
             *(valid ? tG + c : dump) = vG;
             cG[p] = vG;
             if constexpr (NP == 2) {
-                T exH = tpx == 0u ? cH[p] : T(0), eyH = tpy == 0u ? nbH : T(0);
+                T exH = x0 ? cH[p] : T(0), eyH = y0 ? nbH : T(0);
                 T vH = (d.rH + bx * exH + byp * eyH) * inv;
                 vH = d.cf < T(0) ? T(0) : vH;
                 *(valid ? tH + c : dump) = vH;
@@ -2681,7 +2694,7 @@ __global__ void __launch_bounds__(256) k_sweep_strips(Geo g, Vel vel, int K_int,
     T* invdx = cs + (size_t)ny * sw;                        // [nx]
     T* wl = invdx + nx;                                     // [5][n_wall]  1/d, lam_w, U_w, V_w, drho
     int* wsc = (int*)(wl + 5 * (size_t)nw);                 // [n_wall]  side + 4 cell
-    unsigned char* ss = (unsigned char*)(wsc + nw);         // [ny][sw]  the strip's side types
+    unsigned char* ss = (unsigned char*)(wsc + nw);         // [ny][sw]  the strip's side predicates
     const int nbG = split ? (int)(gridDim.x >> 1) : (int)gridDim.x;
     const int plane = (int)blockIdx.x >= nbG ? 1 : 0;
     const int blk = (int)blockIdx.x - plane * nbG;
@@ -2726,7 +2739,7 @@ __global__ void __launch_bounds__(256) k_sweep_strips(Geo g, Vel vel, int K_int,
     const bool ghosts = drho || wprev;
     const T u = vel_u<T>(vel, kk), v = vel_v<T>(vel, kk);
     const bool px = u >= T(0), py = v >= T(0);
-    const int shx = px ? 0 : 2, shy = py ? 4 : 6;           // bit offset of the upwind x / y side type
+    const int shx = px ? 0 : 2, shy = py ? 4 : 6;           // bit offset of the upwind x / y side's predicates
     const T au = px ? u : -u, av = py ? v : -v;
     int iyr[R];                                             // cell row of each slot
     bool rowok[R];
@@ -2817,11 +2830,12 @@ __global__ void __launch_bounds__(256) k_sweep_strips(Geo g, Vel vel, int K_int,
                 fetch(fill[p], p, jx + 3);
                 T nbG = rotG[p];
                 if (R > 1 && lane == 0) nbG = p > 0 ? rotG[p > 0 ? p - 1 : 0] : T(0);
-                unsigned tpx = (d.sc >> shx) & 3u, tpy = (d.sc >> shy) & 3u;
+                const bool x0 = (d.sc >> shx) & 1u, xn3 = (d.sc >> (shx + 1)) & 1u;
+                const bool y0 = (d.sc >> shy) & 1u, yn3 = (d.sc >> (shy + 1)) & 1u;
                 T bx = au * d.idx, byp = by[p];
-                T D = d.cf + (tpx == 3u ? T(0) : bx) + (tpy == 3u ? T(0) : byp);
+                T D = d.cf + (xn3 ? bx : T(0)) + (yn3 ? byp : T(0));
                 T inv = sweep_rcp(D);
-                T exG = tpx == 0u ? cG[p] : T(0), eyG = tpy == 0u ? nbG : T(0);
+                T exG = x0 ? cG[p] : T(0), eyG = y0 ? nbG : T(0);
                 T vG = (d.rG + bx * exG + byp * eyG) * inv;
                 vG = d.cf < T(0) ? T(0) : vG;
                 *(valid ? tw + iyr[p] * wb + ixl : dump) = vG;
@@ -2893,10 +2907,10 @@ __global__ void __launch_bounds__(256) k_sweep_strips(Geo g, Vel vel, int K_int,
 // Short bands keep every lane of a wavefront on a cell of the anti-diagonal
 // for all but hb - 1 of the nx + hb - 1 steps (a tall level swept by one
 // wavefront per velocity keeps ny lanes busy only near the middle of its
-// nx + ny - 1 steps).  The per-cell coefficients and side types are read
-// through the caches: the I velocities of a wavefront are consecutive ones
-// of one row of the velocity grid (the same sign of u), so their lanes read
-// the same cells.  Wall ghosts are added to the staged band as in
+// nx + ny - 1 steps).  The per-cell coefficients and side predicates are
+// read through the caches: the I velocities of a wavefront are consecutive
+// ones of one row of the velocity grid (the same sign of u), so their lanes
+// read the same cells.  Wall ghosts are added to the staged band as in
 // k_sweep_wave; the G plane's wall sums of a block accumulate over the
 // bands in wpart[blk] (the first band writes them).  split as in
 // k_sweep_wave.
@@ -3014,7 +3028,7 @@ __global__ void __launch_bounds__(256) k_sweep_band(Geo g, Vel vel, int K_int, c
     const int t0 = lane - q * h;                            // row within the band
     const T u = __shfl(uq_l, qq, 64), v = __shfl(vq_l, qq, 64);
     const bool px = u >= T(0), py = v >= T(0);
-    const int shx = px ? 0 : 2, shy = py ? 4 : 6;           // bit offset of the upwind x / y side type
+    const int shx = px ? 0 : 2, shy = py ? 4 : 6;           // bit offset of the upwind x / y side's predicates
     const T au = px ? u : -u, av = py ? v : -v;
     const bool rowok = live && t0 < hb;
     const int y0 = band_y0(py);
@@ -3071,15 +3085,19 @@ __global__ void __launch_bounds__(256) k_sweep_band(Geo g, Vel vel, int K_int, c
         for (int u = 0; u < SB; ++u) {
             const T rot = lane_rotate1(cG);
             const T nbG = first ? d.ey[u] : rot;
-            const unsigned tpx = (d.sc[u] >> shx) & 3u, tpy = (d.sc[u] >> shy) & 3u;
+            // the upwind sides' predicates as all-ones / zero masks (a
+            // sign-extending bit extract each; no compares, so no lane masks)
+            const int sc = (int)d.sc[u];
+            const int mx0 = __builtin_amdgcn_sbfe(sc, shx, 1), mxn3 = __builtin_amdgcn_sbfe(sc, shx + 1, 1);
+            const int my0 = __builtin_amdgcn_sbfe(sc, shy, 1), myn3 = __builtin_amdgcn_sbfe(sc, shy + 1, 1);
             const T bx = au * d.idx[u];
             // transport diagonal: every downwind side, and an upwind side only
             // if it is an outflow (where the two cancel)
-            const T D = d.cf[u] + (tpx == 3u ? T(0) : bx) + (tpy == 3u ? T(0) : by);
+            const T D = d.cf[u] + mask_keep(bx, mxn3) + mask_keep(by, myn3);
             const T inv = sweep_rcp(D);
-            const T exG = tpx == 0u ? cG : T(0), eyG = tpy == 0u ? nbG : T(0);
+            const T exG = mask_keep(cG, mx0), eyG = mask_keep(nbG, my0);
             T vG = (d.rG[u] + bx * exG + by * eyG) * inv;
-            vG = d.cf[u] < T(0) ? T(0) : vG;
+            vG = mask_keep(vG, ~sign_mask(d.cf[u]));   // zero in a solid cell (negative coefficient)
             sbase[d.so[u]] = vG;
             cG = vG;
         }

@@ -168,7 +168,7 @@ struct miugks_ctx {
         int strips = 0;   // > 0: k_sweep_strips over that many strips of columns
         int bands = 0, bh = 0;   // > 0: k_sweep_band, that many bands of bh rows (one launch each)
     };
-    std::vector<unsigned char*> stype;
+    std::vector<unsigned char*> stype;   // per cell, the side predicates of the LDS sweeps
     std::vector<void*> coefT;   // 1/tau + 1/dt_n per level in the distribution's type
     // restricted defect after an ordered sweep: per coarse cell the ranges of
     // the fine wall list under it and its inverse fluid volume; the change of
@@ -1250,7 +1250,17 @@ int build_device(miugks_ctx* ctx) {
         ctx->flags[l] = p;
         {
             std::vector<unsigned char> st(h.nc);
-            for (int c = 0; c < h.nc; ++c) st[c] = (unsigned char)(fl[c] & 0xffu);
+            // the side predicates of the LDS sweeps: per side s, bit 2s = an
+            // interior face (type 0), bit 2s + 1 = not an outflow (type 3)
+            for (int c = 0; c < h.nc; ++c) {
+                unsigned bits = 0;
+                for (int sd = 0; sd < 4; ++sd) {
+                    const unsigned t = (fl[c] >> (2 * sd)) & 3u;
+                    bits |= (t == 0u ? 1u : 0u) << (2 * sd);
+                    bits |= (t != 3u ? 1u : 0u) << (2 * sd + 1);
+                }
+                st[c] = (unsigned char)bits;
+            }
             unsigned char* sp;
             if ((rc = upload(ctx, &sp, st))) return rc;
             ctx->stype[l] = sp;
