@@ -44,28 +44,28 @@ MEASURED_TRAFFIC = {
     # ordered sweep over all its launches (bands on the 160- and 80-row
     # levels, the whole-tile wavefront sweep below), the band launches of the
     # 160-row level (those of the last sweep also add df to f)
-    ("square160x160", "fp32f", "flux_div"): 7.6308e9,
-    ("square160x160", "fp32f", "sweep"): 3.9862e8,
-    ("square160x160", "fp32f", "sweep/l0"): 7.0805e8,
-    ("square160x160", "fp64", "flux_div"): 1.7078e10,
-    ("square160x160", "fp64", "sweep"): 4.6308e8,
-    ("square160x160", "fp64", "sweep/l0"): 5.5763e8,
+    ("square160x160", "fp32f", "flux_div"): 7.6077e9,
+    ("square160x160", "fp32f", "sweep"): 3.9865e8,
+    ("square160x160", "fp32f", "sweep/l0"): 7.0812e8,
+    ("square160x160", "fp64", "flux_div"): 1.7050e10,
+    ("square160x160", "fp64", "sweep"): 4.6305e8,
+    ("square160x160", "fp64", "sweep/l0"): 5.5761e8,
     # profiles/plate128x96_kernel_trace_and_hbm_traffic.md (bands on the
     # 96-row level only)
-    ("plate128x96", "fp32f", "flux_div"): 5.1523e8,
-    ("plate128x96", "fp32f", "sweep"): 5.6825e7,
-    ("plate128x96", "fp32f", "sweep/l0"): 8.9940e7,
-    ("plate128x96", "fp64", "flux_div"): 1.3121e9,
-    ("plate128x96", "fp64", "sweep"): 1.1319e8,
-    ("plate128x96", "fp64", "sweep/l0"): 1.7940e8,
+    ("plate128x96", "fp32f", "flux_div"): 5.1537e8,
+    ("plate128x96", "fp32f", "sweep"): 5.6823e7,
+    ("plate128x96", "fp32f", "sweep/l0"): 8.9933e7,
+    ("plate128x96", "fp64", "flux_div"): 1.3118e9,
+    ("plate128x96", "fp64", "sweep"): 1.1317e8,
+    ("plate128x96", "fp64", "sweep/l0"): 1.7939e8,
     # profiles/cavity64_kn0.075_kernel_trace_and_hbm_traffic.md (FP64: bands
     # on the 64-row level; in FP32-f that level's whole-tile sweeps share
     # their kernels with the coarser levels, so no level-0 figure)
-    ("cavity64_kn0.075", "fp32f", "flux_div"): 8.0346e7,
-    ("cavity64_kn0.075", "fp32f", "sweep"): 1.2197e7,
-    ("cavity64_kn0.075", "fp64", "flux_div"): 1.9347e8,
-    ("cavity64_kn0.075", "fp64", "sweep"): 2.3260e7,
-    ("cavity64_kn0.075", "fp64", "sweep/l0"): 4.5393e7,
+    ("cavity64_kn0.075", "fp32f", "flux_div"): 8.0200e7,
+    ("cavity64_kn0.075", "fp32f", "sweep"): 1.2199e7,
+    ("cavity64_kn0.075", "fp64", "flux_div"): 1.9380e8,
+    ("cavity64_kn0.075", "fp64", "sweep"): 2.3247e7,
+    ("cavity64_kn0.075", "fp64", "sweep/l0"): 4.5385e7,
 }
 
 # what each workload recipe is (the sizes are printed from the case itself)
